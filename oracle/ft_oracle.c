@@ -1,0 +1,216 @@
+/*
+ * FP64 CPU oracle for the short-coherence statistic -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Only the test-suite, the smoke check and the CPU-baseline leg of the
+ * benchmark may load this library.  It shares no code with the GPU library.
+ * Everything is plain, slow and sequential in the canonical order:
+ *
+ *   track      f_k   = (f0 + f1 * (t_k - t_ref)) * (1 + v_k . n)
+ *              (Eq. track with a_p = 0 -- an isolated source -- plus a linear
+ *               spindown term; the Doppler factor has the sign of Eq. track)
+ *   bin        B_k   = floor(f_k * T_sft + 1/2)   (bins of width 1/T_sft,
+ *                                                   Sec. IV.A resolution)
+ *   statistic  S     = sum_k w_k * P[k][B_k - first_bin]
+ *                                                  (Eq. short_coh_general)
+ *   critical   z     = (S - 2 sum w) / (2 sqrt(sum w^2))
+ *                      (mu_G, sigma_G of Sec. II.B.1; Eq. critical_ratio)
+ *   toplist    the first K templates of each f0 sub-band under the total
+ *              order (S descending, template index ascending).
+ *
+ * Operation order (fixed, no FMA contraction -- build with -ffp-contract=off):
+ *   d = (vx*nx + vy*ny) + vz*nz ; g = 1 + d ; c = f1*dt ; a = f0 + c ;
+ *   f = a*g ; x = f*T ; B = floor(x + 0.5) ; S accumulates in SFT order.
+ *
+ * Status codes: 0 ok, -1 invalid argument, -3 a track left the table.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_OK 0
+#define OR_E_INVALID (-1)
+#define OR_E_RANGE (-3)
+
+/* Doppler factor 1 + v.n (Eq. track, detector-motion term). */
+static double doppler_factor(const double *v, const double *n)
+{
+    double px = v[0] * n[0];
+    double py = v[1] * n[1];
+    double pz = v[2] * n[2];
+    double d = px + py;
+    d = d + pz;
+    return 1.0 + d;
+}
+
+/* Absolute bin index of the track of (f0, f1) at an SFT with offset dt and
+ * Doppler factor g. */
+static int64_t track_bin(double f0, double f1, double dt, double g, double t_sft)
+{
+    double c = f1 * dt;
+    double a = f0 + c;
+    double f = a * g;
+    double x = f * t_sft;
+    return (int64_t)floor(x + 0.5);
+}
+
+static double weight_of(const float *weight, int64_t k)
+{
+    return weight ? (double)weight[k] : 1.0;
+}
+
+/* Bin indices of an arbitrary list of templates: bins[t*n_sft + k] = B (absolute). */
+int ftor_bins_list(int32_t n_sft, const double *t_mid, double t_ref, double t_sft,
+                   const double *v, int64_t n_tmpl, const double *f0, const double *f1,
+                   const double *sky, int64_t *bins)
+{
+    if (n_sft <= 0 || n_tmpl < 0 || t_sft <= 0.0) return OR_E_INVALID;
+    for (int64_t t = 0; t < n_tmpl; ++t) {
+        for (int32_t k = 0; k < n_sft; ++k) {
+            double g = doppler_factor(v + 3 * (int64_t)k, sky + 3 * t);
+            double dt = t_mid[k] - t_ref;
+            bins[t * n_sft + k] = track_bin(f0[t], f1[t], dt, g, t_sft);
+        }
+    }
+    return OR_OK;
+}
+
+/* Statistic of an arbitrary list of templates.  *first_bad receives the first
+ * template whose track leaves [first_bin, first_bin + n_bins), or -1. */
+int ftor_eval_list(int32_t n_sft, const double *t_mid, double t_ref, double t_sft,
+                   int64_t first_bin, int32_t n_bins, const float *power, const float *weight,
+                   const double *v, int64_t n_tmpl, const double *f0, const double *f1,
+                   const double *sky, double *s_out, int64_t *first_bad)
+{
+    if (n_sft <= 0 || n_bins <= 0 || n_tmpl < 0 || t_sft <= 0.0) return OR_E_INVALID;
+    int64_t bad = -1;
+    for (int64_t t = 0; t < n_tmpl; ++t) {
+        double acc = 0.0;
+        for (int32_t k = 0; k < n_sft; ++k) {
+            double g = doppler_factor(v + 3 * (int64_t)k, sky + 3 * t);
+            double dt = t_mid[k] - t_ref;
+            int64_t b = track_bin(f0[t], f1[t], dt, g, t_sft) - first_bin;
+            if (b < 0 || b >= n_bins) {
+                if (bad < 0) bad = t;
+                acc = NAN;
+                break;
+            }
+            acc = acc + weight_of(weight, k) * (double)power[(int64_t)k * n_bins + b];
+        }
+        s_out[t] = acc;
+    }
+    if (first_bad) *first_bad = bad;
+    return bad >= 0 ? OR_E_RANGE : OR_OK;
+}
+
+/* Statistic of a grid bank; template index t = (s*n_f1 + j)*n_f0 + i.
+ * Sky points are independent, so they run on separate OpenMP threads; every
+ * template still accumulates sequentially in SFT order. */
+int ftor_eval_grid(int32_t n_sft, const double *t_mid, double t_ref, double t_sft,
+                   int64_t first_bin, int32_t n_bins, const float *power, const float *weight,
+                   const double *v, int64_t n_f0, const double *f0, int64_t n_f1,
+                   const double *f1, int64_t n_sky, const double *sky, double *s_out,
+                   int64_t *first_bad)
+{
+    if (n_sft <= 0 || n_bins <= 0 || n_f0 <= 0 || n_f1 <= 0 || n_sky < 0 || t_sft <= 0.0)
+        return OR_E_INVALID;
+    const int64_t per_sky = n_f0 * n_f1;
+    int64_t bad = -1;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t s = 0; s < n_sky; ++s) {
+        double *acc = s_out + s * per_sky;
+        for (int64_t q = 0; q < per_sky; ++q) acc[q] = 0.0;
+        int64_t local_bad = -1;
+        for (int32_t k = 0; k < n_sft; ++k) {
+            double g = doppler_factor(v + 3 * (int64_t)k, sky + 3 * s);
+            double dt = t_mid[k] - t_ref;
+            double w = weight_of(weight, k);
+            const float *row = power + (int64_t)k * n_bins;
+            for (int64_t j = 0; j < n_f1; ++j) {
+                for (int64_t i = 0; i < n_f0; ++i) {
+                    int64_t b = track_bin(f0[i], f1[j], dt, g, t_sft) - first_bin;
+                    if (b < 0 || b >= n_bins) {
+                        int64_t t = s * per_sky + j * n_f0 + i;
+                        if (local_bad < 0 || t < local_bad) local_bad = t;
+                        acc[j * n_f0 + i] = NAN;
+                        continue;
+                    }
+                    acc[j * n_f0 + i] = acc[j * n_f0 + i] + w * (double)row[b];
+                }
+            }
+        }
+        if (local_bad >= 0) {
+#pragma omp critical
+            { if (bad < 0 || local_bad < bad) bad = local_bad; }
+        }
+    }
+    if (first_bad) *first_bad = bad;
+    return bad >= 0 ? OR_E_RANGE : OR_OK;
+}
+
+/* Noise-hypothesis moments: mu_G = 2 sum w, sigma_G = 2 sqrt(sum w^2)
+ * (Sec. II.B.1), sums sequential in SFT order. */
+void ftor_noise_moments(int32_t n_sft, const float *weight, double *mu, double *sigma)
+{
+    double sw = 0.0, sw2 = 0.0;
+    for (int32_t k = 0; k < n_sft; ++k) {
+        double w = weight_of(weight, k);
+        sw = sw + w;
+        sw2 = sw2 + w * w;
+    }
+    *mu = 2.0 * sw;
+    *sigma = 2.0 * sqrt(sw2);
+}
+
+/* Critical ratio z = (S - mu_G)/sigma_G (Eq. critical_ratio). */
+void ftor_critical_ratio(int64_t n, const double *s, int32_t n_sft, const float *weight,
+                         double *z)
+{
+    double mu, sigma;
+    ftor_noise_moments(n_sft, weight, &mu, &sigma);
+    for (int64_t t = 0; t < n; ++t) z[t] = (s[t] - mu) / sigma;
+}
+
+/* Sub-band of each frequency: edges[j] <= f < edges[j+1]; -1 outside. */
+void ftor_subband(int64_t n, const double *f, int32_t n_sub, const double *edges, int32_t *sub)
+{
+    for (int64_t t = 0; t < n; ++t) {
+        int32_t r = -1;
+        for (int32_t j = 0; j < n_sub; ++j)
+            if (edges[j] <= f[t] && f[t] < edges[j + 1]) { r = j; break; }
+        sub[t] = r;
+    }
+}
+
+static const double *g_sort_s;
+static int cmp_desc_s_asc_idx(const void *pa, const void *pb)
+{
+    int64_t a = *(const int64_t *)pa, b = *(const int64_t *)pb;
+    double sa = g_sort_s[a], sb = g_sort_s[b];
+    if (sa > sb) return -1;
+    if (sa < sb) return 1;
+    return (a < b) ? -1 : (a > b);
+}
+
+/* Toplist: for every sub-band j, out_idx[j*k + r] is the r-th template under
+ * (S desc, index asc); out_n[j] counts them (<= k).  Not thread-safe. */
+int ftor_toplist(int64_t n, const double *s, const int32_t *sub, int32_t n_sub, int32_t k,
+                 int64_t *out_idx, int32_t *out_n)
+{
+    if (k <= 0 || n_sub <= 0) return OR_E_INVALID;
+    int64_t *members = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    if (!members) return OR_E_INVALID;
+    for (int32_t j = 0; j < n_sub; ++j) {
+        int64_t m = 0;
+        for (int64_t t = 0; t < n; ++t)
+            if (sub[t] == j) members[m++] = t;
+        g_sort_s = s;
+        qsort(members, (size_t)m, sizeof(int64_t), cmp_desc_s_asc_idx);
+        int32_t cnt = (int32_t)(m < k ? m : k);
+        for (int32_t r = 0; r < cnt; ++r) out_idx[(int64_t)j * k + r] = members[r];
+        for (int32_t r = cnt; r < k; ++r) out_idx[(int64_t)j * k + r] = -1;
+        out_n[j] = cnt;
+    }
+    free(members);
+    return OR_OK;
+}

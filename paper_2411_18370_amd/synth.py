@@ -1,0 +1,189 @@
+"""Seeded synthetic inputs shaped like the paper's all-sky short-coherence search.
+
+This module produces *inputs only*: SFT mid-times with gaps, detector velocities
+from an analytic Earth orbit plus rotation, isotropic sky points, template-bank
+grids and unit-variance complex-Gaussian noise power.  It holds none of the
+method's arithmetic (no track, no bin index, no statistic, no signal model), so
+both the FP64 oracle and the GPU library can consume what it produces.
+
+Physical model of the inputs (Sec. II of the paper uses real LVK SFTs; these
+stand in for them):
+
+* SFTs have duration ``t_sft``; a detector observes on a grid of consecutive
+  slots, of which a seeded uniform random subset is present (gaps are allowed,
+  Sec. II.B footnote on timestamps).  Timestamps are slot *mid-times*.
+* Detector velocity ``v/c`` in equatorial Cartesian coordinates: circular
+  heliocentric orbit (1 AU, sidereal year, obliquity 23.4393 deg) plus the
+  detector's rotation with the Earth (sidereal day, equatorial radius).
+* Isotropic sky: right ascension uniform in [0, 2 pi), sin(declination)
+  uniform in [-1, 1] (App. A parametrisation of the sky).
+* Noise power: Re, Im ~ N(0, 1) i.i.d. per bin, power = Re^2 + Im^2, so each
+  bin is chi^2 with 2 degrees of freedom (Eq. s_chi2).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+C_LIGHT = 299792458.0
+AU = 1.495978707e11
+SIDEREAL_YEAR = 365.256363004 * 86400.0
+SIDEREAL_DAY = 86164.0905
+R_EARTH = 6.378137e6
+OBLIQUITY = math.radians(23.4393)
+EPOCH = 1.2e9  # GPS-like start of observation [s]
+
+
+@dataclass(frozen=True)
+class Detector:
+    """A synthetic ground-based interferometer (geometry loosely LIGO-like)."""
+    name: str
+    lat_deg: float
+    lon_deg: float
+    arm_azimuths_deg: tuple  # azimuths of the two arms, from North towards East
+
+
+DETECTORS = (
+    Detector("H1-like", 46.455, -119.408, (125.9994, 215.9994)),
+    Detector("L1-like", 30.563, -90.774, (197.7165, 287.7165)),
+)
+
+
+def sidereal_angle(t: np.ndarray, lon_deg: float) -> np.ndarray:
+    """Local sidereal angle of a detector at time t (zero at EPOCH for lon 0)."""
+    return 2.0 * np.pi * (t - EPOCH) / SIDEREAL_DAY + math.radians(lon_deg)
+
+
+def detector_velocity(t_mid: np.ndarray, det: Detector) -> np.ndarray:
+    """v/c [N,3] (equatorial) at the SFT mid-times: orbit + rotation."""
+    t = np.asarray(t_mid, dtype=np.float64)
+    v_orb = 2.0 * np.pi * AU / SIDEREAL_YEAR
+    lam = 2.0 * np.pi * (t - EPOCH) / SIDEREAL_YEAR + 0.3  # ecliptic longitude
+    vx_e = -v_orb * np.sin(lam)
+    vy_e = v_orb * np.cos(lam)
+    # ecliptic -> equatorial: rotation about x by the obliquity
+    vx = vx_e
+    vy = vy_e * math.cos(OBLIQUITY)
+    vz = vy_e * math.sin(OBLIQUITY)
+    th = sidereal_angle(t, det.lon_deg)
+    w = 2.0 * np.pi / SIDEREAL_DAY
+    rc = R_EARTH * math.cos(math.radians(det.lat_deg))
+    vx = vx - w * rc * np.sin(th)
+    vy = vy + w * rc * np.cos(th)
+    return np.stack([vx, vy, vz], axis=1) / C_LIGHT
+
+
+def sft_mid_times(n_present: int, t_sft: float, gap_frac: float, rng: np.random.Generator,
+                  t0: float = EPOCH) -> np.ndarray:
+    """Mid-times of ``n_present`` SFTs drawn from ceil(n/(1-gap)) consecutive slots."""
+    if gap_frac <= 0.0:
+        slots = np.arange(n_present)
+    else:
+        n_slots = int(math.ceil(n_present / (1.0 - gap_frac)))
+        slots = np.sort(rng.choice(n_slots, size=n_present, replace=False))
+    return t0 + slots.astype(np.float64) * t_sft + 0.5 * t_sft
+
+
+def isotropic_sky(n: int, rng: np.random.Generator) -> np.ndarray:
+    """Unit vectors [n,3], uniform in (alpha, sin delta)."""
+    alpha = rng.uniform(0.0, 2.0 * np.pi, size=n)
+    sdec = rng.uniform(-1.0, 1.0, size=n)
+    cdec = np.sqrt(np.maximum(0.0, 1.0 - sdec * sdec))
+    n_xyz = np.stack([cdec * np.cos(alpha), cdec * np.sin(alpha), sdec], axis=1)
+    return n_xyz / np.linalg.norm(n_xyz, axis=1, keepdims=True)
+
+
+def noise_power(n_sft: int, n_bins: int, rng: np.random.Generator) -> np.ndarray:
+    """Normalised power of unit-variance complex Gaussian bins, float32 [n_sft, n_bins]."""
+    re = rng.standard_normal((n_sft, n_bins))
+    im = rng.standard_normal((n_sft, n_bins))
+    return (re * re + im * im).astype(np.float32)
+
+
+def table_range(f0_min, f0_max, f1_min, f1_max, dt_min, dt_max, v_max, t_sft, margin=2):
+    """Conservative [first_bin, n_bins] covering every track of the bank (sizing only)."""
+    corners = [f1_min * dt_min, f1_min * dt_max, f1_max * dt_min, f1_max * dt_max]
+    lo = math.floor((f0_min + min(corners)) * (1.0 - v_max) * t_sft) - margin
+    hi = math.ceil((f0_max + max(corners)) * (1.0 + v_max) * t_sft) + margin
+    return int(lo), int(hi - lo + 1)
+
+
+@dataclass
+class Workload:
+    """Everything one plain evaluation needs, as host numpy arrays."""
+    name: str
+    t_sft: float
+    n_sft_per_det: list
+    t_mid: np.ndarray            # [N] float64, detector-major, time ascending
+    v: np.ndarray                # [N,3] float64, v/c
+    t_ref: float
+    first_bin: int
+    n_bins: int
+    power: np.ndarray            # [N, n_bins] float32
+    weight: np.ndarray | None    # [N] float32 or None (all ones)
+    f0: np.ndarray               # [n_f0]
+    f1: np.ndarray               # [n_f1]
+    sky: np.ndarray              # [n_sky,3]
+    k: int
+    sub_edges: np.ndarray        # [n_sub+1]
+    injections: list = field(default_factory=list)  # dicts of injection parameters
+
+    @property
+    def n_sft(self):
+        return int(self.t_mid.shape[0])
+
+    @property
+    def n_templates(self):
+        return int(self.f0.size * self.f1.size * self.sky.shape[0])
+
+    @property
+    def evals(self):
+        return self.n_templates * self.n_sft
+
+
+def _build(name, n_det, n_per_det, t_sft, gap, f_start, n_f0, f1, n_sky, k, n_sub, seed,
+           with_noise=True, sky=None):
+    rng = np.random.default_rng(seed)
+    t_parts, v_parts = [], []
+    for d in range(n_det):
+        t = sft_mid_times(n_per_det, t_sft, gap, rng)
+        t_parts.append(t)
+        v_parts.append(detector_velocity(t, DETECTORS[d]))
+    t_mid = np.concatenate(t_parts)
+    v = np.concatenate(v_parts)
+    t_ref = EPOCH
+    f0 = f_start + np.arange(n_f0, dtype=np.float64) / t_sft
+    f1 = np.asarray(f1, dtype=np.float64)
+    if sky is None:
+        sky = isotropic_sky(n_sky, rng)
+    vmax = float(np.max(np.linalg.norm(v, axis=1)))
+    dt = t_mid - t_ref
+    first_bin, n_bins = table_range(f0.min(), f0.max(), f1.min(), f1.max(), dt.min(), dt.max(),
+                                    vmax, t_sft)
+    power = noise_power(t_mid.size, n_bins, rng) if with_noise else \
+        np.zeros((t_mid.size, n_bins), np.float32)
+    per = n_f0 // n_sub
+    edges = np.array([f_start + (j * per - 0.5) / t_sft for j in range(n_sub)]
+                     + [f_start + (n_f0 - 0.5) / t_sft], dtype=np.float64)
+    return Workload(name, t_sft, [n_per_det] * n_det, t_mid, v, t_ref, first_bin, n_bins, power,
+                    None, f0, f1, sky, k, edges)
+
+
+def plain_small(seed: int = 1, n_sky: int = 20) -> Workload:
+    """1 detector, 100 contiguous SFTs, 100.0-100.1 Hz, 180 f0 x 3 f1 x 20 sky, K=10."""
+    return _build("plain-1det-100sft-100Hz", 1, 100, 1800.0, 0.0, 100.0, 180,
+                  [-1e-10, 0.0, 1e-10], n_sky, 10, 1, seed)
+
+
+def allsky_band(seed: int = 2, n_sky: int = 100_000, n_per_det: int = 5000) -> Workload:
+    """2 detectors x 5000 SFTs (10% gaps), 200-200.5 Hz, 900 f0 x 11 f1 x n_sky, K=100/0.05 Hz."""
+    return _build("allsky-2det-10ksft-200Hz", 2, n_per_det, 1800.0, 0.1, 200.0, 900,
+                  np.linspace(-1e-9, 0.0, 11), n_sky, 100, 10, seed)
+
+
+def precision_stress(seed: int = 2, n_sky: int = 20_000, n_per_det: int = 5000) -> Workload:
+    """Same timestamps as the all-sky band; 1000-1000.1 Hz, 180 f0 x 5 f1 x n_sky."""
+    return _build("precision-2det-10ksft-1kHz", 2, n_per_det, 1800.0, 0.1, 1000.0, 180,
+                  np.linspace(-1e-9, 0.0, 5), n_sky, 100, 2, seed)
