@@ -1,0 +1,227 @@
+/*
+ * fasttracks.h -- C ABI of the MI355X (gfx950) brute-force short-coherence
+ * statistic library (arXiv:2411.18370, Secs. II-III).
+ *
+ * The library evaluates, for every template lambda = (f0, f1, n) of a bank and
+ * every SFT k of the data,
+ *
+ *     f_k(lambda) = (f0 + f1 (t_k - t_ref)) (1 + v_k . n)        (Eq. track,
+ *                   isolated source a_p = 0, plus a linear spindown term)
+ *     B_k         = floor(f_k T_sft + 1/2)                         (bins of
+ *                   width 1/T_sft, Sec. IV.A resolution Eq. resolution)
+ *     S(lambda)   = sum_k w_k P[k][B_k - first_bin]               (Eq.
+ *                   short_coh_general with the normalised power of Eq. s_tf)
+ *
+ * and keeps, for every sub-band of f0, the K loudest templates (the list of
+ * per-region loudest candidates of Secs. IV.B and VI), each with its critical
+ * ratio z = (S - mu_G)/sigma_G, mu_G = 2 sum w, sigma_G = 2 sqrt(sum w^2)
+ * (Sec. II.B.1, Eq. critical_ratio).
+ *
+ * Exactness.  Bin indices are computed in FP64 in the fixed order
+ *   d = (vx*nx + vy*ny) + vz*nz ; g = 1 + d ; c = f1*dt ; a = f0 + c ;
+ *   f = a*g ; x = f*T_sft ; B = floor(x + 0.5)
+ * with no fused multiply-add, so every bin equals the one of a plain FP64
+ * evaluation.  Sums run in FP32 over aligned blocks of 32 SFTs, the block sums
+ * are accumulated in FP64 (relative error <= 40*2^-24 + 4*N*2^-53 against the
+ * FP64 sum).  Toplists are exact: every template whose FP32 statistic could
+ * belong to the FP64 top-K is re-summed in FP64 in SFT order and ranked by
+ * (S descending, template index ascending).
+ *
+ * Memory.  Every pointer argument may be host or device memory (HIP unified
+ * addressing); every ft_set_* call copies what it is given, so the caller may
+ * free or reuse its buffers when the call returns.  Output buffers are owned by
+ * the caller.
+ *
+ * Streams and threads.  A context serialises all its GPU work on one HIP
+ * stream (the caller's, or one it owns).  ft_eval_templates is asynchronous;
+ * errors detectable on the host are returned synchronously, errors found by
+ * the GPU (a track leaving the table) are returned by the next ft_sync /
+ * ft_toplist.  A context is not thread-safe: use one per host thread.
+ */
+#ifndef FASTTRACKS_H
+#define FASTTRACKS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FT_OK = 0,
+    FT_E_INVALID = -1,     /* bad argument: non-finite value, |v| >= 1, |n| != 1, ...     */
+    FT_E_STATE = -2,       /* call out of order (eval before set_sfts/set_velocities)     */
+    FT_E_RANGE = -3,       /* a track bin lies outside [first_bin, first_bin + n_bins)    */
+    FT_E_NOMEM = -4,       /* device allocation failed                                    */
+    FT_E_DEVICE = -5,      /* HIP runtime error / no device                               */
+    FT_E_UNSUPPORTED = -6, /* valid request outside the library's limits                  */
+    FT_E_INTERNAL = -7     /* internal consistency check failed (a bug: please report)    */
+} ft_status;
+
+typedef struct ft_ctx_s *ft_ctx;
+
+/* Create a context on HIP device `device`.  `hip_stream` is a hipStream_t the
+ * context will use (not owned), or NULL for a stream the context owns. */
+ft_status ft_create(ft_ctx *out, int device, void *hip_stream);
+/* Destroy a context and free its device memory (NULL is a no-op). */
+void ft_destroy(ft_ctx ctx);
+/* Text of the last error on this context ("" if none).  Valid until the next call. */
+const char *ft_last_error(ft_ctx ctx);
+/* Name of a status code. */
+const char *ft_status_string(int status);
+
+/*
+ * ft_set_sfts -- the normalised spectrogram (Eq. s_tf) and its timestamps
+ * (Sec. II.B: SFTs of duration T_sft labelled by detector X and time index
+ * alpha; consecutive timestamps may be further apart than T_sft when there
+ * are gaps).
+ *   n_det      number of detectors (>= 1)
+ *   n_sft      [n_det] SFTs per detector (>= 1 each); N = sum n_sft[d] <= 2^31-1
+ *   t_mid      [N] SFT mid-times in seconds, detector-major; the summation order
+ *              of the statistic is this order
+ *   t_sft      SFT duration in seconds (> 0); bin B has frequency B / t_sft
+ *   first_bin  absolute bin index of column 0 of the table (>= 0)
+ *   n_bins     columns of the table (>= 1); first_bin + n_bins < 2^31
+ *   power      [N][n_bins] row-major normalised power, finite and >= 0
+ *   weight     [N] per-SFT weights w_k (finite, >= 0) or NULL for w_k = 1
+ * Errors: FT_E_INVALID for any violated condition above.  Invalidates the
+ * velocities if N changes.
+ */
+ft_status ft_set_sfts(ft_ctx ctx, int32_t n_det, const int32_t *n_sft, const double *t_mid,
+                      double t_sft, int64_t first_bin, int32_t n_bins, const float *power,
+                      const float *weight);
+
+/*
+ * ft_set_velocities -- detector velocity at each SFT mid-time, v/c, [N][3] in
+ * equatorial Cartesian coordinates (the v(t)/c of Eq. track), same order as
+ * t_mid.  Errors: FT_E_STATE before ft_set_sfts; FT_E_INVALID if a value is
+ * non-finite or |v| >= 1.
+ */
+ft_status ft_set_velocities(ft_ctx ctx, const double *v_over_c);
+
+enum { FT_BANK_GRID = 0, FT_BANK_LIST = 1 };
+
+/*
+ * Template bank (Sec. III: a batch of templates with no assumption on its
+ * structure; the grid form is the Cartesian product used by the paper's
+ * all-sky setups).
+ *   GRID: f0[n_f0] strictly increasing and > 0, f1[n_f1], sky_xyz[n_sky][3]
+ *         unit vectors; template index t = (s*n_f1 + j)*n_f0 + i.
+ *   LIST: f0[n_list] > 0, f1[n_list], sky_xyz[n_list][3]; template index t.
+ * Every f0 + f1*(t_k - t_ref) must be > 0.
+ */
+typedef struct {
+    int32_t kind;
+    int32_t reserved;
+    int64_t n_f0, n_f1, n_sky;
+    int64_t n_list;
+    const double *f0;
+    const double *f1;
+    const double *sky_xyz;
+} ft_bank;
+
+enum {
+    FT_INDEX_FP64 = 0,    /* exact: canonical FP64 bins (default)                       */
+    FT_INDEX_FP32 = 1,    /* study: the same expression in FP32                          */
+    FT_INDEX_DF64 = 2,    /* study: unevaluated float-float sums/products, then floor    */
+    FT_INDEX_GUARDED = 3  /* exact: FP32 estimate, FP64 recomputation near half-bins     */
+};
+
+enum { FT_SUM_BLOCKED = 0, FT_SUM_PLAIN_FP32 = 1 };
+
+/*
+ * Evaluation options.
+ *   precision  FT_INDEX_* (bins of the stored statistic; toplists are always
+ *              re-summed with canonical FP64 bins)
+ *   k          toplist length per sub-band (1..65536)
+ *   n_sub      number of f0 sub-bands (1..4096)
+ *   sub_edges  [n_sub+1] strictly increasing; sub-band j is
+ *              sub_edges[j] <= f0 < sub_edges[j+1] (templates outside every
+ *              sub-band are evaluated but enter no toplist)
+ *   sum_mode   FT_SUM_BLOCKED (default) or FT_SUM_PLAIN_FP32 (study only:
+ *              toplists are then not guaranteed exact)
+ *   tile       0 = library choice; otherwise a tile id in 1..ft_tile_count()
+ *              (see ft_tile_name); ignored for LIST banks
+ */
+typedef struct {
+    int32_t precision;
+    int32_t k;
+    int32_t n_sub;
+    int32_t sum_mode;
+    const double *sub_edges;
+    int32_t tile;
+    int32_t reserved;
+} ft_eval_opts;
+
+/*
+ * ft_eval_templates -- evaluate S for every template of `bank` and build the
+ * per-sub-band toplists.  `stats` ([n_templates] float, host or device) receives
+ * the FP32 statistic of every template in template order, or is NULL.
+ * Asynchronous on the context's stream.  Errors: FT_E_STATE (no SFTs or
+ * velocities), FT_E_INVALID (bank/options), FT_E_UNSUPPORTED (sizes beyond
+ * limits), FT_E_NOMEM; FT_E_RANGE is reported by the next ft_sync/ft_toplist.
+ */
+ft_status ft_eval_templates(ft_ctx ctx, const ft_bank *bank, double t_ref,
+                            const ft_eval_opts *opts, float *stats);
+
+/* One toplist entry. */
+typedef struct {
+    int64_t index;   /* template index in the bank                              */
+    int32_t sub;     /* sub-band                                                */
+    float s32;       /* FP32 statistic of the evaluation pass                   */
+    double f0, f1;   /* template parameters                                     */
+    double n[3];     /* sky unit vector                                         */
+    double s64;      /* S re-summed in FP64 in SFT order                        */
+    double z;        /* critical ratio (S64 - mu_G)/sigma_G                     */
+} ft_candidate;
+
+/*
+ * ft_toplist -- copy the toplist of sub-band `sub` of the last evaluation,
+ * ordered by (s64 descending, index ascending), into out[0..*n_out-1]
+ * (capacity k).  Synchronises the context's stream; returns deferred GPU
+ * errors (FT_E_RANGE).
+ */
+ft_status ft_toplist(ft_ctx ctx, int32_t sub, ft_candidate *out, int32_t *n_out);
+
+/* Wait for the context's stream and report deferred GPU errors. */
+ft_status ft_sync(ft_ctx ctx);
+
+/* Timing and bookkeeping of the last ft_eval_templates (after ft_sync). */
+typedef struct {
+    double eval_ms;        /* evaluation kernel, HIP events on the context stream     */
+    double select_ms;      /* selection + FP64 re-summation + ranking                 */
+    int64_t n_templates;
+    int64_t n_evals;       /* n_templates * N                                         */
+    int64_t n_candidates;  /* templates re-summed in FP64                             */
+    int32_t tile;          /* tile id used (1-based; 0 for LIST banks)                */
+    int32_t window;        /* LDS window width per SFT (bins)                          */
+    int64_t slow_groups;   /* reserved                                                */
+} ft_eval_info;
+ft_status ft_last_eval_info(ft_ctx ctx, ft_eval_info *info);
+
+/*
+ * ft_bins -- study/parity helper: absolute bin B_k of every template of a LIST
+ * bank at every SFT, computed with index mode `precision`, into
+ * bins[t*N + k] (int32, host or device).  Errors as ft_eval_templates.
+ */
+ft_status ft_bins(ft_ctx ctx, const ft_bank *bank, double t_ref, int32_t precision,
+                  int32_t *bins);
+
+/*
+ * ft_count_index_mismatches -- precision study (bins of FT_INDEX_FP32/DF64/
+ * GUARDED against the canonical FP64 bin): number of (template, SFT) pairs of
+ * `bank` (GRID or LIST) whose bin differs, written to *n_mismatch.
+ */
+ft_status ft_count_index_mismatches(ft_ctx ctx, const ft_bank *bank, double t_ref,
+                                    int32_t precision, int64_t *n_mismatch);
+
+/* Tiles of the grid evaluation kernel (for the autotuner and tests); ids are
+ * 1..ft_tile_count(), names describe run length L, f1 values JT, waves NW and
+ * SFTs per LDS stage KS. */
+int32_t ft_tile_count(void);
+const char *ft_tile_name(int32_t tile);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FASTTRACKS_H */

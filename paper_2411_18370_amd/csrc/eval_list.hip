@@ -1,0 +1,368 @@
+// List-bank evaluation (one lane per template, no assumption on the bank's
+// structure -- the batch evaluation of Sec. III), bin dumps and the index
+// precision study (FP32 / split double-FP32 / guarded against FP64), plus the
+// small helper kernels of the host layer.
+#include "ft_internal.h"
+
+namespace ft {
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Index precision variants.
+// ---------------------------------------------------------------------------
+
+// The canonical expression evaluated in FP32 throughout.
+__device__ __forceinline__ int bin_fp32(double f0, double f1, double dt, const double *v,
+                                        const double *n, double t_sft)
+{
+    const float px = (float)v[0] * (float)n[0];
+    const float py = (float)v[1] * (float)n[1];
+    const float pz = (float)v[2] * (float)n[2];
+    float d = px + py;
+    d = d + pz;
+    const float g = 1.f + d;
+    const float c = (float)f1 * (float)dt;
+    const float a = (float)f0 + c;
+    const float f = a * g;
+    const float x = f * (float)t_sft;
+    return (int)floorf(x + 0.5f);
+}
+
+// Unevaluated sums of two floats ("double-float"): error-free two-sum
+// (Knuth, TAOCP vol. 2, 4.2.2) and two-product via a fused multiply-add
+// (Dekker 1971), combined as in the double-double arithmetic of Hida, Li and
+// Bailey (2001) with float limbs.
+struct df {
+    float hi, lo;
+};
+__device__ __forceinline__ df two_sum(float a, float b)
+{
+    const float s = a + b;
+    const float bb = s - a;
+    const float e = (a - (s - bb)) + (b - bb);
+    return {s, e};
+}
+__device__ __forceinline__ df fast_two_sum(float a, float b)
+{
+    const float s = a + b;
+    const float e = b - (s - a);
+    return {s, e};
+}
+__device__ __forceinline__ df df_split(double x)
+{
+    const float h = (float)x;
+    return {h, (float)(x - (double)h)};
+}
+__device__ __forceinline__ df df_add(df a, df b)
+{
+    df s = two_sum(a.hi, b.hi);
+    const df t = two_sum(a.lo, b.lo);
+    s.lo += t.hi;
+    s = fast_two_sum(s.hi, s.lo);
+    s.lo += t.lo;
+    return fast_two_sum(s.hi, s.lo);
+}
+__device__ __forceinline__ df df_mul(df a, df b)
+{
+    const float p = a.hi * b.hi;
+    float e = fmaf(a.hi, b.hi, -p);
+    const float cross = a.hi * b.lo + a.lo * b.hi;
+    e += cross;
+    return fast_two_sum(p, e);
+}
+__device__ __forceinline__ int bin_df64(double f0, double f1, double dt, const double *v,
+                                        const double *n, double t_sft)
+{
+    const df px = df_mul(df_split(v[0]), df_split(n[0]));
+    const df py = df_mul(df_split(v[1]), df_split(n[1]));
+    const df pz = df_mul(df_split(v[2]), df_split(n[2]));
+    df d = df_add(px, py);
+    d = df_add(d, pz);
+    const df g = df_add(df{1.f, 0.f}, d);
+    const df c = df_mul(df_split(f1), df_split(dt));
+    const df a = df_add(df_split(f0), c);
+    const df f = df_mul(a, g);
+    const df x = df_mul(f, df_split(t_sft));
+    const df t = df_add(x, df{0.5f, 0.f});
+    float fl = floorf(t.hi);
+    if (fl == t.hi && t.lo < 0.f) fl -= 1.f;
+    return (int)fl;
+}
+
+__device__ __forceinline__ int bin_canonical(double f0, double f1, double dt, const double *v,
+                                             const double *n, double t_sft)
+{
+    const double g = doppler_factor(v[0], v[1], v[2], n[0], n[1], n[2]);
+    return bin_fp64(f0, f1 * dt, g, t_sft);
+}
+
+// FP32 estimate accepted only when it is farther from a bin edge than its
+// error bound; otherwise the canonical FP64 bin.  The FP32 evaluation has
+// relative error below 8*2^-24 (input roundings plus five operations), so a
+// margin of 16*2^-24*x + 2^-20 bins certifies the FP32 floor.
+__device__ __forceinline__ int bin_guarded(double f0, double f1, double dt, const double *v,
+                                           const double *n, double t_sft, int *fallback)
+{
+    const float px = (float)v[0] * (float)n[0];
+    const float py = (float)v[1] * (float)n[1];
+    const float pz = (float)v[2] * (float)n[2];
+    float d = px + py;
+    d = d + pz;
+    const float g = 1.f + d;
+    const float c = (float)f1 * (float)dt;
+    const float a = (float)f0 + c;
+    const float f = a * g;
+    const float x = f * (float)t_sft;
+    const float t = x + 0.5f;
+    const float fl = floorf(t);
+    const float u = t - fl;
+    const float beta = 16.f * 5.9604645e-8f * fabsf(x) + 9.5367432e-7f;
+    if (u > beta && u < 1.f - beta) return (int)fl;
+    ++*fallback;
+    return bin_canonical(f0, f1, dt, v, n, t_sft);
+}
+
+__device__ __forceinline__ int bin_mode(int mode, double f0, double f1, double dt,
+                                        const double *v, const double *n, double t_sft,
+                                        int *fallback)
+{
+    switch (mode) {
+    case FT_INDEX_FP32: return bin_fp32(f0, f1, dt, v, n, t_sft);
+    case FT_INDEX_DF64: return bin_df64(f0, f1, dt, v, n, t_sft);
+    case FT_INDEX_GUARDED: return bin_guarded(f0, f1, dt, v, n, t_sft, fallback);
+    default: return bin_canonical(f0, f1, dt, v, n, t_sft);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Direct evaluation: one lane per template, gathers straight from the (cached)
+// table.  Used for LIST banks and for grids whose tile window would not fit
+// in LDS.
+// ---------------------------------------------------------------------------
+template <bool GRID>
+__device__ __forceinline__ void eval_direct_one(const EvalRun &r, int64_t t)
+{
+    double f0, f1;
+    const double *n;
+    if (GRID) {
+        const int64_t i = t % r.n_f0;
+        const int64_t rest = t / r.n_f0;
+        f0 = r.f0[i];
+        f1 = r.f1[rest % r.n_f1];
+        n = r.sky + 3 * (rest / r.n_f1);
+    } else {
+        f0 = r.f0[t];
+        f1 = r.f1[t];
+        n = r.sky + 3 * t;
+    }
+    const double nx = n[0], ny = n[1], nz = n[2];
+    float acc = 0.f;
+    double tot = 0.0;
+    uint32_t bad = 0;
+    for (int k = 0; k < r.n_sft; ++k) {
+        const double *vk = r.v + 3 * (int64_t)k;
+        const double g = doppler_factor(vk[0], vk[1], vk[2], nx, ny, nz);
+        const int B = bin_fp64(f0, f1 * r.dt[k], g, r.t_sft);
+        int b = B - r.first_bin;
+        if (b < 0 || b >= r.n_bins) {
+            bad = ERR_RANGE;
+            b = b < 0 ? 0 : r.n_bins - 1;
+        }
+        float val = r.power[(int64_t)k * r.n_bins + b];
+        if (r.weight) val *= r.weight[k];
+        acc += val;
+        if (r.sum_mode == FT_SUM_BLOCKED && ((k + 1) & (SUM_BLOCK - 1)) == 0) {
+            tot += (double)acc;
+            acc = 0.f;
+        }
+    }
+    if (bad) atomicOr(r.err, bad);
+    r.stats[t] = (float)(tot + (double)acc);
+}
+
+template <bool GRID>
+__global__ __launch_bounds__(256) void eval_direct_kernel(EvalRun r)
+{
+    const int64_t n_t = GRID ? (int64_t)r.n_f0 * r.n_f1 * r.n_sky : r.n_list;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n_t;
+         t += (int64_t)gridDim.x * blockDim.x)
+        eval_direct_one<GRID>(r, t);
+}
+
+__global__ __launch_bounds__(256) void bins_list_kernel(EvalRun r, int mode, int32_t *bins)
+{
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < r.n_list;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const double *n = r.sky + 3 * t;
+        int fallback = 0;
+        for (int k = 0; k < r.n_sft; ++k)
+            bins[t * r.n_sft + k] = bin_mode(mode, r.f0[t], r.f1[t], r.dt[k],
+                                             r.v + 3 * (int64_t)k, n, r.t_sft, &fallback);
+    }
+}
+
+// Index mismatches of `mode` against the canonical FP64 bin; one thread per
+// template, every SFT.
+template <bool GRID>
+__global__ __launch_bounds__(256) void mismatch_kernel(EvalRun r, int mode,
+                                                       unsigned long long *count)
+{
+    const int64_t n_t = GRID ? (int64_t)r.n_f0 * r.n_f1 * r.n_sky : r.n_list;
+    unsigned long long mism = 0;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n_t;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        double f0, f1;
+        const double *n;
+        if (GRID) {
+            const int64_t i = t % r.n_f0;
+            const int64_t rest = t / r.n_f0;
+            const int64_t j = rest % r.n_f1;
+            const int64_t s = rest / r.n_f1;
+            f0 = r.f0[i];
+            f1 = r.f1[j];
+            n = r.sky + 3 * s;
+        } else {
+            f0 = r.f0[t];
+            f1 = r.f1[t];
+            n = r.sky + 3 * t;
+        }
+        int fallback = 0;
+        for (int k = 0; k < r.n_sft; ++k) {
+            const double *vk = r.v + 3 * (int64_t)k;
+            const int ref = bin_canonical(f0, f1, r.dt[k], vk, n, r.t_sft);
+            const int got = bin_mode(mode, f0, f1, r.dt[k], vk, n, r.t_sft, &fallback);
+            mism += (ref != got);
+        }
+    }
+    // wave reduction, one atomic per wave
+    for (int off = 32; off > 0; off >>= 1) mism += __shfl_down(mism, off, 64);
+    if ((threadIdx.x & 63) == 0 && mism) atomicAdd(count, mism);
+}
+
+__global__ void check_table_kernel(const float *power, const float *weight, int64_t n_rows,
+                                   int64_t n_cols, uint32_t *err)
+{
+    const int64_t n = n_rows * n_cols;
+    bool bad = false;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const float p = power[q];
+        bad |= !(p >= 0.f && p <= 3.402823466e38f);
+    }
+    if (weight)
+        for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n_rows;
+             q += (int64_t)gridDim.x * blockDim.x) {
+            const float w = weight[q];
+            bad |= !(w >= 0.f && w <= 3.402823466e38f);
+        }
+    if (bad) atomicOr(err, ERR_BAD_POWER);
+}
+
+__global__ void fill_u32_kernel(uint32_t *p, uint32_t value, int64_t n)
+{
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
+         q += (int64_t)gridDim.x * blockDim.x)
+        p[q] = value;
+}
+
+__global__ void dt_kernel(const double *t_mid, double t_ref, double *dt, int n)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) dt[k] = t_mid[k] - t_ref;
+}
+
+// mu_G = 2 sum w and sigma_G = 2 sqrt(sum w^2) (Sec. II.B.1), sequential in
+// SFT order.
+__global__ void noise_moments_kernel(const float *weight, int n, double *mu_sigma)
+{
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    double sw = 0.0, sw2 = 0.0;
+    for (int k = 0; k < n; ++k) {
+        const double w = weight ? (double)weight[k] : 1.0;
+        sw = sw + w;
+        sw2 = sw2 + w * w;
+    }
+    mu_sigma[0] = 2.0 * sw;
+    mu_sigma[1] = 2.0 * sqrt(sw2);
+}
+
+unsigned grid_for(int64_t n, int block, unsigned cap = 1u << 20)
+{
+    int64_t g = (n + block - 1) / block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (unsigned)g;
+}
+
+}  // namespace
+
+hipError_t launch_eval_list(const EvalRun &run, hipStream_t s)
+{
+    if (run.n_list <= 0) return hipSuccess;
+    hipLaunchKernelGGL(eval_direct_kernel<false>, dim3(grid_for(run.n_list, 256, (1u << 22))),
+                       dim3(256), 0, s, run);
+    return hipGetLastError();
+}
+
+hipError_t launch_eval_grid_direct(const EvalRun &run, hipStream_t s)
+{
+    const int64_t n = (int64_t)run.n_f0 * run.n_f1 * run.n_sky;
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(eval_direct_kernel<true>, dim3(grid_for(n, 256, (1u << 22))), dim3(256),
+                       0, s, run);
+    return hipGetLastError();
+}
+
+hipError_t launch_bins_list(const EvalRun &run, int precision, int32_t *bins, hipStream_t s)
+{
+    if (run.n_list <= 0) return hipSuccess;
+    hipLaunchKernelGGL(bins_list_kernel, dim3(grid_for(run.n_list, 256, (1u << 22))), dim3(256),
+                       0, s, run, precision, bins);
+    return hipGetLastError();
+}
+
+hipError_t launch_count_mismatch(const EvalRun &run, bool grid, int precision,
+                                 unsigned long long *count, hipStream_t s)
+{
+    const int64_t n = grid ? (int64_t)run.n_f0 * run.n_f1 * run.n_sky : run.n_list;
+    if (n <= 0) return hipSuccess;
+    if (grid)
+        hipLaunchKernelGGL(mismatch_kernel<true>, dim3(grid_for(n, 256, (1u << 22))), dim3(256),
+                           0, s, run, precision, count);
+    else
+        hipLaunchKernelGGL(mismatch_kernel<false>, dim3(grid_for(n, 256, (1u << 22))),
+                           dim3(256), 0, s, run, precision, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_table(const float *power, const float *weight, int64_t n_rows,
+                              int64_t n_cols, uint32_t *err, hipStream_t s)
+{
+    hipLaunchKernelGGL(check_table_kernel, dim3(grid_for(n_rows * n_cols, 256, 4096)), dim3(256),
+                       0, s, power, weight, n_rows, n_cols, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(uint32_t *p, uint32_t value, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, p, value,
+                       n);
+    return hipGetLastError();
+}
+
+hipError_t launch_dt(const double *t_mid, double t_ref, double *dt, int n, hipStream_t s)
+{
+    hipLaunchKernelGGL(dt_kernel, dim3(grid_for(n, 256, (1u << 22))), dim3(256), 0, s, t_mid,
+                       t_ref, dt, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_noise_moments(const float *weight, int n, double *mu_sigma, hipStream_t s)
+{
+    hipLaunchKernelGGL(noise_moments_kernel, dim3(1), dim3(64), 0, s, weight, n, mu_sigma);
+    return hipGetLastError();
+}
+
+}  // namespace ft

@@ -1,0 +1,121 @@
+// Internal declarations shared by the HIP translation units of libfasttracks.
+// Every file that computes a bin index is compiled with -ffp-contract=off so
+// that the FP64 expression below is never fused into an FMA.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/fasttracks.h"
+
+namespace ft {
+
+// Device-side error flags (bit mask in a uint32 owned by the context).
+enum : uint32_t {
+    ERR_RANGE = 1u,          // a track bin left [first_bin, first_bin + n_bins)
+    ERR_WINDOW = 2u,         // a tile needed a wider LDS window than allocated
+    ERR_CAND_OVERFLOW = 4u,  // more toplist candidates than the buffer holds
+    ERR_BAD_POWER = 8u,      // non-finite or negative power / weight
+};
+
+// Blocked-summation length: FP32 partial sums over aligned blocks of this many
+// SFTs, accumulated in FP64.
+constexpr int SUM_BLOCK = 32;
+
+// ---------------------------------------------------------------------------
+// Canonical FP64 track and bin (Eq. track with a_p = 0 plus spindown).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double doppler_factor(double vx, double vy, double vz, double nx,
+                                                 double ny, double nz)
+{
+    double px = vx * nx;
+    double py = vy * ny;
+    double pz = vz * nz;
+    double d = px + py;
+    d = d + pz;
+    return 1.0 + d;
+}
+
+// floor(((f0 + c) * g) * T + 0.5) for positive arguments (truncation == floor).
+__device__ __forceinline__ int bin_fp64(double f0, double c, double g, double t_sft)
+{
+    double a = f0 + c;
+    double f = a * g;
+    double x = f * t_sft;
+    double t = x + 0.5;
+    return (int)t;
+}
+
+// The data of one evaluation: an SFT set, its velocities and a grid bank.
+struct EvalRun {
+    const float *power;   // [n_sft][n_bins]
+    const float *weight;  // [n_sft] or nullptr (all ones)
+    const double *dt;     // [n_sft] t_mid - t_ref
+    const double *v;      // [n_sft][3]
+    const double *f0;     // grid [n_f0] / list [n]
+    const double *f1;     // grid [n_f1] / list [n]
+    const double *sky;    // grid [n_sky][3] / list [n][3]
+    float *stats;         // [n_templates]
+    uint32_t *err;        // error flags
+    int32_t n_sft;
+    int32_t n_bins;
+    int32_t first_bin;
+    int32_t n_f0, n_f1, n_sky;
+    int64_t n_list;
+    double t_sft;
+    double dT;            // grid spacing * T_sft (run guard)
+    double eta;           // run-guard margin in bins
+    int32_t wt;           // LDS window width per SFT (bins, including run padding)
+    int32_t tiles_f0, tiles_f1, tiles_sky;
+    int32_t sum_mode;
+    int32_t precision;
+};
+
+// Tile configurations of the grid kernel.
+struct TileCfg {
+    int id;
+    const char *name;
+    int L;    // consecutive f0 per lane (run length)
+    int JT;   // f1 values per workgroup tile
+    int NW;   // waves per workgroup = sky points per tile
+    int KS;   // SFTs per LDS stage
+};
+int tile_count();
+const TileCfg &tile_cfg(int id);
+
+// Launchers (stream-ordered, no synchronisation).
+hipError_t launch_eval_grid(const EvalRun &run, const TileCfg &cfg, hipStream_t s);
+hipError_t launch_eval_list(const EvalRun &run, hipStream_t s);
+hipError_t launch_eval_grid_direct(const EvalRun &run, hipStream_t s);
+hipError_t launch_bins_list(const EvalRun &run, int precision, int32_t *bins, hipStream_t s);
+hipError_t launch_count_mismatch(const EvalRun &run, bool grid, int precision,
+                                 unsigned long long *count, hipStream_t s);
+hipError_t launch_check_table(const float *power, const float *weight, int64_t n_rows,
+                              int64_t n_cols, uint32_t *err, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t *p, uint32_t value, int64_t n, hipStream_t s);
+hipError_t launch_dt(const double *t_mid, double t_ref, double *dt, int n, hipStream_t s);
+hipError_t launch_noise_moments(const float *weight, int n, double *mu_sigma, hipStream_t s);
+
+// Selection: exact toplists per segment (segment = sub-band here).
+struct SelectBufs {
+    uint32_t *hist;       // [n_seg][256]
+    uint32_t *state;      // [n_seg][4]: prefix, mask, k_rem, thr_key
+    uint32_t *cnt;        // [n_seg]
+    uint32_t *off;        // [n_seg + 1]
+    uint32_t *fill;       // [n_seg]
+    int64_t *cand;        // [cap]
+    double *cand_s64;     // [cap]
+    int32_t *seg_of_f0;   // grid [n_f0] or list [n]
+    ft_candidate *out;    // [n_seg][k]
+    int32_t *n_out;       // [n_seg]
+    const double *mu_sigma;
+    int64_t cap;
+};
+hipError_t launch_subband_map(const double *f0, int64_t n, const double *edges, int n_sub,
+                              int32_t *seg, hipStream_t s);
+hipError_t launch_select(const EvalRun &run, bool grid, int n_seg, int k, double rel_err,
+                         const SelectBufs &b, hipStream_t s);
+hipError_t launch_rescore_rank(const EvalRun &run, bool grid, int n_seg, int k,
+                               const SelectBufs &b, hipStream_t s);
+
+}  // namespace ft

@@ -1,0 +1,401 @@
+// Exact per-sub-band toplists (the list of loudest candidates per region of
+// Secs. IV.B and VI) from the FP32 statistic.
+//
+// 1. Radix select (4 passes of 8-bit digits over the IEEE bits of S32, which
+//    order like the values since S32 >= 0) finds K32, the exact K-th largest
+//    FP32 statistic of each sub-band.
+// 2. Every template with S32 >= K32 (1 - 2e)/(1 + 2e) is a candidate, where e
+//    bounds |S32 - S64| / S relative to the sum: if K templates have
+//    S32 >= K32 then the K-th largest S64 is >= K32/(1 + e), so every member of
+//    the FP64 top-K has S32 >= K32 (1 - e)/(1 + e).  Candidates are compacted
+//    per sub-band.
+// 3. Each candidate is re-summed in FP64 in SFT order with canonical bins
+//    (one wavefront per candidate: lanes gather 64 SFTs at a time, the sum is
+//    then taken sequentially across lanes).
+// 4. Candidates are ranked within their sub-band by (S64 desc, index asc);
+//    ranks < K are the toplist, identical to sorting all FP64 statistics.
+#include "ft_internal.h"
+
+namespace ft {
+
+namespace {
+
+constexpr uint32_t NAN_KEY = 0x7f800000u;  // keys above this are NaN
+constexpr int ST = 8;                      // state words per segment
+enum { S_PREFIX = 0, S_MASK = 1, S_KREM = 2, S_DONE = 3, S_THR = 4 };
+
+__global__ void subband_map_kernel(const double *f0, int64_t n, const double *edges, int n_sub,
+                                   int32_t *seg)
+{
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const double f = f0[q];
+        int lo = 0, hi = n_sub;  // find the last edge <= f
+        if (!(edges[0] <= f) || !(f < edges[n_sub])) {
+            seg[q] = -1;
+            continue;
+        }
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (edges[mid] <= f) lo = mid;
+            else hi = mid;
+        }
+        seg[q] = lo;
+    }
+}
+
+// Iterate the templates of a bank as rows: GRID rows are (s, j) pairs of
+// n_f0 templates whose sub-band depends on i only; LIST rows are chunks.
+struct Rows {
+    int64_t n_rows, row_len, n_total;
+    bool grid;
+};
+
+__device__ __forceinline__ int seg_at(const int32_t *seg_of, const Rows &rw, int64_t c,
+                                      int64_t t)
+{
+    return rw.grid ? seg_of[c] : seg_of[t];
+}
+
+template <bool LDS>
+__global__ __launch_bounds__(256) void hist_kernel(const float *stats, const int32_t *seg_of,
+                                                   Rows rw, const uint32_t *state,
+                                                   uint32_t *hist, int n_seg, int shift)
+{
+    extern __shared__ uint32_t hsh[];
+    if (LDS) {
+        for (int q = threadIdx.x; q < n_seg * 256; q += blockDim.x) hsh[q] = 0;
+        __syncthreads();
+    }
+    for (int64_t row = blockIdx.x; row < rw.n_rows; row += gridDim.x) {
+        for (int64_t c = threadIdx.x; c < rw.row_len; c += blockDim.x) {
+            const int64_t t = row * rw.row_len + c;
+            if (t >= rw.n_total) break;
+            const int sg = seg_at(seg_of, rw, c, t);
+            if (sg < 0) continue;
+            const uint32_t *st = state + (int64_t)sg * ST;
+            if (st[S_DONE]) continue;
+            const uint32_t key = __float_as_uint(stats[t]);
+            if (key > NAN_KEY || (key & st[S_MASK]) != st[S_PREFIX]) continue;
+            const uint32_t digit = (key >> shift) & 255u;
+            if (LDS) atomicAdd(&hsh[sg * 256 + digit], 1u);
+            else atomicAdd(&hist[(int64_t)sg * 256 + digit], 1u);
+        }
+    }
+    if (LDS) {
+        __syncthreads();
+        for (int q = threadIdx.x; q < n_seg * 256; q += blockDim.x)
+            if (hsh[q]) atomicAdd(&hist[q], hsh[q]);
+    }
+}
+
+// One thread per segment: choose the digit holding the k_rem-th largest key.
+__global__ void scan_kernel(uint32_t *state, const uint32_t *hist, int n_seg, int shift,
+                            double two_e)
+{
+    const int sg = blockIdx.x * blockDim.x + threadIdx.x;
+    if (sg >= n_seg) return;
+    uint32_t *st = state + (int64_t)sg * ST;
+    if (st[S_DONE]) return;
+    const uint32_t *h = hist + (int64_t)sg * 256;
+    uint32_t k_rem = st[S_KREM], cum = 0;
+    int found = -1;
+    for (int d = 255; d >= 0; --d) {
+        if (cum + h[d] >= k_rem) {
+            found = d;
+            break;
+        }
+        cum += h[d];
+    }
+    if (found < 0) {  // fewer than K members: all of them are candidates
+        st[S_DONE] = 1;
+        st[S_THR] = 0;
+        return;
+    }
+    st[S_PREFIX] |= (uint32_t)found << shift;
+    st[S_MASK] |= 255u << shift;
+    st[S_KREM] = k_rem - cum;
+    if (shift == 0) {
+        const double kth = (double)__uint_as_float(st[S_PREFIX]);
+        const double thr = kth * (1.0 - two_e) / (1.0 + two_e);
+        float tf = (float)thr;
+        if ((double)tf > thr) tf = nextafterf(tf, 0.f);
+        if (!(tf > 0.f)) tf = 0.f;
+        st[S_THR] = __float_as_uint(tf);
+        st[S_DONE] = 1;
+    }
+}
+
+template <bool LDS>
+__global__ __launch_bounds__(256) void count_kernel(const float *stats, const int32_t *seg_of,
+                                                    Rows rw, const uint32_t *state,
+                                                    uint32_t *cnt, int n_seg)
+{
+    extern __shared__ uint32_t csh[];
+    if (LDS) {
+        for (int q = threadIdx.x; q < n_seg; q += blockDim.x) csh[q] = 0;
+        __syncthreads();
+    }
+    for (int64_t row = blockIdx.x; row < rw.n_rows; row += gridDim.x) {
+        for (int64_t c = threadIdx.x; c < rw.row_len; c += blockDim.x) {
+            const int64_t t = row * rw.row_len + c;
+            if (t >= rw.n_total) break;
+            const int sg = seg_at(seg_of, rw, c, t);
+            if (sg < 0) continue;
+            const uint32_t key = __float_as_uint(stats[t]);
+            if (key > NAN_KEY || key < state[(int64_t)sg * ST + S_THR]) continue;
+            if (LDS) atomicAdd(&csh[sg], 1u);
+            else atomicAdd(&cnt[sg], 1u);
+        }
+    }
+    if (LDS) {
+        __syncthreads();
+        for (int q = threadIdx.x; q < n_seg; q += blockDim.x)
+            if (csh[q]) atomicAdd(&cnt[q], csh[q]);
+    }
+}
+
+__global__ void offsets_kernel(const uint32_t *cnt, uint32_t *off, int n_seg, int64_t cap,
+                               uint32_t *err)
+{
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    uint64_t acc = 0;
+    off[0] = 0;
+    for (int s = 0; s < n_seg; ++s) {
+        acc += cnt[s];
+        off[s + 1] = (uint32_t)(acc < 0xffffffffull ? acc : 0xffffffffull);
+    }
+    if (acc > (uint64_t)cap) atomicOr(err, ERR_CAND_OVERFLOW);
+}
+
+__global__ __launch_bounds__(256) void scatter_kernel(const float *stats, const int32_t *seg_of,
+                                                      Rows rw, const uint32_t *state,
+                                                      const uint32_t *off, uint32_t *fill,
+                                                      int64_t *cand, int64_t cap)
+{
+    for (int64_t row = blockIdx.x; row < rw.n_rows; row += gridDim.x) {
+        for (int64_t c = threadIdx.x; c < rw.row_len; c += blockDim.x) {
+            const int64_t t = row * rw.row_len + c;
+            if (t >= rw.n_total) break;
+            const int sg = seg_at(seg_of, rw, c, t);
+            if (sg < 0) continue;
+            const uint32_t key = __float_as_uint(stats[t]);
+            if (key > NAN_KEY || key < state[(int64_t)sg * ST + S_THR]) continue;
+            const int64_t pos = (int64_t)off[sg] + atomicAdd(&fill[sg], 1u);
+            if (pos < cap) cand[pos] = t;
+        }
+    }
+}
+
+struct TemplateParams {
+    double f0, f1, nx, ny, nz;
+};
+
+__device__ __forceinline__ TemplateParams params_of(const EvalRun &r, bool grid, int64_t t)
+{
+    TemplateParams p;
+    int64_t s;
+    if (grid) {
+        const int64_t i = t % r.n_f0;
+        const int64_t rest = t / r.n_f0;
+        const int64_t j = rest % r.n_f1;
+        s = rest / r.n_f1;
+        p.f0 = r.f0[i];
+        p.f1 = r.f1[j];
+    } else {
+        s = t;
+        p.f0 = r.f0[t];
+        p.f1 = r.f1[t];
+    }
+    p.nx = r.sky[3 * s];
+    p.ny = r.sky[3 * s + 1];
+    p.nz = r.sky[3 * s + 2];
+    return p;
+}
+
+__device__ __forceinline__ double readlane_f64(double v, int l)
+{
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+    return __hiloint2double(hi, lo);
+}
+
+// FP64 re-summation in SFT order, one wavefront per candidate.
+__global__ __launch_bounds__(256) void rescore_kernel(EvalRun r, bool grid, const int64_t *cand,
+                                                      const uint32_t *off, int n_seg,
+                                                      int64_t cap, double *s64)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t total = min((int64_t)off[n_seg], cap);
+    const int64_t n_waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+    uint32_t bad = 0;
+    for (int64_t p = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); p < total;
+         p += n_waves) {
+        const TemplateParams tp = params_of(r, grid, cand[p]);
+        double acc = 0.0;
+        for (int k0 = 0; k0 < r.n_sft; k0 += 64) {
+            const int k = k0 + lane;
+            double val = 0.0;
+            if (k < r.n_sft) {
+                const double *vk = r.v + 3 * (int64_t)k;
+                const double g = doppler_factor(vk[0], vk[1], vk[2], tp.nx, tp.ny, tp.nz);
+                int b = bin_fp64(tp.f0, tp.f1 * r.dt[k], g, r.t_sft) - r.first_bin;
+                if (b < 0 || b >= r.n_bins) {
+                    bad = ERR_RANGE;
+                    b = b < 0 ? 0 : r.n_bins - 1;
+                }
+                const double w = r.weight ? (double)r.weight[k] : 1.0;
+                val = w * (double)r.power[(int64_t)k * r.n_bins + b];
+            }
+            const int m = min(64, r.n_sft - k0);
+            for (int l = 0; l < m; ++l) acc = acc + readlane_f64(val, l);
+        }
+        if (lane == 0) s64[p] = acc;
+    }
+    if (bad) atomicOr(r.err, bad);
+}
+
+// Rank of each candidate within its sub-band under (S64 desc, index asc).
+__global__ __launch_bounds__(256) void rank_kernel(EvalRun r, bool grid, const int64_t *cand,
+                                                   const double *s64, const uint32_t *off,
+                                                   int n_seg, int64_t cap, int k,
+                                                   const double *mu_sigma, ft_candidate *out)
+{
+    const int64_t total = min((int64_t)off[n_seg], cap);
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < total;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        int lo = 0, hi = n_seg;  // segment: off[sg] <= p < off[sg+1]
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if ((int64_t)off[mid] <= p) lo = mid;
+            else hi = mid;
+        }
+        const int sg = lo;
+        const int64_t q0 = off[sg];
+        const int64_t q1 = min((int64_t)off[sg + 1], cap);
+        const double sp = s64[p];
+        const int64_t tp = cand[p];
+        int64_t rank = 0;
+        for (int64_t q = q0; q < q1 && rank < k; ++q) {
+            const double sq = s64[q];
+            rank += (sq > sp) || (sq == sp && cand[q] < tp);
+        }
+        if (rank < k) {
+            const TemplateParams par = params_of(r, grid, tp);
+            ft_candidate c;
+            c.index = tp;
+            c.sub = sg;
+            c.s32 = r.stats[tp];
+            c.f0 = par.f0;
+            c.f1 = par.f1;
+            c.n[0] = par.nx;
+            c.n[1] = par.ny;
+            c.n[2] = par.nz;
+            c.s64 = sp;
+            c.z = (sp - mu_sigma[0]) / mu_sigma[1];
+            out[(int64_t)sg * k + rank] = c;
+        }
+    }
+}
+
+__global__ void n_out_kernel(const uint32_t *cnt, int n_seg, int k, int32_t *n_out)
+{
+    const int sg = blockIdx.x * blockDim.x + threadIdx.x;
+    if (sg < n_seg) n_out[sg] = (int32_t)min(cnt[sg], (uint32_t)k);
+}
+
+__global__ void init_state_kernel(uint32_t *state, uint32_t *cnt, uint32_t *fill, int n_seg,
+                                  int k)
+{
+    const int sg = blockIdx.x * blockDim.x + threadIdx.x;
+    if (sg >= n_seg) return;
+    uint32_t *st = state + (int64_t)sg * ST;
+    st[S_PREFIX] = 0;
+    st[S_MASK] = 0;
+    st[S_KREM] = (uint32_t)k;
+    st[S_DONE] = 0;
+    st[S_THR] = 0;
+    cnt[sg] = 0;
+    fill[sg] = 0;
+}
+
+Rows rows_of(const EvalRun &r, bool grid)
+{
+    Rows rw;
+    rw.grid = grid;
+    if (grid) {
+        rw.row_len = r.n_f0;
+        rw.n_rows = (int64_t)r.n_sky * r.n_f1;
+        rw.n_total = rw.n_rows * rw.row_len;
+    } else {
+        rw.row_len = 4096;
+        rw.n_total = r.n_list;
+        rw.n_rows = (r.n_list + rw.row_len - 1) / rw.row_len;
+    }
+    return rw;
+}
+
+unsigned blocks_for(int64_t n_rows) { return (unsigned)std::min<int64_t>(std::max<int64_t>(n_rows, 1), 8192); }
+
+}  // namespace
+
+hipError_t launch_subband_map(const double *f0, int64_t n, const double *edges, int n_sub,
+                              int32_t *seg, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const unsigned g = (unsigned)std::min<int64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(subband_map_kernel, dim3(g), dim3(256), 0, s, f0, n, edges, n_sub, seg);
+    return hipGetLastError();
+}
+
+hipError_t launch_select(const EvalRun &r, bool grid, int n_seg, int k, double rel_err,
+                         const SelectBufs &b, hipStream_t s)
+{
+    const Rows rw = rows_of(r, grid);
+    const unsigned sg_blocks = (unsigned)((n_seg + 255) / 256);
+    hipLaunchKernelGGL(init_state_kernel, dim3(sg_blocks), dim3(256), 0, s, b.state, b.cnt,
+                       b.fill, n_seg, k);
+    const bool lds_hist = n_seg * 256 <= 8192;
+    const unsigned nb = blocks_for(rw.n_rows);
+    for (int pass = 0; pass < 4; ++pass) {
+        const int shift = 24 - 8 * pass;
+        hipError_t e = launch_fill_u32(b.hist, 0u, (int64_t)n_seg * 256, s);
+        if (e != hipSuccess) return e;
+        if (lds_hist)
+            hipLaunchKernelGGL(hist_kernel<true>, dim3(nb), dim3(256),
+                               (size_t)n_seg * 256 * sizeof(uint32_t), s, r.stats, b.seg_of_f0,
+                               rw, b.state, b.hist, n_seg, shift);
+        else
+            hipLaunchKernelGGL(hist_kernel<false>, dim3(nb), dim3(256), 0, s, r.stats,
+                               b.seg_of_f0, rw, b.state, b.hist, n_seg, shift);
+        hipLaunchKernelGGL(scan_kernel, dim3(sg_blocks), dim3(256), 0, s, b.state, b.hist, n_seg,
+                           shift, 2.0 * rel_err);
+    }
+    const bool lds_cnt = n_seg <= 8192;
+    if (lds_cnt)
+        hipLaunchKernelGGL(count_kernel<true>, dim3(nb), dim3(256),
+                           (size_t)n_seg * sizeof(uint32_t), s, r.stats, b.seg_of_f0, rw,
+                           b.state, b.cnt, n_seg);
+    else
+        hipLaunchKernelGGL(count_kernel<false>, dim3(nb), dim3(256), 0, s, r.stats, b.seg_of_f0,
+                           rw, b.state, b.cnt, n_seg);
+    hipLaunchKernelGGL(offsets_kernel, dim3(1), dim3(64), 0, s, b.cnt, b.off, n_seg, b.cap,
+                       r.err);
+    hipLaunchKernelGGL(scatter_kernel, dim3(nb), dim3(256), 0, s, r.stats, b.seg_of_f0, rw,
+                       b.state, b.off, b.fill, b.cand, b.cap);
+    return hipGetLastError();
+}
+
+hipError_t launch_rescore_rank(const EvalRun &r, bool grid, int n_seg, int k,
+                               const SelectBufs &b, hipStream_t s)
+{
+    hipLaunchKernelGGL(rescore_kernel, dim3(2048), dim3(256), 0, s, r, grid, b.cand, b.off, n_seg,
+                       b.cap, b.cand_s64);
+    hipLaunchKernelGGL(rank_kernel, dim3(1024), dim3(256), 0, s, r, grid, b.cand, b.cand_s64,
+                       b.off, n_seg, b.cap, k, b.mu_sigma, b.out);
+    hipLaunchKernelGGL(n_out_kernel, dim3((unsigned)((n_seg + 255) / 256)), dim3(256), 0, s,
+                       b.cnt, n_seg, k, b.n_out);
+    return hipGetLastError();
+}
+
+}  // namespace ft

@@ -1,0 +1,296 @@
+"""Thin ctypes binding of libfasttracks (C ABI in include/fasttracks.h).
+
+Argument marshalling only: every function forwards to the C entry point of the
+same name; arrays may be numpy arrays (host) or torch tensors (host or device),
+passed as raw pointers.  All computation happens in the HIP library, which must
+be built (``paper_2411_18370_amd.build``); loading fails loudly otherwise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfasttracks.so")
+
+FT_OK, FT_E_INVALID, FT_E_STATE, FT_E_RANGE, FT_E_NOMEM, FT_E_DEVICE, FT_E_UNSUPPORTED, \
+    FT_E_INTERNAL = 0, -1, -2, -3, -4, -5, -6, -7
+FT_BANK_GRID, FT_BANK_LIST = 0, 1
+FT_INDEX_FP64, FT_INDEX_FP32, FT_INDEX_DF64, FT_INDEX_GUARDED = 0, 1, 2, 3
+FT_SUM_BLOCKED, FT_SUM_PLAIN_FP32 = 0, 1
+
+
+class FtError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__("%s: %s" % (_status_name(status), message))
+        self.status = status
+
+
+class ft_bank(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("reserved", C.c_int32), ("n_f0", C.c_int64),
+                ("n_f1", C.c_int64), ("n_sky", C.c_int64), ("n_list", C.c_int64),
+                ("f0", C.c_void_p), ("f1", C.c_void_p), ("sky_xyz", C.c_void_p)]
+
+
+class ft_eval_opts(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("k", C.c_int32), ("n_sub", C.c_int32),
+                ("sum_mode", C.c_int32), ("sub_edges", C.c_void_p), ("tile", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
+class ft_candidate(C.Structure):
+    _fields_ = [("index", C.c_int64), ("sub", C.c_int32), ("s32", C.c_float),
+                ("f0", C.c_double), ("f1", C.c_double), ("n", C.c_double * 3),
+                ("s64", C.c_double), ("z", C.c_double)]
+
+
+class ft_eval_info(C.Structure):
+    _fields_ = [("eval_ms", C.c_double), ("select_ms", C.c_double),
+                ("n_templates", C.c_int64), ("n_evals", C.c_int64),
+                ("n_candidates", C.c_int64), ("tile", C.c_int32), ("window", C.c_int32),
+                ("slow_groups", C.c_int64)]
+
+
+_lib = None
+EXPORTS = ("ft_create", "ft_destroy", "ft_last_error", "ft_status_string", "ft_set_sfts",
+           "ft_set_velocities", "ft_eval_templates", "ft_toplist", "ft_sync",
+           "ft_last_eval_info", "ft_bins", "ft_count_index_mismatches", "ft_tile_count",
+           "ft_tile_name")
+
+
+def load(path: str = LIB_PATH):
+    """Load libfasttracks.so and declare its signatures (raises if it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise FileNotFoundError(
+            "libfasttracks.so is not built (%s); run paper_2411_18370_amd.build.build()" % path)
+    lib = C.CDLL(path)
+    P, i32, i64, f64 = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    sig = {
+        "ft_create": (C.c_int, [C.POINTER(P), C.c_int, P]),
+        "ft_destroy": (None, [P]),
+        "ft_last_error": (C.c_char_p, [P]),
+        "ft_status_string": (C.c_char_p, [C.c_int]),
+        "ft_set_sfts": (C.c_int, [P, i32, P, P, f64, i64, i32, P, P]),
+        "ft_set_velocities": (C.c_int, [P, P]),
+        "ft_eval_templates": (C.c_int, [P, C.POINTER(ft_bank), f64, C.POINTER(ft_eval_opts), P]),
+        "ft_toplist": (C.c_int, [P, i32, C.POINTER(ft_candidate), C.POINTER(i32)]),
+        "ft_sync": (C.c_int, [P]),
+        "ft_last_eval_info": (C.c_int, [P, C.POINTER(ft_eval_info)]),
+        "ft_bins": (C.c_int, [P, C.POINTER(ft_bank), f64, i32, P]),
+        "ft_count_index_mismatches": (C.c_int, [P, C.POINTER(ft_bank), f64, i32,
+                                                C.POINTER(i64)]),
+        "ft_tile_count": (i32, []),
+        "ft_tile_name": (C.c_char_p, [i32]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _status_name(st):
+    try:
+        return load().ft_status_string(st).decode()
+    except Exception:
+        return str(st)
+
+
+def _check(ctx, st):
+    if st != FT_OK:
+        msg = load().ft_last_error(ctx).decode() if ctx else ""
+        raise FtError(st, msg)
+
+
+class _Arr:
+    """Pointer to a contiguous numpy array or torch tensor of a required dtype."""
+
+    def __init__(self, a, dtype):
+        self.keep = None
+        if a is None:
+            self.ptr = None
+            return
+        try:
+            import torch
+            if isinstance(a, torch.Tensor):
+                tdt = {np.float64: torch.float64, np.float32: torch.float32,
+                       np.int32: torch.int32, np.int64: torch.int64}[dtype]
+                if a.dtype != tdt:
+                    raise TypeError("expected %s, got %s" % (tdt, a.dtype))
+                a = a.contiguous()
+                self.keep = a
+                self.ptr = a.data_ptr()
+                return
+        except ImportError:
+            pass
+        a = np.ascontiguousarray(a, dtype=dtype)
+        self.keep = a
+        self.ptr = a.ctypes.data
+
+
+def ft_create(device: int = 0, stream=None):
+    """Create a context; `stream` is a hipStream_t handle (int) or None."""
+    lib = load()
+    ctx = C.c_void_p()
+    st = lib.ft_create(C.byref(ctx), device, C.c_void_p(stream) if stream else None)
+    if st != FT_OK:
+        raise FtError(st, "ft_create failed")
+    return ctx
+
+
+def ft_destroy(ctx):
+    load().ft_destroy(ctx)
+
+
+def ft_set_sfts(ctx, n_sft_per_det, t_mid, t_sft, first_bin, power, weight=None):
+    n = _Arr(np.asarray(n_sft_per_det, np.int32), np.int32)
+    tm = _Arr(t_mid, np.float64)
+    p = _Arr(power, np.float32)
+    w = _Arr(weight, np.float32)
+    n_bins = int(power.shape[1])
+    _check(ctx, load().ft_set_sfts(ctx, len(n_sft_per_det), n.ptr, tm.ptr, float(t_sft),
+                                   int(first_bin), n_bins, p.ptr, w.ptr))
+
+
+def ft_set_velocities(ctx, v_over_c):
+    v = _Arr(v_over_c, np.float64)
+    _check(ctx, load().ft_set_velocities(ctx, v.ptr))
+
+
+def _bank(f0, f1, sky, kind):
+    a0, a1, a2 = _Arr(f0, np.float64), _Arr(f1, np.float64), _Arr(sky, np.float64)
+    b = ft_bank()
+    b.kind = kind
+    if kind == FT_BANK_GRID:
+        b.n_f0, b.n_f1, b.n_sky = len(f0), len(f1), int(sky.shape[0])
+    else:
+        b.n_list = len(f0)
+    b.f0, b.f1, b.sky_xyz = a0.ptr, a1.ptr, a2.ptr
+    return b, (a0, a1, a2)
+
+
+def ft_eval_templates(ctx, f0, f1, sky, t_ref, k, sub_edges, kind=FT_BANK_GRID,
+                      precision=FT_INDEX_FP64, sum_mode=FT_SUM_BLOCKED, tile=0, stats=None):
+    """Evaluate a GRID (f0[n_f0], f1[n_f1], sky[n_sky,3]) or LIST bank; optional
+    `stats` output (float32, n_templates, host or device)."""
+    bank, keep = _bank(f0, f1, sky, kind)
+    edges = _Arr(sub_edges, np.float64)
+    o = ft_eval_opts()
+    o.precision, o.k, o.n_sub, o.sum_mode, o.tile = precision, k, len(sub_edges) - 1, \
+        sum_mode, tile
+    o.sub_edges = edges.ptr
+    s = _Arr(stats, np.float32)
+    _check(ctx, load().ft_eval_templates(ctx, C.byref(bank), float(t_ref), C.byref(o), s.ptr))
+
+
+def ft_toplist(ctx, sub, k):
+    """List of ft_candidate records of sub-band `sub` (at most k)."""
+    out = (ft_candidate * k)()
+    n = C.c_int32()
+    _check(ctx, load().ft_toplist(ctx, sub, out, C.byref(n)))
+    return [out[i] for i in range(n.value)]
+
+
+def ft_sync(ctx):
+    _check(ctx, load().ft_sync(ctx))
+
+
+def ft_last_eval_info(ctx):
+    info = ft_eval_info()
+    _check(ctx, load().ft_last_eval_info(ctx, C.byref(info)))
+    return info
+
+
+def ft_bins(ctx, f0, f1, sky, t_ref, precision=FT_INDEX_FP64):
+    """Absolute bins [n_list, N] (int32) of a LIST bank."""
+    bank, keep = _bank(f0, f1, sky, FT_BANK_LIST)
+    n_sft = _n_sft_of(ctx)
+    out = np.empty((len(f0), n_sft), np.int32)
+    _check(ctx, load().ft_bins(ctx, C.byref(bank), float(t_ref), precision,
+                               out.ctypes.data_as(C.c_void_p)))
+    return out
+
+
+def ft_count_index_mismatches(ctx, f0, f1, sky, t_ref, precision, kind=FT_BANK_GRID):
+    bank, keep = _bank(f0, f1, sky, kind)
+    n = C.c_int64()
+    _check(ctx, load().ft_count_index_mismatches(ctx, C.byref(bank), float(t_ref), precision,
+                                                 C.byref(n)))
+    return int(n.value)
+
+
+def ft_tile_count():
+    return int(load().ft_tile_count())
+
+
+def ft_tile_name(tile):
+    return load().ft_tile_name(tile).decode()
+
+
+_n_sft_cache = {}
+
+
+def _n_sft_of(ctx):
+    return _n_sft_cache[ctx.value]
+
+
+# ---------------------------------------------------------------------------
+# Convenience wrapper holding a context and the SFT count.
+# ---------------------------------------------------------------------------
+class Context:
+    def __init__(self, device=0, stream=None):
+        self.ctx = ft_create(device, stream)
+
+    def close(self):
+        if self.ctx:
+            _n_sft_cache.pop(self.ctx.value, None)
+            ft_destroy(self.ctx)
+            self.ctx = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_sfts(self, n_sft_per_det, t_mid, t_sft, first_bin, power, weight=None):
+        ft_set_sfts(self.ctx, n_sft_per_det, t_mid, t_sft, first_bin, power, weight)
+        _n_sft_cache[self.ctx.value] = int(sum(n_sft_per_det))
+
+    def set_velocities(self, v):
+        ft_set_velocities(self.ctx, v)
+
+    def eval_templates(self, *a, **kw):
+        ft_eval_templates(self.ctx, *a, **kw)
+
+    def toplist(self, sub, k):
+        return ft_toplist(self.ctx, sub, k)
+
+    def sync(self):
+        ft_sync(self.ctx)
+
+    def info(self):
+        return ft_last_eval_info(self.ctx)
+
+    def bins(self, *a, **kw):
+        return ft_bins(self.ctx, *a, **kw)
+
+    def count_index_mismatches(self, *a, **kw):
+        return ft_count_index_mismatches(self.ctx, *a, **kw)
+
+    def load_workload(self, w):
+        """Upload a synth.Workload's SFTs and velocities."""
+        self.set_sfts(w.n_sft_per_det, w.t_mid, w.t_sft, w.first_bin, w.power, w.weight)
+        self.set_velocities(w.v)
