@@ -11,6 +11,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "ft_internal.h"
@@ -35,15 +36,21 @@ struct ft_ctx_s {
     size_t cap_power = 0;
     float *d_weight = nullptr;
     size_t cap_weight = 0;
+    float *d_power_w = nullptr;
+    size_t cap_power_w = 0;
     double *d_tmid = nullptr, *d_v = nullptr, *d_dt = nullptr;
     size_t cap_tmid = 0, cap_v = 0, cap_dt = 0;
     double *d_mu_sigma = nullptr;
     uint32_t *d_err = nullptr;
 
     // bank
-    std::vector<double> f0_h, f1_h, sky_h;
-    double *d_f0 = nullptr, *d_f1 = nullptr, *d_sky = nullptr, *d_edges = nullptr;
-    size_t cap_f0 = 0, cap_f1 = 0, cap_sky = 0, cap_edges = 0;
+    std::vector<double> f0_h, f1_h, sky_h, sky_tile_h;
+    std::vector<int32_t> perm_h;
+    double *d_f0 = nullptr, *d_f1 = nullptr, *d_sky = nullptr, *d_edges = nullptr,
+           *d_sky_tile = nullptr;
+    size_t cap_f0 = 0, cap_f1 = 0, cap_sky = 0, cap_edges = 0, cap_sky_tile = 0;
+    int32_t *d_perm = nullptr;
+    size_t cap_perm = 0;
     float *d_stats = nullptr;
     size_t cap_stats = 0;
 
@@ -173,6 +180,28 @@ ft_status sync_and_check(ft_ctx c)
     return FT_OK;
 }
 
+// Doppler-coherent visiting order of the sky points: bands of equal height in
+// sin(declination), right ascension ascending in even bands and descending in
+// odd ones, about as many bands as points per band.  Consecutive points are
+// then close on the sphere, so the Doppler factors of a tile's sky points
+// differ little and its LDS window stays narrow.
+void sky_order(const std::vector<double> &sky, int64_t n, std::vector<int32_t> &perm)
+{
+    perm.resize((size_t)n);
+    const int64_t nb = std::max<int64_t>(1, (int64_t)std::llround(std::sqrt((double)n / 3.14159265358979)));
+    std::vector<std::pair<double, int32_t>> key((size_t)n);
+    for (int64_t s = 0; s < n; ++s) {
+        const double x = sky[3 * s], y = sky[3 * s + 1], z = sky[3 * s + 2];
+        int64_t band = (int64_t)std::floor((z + 1.0) * 0.5 * (double)nb);
+        band = std::min<int64_t>(std::max<int64_t>(band, 0), nb - 1);
+        double ra = std::atan2(y, x);
+        if (band & 1) ra = -ra;
+        key[(size_t)s] = {(double)band * 16.0 + ra, (int32_t)s};
+    }
+    std::sort(key.begin(), key.end());
+    for (int64_t s = 0; s < n; ++s) perm[(size_t)s] = key[(size_t)s].second;
+}
+
 int choose_tile(int64_t n_f0, int64_t n_f1, bool uniform)
 {
     if (!uniform || n_f0 < 96) return n_f1 >= 4 ? 1 : 0;
@@ -267,6 +296,7 @@ void ft_destroy(ft_ctx c)
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     release(&c->d_power, &c->cap_power);
     release(&c->d_weight, &c->cap_weight);
+    release(&c->d_power_w, &c->cap_power_w);
     release(&c->d_tmid, &c->cap_tmid);
     release(&c->d_v, &c->cap_v);
     release(&c->d_dt, &c->cap_dt);
@@ -275,6 +305,8 @@ void ft_destroy(ft_ctx c)
     release(&c->d_f0, &c->cap_f0);
     release(&c->d_f1, &c->cap_f1);
     release(&c->d_sky, &c->cap_sky);
+    release(&c->d_sky_tile, &c->cap_sky_tile);
+    release(&c->d_perm, &c->cap_perm);
     release(&c->d_edges, &c->cap_edges);
     release(&c->d_stats, &c->cap_stats);
     release(&c->d_hist, &c->cap_hist);
@@ -328,7 +360,8 @@ ft_status ft_set_sfts(ft_ctx c, int32_t n_det, const int32_t *n_sft, const doubl
     if ((e = ensure(&c->d_power, &c->cap_power, n_cells)) != hipSuccess) return hip_fail(c, e, "alloc power");
     if ((e = ensure(&c->d_tmid, &c->cap_tmid, (size_t)total)) != hipSuccess) return hip_fail(c, e, "alloc t_mid");
     if ((e = ensure(&c->d_dt, &c->cap_dt, (size_t)total)) != hipSuccess) return hip_fail(c, e, "alloc dt");
-    if (weight && (e = ensure(&c->d_weight, &c->cap_weight, (size_t)total)) != hipSuccess)
+    if (weight && ((e = ensure(&c->d_weight, &c->cap_weight, (size_t)total)) != hipSuccess ||
+                   (e = ensure(&c->d_power_w, &c->cap_power_w, n_cells)) != hipSuccess))
         return hip_fail(c, e, "alloc weight");
     e = hipMemcpyAsync(c->d_power, power, n_cells * sizeof(float), hipMemcpyDefault, c->stream);
     if (e == hipSuccess)
@@ -345,6 +378,10 @@ ft_status ft_set_sfts(ft_ctx c, int32_t n_det, const int32_t *n_sft, const doubl
     if ((e = launch_noise_moments(weight ? c->d_weight : nullptr, (int)total, c->d_mu_sigma,
                                   c->stream)) != hipSuccess)
         return hip_fail(c, e, "noise moments");
+    // The grid kernel stages w_k * P[k][b] (FP32 product) directly into LDS.
+    if (weight && (e = launch_weight_table(c->d_power, c->d_weight, c->d_power_w, total, n_bins,
+                                           c->stream)) != hipSuccess)
+        return hip_fail(c, e, "weight table");
     ft_status st = sync_and_check(c);
     if (st != FT_OK) {
         c->have_sfts = false;
@@ -470,6 +507,19 @@ static ft_status prepare_bank(ft_ctx c, const ft_bank *bank, double t_ref, EvalR
         (e = ensure(&c->d_sky, &c->cap_sky, (size_t)ns * 3)) != hipSuccess ||
         (e = ensure(&c->d_stats, &c->cap_stats, (size_t)n_t)) != hipSuccess)
         return hip_fail(c, e, "alloc bank");
+    if (grid) {
+        sky_order(c->sky_h, ns, c->perm_h);
+        c->sky_tile_h.resize((size_t)ns * 3);
+        for (int64_t s = 0; s < ns; ++s)
+            for (int d = 0; d < 3; ++d) c->sky_tile_h[3 * s + d] = c->sky_h[3 * (size_t)c->perm_h[s] + d];
+        if ((e = ensure(&c->d_sky_tile, &c->cap_sky_tile, (size_t)ns * 3)) != hipSuccess ||
+            (e = ensure(&c->d_perm, &c->cap_perm, (size_t)ns)) != hipSuccess)
+            return hip_fail(c, e, "alloc sky order");
+        e = hipMemcpyAsync(c->d_sky_tile, c->sky_tile_h.data(), ns * 3 * sizeof(double), hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(c->d_perm, c->perm_h.data(), ns * sizeof(int32_t), hipMemcpyHostToDevice, c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "upload sky order");
+    }
     e = hipMemcpyAsync(c->d_f0, c->f0_h.data(), n0 * sizeof(double), hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(c->d_f1, c->f1_h.data(), n1 * sizeof(double), hipMemcpyHostToDevice, c->stream);
@@ -480,12 +530,15 @@ static ft_status prepare_bank(ft_ctx c, const ft_bank *bank, double t_ref, EvalR
 
     run = EvalRun{};
     run.power = c->d_power;
+    run.power_w = c->has_weight ? c->d_power_w : c->d_power;
     run.weight = c->has_weight ? c->d_weight : nullptr;
     run.dt = c->d_dt;
     run.v = c->d_v;
     run.f0 = c->d_f0;
     run.f1 = c->d_f1;
     run.sky = c->d_sky;
+    run.sky_tile = grid ? c->d_sky_tile : nullptr;
+    run.sky_perm = grid ? c->d_perm : nullptr;
     run.stats = c->d_stats;
     run.err = c->d_err;
     run.n_sft = c->n_sft;
@@ -504,8 +557,12 @@ static ft_status prepare_bank(ft_ctx c, const ft_bank *bank, double t_ref, EvalR
         for (int64_t i = 0; i < n0; ++i)
             tau = std::max(tau, std::fabs(c->f0_h[i] - c->f0_h[0] - (double)i * (dT / T)));
         tau += 8.0 * std::ldexp(f0_max, -52);
-        const double rho1 = 6.0 * std::ldexp(x_max, -53);
-        double eta = 2.0 * (2.0 * rho1 + 2.0 * tau * (1.0 + c->vmax) * T + 8.0 * std::ldexp(1.0, -52));
+        // eta bounds, in bins: the rounding of the canonical x + 1/2 and of the
+        // estimate (f0 + c + 1/(2 g T)) * (g T) (each below 6 * 2^-53 * x_max),
+        // the grid's deviation tau from uniform spacing, and the rounding of the
+        // per-SFT drift e = dT*g - 1 over a run; doubled for margin.
+        const double rho = 6.0 * std::ldexp(x_max, -53);
+        double eta = 2.0 * (2.0 * rho + 2.0 * tau * (1.0 + c->vmax) * T + std::ldexp(1.0, -40));
         run.dT = dT;
         run.eta = eta;
         (void)dt_min;
@@ -613,12 +670,13 @@ ft_status ft_eval_templates(ft_ctx c, const ft_bank *bank, double t_ref, const f
             span_f1 = std::max(span_f1, hi - lo);
         }
         double diam = 0.0;
+        const std::vector<double> &st = c->sky_tile_h;
         for (int64_t s0 = 0; s0 < ns; s0 += cfg.NW)
             for (int64_t a = s0; a < std::min<int64_t>(s0 + cfg.NW, ns); ++a)
                 for (int64_t b2 = a + 1; b2 < std::min<int64_t>(s0 + cfg.NW, ns); ++b2) {
-                    const double dx = c->sky_h[3 * a] - c->sky_h[3 * b2];
-                    const double dy = c->sky_h[3 * a + 1] - c->sky_h[3 * b2 + 1];
-                    const double dz = c->sky_h[3 * a + 2] - c->sky_h[3 * b2 + 2];
+                    const double dx = st[3 * a] - st[3 * b2];
+                    const double dy = st[3 * a + 1] - st[3 * b2 + 1];
+                    const double dz = st[3 * a + 2] - st[3 * b2 + 2];
                     diam = std::max(diam, std::sqrt(dx * dx + dy * dy + dz * dz));
                 }
         double f1_absmax = 0.0;
@@ -627,10 +685,12 @@ ft_status ft_eval_templates(ft_ctx c, const ft_bank *bank, double t_ref, const f
         const double width = (span_f0 + span_f1 * dt_absmax) * (1.0 + c->vmax) * T +
                              a_max * c->vmax * diam * (1.0 + 1e-9) * T;
         const double wt = std::ceil(width * (1.0 + 1e-9)) + 3.0 + cfg.L;
+        const double wtp = std::ceil(wt / 64.0) * 64.0;
         // A window beyond the LDS budget (extreme Doppler spread or a very
-        // wide f1 tile) falls back to the direct kernel (tile id 0).
-        if (wt * cfg.KS * 4.0 > 96.0 * 1024.0) tile = -1;
+        // wide f1 tile) falls back to the direct kernel.
+        if (2.0 * wtp * cfg.KS * 4.0 + (double)tile_static_lds(tile) > 150.0 * 1024.0) tile = -1;
         run.wt = (int32_t)std::min(wt, 1e9);
+        run.wtp = (int32_t)std::min(wtp, 1e9);
         run.tiles_f0 = (int32_t)((n0 + 64 * cfg.L - 1) / (64 * cfg.L));
         run.tiles_f1 = (int32_t)((n1 + cfg.JT - 1) / cfg.JT);
         run.tiles_sky = (int32_t)((ns + cfg.NW - 1) / cfg.NW);

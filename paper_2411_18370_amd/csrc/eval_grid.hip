@@ -4,26 +4,32 @@
 //
 // Workgroup tile: 64*L consecutive f0 values (lane l owns the run
 // [i0, i0 + L), i0 = tile_start + l*L) x JT f1 values x NW sky points (one per
-// wave).  SFTs are processed in stages of KS.  Per stage the workgroup
-//   A. computes the Doppler factor g[s][k] of its sky points and c[j][k] =
-//      f1_j * dt_k of its f1 values (FP64, canonical order);
-//   B. derives, per SFT, the exact bin range [lo, hi] of the whole tile.  The
-//      FP64 bin is monotone in each of f0, c and g, and the tile is a
-//      Cartesian product, so lo/hi are the bins of two actual templates: the
-//      range check against the table is exact, and hi - lo bounds the window;
-//   C. copies row k of the power table, columns [lo, lo + wt), into LDS
-//      (coalesced), pre-multiplied by the SFT weight;
-//   D. accumulates: each lane computes the canonical FP64 bin B of the first
-//      template of its run and reads B, B+1, ..., B+L-1 from LDS.
+// wave; sky points are visited in a Doppler-coherent order chosen by the
+// host).  SFTs are processed in stages of KS, double-buffered: while stage p
+// is accumulated, the parameters of stage p+1 are derived and its table
+// windows stream from HBM/L2 straight into LDS (global_load_lds).
+//   prepare(p): Doppler factor g[s][k] (canonical FP64 order), G = g*T_sft,
+//      run-guard bounds, c[j][k] = f1_j*dt_k and c' = c + 1/(2G); then the
+//      exact bin range [lo, hi] of the tile per SFT.  The FP64 bin is monotone
+//      in each of f0, c and g and the tile is a Cartesian product, so lo/hi
+//      are bins of actual templates: the range check against the table is
+//      exact and hi - lo bounds the window.
+//   stage(p): row k of the (weighted) power table, columns [lo, lo + wtp),
+//      into LDS; columns are clamped into the table (a column outside it can
+//      only be read after a range error, which is reported).
+//   accumulate(p): for every f1 value each lane forms the estimate
+//      t~ = (f0 + c')*G of x + 1/2 for the first template of its run, takes
+//      B = floor(t~) and reads B, B+1, ..., B+L-1 from LDS (immediate
+//      offsets; consecutive lanes hit consecutive banks for odd L).
 //
-// Run guard (exactness of B + l).  With u = (x + 1/2) - B in [0, 1) and
-// e = dT*g - 1 (dT = grid spacing * T_sft), the exact position of template l
-// of the run is u + l*e + err with |err| <= eta, where eta bounds the FP64
-// rounding of both evaluations and the grid's deviation from uniform spacing
-// (computed on the host).  If u + l*e stays inside [eta, 1 - eta) for l = 1 and
-// l = L-1 (and so for all l, by linearity) then floor = B + l exactly.  When
-// any lane of the wave fails the guard the wave recomputes every template of
-// the run with the canonical FP64 expression.
+// Run guard.  |t~ - (x + 1/2)| and the rounding of every canonical evaluation
+// are bounded by the host, together with the grid's deviation from uniform
+// spacing dT/T_sft, by eta.  With u = t~ - B and e = dT*g - 1, template l of
+// the run has canonical floor(x_l + 1/2) = B + l whenever u + l*e lies in
+// [eta, 1 - eta) for every l in [0, L) -- checked at l = 0 and l = L-1 (the
+// expression is linear in l).  If any lane of the wave fails for any f1 value
+// the wave evaluates every template of the step with the canonical FP64
+// expression.  Either way every bin equals the canonical FP64 bin.
 //
 // Sums: FP32 within aligned blocks of 32 SFTs, block sums accumulated in FP64.
 #include "ft_internal.h"
@@ -33,24 +39,131 @@ namespace ft {
 namespace {
 
 template <int L, int JT, int NW, int KS>
-struct Shared {
-    double g[NW][KS];
-    double ulo[NW][KS];
+struct StageParams {
+    double g[NW][KS];       // canonical Doppler factor
+    double G[NW][KS];       // g * T_sft
+    double ulo[NW][KS];     // run-guard bounds on u
     double uhi[NW][KS];
-    double c[JT][KS];
-    int lo[KS];
+    double c[JT][KS];       // canonical f1 * dt
+    double cp[NW][JT][KS];  // c + 1/(2G)
+    int lo[KS];             // first staged bin
+};
+
+template <int L, int JT, int NW, int KS>
+struct Shared {
+    StageParams<L, JT, NW, KS> p[2];
+    double f0[64 * L];
     int tile_bad;
 };
+
+__device__ __forceinline__ bool wave_all(bool p)
+{
+    return __builtin_amdgcn_ballot_w64(!p) == 0;
+}
+
+// LDS read of the rare guard-fallback path.  A volatile access keeps the
+// compiler from merging it with the fast path's reads (which would force
+// computed addresses on the fast path instead of immediate offsets).
+__device__ __forceinline__ float slow_read(const float *p)
+{
+    return *(const volatile float *)p;
+}
+
+__device__ __forceinline__ void wait_loads()
+{
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+}
+
+struct TileGeom {
+    int i_base, i_last, n_in, j_base, j_last, s_base, s_last;
+    double f0min, f0max;
+};
+
+// Parameters and exact window of SFT stage [k0, k0 + ks) of a tile.  Two
+// barriers; returns false if the tile's window does not fit (flagged).
+template <int L, int JT, int NW, int KS>
+__device__ __forceinline__ bool prepare_stage(const EvalRun &r, const TileGeom &tg, int k0,
+                                              int ks, StageParams<L, JT, NW, KS> &P,
+                                              Shared<L, JT, NW, KS> &sh)
+{
+    const int nthreads = 64 * NW;
+    const double T = r.t_sft;
+    for (int q = threadIdx.x; q < NW * KS; q += nthreads) {
+        const int sl = q / KS, kk = q % KS;
+        if (kk < ks) {
+            const int s = min(tg.s_base + sl, tg.s_last);
+            const double *vk = r.v + 3 * (int64_t)(k0 + kk);
+            const double *n = r.sky_tile + 3 * (int64_t)s;
+            const double g = doppler_factor(vk[0], vk[1], vk[2], n[0], n[1], n[2]);
+            P.g[sl][kk] = g;
+            P.G[sl][kk] = g * T;
+            if (L > 1) {
+                const double eL = (double)(L - 1) * (r.dT * g - 1.0);
+                P.ulo[sl][kk] = r.eta + fmax(0.0, -eL);
+                P.uhi[sl][kk] = (1.0 - r.eta) - fmax(0.0, eL);
+            }
+        }
+    }
+    for (int q = threadIdx.x; q < JT * KS; q += nthreads) {
+        const int jl = q / KS, kk = q % KS;
+        if (kk < ks) P.c[jl][kk] = r.f1[min(tg.j_base + jl, tg.j_last)] * r.dt[k0 + kk];
+    }
+    __syncthreads();
+    if (L > 1)
+        for (int q = threadIdx.x; q < NW * JT * KS; q += nthreads) {
+            const int sl = q / (JT * KS), jl = (q / KS) % JT, kk = q % KS;
+            if (kk < ks) P.cp[sl][jl][kk] = P.c[jl][kk] + 0.5 / P.G[sl][kk];
+        }
+    for (int kk = threadIdx.x; kk < ks; kk += nthreads) {
+        double gmin = P.g[0][kk], gmax = gmin;
+#pragma unroll
+        for (int sl = 1; sl < NW; ++sl) {
+            gmin = fmin(gmin, P.g[sl][kk]);
+            gmax = fmax(gmax, P.g[sl][kk]);
+        }
+        double cmin = P.c[0][kk], cmax = cmin;
+#pragma unroll
+        for (int jl = 1; jl < JT; ++jl) {
+            cmin = fmin(cmin, P.c[jl][kk]);
+            cmax = fmax(cmax, P.c[jl][kk]);
+        }
+        const int lo = bin_fp64(tg.f0min, cmin, gmin, T);
+        const int hi = bin_fp64(tg.f0max, cmax, gmax, T);
+        uint32_t bad = 0;
+        if (lo < r.first_bin || hi - r.first_bin >= r.n_bins) bad |= ERR_RANGE;
+        if (hi - lo + L > r.wt) bad |= ERR_WINDOW;
+        if (bad) {
+            atomicOr(r.err, bad);
+            if (bad & ERR_WINDOW) sh.tile_bad = 1;
+        }
+        P.lo[kk] = lo;
+    }
+    __syncthreads();
+    return sh.tile_bad == 0;
+}
+
+// Issue the HBM/L2 -> LDS copies of a stage's windows (asynchronous).
+template <int L, int JT, int NW, int KS>
+__device__ __forceinline__ void stage_windows(const EvalRun &r, int k0, int ks,
+                                              const StageParams<L, JT, NW, KS> &P, float *wbuf)
+{
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int wtp = r.wtp;
+    for (int kk = wave; kk < ks; kk += NW) {
+        const float *row = r.power_w + (int64_t)(k0 + kk) * r.n_bins;
+        const int col0 = P.lo[kk] - r.first_bin + lane;
+        for (int x0 = 0; x0 < wtp; x0 += 64) {
+            const int col = min(max(col0 + x0, 0), r.n_bins - 1);
+            __builtin_amdgcn_global_load_lds(row + col, wbuf + kk * wtp + x0, 4, 0, 0);
+        }
+    }
+}
 
 template <int L, int JT, int NW, int KS>
 __device__ __forceinline__ void eval_tile(const EvalRun &r, int64_t b, float *win,
                                           Shared<L, JT, NW, KS> &sh)
 {
-    auto &g_sh = sh.g;
-    auto &ulo_sh = sh.ulo;
-    auto &uhi_sh = sh.uhi;
-    auto &c_sh = sh.c;
-    auto &lo_sh = sh.lo;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int nthreads = 64 * NW;
@@ -60,19 +173,27 @@ __device__ __forceinline__ void eval_tile(const EvalRun &r, int64_t b, float *wi
     const int tf1 = (int)(rest % r.tiles_f1);
     const int tf0 = (int)(rest / r.tiles_f1);
 
-    const int i_base = tf0 * 64 * L;
-    const int i_last = min(i_base + 64 * L, r.n_f0) - 1;
-    const int j_base = tf1 * JT;
-    const int j_last = min(j_base + JT, r.n_f1) - 1;
-    const int s_base = tsky * NW;
-    const int s_last = min(s_base + NW, r.n_sky) - 1;
+    TileGeom tg;
+    tg.i_base = tf0 * 64 * L;
+    tg.i_last = min(tg.i_base + 64 * L, r.n_f0) - 1;
+    tg.n_in = tg.i_last - tg.i_base + 1;
+    tg.j_base = tf1 * JT;
+    tg.j_last = min(tg.j_base + JT, r.n_f1) - 1;
+    tg.s_base = tsky * NW;
+    tg.s_last = min(tg.s_base + NW, r.n_sky) - 1;
+    tg.f0min = r.f0[tg.i_base];
+    tg.f0max = r.f0[tg.i_last];
 
     const double T = r.t_sft;
-    const double f0min = r.f0[i_base];
-    const double f0max = r.f0[i_last];
-    const int i0 = i_base + lane * L;
-    const double f0_lane = r.f0[min(i0, i_last)];
-    const int wt = r.wt;
+    const int i0 = tg.i_base + lane * L;
+    const double f0_lane = r.f0[min(i0, tg.i_last)];
+    const int wtp = r.wtp;
+
+    __syncthreads();  // the previous tile's threads are done with the shared state
+    if (threadIdx.x == 0) sh.tile_bad = 0;
+    if (L > 1)
+        for (int q = threadIdx.x; q < 64 * L; q += nthreads)
+            sh.f0[q] = r.f0[tg.i_base + min(q, tg.n_in - 1)];
 
     float acc[JT][L];
     double tot[JT][L];
@@ -84,106 +205,62 @@ __device__ __forceinline__ void eval_tile(const EvalRun &r, int64_t b, float *wi
             tot[j][l] = 0.0;
         }
 
-    __syncthreads();  // the previous tile's threads are done with the shared state
-    if (threadIdx.x == 0) sh.tile_bad = 0;
-    for (int k0 = 0; k0 < r.n_sft; k0 += KS) {
+    const int n_stage = (r.n_sft + KS - 1) / KS;
+    if (!prepare_stage<L, JT, NW, KS>(r, tg, 0, min(KS, r.n_sft), sh.p[0], sh)) return;
+    stage_windows<L, JT, NW, KS>(r, 0, min(KS, r.n_sft), sh.p[0], win);
+    wait_loads();
+    __syncthreads();
+
+    for (int p = 0; p < n_stage; ++p) {
+        const int k0 = p * KS;
         const int ks = min(KS, r.n_sft - k0);
-        // --- A: Doppler factors, guard bounds, spindown offsets -------------
-        for (int q = threadIdx.x; q < NW * KS; q += nthreads) {
-            const int sl = q / KS, kk = q % KS;
-            if (kk < ks) {
-                const int s = min(s_base + sl, s_last);
-                const double *vk = r.v + 3 * (int64_t)(k0 + kk);
-                const double *n = r.sky + 3 * (int64_t)s;
-                const double g = doppler_factor(vk[0], vk[1], vk[2], n[0], n[1], n[2]);
-                g_sh[sl][kk] = g;
-                if (L > 1) {
-                    const double e = r.dT * g - 1.0;
-                    const double eL = (double)(L - 1) * e;
-                    ulo_sh[sl][kk] = r.eta + fmax(-e, -eL);
-                    uhi_sh[sl][kk] = (1.0 - r.eta) - fmax(e, eL);
+        const int cur = p & 1;
+        if (p + 1 < n_stage) {
+            const int k1 = k0 + KS;
+            const int ks1 = min(KS, r.n_sft - k1);
+            if (!prepare_stage<L, JT, NW, KS>(r, tg, k1, ks1, sh.p[cur ^ 1], sh)) return;
+            stage_windows<L, JT, NW, KS>(r, k1, ks1, sh.p[cur ^ 1], win + (cur ^ 1) * KS * wtp);
+        }
+        const StageParams<L, JT, NW, KS> &P = sh.p[cur];
+        const float *wb = win + cur * KS * wtp;
+        for (int kk = 0; kk < ks; ++kk) {
+            const int base = kk * wtp - P.lo[kk];
+            if (L == 1) {
+                const double g = P.g[wave][kk];
+#pragma unroll
+                for (int jl = 0; jl < JT; ++jl) {
+                    const int B = bin_fp64(f0_lane, P.c[jl][kk], g, T);
+                    acc[jl][0] += wb[base + B];
                 }
-            }
-        }
-        for (int q = threadIdx.x; q < JT * KS; q += nthreads) {
-            const int jl = q / KS, kk = q % KS;
-            if (kk < ks) c_sh[jl][kk] = r.f1[min(j_base + jl, j_last)] * r.dt[k0 + kk];
-        }
-        __syncthreads();
-        // --- B: exact bin range of the tile per SFT -------------------------
-        for (int kk = threadIdx.x; kk < ks; kk += nthreads) {
-            double gmin = g_sh[0][kk], gmax = gmin;
+            } else {
+                const double G = P.G[wave][kk];
+                const double ulo = P.ulo[wave][kk], uhi = P.uhi[wave][kk];
+                int B[JT];
+                bool ok = true;
 #pragma unroll
-            for (int sl = 1; sl < NW; ++sl) {
-                gmin = fmin(gmin, g_sh[sl][kk]);
-                gmax = fmax(gmax, g_sh[sl][kk]);
-            }
-            double cmin = c_sh[0][kk], cmax = cmin;
+                for (int jl = 0; jl < JT; ++jl) {
+                    const double a = f0_lane + P.cp[wave][jl][kk];
+                    const double t = a * G;
+                    B[jl] = (int)t;
+                    const double u = __builtin_amdgcn_fract(t);
+                    ok = ok && (u >= ulo) && (u < uhi);
+                }
+                if (wave_all(ok)) {
 #pragma unroll
-            for (int jl = 1; jl < JT; ++jl) {
-                cmin = fmin(cmin, c_sh[jl][kk]);
-                cmax = fmax(cmax, c_sh[jl][kk]);
-            }
-            const int lo = bin_fp64(f0min, cmin, gmin, T);
-            const int hi = bin_fp64(f0max, cmax, gmax, T);
-            uint32_t bad = 0;
-            if (lo < r.first_bin || hi - r.first_bin >= r.n_bins) bad |= ERR_RANGE;
-            if (hi - lo + L > wt) bad |= ERR_WINDOW;
-            if (bad) {
-                atomicOr(r.err, bad);
-                if (bad & ERR_WINDOW) sh.tile_bad = 1;
-            }
-            lo_sh[kk] = lo;
-        }
-        __syncthreads();
-        // A window wider than the allocation would read outside this SFT's
-        // slice: the error is flagged and the tile's result is abandoned.
-        if (sh.tile_bad) return;
-        // --- C: stage the windows ------------------------------------------
-        for (int kk = 0; kk < ks; ++kk) {
-            const int col0 = lo_sh[kk] - r.first_bin;
-            const float *row = r.power + (int64_t)(k0 + kk) * r.n_bins;
-            const float w = r.weight ? r.weight[k0 + kk] : 1.f;
-            for (int x = threadIdx.x; x < wt; x += nthreads) {
-                const int col = col0 + x;
-                float val = (col >= 0 && col < r.n_bins) ? row[col] : 0.f;
-                win[kk * wt + x] = val * w;
-            }
-        }
-        __syncthreads();
-        // --- D: gather and accumulate --------------------------------------
-        for (int kk = 0; kk < ks; ++kk) {
-            const double g = g_sh[wave][kk];
-            const int base = kk * wt - lo_sh[kk];
-            double ulo = 0.0, uhi = 1.0;
-            if (L > 1) {
-                ulo = ulo_sh[wave][kk];
-                uhi = uhi_sh[wave][kk];
-            }
-#pragma unroll
-            for (int jl = 0; jl < JT; ++jl) {
-                const double c = c_sh[jl][kk];
-                const double a = f0_lane + c;
-                const double f = a * g;
-                const double x = f * T;
-                const double t = x + 0.5;
-                const int B = (int)t;
-                const float *wp = win + (base + B);
-                if (L == 1) {
-                    acc[jl][0] += wp[0];
-                } else {
-                    const double u = t - (double)B;
-                    const bool ok = (u >= ulo) && (u < uhi);
-                    if (__all(ok)) {
+                    for (int jl = 0; jl < JT; ++jl) {
+                        const float *wp = wb + (base + B[jl]);
 #pragma unroll
                         for (int l = 0; l < L; ++l) acc[jl][l] += wp[l];
-                    } else {
+                    }
+                } else {
+                    // rare: some lane is within the guard margin of a bin edge
+                    const double g = P.g[wave][kk];
 #pragma unroll
-                        for (int l = 0; l < L; ++l) {
-                            const int il = min(i0 + l, i_last);
-                            const int Bl = bin_fp64(r.f0[il], c, g, T);
-                            acc[jl][l] += win[base + Bl];
-                        }
+                    for (int l = 0; l < L; ++l) {
+                        const double f0l = sh.f0[min(lane * L + l, tg.n_in - 1)];
+#pragma unroll
+                        for (int jl = 0; jl < JT; ++jl)
+                            acc[jl][l] += slow_read(wb + (base + bin_fp64(f0l, P.c[jl][kk], g, T)));
                     }
                 }
             }
@@ -197,21 +274,23 @@ __device__ __forceinline__ void eval_tile(const EvalRun &r, int64_t b, float *wi
                     }
             }
         }
+        wait_loads();
         __syncthreads();
     }
 
-    // --- epilogue: write the statistic -------------------------------------
-    const int s = s_base + wave;
-    if (s > s_last) return;
+    // --- epilogue: write the statistic (original sky order) ----------------
+    const int s = tg.s_base + wave;
+    if (s > tg.s_last) return;
+    const int64_t s_orig = r.sky_perm ? r.sky_perm[s] : s;
 #pragma unroll
     for (int jl = 0; jl < JT; ++jl) {
-        const int j = j_base + jl;
-        if (j > j_last) continue;
-        const int64_t row = ((int64_t)s * r.n_f1 + j) * r.n_f0;
+        const int j = tg.j_base + jl;
+        if (j > tg.j_last) continue;
+        const int64_t row = (s_orig * r.n_f1 + j) * r.n_f0;
 #pragma unroll
         for (int l = 0; l < L; ++l) {
             const int i = i0 + l;
-            if (i <= i_last) r.stats[row + i] = (float)(tot[jl][l] + (double)acc[jl][l]);
+            if (i <= tg.i_last) r.stats[row + i] = (float)(tot[jl][l] + (double)acc[jl][l]);
         }
     }
 }
@@ -223,7 +302,7 @@ __device__ __forceinline__ void eval_tile(const EvalRun &r, int64_t b, float *wi
 template <int L, int JT, int NW, int KS>
 __global__ __launch_bounds__(64 * NW) void eval_grid_kernel(EvalRun r)
 {
-    extern __shared__ float win[];  // [KS][wt]
+    extern __shared__ float win[];  // [2][KS][wtp]
     __shared__ Shared<L, JT, NW, KS> sh;
     const int64_t nt = (int64_t)r.tiles_f0 * r.tiles_f1 * r.tiles_sky;
     const int64_t full = nt - (nt & 7);
@@ -238,7 +317,7 @@ hipError_t launch_t(const EvalRun &r, hipStream_t s)
 {
     const int64_t nt = (int64_t)r.tiles_f0 * r.tiles_f1 * r.tiles_sky;
     if (nt <= 0) return hipSuccess;
-    const size_t lds = (size_t)KS * r.wt * sizeof(float);
+    const size_t lds = (size_t)2 * KS * r.wtp * sizeof(float);
     // at most 2^22 blocks (work-items stay below 2^32); a multiple of 8 keeps
     // every block's tiles on one XCD
     int64_t grid = nt < (1 << 22) ? nt : (1 << 22);
@@ -253,22 +332,28 @@ using Launcher = hipError_t (*)(const EvalRun &, hipStream_t);
 struct TileEntry {
     TileCfg cfg;
     Launcher fn;
+    size_t static_lds;
 };
 
-#define FT_TILE(id, L, JT, NW, KS) \
-    {{id, "L" #L "_J" #JT "_W" #NW "_K" #KS, L, JT, NW, KS}, &launch_t<L, JT, NW, KS>}
+#define FT_TILE(id, L, JT, NW, KS)                                                       \
+    {{id, "L" #L "_J" #JT "_W" #NW "_K" #KS, L, JT, NW, KS}, &launch_t<L, JT, NW, KS>, \
+     sizeof(Shared<L, JT, NW, KS>)}
 
 const TileEntry kTiles[] = {
-    FT_TILE(0, 1, 1, 4, 32),
-    FT_TILE(1, 1, 4, 4, 32),
-    FT_TILE(2, 3, 4, 4, 32),
-    FT_TILE(3, 5, 4, 4, 32),
-    FT_TILE(4, 5, 3, 4, 32),
-    FT_TILE(5, 7, 3, 4, 32),
-    FT_TILE(6, 5, 6, 4, 32),
-    FT_TILE(7, 3, 6, 4, 32),
-    FT_TILE(8, 5, 4, 4, 16),
-    FT_TILE(9, 3, 4, 4, 16),
+    FT_TILE(0, 1, 1, 4, 16),
+    FT_TILE(1, 1, 4, 4, 16),
+    FT_TILE(2, 3, 4, 4, 16),
+    FT_TILE(3, 5, 4, 4, 16),
+    FT_TILE(4, 5, 3, 4, 16),
+    FT_TILE(5, 7, 3, 4, 16),
+    FT_TILE(6, 5, 6, 4, 8),
+    FT_TILE(7, 3, 6, 4, 16),
+    FT_TILE(8, 5, 4, 4, 8),
+    FT_TILE(9, 5, 4, 8, 8),
+    FT_TILE(10, 3, 4, 8, 16),
+    FT_TILE(11, 7, 2, 4, 16),
+    FT_TILE(12, 9, 2, 4, 16),
+    FT_TILE(13, 3, 8, 4, 8),
 };
 
 }  // namespace
@@ -276,6 +361,8 @@ const TileEntry kTiles[] = {
 int tile_count() { return (int)(sizeof(kTiles) / sizeof(kTiles[0])); }
 
 const TileCfg &tile_cfg(int id) { return kTiles[id].cfg; }
+
+size_t tile_static_lds(int id) { return kTiles[id].static_lds; }
 
 hipError_t launch_eval_grid(const EvalRun &run, const TileCfg &cfg, hipStream_t s)
 {

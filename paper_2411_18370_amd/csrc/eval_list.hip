@@ -259,6 +259,14 @@ __global__ void check_table_kernel(const float *power, const float *weight, int6
     if (bad) atomicOr(err, ERR_BAD_POWER);
 }
 
+__global__ void weight_table_kernel(const float *power, const float *weight, float *out,
+                                    int64_t n_rows, int64_t n_cols)
+{
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n_rows * n_cols;
+         q += (int64_t)gridDim.x * blockDim.x)
+        out[q] = power[q] * weight[q / n_cols];
+}
+
 __global__ void fill_u32_kernel(uint32_t *p, uint32_t value, int64_t n)
 {
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
@@ -341,6 +349,14 @@ hipError_t launch_check_table(const float *power, const float *weight, int64_t n
 {
     hipLaunchKernelGGL(check_table_kernel, dim3(grid_for(n_rows * n_cols, 256, 4096)), dim3(256),
                        0, s, power, weight, n_rows, n_cols, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_weight_table(const float *power, const float *weight, float *out,
+                               int64_t n_rows, int64_t n_cols, hipStream_t s)
+{
+    hipLaunchKernelGGL(weight_table_kernel, dim3(grid_for(n_rows * n_cols, 256, 8192)), dim3(256),
+                       0, s, power, weight, out, n_rows, n_cols);
     return hipGetLastError();
 }
 

@@ -49,12 +49,15 @@ __device__ __forceinline__ int bin_fp64(double f0, double c, double g, double t_
 // The data of one evaluation: an SFT set, its velocities and a grid bank.
 struct EvalRun {
     const float *power;   // [n_sft][n_bins]
+    const float *power_w; // [n_sft][n_bins], w_k * P[k][b] in FP32 (== power without weights)
     const float *weight;  // [n_sft] or nullptr (all ones)
     const double *dt;     // [n_sft] t_mid - t_ref
     const double *v;      // [n_sft][3]
     const double *f0;     // grid [n_f0] / list [n]
     const double *f1;     // grid [n_f1] / list [n]
     const double *sky;    // grid [n_sky][3] / list [n][3]
+    const double *sky_tile;   // grid: sky points in tile (Doppler-coherent) order
+    const int32_t *sky_perm;  // grid: tile position -> original sky index
     float *stats;         // [n_templates]
     uint32_t *err;        // error flags
     int32_t n_sft;
@@ -66,6 +69,7 @@ struct EvalRun {
     double dT;            // grid spacing * T_sft (run guard)
     double eta;           // run-guard margin in bins
     int32_t wt;           // LDS window width per SFT (bins, including run padding)
+    int32_t wtp;          // wt rounded up to a multiple of 64 (LDS row stride)
     int32_t tiles_f0, tiles_f1, tiles_sky;
     int32_t sum_mode;
     int32_t precision;
@@ -82,6 +86,7 @@ struct TileCfg {
 };
 int tile_count();
 const TileCfg &tile_cfg(int id);
+size_t tile_static_lds(int id);
 
 // Launchers (stream-ordered, no synchronisation).
 hipError_t launch_eval_grid(const EvalRun &run, const TileCfg &cfg, hipStream_t s);
@@ -92,6 +97,8 @@ hipError_t launch_count_mismatch(const EvalRun &run, bool grid, int precision,
                                  unsigned long long *count, hipStream_t s);
 hipError_t launch_check_table(const float *power, const float *weight, int64_t n_rows,
                               int64_t n_cols, uint32_t *err, hipStream_t s);
+hipError_t launch_weight_table(const float *power, const float *weight, float *out,
+                               int64_t n_rows, int64_t n_cols, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t value, int64_t n, hipStream_t s);
 hipError_t launch_dt(const double *t_mid, double t_ref, double *dt, int n, hipStream_t s);
 hipError_t launch_noise_moments(const float *weight, int n, double *mu_sigma, hipStream_t s);
