@@ -75,6 +75,21 @@ def detector_velocity(t_mid: np.ndarray, det: Detector) -> np.ndarray:
     return np.stack([vx, vy, vz], axis=1) / C_LIGHT
 
 
+def detector_arms(t_mid: np.ndarray, det: Detector) -> np.ndarray:
+    """Arm unit vectors [N, 6] = (u, w) in equatorial coordinates at the mid-times:
+    local North/East frame of the detector rotated with the Earth."""
+    th = sidereal_angle(np.asarray(t_mid, dtype=np.float64), det.lon_deg)
+    lat = math.radians(det.lat_deg)
+    east = np.stack([-np.sin(th), np.cos(th), np.zeros_like(th)], axis=1)
+    north = np.stack([-math.sin(lat) * np.cos(th), -math.sin(lat) * np.sin(th),
+                      np.full_like(th, math.cos(lat))], axis=1)
+    arms = []
+    for az in det.arm_azimuths_deg:
+        a = math.radians(az)
+        arms.append(math.cos(a) * north + math.sin(a) * east)
+    return np.concatenate(arms, axis=1)
+
+
 def sft_mid_times(n_present: int, t_sft: float, gap_frac: float, rng: np.random.Generator,
                   t0: float = EPOCH) -> np.ndarray:
     """Mid-times of ``n_present`` SFTs drawn from ceil(n/(1-gap)) consecutive slots."""
@@ -129,6 +144,7 @@ class Workload:
     k: int
     sub_edges: np.ndarray        # [n_sub+1]
     injections: list = field(default_factory=list)  # dicts of injection parameters
+    arms: np.ndarray | None = None  # [N, 6] detector arm unit vectors (u, w) at t_mid
 
     @property
     def n_sft(self):
@@ -146,13 +162,15 @@ class Workload:
 def _build(name, n_det, n_per_det, t_sft, gap, f_start, n_f0, f1, n_sky, k, n_sub, seed,
            with_noise=True, sky=None):
     rng = np.random.default_rng(seed)
-    t_parts, v_parts = [], []
+    t_parts, v_parts, a_parts = [], [], []
     for d in range(n_det):
         t = sft_mid_times(n_per_det, t_sft, gap, rng)
         t_parts.append(t)
         v_parts.append(detector_velocity(t, DETECTORS[d]))
+        a_parts.append(detector_arms(t, DETECTORS[d]))
     t_mid = np.concatenate(t_parts)
     v = np.concatenate(v_parts)
+    arms = np.concatenate(a_parts)
     t_ref = EPOCH
     f0 = f_start + np.arange(n_f0, dtype=np.float64) / t_sft
     f1 = np.asarray(f1, dtype=np.float64)
@@ -168,7 +186,21 @@ def _build(name, n_det, n_per_det, t_sft, gap, f_start, n_f0, f1, n_sky, k, n_su
     edges = np.array([f_start + (j * per - 0.5) / t_sft for j in range(n_sub)]
                      + [f_start + (n_f0 - 0.5) / t_sft], dtype=np.float64)
     return Workload(name, t_sft, [n_per_det] * n_det, t_mid, v, t_ref, first_bin, n_bins, power,
-                    None, f0, f1, sky, k, edges)
+                    None, f0, f1, sky, k, edges, arms=arms)
+
+
+def injection_params(rng: np.random.Generator, f_lo: float, f_hi: float, amp_lo: float,
+                     amp_hi: float, f1_lo: float = 0.0, f1_hi: float = 0.0,
+                     log_amp: bool = False) -> dict:
+    """One injected signal: amplitude h0/sqrt(S_n), isotropic orientation and sky."""
+    if log_amp:
+        amp = float(np.exp(rng.uniform(np.log(amp_lo), np.log(amp_hi))))
+    else:
+        amp = float(rng.uniform(amp_lo, amp_hi))
+    sky = isotropic_sky(1, rng)[0]
+    return {"amp": amp, "cos_iota": float(rng.uniform(-1.0, 1.0)),
+            "psi": float(rng.uniform(-np.pi / 4, np.pi / 4)), "sky": sky,
+            "f0": float(rng.uniform(f_lo, f_hi)), "f1": float(rng.uniform(f1_lo, f1_hi))}
 
 
 def plain_small(seed: int = 1, n_sky: int = 20) -> Workload:

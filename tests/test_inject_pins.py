@@ -1,0 +1,126 @@
+"""Pins of the oracle's injection-campaign generator (signal hypothesis, Sec. II.B.2).
+
+Philox is pinned to its published known-answer vectors, the Gaussian noise to
+N(0, 1), the bin-offset factor to the paper's printed 0.7737, the antenna
+patterns to textbook sky averages and a closed-form geometry, and the complete
+generator to the non-central chi-squared mean and variance of the statistic.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+from scipy import stats
+
+import oracle
+from oracle import inject
+from paper_2411_18370_amd import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def test_philox_known_answers():
+    kat = json.load(open(os.path.join(GOLDEN, "philox4x32_10_kat.json")))
+    for v in kat["vectors"]:
+        ctr = np.array([[int(x, 16) for x in v["ctr"]]], np.uint64)
+        key = np.array([[int(x, 16) for x in v["key"]]], np.uint64)
+        out = inject.philox4x32_10(ctr, key)[0]
+        assert [int(x) for x in out] == [int(x, 16) for x in v["out"]]
+
+
+def test_noise_is_standard_normal_and_decorrelated():
+    re, im = inject.noise_normals(seed=0x1234_5678_9ABC, run=3, n_sft=200, n_bins=300)
+    for x in (re.ravel(), im.ravel()):
+        assert stats.kstest(x, "norm").pvalue > 1e-3
+    assert abs(np.corrcoef(re.ravel(), im.ravel())[0, 1]) < 0.01
+    re2, _ = inject.noise_normals(seed=0x1234_5678_9ABC, run=4, n_sft=200, n_bins=300)
+    assert abs(np.corrcoef(re.ravel(), re2.ravel())[0, 1]) < 0.01
+    p = re * re + im * im
+    assert stats.kstest(p.ravel(), stats.chi2(2).cdf).pvalue > 1e-3
+
+
+def test_sinc2_bin_average_is_papers_factor():
+    """Mean of sinc^2(pi delta) over delta uniform in [-1/2, 1/2): the paper's 0.7737."""
+    want = json.load(open(os.path.join(GOLDEN, "paper_constants.json")))["sinc2_bin_average"]["value"]
+    delta = (np.arange(200_000) + 0.5) / 200_000 - 0.5
+    got = float(np.mean(inject.sinc(np.pi * delta) ** 2))
+    assert abs(got - want) < 5e-5
+    # the three modelled bins keep at least 85% of the power (the sum over all m is 1)
+    tot = sum(inject.sinc(np.pi * (delta - m)) ** 2 for m in (-1, 0, 1))
+    assert 0.85 < tot.min() and tot.max() <= 1.0 + 1e-12
+
+
+def test_antenna_pattern_sky_averages():
+    """Isotropic sky and uniform psi: <F+^2> = <Fx^2> = 1/5 for a 90-degree
+    interferometer; orientation averages <A+^2> = 7/15, <Ax^2> = 1/3."""
+    rng = np.random.default_rng(1)
+    t = synth.EPOCH + 1800.0 * np.arange(24)
+    arms = synth.detector_arms(t, synth.DETECTORS[0])
+    fp2, fx2 = [], []
+    for n in synth.isotropic_sky(4000, rng):
+        psi = rng.uniform(-np.pi / 4, np.pi / 4)
+        fp, fx = inject.antenna_patterns(arms, n, psi)
+        fp2.append(np.mean(fp ** 2))
+        fx2.append(np.mean(fx ** 2))
+        assert np.all(fp ** 2 + fx ** 2 <= 1.0 + 1e-12)
+    assert abs(np.mean(fp2) - 0.2) < 0.01 and abs(np.mean(fx2) - 0.2) < 0.01
+    ci = rng.uniform(-1, 1, 400_000)
+    assert abs(np.mean((0.5 * (1 + ci ** 2)) ** 2) - 7 / 15) < 2e-3
+    assert abs(np.mean(ci ** 2) - 1 / 3) < 2e-3
+
+
+def test_antenna_pattern_zenith_closed_form():
+    """Source at the detector's zenith, polarisation axes along the arms:
+    F+ = +-1, Fx = 0; rotated by 45 degrees: |F+| = 0, |Fx| = 1."""
+    u = np.array([1.0, 0.0, 0.0])
+    w = np.array([0.0, 1.0, 0.0])
+    arms = np.concatenate([u, w])[None, :]
+    n = np.array([0.0, 0.0, 1.0])  # zenith of an equatorial-plane detector at the pole
+    p, q = inject.wave_frame(n, 0.0)
+    psi0 = np.arctan2(p @ w, p @ u)  # rotate the frame so p lies along u
+    fp, fx = inject.antenna_patterns(arms, n, -psi0)
+    assert abs(abs(fp[0]) - 1.0) < 1e-12 and abs(fx[0]) < 1e-12
+    fp, fx = inject.antenna_patterns(arms, n, -psi0 + np.pi / 4)
+    assert abs(fp[0]) < 1e-12 and abs(abs(fx[0]) - 1.0) < 1e-12
+
+
+def test_injected_statistic_is_noncentral_chi2():
+    """At the injection's own template, S over N SFTs is non-central chi^2_{2N}
+    with non-centrality sum_k rho_k^2 sinc^2(pi delta_k): mean 2N + lambda,
+    variance 4N + 4 lambda (Sec. II.B.2 with the textbook variance)."""
+    w = synth.plain_small(seed=21, n_sky=1)
+    rng = np.random.default_rng(22)
+    inj = synth.injection_params(rng, 100.02, 100.08, 0.05, 0.05, -1e-10, 1e-10)
+    B, A = inject.signal_amplitudes(w.t_mid, w.t_ref, w.t_sft, w.v, w.arms, inj)
+    lam = float(np.sum(A[:, 1] ** 2))
+    assert 20 < lam < 2000
+    s = []
+    for seed in range(300):
+        p = inject.generate_table(1000 + seed, 0, w.t_mid, w.t_ref, w.t_sft, w.v, w.arms,
+                                  w.first_bin, w.n_bins, inj)
+        v, _ = oracle.eval_list(w.t_mid, w.t_ref, w.t_sft, w.first_bin, p, None, w.v,
+                                [inj["f0"]], [inj["f1"]], [inj["sky"]])
+        s.append(v[0])
+    s = np.array(s)
+    n = w.n_sft
+    assert abs(s.mean() - (2 * n + lam)) < 5 * np.sqrt((4 * n + 4 * lam) / len(s))
+    assert abs(s.var() / (4 * n + 4 * lam) - 1) < 0.25
+    assert stats.kstest(s, stats.ncx2(2 * n, lam).cdf).pvalue > 1e-3
+
+
+def test_injected_bins_light_the_track():
+    """A loud injection lights only bins B_k - 1, B_k, B_k + 1 of each SFT, and
+    every one of them that carries a large share of the power."""
+    w = synth.plain_small(seed=23, n_sky=1)
+    rng = np.random.default_rng(24)
+    inj = synth.injection_params(rng, 100.02, 100.08, 50.0, 50.0)
+    p = inject.generate_table(7, 0, w.t_mid, w.t_ref, w.t_sft, w.v, w.arms, w.first_bin,
+                              w.n_bins, inj)
+    B, A = inject.signal_amplitudes(w.t_mid, w.t_ref, w.t_sft, w.v, w.arms, inj)
+    loud = p > 200.0  # a noise-only bin exceeds 200 with probability e^-100
+    assert (A[:, 1] ** 2 > 1000.0).mean() > 0.9
+    for k in range(w.n_sft):
+        cols = set(np.nonzero(loud[k])[0] + w.first_bin)
+        allowed = {int(B[k]) + m for m in (-1, 0, 1)}
+        must = {int(B[k]) + m for m in (-1, 0, 1) if A[k, m + 1] ** 2 > 1000.0}
+        assert must <= cols <= allowed, k
