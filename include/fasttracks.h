@@ -215,6 +215,98 @@ ft_status ft_bins(ft_ctx ctx, const ft_bank *bank, double t_ref, int32_t precisi
 ft_status ft_count_index_mismatches(ft_ctx ctx, const ft_bank *bank, double t_ref,
                                     int32_t precision, int64_t *n_mismatch);
 
+/* One injected continuous-wave signal (Sec. II.B.2).  amp = h0/sqrt(S_n)
+ * (the inverse sensitivity depth of Sec. V; 0 = no signal), cos_iota and psi
+ * its orientation, sky its unit direction, f0/f1 its frequency and spindown at
+ * t_ref. */
+typedef struct {
+    double amp, cos_iota, psi;
+    double sky[3];
+    double f0, f1;
+} ft_injection;
+
+/*
+ * ft_gen_sfts -- load a synthetic SFT set whose table the GPU generates
+ * (injection campaigns): same SFT arguments as ft_set_sfts (no weights), the
+ * velocities of ft_set_velocities, and the detector arm unit vectors
+ * arms [N][6] = (u, w) (equatorial) at each mid-time.  Noise: Re, Im ~ N(0, 1)
+ * per (bin b, SFT k) from Philox-4x32-10 keyed by `seed` with counter
+ * (b, k, run, 0) and Box-Muller; power P = Re^2 + Im^2 (Eq. s_chi2).  Signal
+ * (inj != NULL and inj->amp > 0): track x_k = (f0 + f1 (t_k - t_ref))(1 + v_k.n)
+ * T_sft bins, B_k = floor(x_k + 1/2), delta_k = x_k - B_k; bins B_k + m,
+ * m in {-1, 0, 1}, get sqrt(rho_k^2) |sinc(pi (delta_k - m))| added to Re with
+ * rho_k^2 = T_sft amp^2 (F+^2 A+^2 + Fx^2 Ax^2), A+ = (1 + cos^2 iota)/2,
+ * Ax = cos iota, antenna patterns from D = (u u^T - w w^T)/2 and the source's
+ * polarisation frame (e_alpha, e_delta) rotated by psi.  `power_out`
+ * ([N][n_bins], host or device) receives a copy of the table, or is NULL.
+ * Replaces the SFTs and velocities of the context; errors as ft_set_sfts /
+ * ft_set_velocities.
+ */
+ft_status ft_gen_sfts(ft_ctx ctx, int32_t n_det, const int32_t *n_sft, const double *t_mid,
+                      double t_sft, int64_t first_bin, int32_t n_bins, const double *v_over_c,
+                      const double *arms, uint64_t seed, uint32_t run, double t_ref,
+                      const ft_injection *inj, float *power_out);
+
+/*
+ * Batches (many independent runs in one launch: injection campaigns, uneven
+ * sub-bands).  Each run has its own SFT subset, table and grid bank, given as
+ * slices of shared arrays, and one toplist of length k over all its templates.
+ */
+typedef struct {
+    uint64_t seed;          /* generated tables: Philox key of the run's noise           */
+    uint32_t run_id;        /* generated tables: Philox counter word of the run          */
+    int32_t sft_begin;      /* first SFT of the run in the batch's SFT arrays            */
+    int32_t n_sft;          /* SFTs of the run (>= 1)                                    */
+    int32_t n_bins;         /* table columns (>= 1)                                      */
+    int64_t first_bin;      /* absolute bin of column 0                                  */
+    int64_t table_offset;   /* given tables: element offset of the run's [n_sft][n_bins] */
+    int32_t f0_begin, n_f0; /* grid bank: slices of the batch's f0, f1 and sky arrays    */
+    int32_t f1_begin, n_f1;
+    int32_t sky_begin, n_sky;
+    double t_ref;           /* reference time of the run's f0 and f1                     */
+    ft_injection inj;       /* generated tables: injected signal (amp = 0: none)         */
+} ft_run;
+
+typedef struct {
+    int32_t n_runs;
+    int32_t k;              /* toplist length per run (1..512)                           */
+    const ft_run *runs;     /* [n_runs]                                                  */
+    int32_t n_sft_total;    /* length of the SFT arrays                                  */
+    int32_t generate;       /* 1: tables generated on the GPU (as ft_gen_sfts) from the   */
+                            /*    runs' seeds and injections; 0: tables given in `power`  */
+    const double *t_mid;    /* [n_sft_total] mid-times (s)                               */
+    const double *v_over_c; /* [n_sft_total][3]                                          */
+    const double *arms;     /* [n_sft_total][6], required when generate = 1              */
+    double t_sft;
+    int64_t n_f0_total, n_f1_total, n_sky_total;
+    const double *f0, *f1, *sky_xyz;
+    int64_t power_len;      /* elements of `power` (generate = 0)                        */
+    const float *power;     /* concatenated run tables (generate = 0)                    */
+    int32_t tile;           /* 0: library choice per run; else a tile id for every run   */
+    int32_t reserved;
+} ft_batch;
+
+/*
+ * ft_eval_batch -- evaluate every run of a batch: (optionally) generate the
+ * tables, evaluate all (run, tile) work items with one persistent kernel that
+ * drains a shared queue, and select each run's exact toplist (as
+ * ft_eval_templates with one sub-band covering the run).  use_graph = 1
+ * captures the whole launch sequence in a HIP graph and launches it once.
+ * Asynchronous; errors as ft_eval_templates.
+ */
+ft_status ft_eval_batch(ft_ctx ctx, const ft_batch *batch, int32_t use_graph);
+/* Relaunch the HIP graph captured by the last ft_eval_batch(use_graph = 1)
+ * on the same device buffers (the batch's inputs as then uploaded). */
+ft_status ft_batch_replay(ft_ctx ctx);
+/* GPU time (ms, HIP events on the context stream) of the last batch launch. */
+ft_status ft_batch_time(ft_ctx ctx, double *ms);
+/* Toplist of run `run` of the last batch (synchronises). */
+ft_status ft_batch_toplist(ft_ctx ctx, int32_t run, ft_candidate *out, int32_t *n_out);
+/* Detection labels of the last batch: labels[r] = 1 if the loudest critical
+ * ratio of run r exceeds tau (the detection rule R(z; tau), Sec. V.B);
+ * max_z[r] receives that critical ratio (either pointer may be NULL). */
+ft_status ft_batch_labels(ft_ctx ctx, double tau, uint8_t *labels, double *max_z);
+
 /* Tiles of the grid evaluation kernel (for the autotuner and tests); ids are
  * 1..ft_tile_count(), names describe run length L, f1 values JT, waves NW and
  * SFTs per LDS stage KS. */

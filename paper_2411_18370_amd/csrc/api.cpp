@@ -31,7 +31,20 @@ struct ft_ctx_s {
     double t_sft = 0.0;
     bool has_weight = false;
     std::vector<double> t_mid_h;
+    std::vector<double> v_h;
     double vmax = 0.0;
+    double *d_arms = nullptr;
+    size_t cap_arms = 0;
+    int32_t *d_inj_bin = nullptr;
+    size_t cap_inj_bin = 0;
+    double *d_inj_amp = nullptr;
+    size_t cap_inj_amp = 0;
+    GenRun *d_genruns = nullptr;
+    size_t cap_genruns = 0;
+    int64_t *d_prefix = nullptr;  // generator prefix sums (sft, elements)
+    size_t cap_prefix = 0;
+    std::vector<GenRun> genruns_h;
+    std::vector<int64_t> prefix_h;
     float *d_power = nullptr;
     size_t cap_power = 0;
     float *d_weight = nullptr;
@@ -70,6 +83,40 @@ struct ft_ctx_s {
     unsigned long long *d_count = nullptr;
     int32_t *d_bins = nullptr;
     size_t cap_bins = 0;
+
+    // batches
+    struct BatchBufs {
+        double *tmid = nullptr, *v = nullptr, *arms = nullptr, *dt = nullptr, *f0 = nullptr, *f1 = nullptr,
+               *sky = nullptr, *sky_tile = nullptr, *tref = nullptr, *s64 = nullptr, *maxz = nullptr,
+               *inj_amp = nullptr;
+        size_t c_tmid = 0, c_v = 0, c_arms = 0, c_dt = 0, c_f0 = 0, c_f1 = 0, c_sky = 0, c_sky_tile = 0,
+               c_tref = 0, c_s64 = 0, c_maxz = 0, c_inj_amp = 0;
+        float *power = nullptr, *stats = nullptr;
+        size_t c_power = 0, c_stats = 0;
+        int32_t *perm = nullptr, *sft_begin = nullptr, *nout = nullptr, *inj_bin = nullptr;
+        size_t c_perm = 0, c_sft_begin = 0, c_nout = 0, c_inj_bin = 0;
+        int64_t *dt_prefix = nullptr, *cand = nullptr, *gen_prefix = nullptr;
+        size_t c_dt_prefix = 0, c_cand = 0, c_gen_prefix = 0;
+        EvalRun *runs = nullptr;
+        size_t c_runs = 0;
+        GenRun *gen = nullptr;
+        size_t c_gen = 0;
+        int2 *items = nullptr;
+        size_t c_items = 0;
+        unsigned *counters = nullptr;
+        size_t c_counters = 0;
+        ft_candidate *out = nullptr;
+        size_t c_out = 0;
+        uint8_t *labels = nullptr;
+        size_t c_labels = 0;
+    } bb;
+    bool have_batch = false;
+    int batch_runs = 0, batch_k = 0, batch_cap = 0;
+    hipStream_t capture_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    hipEvent_t bev[2] = {nullptr, nullptr};
+    double batch_ms = 0.0;
 
     // last evaluation
     bool have_eval = false;
@@ -285,6 +332,11 @@ ft_status ft_create(ft_ctx *out, int device, void *hip_stream)
             ft_destroy(c);
             return FT_E_DEVICE;
         }
+    for (auto &e : c->bev)
+        if (hipEventCreate(&e) != hipSuccess) {
+            ft_destroy(c);
+            return FT_E_DEVICE;
+        }
     *out = c;
     return FT_OK;
 }
@@ -297,6 +349,11 @@ void ft_destroy(ft_ctx c)
     release(&c->d_power, &c->cap_power);
     release(&c->d_weight, &c->cap_weight);
     release(&c->d_power_w, &c->cap_power_w);
+    release(&c->d_arms, &c->cap_arms);
+    release(&c->d_inj_bin, &c->cap_inj_bin);
+    release(&c->d_inj_amp, &c->cap_inj_amp);
+    release(&c->d_genruns, &c->cap_genruns);
+    release(&c->d_prefix, &c->cap_prefix);
     release(&c->d_tmid, &c->cap_tmid);
     release(&c->d_v, &c->cap_v);
     release(&c->d_dt, &c->cap_dt);
@@ -321,6 +378,41 @@ void ft_destroy(ft_ctx c)
     release(&c->d_nout, &c->cap_nout);
     release(&c->d_count, nullptr);
     release(&c->d_bins, &c->cap_bins);
+    {
+        auto &b = c->bb;
+        release(&b.tmid, &b.c_tmid);
+        release(&b.v, &b.c_v);
+        release(&b.arms, &b.c_arms);
+        release(&b.dt, &b.c_dt);
+        release(&b.f0, &b.c_f0);
+        release(&b.f1, &b.c_f1);
+        release(&b.sky, &b.c_sky);
+        release(&b.sky_tile, &b.c_sky_tile);
+        release(&b.tref, &b.c_tref);
+        release(&b.s64, &b.c_s64);
+        release(&b.maxz, &b.c_maxz);
+        release(&b.inj_amp, &b.c_inj_amp);
+        release(&b.power, &b.c_power);
+        release(&b.stats, &b.c_stats);
+        release(&b.perm, &b.c_perm);
+        release(&b.sft_begin, &b.c_sft_begin);
+        release(&b.nout, &b.c_nout);
+        release(&b.inj_bin, &b.c_inj_bin);
+        release(&b.dt_prefix, &b.c_dt_prefix);
+        release(&b.cand, &b.c_cand);
+        release(&b.gen_prefix, &b.c_gen_prefix);
+        release(&b.runs, &b.c_runs);
+        release(&b.gen, &b.c_gen);
+        release(&b.items, &b.c_items);
+        release(&b.counters, &b.c_counters);
+        release(&b.out, &b.c_out);
+        release(&b.labels, &b.c_labels);
+    }
+    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
+    for (auto &e : c->bev)
+        if (e) (void)hipEventDestroy(e);
     for (auto &e : c->ev)
         if (e) (void)hipEventDestroy(e);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
@@ -400,7 +492,11 @@ ft_status ft_set_sfts(ft_ctx c, int32_t n_det, const int32_t *n_sft, const doubl
     return FT_OK;
 }
 
-ft_status ft_set_velocities(ft_ctx c, const double *v)
+static ft_status set_velocities_impl(ft_ctx c, const double *v, bool sync);
+
+ft_status ft_set_velocities(ft_ctx c, const double *v) { return set_velocities_impl(c, v, true); }
+
+static ft_status set_velocities_impl(ft_ctx c, const double *v, bool sync)
 {
     if (!c) return FT_E_INVALID;
     c->err.clear();
@@ -421,12 +517,192 @@ ft_status ft_set_velocities(ft_ctx c, const double *v)
     hipError_t e = ensure(&c->d_v, &c->cap_v, n3);
     if (e != hipSuccess) return hip_fail(c, e, "alloc velocities");
     e = hipMemcpyAsync(c->d_v, vh.data(), n3 * sizeof(double), hipMemcpyHostToDevice, c->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e == hipSuccess && sync) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "copy velocities");
+    c->v_h.swap(vh);
     c->vmax = vmax;
     c->have_vel = true;
     c->have_eval = false;
     return FT_OK;
+}
+
+ft_status ft_gen_sfts(ft_ctx c, int32_t n_det, const int32_t *n_sft, const double *t_mid, double t_sft,
+                      int64_t first_bin, int32_t n_bins, const double *v_over_c, const double *arms,
+                      uint64_t seed, uint32_t run, double t_ref, const ft_injection *inj, float *power_out)
+{
+    if (!c) return FT_E_INVALID;
+    c->err.clear();
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, FT_E_DEVICE, "hipSetDevice");
+    if (n_det < 1 || !n_sft || !t_mid || !v_over_c || !arms)
+        return fail(c, FT_E_INVALID, "n_det >= 1 and non-null n_sft, t_mid, v_over_c, arms are required");
+    std::vector<int32_t> counts;
+    if (fetch(counts, n_sft, (size_t)n_det) != hipSuccess) return fail(c, FT_E_INVALID, "cannot read n_sft");
+    int64_t total = 0;
+    for (int32_t n : counts) {
+        if (n < 1) return fail(c, FT_E_INVALID, "every detector needs at least one SFT");
+        total += n;
+    }
+    if (total > 0x7fffffff) return fail(c, FT_E_UNSUPPORTED, "more than 2^31-1 SFTs");
+    if (!(t_sft > 0.0) || !is_finite(t_sft) || !is_finite(t_ref))
+        return fail(c, FT_E_INVALID, "t_sft must be finite and > 0, t_ref finite");
+    if (n_bins < 1) return fail(c, FT_E_INVALID, "n_bins must be >= 1");
+    if (first_bin < 0 || first_bin + (int64_t)n_bins >= 0x7fffffffLL)
+        return fail(c, FT_E_UNSUPPORTED, "bins must lie in [0, 2^31-1)");
+    ft_injection in{};
+    if (inj) {
+        in = *inj;
+        const double vals[] = {in.amp, in.cos_iota, in.psi, in.sky[0], in.sky[1], in.sky[2], in.f0, in.f1};
+        for (double x : vals)
+            if (!is_finite(x)) return fail(c, FT_E_INVALID, "injection parameters must be finite");
+        if (in.amp < 0.0 || in.cos_iota < -1.0 || in.cos_iota > 1.0)
+            return fail(c, FT_E_INVALID, "injection needs amp >= 0 and cos_iota in [-1, 1]");
+        if (in.amp > 0.0 && std::fabs(std::sqrt(in.sky[0] * in.sky[0] + in.sky[1] * in.sky[1] + in.sky[2] * in.sky[2]) - 1.0) > 1e-12)
+            return fail(c, FT_E_INVALID, "injection sky must be a unit vector");
+        if (in.amp > 0.0 && !(in.f0 > 0.0)) return fail(c, FT_E_INVALID, "injection f0 must be > 0");
+    }
+    std::vector<double> tm, ah;
+    if (fetch(tm, t_mid, (size_t)total) != hipSuccess || fetch(ah, arms, (size_t)total * 6) != hipSuccess)
+        return fail(c, FT_E_INVALID, "cannot read t_mid / arms");
+    for (double t : tm)
+        if (!is_finite(t)) return fail(c, FT_E_INVALID, "t_mid holds a non-finite value");
+    for (double a : ah)
+        if (!is_finite(a)) return fail(c, FT_E_INVALID, "arms hold a non-finite value");
+    // SFT bookkeeping first (as ft_set_sfts), then the velocities
+    hipError_t e;
+    const size_t n_cells = (size_t)total * (size_t)n_bins;
+    if ((e = ensure(&c->d_power, &c->cap_power, n_cells)) != hipSuccess ||
+        (e = ensure(&c->d_tmid, &c->cap_tmid, (size_t)total)) != hipSuccess ||
+        (e = ensure(&c->d_dt, &c->cap_dt, (size_t)total)) != hipSuccess ||
+        (e = ensure(&c->d_arms, &c->cap_arms, (size_t)total * 6)) != hipSuccess ||
+        (e = ensure(&c->d_inj_bin, &c->cap_inj_bin, (size_t)total)) != hipSuccess ||
+        (e = ensure(&c->d_inj_amp, &c->cap_inj_amp, (size_t)total * 3)) != hipSuccess)
+        return hip_fail(c, e, "alloc generated SFTs");
+    e = hipMemcpyAsync(c->d_tmid, tm.data(), (size_t)total * sizeof(double), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(c->d_arms, ah.data(), ah.size() * sizeof(double), hipMemcpyHostToDevice, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "copy SFT times");
+    c->have_sfts = true;
+    c->n_sft = (int32_t)total;
+    c->n_bins = n_bins;
+    c->first_bin = first_bin;
+    c->t_sft = t_sft;
+    c->has_weight = false;
+    c->t_mid_h.swap(tm);
+    c->have_eval = false;
+    c->have_vel = false;
+    ft_status st = set_velocities_impl(c, v_over_c, false);
+    if (st != FT_OK) {
+        c->have_sfts = false;
+        return st;
+    }
+    GenRun g{};
+    g.seed = seed;
+    g.run = run;
+    g.sft_offset = 0;
+    g.n_sft = (int32_t)total;
+    g.n_bins = n_bins;
+    g.first_bin = first_bin;
+    g.t_mid = c->d_tmid;
+    g.v = c->d_v;
+    g.arms = c->d_arms;
+    g.t_ref = t_ref;
+    g.t_sft = t_sft;
+    g.amp = in.amp;
+    g.cos_iota = in.cos_iota;
+    g.psi = in.psi;
+    for (int d = 0; d < 3; ++d) g.sky[d] = in.sky[d];
+    g.f0 = in.f0;
+    g.f1 = in.f1;
+    g.table = c->d_power;
+    g.inj_bin = c->d_inj_bin;
+    g.inj_amp = c->d_inj_amp;
+    c->genruns_h.assign(1, g);
+    c->prefix_h = {0, total, 0, (int64_t)n_cells};
+    if ((e = ensure(&c->d_genruns, &c->cap_genruns, 1)) != hipSuccess ||
+        (e = ensure(&c->d_prefix, &c->cap_prefix, 4)) != hipSuccess)
+        return hip_fail(c, e, "alloc generator descriptors");
+    e = hipMemcpyAsync(c->d_genruns, c->genruns_h.data(), sizeof(GenRun), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(c->d_prefix, c->prefix_h.data(), 4 * sizeof(int64_t), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess)
+        e = launch_gen_tables(c->d_genruns, 1, c->d_prefix, c->d_prefix + 2, total, (int64_t)n_cells, c->stream);
+    if (e == hipSuccess) e = launch_noise_moments(nullptr, (int)total, c->d_mu_sigma, c->stream);
+    if (e == hipSuccess && power_out)
+        e = hipMemcpyAsync(power_out, c->d_power, n_cells * sizeof(float), hipMemcpyDefault, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+        c->have_sfts = false;
+        return hip_fail(c, e, "generate table");
+    }
+    return FT_OK;
+}
+
+// Guard parameters of a uniform f0 grid: dT = spacing * T_sft and eta, the
+// bound (in bins) on the rounding of the canonical x + 1/2 and of the estimate
+// (f0 + c + 1/(2 g T)) * (g T) (each below 6 * 2^-53 * x_max), the grid's
+// deviation tau from uniform spacing and the rounding of the per-SFT drift
+// e = dT*g - 1 over a run; doubled for margin.
+static void guard_params(const double *f0, int64_t n0, double f0_max, double x_max, double vmax,
+                         double T, double &dT, double &eta)
+{
+    dT = n0 > 1 ? (f0[n0 - 1] - f0[0]) / (double)(n0 - 1) * T : T;
+    double tau = 0.0;
+    for (int64_t i = 0; i < n0; ++i) tau = std::max(tau, std::fabs(f0[i] - f0[0] - (double)i * (dT / T)));
+    tau += 8.0 * std::ldexp(f0_max, -52);
+    const double rho = 6.0 * std::ldexp(x_max, -53);
+    eta = 2.0 * (2.0 * rho + 2.0 * tau * (1.0 + vmax) * T + std::ldexp(1.0, -40));
+}
+
+struct WindowPlan {
+    int tile = -1;  // -1: direct kernel
+    int32_t wt = 0, wtp = 0, tiles_f0 = 0, tiles_f1 = 0, tiles_sky = 0;
+};
+
+// LDS window of a tile shape: bound on hi - lo over every tile and SFT.  The
+// f0 span of a tile, the spindown spread of its f1 values and the Doppler
+// spread of its sky points (|g - g'| <= vmax |n - n'|) bound the exact range.
+static WindowPlan plan_window(const double *f0, int64_t n0, const double *f1, int64_t n1,
+                              const double *sky_tile, int64_t ns, double dt_absmax, double vmax,
+                              double T, int tile)
+{
+    WindowPlan wp;
+    const TileCfg &cfg = tile_cfg(tile);
+    double span_f0 = 0.0;
+    for (int64_t i0 = 0; i0 < n0; i0 += 64 * cfg.L) {
+        const int64_t i1 = std::min<int64_t>(i0 + 64 * cfg.L, n0) - 1;
+        span_f0 = std::max(span_f0, f0[i1] - f0[i0]);
+    }
+    double span_f1 = 0.0, f1_absmax = 0.0;
+    for (int64_t j0 = 0; j0 < n1; j0 += cfg.JT) {
+        double lo = f1[j0], hi = lo;
+        for (int64_t j = j0; j < std::min<int64_t>(j0 + cfg.JT, n1); ++j) {
+            lo = std::min(lo, f1[j]);
+            hi = std::max(hi, f1[j]);
+        }
+        span_f1 = std::max(span_f1, hi - lo);
+    }
+    for (int64_t j = 0; j < n1; ++j) f1_absmax = std::max(f1_absmax, std::fabs(f1[j]));
+    double diam = 0.0;
+    for (int64_t s0 = 0; s0 < ns; s0 += cfg.NW)
+        for (int64_t a = s0; a < std::min<int64_t>(s0 + cfg.NW, ns); ++a)
+            for (int64_t b2 = a + 1; b2 < std::min<int64_t>(s0 + cfg.NW, ns); ++b2) {
+                const double dx = sky_tile[3 * a] - sky_tile[3 * b2];
+                const double dy = sky_tile[3 * a + 1] - sky_tile[3 * b2 + 1];
+                const double dz = sky_tile[3 * a + 2] - sky_tile[3 * b2 + 2];
+                diam = std::max(diam, std::sqrt(dx * dx + dy * dy + dz * dz));
+            }
+    const double a_max = f0[n0 - 1] + f1_absmax * dt_absmax;
+    const double width = (span_f0 + span_f1 * dt_absmax) * (1.0 + vmax) * T + a_max * vmax * diam * (1.0 + 1e-9) * T;
+    const double wt = std::ceil(width * (1.0 + 1e-9)) + 3.0 + cfg.L;
+    const double wtp = std::ceil(wt / 64.0) * 64.0;
+    if (2.0 * wtp * cfg.KS * 4.0 + (double)tile_static_lds(tile) > 150.0 * 1024.0) return wp;
+    wp.tile = tile;
+    wp.wt = (int32_t)wt;
+    wp.wtp = (int32_t)wtp;
+    wp.tiles_f0 = (int32_t)((n0 + 64 * cfg.L - 1) / (64 * cfg.L));
+    wp.tiles_f1 = (int32_t)((n1 + cfg.JT - 1) / cfg.JT);
+    wp.tiles_sky = (int32_t)((ns + cfg.NW - 1) / cfg.NW);
+    return wp;
 }
 
 static ft_status prepare_bank(ft_ctx c, const ft_bank *bank, double t_ref, EvalRun &run,
@@ -550,23 +826,8 @@ static ft_status prepare_bank(ft_ctx c, const ft_bank *bank, double t_ref, EvalR
     run.n_list = grid ? 0 : n0;
     run.t_sft = c->t_sft;
     // bounds used by the grid kernel
-    if (grid) {
-        const double T = c->t_sft;
-        double dT = n0 > 1 ? (c->f0_h[n0 - 1] - c->f0_h[0]) / (double)(n0 - 1) * T : T;
-        double tau = 0.0;
-        for (int64_t i = 0; i < n0; ++i)
-            tau = std::max(tau, std::fabs(c->f0_h[i] - c->f0_h[0] - (double)i * (dT / T)));
-        tau += 8.0 * std::ldexp(f0_max, -52);
-        // eta bounds, in bins: the rounding of the canonical x + 1/2 and of the
-        // estimate (f0 + c + 1/(2 g T)) * (g T) (each below 6 * 2^-53 * x_max),
-        // the grid's deviation tau from uniform spacing, and the rounding of the
-        // per-SFT drift e = dT*g - 1 over a run; doubled for margin.
-        const double rho = 6.0 * std::ldexp(x_max, -53);
-        double eta = 2.0 * (2.0 * rho + 2.0 * tau * (1.0 + c->vmax) * T + std::ldexp(1.0, -40));
-        run.dT = dT;
-        run.eta = eta;
-        (void)dt_min;
-    }
+    if (grid) guard_params(c->f0_h.data(), n0, f0_max, x_max, c->vmax, c->t_sft, run.dT, run.eta);
+    (void)dt_min;
     return FT_OK;
 }
 
@@ -647,53 +908,17 @@ ft_status ft_eval_templates(ft_ctx c, const ft_bank *bank, double t_ref, const f
         } else {
             tile = choose_tile(n0, n1, run.eta < 1e-4);
         }
-        TileCfg cfg = tile_cfg(tile);
-        if (cfg.L > 1 && !(run.eta < 1e-4)) {
-            tile = 1;
-            cfg = tile_cfg(tile);
-        }
-        const double T = c->t_sft;
+        if (tile_cfg(tile).L > 1 && !(run.eta < 1e-4)) tile = 1;
         double dt_absmax = 0.0;
         for (double t : c->t_mid_h) dt_absmax = std::max(dt_absmax, std::fabs(t - t_ref));
-        double span_f0 = 0.0;
-        for (int64_t i0 = 0; i0 < n0; i0 += 64 * cfg.L) {
-            const int64_t i1 = std::min<int64_t>(i0 + 64 * cfg.L, n0) - 1;
-            span_f0 = std::max(span_f0, c->f0_h[i1] - c->f0_h[i0]);
-        }
-        double span_f1 = 0.0;
-        for (int64_t j0 = 0; j0 < n1; j0 += cfg.JT) {
-            double lo = c->f1_h[j0], hi = lo;
-            for (int64_t j = j0; j < std::min<int64_t>(j0 + cfg.JT, n1); ++j) {
-                lo = std::min(lo, c->f1_h[j]);
-                hi = std::max(hi, c->f1_h[j]);
-            }
-            span_f1 = std::max(span_f1, hi - lo);
-        }
-        double diam = 0.0;
-        const std::vector<double> &st = c->sky_tile_h;
-        for (int64_t s0 = 0; s0 < ns; s0 += cfg.NW)
-            for (int64_t a = s0; a < std::min<int64_t>(s0 + cfg.NW, ns); ++a)
-                for (int64_t b2 = a + 1; b2 < std::min<int64_t>(s0 + cfg.NW, ns); ++b2) {
-                    const double dx = st[3 * a] - st[3 * b2];
-                    const double dy = st[3 * a + 1] - st[3 * b2 + 1];
-                    const double dz = st[3 * a + 2] - st[3 * b2 + 2];
-                    diam = std::max(diam, std::sqrt(dx * dx + dy * dy + dz * dz));
-                }
-        double f1_absmax = 0.0;
-        for (double f : c->f1_h) f1_absmax = std::max(f1_absmax, std::fabs(f));
-        const double a_max = c->f0_h[n0 - 1] + f1_absmax * dt_absmax;
-        const double width = (span_f0 + span_f1 * dt_absmax) * (1.0 + c->vmax) * T +
-                             a_max * c->vmax * diam * (1.0 + 1e-9) * T;
-        const double wt = std::ceil(width * (1.0 + 1e-9)) + 3.0 + cfg.L;
-        const double wtp = std::ceil(wt / 64.0) * 64.0;
-        // A window beyond the LDS budget (extreme Doppler spread or a very
-        // wide f1 tile) falls back to the direct kernel.
-        if (2.0 * wtp * cfg.KS * 4.0 + (double)tile_static_lds(tile) > 150.0 * 1024.0) tile = -1;
-        run.wt = (int32_t)std::min(wt, 1e9);
-        run.wtp = (int32_t)std::min(wtp, 1e9);
-        run.tiles_f0 = (int32_t)((n0 + 64 * cfg.L - 1) / (64 * cfg.L));
-        run.tiles_f1 = (int32_t)((n1 + cfg.JT - 1) / cfg.JT);
-        run.tiles_sky = (int32_t)((ns + cfg.NW - 1) / cfg.NW);
+        const WindowPlan wp = plan_window(c->f0_h.data(), n0, c->f1_h.data(), n1, c->sky_tile_h.data(), ns,
+                                          dt_absmax, c->vmax, c->t_sft, tile);
+        tile = wp.tile;  // -1: the window does not fit in LDS, use the direct kernel
+        run.wt = wp.wt;
+        run.wtp = wp.wtp;
+        run.tiles_f0 = wp.tiles_f0;
+        run.tiles_f1 = wp.tiles_f1;
+        run.tiles_sky = wp.tiles_sky;
         if ((int64_t)run.tiles_f0 * run.tiles_f1 * run.tiles_sky >= 0x7fffffffLL)
             return fail(c, FT_E_UNSUPPORTED, "too many tiles");
     }
@@ -849,6 +1074,454 @@ ft_status ft_count_index_mismatches(ft_ctx c, const ft_bank *bank, double t_ref,
     if (e != hipSuccess) return hip_fail(c, e, "count mismatches");
     *n_mismatch = (int64_t)cnt;
     c->have_eval = false;
+    return FT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Batches
+// ---------------------------------------------------------------------------
+namespace {
+
+// Tile of one batch run: fewest wasted lanes over the tiles whose f1 tile
+// suits small f1 sets.
+int choose_batch_tile(int64_t n_f0, int64_t n_f1, bool uniform)
+{
+    const int with_runs[] = {15, 16, 2, 8};  // L3_J3, L5_J3, L3_J4, L5_J4
+    const int plain[] = {14, 1};             // L1_J3, L1_J4
+    double best = 1e30;
+    int best_id = 14;
+    auto consider = [&](int id) {
+        const TileCfg &t = tile_cfg(id);
+        const double f0w = std::ceil((double)n_f0 / (64.0 * t.L)) * 64.0 * t.L / (double)n_f0;
+        const double f1w = std::ceil((double)n_f1 / t.JT) * t.JT / (double)n_f1;
+        const double ops = t.L > 1 ? (7.0 + t.L) / t.L : 7.0;
+        const double cost = f0w * f1w * ops;
+        if (cost < best - 1e-9) {
+            best = cost;
+            best_id = id;
+        }
+    };
+    if (uniform && n_f0 >= 32)
+        for (int id : with_runs) consider(id);
+    for (int id : plain) consider(id);
+    return best_id;
+}
+
+struct BatchPlan {
+    std::vector<EvalRun> runs;
+    std::vector<GenRun> gen;
+    std::vector<int> tile;                 // per run
+    std::vector<int64_t> dt_prefix, stats_prefix, gen_prefix_sft, gen_prefix_elem, sky_prefix;
+    std::vector<int32_t> sft_begin, perm;
+    std::vector<double> tref, sky_tile;
+    std::vector<std::vector<int2>> items;  // per tile id
+    int max_wtp = 64;
+};
+
+}  // namespace
+
+static ft_status launch_batch_sequence(ft_ctx c, const BatchPlan &pl, bool generate, hipStream_t st)
+{
+    auto &b = c->bb;
+    const int n_runs = (int)pl.runs.size();
+    hipError_t e = launch_fill_u32(c->d_err, 0u, 1, st);
+    if (e == hipSuccess) e = launch_fill_u32(b.counters, 0u, tile_count(), st);
+    if (e == hipSuccess)
+        e = launch_batch_dt(b.tmid, b.sft_begin, b.tref, b.dt_prefix, n_runs, pl.dt_prefix[n_runs], b.dt, st);
+    if (e == hipSuccess && generate)
+        e = launch_gen_tables(b.gen, n_runs, b.gen_prefix, b.gen_prefix + (n_runs + 1), pl.gen_prefix_sft[n_runs],
+                              pl.gen_prefix_elem[n_runs], st);
+    int64_t item_off = 0;
+    for (int id = 0; id < tile_count() && e == hipSuccess; ++id) {
+        const int n_items = (int)pl.items[id].size();
+        if (n_items == 0) continue;
+        const int grid = std::min(n_items, 2048);
+        e = launch_eval_batch(b.runs, b.items + item_off, n_items, pl.max_wtp, b.counters + id, grid, tile_cfg(id), st);
+        item_off += n_items;
+    }
+    if (e == hipSuccess)
+        e = launch_select_batch(b.runs, n_runs, c->batch_k, c->batch_cap, b.cand, b.s64, b.out, b.nout, b.maxz, c->d_err,
+                                st);
+    if (e != hipSuccess) return hip_fail(c, e, "launch batch");
+    return FT_OK;
+}
+
+ft_status ft_eval_batch(ft_ctx c, const ft_batch *bt, int32_t use_graph)
+{
+    if (!c) return FT_E_INVALID;
+    c->err.clear();
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, FT_E_DEVICE, "hipSetDevice");
+    if (!bt || bt->n_runs < 1 || !bt->runs) return fail(c, FT_E_INVALID, "batch needs n_runs >= 1 and runs");
+    if (bt->k < 1 || bt->k > 512) return fail(c, FT_E_INVALID, "batch k must be in [1, 512]");
+    if (bt->n_sft_total < 1 || !bt->t_mid || !bt->v_over_c) return fail(c, FT_E_INVALID, "batch SFT arrays missing");
+    if (!(bt->t_sft > 0.0) || !is_finite(bt->t_sft)) return fail(c, FT_E_INVALID, "t_sft must be finite and > 0");
+    if (bt->n_f0_total < 1 || bt->n_f1_total < 1 || bt->n_sky_total < 1 || !bt->f0 || !bt->f1 || !bt->sky_xyz)
+        return fail(c, FT_E_INVALID, "batch bank arrays missing");
+    if (bt->generate != 0 && bt->generate != 1) return fail(c, FT_E_INVALID, "generate must be 0 or 1");
+    const bool gen = bt->generate == 1;
+    if (gen && !bt->arms) return fail(c, FT_E_INVALID, "generated batches need arms");
+    if (!gen && (!bt->power || bt->power_len < 1)) return fail(c, FT_E_INVALID, "batch tables missing");
+    if (bt->tile != 0 && (bt->tile < 1 || bt->tile > tile_count())) return fail(c, FT_E_INVALID, "unknown tile");
+    const int n_runs = bt->n_runs;
+    const int64_t NS = bt->n_sft_total;
+    std::vector<ft_run> runs;
+    std::vector<double> tm, vh, ah, f0h, f1h, skyh;
+    if (fetch(runs, bt->runs, (size_t)n_runs) != hipSuccess || fetch(tm, bt->t_mid, (size_t)NS) != hipSuccess ||
+        fetch(vh, bt->v_over_c, (size_t)NS * 3) != hipSuccess || (gen && fetch(ah, bt->arms, (size_t)NS * 6) != hipSuccess) ||
+        fetch(f0h, bt->f0, (size_t)bt->n_f0_total) != hipSuccess || fetch(f1h, bt->f1, (size_t)bt->n_f1_total) != hipSuccess ||
+        fetch(skyh, bt->sky_xyz, (size_t)bt->n_sky_total * 3) != hipSuccess)
+        return fail(c, FT_E_INVALID, "cannot read the batch arrays");
+    std::vector<double> vabs((size_t)NS);
+    for (int64_t k = 0; k < NS; ++k) {
+        const double x = vh[3 * k], y = vh[3 * k + 1], z = vh[3 * k + 2];
+        if (!is_finite(tm[k]) || !is_finite(x) || !is_finite(y) || !is_finite(z))
+            return fail(c, FT_E_INVALID, "batch SFT arrays hold a non-finite value");
+        vabs[k] = std::sqrt(x * x + y * y + z * z);
+        if (!(vabs[k] < 1.0)) return fail(c, FT_E_INVALID, "|v|/c must be < 1");
+    }
+    for (double a : ah)
+        if (!is_finite(a)) return fail(c, FT_E_INVALID, "arms hold a non-finite value");
+    for (int64_t sk = 0; sk < bt->n_sky_total; ++sk) {
+        const double x = skyh[3 * sk], y = skyh[3 * sk + 1], z = skyh[3 * sk + 2];
+        if (!is_finite(x) || !is_finite(y) || !is_finite(z) || std::fabs(std::sqrt(x * x + y * y + z * z) - 1.0) > 1e-12)
+            return fail(c, FT_E_INVALID, "batch sky vectors must be finite unit vectors");
+    }
+    for (double f : f1h)
+        if (!is_finite(f)) return fail(c, FT_E_INVALID, "batch f1 must be finite");
+
+    BatchPlan pl;
+    pl.runs.resize(n_runs);
+    pl.tile.resize(n_runs);
+    pl.items.assign(tile_count(), {});
+    pl.dt_prefix.assign(n_runs + 1, 0);
+    pl.stats_prefix.assign(n_runs + 1, 0);
+    pl.gen_prefix_sft.assign(n_runs + 1, 0);
+    pl.gen_prefix_elem.assign(n_runs + 1, 0);
+    pl.sky_prefix.assign(n_runs + 1, 0);
+    pl.sft_begin.resize(n_runs);
+    pl.tref.resize(n_runs);
+    for (int r = 0; r < n_runs; ++r) {
+        const ft_run &R = runs[r];
+        if (R.n_sft < 1 || R.sft_begin < 0 || (int64_t)R.sft_begin + R.n_sft > NS)
+            return fail(c, FT_E_INVALID, "run %d: SFT slice out of range", r);
+        if (R.n_bins < 1 || R.first_bin < 0 || R.first_bin + (int64_t)R.n_bins >= 0x7fffffffLL)
+            return fail(c, FT_E_INVALID, "run %d: bad table columns", r);
+        if (R.n_f0 < 1 || R.n_f1 < 1 || R.n_sky < 1 || R.f0_begin < 0 || R.f1_begin < 0 || R.sky_begin < 0 ||
+            (int64_t)R.f0_begin + R.n_f0 > bt->n_f0_total || (int64_t)R.f1_begin + R.n_f1 > bt->n_f1_total ||
+            (int64_t)R.sky_begin + R.n_sky > bt->n_sky_total)
+            return fail(c, FT_E_INVALID, "run %d: bank slice out of range", r);
+        if (!is_finite(R.t_ref)) return fail(c, FT_E_INVALID, "run %d: t_ref must be finite", r);
+        const int64_t cells = (int64_t)R.n_sft * R.n_bins;
+        if (!gen && (R.table_offset < 0 || R.table_offset + cells > bt->power_len))
+            return fail(c, FT_E_INVALID, "run %d: table slice out of range", r);
+        if (gen) {
+            const ft_injection &in = R.inj;
+            const double vals[] = {in.amp, in.cos_iota, in.psi, in.sky[0], in.sky[1], in.sky[2], in.f0, in.f1};
+            for (double x : vals)
+                if (!is_finite(x)) return fail(c, FT_E_INVALID, "run %d: injection must be finite", r);
+            if (in.amp < 0.0 || in.cos_iota < -1.0 || in.cos_iota > 1.0)
+                return fail(c, FT_E_INVALID, "run %d: injection needs amp >= 0 and cos_iota in [-1, 1]", r);
+            if (in.amp > 0.0 &&
+                (std::fabs(std::sqrt(in.sky[0] * in.sky[0] + in.sky[1] * in.sky[1] + in.sky[2] * in.sky[2]) - 1.0) > 1e-12 ||
+                 !(in.f0 > 0.0)))
+                return fail(c, FT_E_INVALID, "run %d: injection needs a unit sky vector and f0 > 0", r);
+        }
+        const double *f0 = f0h.data() + R.f0_begin;
+        const double *f1 = f1h.data() + R.f1_begin;
+        for (int i = 0; i < R.n_f0; ++i)
+            if (!is_finite(f0[i]) || !(f0[i] > 0.0) || (i > 0 && !(f0[i] > f0[i - 1])))
+                return fail(c, FT_E_INVALID, "run %d: f0 must be finite, > 0 and strictly increasing", r);
+        double dt_min = 1e300, dt_max = -1e300, vmax = 0.0;
+        for (int k = 0; k < R.n_sft; ++k) {
+            const double dt = tm[R.sft_begin + k] - R.t_ref;
+            dt_min = std::min(dt_min, dt);
+            dt_max = std::max(dt_max, dt);
+            vmax = std::max(vmax, vabs[R.sft_begin + k]);
+        }
+        double f1_min = 1e300, f1_max = -1e300;
+        for (int j = 0; j < R.n_f1; ++j) {
+            f1_min = std::min(f1_min, f1[j]);
+            f1_max = std::max(f1_max, f1[j]);
+        }
+        const double cs[4] = {f1_min * dt_min, f1_min * dt_max, f1_max * dt_min, f1_max * dt_max};
+        const double c_min = *std::min_element(cs, cs + 4), c_max = *std::max_element(cs, cs + 4);
+        if (!(f0[0] + c_min > 0.0)) return fail(c, FT_E_INVALID, "run %d: f0 + f1*(t - t_ref) must stay > 0", r);
+        const double x_max = (f0[R.n_f0 - 1] + c_max) * (1.0 + vmax) * bt->t_sft;
+        if (!(x_max < 2147483000.0)) return fail(c, FT_E_UNSUPPORTED, "run %d: frequencies above 2^31/T_sft", r);
+        // sky order of the run
+        std::vector<double> sky_run(skyh.begin() + 3 * (size_t)R.sky_begin, skyh.begin() + 3 * ((size_t)R.sky_begin + R.n_sky));
+        std::vector<int32_t> perm;
+        sky_order(sky_run, R.n_sky, perm);
+        const size_t sky_base = pl.sky_tile.size() / 3;
+        for (int sk = 0; sk < R.n_sky; ++sk) {
+            for (int d = 0; d < 3; ++d) pl.sky_tile.push_back(sky_run[3 * (size_t)perm[sk] + d]);
+            pl.perm.push_back(perm[sk]);
+        }
+        EvalRun &E = pl.runs[r];
+        E = EvalRun{};
+        guard_params(f0, R.n_f0, f0[R.n_f0 - 1], x_max, vmax, bt->t_sft, E.dT, E.eta);
+        int tile = bt->tile ? bt->tile - 1 : choose_batch_tile(R.n_f0, R.n_f1, E.eta < 1e-4);
+        if (tile_cfg(tile).L > 1 && !(E.eta < 1e-4)) tile = 14;
+        const double dt_absmax = std::max(std::fabs(dt_min), std::fabs(dt_max));
+        const WindowPlan wp = plan_window(f0, R.n_f0, f1, R.n_f1, pl.sky_tile.data() + 3 * sky_base, R.n_sky, dt_absmax,
+                                          vmax, bt->t_sft, tile);
+        if (wp.tile < 0) return fail(c, FT_E_UNSUPPORTED, "run %d: tile window exceeds the LDS budget", r);
+        pl.tile[r] = tile;
+        E.wt = wp.wt;
+        E.wtp = wp.wtp;
+        E.tiles_f0 = wp.tiles_f0;
+        E.tiles_f1 = wp.tiles_f1;
+        E.tiles_sky = wp.tiles_sky;
+        pl.max_wtp = std::max(pl.max_wtp, wp.wtp);
+        const int64_t n_tiles = (int64_t)wp.tiles_f0 * wp.tiles_f1 * wp.tiles_sky;
+        if (n_tiles >= 0x7fffffff) return fail(c, FT_E_UNSUPPORTED, "run %d: too many tiles", r);
+        for (int64_t tt = 0; tt < n_tiles; ++tt) pl.items[tile].push_back(make_int2(r, (int)tt));
+        E.n_sft = R.n_sft;
+        E.n_bins = R.n_bins;
+        E.first_bin = (int32_t)R.first_bin;
+        E.n_f0 = R.n_f0;
+        E.n_f1 = R.n_f1;
+        E.n_sky = R.n_sky;
+        E.t_sft = bt->t_sft;
+        E.sum_mode = FT_SUM_BLOCKED;
+        pl.sft_begin[r] = R.sft_begin;
+        pl.tref[r] = R.t_ref;
+        pl.dt_prefix[r + 1] = pl.dt_prefix[r] + R.n_sft;
+        pl.stats_prefix[r + 1] = pl.stats_prefix[r] + (int64_t)R.n_f0 * R.n_f1 * R.n_sky;
+        pl.gen_prefix_sft[r + 1] = pl.gen_prefix_sft[r] + R.n_sft;
+        pl.gen_prefix_elem[r + 1] = pl.gen_prefix_elem[r] + cells;
+        pl.sky_prefix[r + 1] = pl.sky_prefix[r] + R.n_sky;
+    }
+    int64_t total_items = 0;
+    for (auto &v : pl.items) total_items += (int64_t)v.size();
+    if (total_items >= 0x7fffffff) return fail(c, FT_E_UNSUPPORTED, "too many work items");
+    const int k = bt->k;
+    const int cap = std::max(4096, 8 * k);
+
+    // device buffers
+    auto &b = c->bb;
+    hipError_t e;
+    const int64_t n_dt = pl.dt_prefix[n_runs], n_stats = pl.stats_prefix[n_runs];
+    const int64_t n_power = gen ? pl.gen_prefix_elem[n_runs] : bt->power_len;
+    if ((e = ensure(&b.tmid, &b.c_tmid, (size_t)NS)) != hipSuccess || (e = ensure(&b.v, &b.c_v, (size_t)NS * 3)) != hipSuccess ||
+        (gen && (e = ensure(&b.arms, &b.c_arms, (size_t)NS * 6)) != hipSuccess) ||
+        (e = ensure(&b.dt, &b.c_dt, (size_t)n_dt)) != hipSuccess ||
+        (e = ensure(&b.f0, &b.c_f0, (size_t)bt->n_f0_total)) != hipSuccess ||
+        (e = ensure(&b.f1, &b.c_f1, (size_t)bt->n_f1_total)) != hipSuccess ||
+        (e = ensure(&b.sky, &b.c_sky, (size_t)bt->n_sky_total * 3)) != hipSuccess ||
+        (e = ensure(&b.sky_tile, &b.c_sky_tile, pl.sky_tile.size())) != hipSuccess ||
+        (e = ensure(&b.perm, &b.c_perm, pl.perm.size())) != hipSuccess ||
+        (e = ensure(&b.tref, &b.c_tref, (size_t)n_runs)) != hipSuccess ||
+        (e = ensure(&b.sft_begin, &b.c_sft_begin, (size_t)n_runs)) != hipSuccess ||
+        (e = ensure(&b.dt_prefix, &b.c_dt_prefix, (size_t)n_runs + 1)) != hipSuccess ||
+        (e = ensure(&b.power, &b.c_power, (size_t)n_power)) != hipSuccess ||
+        (e = ensure(&b.stats, &b.c_stats, (size_t)n_stats)) != hipSuccess ||
+        (e = ensure(&b.runs, &b.c_runs, (size_t)n_runs)) != hipSuccess ||
+        (e = ensure(&b.items, &b.c_items, (size_t)std::max<int64_t>(total_items, 1))) != hipSuccess ||
+        (e = ensure(&b.counters, &b.c_counters, (size_t)tile_count())) != hipSuccess ||
+        (e = ensure(&b.cand, &b.c_cand, (size_t)n_runs * cap)) != hipSuccess ||
+        (e = ensure(&b.s64, &b.c_s64, (size_t)n_runs * cap)) != hipSuccess ||
+        (e = ensure(&b.out, &b.c_out, (size_t)n_runs * k)) != hipSuccess ||
+        (e = ensure(&b.nout, &b.c_nout, (size_t)n_runs)) != hipSuccess ||
+        (e = ensure(&b.maxz, &b.c_maxz, (size_t)n_runs)) != hipSuccess ||
+        (e = ensure(&b.labels, &b.c_labels, (size_t)n_runs)) != hipSuccess ||
+        (gen && ((e = ensure(&b.gen, &b.c_gen, (size_t)n_runs)) != hipSuccess ||
+                 (e = ensure(&b.gen_prefix, &b.c_gen_prefix, (size_t)(n_runs + 1) * 2)) != hipSuccess ||
+                 (e = ensure(&b.inj_bin, &b.c_inj_bin, (size_t)pl.gen_prefix_sft[n_runs])) != hipSuccess ||
+                 (e = ensure(&b.inj_amp, &b.c_inj_amp, (size_t)pl.gen_prefix_sft[n_runs] * 3)) != hipSuccess)))
+        return hip_fail(c, e, "alloc batch buffers");
+    // device pointers of every run
+    for (int r = 0; r < n_runs; ++r) {
+        const ft_run &R = runs[r];
+        EvalRun &E = pl.runs[r];
+        E.power = b.power + (gen ? pl.gen_prefix_elem[r] : R.table_offset);
+        E.power_w = E.power;
+        E.weight = nullptr;
+        E.dt = b.dt + pl.dt_prefix[r];
+        E.v = b.v + 3 * (int64_t)R.sft_begin;
+        E.f0 = b.f0 + R.f0_begin;
+        E.f1 = b.f1 + R.f1_begin;
+        E.sky = b.sky + 3 * (int64_t)R.sky_begin;
+        E.sky_tile = b.sky_tile + 3 * pl.sky_prefix[r];
+        E.sky_perm = b.perm + pl.sky_prefix[r];
+        E.stats = b.stats + pl.stats_prefix[r];
+        E.err = c->d_err;
+        if (gen) {
+            GenRun g{};
+            g.seed = R.seed;
+            g.run = R.run_id;
+            g.sft_offset = 0;
+            g.n_sft = R.n_sft;
+            g.n_bins = R.n_bins;
+            g.first_bin = R.first_bin;
+            g.t_mid = b.tmid + R.sft_begin;
+            g.v = b.v + 3 * (int64_t)R.sft_begin;
+            g.arms = b.arms + 6 * (int64_t)R.sft_begin;
+            g.t_ref = R.t_ref;
+            g.t_sft = bt->t_sft;
+            g.amp = R.inj.amp;
+            g.cos_iota = R.inj.cos_iota;
+            g.psi = R.inj.psi;
+            for (int d = 0; d < 3; ++d) g.sky[d] = R.inj.sky[d];
+            g.f0 = R.inj.f0;
+            g.f1 = R.inj.f1;
+            g.table = b.power + pl.gen_prefix_elem[r];
+            g.inj_bin = b.inj_bin + pl.gen_prefix_sft[r];
+            g.inj_amp = b.inj_amp + 3 * pl.gen_prefix_sft[r];
+            pl.gen.push_back(g);
+        }
+    }
+    std::vector<int2> items_flat;
+    items_flat.reserve((size_t)total_items);
+    for (auto &v : pl.items) items_flat.insert(items_flat.end(), v.begin(), v.end());
+    std::vector<int64_t> gp;
+    if (gen) {
+        gp = pl.gen_prefix_sft;
+        gp.insert(gp.end(), pl.gen_prefix_elem.begin(), pl.gen_prefix_elem.end());
+    }
+    struct Up {
+        void *dst;
+        const void *src;
+        size_t bytes;
+    } ups[] = {
+        {b.tmid, tm.data(), tm.size() * 8},
+        {b.v, vh.data(), vh.size() * 8},
+        {b.arms, ah.data(), ah.size() * 8},
+        {b.f0, f0h.data(), f0h.size() * 8},
+        {b.f1, f1h.data(), f1h.size() * 8},
+        {b.sky, skyh.data(), skyh.size() * 8},
+        {b.sky_tile, pl.sky_tile.data(), pl.sky_tile.size() * 8},
+        {b.perm, pl.perm.data(), pl.perm.size() * 4},
+        {b.tref, pl.tref.data(), pl.tref.size() * 8},
+        {b.sft_begin, pl.sft_begin.data(), pl.sft_begin.size() * 4},
+        {b.dt_prefix, pl.dt_prefix.data(), pl.dt_prefix.size() * 8},
+        {b.runs, pl.runs.data(), pl.runs.size() * sizeof(EvalRun)},
+        {b.items, items_flat.data(), items_flat.size() * sizeof(int2)},
+        {b.gen, pl.gen.data(), pl.gen.size() * sizeof(GenRun)},
+        {b.gen_prefix, gp.data(), gp.size() * 8},
+    };
+    for (const Up &u : ups) {
+        if (u.bytes == 0 || !u.dst) continue;
+        e = hipMemcpyAsync(u.dst, u.src, u.bytes, hipMemcpyHostToDevice, c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "upload batch");
+    }
+    if (!gen) {
+        e = hipMemcpyAsync(b.power, bt->power, (size_t)bt->power_len * sizeof(float), hipMemcpyDefault, c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "upload batch tables");
+    }
+    // the host vectors above are released on return: make the copies complete
+    e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "upload batch");
+    c->batch_runs = n_runs;
+    c->batch_k = k;
+    c->batch_cap = cap;
+    c->have_batch = false;
+    if (c->graph_exec) {
+        (void)hipGraphExecDestroy(c->graph_exec);
+        c->graph_exec = nullptr;
+    }
+    if (c->graph) {
+        (void)hipGraphDestroy(c->graph);
+        c->graph = nullptr;
+    }
+    if (use_graph) {
+        if (!c->capture_stream && hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking) != hipSuccess)
+            return fail(c, FT_E_DEVICE, "capture stream");
+        e = hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return hip_fail(c, e, "begin capture");
+        ft_status st = launch_batch_sequence(c, pl, gen, c->capture_stream);
+        hipGraph_t g = nullptr;
+        hipError_t e2 = hipStreamEndCapture(c->capture_stream, &g);
+        if (st != FT_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return st;
+        }
+        if (e2 != hipSuccess) return hip_fail(c, e2, "end capture");
+        c->graph = g;
+        e = hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) return hip_fail(c, e, "instantiate graph");
+        e = hipEventRecord(c->bev[0], c->stream);
+        if (e == hipSuccess) e = hipGraphLaunch(c->graph_exec, c->stream);
+        if (e == hipSuccess) e = hipEventRecord(c->bev[1], c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "launch graph");
+    } else {
+        e = hipEventRecord(c->bev[0], c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "record event");
+        ft_status st = launch_batch_sequence(c, pl, gen, c->stream);
+        if (st != FT_OK) return st;
+        e = hipEventRecord(c->bev[1], c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "record event");
+    }
+    c->have_batch = true;
+    return FT_OK;
+}
+
+ft_status ft_batch_replay(ft_ctx c)
+{
+    if (!c) return FT_E_INVALID;
+    c->err.clear();
+    if (!c->have_batch || !c->graph_exec) return fail(c, FT_E_STATE, "no captured batch to replay");
+    hipError_t e = hipEventRecord(c->bev[0], c->stream);
+    if (e == hipSuccess) e = hipGraphLaunch(c->graph_exec, c->stream);
+    if (e == hipSuccess) e = hipEventRecord(c->bev[1], c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "replay graph");
+    return FT_OK;
+}
+
+ft_status ft_batch_toplist(ft_ctx c, int32_t run, ft_candidate *out, int32_t *n_out)
+{
+    if (!c) return FT_E_INVALID;
+    c->err.clear();
+    if (!c->have_batch) return fail(c, FT_E_STATE, "no batch evaluated");
+    if (run < 0 || run >= c->batch_runs) return fail(c, FT_E_INVALID, "run %d out of range", run);
+    if (!out || !n_out) return fail(c, FT_E_INVALID, "out and n_out must be non-null");
+    ft_status st = sync_and_check(c);
+    if (st != FT_OK) return st;
+    uint32_t flags = 0;
+    if (hipMemcpy(&flags, c->d_err, sizeof flags, hipMemcpyDeviceToHost) != hipSuccess)
+        return fail(c, FT_E_DEVICE, "read flags");
+    if (flags & ERR_CAND_OVERFLOW)
+        return fail(c, FT_E_UNSUPPORTED, "a run has more tied toplist candidates than the batch buffer holds");
+    int32_t n = 0;
+    hipError_t e = hipMemcpy(&n, c->bb.nout + run, sizeof n, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && n > 0)
+        e = hipMemcpy(out, c->bb.out + (size_t)run * c->batch_k, (size_t)n * sizeof(ft_candidate), hipMemcpyDefault);
+    if (e != hipSuccess) return hip_fail(c, e, "copy batch toplist");
+    *n_out = n;
+    return FT_OK;
+}
+
+ft_status ft_batch_labels(ft_ctx c, double tau, uint8_t *labels, double *max_z)
+{
+    if (!c) return FT_E_INVALID;
+    c->err.clear();
+    if (!c->have_batch) return fail(c, FT_E_STATE, "no batch evaluated");
+    if (!is_finite(tau)) return fail(c, FT_E_INVALID, "tau must be finite");
+    hipError_t e = launch_labels(c->bb.maxz, c->batch_runs, tau, c->bb.labels, c->stream);
+    if (e == hipSuccess && labels)
+        e = hipMemcpyAsync(labels, c->bb.labels, (size_t)c->batch_runs, hipMemcpyDefault, c->stream);
+    if (e == hipSuccess && max_z)
+        e = hipMemcpyAsync(max_z, c->bb.maxz, (size_t)c->batch_runs * sizeof(double), hipMemcpyDefault, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "labels");
+    ft_status st = sync_and_check(c);
+    if (st != FT_OK) return st;
+    uint32_t flags = 0;
+    if (hipMemcpy(&flags, c->d_err, sizeof flags, hipMemcpyDeviceToHost) != hipSuccess)
+        return fail(c, FT_E_DEVICE, "read flags");
+    if (flags & ERR_CAND_OVERFLOW)
+        return fail(c, FT_E_UNSUPPORTED, "a run has more tied toplist candidates than the batch buffer holds");
+    return FT_OK;
+}
+
+ft_status ft_batch_time(ft_ctx c, double *ms)
+{
+    if (!c || !ms) return FT_E_INVALID;
+    if (!c->have_batch) return fail(c, FT_E_STATE, "no batch evaluated");
+    ft_status st = sync_and_check(c);
+    if (st != FT_OK) return st;
+    float f = 0.f;
+    if (hipEventElapsedTime(&f, c->bev[0], c->bev[1]) != hipSuccess) return fail(c, FT_E_DEVICE, "event time");
+    *ms = f;
     return FT_OK;
 }
 

@@ -312,6 +312,41 @@ __global__ __launch_bounds__(64 * NW) void eval_grid_kernel(EvalRun r)
     }
 }
 
+// Persistent batch kernel: workgroups pull (run, tile) items from a queue
+// shared by every run of a batch until it is drained; each item is one tile of
+// one run's grid bank.  The queue counter is reset by the launcher's preceding
+// fill kernel, so the sequence can be captured in a HIP graph.
+template <int L, int JT, int NW, int KS>
+__global__ __launch_bounds__(64 * NW) void eval_batch_kernel(const EvalRun *runs,
+                                                             const int2 *items, int n_items,
+                                                             unsigned *counter)
+{
+    extern __shared__ float win[];
+    __shared__ Shared<L, JT, NW, KS> sh;
+    __shared__ int item_sh;
+    for (;;) {
+        __syncthreads();  // every thread has read the previous item
+        if (threadIdx.x == 0) item_sh = (int)atomicAdd(counter, 1u);
+        __syncthreads();
+        const int item = __builtin_amdgcn_readfirstlane(item_sh);
+        if (item >= n_items) break;
+        const int2 it = items[item];
+        const EvalRun r = runs[__builtin_amdgcn_readfirstlane(it.x)];
+        eval_tile<L, JT, NW, KS>(r, __builtin_amdgcn_readfirstlane(it.y), win, sh);
+    }
+}
+
+template <int L, int JT, int NW, int KS>
+hipError_t launch_batch_t(const EvalRun *runs, const int2 *items, int n_items, int max_wtp,
+                          unsigned *counter, int grid, hipStream_t s)
+{
+    if (n_items <= 0) return hipSuccess;
+    const size_t lds = (size_t)2 * KS * max_wtp * sizeof(float);
+    hipLaunchKernelGGL((eval_batch_kernel<L, JT, NW, KS>), dim3((unsigned)grid), dim3(64 * NW), lds,
+                       s, runs, items, n_items, counter);
+    return hipGetLastError();
+}
+
 template <int L, int JT, int NW, int KS>
 hipError_t launch_t(const EvalRun &r, hipStream_t s)
 {
@@ -328,16 +363,19 @@ hipError_t launch_t(const EvalRun &r, hipStream_t s)
 }
 
 using Launcher = hipError_t (*)(const EvalRun &, hipStream_t);
+using BatchLauncher = hipError_t (*)(const EvalRun *, const int2 *, int, int, unsigned *, int,
+                                     hipStream_t);
 
 struct TileEntry {
     TileCfg cfg;
     Launcher fn;
+    BatchLauncher batch_fn;
     size_t static_lds;
 };
 
 #define FT_TILE(id, L, JT, NW, KS)                                                       \
     {{id, "L" #L "_J" #JT "_W" #NW "_K" #KS, L, JT, NW, KS}, &launch_t<L, JT, NW, KS>, \
-     sizeof(Shared<L, JT, NW, KS>)}
+     &launch_batch_t<L, JT, NW, KS>, sizeof(Shared<L, JT, NW, KS>)}
 
 const TileEntry kTiles[] = {
     FT_TILE(0, 1, 1, 4, 16),
@@ -354,6 +392,9 @@ const TileEntry kTiles[] = {
     FT_TILE(11, 7, 2, 4, 16),
     FT_TILE(12, 9, 2, 4, 16),
     FT_TILE(13, 3, 8, 4, 8),
+    FT_TILE(14, 1, 3, 4, 16),
+    FT_TILE(15, 3, 3, 4, 16),
+    FT_TILE(16, 5, 3, 4, 8),
 };
 
 }  // namespace
@@ -367,6 +408,12 @@ size_t tile_static_lds(int id) { return kTiles[id].static_lds; }
 hipError_t launch_eval_grid(const EvalRun &run, const TileCfg &cfg, hipStream_t s)
 {
     return kTiles[cfg.id].fn(run, s);
+}
+
+hipError_t launch_eval_batch(const EvalRun *runs, const int2 *items, int n_items, int max_wtp,
+                             unsigned *counter, int grid, const TileCfg &cfg, hipStream_t s)
+{
+    return kTiles[cfg.id].batch_fn(runs, items, n_items, max_wtp, counter, grid, s);
 }
 
 }  // namespace ft

@@ -280,6 +280,22 @@ __global__ void dt_kernel(const double *t_mid, double t_ref, double *dt, int n)
     if (k < n) dt[k] = t_mid[k] - t_ref;
 }
 
+// dt of every run of a batch: dt[dt_prefix[r] + k] = t_mid[sft_begin[r] + k] - t_ref[r].
+__global__ void batch_dt_kernel(const double *t_mid, const int32_t *sft_begin, const double *t_ref,
+                                const int64_t *dt_prefix, int n_runs, int64_t total, double *dt)
+{
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        int lo = 0, hi = n_runs;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (dt_prefix[mid] <= q) lo = mid;
+            else hi = mid;
+        }
+        dt[q] = t_mid[sft_begin[lo] + (q - dt_prefix[lo])] - t_ref[lo];
+    }
+}
+
 // mu_G = 2 sum w and sigma_G = 2 sqrt(sum w^2) (Sec. II.B.1), sequential in
 // SFT order.
 __global__ void noise_moments_kernel(const float *weight, int n, double *mu_sigma)
@@ -372,6 +388,16 @@ hipError_t launch_dt(const double *t_mid, double t_ref, double *dt, int n, hipSt
 {
     hipLaunchKernelGGL(dt_kernel, dim3(grid_for(n, 256, (1u << 22))), dim3(256), 0, s, t_mid,
                        t_ref, dt, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_dt(const double *t_mid, const int32_t *sft_begin, const double *t_ref,
+                           const int64_t *dt_prefix, int n_runs, int64_t total, double *dt,
+                           hipStream_t s)
+{
+    if (total <= 0) return hipSuccess;
+    hipLaunchKernelGGL(batch_dt_kernel, dim3(grid_for(total, 256, 8192)), dim3(256), 0, s, t_mid,
+                       sft_begin, t_ref, dt_prefix, n_runs, total, dt);
     return hipGetLastError();
 }
 

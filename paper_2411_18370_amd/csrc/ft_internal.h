@@ -90,6 +90,16 @@ size_t tile_static_lds(int id);
 
 // Launchers (stream-ordered, no synchronisation).
 hipError_t launch_eval_grid(const EvalRun &run, const TileCfg &cfg, hipStream_t s);
+// items[i] = (run, tile within the run); counter must be zero at launch.
+hipError_t launch_eval_batch(const EvalRun *runs, const int2 *items, int n_items, int max_wtp,
+                             unsigned *counter, int grid, const TileCfg &cfg, hipStream_t s);
+// Exact per-run toplists of a batch (one workgroup per run, all of a run's
+// templates form one segment): out[r*k + rank], n_out[r], max_z[r].
+hipError_t launch_select_batch(const EvalRun *runs, int n_runs, int k, int cap_per_run,
+                               int64_t *cand, double *cand_s64, ft_candidate *out,
+                               int32_t *n_out, double *max_z, uint32_t *err, hipStream_t s);
+hipError_t launch_labels(const double *max_z, int n_runs, double tau, uint8_t *labels,
+                         hipStream_t s);
 hipError_t launch_eval_list(const EvalRun &run, hipStream_t s);
 hipError_t launch_eval_grid_direct(const EvalRun &run, hipStream_t s);
 hipError_t launch_bins_list(const EvalRun &run, int precision, int32_t *bins, hipStream_t s);
@@ -102,6 +112,32 @@ hipError_t launch_weight_table(const float *power, const float *weight, float *o
 hipError_t launch_fill_u32(uint32_t *p, uint32_t value, int64_t n, hipStream_t s);
 hipError_t launch_dt(const double *t_mid, double t_ref, double *dt, int n, hipStream_t s);
 hipError_t launch_noise_moments(const float *weight, int n, double *mu_sigma, hipStream_t s);
+hipError_t launch_batch_dt(const double *t_mid, const int32_t *sft_begin, const double *t_ref,
+                           const int64_t *dt_prefix, int n_runs, int64_t total, double *dt,
+                           hipStream_t s);
+
+// One synthetic run of an injection campaign (table generator).
+struct GenRun {
+    uint64_t seed;
+    uint32_t run;
+    int32_t sft_offset;   // added to the SFT index in the Philox counter
+    int32_t n_sft, n_bins;
+    int64_t first_bin;
+    const double *t_mid;  // [n_sft]
+    const double *v;      // [n_sft][3]
+    const double *arms;   // [n_sft][6]
+    double t_ref, t_sft;
+    double amp, cos_iota, psi, sky[3], f0, f1;
+    float *table;         // [n_sft][n_bins] output
+    int32_t *inj_bin;     // [n_sft] scratch
+    double *inj_amp;      // [n_sft][3] scratch
+};
+// Generate the tables of n_runs runs (device array of GenRun);
+// sft_prefix[r] / elem_prefix[r] are exclusive prefix sums of n_sft and
+// n_sft*n_bins (n_runs + 1 entries each, device).
+hipError_t launch_gen_tables(const GenRun *runs, int n_runs, const int64_t *sft_prefix,
+                             const int64_t *elem_prefix, int64_t total_sft, int64_t total_elem,
+                             hipStream_t s);
 
 // Selection: exact toplists per segment (segment = sub-band here).
 struct SelectBufs {

@@ -1,0 +1,180 @@
+// Synthetic SFT tables for injection campaigns: circular complex Gaussian
+// noise plus an optional continuous-wave signal (signal hypothesis of
+// Sec. II.B.2), generated on the device.
+//
+// Noise: Re, Im ~ N(0, 1) per (SFT k, bin b), from the counter-based generator
+// Philox-4x32-10 (Salmon, Moraes, Dror and Shaw, SC'11) with counter
+// (b, k, run, 0) and key (seed_lo, seed_hi); the two 64-bit halves of the
+// output give two uniforms (m + 1/2) 2^-53 (m = top 53 bits) for the
+// Box-Muller transform (Box and Muller 1958): r = sqrt(-2 ln u1),
+// th = 2 pi u2, (Re, Im) = (r cos th, r sin th).
+//
+// Signal: in SFT k the track is at x_k = ((f0 + f1 dt_k) g_k) T bins (the
+// canonical FP64 track), B_k = floor(x_k + 1/2), delta_k = x_k - B_k; power
+// non-centrality rho_k^2 = T amp^2 (F+^2 A+^2 + Fx^2 Ax^2), amp = h0/sqrt(S_n),
+// A+ = (1 + cos^2 iota)/2, Ax = cos iota; bins B_k + m (m = -1, 0, 1) receive
+// sqrt(rho_k^2) |sinc(pi (delta_k - m))| added to Re.  Antenna patterns:
+// F+ = D:e+, Fx = D:ex with D = (u u^T - w w^T)/2 from the arm unit vectors and
+// (p, q) = (e_alpha, e_delta) rotated by psi.
+#include "ft_internal.h"
+
+namespace ft {
+
+namespace {
+
+constexpr uint32_t PH_M0 = 0xD2511F53u, PH_M1 = 0xCD9E8D57u;
+constexpr uint32_t PH_W0 = 0x9E3779B9u, PH_W1 = 0xBB67AE85u;
+
+__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t hi0 = __umulhi(PH_M0, c[0]), lo0 = PH_M0 * c[0];
+        const uint32_t hi1 = __umulhi(PH_M1, c[2]), lo1 = PH_M1 * c[2];
+        const uint32_t n0 = hi1 ^ c[1] ^ k0;
+        const uint32_t n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0;
+        c[1] = lo1;
+        c[2] = n2;
+        c[3] = lo0;
+        k0 += PH_W0;
+        k1 += PH_W1;
+    }
+}
+
+__device__ __forceinline__ double unit53(uint32_t hi, uint32_t lo)
+{
+    const uint64_t m = (((uint64_t)hi << 32) | lo) >> 11;
+    return ((double)m + 0.5) * 0x1p-53;
+}
+
+__device__ __forceinline__ double sinc_pi(double d)
+{
+    const double y = M_PI * d;
+    return y != 0.0 ? sin(y) / y : 1.0;
+}
+
+// Run r of a batch holding global index q, given exclusive prefix sums.
+__device__ __forceinline__ int find_run(const int64_t *prefix, int n_runs, int64_t q)
+{
+    int lo = 0, hi = n_runs;  // last r with prefix[r] <= q
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (prefix[mid] <= q) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Per SFT of a run: injection bin and the three bin amplitudes.
+__device__ void gen_prep_one(const GenRun &g, int k)
+{
+    if (g.amp == 0.0) {
+        g.inj_bin[k] = INT32_MIN;
+        return;
+    }
+    const double *v = g.v + 3 * (int64_t)k;
+    const double gk = doppler_factor(v[0], v[1], v[2], g.sky[0], g.sky[1], g.sky[2]);
+    const double dt = g.t_mid[k] - g.t_ref;
+    const double c = g.f1 * dt;
+    const double a = g.f0 + c;
+    const double f = a * gk;
+    const double x = f * g.t_sft;
+    const double B = floor(x + 0.5);
+    const double delta = x - B;
+    // polarisation frame of the source
+    const double n0 = g.sky[0], n1 = g.sky[1], n2 = g.sky[2];
+    const double rho = hypot(n0, n1);
+    double ea[3], ed[3];
+    if (rho > 0.0) {
+        ea[0] = -n1 / rho;
+        ea[1] = n0 / rho;
+        ea[2] = 0.0;
+        ed[0] = -n2 * n0 / rho;
+        ed[1] = -n2 * n1 / rho;
+        ed[2] = rho;
+    } else {
+        ea[0] = 0.0;
+        ea[1] = 1.0;
+        ea[2] = 0.0;
+        ed[0] = -n2;
+        ed[1] = 0.0;
+        ed[2] = 0.0;
+    }
+    const double cp = cos(g.psi), sp = sin(g.psi);
+    double p[3], q[3];
+    for (int i = 0; i < 3; ++i) {
+        p[i] = cp * ea[i] + sp * ed[i];
+        q[i] = -sp * ea[i] + cp * ed[i];
+    }
+    const double *arm = g.arms + 6 * (int64_t)k;
+    const double up = arm[0] * p[0] + arm[1] * p[1] + arm[2] * p[2];
+    const double uq = arm[0] * q[0] + arm[1] * q[1] + arm[2] * q[2];
+    const double wp = arm[3] * p[0] + arm[4] * p[1] + arm[5] * p[2];
+    const double wq = arm[3] * q[0] + arm[4] * q[1] + arm[5] * q[2];
+    const double fp = 0.5 * ((up * up - uq * uq) - (wp * wp - wq * wq));
+    const double fx = up * uq - wp * wq;
+    const double ap = 0.5 * (1.0 + g.cos_iota * g.cos_iota);
+    const double ax = g.cos_iota;
+    const double r2 = g.t_sft * g.amp * g.amp * (fp * fp * ap * ap + fx * fx * ax * ax);
+    const double sr = sqrt(r2);
+    for (int m = -1; m <= 1; ++m) g.inj_amp[3 * k + (m + 1)] = sr * fabs(sinc_pi(delta - (double)m));
+    g.inj_bin[k] = (int32_t)B;
+}
+
+__global__ void gen_prep_kernel(const GenRun *runs, int n_runs, const int64_t *sft_prefix,
+                                int64_t total_sft)
+{
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total_sft;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const int r = find_run(sft_prefix, n_runs, q);
+        gen_prep_one(runs[r], (int)(q - sft_prefix[r]));
+    }
+}
+
+__global__ void gen_noise_kernel(const GenRun *runs, int n_runs, const int64_t *elem_prefix,
+                                 int64_t total_elem)
+{
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total_elem;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const int rr = find_run(elem_prefix, n_runs, q);
+        const GenRun &g = runs[rr];
+        const int64_t e = q - elem_prefix[rr];
+        const int k = (int)(e / g.n_bins);
+        const int b = (int)(e - (int64_t)k * g.n_bins);
+        uint32_t c[4] = {(uint32_t)b, (uint32_t)(k + g.sft_offset), g.run, 0u};
+        philox4x32_10(c, (uint32_t)g.seed, (uint32_t)(g.seed >> 32));
+        const double u1 = unit53(c[0], c[1]);
+        const double u2 = unit53(c[2], c[3]);
+        const double r = sqrt(-2.0 * log(u1));
+        const double th = 2.0 * M_PI * u2;
+        double re = r * cos(th);
+        const double im = r * sin(th);
+        const int32_t B = g.inj_bin[k];
+        if (B != INT32_MIN) {
+            const int64_t m = g.first_bin + b - (int64_t)B;
+            if (m >= -1 && m <= 1) re += g.inj_amp[3 * k + (int)(m + 1)];
+        }
+        g.table[e] = (float)(re * re + im * im);
+    }
+}
+
+}  // namespace
+
+hipError_t launch_gen_tables(const GenRun *runs, int n_runs, const int64_t *sft_prefix,
+                             const int64_t *elem_prefix, int64_t total_sft, int64_t total_elem,
+                             hipStream_t s)
+{
+    if (n_runs <= 0 || total_elem <= 0) return hipSuccess;
+    int64_t b1 = (total_sft + 255) / 256;
+    if (b1 > 16384) b1 = 16384;
+    hipLaunchKernelGGL(gen_prep_kernel, dim3((unsigned)b1), dim3(256), 0, s, runs, n_runs,
+                       sft_prefix, total_sft);
+    int64_t b2 = (total_elem + 255) / 256;
+    if (b2 > 32768) b2 = 32768;
+    hipLaunchKernelGGL(gen_noise_kernel, dim3((unsigned)b2), dim3(256), 0, s, runs, n_runs,
+                       elem_prefix, total_elem);
+    return hipGetLastError();
+}
+
+}  // namespace ft

@@ -319,6 +319,151 @@ __global__ void init_state_kernel(uint32_t *state, uint32_t *cnt, uint32_t *fill
     fill[sg] = 0;
 }
 
+// ---------------------------------------------------------------------------
+// Batches: one workgroup per run does the whole exact selection of that run
+// (runs hold at most a few 1e5 templates): radix select in LDS, candidate
+// compaction, FP64 re-summation (one wavefront per candidate) and ranking.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void select_batch_kernel(const EvalRun *runs, int k, int cap,
+                                                           int64_t *cand_all, double *s64_all,
+                                                           ft_candidate *out, int32_t *n_out,
+                                                           double *max_z, uint32_t *err)
+{
+    __shared__ uint32_t hist[256];
+    __shared__ uint32_t st_prefix, st_mask, st_krem, st_thr, st_done, n_cand;
+    const int r = blockIdx.x;
+    const EvalRun R = runs[r];
+    const int64_t n_t = (int64_t)R.n_f0 * R.n_f1 * R.n_sky;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const double N = (double)R.n_sft;
+    const double two_e = 2.0 * (40.0 * 0x1p-24 + 4.0 * N * 0x1p-53);
+    int64_t *cand = cand_all + (int64_t)r * cap;
+    double *s64 = s64_all + (int64_t)r * cap;
+    if (tid == 0) {
+        st_prefix = 0;
+        st_mask = 0;
+        st_krem = (uint32_t)k;
+        st_done = 0;
+        st_thr = 0;
+        n_cand = 0;
+    }
+    for (int pass = 0; pass < 4; ++pass) {
+        const int shift = 24 - 8 * pass;
+        hist[tid] = 0;
+        __syncthreads();
+        if (!st_done) {
+            const uint32_t mask = st_mask, prefix = st_prefix;
+            for (int64_t t = tid; t < n_t; t += 256) {
+                const uint32_t key = __float_as_uint(R.stats[t]);
+                if (key > NAN_KEY || (key & mask) != prefix) continue;
+                atomicAdd(&hist[(key >> shift) & 255u], 1u);
+            }
+        }
+        __syncthreads();
+        if (tid == 0 && !st_done) {
+            uint32_t cum = 0;
+            int found = -1;
+            for (int d = 255; d >= 0; --d) {
+                if (cum + hist[d] >= st_krem) {
+                    found = d;
+                    break;
+                }
+                cum += hist[d];
+            }
+            if (found < 0) {
+                st_done = 1;
+                st_thr = 0;
+            } else {
+                st_prefix |= (uint32_t)found << shift;
+                st_mask |= 255u << shift;
+                st_krem -= cum;
+                if (shift == 0) {
+                    const double kth = (double)__uint_as_float(st_prefix);
+                    const double thr = kth * (1.0 - two_e) / (1.0 + two_e);
+                    float tf = (float)thr;
+                    if ((double)tf > thr) tf = nextafterf(tf, 0.f);
+                    if (!(tf > 0.f)) tf = 0.f;
+                    st_thr = __float_as_uint(tf);
+                    st_done = 1;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    const uint32_t thr = st_thr;
+    for (int64_t t = tid; t < n_t; t += 256) {
+        const uint32_t key = __float_as_uint(R.stats[t]);
+        if (key > NAN_KEY || key < thr) continue;
+        const uint32_t pos = atomicAdd(&n_cand, 1u);
+        if (pos < (uint32_t)cap) cand[pos] = t;
+    }
+    __syncthreads();
+    int nc = (int)n_cand;
+    if (nc > cap) {
+        if (tid == 0) atomicOr(err, ERR_CAND_OVERFLOW);
+        nc = cap;
+    }
+    // FP64 re-summation in SFT order with canonical bins
+    uint32_t bad = 0;
+    for (int p = wave; p < nc; p += 4) {
+        const TemplateParams tp = params_of(R, true, cand[p]);
+        double acc = 0.0;
+        for (int k0 = 0; k0 < R.n_sft; k0 += 64) {
+            const int kq = k0 + lane;
+            double val = 0.0;
+            if (kq < R.n_sft) {
+                const double *vk = R.v + 3 * (int64_t)kq;
+                const double g = doppler_factor(vk[0], vk[1], vk[2], tp.nx, tp.ny, tp.nz);
+                int b = bin_fp64(tp.f0, tp.f1 * R.dt[kq], g, R.t_sft) - R.first_bin;
+                if (b < 0 || b >= R.n_bins) {
+                    bad = ERR_RANGE;
+                    b = b < 0 ? 0 : R.n_bins - 1;
+                }
+                const double w = R.weight ? (double)R.weight[kq] : 1.0;
+                val = w * (double)R.power[(int64_t)kq * R.n_bins + b];
+            }
+            const int m = min(64, R.n_sft - k0);
+            for (int l = 0; l < m; ++l) acc = acc + readlane_f64(val, l);
+        }
+        if (lane == 0) s64[p] = acc;
+    }
+    if (bad) atomicOr(err, bad);
+    __syncthreads();
+    const double mu = 2.0 * N, sigma = 2.0 * sqrt(N);
+    for (int p = tid; p < nc; p += 256) {
+        const double sp = s64[p];
+        const int64_t tp = cand[p];
+        int rank = 0;
+        for (int q = 0; q < nc && rank < k; ++q) {
+            const double sq = s64[q];
+            rank += (sq > sp) || (sq == sp && cand[q] < tp);
+        }
+        if (rank < k) {
+            const TemplateParams par = params_of(R, true, tp);
+            ft_candidate c;
+            c.index = tp;
+            c.sub = 0;
+            c.s32 = R.stats[tp];
+            c.f0 = par.f0;
+            c.f1 = par.f1;
+            c.n[0] = par.nx;
+            c.n[1] = par.ny;
+            c.n[2] = par.nz;
+            c.s64 = sp;
+            c.z = (sp - mu) / sigma;
+            out[(int64_t)r * k + rank] = c;
+            if (rank == 0) max_z[r] = c.z;
+        }
+    }
+    if (tid == 0) n_out[r] = min(nc, k);
+}
+
+__global__ void labels_kernel(const double *max_z, int n_runs, double tau, uint8_t *labels)
+{
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < n_runs) labels[r] = max_z[r] > tau ? 1 : 0;
+}
+
 Rows rows_of(const EvalRun &r, bool grid)
 {
     Rows rw;
@@ -338,6 +483,25 @@ Rows rows_of(const EvalRun &r, bool grid)
 unsigned blocks_for(int64_t n_rows) { return (unsigned)std::min<int64_t>(std::max<int64_t>(n_rows, 1), 8192); }
 
 }  // namespace
+
+hipError_t launch_select_batch(const EvalRun *runs, int n_runs, int k, int cap_per_run,
+                               int64_t *cand, double *cand_s64, ft_candidate *out,
+                               int32_t *n_out, double *max_z, uint32_t *err, hipStream_t s)
+{
+    if (n_runs <= 0) return hipSuccess;
+    hipLaunchKernelGGL(select_batch_kernel, dim3((unsigned)n_runs), dim3(256), 0, s, runs, k,
+                       cap_per_run, cand, cand_s64, out, n_out, max_z, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_labels(const double *max_z, int n_runs, double tau, uint8_t *labels,
+                         hipStream_t s)
+{
+    if (n_runs <= 0) return hipSuccess;
+    hipLaunchKernelGGL(labels_kernel, dim3((unsigned)((n_runs + 255) / 256)), dim3(256), 0, s,
+                       max_z, n_runs, tau, labels);
+    return hipGetLastError();
+}
 
 hipError_t launch_subband_map(const double *f0, int64_t n, const double *edges, int n_sub,
                               int32_t *seg, hipStream_t s)

@@ -46,6 +46,29 @@ class ft_candidate(C.Structure):
                 ("s64", C.c_double), ("z", C.c_double)]
 
 
+class ft_injection(C.Structure):
+    _fields_ = [("amp", C.c_double), ("cos_iota", C.c_double), ("psi", C.c_double),
+                ("sky", C.c_double * 3), ("f0", C.c_double), ("f1", C.c_double)]
+
+
+class ft_run(C.Structure):
+    _fields_ = [("seed", C.c_uint64), ("run_id", C.c_uint32), ("sft_begin", C.c_int32),
+                ("n_sft", C.c_int32), ("n_bins", C.c_int32), ("first_bin", C.c_int64),
+                ("table_offset", C.c_int64), ("f0_begin", C.c_int32), ("n_f0", C.c_int32),
+                ("f1_begin", C.c_int32), ("n_f1", C.c_int32), ("sky_begin", C.c_int32),
+                ("n_sky", C.c_int32), ("t_ref", C.c_double), ("inj", ft_injection)]
+
+
+class ft_batch(C.Structure):
+    _fields_ = [("n_runs", C.c_int32), ("k", C.c_int32), ("runs", C.c_void_p),
+                ("n_sft_total", C.c_int32), ("generate", C.c_int32), ("t_mid", C.c_void_p),
+                ("v_over_c", C.c_void_p), ("arms", C.c_void_p), ("t_sft", C.c_double),
+                ("n_f0_total", C.c_int64), ("n_f1_total", C.c_int64), ("n_sky_total", C.c_int64),
+                ("f0", C.c_void_p), ("f1", C.c_void_p), ("sky_xyz", C.c_void_p),
+                ("power_len", C.c_int64), ("power", C.c_void_p), ("tile", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
 class ft_eval_info(C.Structure):
     _fields_ = [("eval_ms", C.c_double), ("select_ms", C.c_double),
                 ("n_templates", C.c_int64), ("n_evals", C.c_int64),
@@ -57,7 +80,8 @@ _lib = None
 EXPORTS = ("ft_create", "ft_destroy", "ft_last_error", "ft_status_string", "ft_set_sfts",
            "ft_set_velocities", "ft_eval_templates", "ft_toplist", "ft_sync",
            "ft_last_eval_info", "ft_bins", "ft_count_index_mismatches", "ft_tile_count",
-           "ft_tile_name")
+           "ft_tile_name", "ft_gen_sfts", "ft_eval_batch", "ft_batch_toplist", "ft_batch_labels",
+           "ft_batch_replay", "ft_batch_time")
 
 
 def load(path: str = LIB_PATH):
@@ -85,7 +109,14 @@ def load(path: str = LIB_PATH):
         "ft_count_index_mismatches": (C.c_int, [P, C.POINTER(ft_bank), f64, i32,
                                                 C.POINTER(i64)]),
         "ft_tile_count": (i32, []),
+        "ft_gen_sfts": (C.c_int, [P, i32, P, P, f64, i64, i32, P, P, C.c_uint64, C.c_uint32, f64,
+                                  C.POINTER(ft_injection), P]),
         "ft_tile_name": (C.c_char_p, [i32]),
+        "ft_eval_batch": (C.c_int, [P, C.POINTER(ft_batch), i32]),
+        "ft_batch_toplist": (C.c_int, [P, i32, C.POINTER(ft_candidate), C.POINTER(i32)]),
+        "ft_batch_labels": (C.c_int, [P, f64, P, P]),
+        "ft_batch_replay": (C.c_int, [P]),
+        "ft_batch_time": (C.c_int, [P, C.POINTER(f64)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -156,6 +187,30 @@ def ft_set_sfts(ctx, n_sft_per_det, t_mid, t_sft, first_bin, power, weight=None)
     n_bins = int(power.shape[1])
     _check(ctx, load().ft_set_sfts(ctx, len(n_sft_per_det), n.ptr, tm.ptr, float(t_sft),
                                    int(first_bin), n_bins, p.ptr, w.ptr))
+
+
+def make_injection(inj):
+    """ft_injection from a dict with amp, cos_iota, psi, sky, f0, f1 (or None)."""
+    if inj is None:
+        return None
+    r = ft_injection()
+    r.amp, r.cos_iota, r.psi = inj["amp"], inj["cos_iota"], inj["psi"]
+    for d in range(3):
+        r.sky[d] = float(inj["sky"][d])
+    r.f0, r.f1 = inj["f0"], inj["f1"]
+    return r
+
+
+def ft_gen_sfts(ctx, n_sft_per_det, t_mid, t_sft, first_bin, n_bins, v_over_c, arms, seed, run,
+                t_ref, inj=None, power_out=None):
+    n = _Arr(np.asarray(n_sft_per_det, np.int32), np.int32)
+    tm, v, a = _Arr(t_mid, np.float64), _Arr(v_over_c, np.float64), _Arr(arms, np.float64)
+    out = _Arr(power_out, np.float32)
+    ij = make_injection(inj)
+    _check(ctx, load().ft_gen_sfts(ctx, len(n_sft_per_det), n.ptr, tm.ptr, float(t_sft),
+                                   int(first_bin), int(n_bins), v.ptr, a.ptr, int(seed), int(run),
+                                   float(t_ref), C.byref(ij) if ij is not None else None,
+                                   out.ptr))
 
 
 def ft_set_velocities(ctx, v_over_c):
@@ -233,6 +288,71 @@ def ft_tile_name(tile):
     return load().ft_tile_name(tile).decode()
 
 
+def make_runs(runs):
+    """ft_run array from a list of dicts (keys as the C fields; 'inj' a dict or None)."""
+    arr = (ft_run * len(runs))()
+    for i, d in enumerate(runs):
+        r = arr[i]
+        r.seed, r.run_id = int(d.get("seed", 0)), int(d.get("run_id", i))
+        r.sft_begin, r.n_sft = int(d["sft_begin"]), int(d["n_sft"])
+        r.n_bins, r.first_bin = int(d["n_bins"]), int(d["first_bin"])
+        r.table_offset = int(d.get("table_offset", 0))
+        r.f0_begin, r.n_f0 = int(d["f0_begin"]), int(d["n_f0"])
+        r.f1_begin, r.n_f1 = int(d["f1_begin"]), int(d["n_f1"])
+        r.sky_begin, r.n_sky = int(d["sky_begin"]), int(d["n_sky"])
+        r.t_ref = float(d["t_ref"])
+        if d.get("inj") is not None:
+            r.inj = make_injection(d["inj"])
+    return arr
+
+
+def ft_eval_batch(ctx, runs, t_mid, v_over_c, t_sft, f0, f1, sky, k, arms=None, power=None,
+                  tile=0, use_graph=0):
+    """Evaluate a batch; runs is a list of dicts (see make_runs).  Tables are
+    generated on the GPU when `power` is None (arms required)."""
+    keep = [_Arr(t_mid, np.float64), _Arr(v_over_c, np.float64), _Arr(arms, np.float64),
+            _Arr(f0, np.float64), _Arr(f1, np.float64), _Arr(sky, np.float64),
+            _Arr(power, np.float32)]
+    rr = make_runs(runs)
+    b = ft_batch()
+    b.n_runs, b.k, b.runs = len(runs), int(k), C.cast(rr, C.c_void_p)
+    b.n_sft_total = len(t_mid)
+    b.generate = 1 if power is None else 0
+    b.t_mid, b.v_over_c, b.arms = keep[0].ptr, keep[1].ptr, keep[2].ptr
+    b.t_sft = float(t_sft)
+    b.n_f0_total, b.n_f1_total, b.n_sky_total = len(f0), len(f1), int(sky.shape[0])
+    b.f0, b.f1, b.sky_xyz = keep[3].ptr, keep[4].ptr, keep[5].ptr
+    b.power_len = 0 if power is None else int(np.prod(power.shape))
+    b.power = keep[6].ptr
+    b.tile = tile
+    _check(ctx, load().ft_eval_batch(ctx, C.byref(b), int(use_graph)))
+
+
+def ft_batch_toplist(ctx, run, k):
+    out = (ft_candidate * k)()
+    n = C.c_int32()
+    _check(ctx, load().ft_batch_toplist(ctx, run, out, C.byref(n)))
+    return [out[i] for i in range(n.value)]
+
+
+def ft_batch_labels(ctx, tau, n_runs):
+    labels = np.empty(n_runs, np.uint8)
+    max_z = np.empty(n_runs, np.float64)
+    _check(ctx, load().ft_batch_labels(ctx, float(tau), labels.ctypes.data_as(C.c_void_p),
+                                       max_z.ctypes.data_as(C.c_void_p)))
+    return labels, max_z
+
+
+def ft_batch_replay(ctx):
+    _check(ctx, load().ft_batch_replay(ctx))
+
+
+def ft_batch_time(ctx):
+    ms = C.c_double()
+    _check(ctx, load().ft_batch_time(ctx, C.byref(ms)))
+    return ms.value
+
+
 _n_sft_cache = {}
 
 
@@ -272,6 +392,12 @@ class Context:
     def set_velocities(self, v):
         ft_set_velocities(self.ctx, v)
 
+    def gen_sfts(self, n_sft_per_det, t_mid, t_sft, first_bin, n_bins, v, arms, seed, run, t_ref,
+                 inj=None, power_out=None):
+        ft_gen_sfts(self.ctx, n_sft_per_det, t_mid, t_sft, first_bin, n_bins, v, arms, seed, run,
+                    t_ref, inj, power_out)
+        _n_sft_cache[self.ctx.value] = int(sum(n_sft_per_det))
+
     def eval_templates(self, *a, **kw):
         ft_eval_templates(self.ctx, *a, **kw)
 
@@ -289,6 +415,26 @@ class Context:
 
     def count_index_mismatches(self, *a, **kw):
         return ft_count_index_mismatches(self.ctx, *a, **kw)
+
+    def eval_batch(self, *a, **kw):
+        ft_eval_batch(self.ctx, *a, **kw)
+
+    def batch_toplist(self, run, k):
+        return ft_batch_toplist(self.ctx, run, k)
+
+    def batch_labels(self, tau, n_runs):
+        return ft_batch_labels(self.ctx, tau, n_runs)
+
+    def batch_replay(self):
+        ft_batch_replay(self.ctx)
+
+    def batch_time(self):
+        return ft_batch_time(self.ctx)
+
+    def eval_campaign(self, cp, use_graph=0, tile=0, power=None):
+        """Evaluate a synth.Campaign (tables generated on the GPU unless given)."""
+        ft_eval_batch(self.ctx, cp.runs, cp.t_mid, cp.v, cp.t_sft, cp.f0, cp.f1, cp.sky, cp.k,
+                      arms=cp.arms, power=power, tile=tile, use_graph=use_graph)
 
     def load_workload(self, w):
         """Upload a synth.Workload's SFTs and velocities."""

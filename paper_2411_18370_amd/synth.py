@@ -219,3 +219,77 @@ def precision_stress(seed: int = 2, n_sky: int = 20_000, n_per_det: int = 5000) 
     """Same timestamps as the all-sky band; 1000-1000.1 Hz, 180 f0 x 5 f1 x n_sky."""
     return _build("precision-2det-10ksft-1kHz", 2, n_per_det, 1800.0, 0.1, 1000.0, 180,
                   np.linspace(-1e-9, 0.0, 5), n_sky, 100, 2, seed)
+
+
+@dataclass
+class Campaign:
+    """Many independent runs sharing one SFT pool and one bank pool (inputs only)."""
+    t_sft: float
+    t_mid: np.ndarray     # [n_pool] time-interleaved SFTs of the two detectors
+    v: np.ndarray         # [n_pool, 3]
+    arms: np.ndarray      # [n_pool, 6]
+    f0: np.ndarray        # concatenated per-run f0 grids
+    f1: np.ndarray        # concatenated per-run f1 sets
+    sky: np.ndarray       # concatenated per-run sky sets
+    runs: list            # dicts: seed, run_id, sft_begin, n_sft, first_bin, n_bins, f0_begin,
+                          # n_f0, f1_begin, n_f1, sky_begin, n_sky, t_ref, inj
+    k: int
+
+    @property
+    def evals(self):
+        return sum(r["n_f0"] * r["n_f1"] * r["n_sky"] * r["n_sft"] for r in self.runs)
+
+
+def campaign(n_runs: int, seed: int = 4, n_pool: int = 5000, n_sft_range=(500, 5000),
+             f_range=(100.0, 300.0), width_range=(0.01, 0.2), nt_range=(1e3, 1e5), n_f1: int = 3,
+             amp_range=(0.05, 0.2), k: int = 10, t_sft: float = 1800.0, gap: float = 0.1) -> Campaign:
+    """Uneven injection-recovery runs: N ~ U{n_sft_range} SFTs (a contiguous slice of a
+    two-detector, time-interleaved pool with gaps), band start ~ U(f_range), width
+    ~ U(width_range), template count log-uniform in nt_range as a grid of
+    round(width T) f0 x n_f1 f1 x ceil(n_T/(n_f1 n_f0)) isotropic sky points, one
+    injected signal inside each band."""
+    rng = np.random.default_rng(seed)
+    per_det = (n_pool + 1) // 2
+    ts, vs, arms = [], [], []
+    for d in range(2):
+        t = sft_mid_times(per_det, t_sft, gap, rng)
+        ts.append(t)
+        vs.append(detector_velocity(t, DETECTORS[d]))
+        arms.append(detector_arms(t, DETECTORS[d]))
+    t_all = np.concatenate(ts)
+    order = np.argsort(t_all, kind="stable")[:n_pool]
+    t_mid = t_all[order]
+    v = np.concatenate(vs)[order]
+    arm = np.concatenate(arms)[order]
+    vmax = float(np.max(np.linalg.norm(v, axis=1)))
+    f0_parts, f1_parts, sky_parts, runs = [], [], [], []
+    nf0 = nf1 = nsk = 0
+    for r in range(n_runs):
+        n_sft = int(rng.integers(n_sft_range[0], n_sft_range[1] + 1))
+        n_sft = min(n_sft, n_pool)
+        begin = int(rng.integers(0, n_pool - n_sft + 1))
+        f_lo = float(rng.uniform(*f_range))
+        width = float(rng.uniform(*width_range))
+        n_f0 = max(1, int(round(width * t_sft)))
+        n_t = float(np.exp(rng.uniform(np.log(nt_range[0]), np.log(nt_range[1]))))
+        n_sky = max(1, int(math.ceil(n_t / (n_f1 * n_f0))))
+        f0 = f_lo + np.arange(n_f0, dtype=np.float64) / t_sft
+        f1 = np.linspace(-1e-9, 0.0, n_f1) if n_f1 > 1 else np.zeros(1)
+        sky = isotropic_sky(n_sky, rng)
+        t_ref = float(t_mid[begin] - 0.5 * t_sft)
+        dt = t_mid[begin:begin + n_sft] - t_ref
+        first_bin, n_bins = table_range(f0.min(), f0.max(), f1.min(), f1.max(), dt.min(),
+                                        dt.max(), vmax, t_sft)
+        inj = injection_params(rng, f0[0], f0[-1], amp_range[0], amp_range[1], f1.min(), f1.max())
+        runs.append({"seed": int(rng.integers(1, 2 ** 62)), "run_id": r, "sft_begin": begin,
+                     "n_sft": n_sft, "first_bin": first_bin, "n_bins": n_bins, "f0_begin": nf0,
+                     "n_f0": n_f0, "f1_begin": nf1, "n_f1": len(f1), "sky_begin": nsk,
+                     "n_sky": n_sky, "t_ref": t_ref, "inj": inj})
+        f0_parts.append(f0)
+        f1_parts.append(f1)
+        sky_parts.append(sky)
+        nf0 += n_f0
+        nf1 += len(f1)
+        nsk += n_sky
+    return Campaign(t_sft, t_mid, v, arm, np.concatenate(f0_parts), np.concatenate(f1_parts),
+                    np.concatenate(sky_parts), runs, k)
