@@ -307,6 +307,34 @@ ft_status ft_batch_toplist(ft_ctx ctx, int32_t run, ft_candidate *out, int32_t *
  * max_z[r] receives that critical ratio (either pointer may be NULL). */
 ft_status ft_batch_labels(ft_ctx ctx, double tau, uint8_t *labels, double *max_z);
 
+/*
+ * Surrogate of the detection probability p_det (Sec. V, Eqs. pdet_abstract
+ * and sampling): MLP 6 -> 256 -> 256 -> 256 -> 1 with GELU hidden units and a
+ * sigmoid output, trained on detection labels with binary cross-entropy and
+ * Adam, on the GPU (BF16 matrix-core products, FP32 accumulation and master
+ * weights).  Raw inputs per sample: (h0/sqrt(S_n), cos iota, psi, sin delta,
+ * alpha, f); features are (log of the first, the rest as given), standardised
+ * as (g - shift)/scale.  Parameters (flat FP32, 133,633): W1 [256][6], b1,
+ * W2 [256][256], b2, W3 [256][256], b3, W4 [256], b4.
+ */
+typedef struct ft_mlp_s *ft_mlp;
+/* params: initial parameters (host or device) or NULL for He initialisation
+ * from `seed`; max_batch: largest batch of any later call (>= 1). */
+ft_status ft_mlp_create(ft_ctx ctx, const float *params, uint64_t seed, const float *feat_shift,
+                        const float *feat_scale, int32_t max_batch, ft_mlp *out);
+void ft_mlp_destroy(ft_mlp mlp);
+ft_status ft_mlp_get_params(ft_mlp mlp, float *params);
+/* p[i] = network output for raw inputs raw[i][6], i < n. */
+ft_status ft_mlp_predict(ft_mlp mlp, const float *raw, int64_t n, float *p);
+/* Mean BCE loss and its gradient (flat, like the parameters) on one batch. */
+ft_status ft_mlp_loss_grad(ft_mlp mlp, const float *raw, const float *y, int32_t n, float *loss,
+                           float *grad);
+/* Adam training: `epochs` passes over n samples in batches of `batch`
+ * (a fresh affine permutation of the samples per epoch from `seed`);
+ * epoch_loss[e] (or NULL) receives the mean batch loss of epoch e. */
+ft_status ft_mlp_train(ft_mlp mlp, const float *raw, const float *y, int64_t n, int32_t batch,
+                       int32_t epochs, float lr, uint64_t seed, float *epoch_loss);
+
 /* Tiles of the grid evaluation kernel (for the autotuner and tests); ids are
  * 1..ft_tile_count(), names describe run length L, f1 values JT, waves NW and
  * SFTs per LDS stage KS. */

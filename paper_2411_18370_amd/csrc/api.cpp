@@ -11,6 +11,8 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <numeric>
+#include <random>
 #include <utility>
 #include <vector>
 
@@ -1522,6 +1524,262 @@ ft_status ft_batch_time(ft_ctx c, double *ms)
     float f = 0.f;
     if (hipEventElapsedTime(&f, c->bev[0], c->bev[1]) != hipSuccess) return fail(c, FT_E_DEVICE, "event time");
     *ms = f;
+    return FT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Surrogate MLP
+// ---------------------------------------------------------------------------
+struct ft_mlp_s {
+    ft_ctx ctx = nullptr;
+    MlpBufs m{};
+    MlpConst cst{};
+    int step = 0;
+    float *d_raw = nullptr;
+    size_t cap_raw = 0;
+    float *d_y = nullptr;
+    size_t cap_y = 0;
+    float *d_prob = nullptr;
+    size_t cap_prob = 0;
+    std::vector<void *> allocs;
+};
+
+static void mlp_free(ft_mlp p)
+{
+    for (void *a : p->allocs) (void)hipFree(a);
+    p->allocs.clear();
+    release(&p->d_raw, &p->cap_raw);
+    release(&p->d_y, &p->cap_y);
+    release(&p->d_prob, &p->cap_prob);
+}
+
+}  // extern "C"
+
+template <typename T>
+static hipError_t mlp_alloc(ft_mlp p, T **dst, size_t n)
+{
+    size_t cap = 0;
+    *dst = nullptr;
+    hipError_t e = ensure(dst, &cap, n);
+    if (e == hipSuccess) p->allocs.push_back((void *)*dst);
+    return e;
+}
+
+extern "C" {
+
+ft_status ft_mlp_create(ft_ctx c, const float *params, uint64_t seed, const float *feat_shift,
+                        const float *feat_scale, int32_t max_batch, ft_mlp *out)
+{
+    if (!c || !out) return FT_E_INVALID;
+    *out = nullptr;
+    c->err.clear();
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, FT_E_DEVICE, "hipSetDevice");
+    if (!feat_shift || !feat_scale || max_batch < 1) return fail(c, FT_E_INVALID, "feature map and max_batch >= 1 required");
+    std::vector<float> sh, sc;
+    if (fetch(sh, feat_shift, 6) != hipSuccess || fetch(sc, feat_scale, 6) != hipSuccess)
+        return fail(c, FT_E_INVALID, "cannot read the feature map");
+    for (int i = 0; i < 6; ++i)
+        if (!is_finite(sh[i]) || !is_finite(sc[i]) || !(sc[i] != 0.0f)) return fail(c, FT_E_INVALID, "feature map must be finite, scale != 0");
+    ft_mlp p = new ft_mlp_s();
+    p->ctx = c;
+    for (int i = 0; i < 6; ++i) {
+        p->cst.shift[i] = sh[i];
+        p->cst.scale[i] = sc[i];
+    }
+    const int mb = (max_batch + 63) / 64 * 64;
+    p->m.max_batch = mb;
+    const size_t act = (size_t)mb * MLP_H;
+    MlpBufs &m = p->m;
+    hipError_t e = hipSuccess;
+    float **f32s[] = {&m.theta, &m.m, &m.v, &m.grad};
+    for (float **q : f32s)
+        if (e == hipSuccess) e = mlp_alloc(p, q, (size_t)MLP_N_PARAMS);
+    if (e == hipSuccess) e = mlp_alloc(p, &m.w2b, (size_t)MLP_H * MLP_H);
+    if (e == hipSuccess) e = mlp_alloc(p, &m.w3b, (size_t)MLP_H * MLP_H);
+    float **acts[] = {&m.z1, &m.z2, &m.z3, &m.dz1, &m.dz2, &m.dz3};
+    for (float **q : acts)
+        if (e == hipSuccess) e = mlp_alloc(p, q, act);
+    __bf16 **bacts[] = {&m.a1, &m.a2, &m.a3, &m.dz1b, &m.dz2b, &m.dz3b};
+    for (__bf16 **q : bacts)
+        if (e == hipSuccess) e = mlp_alloc(p, q, act);
+    if (e == hipSuccess) e = mlp_alloc(p, &m.x, (size_t)mb * 6);
+    if (e == hipSuccess) e = mlp_alloc(p, &m.logit, (size_t)mb);
+    if (e == hipSuccess) e = mlp_alloc(p, &m.dlogit, (size_t)mb);
+    if (e == hipSuccess) e = mlp_alloc(p, &m.loss, (size_t)1);
+    if (e != hipSuccess) {
+        mlp_free(p);
+        delete p;
+        return hip_fail(c, e, "alloc MLP");
+    }
+    std::vector<float> theta((size_t)MLP_N_PARAMS, 0.0f);
+    if (params) {
+        if (hipMemcpy(theta.data(), params, theta.size() * 4, hipMemcpyDefault) != hipSuccess) {
+            mlp_free(p);
+            delete p;
+            return fail(c, FT_E_INVALID, "cannot read params");
+        }
+        for (float x : theta)
+            if (!is_finite(x)) {
+                mlp_free(p);
+                delete p;
+                return fail(c, FT_E_INVALID, "params must be finite");
+            }
+    } else {  // He initialisation: N(0, 2/fan_in) weights, zero biases
+        std::mt19937_64 rng(seed);
+        const int fan[4] = {6, MLP_H, MLP_H, MLP_H};
+        const int off[4] = {0, MLP_OFF_W2, MLP_OFF_W3, MLP_OFF_W4};
+        const int cnt[4] = {MLP_H * 6, MLP_H * MLP_H, MLP_H * MLP_H, MLP_H};
+        for (int l = 0; l < 4; ++l) {
+            std::normal_distribution<double> nd(0.0, std::sqrt(2.0 / fan[l]));
+            for (int i = 0; i < cnt[l]; ++i) theta[(size_t)off[l] + i] = (float)nd(rng);
+        }
+    }
+    std::vector<float> zeros((size_t)MLP_N_PARAMS, 0.0f);
+    e = hipMemcpyAsync(m.theta, theta.data(), theta.size() * 4, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(m.m, zeros.data(), zeros.size() * 4, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(m.v, zeros.data(), zeros.size() * 4, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = mlp_refresh_bf16(m, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+        mlp_free(p);
+        delete p;
+        return hip_fail(c, e, "init MLP");
+    }
+    *out = p;
+    return FT_OK;
+}
+
+void ft_mlp_destroy(ft_mlp p)
+{
+    if (!p) return;
+    (void)hipSetDevice(p->ctx->device);
+    (void)hipStreamSynchronize(p->ctx->stream);
+    mlp_free(p);
+    delete p;
+}
+
+ft_status ft_mlp_get_params(ft_mlp p, float *params)
+{
+    if (!p || !params) return FT_E_INVALID;
+    ft_ctx c = p->ctx;
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e == hipSuccess) e = hipMemcpy(params, p->m.theta, (size_t)MLP_N_PARAMS * 4, hipMemcpyDefault);
+    if (e != hipSuccess) return hip_fail(c, e, "get params");
+    return FT_OK;
+}
+
+static ft_status mlp_upload(ft_mlp p, const float *raw, const float *y, int64_t n)
+{
+    ft_ctx c = p->ctx;
+    hipError_t e = ensure(&p->d_raw, &p->cap_raw, (size_t)n * 6);
+    if (e == hipSuccess && y) e = ensure(&p->d_y, &p->cap_y, (size_t)n);
+    if (e == hipSuccess) e = hipMemcpyAsync(p->d_raw, raw, (size_t)n * 6 * 4, hipMemcpyDefault, c->stream);
+    if (e == hipSuccess && y) e = hipMemcpyAsync(p->d_y, y, (size_t)n * 4, hipMemcpyDefault, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "upload MLP data");
+    // validate on the host (amp > 0 for the log feature, finite values, labels in [0, 1])
+    std::vector<float> h;
+    if (fetch(h, raw, (size_t)n * 6) != hipSuccess) return fail(c, FT_E_INVALID, "cannot read inputs");
+    for (int64_t i = 0; i < n; ++i) {
+        if (!(h[(size_t)i * 6] > 0.0f)) return fail(c, FT_E_INVALID, "input %lld: amplitude must be > 0", (long long)i);
+        for (int j = 0; j < 6; ++j)
+            if (!is_finite(h[(size_t)i * 6 + j])) return fail(c, FT_E_INVALID, "inputs must be finite");
+    }
+    if (y) {
+        std::vector<float> hy;
+        if (fetch(hy, y, (size_t)n) != hipSuccess) return fail(c, FT_E_INVALID, "cannot read labels");
+        for (float v : hy)
+            if (!(v >= 0.0f && v <= 1.0f)) return fail(c, FT_E_INVALID, "labels must lie in [0, 1]");
+    }
+    return FT_OK;
+}
+
+ft_status ft_mlp_predict(ft_mlp p, const float *raw, int64_t n, float *prob)
+{
+    if (!p) return FT_E_INVALID;
+    ft_ctx c = p->ctx;
+    c->err.clear();
+    if (!raw || !prob || n < 1 || n > 0x7fffffff) return fail(c, FT_E_INVALID, "predict needs 1 <= n < 2^31 and buffers");
+    ft_status st = mlp_upload(p, raw, nullptr, n);
+    if (st != FT_OK) return st;
+    hipError_t e = ensure(&p->d_prob, &p->cap_prob, (size_t)n);
+    for (int64_t b0 = 0; b0 < n && e == hipSuccess; b0 += p->m.max_batch) {
+        const int bsz = (int)std::min<int64_t>(p->m.max_batch, n - b0);
+        MlpConst cst = p->cst;
+        cst.base = b0;
+        cst.n_total = n;
+        cst.perm_a = 0;
+        e = mlp_forward(p->m, p->d_raw, nullptr, cst, bsz, p->d_prob + b0, c->stream);
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(prob, p->d_prob, (size_t)n * 4, hipMemcpyDefault, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "predict");
+    return FT_OK;
+}
+
+ft_status ft_mlp_loss_grad(ft_mlp p, const float *raw, const float *y, int32_t n, float *loss, float *grad)
+{
+    if (!p) return FT_E_INVALID;
+    ft_ctx c = p->ctx;
+    c->err.clear();
+    if (!raw || !y || !loss || !grad || n < 1 || n > p->m.max_batch)
+        return fail(c, FT_E_INVALID, "loss_grad needs 1 <= n <= max_batch and buffers");
+    ft_status st = mlp_upload(p, raw, y, n);
+    if (st != FT_OK) return st;
+    MlpConst cst = p->cst;
+    cst.base = 0;
+    cst.n_total = n;
+    cst.perm_a = 0;
+    hipError_t e = launch_fill_u32((uint32_t *)p->m.loss, 0u, 1, c->stream);
+    if (e == hipSuccess) e = mlp_forward(p->m, p->d_raw, p->d_y, cst, n, nullptr, c->stream);
+    if (e == hipSuccess) e = mlp_backward(p->m, n, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(loss, p->m.loss, 4, hipMemcpyDefault, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(grad, p->m.grad, (size_t)MLP_N_PARAMS * 4, hipMemcpyDefault, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "loss_grad");
+    return FT_OK;
+}
+
+ft_status ft_mlp_train(ft_mlp p, const float *raw, const float *y, int64_t n, int32_t batch, int32_t epochs,
+                       float lr, uint64_t seed, float *epoch_loss)
+{
+    if (!p) return FT_E_INVALID;
+    ft_ctx c = p->ctx;
+    c->err.clear();
+    if (!raw || !y || n < 1 || n > 0x7fffffff || batch < 1 || batch > p->m.max_batch || epochs < 0 ||
+        !(lr > 0.0f) || !is_finite(lr))
+        return fail(c, FT_E_INVALID, "train needs 1 <= batch <= max_batch, epochs >= 0, lr > 0");
+    ft_status st = mlp_upload(p, raw, y, n);
+    if (st != FT_OK) return st;
+    std::mt19937_64 rng(seed);
+    hipError_t e = hipSuccess;
+    for (int ep = 0; ep < epochs && e == hipSuccess; ++ep) {
+        // affine permutation i -> (a i + b) mod n with gcd(a, n) = 1
+        uint64_t a = 1 + rng() % (uint64_t)std::max<int64_t>(n - 1, 1);
+        while (std::gcd(a, (uint64_t)n) != 1) a = a % (uint64_t)n + 1;
+        const uint64_t b = rng() % (uint64_t)n;
+        e = launch_fill_u32((uint32_t *)p->m.loss, 0u, 1, c->stream);
+        int n_batches = 0;
+        for (int64_t b0 = 0; b0 < n && e == hipSuccess; b0 += batch) {
+            const int bsz = (int)std::min<int64_t>(batch, n - b0);
+            MlpConst cst = p->cst;
+            cst.base = b0;
+            cst.n_total = n;
+            cst.perm_a = n > 1 ? a : 0;
+            cst.perm_c = b;
+            e = mlp_forward(p->m, p->d_raw, p->d_y, cst, bsz, nullptr, c->stream);
+            if (e == hipSuccess) e = mlp_backward(p->m, bsz, c->stream);
+            if (e == hipSuccess) e = mlp_adam(p->m, lr, ++p->step, c->stream);
+            ++n_batches;
+        }
+        if (epoch_loss && e == hipSuccess) {
+            float l = 0.0f;
+            e = hipMemcpyAsync(&l, p->m.loss, 4, hipMemcpyDeviceToHost, c->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+            epoch_loss[ep] = l / (float)std::max(n_batches, 1);
+        }
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "train");
     return FT_OK;
 }
 

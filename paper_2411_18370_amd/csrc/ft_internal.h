@@ -161,4 +161,31 @@ hipError_t launch_select(const EvalRun &run, bool grid, int n_seg, int k, double
 hipError_t launch_rescore_rank(const EvalRun &run, bool grid, int n_seg, int k,
                                const SelectBufs &b, hipStream_t s);
 
+// Surrogate MLP (6 -> 256 -> 256 -> 256 -> 1).
+constexpr int MLP_H = 256;
+constexpr int MLP_OFF_W2 = MLP_H * 6 + MLP_H;
+constexpr int MLP_OFF_W3 = MLP_OFF_W2 + MLP_H * MLP_H + MLP_H;
+constexpr int MLP_OFF_W4 = MLP_OFF_W3 + MLP_H * MLP_H + MLP_H;
+constexpr int MLP_N_PARAMS = MLP_OFF_W4 + MLP_H + 1;  // 133,633
+
+struct MlpConst {
+    float shift[6], scale[6];  // feature standardisation
+    int64_t base;              // first sample of the batch (in permuted order)
+    int64_t n_total;           // samples in the data set
+    uint64_t perm_a, perm_c;   // sample = (perm_a * i + perm_c) mod n_total (perm_a = 0: i)
+};
+
+struct MlpBufs {
+    float *theta, *m, *v, *grad;
+    __bf16 *w2b, *w3b;
+    float *x, *z1, *z2, *z3, *dz1, *dz2, *dz3, *logit, *dlogit, *loss;
+    __bf16 *a1, *a2, *a3, *dz1b, *dz2b, *dz3b;
+    int max_batch;  // multiple of 64
+};
+hipError_t mlp_refresh_bf16(const MlpBufs &m, hipStream_t s);
+hipError_t mlp_forward(const MlpBufs &m, const float *raw, const float *labels, const MlpConst &c,
+                       int bsz, float *prob, hipStream_t s);
+hipError_t mlp_backward(const MlpBufs &m, int bsz, hipStream_t s);
+hipError_t mlp_adam(const MlpBufs &m, float lr, int t, hipStream_t s);
+
 }  // namespace ft

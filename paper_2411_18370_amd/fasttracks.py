@@ -81,7 +81,8 @@ EXPORTS = ("ft_create", "ft_destroy", "ft_last_error", "ft_status_string", "ft_s
            "ft_set_velocities", "ft_eval_templates", "ft_toplist", "ft_sync",
            "ft_last_eval_info", "ft_bins", "ft_count_index_mismatches", "ft_tile_count",
            "ft_tile_name", "ft_gen_sfts", "ft_eval_batch", "ft_batch_toplist", "ft_batch_labels",
-           "ft_batch_replay", "ft_batch_time")
+           "ft_batch_replay", "ft_batch_time", "ft_mlp_create", "ft_mlp_destroy",
+           "ft_mlp_get_params", "ft_mlp_predict", "ft_mlp_loss_grad", "ft_mlp_train")
 
 
 def load(path: str = LIB_PATH):
@@ -117,6 +118,12 @@ def load(path: str = LIB_PATH):
         "ft_batch_labels": (C.c_int, [P, f64, P, P]),
         "ft_batch_replay": (C.c_int, [P]),
         "ft_batch_time": (C.c_int, [P, C.POINTER(f64)]),
+        "ft_mlp_create": (C.c_int, [P, P, C.c_uint64, P, P, i32, C.POINTER(P)]),
+        "ft_mlp_destroy": (None, [P]),
+        "ft_mlp_get_params": (C.c_int, [P, P]),
+        "ft_mlp_predict": (C.c_int, [P, P, i64, P]),
+        "ft_mlp_loss_grad": (C.c_int, [P, P, P, i32, C.POINTER(C.c_float), P]),
+        "ft_mlp_train": (C.c_int, [P, P, P, i64, i32, i32, C.c_float, C.c_uint64, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -351,6 +358,67 @@ def ft_batch_time(ctx):
     ms = C.c_double()
     _check(ctx, load().ft_batch_time(ctx, C.byref(ms)))
     return ms.value
+
+
+MLP_N_PARAMS = 133_633
+
+
+class Mlp:
+    """The p_det surrogate network (ft_mlp_*)."""
+
+    def __init__(self, ctx, feat_shift, feat_scale, max_batch=8192, params=None, seed=0):
+        self.ctx = ctx.ctx if isinstance(ctx, Context) else ctx
+        self._p = None
+        sh = _Arr(np.asarray(feat_shift, np.float32), np.float32)
+        sc = _Arr(np.asarray(feat_scale, np.float32), np.float32)
+        pr = _Arr(params, np.float32)
+        h = C.c_void_p()
+        _check(self.ctx, load().ft_mlp_create(self.ctx, pr.ptr, int(seed), sh.ptr, sc.ptr,
+                                              int(max_batch), C.byref(h)))
+        self._p = h
+
+    def close(self):
+        if self._p:
+            load().ft_mlp_destroy(self._p)
+            self._p = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def params(self):
+        out = np.empty(MLP_N_PARAMS, np.float32)
+        _check(self.ctx, load().ft_mlp_get_params(self._p, out.ctypes.data_as(C.c_void_p)))
+        return out
+
+    def predict(self, raw):
+        raw = np.ascontiguousarray(raw, np.float32)
+        out = np.empty(raw.shape[0], np.float32)
+        _check(self.ctx, load().ft_mlp_predict(self._p, raw.ctypes.data_as(C.c_void_p),
+                                               raw.shape[0], out.ctypes.data_as(C.c_void_p)))
+        return out
+
+    def loss_grad(self, raw, y):
+        raw = np.ascontiguousarray(raw, np.float32)
+        y = np.ascontiguousarray(y, np.float32)
+        loss = C.c_float()
+        g = np.empty(MLP_N_PARAMS, np.float32)
+        _check(self.ctx, load().ft_mlp_loss_grad(self._p, raw.ctypes.data_as(C.c_void_p),
+                                                 y.ctypes.data_as(C.c_void_p), raw.shape[0],
+                                                 C.byref(loss), g.ctypes.data_as(C.c_void_p)))
+        return loss.value, g
+
+    def train(self, raw, y, batch, epochs, lr, seed=0):
+        raw = _Arr(raw, np.float32)
+        yy = _Arr(y, np.float32)
+        n = int(raw.keep.shape[0])
+        hist = np.empty(max(epochs, 1), np.float32)
+        _check(self.ctx, load().ft_mlp_train(self._p, raw.ptr, yy.ptr, n, int(batch), int(epochs),
+                                             float(lr), int(seed),
+                                             hist.ctypes.data_as(C.c_void_p)))
+        return hist[:epochs]
 
 
 _n_sft_cache = {}
