@@ -1116,7 +1116,7 @@ struct BatchPlan {
     std::vector<int64_t> dt_prefix, stats_prefix, gen_prefix_sft, gen_prefix_elem, sky_prefix;
     std::vector<int32_t> sft_begin, perm;
     std::vector<double> tref, sky_tile;
-    std::vector<std::vector<int2>> items;  // per tile id
+    std::vector<std::vector<int2>> items;  // per tile id; index tile_count(): direct items
     int max_wtp = 64;
 };
 
@@ -1127,7 +1127,7 @@ static ft_status launch_batch_sequence(ft_ctx c, const BatchPlan &pl, bool gener
     auto &b = c->bb;
     const int n_runs = (int)pl.runs.size();
     hipError_t e = launch_fill_u32(c->d_err, 0u, 1, st);
-    if (e == hipSuccess) e = launch_fill_u32(b.counters, 0u, tile_count(), st);
+    if (e == hipSuccess) e = launch_fill_u32(b.counters, 0u, tile_count() + 1, st);
     if (e == hipSuccess)
         e = launch_batch_dt(b.tmid, b.sft_begin, b.tref, b.dt_prefix, n_runs, pl.dt_prefix[n_runs], b.dt, st);
     if (e == hipSuccess && generate)
@@ -1140,6 +1140,12 @@ static ft_status launch_batch_sequence(ft_ctx c, const BatchPlan &pl, bool gener
         const int grid = std::min(n_items, 2048);
         e = launch_eval_batch(b.runs, b.items + item_off, n_items, pl.max_wtp, b.counters + id, grid, tile_cfg(id), st);
         item_off += n_items;
+    }
+    {
+        const int n_direct = (int)pl.items[tile_count()].size();
+        if (e == hipSuccess && n_direct > 0)
+            e = launch_eval_batch_direct(b.runs, b.items + item_off, n_direct, b.counters + tile_count(),
+                                         std::min(n_direct, 4096), st);
     }
     if (e == hipSuccess)
         e = launch_select_batch(b.runs, n_runs, c->batch_k, c->batch_cap, b.cand, b.s64, b.out, b.nout, b.maxz, c->d_err,
@@ -1194,7 +1200,7 @@ ft_status ft_eval_batch(ft_ctx c, const ft_batch *bt, int32_t use_graph)
     BatchPlan pl;
     pl.runs.resize(n_runs);
     pl.tile.resize(n_runs);
-    pl.items.assign(tile_count(), {});
+    pl.items.assign(tile_count() + 1, {});
     pl.dt_prefix.assign(n_runs + 1, 0);
     pl.stats_prefix.assign(n_runs + 1, 0);
     pl.gen_prefix_sft.assign(n_runs + 1, 0);
@@ -1262,22 +1268,34 @@ ft_status ft_eval_batch(ft_ctx c, const ft_batch *bt, int32_t use_graph)
         EvalRun &E = pl.runs[r];
         E = EvalRun{};
         guard_params(f0, R.n_f0, f0[R.n_f0 - 1], x_max, vmax, bt->t_sft, E.dT, E.eta);
-        int tile = bt->tile ? bt->tile - 1 : choose_batch_tile(R.n_f0, R.n_f1, E.eta < 1e-4);
-        if (tile_cfg(tile).L > 1 && !(E.eta < 1e-4)) tile = 14;
+        // Small f0 grids would leave most lanes of a 64-wide f0 tile idle: they
+        // are evaluated directly, one lane per template.
+        int tile = bt->tile ? bt->tile - 1 : (R.n_f0 < 32 ? -1 : choose_batch_tile(R.n_f0, R.n_f1, E.eta < 1e-4));
+        if (tile >= 0 && tile_cfg(tile).L > 1 && !(E.eta < 1e-4)) tile = 14;
         const double dt_absmax = std::max(std::fabs(dt_min), std::fabs(dt_max));
-        const WindowPlan wp = plan_window(f0, R.n_f0, f1, R.n_f1, pl.sky_tile.data() + 3 * sky_base, R.n_sky, dt_absmax,
-                                          vmax, bt->t_sft, tile);
-        if (wp.tile < 0) return fail(c, FT_E_UNSUPPORTED, "run %d: tile window exceeds the LDS budget", r);
+        WindowPlan wp;
+        if (tile >= 0) {
+            wp = plan_window(f0, R.n_f0, f1, R.n_f1, pl.sky_tile.data() + 3 * sky_base, R.n_sky, dt_absmax, vmax,
+                             bt->t_sft, tile);
+            if (wp.tile < 0) tile = -1;  // window beyond the LDS budget: direct
+        }
         pl.tile[r] = tile;
-        E.wt = wp.wt;
-        E.wtp = wp.wtp;
-        E.tiles_f0 = wp.tiles_f0;
-        E.tiles_f1 = wp.tiles_f1;
-        E.tiles_sky = wp.tiles_sky;
-        pl.max_wtp = std::max(pl.max_wtp, wp.wtp);
-        const int64_t n_tiles = (int64_t)wp.tiles_f0 * wp.tiles_f1 * wp.tiles_sky;
-        if (n_tiles >= 0x7fffffff) return fail(c, FT_E_UNSUPPORTED, "run %d: too many tiles", r);
-        for (int64_t tt = 0; tt < n_tiles; ++tt) pl.items[tile].push_back(make_int2(r, (int)tt));
+        const int64_t n_tmpl = (int64_t)R.n_f0 * R.n_f1 * R.n_sky;
+        if (tile >= 0) {
+            E.wt = wp.wt;
+            E.wtp = wp.wtp;
+            E.tiles_f0 = wp.tiles_f0;
+            E.tiles_f1 = wp.tiles_f1;
+            E.tiles_sky = wp.tiles_sky;
+            pl.max_wtp = std::max(pl.max_wtp, wp.wtp);
+            const int64_t n_tiles = (int64_t)wp.tiles_f0 * wp.tiles_f1 * wp.tiles_sky;
+            if (n_tiles >= 0x7fffffff) return fail(c, FT_E_UNSUPPORTED, "run %d: too many tiles", r);
+            for (int64_t tt = 0; tt < n_tiles; ++tt) pl.items[tile].push_back(make_int2(r, (int)tt));
+        } else {
+            const int64_t n_chunks = (n_tmpl + 255) / 256;
+            if (n_chunks >= 0x7fffffff) return fail(c, FT_E_UNSUPPORTED, "run %d: too many templates", r);
+            for (int64_t ch = 0; ch < n_chunks; ++ch) pl.items[tile_count()].push_back(make_int2(r, (int)ch));
+        }
         E.n_sft = R.n_sft;
         E.n_bins = R.n_bins;
         E.first_bin = (int32_t)R.first_bin;
@@ -1320,7 +1338,7 @@ ft_status ft_eval_batch(ft_ctx c, const ft_batch *bt, int32_t use_graph)
         (e = ensure(&b.stats, &b.c_stats, (size_t)n_stats)) != hipSuccess ||
         (e = ensure(&b.runs, &b.c_runs, (size_t)n_runs)) != hipSuccess ||
         (e = ensure(&b.items, &b.c_items, (size_t)std::max<int64_t>(total_items, 1))) != hipSuccess ||
-        (e = ensure(&b.counters, &b.c_counters, (size_t)tile_count())) != hipSuccess ||
+        (e = ensure(&b.counters, &b.c_counters, (size_t)tile_count() + 1)) != hipSuccess ||
         (e = ensure(&b.cand, &b.c_cand, (size_t)n_runs * cap)) != hipSuccess ||
         (e = ensure(&b.s64, &b.c_s64, (size_t)n_runs * cap)) != hipSuccess ||
         (e = ensure(&b.out, &b.c_out, (size_t)n_runs * k)) != hipSuccess ||

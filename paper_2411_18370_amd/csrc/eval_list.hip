@@ -190,6 +190,26 @@ __global__ __launch_bounds__(256) void eval_direct_kernel(EvalRun r)
         eval_direct_one<GRID>(r, t);
 }
 
+// Persistent direct evaluation of batch runs whose grid is too small for the
+// tile kernel: workgroups pull (run, chunk of 256 templates) items.
+__global__ __launch_bounds__(256) void eval_batch_direct_kernel(const EvalRun *runs,
+                                                                const int2 *items, int n_items,
+                                                                unsigned *counter)
+{
+    __shared__ int item_sh;
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) item_sh = (int)atomicAdd(counter, 1u);
+        __syncthreads();
+        const int item = __builtin_amdgcn_readfirstlane(item_sh);
+        if (item >= n_items) break;
+        const int2 it = items[item];
+        const EvalRun r = runs[__builtin_amdgcn_readfirstlane(it.x)];
+        const int64_t t = (int64_t)it.y * 256 + threadIdx.x;
+        if (t < (int64_t)r.n_f0 * r.n_f1 * r.n_sky) eval_direct_one<true>(r, t);
+    }
+}
+
 __global__ __launch_bounds__(256) void bins_list_kernel(EvalRun r, int mode, int32_t *bins)
 {
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < r.n_list;
@@ -335,6 +355,15 @@ hipError_t launch_eval_grid_direct(const EvalRun &run, hipStream_t s)
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(eval_direct_kernel<true>, dim3(grid_for(n, 256, (1u << 22))), dim3(256),
                        0, s, run);
+    return hipGetLastError();
+}
+
+hipError_t launch_eval_batch_direct(const EvalRun *runs, const int2 *items, int n_items,
+                                    unsigned *counter, int grid, hipStream_t s)
+{
+    if (n_items <= 0) return hipSuccess;
+    hipLaunchKernelGGL(eval_batch_direct_kernel, dim3((unsigned)grid), dim3(256), 0, s, runs, items,
+                       n_items, counter);
     return hipGetLastError();
 }
 

@@ -295,8 +295,27 @@ def ft_tile_name(tile):
     return load().ft_tile_name(tile).decode()
 
 
+RUN_DTYPE = np.dtype([("seed", "<u8"), ("run_id", "<u4"), ("sft_begin", "<i4"),
+                      ("n_sft", "<i4"), ("n_bins", "<i4"), ("first_bin", "<i8"),
+                      ("table_offset", "<i8"), ("f0_begin", "<i4"), ("n_f0", "<i4"),
+                      ("f1_begin", "<i4"), ("n_f1", "<i4"), ("sky_begin", "<i4"),
+                      ("n_sky", "<i4"), ("t_ref", "<f8"), ("amp", "<f8"), ("cos_iota", "<f8"),
+                      ("psi", "<f8"), ("inj_sky", "<f8", (3,)), ("inj_f0", "<f8"),
+                      ("inj_f1", "<f8")], align=True)
+
+
 def make_runs(runs):
-    """ft_run array from a list of dicts (keys as the C fields; 'inj' a dict or None)."""
+    """ft_run array from a list of dicts (keys as the C fields; 'inj' a dict or
+    None) or from a dict of columns (injection columns amp, cos_iota, psi,
+    inj_sky, inj_f0, inj_f1)."""
+    if isinstance(runs, dict):
+        n = len(runs["seed"])
+        arr = np.zeros(n, RUN_DTYPE)
+        for name in RUN_DTYPE.names:
+            if name in runs:
+                arr[name] = runs[name]
+        assert arr.itemsize == C.sizeof(ft_run)
+        return arr
     arr = (ft_run * len(runs))()
     for i, d in enumerate(runs):
         r = arr[i]
@@ -322,7 +341,9 @@ def ft_eval_batch(ctx, runs, t_mid, v_over_c, t_sft, f0, f1, sky, k, arms=None, 
             _Arr(power, np.float32)]
     rr = make_runs(runs)
     b = ft_batch()
-    b.n_runs, b.k, b.runs = len(runs), int(k), C.cast(rr, C.c_void_p)
+    n_runs = len(rr)
+    b.n_runs, b.k = n_runs, int(k)
+    b.runs = rr.ctypes.data if isinstance(rr, np.ndarray) else C.cast(rr, C.c_void_p)
     b.n_sft_total = len(t_mid)
     b.generate = 1 if power is None else 0
     b.t_mid, b.v_over_c, b.arms = keep[0].ptr, keep[1].ptr, keep[2].ptr

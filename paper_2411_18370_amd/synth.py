@@ -231,13 +231,22 @@ class Campaign:
     f0: np.ndarray        # concatenated per-run f0 grids
     f1: np.ndarray        # concatenated per-run f1 sets
     sky: np.ndarray       # concatenated per-run sky sets
-    runs: list            # dicts: seed, run_id, sft_begin, n_sft, first_bin, n_bins, f0_begin,
-                          # n_f0, f1_begin, n_f1, sky_begin, n_sky, t_ref, inj
+    runs: object          # list of dicts (seed, run_id, sft_begin, n_sft, first_bin, n_bins,
+                          # f0_begin, n_f0, f1_begin, n_f1, sky_begin, n_sky, t_ref, inj) or
+                          # the same as columns (injection: amp, cos_iota, psi, inj_sky,
+                          # inj_f0, inj_f1)
     k: int
 
     @property
     def evals(self):
+        if isinstance(self.runs, dict):
+            R = self.runs
+            return int(np.sum(R["n_f0"].astype(np.int64) * R["n_f1"] * R["n_sky"] * R["n_sft"]))
         return sum(r["n_f0"] * r["n_f1"] * r["n_sky"] * r["n_sft"] for r in self.runs)
+
+    @property
+    def n_runs(self):
+        return len(self.runs["seed"]) if isinstance(self.runs, dict) else len(self.runs)
 
 
 def campaign(n_runs: int, seed: int = 4, n_pool: int = 5000, n_sft_range=(500, 5000),
@@ -293,3 +302,77 @@ def campaign(n_runs: int, seed: int = 4, n_pool: int = 5000, n_sft_range=(500, 5
         nsk += n_sky
     return Campaign(t_sft, t_mid, v, arm, np.concatenate(f0_parts), np.concatenate(f1_parts),
                     np.concatenate(sky_parts), runs, k)
+
+
+def cap_points(center: np.ndarray, n: int, radius: float, rng: np.random.Generator) -> np.ndarray:
+    """n unit vectors uniform in the spherical cap of angular radius `radius` around center."""
+    c = np.asarray(center, np.float64)
+    a = np.array([1.0, 0.0, 0.0]) if abs(c[0]) < 0.9 else np.array([0.0, 1.0, 0.0])
+    e1 = np.cross(c, a)
+    e1 /= np.linalg.norm(e1)
+    e2 = np.cross(c, e1)
+    cos_t = rng.uniform(math.cos(radius), 1.0, n)
+    sin_t = np.sqrt(np.maximum(0.0, 1.0 - cos_t * cos_t))
+    ph = rng.uniform(0.0, 2.0 * np.pi, n)
+    pts = cos_t[:, None] * c + sin_t[:, None] * (np.cos(ph)[:, None] * e1 + np.sin(ph)[:, None] * e2)
+    return pts / np.linalg.norm(pts, axis=1, keepdims=True)
+
+
+def label_campaign(n_runs: int, seed: int, base: "Workload", amp_range=(0.005, 0.1),
+                   f_range=(100.0, 300.0), n_f0: int = 5, n_f1: int = 11, n_sky: int = 16,
+                   n_sky_bank: int = 100_000, k: int = 1):
+    """Injection-recovery runs on the SFTs of `base` (inputs of the p_det labels).
+
+    Each run injects one signal (amplitude log-uniform in amp_range, isotropic
+    orientation and sky, f uniform in f_range, f1 uniform in [-1e-9, 0]) and
+    searches it with a local bank: the 5 f0 bins of the 1/T_sft grid nearest to
+    f, 11 f1 values in [-1e-9, 0] and 16 sky points spread uniformly over the cap
+    that holds, on average, the 16 nearest points of an isotropic bank of
+    `n_sky_bank` points.  Runs are returned as columns (arrays named like the
+    fields of a run).  Returns (Campaign, raw [n_runs, 6]) with
+    raw = (amp, cos iota, psi, sin delta, alpha, f)."""
+    rng = np.random.default_rng(seed)
+    radius = math.acos(1.0 - 2.0 * n_sky / n_sky_bank)
+    f1 = np.linspace(-1e-9, 0.0, n_f1)
+    vmax = float(np.max(np.linalg.norm(base.v, axis=1)))
+    dt = base.t_mid - base.t_ref
+    amp = np.exp(rng.uniform(np.log(amp_range[0]), np.log(amp_range[1]), n_runs))
+    cos_iota = rng.uniform(-1.0, 1.0, n_runs)
+    psi = rng.uniform(-np.pi / 4, np.pi / 4, n_runs)
+    inj_sky = isotropic_sky(n_runs, rng)
+    f_inj = rng.uniform(f_range[0], f_range[1], n_runs)
+    f1_inj = rng.uniform(-1e-9, 0.0, n_runs)
+    i0 = np.round((f_inj - f_range[0]) * base.t_sft).astype(np.int64)
+    offs = np.arange(-(n_f0 // 2), n_f0 - n_f0 // 2)
+    f0 = f_range[0] + (i0[:, None] + offs[None, :]) / base.t_sft          # [n_runs, n_f0]
+    # sky caps, vectorised
+    a = np.where(np.abs(inj_sky[:, :1]) < 0.9, np.array([[1.0, 0.0, 0.0]]), np.array([[0.0, 1.0, 0.0]]))
+    e1 = np.cross(inj_sky, a)
+    e1 /= np.linalg.norm(e1, axis=1, keepdims=True)
+    e2 = np.cross(inj_sky, e1)
+    cos_t = rng.uniform(math.cos(radius), 1.0, (n_runs, n_sky))
+    sin_t = np.sqrt(np.maximum(0.0, 1.0 - cos_t * cos_t))
+    ph = rng.uniform(0.0, 2.0 * np.pi, (n_runs, n_sky))
+    sky = (cos_t[..., None] * inj_sky[:, None, :]
+           + sin_t[..., None] * (np.cos(ph)[..., None] * e1[:, None, :]
+                                 + np.sin(ph)[..., None] * e2[:, None, :]))
+    sky /= np.linalg.norm(sky, axis=2, keepdims=True)
+    corners = np.array([f1.min() * dt.min(), f1.min() * dt.max(), f1.max() * dt.min(),
+                        f1.max() * dt.max()])
+    lo = np.floor((f0[:, 0] + corners.min()) * (1.0 - vmax) * base.t_sft).astype(np.int64) - 2
+    hi = np.ceil((f0[:, -1] + corners.max()) * (1.0 + vmax) * base.t_sft).astype(np.int64) + 2
+    r = np.arange(n_runs)
+    runs = {"seed": rng.integers(1, 2 ** 62, n_runs, dtype=np.int64).astype(np.uint64),
+            "run_id": r.astype(np.uint32), "sft_begin": np.zeros(n_runs, np.int32),
+            "n_sft": np.full(n_runs, base.n_sft, np.int32), "first_bin": lo,
+            "n_bins": (hi - lo + 1).astype(np.int32), "f0_begin": (r * n_f0).astype(np.int32),
+            "n_f0": np.full(n_runs, n_f0, np.int32), "f1_begin": np.zeros(n_runs, np.int32),
+            "n_f1": np.full(n_runs, n_f1, np.int32), "sky_begin": (r * n_sky).astype(np.int32),
+            "n_sky": np.full(n_runs, n_sky, np.int32), "t_ref": np.full(n_runs, base.t_ref),
+            "amp": amp, "cos_iota": cos_iota, "psi": psi, "inj_sky": inj_sky, "inj_f0": f_inj,
+            "inj_f1": f1_inj}
+    cp = Campaign(base.t_sft, base.t_mid, base.v, base.arms, f0.ravel(), f1,
+                  sky.reshape(-1, 3), runs, k)
+    alpha = np.mod(np.arctan2(inj_sky[:, 1], inj_sky[:, 0]), 2.0 * np.pi)
+    raw = np.stack([amp, cos_iota, psi, inj_sky[:, 2], alpha, f_inj], axis=1)
+    return cp, raw
