@@ -32,11 +32,12 @@ def log(*a):
 def valu_ops_per_eval(tile_name):
     """VALU lane-operations the grid kernel issues per template-SFT evaluation.
 
-    A lane's run of L templates costs 10 operations for the first bin
-    (4 FP64 arithmetic, 2 conversions, 1 subtraction, 2 guard compares, 1 LDS
-    address) plus one FP32 accumulate per template."""
+    A lane's run of L consecutive f0 costs 7 operations for the first bin
+    (FP64 add and multiply, conversion, fraction, 2 guard compares, 1 LDS
+    address) plus one FP32 accumulate per template; with L = 1 the canonical
+    bin costs 3 FP64 arithmetic, 1 add, 1 conversion, 1 address, 1 accumulate."""
     L = int(tile_name.split("_")[0][1:]) if tile_name else 1
-    return (10.0 + L) / L if L > 1 else 7.0
+    return (7.0 + L) / L if L > 1 else 7.0
 
 
 def cpu_baseline(w, target_s):
@@ -64,6 +65,129 @@ def cpu_baseline(w, target_s):
                       "(%.3g evals, %.1f s)" % (n_sky, evals, dt)}
 
 
+def bench_batched(ft, synth, n_runs, log):
+    """Uneven injection campaign: plain (one call per run) against batched (one
+    persistent graph-captured launch)."""
+    import numpy as np
+    import torch
+    cp = synth.campaign(n_runs, seed=4)
+    evals = cp.evals
+    c = ft.Context(0, torch.cuda.current_stream().cuda_stream)
+    # plain: table generation + evaluation + toplist, run by run
+    def plain():
+        for R in cp.runs:
+            sl = slice(R["sft_begin"], R["sft_begin"] + R["n_sft"])
+            c.gen_sfts([R["n_sft"]], cp.t_mid[sl], cp.t_sft, R["first_bin"], R["n_bins"],
+                       cp.v[sl], cp.arms[sl], R["seed"], R["run_id"], R["t_ref"], R["inj"])
+            f0 = cp.f0[R["f0_begin"]:R["f0_begin"] + R["n_f0"]]
+            f1 = cp.f1[R["f1_begin"]:R["f1_begin"] + R["n_f1"]]
+            sky = cp.sky[R["sky_begin"]:R["sky_begin"] + R["n_sky"]]
+            c.eval_templates(f0, f1, sky, R["t_ref"], cp.k, np.array([f0[0] - 1.0, f0[-1] + 1.0]))
+            c.toplist(0, cp.k)
+    plain()  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plain()
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    log("batched campaign: plain %.3f s for %d runs" % (t_plain, n_runs))
+    # batched: capture once (includes host planning and uploads), then replay
+    t0 = time.perf_counter()
+    c.eval_campaign(cp, use_graph=1)
+    c.batch_toplist(0, cp.k)
+    t_first = time.perf_counter() - t0
+    reps = 5
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gpu = []
+    for _ in range(reps):
+        c.batch_replay()
+        c.batch_toplist(n_runs - 1, cp.k)
+        gpu.append(c.batch_time())
+    t_replay = (time.perf_counter() - t0) / reps
+    log("batched campaign: first call %.3f s, graph replay %.4f s (GPU %.4f s)"
+        % (t_first, t_replay, np.mean(gpu) * 1e-3))
+    c.close()
+    return {"workload": "%d uneven injection runs, 2 det, N ~ U{500..5000}, band 100-300 Hz, "
+                        "width U[0.01,0.2] Hz, 1e3-1e5 templates each, K=%d" % (n_runs, cp.k),
+            "evals": evals, "plain_evals_per_s": evals / t_plain,
+            "batched_evals_per_s": evals / t_replay,
+            "batched_first_call_evals_per_s": evals / t_first,
+            "batched_gpu_ms": float(np.mean(gpu)), "speedup_vs_plain": t_plain / t_replay}
+
+
+def bench_precision(ft, synth, log):
+    """Index precision at 1 kHz (mismatches against the FP64 bin) and the error of
+    plain against blocked FP32 sums (against the FP64 re-summed toplist)."""
+    import numpy as np
+    import torch
+    w = synth.precision_stress(seed=2)
+    dev = torch.device("cuda:0")
+    c = ft.Context(0, torch.cuda.current_stream().cuda_stream)
+    c.set_sfts(w.n_sft_per_det, torch.from_numpy(w.t_mid).to(dev), w.t_sft, w.first_bin,
+               torch.from_numpy(w.power).to(dev))
+    c.set_velocities(torch.from_numpy(w.v).to(dev))
+    out = {"workload": "2 det x 5000 SFTs, 1000-1000.1 Hz, 180 f0 x 5 f1 x 2e4 sky "
+                       "(%.3g evals)" % w.evals}
+    for name, mode in (("fp32", ft.FT_INDEX_FP32), ("df64", ft.FT_INDEX_DF64),
+                       ("guarded", ft.FT_INDEX_GUARDED), ("fp64", ft.FT_INDEX_FP64)):
+        t0 = time.perf_counter()
+        n = c.count_index_mismatches(w.f0, w.f1, w.sky, w.t_ref, mode)
+        out["mismatch_" + name] = n
+        log("precision: %s index mismatches %d (%.2f s)" % (name, n, time.perf_counter() - t0))
+    out["evals"] = w.evals
+    stats = torch.empty(w.n_templates, dtype=torch.float32, device=dev)
+    for name, mode in (("blocked", ft.FT_SUM_BLOCKED), ("plain", ft.FT_SUM_PLAIN_FP32)):
+        c.eval_templates(w.f0, w.f1, w.sky, w.t_ref, w.k, w.sub_edges, sum_mode=mode, stats=stats)
+        tops = [c.toplist(j, w.k) for j in range(len(w.sub_edges) - 1)]
+        info = c.info()
+        s = stats.cpu().numpy()
+        rel = np.array([abs(float(s[t.index]) - t.s64) / t.s64 for top in tops for t in top])
+        out["sum_%s_max_rel_err" % name] = float(rel.max())
+        out["sum_%s_rms_rel_err" % name] = float(np.sqrt(np.mean(rel ** 2)))
+        if name == "blocked":
+            out["fp64_index_evals_per_s"] = w.evals / (info.eval_ms * 1e-3)
+    c.close()
+    return out
+
+
+def bench_surrogate(ft, synth, tau, n_train, n_test, log):
+    """Labels from GPU injection campaigns, GPU training, calibration on held-out
+    injections, and the cost of a surrogate query against a plain label."""
+    import numpy as np
+    import torch
+    from paper_2411_18370_amd import surrogate
+    base = synth.allsky_band(seed=2, n_sky=1)
+    c = ft.Context(0, torch.cuda.current_stream().cuda_stream)
+    t0 = time.perf_counter()
+    raw, y, _, gpu_tr = surrogate.make_labels(c, base, n_train, 11, tau)
+    rt, yt, _, gpu_te = surrogate.make_labels(c, base, n_test, 12, tau)
+    t_labels = time.perf_counter() - t0
+    log("surrogate: %d + %d labels in %.1f s (GPU %.1f s), detected fraction %.3f"
+        % (n_train, n_test, t_labels, gpu_tr + gpu_te, y.mean()))
+    net, hist, t_train = surrogate.train(c, raw, y, epochs=20, batch=4096, lr=2e-3, seed=13)
+    t0 = time.perf_counter()
+    p = net.predict(rt.astype(np.float32))
+    t_pred = time.perf_counter() - t0
+    cal = surrogate.calibration(p, yt, rt)
+    log("surrogate: trained in %.1f s, calibration max err %.4f (amp bins), %.4f (p deciles)"
+        % (t_train, cal["max_abs_err_amp_bins"], cal["max_abs_err_p_deciles"]))
+    net.close()
+    c.close()
+    per_label = (gpu_tr + gpu_te) / (n_train + n_test)
+    per_query = t_pred / n_test
+    return {"workload": "labels on the all-sky SFT set (2 det x 5000 SFTs), local bank 5 f0 x "
+                        "11 f1 x 16 sky, f ~ U[100,300] Hz, h0/sqrt(Sn) log-uniform [0.005, 0.1]; "
+                        "MLP 6-256-256-256-1 GELU/sigmoid, BF16 MFMA, 20 epochs",
+            "tau_z": tau, "n_train": n_train, "n_test": n_test,
+            "p_det_abs_err": cal["max_abs_err_amp_bins"],
+            "p_det_abs_err_p_deciles": cal["max_abs_err_p_deciles"],
+            "binomial_se_worst_bin": cal["se_worst_amp_bin"],
+            "train_s": t_train, "final_loss": float(hist[-1]),
+            "s_per_plain_label": per_label, "s_per_surrogate_query": per_query,
+            "speedup": per_label / per_query}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -73,6 +197,11 @@ def main():
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batched-runs", type=int, default=512)
+    ap.add_argument("--surrogate-train", type=int, default=200_000)
+    ap.add_argument("--surrogate-test", type=int, default=50_000)
+    ap.add_argument("--skip-extras", action="store_true",
+                    help="plain workload only (no batched, precision or surrogate sections)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -133,8 +262,11 @@ def main():
     achieved = evals * ops / (k_ms * 1e-3) / 1e12
     peak = VALU_LANE_OPS_PEAK / 1e12
     top1 = max((t[0] for t in tops if t), key=lambda c_: c_.z)
+    # detection threshold of the learned part: mean over the sub-bands of the
+    # 100th-largest critical ratio of this noise-only search
+    tau = float(np.mean([t[min(100, len(t)) - 1].z for t in tops if t]))
     line = {
-        "metric": "template*SFT evals/s on 1 GPU (plain)",
+        "metric": "template*SFT evals/s on 1 GPU, plain vs batched; surrogate p_det abs error",
         "value": value,
         "unit": "template*SFT evals/s",
         "n_gpus": 1,
@@ -159,11 +291,18 @@ def main():
                      "note": "VALU lane-ops of the grid kernel per evaluation x evals / kernel "
                              "time (HIP events on the library stream)"},
         "loudest_z": top1.z,
+        "tau_z": tau,
     }
+    c.close()
+    if not args.skip_extras:
+        line["batched"] = bench_batched(ft, synth, args.batched_runs, log)
+        line["precision"] = bench_precision(ft, synth, log)
+        if args.surrogate_train > 0:
+            line["surrogate"] = bench_surrogate(ft, synth, tau, args.surrogate_train,
+                                                args.surrogate_test, log)
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on a CPU sample")
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
-    c.close()
     print(json.dumps(line), flush=True)
 
 
