@@ -93,9 +93,10 @@ def bench_batched(ft, synth, n_runs, log):
     log("batched campaign: plain %.3f s for %d runs" % (t_plain, n_runs))
     # batched: capture once (includes host planning and uploads), then replay
     t0 = time.perf_counter()
-    c.eval_campaign(cp, use_graph=1)
+    c.eval_campaign(cp, use_graph=1, tile=ft.FT_TILE_TUNE)
     c.batch_toplist(0, cp.k)
     t_first = time.perf_counter() - t0
+    rep, tune_ms = c.tune_report()
     reps = 5
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -113,7 +114,10 @@ def bench_batched(ft, synth, n_runs, log):
             "evals": evals, "plain_evals_per_s": evals / t_plain,
             "batched_evals_per_s": evals / t_replay,
             "batched_first_call_evals_per_s": evals / t_first,
-            "batched_gpu_ms": float(np.mean(gpu)), "speedup_vs_plain": t_plain / t_replay}
+            "batched_gpu_ms": float(np.mean(gpu)), "speedup_vs_plain": t_plain / t_replay,
+            "autotune": {"tune_ms": tune_ms,
+                         "chosen": {str(e["klass"]): e["name"] for e in rep if e["chosen"]},
+                         "n_timed": len(rep)}}
 
 
 def bench_precision(ft, synth, log):
@@ -194,7 +198,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n-sky", type=int, default=100_000)
-    ap.add_argument("--tile", type=int, default=0)
+    ap.add_argument("--tile", type=int, default=-1,
+                    help="-1: autotune during warm-up (default), 0: cost model, else a tile id")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batched-runs", type=int, default=512)
@@ -241,6 +246,11 @@ def main():
     for i in range(args.warmup):
         step()
         log("warmup step %d done: eval %.1f ms" % (i, c.info().eval_ms))
+    tune_rep, tune_ms = c.tune_report()
+    if tune_rep:
+        log("autotune (%.0f ms): %s" % (tune_ms, ", ".join(
+            "%s%s %.3g" % (e["name"], "*" if e["chosen"] else "", e["evals_per_s"])
+            for e in tune_rep)))
     torch.cuda.synchronize()
     eval_ms, sel_ms = [], []
     t0 = time.perf_counter()
@@ -290,6 +300,9 @@ def main():
                      "ops_per_eval": ops,
                      "note": "VALU lane-ops of the grid kernel per evaluation x evals / kernel "
                              "time (HIP events on the library stream)"},
+        "autotune": {"tune_ms": tune_ms,
+                     "timed": {e["name"]: e["evals_per_s"] for e in tune_rep},
+                     "sample_evals": tune_rep[0]["sample_evals"] if tune_rep else 0},
         "loudest_z": top1.z,
         "tau_z": tau,
     }

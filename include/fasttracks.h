@@ -140,8 +140,11 @@ enum { FT_SUM_BLOCKED = 0, FT_SUM_PLAIN_FP32 = 1 };
  *              sub-band are evaluated but enter no toplist)
  *   sum_mode   FT_SUM_BLOCKED (default) or FT_SUM_PLAIN_FP32 (study only:
  *              toplists are then not guaranteed exact)
- *   tile       0 = library choice; otherwise a tile id in 1..ft_tile_count()
- *              (see ft_tile_name); ignored for LIST banks
+ *   tile       0 = library choice (the tile the autotuner cached for this
+ *              shape class in this context, else the cost model);
+ *              FT_TILE_TUNE = time the eligible tiles first if the class is
+ *              not cached (see ft_tune_report); otherwise a tile id in
+ *              1..ft_tile_count() (see ft_tile_name); ignored for LIST banks
  */
 typedef struct {
     int32_t precision;
@@ -282,7 +285,9 @@ typedef struct {
     const double *f0, *f1, *sky_xyz;
     int64_t power_len;      /* elements of `power` (generate = 0)                        */
     const float *power;     /* concatenated run tables (generate = 0)                    */
-    int32_t tile;           /* 0: library choice per run; else a tile id for every run   */
+    int32_t tile;           /* 0: library choice per run (cached tuned tile of the run's */
+                            /*    size class, else the cost model); FT_TILE_TUNE: tune   */
+                            /*    uncached classes first; else a tile id for every run   */
     int32_t reserved;
 } ft_batch;
 
@@ -340,6 +345,42 @@ ft_status ft_mlp_train(ft_mlp mlp, const float *raw, const float *y, int64_t n, 
  * SFTs per LDS stage KS. */
 int32_t ft_tile_count(void);
 const char *ft_tile_name(int32_t tile);
+
+/*
+ * Tile autotuner (the batching form's tile choice).  A call with
+ * tile = FT_TILE_TUNE whose shape class has no cached tile times candidate
+ * tiles on the call's own data before evaluating:
+ *   GRID bank   class = (n_f0, n_f1, n_sft, floor(log2 n_sky), Doppler
+ *               half-width in bins, guard eligibility); every candidate runs
+ *               over one contiguous range of the Doppler-ordered sky (about
+ *               2.5e11 evaluations, or the whole bank if smaller)
+ *   batch       class of a run = (floor(log2 n_f0), min(n_f1, 8), guard
+ *               eligibility), runs with n_f0 >= 32 only (smaller f0 grids use
+ *               the direct kernel); each pass launches every class's work
+ *               items with its next candidate and times each class alone
+ * Candidates are the tiles whose cost-model estimate (wasted lanes x VALU
+ * operations per evaluation) is within 1.6x of the best and whose LDS window
+ * fits; the fastest is cached per context and used by later calls of that
+ * class with tile = 0 or FT_TILE_TUNE.  Tuning synchronises the stream and
+ * overwrites the statistic buffer (the call then evaluates as usual).
+ */
+#define FT_TILE_TUNE (-1)
+
+typedef struct {
+    int32_t klass;       /* 0 for a GRID call; batch: 1 + class number              */
+    int32_t tile;        /* candidate tile id (1-based)                             */
+    int32_t chosen;      /* 1 for the tile kept for the class                       */
+    int32_t reserved;
+    double evals_per_s;  /* measured template-SFT evaluations per second            */
+    double sample_evals; /* evaluations timed                                       */
+} ft_tune_entry;
+
+/* The timings of the most recent tuning in this context: up to `cap` entries
+ * into out[], their number into *n_out, the wall time of the tuning (ms) into
+ * *tune_ms (any pointer but n_out may be NULL). */
+ft_status ft_tune_report(ft_ctx ctx, ft_tune_entry *out, int32_t cap, int32_t *n_out, double *tune_ms);
+/* Forget every cached tile choice of the context. */
+ft_status ft_tune_clear(ft_ctx ctx);
 
 #ifdef __cplusplus
 }

@@ -5,11 +5,13 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <string>
 #include <numeric>
 #include <random>
@@ -129,6 +131,11 @@ struct ft_ctx_s {
     double last_rel_err = 0.0;
     int last_tile = -1;
     hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+
+    // autotuner: shape class -> tile id (0-based), and the last tuning's timings
+    std::map<std::vector<int64_t>, int> tune_cache;
+    std::vector<ft_tune_entry> tune_log;
+    double tune_ms = 0.0;
 };
 
 namespace {
@@ -251,25 +258,58 @@ void sky_order(const std::vector<double> &sky, int64_t n, std::vector<int32_t> &
     for (int64_t s = 0; s < n; ++s) perm[(size_t)s] = key[(size_t)s].second;
 }
 
+// Cost model of a tile: lanes issued per useful template (partial f0 and f1
+// tiles) times the VALU operations per evaluation of its inner loop.
+double model_cost(int id, double n_f0, double n_f1)
+{
+    const TileCfg &t = tile_cfg(id);
+    const double f0w = std::ceil(n_f0 / (64.0 * t.L)) * 64.0 * t.L / n_f0;
+    const double f1w = std::ceil(n_f1 / t.JT) * t.JT / n_f1;
+    const double ops = t.L > 1 ? (7.0 + t.L) / t.L : 7.0;
+    return f0w * f1w * ops;
+}
+
 int choose_tile(int64_t n_f0, int64_t n_f1, bool uniform)
 {
     if (!uniform || n_f0 < 96) return n_f1 >= 4 ? 1 : 0;
-    // prefer the run length and f1 tile that waste the fewest lanes
-    const int cands[] = {3, 4, 5, 2, 7, 6};
+    // fewest wasted lanes x operations; on ties the first listed (SFT stages
+    // of 8 before 16: more workgroups fit in LDS)
+    const int cands[] = {8, 3, 2, 4, 5, 7, 6};
     double best = 1e30;
-    int best_id = 3;
+    int best_id = 8;
     for (int id : cands) {
-        const TileCfg &t = tile_cfg(id);
-        const double f0w = std::ceil((double)n_f0 / (64.0 * t.L)) * 64.0 * t.L / (double)n_f0;
-        const double f1w = std::ceil((double)n_f1 / t.JT) * t.JT / (double)n_f1;
-        const double ops = (9.0 + t.L) / t.L;  // VALU per evaluation of the run loop
-        const double cost = f0w * f1w * ops;
+        const double cost = model_cost(id, (double)n_f0, (double)n_f1);
         if (cost < best - 1e-9) {
             best = cost;
             best_id = id;
         }
     }
     return best_id;
+}
+
+// Tiles the autotuner times: eligible (run-length tiles need the guard), cost
+// model within 1.6x of the best, cheapest first.
+std::vector<int> tune_candidates(double n_f0, double n_f1, bool uniform)
+{
+    std::vector<std::pair<double, int>> cost;
+    for (int id = 0; id < tile_count(); ++id)
+        if (tile_cfg(id).L == 1 || uniform) cost.push_back({model_cost(id, n_f0, n_f1), id});
+    std::stable_sort(cost.begin(), cost.end(),
+                     [](const std::pair<double, int> &a, const std::pair<double, int> &b) { return a.first < b.first; });
+    std::vector<int> out;
+    for (auto &pc : cost)
+        if (pc.first <= 1.6 * cost.front().first) out.push_back(pc.second);
+    return out;
+}
+
+int floor_log2(int64_t x)
+{
+    int l = 0;
+    while (x > 1) {
+        x >>= 1;
+        ++l;
+    }
+    return l;
 }
 
 }  // namespace
@@ -298,6 +338,28 @@ const char *ft_tile_name(int32_t tile)
 {
     if (tile < 1 || tile > tile_count()) return "";
     return tile_cfg(tile - 1).name;
+}
+
+ft_status ft_tune_report(ft_ctx c, ft_tune_entry *out, int32_t cap, int32_t *n_out, double *tune_ms)
+{
+    if (!c) return FT_E_INVALID;
+    c->err.clear();
+    if (!n_out) return fail(c, FT_E_INVALID, "n_out must be non-null");
+    if (cap < 0 || (cap > 0 && !out)) return fail(c, FT_E_INVALID, "out must hold cap >= 0 entries");
+    const int32_t n = (int32_t)std::min<size_t>(c->tune_log.size(), (size_t)cap);
+    for (int32_t i = 0; i < n; ++i) out[i] = c->tune_log[(size_t)i];
+    *n_out = (int32_t)c->tune_log.size();
+    if (tune_ms) *tune_ms = c->tune_ms;
+    return FT_OK;
+}
+
+ft_status ft_tune_clear(ft_ctx c)
+{
+    if (!c) return FT_E_INVALID;
+    c->tune_cache.clear();
+    c->tune_log.clear();
+    c->tune_ms = 0.0;
+    return FT_OK;
 }
 
 ft_status ft_create(ft_ctx *out, int device, void *hip_stream)
@@ -868,6 +930,77 @@ static SelectBufs select_bufs(ft_ctx c, int64_t cap)
     return b;
 }
 
+// Shape class of a GRID call for the tile cache.
+static std::vector<int64_t> plain_tune_key(ft_ctx c, int64_t n0, int64_t n1, int64_t ns, bool uniform)
+{
+    const double dop = c->f0_h[(size_t)n0 - 1] * c->vmax * c->t_sft;
+    return {0, n0, n1, (int64_t)c->n_sft, (int64_t)floor_log2(ns), (int64_t)dop, uniform ? 1 : 0};
+}
+
+// Times the candidate tiles on one contiguous range of the Doppler-ordered sky
+// (the middle of the list, about 2.5e11 evaluations) and returns the fastest
+// in best (0-based; -1 when no candidate's window fits in LDS).
+static ft_status tune_plain(ft_ctx c, const EvalRun &run, double dt_absmax, bool uniform, int &best)
+{
+    const auto t_start = std::chrono::steady_clock::now();
+    best = -1;
+    const int64_t n0 = run.n_f0, n1 = run.n_f1, ns = run.n_sky;
+    const double per_sky = (double)n0 * (double)n1 * (double)c->n_sft;
+    int64_t n_s = (int64_t)std::ceil(2.5e11 / per_sky);
+    n_s = (n_s + 7) / 8 * 8;
+    if (n_s > ns) n_s = ns;
+    const int64_t s0 = (ns - n_s) / 2 / 8 * 8;
+    struct Trial {
+        int tile;
+        EvalRun r;
+    };
+    std::vector<Trial> trials;
+    for (int id : tune_candidates((double)n0, (double)n1, uniform)) {
+        const WindowPlan wp = plan_window(c->f0_h.data(), n0, c->f1_h.data(), n1, c->sky_tile_h.data(), ns, dt_absmax,
+                                          c->vmax, c->t_sft, id);
+        if (wp.tile < 0) continue;
+        EvalRun r = run;
+        r.wt = wp.wt;
+        r.wtp = wp.wtp;
+        r.tiles_f0 = wp.tiles_f0;
+        r.tiles_f1 = wp.tiles_f1;
+        r.sky_tile = run.sky_tile + 3 * s0;
+        r.sky_perm = run.sky_perm + s0;
+        r.n_sky = (int32_t)n_s;
+        r.tiles_sky = (int32_t)((n_s + tile_cfg(id).NW - 1) / tile_cfg(id).NW);
+        trials.push_back({id, r});
+    }
+    c->tune_log.clear();
+    if (trials.empty()) return FT_OK;
+    // the first launch also brings the clocks up; it is not timed
+    hipError_t e = launch_eval_grid(trials[0].r, tile_cfg(trials[0].tile), c->stream);
+    std::vector<float> ms(trials.size(), 0.f);
+    for (size_t i = 0; i < trials.size() && e == hipSuccess; ++i) {
+        e = hipEventRecord(c->ev[0], c->stream);
+        if (e == hipSuccess) e = launch_eval_grid(trials[i].r, tile_cfg(trials[i].tile), c->stream);
+        if (e == hipSuccess) e = hipEventRecord(c->ev[1], c->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(c->ev[1]);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms[i], c->ev[0], c->ev[1]);
+    }
+    if (e != hipSuccess) return hip_fail(c, e, "tile tuning");
+    size_t bi = 0;
+    for (size_t i = 1; i < trials.size(); ++i)
+        if (ms[i] < ms[bi]) bi = i;
+    best = trials[bi].tile;
+    const double evals = per_sky * (double)n_s;
+    for (size_t i = 0; i < trials.size(); ++i) {
+        ft_tune_entry t{};
+        t.klass = 0;
+        t.tile = trials[i].tile + 1;
+        t.chosen = i == bi;
+        t.evals_per_s = ms[i] > 0.f ? evals / (ms[i] * 1e-3) : 0.0;
+        t.sample_evals = evals;
+        c->tune_log.push_back(t);
+    }
+    c->tune_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+    return FT_OK;
+}
+
 ft_status ft_eval_templates(ft_ctx c, const ft_bank *bank, double t_ref, const ft_eval_opts *opts,
                             float *stats)
 {
@@ -884,6 +1017,7 @@ ft_status ft_eval_templates(ft_ctx c, const ft_bank *bank, double t_ref, const f
     if (!opts->sub_edges) return fail(c, FT_E_INVALID, "sub_edges is null");
     if (opts->sum_mode != FT_SUM_BLOCKED && opts->sum_mode != FT_SUM_PLAIN_FP32)
         return fail(c, FT_E_INVALID, "unknown sum_mode");
+    if (opts->tile < FT_TILE_TUNE || opts->tile > tile_count()) return fail(c, FT_E_INVALID, "unknown tile %d", opts->tile);
     std::vector<double> edges;
     if (fetch(edges, opts->sub_edges, (size_t)opts->n_sub + 1) != hipSuccess)
         return fail(c, FT_E_INVALID, "cannot read sub_edges");
@@ -904,15 +1038,25 @@ ft_status ft_eval_templates(ft_ctx c, const ft_bank *bank, double t_ref, const f
     int tile = -1;
     if (grid) {
         const int64_t n0 = bank->n_f0, n1 = bank->n_f1, ns = bank->n_sky;
-        if (opts->tile != 0) {
-            if (opts->tile < 1 || opts->tile > tile_count()) return fail(c, FT_E_INVALID, "unknown tile %d", opts->tile);
-            tile = opts->tile - 1;
-        } else {
-            tile = choose_tile(n0, n1, run.eta < 1e-4);
-        }
-        if (tile_cfg(tile).L > 1 && !(run.eta < 1e-4)) tile = 1;
+        const bool uniform = run.eta < 1e-4;
         double dt_absmax = 0.0;
         for (double t : c->t_mid_h) dt_absmax = std::max(dt_absmax, std::fabs(t - t_ref));
+        if (opts->tile > 0) {
+            tile = opts->tile - 1;
+        } else {
+            const std::vector<int64_t> key = plain_tune_key(c, n0, n1, ns, uniform);
+            const auto it = c->tune_cache.find(key);
+            tile = -1;
+            if (it != c->tune_cache.end()) {
+                tile = it->second;
+            } else if (opts->tile == FT_TILE_TUNE) {
+                st = tune_plain(c, run, dt_absmax, uniform, tile);
+                if (st != FT_OK) return st;
+                if (tile >= 0) c->tune_cache[key] = tile;
+            }
+            if (tile < 0) tile = choose_tile(n0, n1, uniform);
+        }
+        if (tile_cfg(tile).L > 1 && !uniform) tile = 1;
         const WindowPlan wp = plan_window(c->f0_h.data(), n0, c->f1_h.data(), n1, c->sky_tile_h.data(), ns,
                                           dt_absmax, c->vmax, c->t_sft, tile);
         tile = wp.tile;  // -1: the window does not fit in LDS, use the direct kernel
@@ -1117,8 +1261,56 @@ struct BatchPlan {
     std::vector<int32_t> sft_begin, perm;
     std::vector<double> tref, sky_tile;
     std::vector<std::vector<int2>> items;  // per tile id; index tile_count(): direct items
-    int max_wtp = 64;
+    std::vector<char> uniform;             // per run: the run-length guard applies
+    std::vector<double> dt_absmax, vmax;   // per run: window inputs
+    std::vector<int> group_wtp;            // per tile id: widest LDS row of its runs
 };
+
+// Tile-dependent fields of batch run r for `tile` (0-based, -1: direct).
+// Returns the tile used: -1 when the run's window does not fit in LDS.
+int assign_run_tile(BatchPlan &pl, int r, int tile, const ft_run &R, const double *f0h, const double *f1h,
+                    double t_sft)
+{
+    EvalRun &E = pl.runs[r];
+    if (tile >= 0 && tile_cfg(tile).L > 1 && !pl.uniform[r]) tile = 14;
+    WindowPlan wp;
+    if (tile >= 0) {
+        wp = plan_window(f0h + R.f0_begin, R.n_f0, f1h + R.f1_begin, R.n_f1, pl.sky_tile.data() + 3 * pl.sky_prefix[r],
+                         R.n_sky, pl.dt_absmax[r], pl.vmax[r], t_sft, tile);
+        if (wp.tile < 0) tile = -1;  // window beyond the LDS budget: direct
+    }
+    E.wt = tile >= 0 ? wp.wt : 0;
+    E.wtp = tile >= 0 ? wp.wtp : 0;
+    E.tiles_f0 = tile >= 0 ? wp.tiles_f0 : 0;
+    E.tiles_f1 = tile >= 0 ? wp.tiles_f1 : 0;
+    E.tiles_sky = tile >= 0 ? wp.tiles_sky : 0;
+    pl.tile[r] = tile;
+    return tile;
+}
+
+// Work items of batch run r: its tiles, or 256-template chunks for the direct kernel.
+int64_t run_items(const BatchPlan &pl, int r)
+{
+    const EvalRun &E = pl.runs[r];
+    if (pl.tile[r] >= 0) return (int64_t)E.tiles_f0 * E.tiles_f1 * E.tiles_sky;
+    return ((int64_t)E.n_f0 * E.n_f1 * E.n_sky + 255) / 256;
+}
+
+void append_items(const BatchPlan &pl, int r, std::vector<int2> &out)
+{
+    const int64_t n = run_items(pl, r);
+    for (int64_t t = 0; t < n; ++t) out.push_back(make_int2(r, (int)t));
+}
+
+// Size class of a batch run for the tile cache; -1 for f0 grids too small for
+// a 64-wide f0 tile (the direct kernel evaluates them, one lane per template).
+int batch_class(const ft_run &R, bool uniform)
+{
+    if (R.n_f0 < 32) return -1;
+    const int b = std::min(floor_log2(R.n_f0) - 5, 7);
+    const int j = std::min<int>(R.n_f1, 8) - 1;
+    return (uniform ? 64 : 0) + b * 8 + j;
+}
 
 }  // namespace
 
@@ -1138,7 +1330,8 @@ static ft_status launch_batch_sequence(ft_ctx c, const BatchPlan &pl, bool gener
         const int n_items = (int)pl.items[id].size();
         if (n_items == 0) continue;
         const int grid = std::min(n_items, 2048);
-        e = launch_eval_batch(b.runs, b.items + item_off, n_items, pl.max_wtp, b.counters + id, grid, tile_cfg(id), st);
+        e = launch_eval_batch(b.runs, b.items + item_off, n_items, pl.group_wtp[id], b.counters + id, grid, tile_cfg(id),
+                              st);
         item_off += n_items;
     }
     {
@@ -1151,6 +1344,133 @@ static ft_status launch_batch_sequence(ft_ctx c, const BatchPlan &pl, bool gener
         e = launch_select_batch(b.runs, n_runs, c->batch_k, c->batch_cap, b.cand, b.s64, b.out, b.nout, b.maxz, c->d_err,
                                 st);
     if (e != hipSuccess) return hip_fail(c, e, "launch batch");
+    return FT_OK;
+}
+
+// Autotuning of batch size classes.  The base arrays must be on the device;
+// the time offsets and tables are produced first.  Pass p launches the work
+// items of every class with its p-th candidate tile, each class in a
+// persistent launch of its own between two events, after one untimed pass
+// that brings the clocks up.  The fastest tile of each class is cached.
+static ft_status tune_batch(ft_ctx c, BatchPlan &pl, const std::vector<ft_run> &runs, const double *f0h,
+                            const double *f1h, double t_sft, bool gen, const std::map<int, std::vector<int>> &classes)
+{
+    const auto t_start = std::chrono::steady_clock::now();
+    auto &b = c->bb;
+    const int n_runs = (int)pl.runs.size();
+    hipError_t e = launch_batch_dt(b.tmid, b.sft_begin, b.tref, b.dt_prefix, n_runs, pl.dt_prefix[n_runs], b.dt, c->stream);
+    if (e == hipSuccess && gen)
+        e = launch_gen_tables(b.gen, n_runs, b.gen_prefix, b.gen_prefix + (n_runs + 1), pl.gen_prefix_sft[n_runs],
+                              pl.gen_prefix_elem[n_runs], c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "tile tuning");
+    struct Cls {
+        int id;
+        std::vector<int> runs, cand;
+        std::vector<double> rate;
+        double evals;
+    };
+    std::vector<Cls> cls;
+    size_t n_pass = 0;
+    for (const auto &kv : classes) {
+        Cls cl;
+        cl.id = kv.first;
+        cl.runs = kv.second;
+        double w = 0.0, s0 = 0.0, s1 = 0.0;
+        for (int r : cl.runs) {
+            const ft_run &R = runs[r];
+            const double ev = (double)R.n_f0 * R.n_f1 * R.n_sky * R.n_sft;
+            w += ev;
+            s0 += ev * R.n_f0;
+            s1 += ev * R.n_f1;
+        }
+        cl.evals = w;
+        cl.cand = tune_candidates(s0 / w, s1 / w, pl.uniform[cl.runs[0]] != 0);
+        cl.rate.assign(cl.cand.size(), 0.0);
+        n_pass = std::max(n_pass, cl.cand.size());
+        cls.push_back(std::move(cl));
+    }
+    const size_t nc = cls.size();
+    std::vector<hipEvent_t> ev(2 * nc, nullptr);
+    ft_status st = FT_OK;
+    for (auto &x : ev)
+        if (hipEventCreate(&x) != hipSuccess) {
+            x = nullptr;
+            st = fail(c, FT_E_DEVICE, "hipEventCreate");
+            break;
+        }
+    std::vector<int2> items;
+    std::vector<size_t> off(nc + 1, 0);
+    std::vector<char> active(nc, 0);
+    std::vector<int> wtp(nc, 64);
+    for (int pp = -1; pp < (int)n_pass && st == FT_OK; ++pp) {
+        const size_t p = pp < 0 ? 0 : (size_t)pp;
+        items.clear();
+        for (size_t q = 0; q < nc; ++q) {
+            off[q] = items.size();
+            active[q] = p < cls[q].cand.size();
+            wtp[q] = 64;
+            if (!active[q]) continue;
+            const int tile = cls[q].cand[p];
+            int64_t n_items = 0;
+            for (int r : cls[q].runs) {
+                if (assign_run_tile(pl, r, tile, runs[r], f0h, f1h, t_sft) != tile) {
+                    active[q] = 0;  // some run's window does not fit this tile
+                    break;
+                }
+                wtp[q] = std::max(wtp[q], pl.runs[r].wtp);
+                n_items += run_items(pl, r);
+            }
+            if (active[q] && (int64_t)items.size() + n_items >= 0x7fffffffLL) active[q] = 0;
+            if (!active[q]) continue;
+            for (int r : cls[q].runs) append_items(pl, r, items);
+        }
+        off[nc] = items.size();
+        if (items.empty()) continue;
+        e = ensure(&b.items, &b.c_items, items.size());
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(b.runs, pl.runs.data(), (size_t)n_runs * sizeof(EvalRun), hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(b.items, items.data(), items.size() * sizeof(int2), hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess) e = launch_fill_u32(b.counters, 0u, (int)nc, c->stream);
+        for (size_t q = 0; q < nc && e == hipSuccess; ++q) {
+            if (!active[q]) continue;
+            const int n_items = (int)(off[q + 1] - off[q]);
+            e = hipEventRecord(ev[2 * q], c->stream);
+            if (e == hipSuccess)
+                e = launch_eval_batch(b.runs, b.items + off[q], n_items, wtp[q], b.counters + q, std::min(n_items, 2048),
+                                      tile_cfg(cls[q].cand[p]), c->stream);
+            if (e == hipSuccess) e = hipEventRecord(ev[2 * q + 1], c->stream);
+        }
+        // the host item list is reused by the next pass
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        for (size_t q = 0; q < nc && e == hipSuccess && pp >= 0; ++q) {
+            if (!active[q]) continue;
+            float ms = 0.f;
+            e = hipEventElapsedTime(&ms, ev[2 * q], ev[2 * q + 1]);
+            if (e == hipSuccess && ms > 0.f) cls[q].rate[p] = cls[q].evals / (ms * 1e-3);
+        }
+        if (e != hipSuccess) st = hip_fail(c, e, "tile tuning");
+    }
+    for (hipEvent_t x : ev)
+        if (x) (void)hipEventDestroy(x);
+    if (st != FT_OK) return st;
+    c->tune_log.clear();
+    for (const Cls &cl : cls) {
+        size_t bi = 0;
+        for (size_t i = 1; i < cl.cand.size(); ++i)
+            if (cl.rate[i] > cl.rate[bi]) bi = i;
+        if (cl.rate[bi] > 0.0) c->tune_cache[{1, (int64_t)cl.id}] = cl.cand[bi];
+        for (size_t i = 0; i < cl.cand.size(); ++i) {
+            ft_tune_entry t{};
+            t.klass = 1 + cl.id;
+            t.tile = cl.cand[i] + 1;
+            t.chosen = cl.rate[bi] > 0.0 && i == bi;
+            t.evals_per_s = cl.rate[i];
+            t.sample_evals = cl.evals;
+            c->tune_log.push_back(t);
+        }
+    }
+    c->tune_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
     return FT_OK;
 }
 
@@ -1169,7 +1489,7 @@ ft_status ft_eval_batch(ft_ctx c, const ft_batch *bt, int32_t use_graph)
     const bool gen = bt->generate == 1;
     if (gen && !bt->arms) return fail(c, FT_E_INVALID, "generated batches need arms");
     if (!gen && (!bt->power || bt->power_len < 1)) return fail(c, FT_E_INVALID, "batch tables missing");
-    if (bt->tile != 0 && (bt->tile < 1 || bt->tile > tile_count())) return fail(c, FT_E_INVALID, "unknown tile");
+    if (bt->tile < FT_TILE_TUNE || bt->tile > tile_count()) return fail(c, FT_E_INVALID, "unknown tile");
     const int n_runs = bt->n_runs;
     const int64_t NS = bt->n_sft_total;
     std::vector<ft_run> runs;
@@ -1208,6 +1528,9 @@ ft_status ft_eval_batch(ft_ctx c, const ft_batch *bt, int32_t use_graph)
     pl.sky_prefix.assign(n_runs + 1, 0);
     pl.sft_begin.resize(n_runs);
     pl.tref.resize(n_runs);
+    pl.uniform.assign(n_runs, 0);
+    pl.dt_absmax.assign(n_runs, 0.0);
+    pl.vmax.assign(n_runs, 0.0);
     for (int r = 0; r < n_runs; ++r) {
         const ft_run &R = runs[r];
         if (R.n_sft < 1 || R.sft_begin < 0 || (int64_t)R.sft_begin + R.n_sft > NS)
@@ -1268,34 +1591,9 @@ ft_status ft_eval_batch(ft_ctx c, const ft_batch *bt, int32_t use_graph)
         EvalRun &E = pl.runs[r];
         E = EvalRun{};
         guard_params(f0, R.n_f0, f0[R.n_f0 - 1], x_max, vmax, bt->t_sft, E.dT, E.eta);
-        // Small f0 grids would leave most lanes of a 64-wide f0 tile idle: they
-        // are evaluated directly, one lane per template.
-        int tile = bt->tile ? bt->tile - 1 : (R.n_f0 < 32 ? -1 : choose_batch_tile(R.n_f0, R.n_f1, E.eta < 1e-4));
-        if (tile >= 0 && tile_cfg(tile).L > 1 && !(E.eta < 1e-4)) tile = 14;
-        const double dt_absmax = std::max(std::fabs(dt_min), std::fabs(dt_max));
-        WindowPlan wp;
-        if (tile >= 0) {
-            wp = plan_window(f0, R.n_f0, f1, R.n_f1, pl.sky_tile.data() + 3 * sky_base, R.n_sky, dt_absmax, vmax,
-                             bt->t_sft, tile);
-            if (wp.tile < 0) tile = -1;  // window beyond the LDS budget: direct
-        }
-        pl.tile[r] = tile;
-        const int64_t n_tmpl = (int64_t)R.n_f0 * R.n_f1 * R.n_sky;
-        if (tile >= 0) {
-            E.wt = wp.wt;
-            E.wtp = wp.wtp;
-            E.tiles_f0 = wp.tiles_f0;
-            E.tiles_f1 = wp.tiles_f1;
-            E.tiles_sky = wp.tiles_sky;
-            pl.max_wtp = std::max(pl.max_wtp, wp.wtp);
-            const int64_t n_tiles = (int64_t)wp.tiles_f0 * wp.tiles_f1 * wp.tiles_sky;
-            if (n_tiles >= 0x7fffffff) return fail(c, FT_E_UNSUPPORTED, "run %d: too many tiles", r);
-            for (int64_t tt = 0; tt < n_tiles; ++tt) pl.items[tile].push_back(make_int2(r, (int)tt));
-        } else {
-            const int64_t n_chunks = (n_tmpl + 255) / 256;
-            if (n_chunks >= 0x7fffffff) return fail(c, FT_E_UNSUPPORTED, "run %d: too many templates", r);
-            for (int64_t ch = 0; ch < n_chunks; ++ch) pl.items[tile_count()].push_back(make_int2(r, (int)ch));
-        }
+        pl.uniform[r] = E.eta < 1e-4;
+        pl.dt_absmax[r] = std::max(std::fabs(dt_min), std::fabs(dt_max));
+        pl.vmax[r] = vmax;
         E.n_sft = R.n_sft;
         E.n_bins = R.n_bins;
         E.first_bin = (int32_t)R.first_bin;
@@ -1312,9 +1610,27 @@ ft_status ft_eval_batch(ft_ctx c, const ft_batch *bt, int32_t use_graph)
         pl.gen_prefix_elem[r + 1] = pl.gen_prefix_elem[r] + cells;
         pl.sky_prefix[r + 1] = pl.sky_prefix[r] + R.n_sky;
     }
-    int64_t total_items = 0;
-    for (auto &v : pl.items) total_items += (int64_t)v.size();
-    if (total_items >= 0x7fffffff) return fail(c, FT_E_UNSUPPORTED, "too many work items");
+    // Tile of every run: the forced one, the tile cached for its size class,
+    // else the cost model; with FT_TILE_TUNE, uncached classes are timed below.
+    std::map<int, std::vector<int>> to_tune;
+    auto plan_tiles = [&]() {
+        for (int r = 0; r < n_runs; ++r) {
+            const ft_run &R = runs[r];
+            const int kl = batch_class(R, pl.uniform[r] != 0);
+            int tile;
+            if (bt->tile > 0) {
+                tile = bt->tile - 1;
+            } else if (kl < 0) {
+                tile = -1;
+            } else {
+                const auto it = c->tune_cache.find({1, (int64_t)kl});
+                tile = it != c->tune_cache.end() ? it->second : choose_batch_tile(R.n_f0, R.n_f1, pl.uniform[r] != 0);
+                if (it == c->tune_cache.end() && bt->tile == FT_TILE_TUNE) to_tune[kl].push_back(r);
+            }
+            assign_run_tile(pl, r, tile, R, f0h.data(), f1h.data(), bt->t_sft);
+        }
+    };
+    plan_tiles();
     const int k = bt->k;
     const int cap = std::max(4096, 8 * k);
 
@@ -1337,8 +1653,7 @@ ft_status ft_eval_batch(ft_ctx c, const ft_batch *bt, int32_t use_graph)
         (e = ensure(&b.power, &b.c_power, (size_t)n_power)) != hipSuccess ||
         (e = ensure(&b.stats, &b.c_stats, (size_t)n_stats)) != hipSuccess ||
         (e = ensure(&b.runs, &b.c_runs, (size_t)n_runs)) != hipSuccess ||
-        (e = ensure(&b.items, &b.c_items, (size_t)std::max<int64_t>(total_items, 1))) != hipSuccess ||
-        (e = ensure(&b.counters, &b.c_counters, (size_t)tile_count() + 1)) != hipSuccess ||
+        (e = ensure(&b.counters, &b.c_counters, (size_t)std::max(tile_count() + 1, 129))) != hipSuccess ||
         (e = ensure(&b.cand, &b.c_cand, (size_t)n_runs * cap)) != hipSuccess ||
         (e = ensure(&b.s64, &b.c_s64, (size_t)n_runs * cap)) != hipSuccess ||
         (e = ensure(&b.out, &b.c_out, (size_t)n_runs * k)) != hipSuccess ||
@@ -1391,9 +1706,6 @@ ft_status ft_eval_batch(ft_ctx c, const ft_batch *bt, int32_t use_graph)
             pl.gen.push_back(g);
         }
     }
-    std::vector<int2> items_flat;
-    items_flat.reserve((size_t)total_items);
-    for (auto &v : pl.items) items_flat.insert(items_flat.end(), v.begin(), v.end());
     std::vector<int64_t> gp;
     if (gen) {
         gp = pl.gen_prefix_sft;
@@ -1415,8 +1727,6 @@ ft_status ft_eval_batch(ft_ctx c, const ft_batch *bt, int32_t use_graph)
         {b.tref, pl.tref.data(), pl.tref.size() * 8},
         {b.sft_begin, pl.sft_begin.data(), pl.sft_begin.size() * 4},
         {b.dt_prefix, pl.dt_prefix.data(), pl.dt_prefix.size() * 8},
-        {b.runs, pl.runs.data(), pl.runs.size() * sizeof(EvalRun)},
-        {b.items, items_flat.data(), items_flat.size() * sizeof(int2)},
         {b.gen, pl.gen.data(), pl.gen.size() * sizeof(GenRun)},
         {b.gen_prefix, gp.data(), gp.size() * 8},
     };
@@ -1429,6 +1739,31 @@ ft_status ft_eval_batch(ft_ctx c, const ft_batch *bt, int32_t use_graph)
         e = hipMemcpyAsync(b.power, bt->power, (size_t)bt->power_len * sizeof(float), hipMemcpyDefault, c->stream);
         if (e != hipSuccess) return hip_fail(c, e, "upload batch tables");
     }
+    if (!to_tune.empty()) {
+        ft_status st = tune_batch(c, pl, runs, f0h.data(), f1h.data(), bt->t_sft, gen, to_tune);
+        if (st != FT_OK) return st;
+        to_tune.clear();
+        plan_tiles();
+    }
+    // work items grouped by tile (the direct kernel's last)
+    int64_t total_items = 0;
+    for (int r = 0; r < n_runs; ++r) total_items += run_items(pl, r);
+    if (total_items >= 0x7fffffff) return fail(c, FT_E_UNSUPPORTED, "too many work items");
+    pl.group_wtp.assign(tile_count() + 1, 64);
+    for (int r = 0; r < n_runs; ++r) {
+        const int t = pl.tile[r];
+        append_items(pl, r, pl.items[t >= 0 ? t : tile_count()]);
+        if (t >= 0) pl.group_wtp[t] = std::max(pl.group_wtp[t], pl.runs[r].wtp);
+    }
+    std::vector<int2> items_flat;
+    items_flat.reserve((size_t)total_items);
+    for (auto &v : pl.items) items_flat.insert(items_flat.end(), v.begin(), v.end());
+    if ((e = ensure(&b.items, &b.c_items, (size_t)std::max<int64_t>(total_items, 1))) != hipSuccess)
+        return hip_fail(c, e, "alloc batch items");
+    e = hipMemcpyAsync(b.runs, pl.runs.data(), pl.runs.size() * sizeof(EvalRun), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b.items, items_flat.data(), items_flat.size() * sizeof(int2), hipMemcpyHostToDevice, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "upload batch items");
     // the host vectors above are released on return: make the copies complete
     e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "upload batch");

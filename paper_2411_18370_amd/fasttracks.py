@@ -20,6 +20,7 @@ FT_OK, FT_E_INVALID, FT_E_STATE, FT_E_RANGE, FT_E_NOMEM, FT_E_DEVICE, FT_E_UNSUP
 FT_BANK_GRID, FT_BANK_LIST = 0, 1
 FT_INDEX_FP64, FT_INDEX_FP32, FT_INDEX_DF64, FT_INDEX_GUARDED = 0, 1, 2, 3
 FT_SUM_BLOCKED, FT_SUM_PLAIN_FP32 = 0, 1
+FT_TILE_TUNE = -1
 
 
 class FtError(RuntimeError):
@@ -76,13 +77,19 @@ class ft_eval_info(C.Structure):
                 ("slow_groups", C.c_int64)]
 
 
+class ft_tune_entry(C.Structure):
+    _fields_ = [("klass", C.c_int32), ("tile", C.c_int32), ("chosen", C.c_int32),
+                ("reserved", C.c_int32), ("evals_per_s", C.c_double), ("sample_evals", C.c_double)]
+
+
 _lib = None
 EXPORTS = ("ft_create", "ft_destroy", "ft_last_error", "ft_status_string", "ft_set_sfts",
            "ft_set_velocities", "ft_eval_templates", "ft_toplist", "ft_sync",
            "ft_last_eval_info", "ft_bins", "ft_count_index_mismatches", "ft_tile_count",
            "ft_tile_name", "ft_gen_sfts", "ft_eval_batch", "ft_batch_toplist", "ft_batch_labels",
            "ft_batch_replay", "ft_batch_time", "ft_mlp_create", "ft_mlp_destroy",
-           "ft_mlp_get_params", "ft_mlp_predict", "ft_mlp_loss_grad", "ft_mlp_train")
+           "ft_mlp_get_params", "ft_mlp_predict", "ft_mlp_loss_grad", "ft_mlp_train",
+           "ft_tune_report", "ft_tune_clear")
 
 
 def load(path: str = LIB_PATH):
@@ -124,6 +131,9 @@ def load(path: str = LIB_PATH):
         "ft_mlp_predict": (C.c_int, [P, P, i64, P]),
         "ft_mlp_loss_grad": (C.c_int, [P, P, P, i32, C.POINTER(C.c_float), P]),
         "ft_mlp_train": (C.c_int, [P, P, P, i64, i32, i32, C.c_float, C.c_uint64, P]),
+        "ft_tune_report": (C.c_int, [P, C.POINTER(ft_tune_entry), i32, C.POINTER(i32),
+                                     C.POINTER(f64)]),
+        "ft_tune_clear": (C.c_int, [P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -289,6 +299,24 @@ def ft_count_index_mismatches(ctx, f0, f1, sky, t_ref, precision, kind=FT_BANK_G
 
 def ft_tile_count():
     return int(load().ft_tile_count())
+
+
+def ft_tune_report(ctx):
+    """(entries, tune_ms) of the context's most recent tile tuning; entries are
+    dicts with klass, tile, name, chosen, evals_per_s, sample_evals."""
+    lib = load()
+    n = C.c_int32()
+    ms = C.c_double()
+    _check(ctx, lib.ft_tune_report(ctx, None, 0, C.byref(n), C.byref(ms)))
+    buf = (ft_tune_entry * max(1, n.value))()
+    _check(ctx, lib.ft_tune_report(ctx, buf, n.value, C.byref(n), C.byref(ms)))
+    out = [{"klass": e.klass, "tile": e.tile, "name": ft_tile_name(e.tile), "chosen": bool(e.chosen),
+            "evals_per_s": e.evals_per_s, "sample_evals": e.sample_evals} for e in buf[:n.value]]
+    return out, ms.value
+
+
+def ft_tune_clear(ctx):
+    _check(ctx, load().ft_tune_clear(ctx))
 
 
 def ft_tile_name(tile):
@@ -519,6 +547,12 @@ class Context:
 
     def batch_time(self):
         return ft_batch_time(self.ctx)
+
+    def tune_report(self):
+        return ft_tune_report(self.ctx)
+
+    def tune_clear(self):
+        ft_tune_clear(self.ctx)
 
     def eval_campaign(self, cp, use_graph=0, tile=0, power=None):
         """Evaluate a synth.Campaign (tables generated on the GPU unless given)."""

@@ -50,6 +50,7 @@ def test_struct_layouts_match_header():
     assert C.sizeof(ft.ft_eval_opts) == 32
     assert C.sizeof(ft.ft_candidate) == 72
     assert ft.ft_candidate.s64.offset == 56
+    assert C.sizeof(ft.ft_tune_entry) == 32
 
 
 def test_null_arguments_are_rejected_without_a_device():
@@ -59,6 +60,8 @@ def test_null_arguments_are_rejected_without_a_device():
     assert lib.ft_set_sfts(None, 1, None, None, 1800.0, 0, 1, None, None) == ft.FT_E_INVALID
     assert lib.ft_set_velocities(None, None) == ft.FT_E_INVALID
     assert lib.ft_sync(None) == ft.FT_E_INVALID
+    assert lib.ft_tune_clear(None) == ft.FT_E_INVALID
+    assert lib.ft_tune_report(None, None, 0, None, None) == ft.FT_E_INVALID
 
 
 def test_oracle_and_library_share_no_code():
