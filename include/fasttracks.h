@@ -234,8 +234,9 @@ typedef struct {
  * velocities of ft_set_velocities, and the detector arm unit vectors
  * arms [N][6] = (u, w) (equatorial) at each mid-time.  Noise: Re, Im ~ N(0, 1)
  * per (bin b, SFT k) from Philox-4x32-10 keyed by `seed` with counter
- * (b, k, run, 0) and Box-Muller; power P = Re^2 + Im^2 (Eq. s_chi2).  Signal
- * (inj != NULL and inj->amp > 0): track x_k = (f0 + f1 (t_k - t_ref))(1 + v_k.n)
+ * (b, k, run, 0) and Box-Muller; power P = Re^2 + Im^2 (Eq. s_chi2).  Signals
+ * (inj[0..n_inj), n_inj <= 64, those with amp > 0; they superpose, each added
+ * to Re in the order given): track x_k = (f0 + f1 (t_k - t_ref))(1 + v_k.n)
  * T_sft bins, B_k = floor(x_k + 1/2), delta_k = x_k - B_k; bins B_k + m,
  * m in {-1, 0, 1}, get sqrt(rho_k^2) |sinc(pi (delta_k - m))| added to Re with
  * rho_k^2 = T_sft amp^2 (F+^2 A+^2 + Fx^2 Ax^2), A+ = (1 + cos^2 iota)/2,
@@ -248,7 +249,7 @@ typedef struct {
 ft_status ft_gen_sfts(ft_ctx ctx, int32_t n_det, const int32_t *n_sft, const double *t_mid,
                       double t_sft, int64_t first_bin, int32_t n_bins, const double *v_over_c,
                       const double *arms, uint64_t seed, uint32_t run, double t_ref,
-                      const ft_injection *inj, float *power_out);
+                      const ft_injection *inj, int32_t n_inj, float *power_out);
 
 /*
  * Batches (many independent runs in one launch: injection campaigns, uneven

@@ -142,12 +142,18 @@ def signal_amplitudes(t_mid, t_ref, t_sft, v, arms, inj):
 
 def generate_table(seed, run, t_mid, t_ref, t_sft, v, arms, first_bin, n_bins, inj=None,
                    sft_offset=0):
-    """FP32 power table [N, n_bins] of one run (noise + optional injection)."""
+    """FP32 power table [N, n_bins] of one run: noise plus the signals of `inj`
+    (None, one dict or a list of dicts).  Signals superpose linearly in the SFT
+    amplitude (the strain is a sum of the sources' strains), so each adds its
+    leakage amplitudes to Re, in the order given."""
     n_sft = len(t_mid)
     re, im = noise_normals(seed, run, n_sft, n_bins, sft_offset)
-    if inj is not None and inj.get("amp", 0.0) != 0.0:
+    injs = [] if inj is None else [inj] if isinstance(inj, dict) else list(inj)
+    for one in injs:
+        if one.get("amp", 0.0) == 0.0:
+            continue
         B, A = signal_amplitudes(np.asarray(t_mid, np.float64), t_ref, t_sft,
-                                 np.asarray(v, np.float64), np.asarray(arms, np.float64), inj)
+                                 np.asarray(v, np.float64), np.asarray(arms, np.float64), one)
         rows = np.arange(n_sft)
         for j, m in enumerate((-1, 0, 1)):
             col = B + m - first_bin

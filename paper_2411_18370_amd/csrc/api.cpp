@@ -592,7 +592,8 @@ static ft_status set_velocities_impl(ft_ctx c, const double *v, bool sync)
 
 ft_status ft_gen_sfts(ft_ctx c, int32_t n_det, const int32_t *n_sft, const double *t_mid, double t_sft,
                       int64_t first_bin, int32_t n_bins, const double *v_over_c, const double *arms,
-                      uint64_t seed, uint32_t run, double t_ref, const ft_injection *inj, float *power_out)
+                      uint64_t seed, uint32_t run, double t_ref, const ft_injection *inj, int32_t n_inj,
+                      float *power_out)
 {
     if (!c) return FT_E_INVALID;
     c->err.clear();
@@ -612,9 +613,11 @@ ft_status ft_gen_sfts(ft_ctx c, int32_t n_det, const int32_t *n_sft, const doubl
     if (n_bins < 1) return fail(c, FT_E_INVALID, "n_bins must be >= 1");
     if (first_bin < 0 || first_bin + (int64_t)n_bins >= 0x7fffffffLL)
         return fail(c, FT_E_UNSUPPORTED, "bins must lie in [0, 2^31-1)");
-    ft_injection in{};
-    if (inj) {
-        in = *inj;
+    if (n_inj < 0 || n_inj > 64 || (n_inj > 0 && !inj))
+        return fail(c, FT_E_INVALID, "n_inj must be in [0, 64] with inj holding n_inj signals");
+    std::vector<ft_injection> ins;
+    if (n_inj > 0 && fetch(ins, inj, (size_t)n_inj) != hipSuccess) return fail(c, FT_E_INVALID, "cannot read inj");
+    for (const ft_injection &in : ins) {
         const double vals[] = {in.amp, in.cos_iota, in.psi, in.sky[0], in.sky[1], in.sky[2], in.f0, in.f1};
         for (double x : vals)
             if (!is_finite(x)) return fail(c, FT_E_INVALID, "injection parameters must be finite");
@@ -638,8 +641,8 @@ ft_status ft_gen_sfts(ft_ctx c, int32_t n_det, const int32_t *n_sft, const doubl
         (e = ensure(&c->d_tmid, &c->cap_tmid, (size_t)total)) != hipSuccess ||
         (e = ensure(&c->d_dt, &c->cap_dt, (size_t)total)) != hipSuccess ||
         (e = ensure(&c->d_arms, &c->cap_arms, (size_t)total * 6)) != hipSuccess ||
-        (e = ensure(&c->d_inj_bin, &c->cap_inj_bin, (size_t)total)) != hipSuccess ||
-        (e = ensure(&c->d_inj_amp, &c->cap_inj_amp, (size_t)total * 3)) != hipSuccess)
+        (e = ensure(&c->d_inj_bin, &c->cap_inj_bin, (size_t)total * std::max(n_inj, 1))) != hipSuccess ||
+        (e = ensure(&c->d_inj_amp, &c->cap_inj_amp, (size_t)total * 3 * std::max(n_inj, 1))) != hipSuccess)
         return hip_fail(c, e, "alloc generated SFTs");
     e = hipMemcpyAsync(c->d_tmid, tm.data(), (size_t)total * sizeof(double), hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess)
@@ -659,6 +662,7 @@ ft_status ft_gen_sfts(ft_ctx c, int32_t n_det, const int32_t *n_sft, const doubl
         c->have_sfts = false;
         return st;
     }
+    // records 0..n_inj-1 prepare one signal each; record n_inj is the table
     GenRun g{};
     g.seed = seed;
     g.run = run;
@@ -671,25 +675,41 @@ ft_status ft_gen_sfts(ft_ctx c, int32_t n_det, const int32_t *n_sft, const doubl
     g.arms = c->d_arms;
     g.t_ref = t_ref;
     g.t_sft = t_sft;
-    g.amp = in.amp;
-    g.cos_iota = in.cos_iota;
-    g.psi = in.psi;
-    for (int d = 0; d < 3; ++d) g.sky[d] = in.sky[d];
-    g.f0 = in.f0;
-    g.f1 = in.f1;
     g.table = c->d_power;
+    c->genruns_h.clear();
+    c->prefix_h.clear();
+    for (int i = 0; i < n_inj; ++i) {
+        GenRun p = g;
+        const ft_injection &in = ins[(size_t)i];
+        p.amp = in.amp;
+        p.cos_iota = in.cos_iota;
+        p.psi = in.psi;
+        for (int d = 0; d < 3; ++d) p.sky[d] = in.sky[d];
+        p.f0 = in.f0;
+        p.f1 = in.f1;
+        p.inj_bin = c->d_inj_bin + (int64_t)i * total;
+        p.inj_amp = c->d_inj_amp + 3 * (int64_t)i * total;
+        p.n_inj = 1;
+        c->genruns_h.push_back(p);
+        c->prefix_h.push_back((int64_t)i * total);
+    }
+    c->prefix_h.push_back((int64_t)n_inj * total);
     g.inj_bin = c->d_inj_bin;
     g.inj_amp = c->d_inj_amp;
-    c->genruns_h.assign(1, g);
-    c->prefix_h = {0, total, 0, (int64_t)n_cells};
-    if ((e = ensure(&c->d_genruns, &c->cap_genruns, 1)) != hipSuccess ||
-        (e = ensure(&c->d_prefix, &c->cap_prefix, 4)) != hipSuccess)
+    g.n_inj = n_inj;
+    c->genruns_h.push_back(g);
+    c->prefix_h.push_back(0);
+    c->prefix_h.push_back((int64_t)n_cells);
+    const size_t n_rec = c->genruns_h.size(), n_pre = c->prefix_h.size();
+    if ((e = ensure(&c->d_genruns, &c->cap_genruns, n_rec)) != hipSuccess ||
+        (e = ensure(&c->d_prefix, &c->cap_prefix, n_pre)) != hipSuccess)
         return hip_fail(c, e, "alloc generator descriptors");
-    e = hipMemcpyAsync(c->d_genruns, c->genruns_h.data(), sizeof(GenRun), hipMemcpyHostToDevice, c->stream);
+    e = hipMemcpyAsync(c->d_genruns, c->genruns_h.data(), n_rec * sizeof(GenRun), hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(c->d_prefix, c->prefix_h.data(), 4 * sizeof(int64_t), hipMemcpyHostToDevice, c->stream);
+        e = hipMemcpyAsync(c->d_prefix, c->prefix_h.data(), n_pre * sizeof(int64_t), hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess)
-        e = launch_gen_tables(c->d_genruns, 1, c->d_prefix, c->d_prefix + 2, total, (int64_t)n_cells, c->stream);
+        e = launch_gen_tables(c->d_genruns, n_inj, c->d_prefix, (int64_t)n_inj * total, c->d_genruns + n_inj, 1,
+                              c->d_prefix + (n_inj + 1), (int64_t)n_cells, c->stream);
     if (e == hipSuccess) e = launch_noise_moments(nullptr, (int)total, c->d_mu_sigma, c->stream);
     if (e == hipSuccess && power_out)
         e = hipMemcpyAsync(power_out, c->d_power, n_cells * sizeof(float), hipMemcpyDefault, c->stream);
@@ -1323,8 +1343,8 @@ static ft_status launch_batch_sequence(ft_ctx c, const BatchPlan &pl, bool gener
     if (e == hipSuccess)
         e = launch_batch_dt(b.tmid, b.sft_begin, b.tref, b.dt_prefix, n_runs, pl.dt_prefix[n_runs], b.dt, st);
     if (e == hipSuccess && generate)
-        e = launch_gen_tables(b.gen, n_runs, b.gen_prefix, b.gen_prefix + (n_runs + 1), pl.gen_prefix_sft[n_runs],
-                              pl.gen_prefix_elem[n_runs], st);
+        e = launch_gen_tables(b.gen, n_runs, b.gen_prefix, pl.gen_prefix_sft[n_runs], b.gen, n_runs,
+                              b.gen_prefix + (n_runs + 1), pl.gen_prefix_elem[n_runs], st);
     int64_t item_off = 0;
     for (int id = 0; id < tile_count() && e == hipSuccess; ++id) {
         const int n_items = (int)pl.items[id].size();
@@ -1360,8 +1380,8 @@ static ft_status tune_batch(ft_ctx c, BatchPlan &pl, const std::vector<ft_run> &
     const int n_runs = (int)pl.runs.size();
     hipError_t e = launch_batch_dt(b.tmid, b.sft_begin, b.tref, b.dt_prefix, n_runs, pl.dt_prefix[n_runs], b.dt, c->stream);
     if (e == hipSuccess && gen)
-        e = launch_gen_tables(b.gen, n_runs, b.gen_prefix, b.gen_prefix + (n_runs + 1), pl.gen_prefix_sft[n_runs],
-                              pl.gen_prefix_elem[n_runs], c->stream);
+        e = launch_gen_tables(b.gen, n_runs, b.gen_prefix, pl.gen_prefix_sft[n_runs], b.gen, n_runs,
+                              b.gen_prefix + (n_runs + 1), pl.gen_prefix_elem[n_runs], c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "tile tuning");
     struct Cls {
         int id;
@@ -1703,6 +1723,7 @@ ft_status ft_eval_batch(ft_ctx c, const ft_batch *bt, int32_t use_graph)
             g.table = b.power + pl.gen_prefix_elem[r];
             g.inj_bin = b.inj_bin + pl.gen_prefix_sft[r];
             g.inj_amp = b.inj_amp + 3 * pl.gen_prefix_sft[r];
+            g.n_inj = 1;
             pl.gen.push_back(g);
         }
     }

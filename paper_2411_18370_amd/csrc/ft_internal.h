@@ -132,14 +132,19 @@ struct GenRun {
     double t_ref, t_sft;
     double amp, cos_iota, psi, sky[3], f0, f1;
     float *table;         // [n_sft][n_bins] output
-    int32_t *inj_bin;     // [n_sft] scratch
-    double *inj_amp;      // [n_sft][3] scratch
+    int32_t *inj_bin;     // [n_inj][n_sft] scratch (a preparation record: [n_sft])
+    double *inj_amp;      // [n_inj][n_sft][3] scratch (a preparation record: [n_sft][3])
+    int32_t n_inj;        // signals the noise step adds (preparation records: unused)
+    int32_t pad;
 };
-// Generate the tables of n_runs runs (device array of GenRun);
-// sft_prefix[r] / elem_prefix[r] are exclusive prefix sums of n_sft and
-// n_sft*n_bins (n_runs + 1 entries each, device).
-hipError_t launch_gen_tables(const GenRun *runs, int n_runs, const int64_t *sft_prefix,
-                             const int64_t *elem_prefix, int64_t total_sft, int64_t total_elem,
+// Generate tables.  prep[0..n_prep) are the per-SFT signal preparations (one
+// record per injected signal, each writing its own inj_bin / inj_amp slice;
+// prep_prefix: exclusive prefix sums of their n_sft, n_prep + 1 entries);
+// runs[0..n_runs) are the tables (elem_prefix: exclusive prefix sums of
+// n_sft*n_bins), each adding its n_inj prepared signals to the noise in order.
+// All arrays on the device.
+hipError_t launch_gen_tables(const GenRun *prep, int n_prep, const int64_t *prep_prefix, int64_t total_prep_sft,
+                             const GenRun *runs, int n_runs, const int64_t *elem_prefix, int64_t total_elem,
                              hipStream_t s);
 
 // Selection: exact toplists per segment (segment = sub-band here).

@@ -15,7 +15,8 @@
 // A+ = (1 + cos^2 iota)/2, Ax = cos iota; bins B_k + m (m = -1, 0, 1) receive
 // sqrt(rho_k^2) |sinc(pi (delta_k - m))| added to Re.  Antenna patterns:
 // F+ = D:e+, Fx = D:ex with D = (u u^T - w w^T)/2 from the arm unit vectors and
-// (p, q) = (e_alpha, e_delta) rotated by psi.
+// (p, q) = (e_alpha, e_delta) rotated by psi.  Several signals superpose: each
+// adds its amplitudes to Re in the order given.
 #include "ft_internal.h"
 
 namespace ft {
@@ -150,10 +151,12 @@ __global__ void gen_noise_kernel(const GenRun *runs, int n_runs, const int64_t *
         const double th = 2.0 * M_PI * u2;
         double re = r * cos(th);
         const double im = r * sin(th);
-        const int32_t B = g.inj_bin[k];
-        if (B != INT32_MIN) {
+        for (int i = 0; i < g.n_inj; ++i) {
+            const int64_t ki = (int64_t)i * g.n_sft + k;
+            const int32_t B = g.inj_bin[ki];
+            if (B == INT32_MIN) continue;
             const int64_t m = g.first_bin + b - (int64_t)B;
-            if (m >= -1 && m <= 1) re += g.inj_amp[3 * k + (int)(m + 1)];
+            if (m >= -1 && m <= 1) re += g.inj_amp[3 * ki + (int)(m + 1)];
         }
         g.table[e] = (float)(re * re + im * im);
     }
@@ -161,20 +164,22 @@ __global__ void gen_noise_kernel(const GenRun *runs, int n_runs, const int64_t *
 
 }  // namespace
 
-hipError_t launch_gen_tables(const GenRun *runs, int n_runs, const int64_t *sft_prefix,
-                             const int64_t *elem_prefix, int64_t total_sft, int64_t total_elem,
+hipError_t launch_gen_tables(const GenRun *prep, int n_prep, const int64_t *prep_prefix, int64_t total_prep_sft,
+                             const GenRun *runs, int n_runs, const int64_t *elem_prefix, int64_t total_elem,
                              hipStream_t s)
 {
-    if (n_runs <= 0 || total_elem <= 0) return hipSuccess;
-    int64_t b1 = (total_sft + 255) / 256;
-    if (b1 > 16384) b1 = 16384;
-    hipLaunchKernelGGL(gen_prep_kernel, dim3((unsigned)b1), dim3(256), 0, s, runs, n_runs,
-                       sft_prefix, total_sft);
-    int64_t b2 = (total_elem + 255) / 256;
-    if (b2 > 32768) b2 = 32768;
-    hipLaunchKernelGGL(gen_noise_kernel, dim3((unsigned)b2), dim3(256), 0, s, runs, n_runs,
-                       elem_prefix, total_elem);
+    if (n_prep > 0 && total_prep_sft > 0) {
+        int64_t b1 = (total_prep_sft + 255) / 256;
+        if (b1 > 16384) b1 = 16384;
+        hipLaunchKernelGGL(gen_prep_kernel, dim3((unsigned)b1), dim3(256), 0, s, prep, n_prep, prep_prefix,
+                           total_prep_sft);
+    }
+    if (n_runs > 0 && total_elem > 0) {
+        int64_t b2 = (total_elem + 255) / 256;
+        if (b2 > 32768) b2 = 32768;
+        hipLaunchKernelGGL(gen_noise_kernel, dim3((unsigned)b2), dim3(256), 0, s, runs, n_runs, elem_prefix,
+                           total_elem);
+    }
     return hipGetLastError();
 }
-
 }  // namespace ft

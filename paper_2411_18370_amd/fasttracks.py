@@ -118,7 +118,7 @@ def load(path: str = LIB_PATH):
                                                 C.POINTER(i64)]),
         "ft_tile_count": (i32, []),
         "ft_gen_sfts": (C.c_int, [P, i32, P, P, f64, i64, i32, P, P, C.c_uint64, C.c_uint32, f64,
-                                  C.POINTER(ft_injection), P]),
+                                  C.POINTER(ft_injection), i32, P]),
         "ft_tile_name": (C.c_char_p, [i32]),
         "ft_eval_batch": (C.c_int, [P, C.POINTER(ft_batch), i32]),
         "ft_batch_toplist": (C.c_int, [P, i32, C.POINTER(ft_candidate), C.POINTER(i32)]),
@@ -223,11 +223,11 @@ def ft_gen_sfts(ctx, n_sft_per_det, t_mid, t_sft, first_bin, n_bins, v_over_c, a
     n = _Arr(np.asarray(n_sft_per_det, np.int32), np.int32)
     tm, v, a = _Arr(t_mid, np.float64), _Arr(v_over_c, np.float64), _Arr(arms, np.float64)
     out = _Arr(power_out, np.float32)
-    ij = make_injection(inj)
+    injs = [] if inj is None else [inj] if isinstance(inj, dict) else list(inj)
+    arr = (ft_injection * max(1, len(injs)))(*[make_injection(x) for x in injs])
     _check(ctx, load().ft_gen_sfts(ctx, len(n_sft_per_det), n.ptr, tm.ptr, float(t_sft),
                                    int(first_bin), int(n_bins), v.ptr, a.ptr, int(seed), int(run),
-                                   float(t_ref), C.byref(ij) if ij is not None else None,
-                                   out.ptr))
+                                   float(t_ref), arr if injs else None, len(injs), out.ptr))
 
 
 def ft_set_velocities(ctx, v_over_c):

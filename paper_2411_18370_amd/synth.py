@@ -210,9 +210,18 @@ def plain_small(seed: int = 1, n_sky: int = 20) -> Workload:
 
 
 def allsky_band(seed: int = 2, n_sky: int = 100_000, n_per_det: int = 5000) -> Workload:
-    """2 detectors x 5000 SFTs (10% gaps), 200-200.5 Hz, 900 f0 x 11 f1 x n_sky, K=100/0.05 Hz."""
-    return _build("allsky-2det-10ksft-200Hz", 2, n_per_det, 1800.0, 0.1, 200.0, 900,
-                  np.linspace(-1e-9, 0.0, 11), n_sky, 100, 10, seed)
+    """2 detectors x 5000 SFTs (10% gaps), 200-200.5 Hz, 900 f0 x 11 f1 x n_sky, K=100/0.05 Hz.
+
+    `power` holds noise only; `injections` lists 3 signals for tables generated with
+    them: h0/sqrt(S_n) ~ U[0.05, 0.2], f1 ~ U[-1e-9, 0], isotropic sky and orientation,
+    f0 ~ U[0.01, 0.04] Hz into three distinct inner 0.05 Hz sub-bands."""
+    w = _build("allsky-2det-10ksft-200Hz", 2, n_per_det, 1800.0, 0.1, 200.0, 900,
+               np.linspace(-1e-9, 0.0, 11), n_sky, 100, 10, seed)
+    rng = np.random.default_rng(seed + 7919)
+    subs = rng.choice(np.arange(1, 9), 3, replace=False)
+    w.injections = [injection_params(rng, 200.0 + 0.05 * j + 0.01, 200.0 + 0.05 * j + 0.04,
+                                     0.05, 0.2, -1e-9, 0.0) for j in subs]
+    return w
 
 
 def precision_stress(seed: int = 2, n_sky: int = 20_000, n_per_det: int = 5000) -> Workload:

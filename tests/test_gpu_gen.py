@@ -44,6 +44,25 @@ def test_generated_table_matches_oracle(ft, amp):
     _assert_tables_close(got, want)
 
 
+def test_several_injections_superpose_like_the_oracle(ft):
+    """Three signals, one with amp 0 and two sharing SFT bins (equal f0 and sky):
+    the GPU adds them in the given order like the oracle."""
+    w = synth.allsky_band(seed=33, n_sky=1, n_per_det=120)
+    rng = np.random.default_rng(34)
+    a = synth.injection_params(rng, 200.1, 200.4, 2.0, 2.0, -1e-9, 0.0)
+    b = dict(synth.injection_params(rng, 200.1, 200.4, 1.5, 1.5, -1e-9, 0.0),
+             f0=a["f0"], sky=a["sky"])
+    z = synth.injection_params(rng, 200.1, 200.4, 0.0, 0.0)
+    seed, run = 99, 3
+    got = _gen_gpu(ft, w, seed, run, [a, z, b])
+    want = inject.generate_table(seed, run, w.t_mid, w.t_ref, w.t_sft, w.v, w.arms, w.first_bin,
+                                 w.n_bins, [a, z, b])
+    _assert_tables_close(got, want)
+    one = inject.generate_table(seed, run, w.t_mid, w.t_ref, w.t_sft, w.v, w.arms, w.first_bin,
+                                w.n_bins, a)
+    assert np.sum(want != one) > w.n_sft  # the second signal changed the table
+
+
 def test_generated_campaign_toplist_recovers_injection(ft):
     """Generate with a loud injection, evaluate a local bank around it: the
     loudest template's FP64 statistic matches the oracle on its own table."""

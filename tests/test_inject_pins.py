@@ -124,3 +124,19 @@ def test_injected_bins_light_the_track():
         allowed = {int(B[k]) + m for m in (-1, 0, 1)}
         must = {int(B[k]) + m for m in (-1, 0, 1) if A[k, m + 1] ** 2 > 1000.0}
         assert must <= cols <= allowed, k
+
+
+def test_signals_superpose_linearly_in_amplitude():
+    """Strain is linear in h0, so two equal signals of amplitude a give the table
+    of one signal of amplitude 2a; a signal of amplitude 0 changes nothing."""
+    w = synth.plain_small(seed=25, n_sky=1)
+    rng = np.random.default_rng(26)
+    a = synth.injection_params(rng, 100.02, 100.08, 3.0, 3.0)
+    args = (11, 2, w.t_mid, w.t_ref, w.t_sft, w.v, w.arms, w.first_bin, w.n_bins)
+    two = inject.generate_table(*args, [a, a])
+    double = inject.generate_table(*args, dict(a, amp=6.0))
+    assert np.allclose(two, double, rtol=1e-6, atol=1e-6)
+    assert np.sum(two != inject.generate_table(*args, a)) > w.n_sft
+    zero = dict(a, amp=0.0)
+    assert np.array_equal(inject.generate_table(*args, [a, zero]), inject.generate_table(*args, a))
+    assert np.array_equal(inject.generate_table(*args, [zero]), inject.generate_table(*args))
