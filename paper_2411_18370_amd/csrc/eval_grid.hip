@@ -9,7 +9,7 @@
 // is accumulated, the parameters of stage p+1 are derived and its table
 // windows stream from HBM/L2 straight into LDS (global_load_lds).
 //   prepare(p): Doppler factor g[s][k] (canonical FP64 order), G = g*T_sft,
-//      run-guard bounds, c[j][k] = f1_j*dt_k and c' = c + 1/(2G); then the
+//      run-guard bounds, c[j][k] = f1_j*dt_k and h = c*G + 1/2; then the
 //      exact bin range [lo, hi] of the tile per SFT.  The FP64 bin is monotone
 //      in each of f0, c and g and the tile is a Cartesian product, so lo/hi
 //      are bins of actual templates: the range check against the table is
@@ -18,9 +18,10 @@
 //      into LDS; columns are clamped into the table (a column outside it can
 //      only be read after a range error, which is reported).
 //   accumulate(p): for every f1 value each lane forms the estimate
-//      t~ = (f0 + c')*G of x + 1/2 for the first template of its run, takes
-//      B = floor(t~) and reads B, B+1, ..., B+L-1 from LDS (immediate
-//      offsets; consecutive lanes hit consecutive banks for odd L).
+//      t~ = f0*G + h (one fused multiply-add) of x + 1/2 for the first
+//      template of its run, takes B = floor(t~) and reads B, B+1, ...,
+//      B+L-1 from LDS (one address per run from a wave-uniform row base,
+//      immediate offsets; lanes hit distinct banks for odd L).
 //
 // Run guard.  |t~ - (x + 1/2)| and the rounding of every canonical evaluation
 // are bounded by the host, together with the grid's deviation from uniform
@@ -45,7 +46,7 @@ struct StageParams {
     double ulo[NW][KS];     // run-guard bounds on u
     double uhi[NW][KS];
     double c[JT][KS];       // canonical f1 * dt
-    double cp[NW][JT][KS];  // c + 1/(2G)
+    double h[NW][JT][KS];   // c * G + 1/2
     int lo[KS];             // first staged bin
 };
 
@@ -112,7 +113,7 @@ __device__ __forceinline__ bool prepare_stage(const EvalRun &r, const TileGeom &
     if (L > 1)
         for (int q = threadIdx.x; q < NW * JT * KS; q += nthreads) {
             const int sl = q / (JT * KS), jl = (q / KS) % JT, kk = q % KS;
-            if (kk < ks) P.cp[sl][jl][kk] = P.c[jl][kk] + 0.5 / P.G[sl][kk];
+            if (kk < ks) P.h[sl][jl][kk] = P.c[jl][kk] * P.G[sl][kk] + 0.5;
         }
     for (int kk = threadIdx.x; kk < ks; kk += nthreads) {
         double gmin = P.g[0][kk], gmax = gmin;
@@ -148,14 +149,22 @@ __device__ __forceinline__ void stage_windows(const EvalRun &r, int k0, int ks,
                                               const StageParams<L, JT, NW, KS> &P, float *wbuf)
 {
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int wtp = r.wtp;
     for (int kk = wave; kk < ks; kk += NW) {
         const float *row = r.power_w + (int64_t)(k0 + kk) * r.n_bins;
-        const int col0 = P.lo[kk] - r.first_bin + lane;
-        for (int x0 = 0; x0 < wtp; x0 += 64) {
-            const int col = min(max(col0 + x0, 0), r.n_bins - 1);
-            __builtin_amdgcn_global_load_lds(row + col, wbuf + kk * wtp + x0, 4, 0, 0);
+        const int c0 = __builtin_amdgcn_readfirstlane(P.lo[kk] - r.first_bin);
+        float *dst = wbuf + kk * wtp;
+        if (c0 >= 0 && c0 <= r.n_bins - wtp) {
+            // the whole window lies in the row: scalar base, one lane offset
+            const float *src = row + c0;
+            for (int x0 = 0; x0 < wtp; x0 += 64)
+                __builtin_amdgcn_global_load_lds(src + x0 + lane, dst + x0, 4, 0, 0);
+        } else {
+            for (int x0 = 0; x0 < wtp; x0 += 64) {
+                const int col = min(max(c0 + lane + x0, 0), r.n_bins - 1);
+                __builtin_amdgcn_global_load_lds(row + col, dst + x0, 4, 0, 0);
+            }
         }
     }
 }
@@ -165,7 +174,7 @@ __device__ __forceinline__ void eval_tile(const EvalRun &r, int64_t b, float *wi
                                           Shared<L, JT, NW, KS> &sh)
 {
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int nthreads = 64 * NW;
 
     const int tsky = (int)(b % r.tiles_sky);
@@ -239,16 +248,16 @@ __device__ __forceinline__ void eval_tile(const EvalRun &r, int64_t b, float *wi
                 bool ok = true;
 #pragma unroll
                 for (int jl = 0; jl < JT; ++jl) {
-                    const double a = f0_lane + P.cp[wave][jl][kk];
-                    const double t = a * G;
+                    const double t = fma(f0_lane, G, P.h[wave][jl][kk]);
                     B[jl] = (int)t;
                     const double u = __builtin_amdgcn_fract(t);
                     ok = ok && (u >= ulo) && (u < uhi);
                 }
                 if (wave_all(ok)) {
+                    const float *wk = wb + __builtin_amdgcn_readfirstlane(base);
 #pragma unroll
                     for (int jl = 0; jl < JT; ++jl) {
-                        const float *wp = wb + (base + B[jl]);
+                        const float *wp = wk + B[jl];
 #pragma unroll
                         for (int l = 0; l < L; ++l) acc[jl][l] += wp[l];
                     }
@@ -299,8 +308,11 @@ __device__ __forceinline__ void eval_tile(const EvalRun &r, int64_t b, float *wi
 // and the grid is a multiple of 8, so block b stays on XCD b % 8; each XCD is
 // given a contiguous range of tiles (f0 tile slowest, sky tile fastest) so
 // the table windows it stages stay in its L2.
-template <int L, int JT, int NW, int KS>
-__global__ __launch_bounds__(64 * NW) void eval_grid_kernel(EvalRun r)
+// OCC > 0 asks the compiler for at least OCC workgroups per CU (a register
+// budget of 512 / OCC per lane at four waves per workgroup); 0 leaves the
+// allocation free.
+template <int L, int JT, int NW, int KS, int OCC>
+__global__ __launch_bounds__(64 * NW, OCC > 0 ? OCC : 1) void eval_grid_kernel(EvalRun r)
 {
     extern __shared__ float win[];  // [2][KS][wtp]
     __shared__ Shared<L, JT, NW, KS> sh;
@@ -316,10 +328,10 @@ __global__ __launch_bounds__(64 * NW) void eval_grid_kernel(EvalRun r)
 // shared by every run of a batch until it is drained; each item is one tile of
 // one run's grid bank.  The queue counter is reset by the launcher's preceding
 // fill kernel, so the sequence can be captured in a HIP graph.
-template <int L, int JT, int NW, int KS>
-__global__ __launch_bounds__(64 * NW) void eval_batch_kernel(const EvalRun *runs,
-                                                             const int2 *items, int n_items,
-                                                             unsigned *counter)
+template <int L, int JT, int NW, int KS, int OCC>
+__global__ __launch_bounds__(64 * NW, OCC > 0 ? OCC : 1) void eval_batch_kernel(const EvalRun *runs,
+                                                                                const int2 *items, int n_items,
+                                                                                unsigned *counter)
 {
     extern __shared__ float win[];
     __shared__ Shared<L, JT, NW, KS> sh;
@@ -336,18 +348,18 @@ __global__ __launch_bounds__(64 * NW) void eval_batch_kernel(const EvalRun *runs
     }
 }
 
-template <int L, int JT, int NW, int KS>
+template <int L, int JT, int NW, int KS, int OCC>
 hipError_t launch_batch_t(const EvalRun *runs, const int2 *items, int n_items, int max_wtp,
                           unsigned *counter, int grid, hipStream_t s)
 {
     if (n_items <= 0) return hipSuccess;
     const size_t lds = (size_t)2 * KS * max_wtp * sizeof(float);
-    hipLaunchKernelGGL((eval_batch_kernel<L, JT, NW, KS>), dim3((unsigned)grid), dim3(64 * NW), lds,
+    hipLaunchKernelGGL((eval_batch_kernel<L, JT, NW, KS, OCC>), dim3((unsigned)grid), dim3(64 * NW), lds,
                        s, runs, items, n_items, counter);
     return hipGetLastError();
 }
 
-template <int L, int JT, int NW, int KS>
+template <int L, int JT, int NW, int KS, int OCC>
 hipError_t launch_t(const EvalRun &r, hipStream_t s)
 {
     const int64_t nt = (int64_t)r.tiles_f0 * r.tiles_f1 * r.tiles_sky;
@@ -357,7 +369,7 @@ hipError_t launch_t(const EvalRun &r, hipStream_t s)
     // every block's tiles on one XCD
     int64_t grid = nt < (1 << 22) ? nt : (1 << 22);
     if (grid > 8) grid &= ~(int64_t)7;
-    hipLaunchKernelGGL((eval_grid_kernel<L, JT, NW, KS>), dim3((unsigned)grid), dim3(64 * NW),
+    hipLaunchKernelGGL((eval_grid_kernel<L, JT, NW, KS, OCC>), dim3((unsigned)grid), dim3(64 * NW),
                        lds, s, r);
     return hipGetLastError();
 }
@@ -373,9 +385,12 @@ struct TileEntry {
     size_t static_lds;
 };
 
-#define FT_TILE(id, L, JT, NW, KS)                                                       \
-    {{id, "L" #L "_J" #JT "_W" #NW "_K" #KS, L, JT, NW, KS}, &launch_t<L, JT, NW, KS>, \
-     &launch_batch_t<L, JT, NW, KS>, sizeof(Shared<L, JT, NW, KS>)}
+#define FT_TILE(id, L, JT, NW, KS)                                                          \
+    {{id, "L" #L "_J" #JT "_W" #NW "_K" #KS, L, JT, NW, KS}, &launch_t<L, JT, NW, KS, 0>, \
+     &launch_batch_t<L, JT, NW, KS, 0>, sizeof(Shared<L, JT, NW, KS>)}
+#define FT_TILE_O(id, L, JT, NW, KS, OCC)                                                            \
+    {{id, "L" #L "_J" #JT "_W" #NW "_K" #KS "_O" #OCC, L, JT, NW, KS}, &launch_t<L, JT, NW, KS, OCC>, \
+     &launch_batch_t<L, JT, NW, KS, OCC>, sizeof(Shared<L, JT, NW, KS>)}
 
 const TileEntry kTiles[] = {
     FT_TILE(0, 1, 1, 4, 16),
@@ -395,6 +410,13 @@ const TileEntry kTiles[] = {
     FT_TILE(14, 1, 3, 4, 16),
     FT_TILE(15, 3, 3, 4, 16),
     FT_TILE(16, 5, 3, 4, 8),
+    FT_TILE_O(17, 5, 4, 4, 8, 4),
+    FT_TILE_O(18, 5, 4, 4, 8, 5),
+    FT_TILE(19, 3, 6, 4, 8),
+    FT_TILE_O(20, 3, 6, 4, 8, 4),
+    FT_TILE_O(21, 3, 6, 4, 8, 5),
+    FT_TILE_O(22, 5, 3, 4, 8, 4),
+    FT_TILE_O(23, 3, 4, 4, 8, 5),
 };
 
 }  // namespace
