@@ -31,14 +31,43 @@ def log(*a):
 
 
 def valu_ops_per_eval(tile_name):
-    """VALU lane-operations the grid kernel issues per template-SFT evaluation.
+    """VALU lane-operations the grid kernel needs per template-SFT evaluation.
 
-    A lane's run of L consecutive f0 costs 7 operations for the first bin
-    (FP64 add and multiply, conversion, fraction, 2 guard compares, 1 LDS
-    address) plus one FP32 accumulate per template; with L = 1 the canonical
-    bin costs 3 FP64 arithmetic, 1 add, 1 conversion, 1 address, 1 accumulate."""
+    A lane's run of L consecutive f0 costs 6 operations for the first bin (one
+    FP64 fused multiply-add, fraction, conversion, 2 guard compares, 1 LDS
+    address) plus one FP32 accumulate per template; with L = 1 the canonical bin
+    costs 3 FP64 arithmetic, 1 add, 1 conversion, 1 address, 1 accumulate."""
     L = int(tile_name.split("_")[0][1:]) if tile_name else 1
-    return (7.0 + L) / L if L > 1 else 7.0
+    return (6.0 + L) / L if L > 1 else 7.0
+
+
+def kernel_source_hash():
+    """SHA-256 of the grid kernel's source (the traffic figure below is only
+    valid for the kernel it was measured on)."""
+    import hashlib
+    with open(os.path.join(ROOT, "paper_2411_18370_amd", "csrc", "eval_grid.hip"), "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()
+
+
+def measured_traffic(tile_name):
+    """HBM bytes per launch of the grid kernel at the all-sky band, from the
+    committed rocprofv3 counter summary, or None when that summary was taken on
+    another kernel source or tile."""
+    path = os.path.join(ROOT, "profiles", "eval_grid_allsky_band_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith(" "):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.split()[0] if v.split() else ""
+    if kv.get("source_sha256") != kernel_source_hash() or kv.get("tile") != tile_name:
+        return None
+    try:
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(w, target_s):
@@ -170,7 +199,7 @@ def bench_surrogate(ft, synth, tau, n_train, n_test, log):
     t_labels = time.perf_counter() - t0
     log("surrogate: %d + %d labels in %.1f s (GPU %.1f s), detected fraction %.3f"
         % (n_train, n_test, t_labels, gpu_tr + gpu_te, y.mean()))
-    net, hist, t_train = surrogate.train(c, raw, y, epochs=20, batch=4096, lr=2e-3, seed=13)
+    net, hist, t_train = surrogate.train(c, raw, y, seed=13)
     t0 = time.perf_counter()
     p = net.predict(rt.astype(np.float32))
     t_pred = time.perf_counter() - t0
@@ -183,7 +212,8 @@ def bench_surrogate(ft, synth, tau, n_train, n_test, log):
     per_query = t_pred / n_test
     return {"workload": "labels on the all-sky SFT set (2 det x 5000 SFTs), local bank 5 f0 x "
                         "11 f1 x 16 sky, f ~ U[100,300] Hz, h0/sqrt(Sn) log-uniform [0.005, 0.1]; "
-                        "MLP 6-256-256-256-1 GELU/sigmoid, BF16 MFMA, 20 epochs",
+                        "MLP 6-256-256-256-1 GELU/sigmoid, BF16 MFMA; Adam, batch 2048, "
+                        "epochs x lr = %s" % (surrogate.SCHEDULE,),
             "tau_z": tau, "n_train": n_train, "n_test": n_test,
             "p_det_abs_err": cal["max_abs_err_amp_bins"],
             "p_det_abs_err_p_deciles": cal["max_abs_err_p_deciles"],
@@ -311,10 +341,12 @@ def main():
         "kernel_ms": k_ms,
         "select_ms": float(np.mean(sel_ms)),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tops/s",
-                     "frac": achieved / peak, "traffic": None,
+                     "frac": achieved / peak,
+                     "traffic": measured_traffic(tile_name) if args.n_sky == 100_000 else None,
                      "ops_per_eval": ops,
                      "note": "VALU lane-ops of the grid kernel per evaluation x evals / kernel "
-                             "time (HIP events on the library stream)"},
+                             "time (HIP events on the library stream); traffic = HBM bytes per "
+                             "launch from rocprofv3 FETCH_SIZE/WRITE_SIZE, copy-calibrated"},
         "autotune": {"tune_ms": tune_ms,
                      "timed": {e["name"]: e["evals_per_s"] for e in tune_rep},
                      "sample_evals": tune_rep[0]["sample_evals"] if tune_rep else 0},

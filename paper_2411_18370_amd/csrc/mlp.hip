@@ -189,38 +189,40 @@ __global__ void head_back_kernel(const float *dlogit, const float *params, const
     dzb[q] = (__bf16)d;
 }
 
-// Column sums g[off + o] = sum_b v[b][o] (bias gradients), and the output
-// layer's gradients g_W4[i] = sum_b dlogit[b] a3[b][i], g_b4 = sum_b dlogit[b].
-__global__ void colsum_kernel(const float *v, int rows, int cols, float *g)
+// Gradient reductions over the batch, in two deterministic stages: chunk c of
+// 64 rows writes part[c][q] = sum over its rows of term(b, q); then
+// out[q] = sum_c part[c][q] in chunk order.
+//   RED_COL:  term = v[b][q], q < 256 (bias gradients)
+//   RED_HEAD: term = dlogit[b] a3[b][q] for q < 256, dlogit[b] for q = 256
+//             (output-layer weights and bias)
+//   RED_W1:   term = dz1[b][q / 6] x[b][q % 6], q < 1536 (first-layer weights)
+enum { RED_COL = 0, RED_HEAD = 1, RED_W1 = 2 };
+
+template <int MODE>
+__global__ __launch_bounds__(256) void reduce_part_kernel(const float *v, const __bf16 *a3,
+                                                          const float *x, int bsz, int n_out,
+                                                          float *part)
 {
-    const int o = blockIdx.x * blockDim.x + threadIdx.x;
-    if (o >= cols) return;
-    float s = 0.f;
-    for (int b = 0; b < rows; ++b) s += v[(int64_t)b * cols + o];
-    g[o] = s;
+    const int c = blockIdx.x;
+    const int b0 = c * 64, b1 = min(b0 + 64, bsz);
+    for (int q = threadIdx.x; q < n_out; q += blockDim.x) {
+        float s = 0.f;
+        for (int b = b0; b < b1; ++b) {
+            if (MODE == RED_COL) s += v[(int64_t)b * H + q];
+            if (MODE == RED_HEAD) s += q < H ? v[b] * (float)a3[(int64_t)b * H + q] : v[b];
+            if (MODE == RED_W1) s += v[(int64_t)b * H + q / 6] * x[b * 6 + q % 6];
+        }
+        part[(int64_t)c * n_out + q] = s;
+    }
 }
 
-__global__ void head_grad_kernel(const float *dlogit, const __bf16 *a3, int bsz, float *g)
-{
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i > H) return;
-    float s = 0.f;
-    if (i < H)
-        for (int b = 0; b < bsz; ++b) s += dlogit[b] * (float)a3[(int64_t)b * H + i];
-    else
-        for (int b = 0; b < bsz; ++b) s += dlogit[b];
-    g[MLP_OFF_W4 + i] = s;
-}
-
-// g_W1[o][i] = sum_b dz1[b][o] x[b][i].
-__global__ void w1_grad_kernel(const float *dz1, const float *x, int bsz, float *g)
+__global__ void reduce_sum_kernel(const float *part, int n_chunks, int n_out, float *out)
 {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= H * 6) return;
-    const int o = q / 6, i = q % 6;
+    if (q >= n_out) return;
     float s = 0.f;
-    for (int b = 0; b < bsz; ++b) s += dz1[(int64_t)b * H + o] * x[b * 6 + i];
-    g[q] = s;
+    for (int c = 0; c < n_chunks; ++c) s += part[(int64_t)c * n_out + q];
+    out[q] = s;
 }
 
 // Adam (Kingma and Ba 2015) with bias correction; refreshes the BF16 copies of
@@ -249,6 +251,17 @@ __global__ void to_bf16_kernel(const float *src, __bf16 *dst, int n)
 }
 
 unsigned blocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+template <int MODE>
+void reduce_rows(const float *v, const __bf16 *a3, const float *x, int bsz, int n_out, float *part,
+                 float *out, hipStream_t s)
+{
+    const int n_chunks = (bsz + 63) / 64;
+    hipLaunchKernelGGL(reduce_part_kernel<MODE>, dim3(n_chunks), dim3(256), 0, s, v, a3, x, bsz, n_out,
+                       part);
+    hipLaunchKernelGGL(reduce_sum_kernel, dim3(blocks(n_out, 256)), dim3(256), 0, s, part, n_chunks, n_out,
+                       out);
+}
 
 }  // namespace
 
@@ -285,25 +298,24 @@ hipError_t mlp_backward(const MlpBufs &m, int bsz, hipStream_t s)
     const dim3 g2(H / 64, m_pad / 64);
     const dim3 gw(H / 64, H / 64);
     float *g = m.grad;
-    hipLaunchKernelGGL(head_grad_kernel, dim3(blocks(H + 1, 256)), dim3(256), 0, s, m.dlogit, m.a3,
-                       bsz, g);
+    reduce_rows<RED_HEAD>(m.dlogit, m.a3, nullptr, bsz, H + 1, m.part, g + MLP_OFF_W4, s);
     hipLaunchKernelGGL(head_back_kernel, dim3(blocks((int64_t)m_pad * H, 256)), dim3(256), 0, s,
                        m.dlogit, m.theta, m.z3, bsz, m_pad, m.dz3, m.dz3b);
     // layer 3: dW3 = dZ3^T A2, db3 = colsum dZ3, dZ2 = (dZ3 W3) * gelu'(Z2)
     hipLaunchKernelGGL((gemm_bf16_kernel<false, false, EPI_STORE>), gw, dim3(256), 0, s, m.dz3b,
                        m.a2, H, H, m_pad, H, H, nullptr, nullptr, g + MLP_OFF_W3, nullptr);
-    hipLaunchKernelGGL(colsum_kernel, dim3(1), dim3(H), 0, s, m.dz3, bsz, H, g + MLP_OFF_W3 + H * H);
+    reduce_rows<RED_COL>(m.dz3, nullptr, nullptr, bsz, H, m.part, g + MLP_OFF_W3 + H * H, s);
     hipLaunchKernelGGL((gemm_bf16_kernel<true, false, EPI_BWD>), g2, dim3(256), 0, s, m.dz3b, m.w3b,
                        m_pad, H, H, H, H, nullptr, m.z2, m.dz2, m.dz2b);
     // layer 2
     hipLaunchKernelGGL((gemm_bf16_kernel<false, false, EPI_STORE>), gw, dim3(256), 0, s, m.dz2b,
                        m.a1, H, H, m_pad, H, H, nullptr, nullptr, g + MLP_OFF_W2, nullptr);
-    hipLaunchKernelGGL(colsum_kernel, dim3(1), dim3(H), 0, s, m.dz2, bsz, H, g + MLP_OFF_W2 + H * H);
+    reduce_rows<RED_COL>(m.dz2, nullptr, nullptr, bsz, H, m.part, g + MLP_OFF_W2 + H * H, s);
     hipLaunchKernelGGL((gemm_bf16_kernel<true, false, EPI_BWD>), g2, dim3(256), 0, s, m.dz2b, m.w2b,
                        m_pad, H, H, H, H, nullptr, m.z1, m.dz1, m.dz1b);
     // layer 1
-    hipLaunchKernelGGL(w1_grad_kernel, dim3(blocks(H * 6, 256)), dim3(256), 0, s, m.dz1, m.x, bsz, g);
-    hipLaunchKernelGGL(colsum_kernel, dim3(1), dim3(H), 0, s, m.dz1, bsz, H, g + H * 6);
+    reduce_rows<RED_W1>(m.dz1, nullptr, m.x, bsz, H * 6, m.part, g, s);
+    reduce_rows<RED_COL>(m.dz1, nullptr, nullptr, bsz, H, m.part, g + H * 6, s);
     return hipGetLastError();
 }
 

@@ -62,14 +62,21 @@ def make_labels(ctx: ft.Context, base: synth.Workload, n: int, seed: int, tau: f
     return np.concatenate(raws), np.concatenate(labels), np.concatenate(zs), gpu_s
 
 
-def train(ctx: ft.Context, raw, y, epochs: int = 20, batch: int = 4096, lr: float = 2e-3,
-          seed: int = 0):
-    """Train the surrogate; returns (Mlp, per-epoch loss, seconds)."""
+SCHEDULE = ((8, 2e-3), (6, 6e-4), (6, 2e-4))
+
+
+def train(ctx: ft.Context, raw, y, schedule=SCHEDULE, batch: int = 2048, seed: int = 0):
+    """Train the surrogate with Adam in phases of (epochs, learning rate) (the
+    moments and step count carry over between phases); returns (Mlp, per-epoch
+    loss, seconds)."""
     net = ft.Mlp(ctx, FEAT_SHIFT, FEAT_SCALE, max_batch=max(batch, 8192), seed=seed)
+    raw = np.asarray(raw, np.float32)
+    y = np.asarray(y, np.float32)
+    hist = []
     t0 = time.perf_counter()
-    hist = net.train(np.asarray(raw, np.float32), np.asarray(y, np.float32), batch=batch,
-                     epochs=epochs, lr=lr, seed=seed + 1)
-    return net, hist, time.perf_counter() - t0
+    for i, (epochs, lr) in enumerate(schedule):
+        hist.extend(net.train(raw, y, batch=batch, epochs=epochs, lr=lr, seed=seed + 1 + i))
+    return net, np.asarray(hist), time.perf_counter() - t0
 
 
 def calibration(p_hat, y, raw, n_amp_bins: int = 20, n_p_bins: int = 10):
