@@ -234,8 +234,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batched-runs", type=int, default=512)
-    ap.add_argument("--surrogate-train", type=int, default=200_000)
-    ap.add_argument("--surrogate-test", type=int, default=50_000)
+    ap.add_argument("--surrogate-train", type=int, default=1_000_000)
+    ap.add_argument("--surrogate-test", type=int, default=100_000)
     ap.add_argument("--skip-extras", action="store_true",
                     help="plain workload only (no batched, precision or surrogate sections)")
     args = ap.parse_args()
