@@ -52,10 +52,33 @@ struct StageParams {
 
 template <int L, int JT, int NW, int KS>
 struct Shared {
+    static_assert(KS <= 64 && NW <= 16, "one lane per SFT of a stage");
     StageParams<L, JT, NW, KS> p[2];
     double f0[64 * L];
-    int tile_bad;
+    int lo_w[NW][KS], hi_w[NW][KS];  // per sky point bin range of the stage being prepared
+    double vdt[2][4 * KS];           // per stage: v/c [KS][3] then dt [KS], prefetched a stage ahead
+    double f1[JT], sky[NW][3];       // the tile's f1 values and sky points
 };
+
+// Asynchronous copy of the velocities and time offsets of SFTs [k0, k0 + ks)
+// into dst = [v (3 ks doubles) | pad | dt]: dwords 0..6 KS-1 hold v, dwords
+// 6 KS..8 KS-1 hold dt.  Issued by wave 0; lanes past the stage's SFTs copy
+// nothing.
+template <int KS>
+__device__ __forceinline__ void stage_vdt(const EvalRun &r, int k0, int ks, double *dst)
+{
+    const int lane = threadIdx.x & 63;
+    const uint32_t *v = (const uint32_t *)(r.v + 3 * (int64_t)k0);
+    const uint32_t *dt = (const uint32_t *)(r.dt + k0);
+#pragma unroll
+    for (int c = 0; c < (8 * KS + 63) / 64; ++c) {
+        const int q = c * 64 + lane;
+        const bool is_v = q < 6 * KS;
+        const int e = is_v ? q : q - 6 * KS;
+        if (q < 8 * KS && e < (is_v ? 6 * ks : 2 * ks))
+            __builtin_amdgcn_global_load_lds(is_v ? v + e : dt + e, (uint32_t *)dst + c * 64, 4, 0, 0);
+    }
+}
 
 __device__ __forceinline__ bool wave_all(bool p)
 {
@@ -65,10 +88,14 @@ __device__ __forceinline__ bool wave_all(bool p)
 // LDS read of the rare guard-fallback path.  A volatile access keeps the
 // compiler from merging it with the fast path's reads (which would force
 // computed addresses on the fast path instead of immediate offsets).
+typedef __attribute__((address_space(3))) const volatile float lds_vfloat;
+
 __device__ __forceinline__ float slow_read(const float *p)
 {
-    return *(const volatile float *)p;
+    return *(lds_vfloat *)p;
 }
+
+
 
 __device__ __forceinline__ void wait_loads()
 {
@@ -80,80 +107,85 @@ struct TileGeom {
     double f0min, f0max;
 };
 
-// Parameters and exact window of SFT stage [k0, k0 + ks) of a tile.  Two
-// barriers; returns false if the tile's window does not fit (flagged).
+// Parameters and exact window of SFT stage [k0, k0 + ks) of a tile, then the
+// asynchronous HBM/L2 -> LDS copies of its windows.  Every wave derives the
+// parameters of its own sky point (lane (jl, kk) for f1 value jl and SFT kk)
+// and that sky point's bin range over the tile's f0 and f1 values; one
+// barrier publishes the ranges, and every wave takes their union for each SFT
+// in lane kk (the FP64 bin is monotone in f0, c and g, so the union is the
+// exact range of the tile).  Returns false, in every wave, if the window does
+// not fit the LDS rows (flagged).
 template <int L, int JT, int NW, int KS>
-__device__ __forceinline__ bool prepare_stage(const EvalRun &r, const TileGeom &tg, int k0,
-                                              int ks, StageParams<L, JT, NW, KS> &P,
-                                              Shared<L, JT, NW, KS> &sh)
+__device__ __forceinline__ bool prepare_stage(const EvalRun &r, const TileGeom &tg, int stage,
+                                              StageParams<L, JT, NW, KS> &P,
+                                              Shared<L, JT, NW, KS> &sh, float *wbuf)
 {
-    const int nthreads = 64 * NW;
-    const double T = r.t_sft;
-    for (int q = threadIdx.x; q < NW * KS; q += nthreads) {
-        const int sl = q / KS, kk = q % KS;
-        if (kk < ks) {
-            const int s = min(tg.s_base + sl, tg.s_last);
-            const double *vk = r.v + 3 * (int64_t)(k0 + kk);
-            const double *n = r.sky_tile + 3 * (int64_t)s;
-            const double g = doppler_factor(vk[0], vk[1], vk[2], n[0], n[1], n[2]);
-            P.g[sl][kk] = g;
-            P.G[sl][kk] = g * T;
-            if (L > 1) {
-                const double eL = (double)(L - 1) * (r.dT * g - 1.0);
-                P.ulo[sl][kk] = r.eta + fmax(0.0, -eL);
-                P.uhi[sl][kk] = (1.0 - r.eta) - fmax(0.0, eL);
-            }
-        }
-    }
-    for (int q = threadIdx.x; q < JT * KS; q += nthreads) {
-        const int jl = q / KS, kk = q % KS;
-        if (kk < ks) P.c[jl][kk] = r.f1[min(tg.j_base + jl, tg.j_last)] * r.dt[k0 + kk];
-    }
-    __syncthreads();
-    if (L > 1)
-        for (int q = threadIdx.x; q < NW * JT * KS; q += nthreads) {
-            const int sl = q / (JT * KS), jl = (q / KS) % JT, kk = q % KS;
-            if (kk < ks) P.h[sl][jl][kk] = P.c[jl][kk] * P.G[sl][kk] + 0.5;
-        }
-    for (int kk = threadIdx.x; kk < ks; kk += nthreads) {
-        double gmin = P.g[0][kk], gmax = gmin;
-#pragma unroll
-        for (int sl = 1; sl < NW; ++sl) {
-            gmin = fmin(gmin, P.g[sl][kk]);
-            gmax = fmax(gmax, P.g[sl][kk]);
-        }
-        double cmin = P.c[0][kk], cmax = cmin;
-#pragma unroll
-        for (int jl = 1; jl < JT; ++jl) {
-            cmin = fmin(cmin, P.c[jl][kk]);
-            cmax = fmax(cmax, P.c[jl][kk]);
-        }
-        const int lo = bin_fp64(tg.f0min, cmin, gmin, T);
-        const int hi = bin_fp64(tg.f0max, cmax, gmax, T);
-        uint32_t bad = 0;
-        if (lo < r.first_bin || hi - r.first_bin >= r.n_bins) bad |= ERR_RANGE;
-        if (hi - lo + L > r.wt) bad |= ERR_WINDOW;
-        if (bad) {
-            atomicOr(r.err, bad);
-            if (bad & ERR_WINDOW) sh.tile_bad = 1;
-        }
-        P.lo[kk] = lo;
-    }
-    __syncthreads();
-    return sh.tile_bad == 0;
-}
-
-// Issue the HBM/L2 -> LDS copies of a stage's windows (asynchronous).
-template <int L, int JT, int NW, int KS>
-__device__ __forceinline__ void stage_windows(const EvalRun &r, int k0, int ks,
-                                              const StageParams<L, JT, NW, KS> &P, float *wbuf)
-{
+    const int k0 = stage * KS;
+    const int ks = min(KS, r.n_sft - k0);
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const double T = r.t_sft;
+    const double nx = sh.sky[wave][0], ny = sh.sky[wave][1], nz = sh.sky[wave][2];
+    const double *vdt = sh.vdt[stage & 1];
+    for (int q = lane; q < JT * KS; q += 64) {
+        const int jl = q / KS, kk = q % KS;
+        if (kk >= ks) continue;
+        const double *vk = vdt + 3 * kk;
+        const double g = doppler_factor(vk[0], vk[1], vk[2], nx, ny, nz);
+        const double G = g * T;
+        const double dt = vdt[3 * KS + kk];
+        const double c = sh.f1[jl] * dt;
+        if (L > 1) P.h[wave][jl][kk] = c * G + 0.5;
+        if (wave == 0) P.c[jl][kk] = c;
+        if (jl == 0) {
+            P.g[wave][kk] = g;
+            P.G[wave][kk] = G;
+            if (L > 1) {
+                const double eL = (double)(L - 1) * (r.dT * g - 1.0);
+                P.ulo[wave][kk] = r.eta + fmax(0.0, -eL);
+                P.uhi[wave][kk] = (1.0 - r.eta) - fmax(0.0, eL);
+            }
+            double cmin = c, cmax = c;
+#pragma unroll
+            for (int j = 1; j < JT; ++j) {
+                const double cj = sh.f1[j] * dt;
+                cmin = fmin(cmin, cj);
+                cmax = fmax(cmax, cj);
+            }
+            sh.lo_w[wave][kk] = bin_fp64(tg.f0min, cmin, g, T);
+            sh.hi_w[wave][kk] = bin_fp64(tg.f0max, cmax, g, T);
+        }
+    }
+    __syncthreads();
+    int lo = 0;
+    bool bad = false;
+    if (lane < ks) {
+        lo = sh.lo_w[0][lane];
+        int hi = sh.hi_w[0][lane];
+#pragma unroll
+        for (int w = 1; w < NW; ++w) {
+            lo = min(lo, sh.lo_w[w][lane]);
+            hi = max(hi, sh.hi_w[w][lane]);
+        }
+        uint32_t err = 0;
+        if (lo < r.first_bin || hi - r.first_bin >= r.n_bins) err |= ERR_RANGE;
+        if (hi - lo + L > r.wt) err |= ERR_WINDOW;
+        if (wave == 0) {
+            P.lo[lane] = lo;
+            if (err) atomicOr(r.err, err);
+        }
+        bad = (err & ERR_WINDOW) != 0;
+    }
+    if (!wave_all(!bad)) return false;
+
+    // the next stage's velocities and time offsets (read by its preparation,
+    // after the end-of-stage wait)
+    if (wave == 0 && k0 + KS < r.n_sft)
+        stage_vdt<KS>(r, k0 + KS, min(KS, r.n_sft - k0 - KS), sh.vdt[(stage + 1) & 1]);
     const int wtp = r.wtp;
     for (int kk = wave; kk < ks; kk += NW) {
         const float *row = r.power_w + (int64_t)(k0 + kk) * r.n_bins;
-        const int c0 = __builtin_amdgcn_readfirstlane(P.lo[kk] - r.first_bin);
+        const int c0 = __builtin_amdgcn_readlane(lo, kk) - r.first_bin;
         float *dst = wbuf + kk * wtp;
         if (c0 >= 0 && c0 <= r.n_bins - wtp) {
             // the whole window lies in the row: scalar base, one lane offset
@@ -161,15 +193,137 @@ __device__ __forceinline__ void stage_windows(const EvalRun &r, int k0, int ks,
             for (int x0 = 0; x0 < wtp; x0 += 64)
                 __builtin_amdgcn_global_load_lds(src + x0 + lane, dst + x0, 4, 0, 0);
         } else {
+            // columns clamped into the row (only after a reported range error
+            // can a clamped column be read)
             for (int x0 = 0; x0 < wtp; x0 += 64) {
                 const int col = min(max(c0 + lane + x0, 0), r.n_bins - 1);
                 __builtin_amdgcn_global_load_lds(row + col, dst + x0, 4, 0, 0);
             }
         }
     }
+    return true;
 }
 
+// Blocked summation: at the end of every aligned block of SUM_BLOCK SFTs the
+// FP32 block sums move into the FP64 totals.
+template <int L, int JT>
+__device__ __forceinline__ void flush_block(const EvalRun &r, int k, float (&acc)[JT][L],
+                                            double (&tot)[JT][L])
+{
+    if (r.sum_mode == FT_SUM_BLOCKED && ((k + 1) & (SUM_BLOCK - 1)) == 0) {
+#pragma unroll
+        for (int j = 0; j < JT; ++j)
+#pragma unroll
+            for (int l = 0; l < L; ++l) {
+                tot[j][l] += (double)acc[j][l];
+                acc[j][l] = 0.f;
+            }
+    }
+}
+
+// Run estimates of SFT step kk from its parameters (already in registers):
+// B[jl] = floor(t~) and whether every run of the lane passes the guard.
+template <int JT>
+__device__ __forceinline__ bool run_bins(double f0_lane, double G, double ulo, double uhi,
+                                         const double (&h)[JT], int (&B)[JT])
+{
+    bool ok = true;
+#pragma unroll
+    for (int jl = 0; jl < JT; ++jl) {
+        const double t = fma(f0_lane, G, h[jl]);
+        B[jl] = (int)t;
+        const double u = __builtin_amdgcn_fract(t);
+        ok = ok && (u >= ulo) && (u < uhi);
+    }
+    return ok;
+}
+
+// Guard fallback of one SFT step: canonical FP64 bins for every template of
+// the lane's runs.
 template <int L, int JT, int NW, int KS>
+__device__ __forceinline__ void step_canonical(const StageParams<L, JT, NW, KS> &P,
+                                               const Shared<L, JT, NW, KS> &sh, const TileGeom &tg,
+                                               const float *wb, int base, int kk, int wave, int lane,
+                                               double T, float (&acc)[JT][L])
+{
+    const double g = P.g[wave][kk];
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+        const double f0l = sh.f0[min(lane * L + l, tg.n_in - 1)];
+#pragma unroll
+        for (int jl = 0; jl < JT; ++jl) acc[jl][l] += slow_read(wb + (base + bin_fp64(f0l, P.c[jl][kk], g, T)));
+    }
+}
+
+// Software-pipelined accumulation of one stage (run-length tiles).  Step kk
+// reads the parameters of step kk+1 from LDS first, then issues its own
+// gathers, then forms the bins of step kk+1 while those gathers are in flight,
+// and only then adds the gathered values -- or, if some run of the wave failed
+// the guard, replaces them by the values at the canonical bins first.  LDS
+// returns in order, so the parameter reads never wait behind the gathers.
+// The gathers are issued before the guard verdict: an estimate is within one
+// bin of the canonical bin, the LDS rows carry that margin, and reads past
+// the last row stay inside the workgroup's LDS allocation.
+template <int L, int JT, int NW, int KS>
+__device__ __forceinline__ void accumulate_pipelined(const EvalRun &r, const StageParams<L, JT, NW, KS> &P,
+                                                     const Shared<L, JT, NW, KS> &sh, const TileGeom &tg,
+                                                     const float *wb, int wtp, int k0, int ks, int wave,
+                                                     int lane, double f0_lane, float (&acc)[JT][L],
+                                                     double (&tot)[JT][L])
+{
+    const double T = r.t_sft;
+    double h[JT];
+#pragma unroll
+    for (int jl = 0; jl < JT; ++jl) h[jl] = P.h[wave][jl][0];
+    int B[JT];
+    bool ok = wave_all(run_bins<JT>(f0_lane, P.G[wave][0], P.ulo[wave][0], P.uhi[wave][0], h, B));
+    int lo = __builtin_amdgcn_readfirstlane(P.lo[0]);
+    for (int kk = 0; kk < ks; ++kk) {
+        const int kn = min(kk + 1, ks - 1);
+        const double Gn = P.G[wave][kn], ulon = P.ulo[wave][kn], uhin = P.uhi[wave][kn];
+        double hn[JT];
+#pragma unroll
+        for (int jl = 0; jl < JT; ++jl) hn[jl] = P.h[wave][jl][kn];
+        const int lon = P.lo[kn];
+        const int base = kk * wtp - lo;
+        const float *wk = wb + base;
+        float v[JT][L];
+#pragma unroll
+        for (int jl = 0; jl < JT; ++jl)
+#pragma unroll
+            for (int l = 0; l < L; ++l) v[jl][l] = wk[B[jl] + l];
+        int Bn[JT];
+        const bool okn = run_bins<JT>(f0_lane, Gn, ulon, uhin, hn, Bn);
+        // keep the next bins ahead of the adds (the compiler would otherwise
+        // sink them past the branch, after the wait for the gathers)
+        const int fast_next = wave_all(okn) ? 1 : 0;
+#pragma unroll
+        for (int jl = 0; jl < JT; ++jl) asm volatile("" ::"v"(Bn[jl]));
+        asm volatile("" ::"s"(fast_next));
+        if (!ok) {
+            // rare: some lane is within the guard margin of a bin edge
+            const double g = P.g[wave][kk];
+#pragma unroll
+            for (int l = 0; l < L; ++l) {
+                const double f0l = sh.f0[min(lane * L + l, tg.n_in - 1)];
+#pragma unroll
+                for (int jl = 0; jl < JT; ++jl)
+                    v[jl][l] = slow_read(wb + (base + bin_fp64(f0l, P.c[jl][kk], g, T)));
+            }
+        }
+#pragma unroll
+        for (int jl = 0; jl < JT; ++jl)
+#pragma unroll
+            for (int l = 0; l < L; ++l) acc[jl][l] += v[jl][l];
+        flush_block<L, JT>(r, k0 + kk, acc, tot);
+#pragma unroll
+        for (int jl = 0; jl < JT; ++jl) B[jl] = Bn[jl];
+        ok = fast_next != 0;
+        lo = __builtin_amdgcn_readfirstlane(lon);  // after the adds' wait: no LDS read pending into the next step
+    }
+}
+
+template <int L, int JT, int NW, int KS, bool PIPE>
 __device__ __forceinline__ void eval_tile(const EvalRun &r, int64_t b, float *win,
                                           Shared<L, JT, NW, KS> &sh)
 {
@@ -199,10 +353,17 @@ __device__ __forceinline__ void eval_tile(const EvalRun &r, int64_t b, float *wi
     const int wtp = r.wtp;
 
     __syncthreads();  // the previous tile's threads are done with the shared state
-    if (threadIdx.x == 0) sh.tile_bad = 0;
     if (L > 1)
         for (int q = threadIdx.x; q < 64 * L; q += nthreads)
             sh.f0[q] = r.f0[tg.i_base + min(q, tg.n_in - 1)];
+    if (threadIdx.x < JT) sh.f1[threadIdx.x] = r.f1[min(tg.j_base + (int)threadIdx.x, tg.j_last)];
+    if (threadIdx.x < 3 * NW) {
+        const int sl = threadIdx.x / 3, d = threadIdx.x % 3;
+        sh.sky[sl][d] = r.sky_tile[3 * (int64_t)min(tg.s_base + sl, tg.s_last) + d];
+    }
+    if (wave == 0) stage_vdt<KS>(r, 0, min(KS, r.n_sft), sh.vdt[0]);
+    wait_loads();
+    __syncthreads();
 
     float acc[JT][L];
     double tot[JT][L];
@@ -215,8 +376,7 @@ __device__ __forceinline__ void eval_tile(const EvalRun &r, int64_t b, float *wi
         }
 
     const int n_stage = (r.n_sft + KS - 1) / KS;
-    if (!prepare_stage<L, JT, NW, KS>(r, tg, 0, min(KS, r.n_sft), sh.p[0], sh)) return;
-    stage_windows<L, JT, NW, KS>(r, 0, min(KS, r.n_sft), sh.p[0], win);
+    if (!prepare_stage<L, JT, NW, KS>(r, tg, 0, sh.p[0], sh, win)) return;
     wait_loads();
     __syncthreads();
 
@@ -225,13 +385,14 @@ __device__ __forceinline__ void eval_tile(const EvalRun &r, int64_t b, float *wi
         const int ks = min(KS, r.n_sft - k0);
         const int cur = p & 1;
         if (p + 1 < n_stage) {
-            const int k1 = k0 + KS;
-            const int ks1 = min(KS, r.n_sft - k1);
-            if (!prepare_stage<L, JT, NW, KS>(r, tg, k1, ks1, sh.p[cur ^ 1], sh)) return;
-            stage_windows<L, JT, NW, KS>(r, k1, ks1, sh.p[cur ^ 1], win + (cur ^ 1) * KS * wtp);
+            if (!prepare_stage<L, JT, NW, KS>(r, tg, p + 1, sh.p[cur ^ 1], sh, win + (cur ^ 1) * KS * wtp))
+                return;
         }
         const StageParams<L, JT, NW, KS> &P = sh.p[cur];
         const float *wb = win + cur * KS * wtp;
+        if (L > 1 && PIPE) {
+            accumulate_pipelined<L, JT, NW, KS>(r, P, sh, tg, wb, wtp, k0, ks, wave, lane, f0_lane, acc, tot);
+        } else
         for (int kk = 0; kk < ks; ++kk) {
             const int base = kk * wtp - P.lo[kk];
             if (L == 1) {
@@ -311,7 +472,7 @@ __device__ __forceinline__ void eval_tile(const EvalRun &r, int64_t b, float *wi
 // OCC > 0 asks the compiler for at least OCC workgroups per CU (a register
 // budget of 512 / OCC per lane at four waves per workgroup); 0 leaves the
 // allocation free.
-template <int L, int JT, int NW, int KS, int OCC>
+template <int L, int JT, int NW, int KS, int OCC, bool PIPE>
 __global__ __launch_bounds__(64 * NW, OCC > 0 ? OCC : 1) void eval_grid_kernel(EvalRun r)
 {
     extern __shared__ float win[];  // [2][KS][wtp]
@@ -320,7 +481,7 @@ __global__ __launch_bounds__(64 * NW, OCC > 0 ? OCC : 1) void eval_grid_kernel(E
     const int64_t full = nt - (nt & 7);
     for (int64_t b0 = blockIdx.x; b0 < nt; b0 += gridDim.x) {
         const int64_t b = b0 < full ? (b0 & 7) * (full >> 3) + (b0 >> 3) : b0;
-        eval_tile<L, JT, NW, KS>(r, b, win, sh);
+        eval_tile<L, JT, NW, KS, PIPE>(r, b, win, sh);
     }
 }
 
@@ -328,7 +489,7 @@ __global__ __launch_bounds__(64 * NW, OCC > 0 ? OCC : 1) void eval_grid_kernel(E
 // shared by every run of a batch until it is drained; each item is one tile of
 // one run's grid bank.  The queue counter is reset by the launcher's preceding
 // fill kernel, so the sequence can be captured in a HIP graph.
-template <int L, int JT, int NW, int KS, int OCC>
+template <int L, int JT, int NW, int KS, int OCC, bool PIPE>
 __global__ __launch_bounds__(64 * NW, OCC > 0 ? OCC : 1) void eval_batch_kernel(const EvalRun *runs,
                                                                                 const int2 *items, int n_items,
                                                                                 unsigned *counter)
@@ -344,22 +505,22 @@ __global__ __launch_bounds__(64 * NW, OCC > 0 ? OCC : 1) void eval_batch_kernel(
         if (item >= n_items) break;
         const int2 it = items[item];
         const EvalRun r = runs[__builtin_amdgcn_readfirstlane(it.x)];
-        eval_tile<L, JT, NW, KS>(r, __builtin_amdgcn_readfirstlane(it.y), win, sh);
+        eval_tile<L, JT, NW, KS, PIPE>(r, __builtin_amdgcn_readfirstlane(it.y), win, sh);
     }
 }
 
-template <int L, int JT, int NW, int KS, int OCC>
+template <int L, int JT, int NW, int KS, int OCC, bool PIPE>
 hipError_t launch_batch_t(const EvalRun *runs, const int2 *items, int n_items, int max_wtp,
                           unsigned *counter, int grid, hipStream_t s)
 {
     if (n_items <= 0) return hipSuccess;
     const size_t lds = (size_t)2 * KS * max_wtp * sizeof(float);
-    hipLaunchKernelGGL((eval_batch_kernel<L, JT, NW, KS, OCC>), dim3((unsigned)grid), dim3(64 * NW), lds,
+    hipLaunchKernelGGL((eval_batch_kernel<L, JT, NW, KS, OCC, PIPE>), dim3((unsigned)grid), dim3(64 * NW), lds,
                        s, runs, items, n_items, counter);
     return hipGetLastError();
 }
 
-template <int L, int JT, int NW, int KS, int OCC>
+template <int L, int JT, int NW, int KS, int OCC, bool PIPE>
 hipError_t launch_t(const EvalRun &r, hipStream_t s)
 {
     const int64_t nt = (int64_t)r.tiles_f0 * r.tiles_f1 * r.tiles_sky;
@@ -369,7 +530,7 @@ hipError_t launch_t(const EvalRun &r, hipStream_t s)
     // every block's tiles on one XCD
     int64_t grid = nt < (1 << 22) ? nt : (1 << 22);
     if (grid > 8) grid &= ~(int64_t)7;
-    hipLaunchKernelGGL((eval_grid_kernel<L, JT, NW, KS, OCC>), dim3((unsigned)grid), dim3(64 * NW),
+    hipLaunchKernelGGL((eval_grid_kernel<L, JT, NW, KS, OCC, PIPE>), dim3((unsigned)grid), dim3(64 * NW),
                        lds, s, r);
     return hipGetLastError();
 }
@@ -385,12 +546,15 @@ struct TileEntry {
     size_t static_lds;
 };
 
-#define FT_TILE(id, L, JT, NW, KS)                                                          \
-    {{id, "L" #L "_J" #JT "_W" #NW "_K" #KS, L, JT, NW, KS}, &launch_t<L, JT, NW, KS, 0>, \
-     &launch_batch_t<L, JT, NW, KS, 0>, sizeof(Shared<L, JT, NW, KS>)}
-#define FT_TILE_O(id, L, JT, NW, KS, OCC)                                                            \
-    {{id, "L" #L "_J" #JT "_W" #NW "_K" #KS "_O" #OCC, L, JT, NW, KS}, &launch_t<L, JT, NW, KS, OCC>, \
-     &launch_batch_t<L, JT, NW, KS, OCC>, sizeof(Shared<L, JT, NW, KS>)}
+#define FT_TILE(id, L, JT, NW, KS)                                                                 \
+    {{id, "L" #L "_J" #JT "_W" #NW "_K" #KS, L, JT, NW, KS}, &launch_t<L, JT, NW, KS, 0, false>,        \
+     &launch_batch_t<L, JT, NW, KS, 0, false>, sizeof(Shared<L, JT, NW, KS>)}
+#define FT_TILE_O(id, L, JT, NW, KS, OCC)                                                          \
+    {{id, "L" #L "_J" #JT "_W" #NW "_K" #KS "_O" #OCC, L, JT, NW, KS}, &launch_t<L, JT, NW, KS, OCC, false>, \
+     &launch_batch_t<L, JT, NW, KS, OCC, false>, sizeof(Shared<L, JT, NW, KS>)}
+#define FT_TILE_P(id, L, JT, NW, KS, OCC)                                                           \
+    {{id, "L" #L "_J" #JT "_W" #NW "_K" #KS "_O" #OCC "_P", L, JT, NW, KS}, &launch_t<L, JT, NW, KS, OCC, true>, \
+     &launch_batch_t<L, JT, NW, KS, OCC, true>, sizeof(Shared<L, JT, NW, KS>)}
 
 const TileEntry kTiles[] = {
     FT_TILE(0, 1, 1, 4, 16),
@@ -417,6 +581,10 @@ const TileEntry kTiles[] = {
     FT_TILE_O(21, 3, 6, 4, 8, 5),
     FT_TILE_O(22, 5, 3, 4, 8, 4),
     FT_TILE_O(23, 3, 4, 4, 8, 5),
+    FT_TILE_P(24, 5, 4, 4, 8, 4),
+    FT_TILE_P(25, 5, 3, 4, 8, 4),
+    FT_TILE_P(26, 3, 4, 4, 8, 4),
+    FT_TILE_P(27, 5, 4, 4, 8, 3),
 };
 
 }  // namespace
