@@ -238,21 +238,31 @@ __device__ __forceinline__ bool run_bins(double f0_lane, double G, double ulo, d
     return ok;
 }
 
-// Guard fallback of one SFT step: canonical FP64 bins for every template of
-// the lane's runs.
+// Guard fallback of one SFT step: the values at the canonical FP64 bins of
+// every template of the lane's runs.  All parameters are read first and all
+// bins formed before the table reads are issued, so the reads go out back to
+// back (one LDS round trip rather than one per template).
 template <int L, int JT, int NW, int KS>
-__device__ __forceinline__ void step_canonical(const StageParams<L, JT, NW, KS> &P,
-                                               const Shared<L, JT, NW, KS> &sh, const TileGeom &tg,
-                                               const float *wb, int base, int kk, int wave, int lane,
-                                               double T, float (&acc)[JT][L])
+__device__ __forceinline__ void canonical_values(const StageParams<L, JT, NW, KS> &P,
+                                                 const Shared<L, JT, NW, KS> &sh, const TileGeom &tg,
+                                                 const float *wb, int base, int kk, int wave, int lane,
+                                                 double T, float (&out)[JT][L])
 {
     const double g = P.g[wave][kk];
+    double c[JT], f0l[L];
 #pragma unroll
-    for (int l = 0; l < L; ++l) {
-        const double f0l = sh.f0[min(lane * L + l, tg.n_in - 1)];
+    for (int jl = 0; jl < JT; ++jl) c[jl] = P.c[jl][kk];
 #pragma unroll
-        for (int jl = 0; jl < JT; ++jl) acc[jl][l] += slow_read(wb + (base + bin_fp64(f0l, P.c[jl][kk], g, T)));
-    }
+    for (int l = 0; l < L; ++l) f0l[l] = sh.f0[min(lane * L + l, tg.n_in - 1)];
+    int idx[JT][L];
+#pragma unroll
+    for (int jl = 0; jl < JT; ++jl)
+#pragma unroll
+        for (int l = 0; l < L; ++l) idx[jl][l] = base + bin_fp64(f0l[l], c[jl], g, T);
+#pragma unroll
+    for (int jl = 0; jl < JT; ++jl)
+#pragma unroll
+        for (int l = 0; l < L; ++l) out[jl][l] = slow_read(wb + idx[jl][l]);
 }
 
 // Software-pipelined accumulation of one stage (run-length tiles).  Step kk
@@ -300,17 +310,8 @@ __device__ __forceinline__ void accumulate_pipelined(const EvalRun &r, const Sta
 #pragma unroll
         for (int jl = 0; jl < JT; ++jl) asm volatile("" ::"v"(Bn[jl]));
         asm volatile("" ::"s"(fast_next));
-        if (!ok) {
-            // rare: some lane is within the guard margin of a bin edge
-            const double g = P.g[wave][kk];
-#pragma unroll
-            for (int l = 0; l < L; ++l) {
-                const double f0l = sh.f0[min(lane * L + l, tg.n_in - 1)];
-#pragma unroll
-                for (int jl = 0; jl < JT; ++jl)
-                    v[jl][l] = slow_read(wb + (base + bin_fp64(f0l, P.c[jl][kk], g, T)));
-            }
-        }
+        if (!ok)  // rare: some lane is within the guard margin of a bin edge
+            canonical_values<L, JT, NW, KS>(P, sh, tg, wb, base, kk, wave, lane, T, v);
 #pragma unroll
         for (int jl = 0; jl < JT; ++jl)
 #pragma unroll
@@ -424,14 +425,12 @@ __device__ __forceinline__ void eval_tile(const EvalRun &r, int64_t b, float *wi
                     }
                 } else {
                     // rare: some lane is within the guard margin of a bin edge
-                    const double g = P.g[wave][kk];
+                    float v[JT][L];
+                    canonical_values<L, JT, NW, KS>(P, sh, tg, wb, base, kk, wave, lane, T, v);
 #pragma unroll
-                    for (int l = 0; l < L; ++l) {
-                        const double f0l = sh.f0[min(lane * L + l, tg.n_in - 1)];
+                    for (int jl = 0; jl < JT; ++jl)
 #pragma unroll
-                        for (int jl = 0; jl < JT; ++jl)
-                            acc[jl][l] += slow_read(wb + (base + bin_fp64(f0l, P.c[jl][kk], g, T)));
-                    }
+                        for (int l = 0; l < L; ++l) acc[jl][l] += v[jl][l];
                 }
             }
             if (r.sum_mode == FT_SUM_BLOCKED && ((k0 + kk + 1) & (SUM_BLOCK - 1)) == 0) {
