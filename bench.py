@@ -354,6 +354,21 @@ def main():
         "injections": recovered,
         "tau_z": tau,
     }
+    # achievable ceiling of the gather-accumulate pattern of the chosen tile
+    # (same block size, LDS row stride and register budget, no index work)
+    wtp = (info.window + 63) // 64 * 64
+    probe = c.probe_lds_gather(info.tile, wtp)
+    achieved_evals = evals / (k_ms * 1e-3)
+    lds_nominal = 256 * 128 * 2.4e9  # bytes/s: 128 B per clock per CU
+    line["lds_gather"] = {
+        "achieved_evals_per_s": achieved_evals, "probe_evals_per_s": probe,
+        "frac_of_probe": achieved_evals / probe,
+        "achieved_TBps": 4.0 * achieved_evals / 1e12, "nominal_TBps": lds_nominal / 1e12,
+        "frac_of_nominal": 4.0 * achieved_evals / lds_nominal,
+        "note": "4 B of LDS gathered per evaluation; probe = the tile's gather-accumulate "
+                "pattern alone (ft_probe_lds_gather) at the same occupancy"}
+    log("LDS gather: kernel %.3g evals/s, probe %.3g evals/s (%.0f%%)"
+        % (achieved_evals, probe, 100 * achieved_evals / probe))
     c.close()
     if not args.skip_extras:
         line["batched"] = bench_batched(ft, synth, args.batched_runs, log)

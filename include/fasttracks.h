@@ -383,6 +383,18 @@ ft_status ft_tune_report(ft_ctx ctx, ft_tune_entry *out, int32_t cap, int32_t *n
 /* Forget every cached tile choice of the context. */
 ft_status ft_tune_clear(ft_ctx ctx);
 
+/*
+ * Achievable rate of the grid kernel's gather-accumulate pattern for `tile`
+ * (template-SFT evaluations per second): the tile's lanes gather JT runs of L
+ * consecutive values per SFT step from an LDS window of row stride wtp floats
+ * (0: the smallest multiple of 64 that holds the pattern) and add them into
+ * FP32 accumulators flushed to FP64 every 32 steps, with no index arithmetic,
+ * window staging or guard, at the tile's block size, LDS and register budget.
+ * Timed with HIP events over 2048 workgroups x 2048 steps; synchronises.  The
+ * denominator of the kernel's achieved fraction of its LDS gather ceiling.
+ */
+ft_status ft_probe_lds_gather(ft_ctx ctx, int32_t tile, int32_t wtp, double *evals_per_s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -132,6 +132,9 @@ struct ft_ctx_s {
     int last_tile = -1;
     hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
 
+    float *d_probe = nullptr;  // output of the LDS gather probe
+    size_t cap_probe = 0;
+
     // autotuner: shape class -> tile id (0-based), and the last tuning's timings
     std::map<std::vector<int64_t>, int> tune_cache;
     std::vector<ft_tune_entry> tune_log;
@@ -353,6 +356,34 @@ ft_status ft_tune_report(ft_ctx c, ft_tune_entry *out, int32_t cap, int32_t *n_o
     return FT_OK;
 }
 
+ft_status ft_probe_lds_gather(ft_ctx c, int32_t tile, int32_t wtp, double *evals_per_s)
+{
+    if (!c) return FT_E_INVALID;
+    c->err.clear();
+    if (!evals_per_s) return fail(c, FT_E_INVALID, "evals_per_s must be non-null");
+    if (tile < 1 || tile > tile_count()) return fail(c, FT_E_INVALID, "unknown tile %d", tile);
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, FT_E_DEVICE, "hipSetDevice");
+    const TileCfg &cfg = tile_cfg(tile - 1);
+    const int min_wtp = (64 * cfg.L + 3 * cfg.JT + 8 + 32 + 63) / 64 * 64;
+    if (wtp == 0) wtp = min_wtp;
+    if (wtp < min_wtp || wtp % 64 != 0 || 2.0 * cfg.KS * wtp * 4.0 + (double)tile_static_lds(tile - 1) > 150.0 * 1024.0)
+        return fail(c, FT_E_INVALID, "wtp must be a multiple of 64 in [%d, LDS budget]", min_wtp);
+    const int n_blocks = 2048, n_step = 2048;
+    const size_t n_out = (size_t)n_blocks * 64 * cfg.NW;
+    hipError_t e = ensure(&c->d_probe, &c->cap_probe, n_out);
+    if (e == hipSuccess) e = launch_lds_probe(cfg, n_blocks, 64, wtp, c->d_probe, c->stream);  // warm-up
+    if (e == hipSuccess) e = hipEventRecord(c->ev[0], c->stream);
+    if (e == hipSuccess) e = launch_lds_probe(cfg, n_blocks, n_step, wtp, c->d_probe, c->stream);
+    if (e == hipSuccess) e = hipEventRecord(c->ev[1], c->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(c->ev[1]);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, c->ev[0], c->ev[1]);
+    if (e != hipSuccess) return hip_fail(c, e, "LDS gather probe");
+    const double evals = (double)n_out * n_step * cfg.JT * cfg.L;
+    *evals_per_s = ms > 0.f ? evals / (ms * 1e-3) : 0.0;
+    return FT_OK;
+}
+
 ft_status ft_tune_clear(ft_ctx c)
 {
     if (!c) return FT_E_INVALID;
@@ -469,6 +500,7 @@ void ft_destroy(ft_ctx c)
         release(&b.gen, &b.c_gen);
         release(&b.items, &b.c_items);
         release(&b.counters, &b.c_counters);
+        release(&c->d_probe, &c->cap_probe);
         release(&b.out, &b.c_out);
         release(&b.labels, &b.c_labels);
     }

@@ -9,7 +9,7 @@
 // is accumulated, the parameters of stage p+1 are derived and its table
 // windows stream from HBM/L2 straight into LDS (global_load_lds).
 //   prepare(p): Doppler factor g[s][k] (canonical FP64 order), G = g*T_sft,
-//      run-guard bounds, c[j][k] = f1_j*dt_k and h = c*G + 1/2; then the
+//      run-guard bounds, c[j][k] = f1_j*dt_k and h = c*G + 1/2 - u_lo; then the
 //      exact bin range [lo, hi] of the tile per SFT.  The FP64 bin is monotone
 //      in each of f0, c and g and the tile is a Cartesian product, so lo/hi
 //      are bins of actual templates: the range check against the table is
@@ -18,18 +18,22 @@
 //      into LDS; columns are clamped into the table (a column outside it can
 //      only be read after a range error, which is reported).
 //   accumulate(p): for every f1 value each lane forms the estimate
-//      t~ = f0*G + h (one fused multiply-add) of x + 1/2 for the first
-//      template of its run, takes B = floor(t~) and reads B, B+1, ...,
+//      t2 = f0*G + h (one fused multiply-add) of x + 1/2 - u_lo for the first
+//      template of its run, takes B = floor(t2) and reads B, B+1, ...,
 //      B+L-1 from LDS (one address per run from a wave-uniform row base,
 //      immediate offsets; lanes hit distinct banks for odd L).
 //
 // Run guard.  |t~ - (x + 1/2)| and the rounding of every canonical evaluation
 // are bounded by the host, together with the grid's deviation from uniform
-// spacing dT/T_sft, by eta.  With u = t~ - B and e = dT*g - 1, template l of
-// the run has canonical floor(x_l + 1/2) = B + l whenever u + l*e lies in
-// [eta, 1 - eta) for every l in [0, L) -- checked at l = 0 and l = L-1 (the
-// expression is linear in l).  If any lane of the wave fails for any f1 value
-// the wave evaluates every template of the step with the canonical FP64
+// spacing dT/T_sft, by eta.  With u = fract(t~) and e = dT*g - 1, template l of
+// the run has canonical floor(x_l + 1/2) = floor(t~) + l whenever u + l*e lies
+// in [eta, 1 - eta) for every l in [0, L) -- i.e. u in [u_lo, u_hi) with
+// u_lo = eta + max(0, -(L-1)e), u_hi = 1 - eta - max(0, (L-1)e) (the expression
+// is linear in l).  The kernel forms t2 = t~ - u_lo directly (h carries the
+// shift); then u in [u_lo, u_hi) exactly when fract(t2) < u_hi - u_lo, and in
+// that case floor(t2) = floor(t~): one compare per run.  The extra rounding of
+// the shift is inside eta.  If any lane of the wave fails for any f1 value the
+// wave evaluates every template of the step with the canonical FP64
 // expression.  Either way every bin equals the canonical FP64 bin.
 //
 // Sums: FP32 within aligned blocks of 32 SFTs, block sums accumulated in FP64.
@@ -43,10 +47,9 @@ template <int L, int JT, int NW, int KS>
 struct StageParams {
     double g[NW][KS];       // canonical Doppler factor
     double G[NW][KS];       // g * T_sft
-    double ulo[NW][KS];     // run-guard bounds on u
-    double uhi[NW][KS];
+    double w[NW][KS];       // run-guard window width u_hi - u_lo
     double c[JT][KS];       // canonical f1 * dt
-    double h[NW][JT][KS];   // c * G + 1/2
+    double h[NW][JT][KS];   // c * G + 1/2 - u_lo
     int lo[KS];             // first staged bin
 };
 
@@ -135,16 +138,14 @@ __device__ __forceinline__ bool prepare_stage(const EvalRun &r, const TileGeom &
         const double G = g * T;
         const double dt = vdt[3 * KS + kk];
         const double c = sh.f1[jl] * dt;
-        if (L > 1) P.h[wave][jl][kk] = c * G + 0.5;
+        const double eL = (double)(L - 1) * (r.dT * g - 1.0);
+        const double ulo = r.eta + fmax(0.0, -eL);
+        if (L > 1) P.h[wave][jl][kk] = (c * G + 0.5) - ulo;
         if (wave == 0) P.c[jl][kk] = c;
         if (jl == 0) {
             P.g[wave][kk] = g;
             P.G[wave][kk] = G;
-            if (L > 1) {
-                const double eL = (double)(L - 1) * (r.dT * g - 1.0);
-                P.ulo[wave][kk] = r.eta + fmax(0.0, -eL);
-                P.uhi[wave][kk] = (1.0 - r.eta) - fmax(0.0, eL);
-            }
+            if (L > 1) P.w[wave][kk] = ((1.0 - r.eta) - fmax(0.0, eL)) - ulo;
             double cmin = c, cmax = c;
 #pragma unroll
             for (int j = 1; j < JT; ++j) {
@@ -222,20 +223,20 @@ __device__ __forceinline__ void flush_block(const EvalRun &r, int k, float (&acc
 }
 
 // Run estimates of SFT step kk from its parameters (already in registers):
-// B[jl] = floor(t~) and whether every run of the lane passes the guard.
+// B[jl] = floor(t2) with t2 = f0 G + h, and the lanes (a wave mask) where a
+// run fails the guard fract(t2) < w.
 template <int JT>
-__device__ __forceinline__ bool run_bins(double f0_lane, double G, double ulo, double uhi,
-                                         const double (&h)[JT], int (&B)[JT])
+__device__ __forceinline__ uint64_t run_bins(double f0_lane, double G, double w, const double (&h)[JT],
+                                             int (&B)[JT])
 {
-    bool ok = true;
+    uint64_t fail = 0;
 #pragma unroll
     for (int jl = 0; jl < JT; ++jl) {
         const double t = fma(f0_lane, G, h[jl]);
         B[jl] = (int)t;
-        const double u = __builtin_amdgcn_fract(t);
-        ok = ok && (u >= ulo) && (u < uhi);
+        fail |= __builtin_amdgcn_ballot_w64(!(__builtin_amdgcn_fract(t) < w));
     }
-    return ok;
+    return fail;
 }
 
 // Guard fallback of one SFT step: the values at the canonical FP64 bins of
@@ -286,11 +287,11 @@ __device__ __forceinline__ void accumulate_pipelined(const EvalRun &r, const Sta
 #pragma unroll
     for (int jl = 0; jl < JT; ++jl) h[jl] = P.h[wave][jl][0];
     int B[JT];
-    bool ok = wave_all(run_bins<JT>(f0_lane, P.G[wave][0], P.ulo[wave][0], P.uhi[wave][0], h, B));
+    bool ok = run_bins<JT>(f0_lane, P.G[wave][0], P.w[wave][0], h, B) == 0;
     int lo = __builtin_amdgcn_readfirstlane(P.lo[0]);
     for (int kk = 0; kk < ks; ++kk) {
         const int kn = min(kk + 1, ks - 1);
-        const double Gn = P.G[wave][kn], ulon = P.ulo[wave][kn], uhin = P.uhi[wave][kn];
+        const double Gn = P.G[wave][kn], wn = P.w[wave][kn];
         double hn[JT];
 #pragma unroll
         for (int jl = 0; jl < JT; ++jl) hn[jl] = P.h[wave][jl][kn];
@@ -303,10 +304,9 @@ __device__ __forceinline__ void accumulate_pipelined(const EvalRun &r, const Sta
 #pragma unroll
             for (int l = 0; l < L; ++l) v[jl][l] = wk[B[jl] + l];
         int Bn[JT];
-        const bool okn = run_bins<JT>(f0_lane, Gn, ulon, uhin, hn, Bn);
         // keep the next bins ahead of the adds (the compiler would otherwise
         // sink them past the branch, after the wait for the gathers)
-        const int fast_next = wave_all(okn) ? 1 : 0;
+        const int fast_next = run_bins<JT>(f0_lane, Gn, wn, hn, Bn) == 0 ? 1 : 0;
 #pragma unroll
         for (int jl = 0; jl < JT; ++jl) asm volatile("" ::"v"(Bn[jl]));
         asm volatile("" ::"s"(fast_next));
@@ -404,18 +404,11 @@ __device__ __forceinline__ void eval_tile(const EvalRun &r, int64_t b, float *wi
                     acc[jl][0] += wb[base + B];
                 }
             } else {
-                const double G = P.G[wave][kk];
-                const double ulo = P.ulo[wave][kk], uhi = P.uhi[wave][kk];
-                int B[JT];
-                bool ok = true;
+                double h[JT];
 #pragma unroll
-                for (int jl = 0; jl < JT; ++jl) {
-                    const double t = fma(f0_lane, G, P.h[wave][jl][kk]);
-                    B[jl] = (int)t;
-                    const double u = __builtin_amdgcn_fract(t);
-                    ok = ok && (u >= ulo) && (u < uhi);
-                }
-                if (wave_all(ok)) {
+                for (int jl = 0; jl < JT; ++jl) h[jl] = P.h[wave][jl][kk];
+                int B[JT];
+                if (run_bins<JT>(f0_lane, P.G[wave][kk], P.w[wave][kk], h, B) == 0) {
                     const float *wk = wb + __builtin_amdgcn_readfirstlane(base);
 #pragma unroll
                     for (int jl = 0; jl < JT; ++jl) {
@@ -534,26 +527,96 @@ hipError_t launch_t(const EvalRun &r, hipStream_t s)
     return hipGetLastError();
 }
 
+// LDS gather probe: the accumulation pattern of a tile shape -- every lane
+// gathers JT runs of L consecutive window values per SFT step from a staged
+// window and adds them into FP32 accumulators flushed to FP64 every SUM_BLOCK
+// steps -- with the index arithmetic, the staging and the guard removed.  Its
+// rate is the achievable ceiling of the grid kernel's gather-accumulate part
+// at the same occupancy (same block size, LDS and register budget).
+template <int L, int JT, int NW, int KS, int OCC>
+__global__ __launch_bounds__(64 * NW, OCC > 0 ? OCC : 1) void lds_probe_kernel(int n_step, int wtp,
+                                                                                 float *out)
+{
+    extern __shared__ float win[];  // [2][KS][wtp]
+    const int lane = threadIdx.x & 63;
+    const int n_win = 2 * KS * wtp;
+    for (int i = threadIdx.x; i < n_win; i += 64 * NW) win[i] = (float)(i & 1023) * 0.25f;
+    __syncthreads();
+    float acc[JT][L];
+    double tot[JT][L];
+#pragma unroll
+    for (int j = 0; j < JT; ++j)
+#pragma unroll
+        for (int l = 0; l < L; ++l) {
+            acc[j][l] = 0.f;
+            tot[j][l] = 0.0;
+        }
+    // lane runs as in a tile: consecutive lanes L bins apart, f1 values a few
+    // bins apart, the whole pattern shifted by a few bins from step to step
+    const int span = 64 * L + 3 * JT + 8;
+    const int room = wtp - span > 0 ? wtp - span : 0;
+    for (int k = 0; k < n_step; ++k) {
+        const int kk = k % (2 * KS);
+        const int shift = room > 0 ? (k * 5) % room : 0;
+        const float *wk = win + kk * wtp + shift;
+#pragma unroll
+        for (int jl = 0; jl < JT; ++jl) {
+            const float *wp = wk + lane * L + 3 * jl;
+#pragma unroll
+            for (int l = 0; l < L; ++l) acc[jl][l] += wp[l];
+        }
+        if (((k + 1) & (SUM_BLOCK - 1)) == 0) {
+#pragma unroll
+            for (int j = 0; j < JT; ++j)
+#pragma unroll
+                for (int l = 0; l < L; ++l) {
+                    tot[j][l] += (double)acc[j][l];
+                    acc[j][l] = 0.f;
+                }
+        }
+    }
+    double sum = 0.0;
+#pragma unroll
+    for (int j = 0; j < JT; ++j)
+#pragma unroll
+        for (int l = 0; l < L; ++l) sum += tot[j][l] + (double)acc[j][l];
+    out[(int64_t)blockIdx.x * blockDim.x + threadIdx.x] = (float)sum;
+}
+
+template <int L, int JT, int NW, int KS, int OCC>
+hipError_t launch_probe_t(int n_blocks, int n_step, int wtp, float *out, hipStream_t s)
+{
+    const size_t lds = (size_t)2 * KS * wtp * sizeof(float);
+    hipLaunchKernelGGL((lds_probe_kernel<L, JT, NW, KS, OCC>), dim3((unsigned)n_blocks), dim3(64 * NW), lds, s,
+                       n_step, wtp, out);
+    return hipGetLastError();
+}
+
 using Launcher = hipError_t (*)(const EvalRun &, hipStream_t);
 using BatchLauncher = hipError_t (*)(const EvalRun *, const int2 *, int, int, unsigned *, int,
                                      hipStream_t);
+
+using ProbeLauncher = hipError_t (*)(int, int, int, float *, hipStream_t);
 
 struct TileEntry {
     TileCfg cfg;
     Launcher fn;
     BatchLauncher batch_fn;
     size_t static_lds;
+    ProbeLauncher probe_fn;
 };
 
 #define FT_TILE(id, L, JT, NW, KS)                                                                 \
     {{id, "L" #L "_J" #JT "_W" #NW "_K" #KS, L, JT, NW, KS}, &launch_t<L, JT, NW, KS, 0, false>,        \
-     &launch_batch_t<L, JT, NW, KS, 0, false>, sizeof(Shared<L, JT, NW, KS>)}
+     &launch_batch_t<L, JT, NW, KS, 0, false>, sizeof(Shared<L, JT, NW, KS>), &launch_probe_t<L, JT, NW, KS, 0>}
 #define FT_TILE_O(id, L, JT, NW, KS, OCC)                                                          \
     {{id, "L" #L "_J" #JT "_W" #NW "_K" #KS "_O" #OCC, L, JT, NW, KS}, &launch_t<L, JT, NW, KS, OCC, false>, \
-     &launch_batch_t<L, JT, NW, KS, OCC, false>, sizeof(Shared<L, JT, NW, KS>)}
+     &launch_batch_t<L, JT, NW, KS, OCC, false>, sizeof(Shared<L, JT, NW, KS>),                     \
+     &launch_probe_t<L, JT, NW, KS, OCC>}
 #define FT_TILE_P(id, L, JT, NW, KS, OCC)                                                           \
     {{id, "L" #L "_J" #JT "_W" #NW "_K" #KS "_O" #OCC "_P", L, JT, NW, KS}, &launch_t<L, JT, NW, KS, OCC, true>, \
-     &launch_batch_t<L, JT, NW, KS, OCC, true>, sizeof(Shared<L, JT, NW, KS>)}
+     &launch_batch_t<L, JT, NW, KS, OCC, true>, sizeof(Shared<L, JT, NW, KS>),                     \
+     &launch_probe_t<L, JT, NW, KS, OCC>}
 
 const TileEntry kTiles[] = {
     FT_TILE(0, 1, 1, 4, 16),
@@ -603,6 +666,11 @@ hipError_t launch_eval_batch(const EvalRun *runs, const int2 *items, int n_items
                              unsigned *counter, int grid, const TileCfg &cfg, hipStream_t s)
 {
     return kTiles[cfg.id].batch_fn(runs, items, n_items, max_wtp, counter, grid, s);
+}
+
+hipError_t launch_lds_probe(const TileCfg &cfg, int n_blocks, int n_step, int wtp, float *out, hipStream_t s)
+{
+    return kTiles[cfg.id].probe_fn(n_blocks, n_step, wtp, out, s);
 }
 
 }  // namespace ft

@@ -105,6 +105,9 @@ hipError_t launch_labels(const double *max_z, int n_runs, double tau, uint8_t *l
                          hipStream_t s);
 hipError_t launch_eval_list(const EvalRun &run, hipStream_t s);
 hipError_t launch_eval_grid_direct(const EvalRun &run, hipStream_t s);
+// LDS gather probe of a tile shape: n_blocks workgroups, n_step SFT steps over
+// a staged window of LDS row stride wtp; out [n_blocks * 64 NW] floats.
+hipError_t launch_lds_probe(const TileCfg &cfg, int n_blocks, int n_step, int wtp, float *out, hipStream_t s);
 hipError_t launch_bins_list(const EvalRun &run, int precision, int32_t *bins, hipStream_t s);
 hipError_t launch_count_mismatch(const EvalRun &run, bool grid, int precision,
                                  unsigned long long *count, hipStream_t s);

@@ -89,7 +89,7 @@ EXPORTS = ("ft_create", "ft_destroy", "ft_last_error", "ft_status_string", "ft_s
            "ft_tile_name", "ft_gen_sfts", "ft_eval_batch", "ft_batch_toplist", "ft_batch_labels",
            "ft_batch_replay", "ft_batch_time", "ft_mlp_create", "ft_mlp_destroy",
            "ft_mlp_get_params", "ft_mlp_predict", "ft_mlp_loss_grad", "ft_mlp_train",
-           "ft_tune_report", "ft_tune_clear")
+           "ft_tune_report", "ft_tune_clear", "ft_probe_lds_gather")
 
 
 def load(path: str = LIB_PATH):
@@ -134,6 +134,7 @@ def load(path: str = LIB_PATH):
         "ft_tune_report": (C.c_int, [P, C.POINTER(ft_tune_entry), i32, C.POINTER(i32),
                                      C.POINTER(f64)]),
         "ft_tune_clear": (C.c_int, [P]),
+        "ft_probe_lds_gather": (C.c_int, [P, i32, i32, C.POINTER(f64)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -317,6 +318,12 @@ def ft_tune_report(ctx):
 
 def ft_tune_clear(ctx):
     _check(ctx, load().ft_tune_clear(ctx))
+
+
+def ft_probe_lds_gather(ctx, tile, wtp=0):
+    r = C.c_double()
+    _check(ctx, load().ft_probe_lds_gather(ctx, int(tile), int(wtp), C.byref(r)))
+    return r.value
 
 
 def ft_tile_name(tile):
@@ -553,6 +560,9 @@ class Context:
 
     def tune_clear(self):
         ft_tune_clear(self.ctx)
+
+    def probe_lds_gather(self, tile, wtp=0):
+        return ft_probe_lds_gather(self.ctx, tile, wtp)
 
     def eval_campaign(self, cp, use_graph=0, tile=0, power=None):
         """Evaluate a synth.Campaign (tables generated on the GPU unless given)."""

@@ -72,3 +72,15 @@ def test_tuned_batch_equals_untuned(ft):
         assert sum(e["chosen"] for e in rows) == 1
         best = max(e["evals_per_s"] for e in rows)
         assert next(e for e in rows if e["chosen"])["evals_per_s"] == best
+
+
+def test_lds_gather_probe(ft):
+    """The gather-accumulate probe runs for every tile shape and rejects bad
+    arguments on the host."""
+    import torch
+    with ft.Context(0, torch.cuda.current_stream().cuda_stream) as c:
+        rates = [c.probe_lds_gather(t) for t in range(1, ft.ft_tile_count() + 1)]
+        assert all(r > 1e11 for r in rates), rates
+        for bad in ((0, 0), (ft.ft_tile_count() + 1, 0), (1, 65), (1, 64)):
+            with pytest.raises(ft.FtError):
+                c.probe_lds_gather(*bad)
