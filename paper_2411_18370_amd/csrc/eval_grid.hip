@@ -56,6 +56,7 @@ struct StageParams {
 template <int L, int JT, int NW, int KS>
 struct Shared {
     static_assert(KS <= 64 && NW <= 16, "one lane per SFT of a stage");
+    static_assert(SUM_BLOCK % KS == 0, "summation blocks end with a stage");
     StageParams<L, JT, NW, KS> p[2];
     double f0[64 * L];
     int lo_w[NW][KS], hi_w[NW][KS];  // per sky point bin range of the stage being prepared
@@ -266,6 +267,33 @@ __device__ __forceinline__ void canonical_values(const StageParams<L, JT, NW, KS
         for (int l = 0; l < L; ++l) out[jl][l] = slow_read(wb + idx[jl][l]);
 }
 
+// Guard fallback accumulating directly: one run position l at a time (its JT
+// canonical bins formed, their reads issued together, then added), which
+// keeps the fallback's register footprint below the fast path's.
+template <int L, int JT, int NW, int KS>
+__device__ __forceinline__ void canonical_accumulate(const StageParams<L, JT, NW, KS> &P,
+                                                     const Shared<L, JT, NW, KS> &sh, const TileGeom &tg,
+                                                     const float *wb, int base, int kk, int wave, int lane,
+                                                     double T, float (&acc)[JT][L])
+{
+    const double g = P.g[wave][kk];
+    double c[JT];
+#pragma unroll
+    for (int jl = 0; jl < JT; ++jl) c[jl] = P.c[jl][kk];
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+        const double f0l = sh.f0[min(lane * L + l, tg.n_in - 1)];
+        int idx[JT];
+#pragma unroll
+        for (int jl = 0; jl < JT; ++jl) idx[jl] = base + bin_fp64(f0l, c[jl], g, T);
+        float v[JT];
+#pragma unroll
+        for (int jl = 0; jl < JT; ++jl) v[jl] = slow_read(wb + idx[jl]);
+#pragma unroll
+        for (int jl = 0; jl < JT; ++jl) acc[jl][l] += v[jl];
+    }
+}
+
 // Software-pipelined accumulation of one stage (run-length tiles).  Step kk
 // reads the parameters of step kk+1 from LDS first, then issues its own
 // gathers, then forms the bins of step kk+1 while those gathers are in flight,
@@ -418,23 +446,19 @@ __device__ __forceinline__ void eval_tile(const EvalRun &r, int64_t b, float *wi
                     }
                 } else {
                     // rare: some lane is within the guard margin of a bin edge
-                    float v[JT][L];
-                    canonical_values<L, JT, NW, KS>(P, sh, tg, wb, base, kk, wave, lane, T, v);
-#pragma unroll
-                    for (int jl = 0; jl < JT; ++jl)
-#pragma unroll
-                        for (int l = 0; l < L; ++l) acc[jl][l] += v[jl][l];
+                    canonical_accumulate<L, JT, NW, KS>(P, sh, tg, wb, base, kk, wave, lane, T, acc);
                 }
             }
-            if (r.sum_mode == FT_SUM_BLOCKED && ((k0 + kk + 1) & (SUM_BLOCK - 1)) == 0) {
+        }
+        // blocks of SUM_BLOCK SFTs end with a stage (KS divides SUM_BLOCK)
+        if (!(L > 1 && PIPE) && r.sum_mode == FT_SUM_BLOCKED && ((k0 + ks) & (SUM_BLOCK - 1)) == 0) {
 #pragma unroll
-                for (int j = 0; j < JT; ++j)
+            for (int j = 0; j < JT; ++j)
 #pragma unroll
-                    for (int l = 0; l < L; ++l) {
-                        tot[j][l] += (double)acc[j][l];
-                        acc[j][l] = 0.f;
-                    }
-            }
+                for (int l = 0; l < L; ++l) {
+                    tot[j][l] += (double)acc[j][l];
+                    acc[j][l] = 0.f;
+                }
         }
         wait_loads();
         __syncthreads();
