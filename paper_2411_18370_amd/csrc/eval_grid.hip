@@ -9,7 +9,7 @@
 // is accumulated, the parameters of stage p+1 are derived and its table
 // windows stream from HBM/L2 straight into LDS (global_load_lds).
 //   prepare(p): Doppler factor g[s][k] (canonical FP64 order), G = g*T_sft,
-//      run-guard bounds, c[j][k] = f1_j*dt_k and h = c*G + 1/2 - u_lo; then the
+//      run-guard bounds, c[j][k] = f1_j*dt_k and h = c*G + 1/2 - u_lo - lo; then the
 //      exact bin range [lo, hi] of the tile per SFT.  The FP64 bin is monotone
 //      in each of f0, c and g and the tile is a Cartesian product, so lo/hi
 //      are bins of actual templates: the range check against the table is
@@ -18,10 +18,11 @@
 //      into LDS; columns are clamped into the table (a column outside it can
 //      only be read after a range error, which is reported).
 //   accumulate(p): for every f1 value each lane forms the estimate
-//      t2 = f0*G + h (one fused multiply-add) of x + 1/2 - u_lo for the first
-//      template of its run, takes B = floor(t2) and reads B, B+1, ...,
-//      B+L-1 from LDS (one address per run from a wave-uniform row base,
-//      immediate offsets; lanes hit distinct banks for odd L).
+//      t2 = f0*G + h (one fused multiply-add) of x + 1/2 - u_lo - lo for the
+//      first template of its run, takes B = floor(t2) -- the LDS row offset of
+//      the bin -- and reads B, B+1, ..., B+L-1 (one address per run from a
+//      wave-uniform row base, immediate offsets; lanes hit distinct banks for
+//      odd L).
 //
 // Run guard.  |t~ - (x + 1/2)| and the rounding of every canonical evaluation
 // are bounded by the host, together with the grid's deviation from uniform
@@ -43,14 +44,20 @@ namespace ft {
 
 namespace {
 
+// One SFT step of one sky point, as the accumulation reads it (one address):
+// G = g T_sft, w = u_hi - u_lo (run-guard window) and, per f1 value,
+// h = c G + 1/2 - u_lo - lo (the estimate then lands on the LDS row offset).
+template <int JT>
+struct StepParams {
+    double G, w, h[JT];
+};
+
 template <int L, int JT, int NW, int KS>
 struct StageParams {
-    double g[NW][KS];       // canonical Doppler factor
-    double G[NW][KS];       // g * T_sft
-    double w[NW][KS];       // run-guard window width u_hi - u_lo
-    double c[JT][KS];       // canonical f1 * dt
-    double h[NW][JT][KS];   // c * G + 1/2 - u_lo
-    int lo[KS];             // first staged bin
+    double g[NW][KS];                // canonical Doppler factor
+    StepParams<JT> q[NW][KS];        // run-estimate parameters
+    double c[JT][KS];                // canonical f1 * dt
+    int lo[KS];                      // first staged bin
 };
 
 template <int L, int JT, int NW, int KS>
@@ -141,12 +148,12 @@ __device__ __forceinline__ bool prepare_stage(const EvalRun &r, const TileGeom &
         const double c = sh.f1[jl] * dt;
         const double eL = (double)(L - 1) * (r.dT * g - 1.0);
         const double ulo = r.eta + fmax(0.0, -eL);
-        if (L > 1) P.h[wave][jl][kk] = (c * G + 0.5) - ulo;
+        if (L > 1) P.q[wave][kk].h[jl] = (c * G + 0.5) - ulo;  // rebased on lo below
         if (wave == 0) P.c[jl][kk] = c;
         if (jl == 0) {
             P.g[wave][kk] = g;
-            P.G[wave][kk] = G;
-            if (L > 1) P.w[wave][kk] = ((1.0 - r.eta) - fmax(0.0, eL)) - ulo;
+            P.q[wave][kk].G = G;
+            if (L > 1) P.q[wave][kk].w = ((1.0 - r.eta) - fmax(0.0, eL)) - ulo;
             double cmin = c, cmax = c;
 #pragma unroll
             for (int j = 1; j < JT; ++j) {
@@ -179,6 +186,18 @@ __device__ __forceinline__ bool prepare_stage(const EvalRun &r, const TileGeom &
         bad = (err & ERR_WINDOW) != 0;
     }
     if (!wave_all(!bad)) return false;
+    // rebase the estimates on the first staged bin (each lane its own entries;
+    // lo is an integer near the estimate, so the difference rounds at most by
+    // an ulp of the window width)
+    if (L > 1)
+        for (int q = lane; q < JT * KS; q += 64) {
+            const int jl = q / KS, kk = q % KS;
+            if (kk >= ks) continue;
+            int lo_k = sh.lo_w[0][kk];
+#pragma unroll
+            for (int w = 1; w < NW; ++w) lo_k = min(lo_k, sh.lo_w[w][kk]);
+            P.q[wave][kk].h[jl] -= (double)lo_k;
+        }
 
     // the next stage's velocities and time offsets (read by its preparation,
     // after the end-of-stage wait)
@@ -223,19 +242,32 @@ __device__ __forceinline__ void flush_block(const EvalRun &r, int k, float (&acc
     }
 }
 
-// Run estimates of SFT step kk from its parameters (already in registers):
-// B[jl] = floor(t2) with t2 = f0 G + h, and the lanes (a wave mask) where a
-// run fails the guard fract(t2) < w.
+// The step parameters of (sky point, SFT) read field by field (a whole-struct
+// copy loses the alias information that keeps these LDS reads from waiting on
+// the window copies in flight).
+template <int L, int JT, int NW, int KS>
+__device__ __forceinline__ StepParams<JT> load_step(const StageParams<L, JT, NW, KS> &P, int wave, int kk)
+{
+    StepParams<JT> q;
+    q.G = P.q[wave][kk].G;
+    q.w = P.q[wave][kk].w;
+#pragma unroll
+    for (int jl = 0; jl < JT; ++jl) q.h[jl] = P.q[wave][kk].h[jl];
+    return q;
+}
+
+// Run estimates of one SFT step from its parameters (already in registers):
+// B[jl] = floor(t2) with t2 = f0 G + h (the LDS row offset of the run's first
+// bin), and the lanes (a wave mask) where a run fails the guard fract(t2) < w.
 template <int JT>
-__device__ __forceinline__ uint64_t run_bins(double f0_lane, double G, double w, const double (&h)[JT],
-                                             int (&B)[JT])
+__device__ __forceinline__ uint64_t run_bins(double f0_lane, const StepParams<JT> &q, int (&B)[JT])
 {
     uint64_t fail = 0;
 #pragma unroll
     for (int jl = 0; jl < JT; ++jl) {
-        const double t = fma(f0_lane, G, h[jl]);
+        const double t = fma(f0_lane, q.G, q.h[jl]);
         B[jl] = (int)t;
-        fail |= __builtin_amdgcn_ballot_w64(!(__builtin_amdgcn_fract(t) < w));
+        fail |= __builtin_amdgcn_ballot_w64(!(__builtin_amdgcn_fract(t) < q.w));
     }
     return fail;
 }
@@ -311,21 +343,12 @@ __device__ __forceinline__ void accumulate_pipelined(const EvalRun &r, const Sta
                                                      double (&tot)[JT][L])
 {
     const double T = r.t_sft;
-    double h[JT];
-#pragma unroll
-    for (int jl = 0; jl < JT; ++jl) h[jl] = P.h[wave][jl][0];
     int B[JT];
-    bool ok = run_bins<JT>(f0_lane, P.G[wave][0], P.w[wave][0], h, B) == 0;
-    int lo = __builtin_amdgcn_readfirstlane(P.lo[0]);
+    bool ok = run_bins<JT>(f0_lane, load_step<L, JT, NW, KS>(P, wave, 0), B) == 0;
     for (int kk = 0; kk < ks; ++kk) {
         const int kn = min(kk + 1, ks - 1);
-        const double Gn = P.G[wave][kn], wn = P.w[wave][kn];
-        double hn[JT];
-#pragma unroll
-        for (int jl = 0; jl < JT; ++jl) hn[jl] = P.h[wave][jl][kn];
-        const int lon = P.lo[kn];
-        const int base = kk * wtp - lo;
-        const float *wk = wb + base;
+        const StepParams<JT> qn = load_step<L, JT, NW, KS>(P, wave, kn);
+        const float *wk = wb + kk * wtp;
         float v[JT][L];
 #pragma unroll
         for (int jl = 0; jl < JT; ++jl)
@@ -334,12 +357,12 @@ __device__ __forceinline__ void accumulate_pipelined(const EvalRun &r, const Sta
         int Bn[JT];
         // keep the next bins ahead of the adds (the compiler would otherwise
         // sink them past the branch, after the wait for the gathers)
-        const int fast_next = run_bins<JT>(f0_lane, Gn, wn, hn, Bn) == 0 ? 1 : 0;
+        const int fast_next = run_bins<JT>(f0_lane, qn, Bn) == 0 ? 1 : 0;
 #pragma unroll
         for (int jl = 0; jl < JT; ++jl) asm volatile("" ::"v"(Bn[jl]));
         asm volatile("" ::"s"(fast_next));
         if (!ok)  // rare: some lane is within the guard margin of a bin edge
-            canonical_values<L, JT, NW, KS>(P, sh, tg, wb, base, kk, wave, lane, T, v);
+            canonical_values<L, JT, NW, KS>(P, sh, tg, wb, kk * wtp - P.lo[kk], kk, wave, lane, T, v);
 #pragma unroll
         for (int jl = 0; jl < JT; ++jl)
 #pragma unroll
@@ -348,7 +371,6 @@ __device__ __forceinline__ void accumulate_pipelined(const EvalRun &r, const Sta
 #pragma unroll
         for (int jl = 0; jl < JT; ++jl) B[jl] = Bn[jl];
         ok = fast_next != 0;
-        lo = __builtin_amdgcn_readfirstlane(lon);  // after the adds' wait: no LDS read pending into the next step
     }
 }
 
@@ -423,8 +445,8 @@ __device__ __forceinline__ void eval_tile(const EvalRun &r, int64_t b, float *wi
             accumulate_pipelined<L, JT, NW, KS>(r, P, sh, tg, wb, wtp, k0, ks, wave, lane, f0_lane, acc, tot);
         } else
         for (int kk = 0; kk < ks; ++kk) {
-            const int base = kk * wtp - P.lo[kk];
             if (L == 1) {
+                const int base = kk * wtp - P.lo[kk];
                 const double g = P.g[wave][kk];
 #pragma unroll
                 for (int jl = 0; jl < JT; ++jl) {
@@ -432,12 +454,10 @@ __device__ __forceinline__ void eval_tile(const EvalRun &r, int64_t b, float *wi
                     acc[jl][0] += wb[base + B];
                 }
             } else {
-                double h[JT];
-#pragma unroll
-                for (int jl = 0; jl < JT; ++jl) h[jl] = P.h[wave][jl][kk];
+                const StepParams<JT> q = load_step<L, JT, NW, KS>(P, wave, kk);
                 int B[JT];
-                if (run_bins<JT>(f0_lane, P.G[wave][kk], P.w[wave][kk], h, B) == 0) {
-                    const float *wk = wb + __builtin_amdgcn_readfirstlane(base);
+                if (run_bins<JT>(f0_lane, q, B) == 0) {
+                    const float *wk = wb + kk * wtp;
 #pragma unroll
                     for (int jl = 0; jl < JT; ++jl) {
                         const float *wp = wk + B[jl];
@@ -446,7 +466,7 @@ __device__ __forceinline__ void eval_tile(const EvalRun &r, int64_t b, float *wi
                     }
                 } else {
                     // rare: some lane is within the guard margin of a bin edge
-                    canonical_accumulate<L, JT, NW, KS>(P, sh, tg, wb, base, kk, wave, lane, T, acc);
+                    canonical_accumulate<L, JT, NW, KS>(P, sh, tg, wb, kk * wtp - P.lo[kk], kk, wave, lane, T, acc);
                 }
             }
         }
