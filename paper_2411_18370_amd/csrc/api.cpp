@@ -97,8 +97,8 @@ struct ft_ctx_s {
                c_tref = 0, c_s64 = 0, c_maxz = 0, c_inj_amp = 0;
         float *power = nullptr, *stats = nullptr;
         size_t c_power = 0, c_stats = 0;
-        int32_t *perm = nullptr, *sft_begin = nullptr, *nout = nullptr, *inj_bin = nullptr;
-        size_t c_perm = 0, c_sft_begin = 0, c_nout = 0, c_inj_bin = 0;
+        int32_t *perm = nullptr, *sft_begin = nullptr, *nout = nullptr, *inj_bin = nullptr, *band = nullptr;
+        size_t c_perm = 0, c_sft_begin = 0, c_nout = 0, c_inj_bin = 0, c_band = 0;
         int64_t *dt_prefix = nullptr, *cand = nullptr, *gen_prefix = nullptr;
         size_t c_dt_prefix = 0, c_cand = 0, c_gen_prefix = 0;
         EvalRun *runs = nullptr;
@@ -493,6 +493,7 @@ void ft_destroy(ft_ctx c)
         release(&b.sft_begin, &b.c_sft_begin);
         release(&b.nout, &b.c_nout);
         release(&b.inj_bin, &b.c_inj_bin);
+        release(&b.band, &b.c_band);
         release(&b.dt_prefix, &b.c_dt_prefix);
         release(&b.cand, &b.c_cand);
         release(&b.gen_prefix, &b.c_gen_prefix);
@@ -731,7 +732,7 @@ ft_status ft_gen_sfts(ft_ctx c, int32_t n_det, const int32_t *n_sft, const doubl
     g.n_inj = n_inj;
     c->genruns_h.push_back(g);
     c->prefix_h.push_back(0);
-    c->prefix_h.push_back((int64_t)n_cells);
+    c->prefix_h.push_back(total);
     const size_t n_rec = c->genruns_h.size(), n_pre = c->prefix_h.size();
     if ((e = ensure(&c->d_genruns, &c->cap_genruns, n_rec)) != hipSuccess ||
         (e = ensure(&c->d_prefix, &c->cap_prefix, n_pre)) != hipSuccess)
@@ -741,7 +742,7 @@ ft_status ft_gen_sfts(ft_ctx c, int32_t n_det, const int32_t *n_sft, const doubl
         e = hipMemcpyAsync(c->d_prefix, c->prefix_h.data(), n_pre * sizeof(int64_t), hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess)
         e = launch_gen_tables(c->d_genruns, n_inj, c->d_prefix, (int64_t)n_inj * total, c->d_genruns + n_inj, 1,
-                              c->d_prefix + (n_inj + 1), (int64_t)n_cells, c->stream);
+                              c->d_prefix + (n_inj + 1), total, c->stream);
     if (e == hipSuccess) e = launch_noise_moments(nullptr, (int)total, c->d_mu_sigma, c->stream);
     if (e == hipSuccess && power_out)
         e = hipMemcpyAsync(power_out, c->d_power, n_cells * sizeof(float), hipMemcpyDefault, c->stream);
@@ -1376,7 +1377,7 @@ static ft_status launch_batch_sequence(ft_ctx c, const BatchPlan &pl, bool gener
         e = launch_batch_dt(b.tmid, b.sft_begin, b.tref, b.dt_prefix, n_runs, pl.dt_prefix[n_runs], b.dt, st);
     if (e == hipSuccess && generate)
         e = launch_gen_tables(b.gen, n_runs, b.gen_prefix, pl.gen_prefix_sft[n_runs], b.gen, n_runs,
-                              b.gen_prefix + (n_runs + 1), pl.gen_prefix_elem[n_runs], st);
+                              b.gen_prefix, pl.gen_prefix_sft[n_runs], st);
     int64_t item_off = 0;
     for (int id = 0; id < tile_count() && e == hipSuccess; ++id) {
         const int n_items = (int)pl.items[id].size();
@@ -1413,7 +1414,7 @@ static ft_status tune_batch(ft_ctx c, BatchPlan &pl, const std::vector<ft_run> &
     hipError_t e = launch_batch_dt(b.tmid, b.sft_begin, b.tref, b.dt_prefix, n_runs, pl.dt_prefix[n_runs], b.dt, c->stream);
     if (e == hipSuccess && gen)
         e = launch_gen_tables(b.gen, n_runs, b.gen_prefix, pl.gen_prefix_sft[n_runs], b.gen, n_runs,
-                              b.gen_prefix + (n_runs + 1), pl.gen_prefix_elem[n_runs], c->stream);
+                              b.gen_prefix, pl.gen_prefix_sft[n_runs], c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "tile tuning");
     struct Cls {
         int id;
@@ -1715,7 +1716,8 @@ ft_status ft_eval_batch(ft_ctx c, const ft_batch *bt, int32_t use_graph)
         (gen && ((e = ensure(&b.gen, &b.c_gen, (size_t)n_runs)) != hipSuccess ||
                  (e = ensure(&b.gen_prefix, &b.c_gen_prefix, (size_t)(n_runs + 1) * 2)) != hipSuccess ||
                  (e = ensure(&b.inj_bin, &b.c_inj_bin, (size_t)pl.gen_prefix_sft[n_runs])) != hipSuccess ||
-                 (e = ensure(&b.inj_amp, &b.c_inj_amp, (size_t)pl.gen_prefix_sft[n_runs] * 3)) != hipSuccess)))
+                 (e = ensure(&b.inj_amp, &b.c_inj_amp, (size_t)pl.gen_prefix_sft[n_runs] * 3)) != hipSuccess ||
+                 (e = ensure(&b.band, &b.c_band, (size_t)pl.gen_prefix_sft[n_runs] * 2)) != hipSuccess)))
         return hip_fail(c, e, "alloc batch buffers");
     // device pointers of every run
     for (int r = 0; r < n_runs; ++r) {
@@ -1756,6 +1758,15 @@ ft_status ft_eval_batch(ft_ctx c, const ft_batch *bt, int32_t use_graph)
             g.inj_bin = b.inj_bin + pl.gen_prefix_sft[r];
             g.inj_amp = b.inj_amp + 3 * pl.gen_prefix_sft[r];
             g.n_inj = 1;
+            g.band_mode = 1;
+            g.n_bank_sky = R.n_sky;
+            g.bank_sky = b.sky + 3 * (int64_t)R.sky_begin;
+            const double *f0r = f0h.data() + R.f0_begin, *f1r = f1h.data() + R.f1_begin;
+            g.bank_f0_lo = f0r[0];
+            g.bank_f0_hi = f0r[R.n_f0 - 1];
+            g.bank_f1_lo = *std::min_element(f1r, f1r + R.n_f1);
+            g.bank_f1_hi = *std::max_element(f1r, f1r + R.n_f1);
+            g.band = b.band + 2 * pl.gen_prefix_sft[r];
             pl.gen.push_back(g);
         }
     }

@@ -138,16 +138,25 @@ struct GenRun {
     int32_t *inj_bin;     // [n_inj][n_sft] scratch (a preparation record: [n_sft])
     double *inj_amp;      // [n_inj][n_sft][3] scratch (a preparation record: [n_sft][3])
     int32_t n_inj;        // signals the noise step adds (preparation records: unused)
-    int32_t pad;
+    // Columns to generate.  band_mode 0: all of them.  band_mode 1 (batch
+    // runs): per SFT only [band[2k], band[2k+1]], the columns the run's grid
+    // bank (f0 in [bank_f0_lo, bank_f0_hi], f1 in [bank_f1_lo, bank_f1_hi],
+    // sky bank_sky[0..n_bank_sky)) can reach; the rest of the table is left
+    // as it was (never read by an evaluation of that bank).
+    int32_t band_mode;
+    int32_t n_bank_sky;
+    const double *bank_sky;
+    double bank_f0_lo, bank_f0_hi, bank_f1_lo, bank_f1_hi;
+    int32_t *band;        // [n_sft][2], written by the preparation step
 };
 // Generate tables.  prep[0..n_prep) are the per-SFT signal preparations (one
-// record per injected signal, each writing its own inj_bin / inj_amp slice;
-// prep_prefix: exclusive prefix sums of their n_sft, n_prep + 1 entries);
-// runs[0..n_runs) are the tables (elem_prefix: exclusive prefix sums of
-// n_sft*n_bins), each adding its n_inj prepared signals to the noise in order.
-// All arrays on the device.
+// record per injected signal, each writing its own inj_bin / inj_amp slice,
+// and for batch runs the generated column band; prep_prefix: exclusive prefix
+// sums of their n_sft, n_prep + 1 entries); runs[0..n_runs) are the tables
+// (row_prefix: exclusive prefix sums of their n_sft), each adding its n_inj
+// prepared signals to the noise in order.  All arrays on the device.
 hipError_t launch_gen_tables(const GenRun *prep, int n_prep, const int64_t *prep_prefix, int64_t total_prep_sft,
-                             const GenRun *runs, int n_runs, const int64_t *elem_prefix, int64_t total_elem,
+                             const GenRun *runs, int n_runs, const int64_t *row_prefix, int64_t total_rows,
                              hipStream_t s);
 
 // Selection: exact toplists per segment (segment = sub-band here).

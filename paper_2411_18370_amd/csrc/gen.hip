@@ -17,6 +17,10 @@
 // F+ = D:e+, Fx = D:ex with D = (u u^T - w w^T)/2 from the arm unit vectors and
 // (p, q) = (e_alpha, e_delta) rotated by psi.  Several signals superpose: each
 // adds its amplitudes to Re in the order given.
+//
+// Batch runs generate only the columns their grid bank can reach (per SFT);
+// the noise of a column is a function of (seed, run, SFT, column) alone, so
+// those columns equal the full table's.
 #include "ft_internal.h"
 
 namespace ft {
@@ -68,8 +72,39 @@ __device__ __forceinline__ int find_run(const int64_t *prefix, int n_runs, int64
 }
 
 // Per SFT of a run: injection bin and the three bin amplitudes.
+// Column range of SFT k that the run's grid bank can reach: the canonical bin
+// is monotone in f0, in c = f1 dt and in the Doppler factor g, so the range
+// is spanned by the bank's extreme f0, c and g (g over the bank's sky points,
+// or over all directions, 1 -+ |v|, for banks of more than 256 points).
+__device__ void gen_band_one(const GenRun &g, int k)
+{
+    const double *v = g.v + 3 * (int64_t)k;
+    double gmin, gmax;
+    if (g.n_bank_sky <= 256) {
+        gmin = 1e300;
+        gmax = -1e300;
+        for (int s = 0; s < g.n_bank_sky; ++s) {
+            const double *n = g.bank_sky + 3 * (int64_t)s;
+            const double gs = doppler_factor(v[0], v[1], v[2], n[0], n[1], n[2]);
+            gmin = fmin(gmin, gs);
+            gmax = fmax(gmax, gs);
+        }
+    } else {
+        const double vabs = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]) * (1.0 + 1e-12);
+        gmin = 1.0 - vabs;
+        gmax = 1.0 + vabs;
+    }
+    const double dt = g.t_mid[k] - g.t_ref;
+    const double c1 = g.bank_f1_lo * dt, c2 = g.bank_f1_hi * dt;
+    const int lo = bin_fp64(g.bank_f0_lo, fmin(c1, c2), gmin, g.t_sft) - (int)g.first_bin - 1;
+    const int hi = bin_fp64(g.bank_f0_hi, fmax(c1, c2), gmax, g.t_sft) - (int)g.first_bin + 1;
+    g.band[2 * k] = max(lo, 0);
+    g.band[2 * k + 1] = min(hi, g.n_bins - 1);
+}
+
 __device__ void gen_prep_one(const GenRun &g, int k)
 {
+    if (g.band_mode) gen_band_one(g, k);
     if (g.amp == 0.0) {
         g.inj_bin[k] = INT32_MIN;
         return;
@@ -133,39 +168,51 @@ __global__ void gen_prep_kernel(const GenRun *runs, int n_runs, const int64_t *s
     }
 }
 
-__global__ void gen_noise_kernel(const GenRun *runs, int n_runs, const int64_t *elem_prefix,
-                                 int64_t total_elem)
+// Noise (and signals) of the table rows: each wavefront takes four SFT rows,
+// sixteen lanes to a row, over the row's columns (its band for batch runs,
+// which is a few tens of columns wide for a local bank).
+constexpr int kRowLanes = 16;
+
+__global__ __launch_bounds__(256) void gen_noise_kernel(const GenRun *runs, int n_runs,
+                                                        const int64_t *row_prefix, int64_t total_rows)
 {
-    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total_elem;
-         q += (int64_t)gridDim.x * blockDim.x) {
-        const int rr = find_run(elem_prefix, n_runs, q);
+    const int lane = threadIdx.x % kRowLanes;
+    const int64_t group0 = (int64_t)blockIdx.x * (blockDim.x / kRowLanes) + threadIdx.x / kRowLanes;
+    const int64_t n_groups = (int64_t)gridDim.x * (blockDim.x / kRowLanes);
+    for (int64_t q = group0; q < total_rows; q += n_groups) {
+        const int rr = find_run(row_prefix, n_runs, q);
         const GenRun &g = runs[rr];
-        const int64_t e = q - elem_prefix[rr];
-        const int k = (int)(e / g.n_bins);
-        const int b = (int)(e - (int64_t)k * g.n_bins);
-        uint32_t c[4] = {(uint32_t)b, (uint32_t)(k + g.sft_offset), g.run, 0u};
-        philox4x32_10(c, (uint32_t)g.seed, (uint32_t)(g.seed >> 32));
-        const double u1 = unit53(c[0], c[1]);
-        const double u2 = unit53(c[2], c[3]);
-        const double r = sqrt(-2.0 * log(u1));
-        const double th = 2.0 * M_PI * u2;
-        double re = r * cos(th);
-        const double im = r * sin(th);
-        for (int i = 0; i < g.n_inj; ++i) {
-            const int64_t ki = (int64_t)i * g.n_sft + k;
-            const int32_t B = g.inj_bin[ki];
-            if (B == INT32_MIN) continue;
-            const int64_t m = g.first_bin + b - (int64_t)B;
-            if (m >= -1 && m <= 1) re += g.inj_amp[3 * ki + (int)(m + 1)];
+        const int k = (int)(q - row_prefix[rr]);
+        int lo = 0, hi = g.n_bins - 1;
+        if (g.band_mode) {
+            lo = g.band[2 * k];
+            hi = g.band[2 * k + 1];
         }
-        g.table[e] = (float)(re * re + im * im);
+        float *row = g.table + (int64_t)k * g.n_bins;
+        for (int b = lo + lane; b <= hi; b += kRowLanes) {
+            uint32_t c[4] = {(uint32_t)b, (uint32_t)(k + g.sft_offset), g.run, 0u};
+            philox4x32_10(c, (uint32_t)g.seed, (uint32_t)(g.seed >> 32));
+            const double u1 = unit53(c[0], c[1]);
+            const double u2 = unit53(c[2], c[3]);
+            const double r = sqrt(-2.0 * log(u1));
+            const double th = 2.0 * M_PI * u2;
+            double re = r * cos(th);
+            const double im = r * sin(th);
+            for (int i = 0; i < g.n_inj; ++i) {
+                const int64_t ki = (int64_t)i * g.n_sft + k;
+                const int32_t B = g.inj_bin[ki];
+                if (B == INT32_MIN) continue;
+                const int64_t m = g.first_bin + b - (int64_t)B;
+                if (m >= -1 && m <= 1) re += g.inj_amp[3 * ki + (int)(m + 1)];
+            }
+            row[b] = (float)(re * re + im * im);
+        }
     }
 }
-
 }  // namespace
 
 hipError_t launch_gen_tables(const GenRun *prep, int n_prep, const int64_t *prep_prefix, int64_t total_prep_sft,
-                             const GenRun *runs, int n_runs, const int64_t *elem_prefix, int64_t total_elem,
+                             const GenRun *runs, int n_runs, const int64_t *row_prefix, int64_t total_rows,
                              hipStream_t s)
 {
     if (n_prep > 0 && total_prep_sft > 0) {
@@ -174,12 +221,13 @@ hipError_t launch_gen_tables(const GenRun *prep, int n_prep, const int64_t *prep
         hipLaunchKernelGGL(gen_prep_kernel, dim3((unsigned)b1), dim3(256), 0, s, prep, n_prep, prep_prefix,
                            total_prep_sft);
     }
-    if (n_runs > 0 && total_elem > 0) {
-        int64_t b2 = (total_elem + 255) / 256;
-        if (b2 > 32768) b2 = 32768;
-        hipLaunchKernelGGL(gen_noise_kernel, dim3((unsigned)b2), dim3(256), 0, s, runs, n_runs, elem_prefix,
-                           total_elem);
+    if (n_runs > 0 && total_rows > 0) {
+        int64_t b2 = (total_rows + 15) / 16;  // sixteen rows per block
+        if (b2 > 65536) b2 = 65536;
+        hipLaunchKernelGGL(gen_noise_kernel, dim3((unsigned)b2), dim3(256), 0, s, runs, n_runs, row_prefix,
+                           total_rows);
     }
     return hipGetLastError();
 }
+
 }  // namespace ft
