@@ -261,7 +261,7 @@ typedef struct {
     uint32_t run_id;        /* generated tables: Philox counter word of the run          */
     int32_t sft_begin;      /* first SFT of the run in the batch's SFT arrays            */
     int32_t n_sft;          /* SFTs of the run (>= 1)                                    */
-    int32_t n_bins;         /* table columns (>= 1)                                      */
+    int32_t n_bins;         /* table columns (1 .. 2^28 - 1)                             */
     int64_t first_bin;      /* absolute bin of column 0                                  */
     int64_t table_offset;   /* given tables: element offset of the run's [n_sft][n_bins] */
     int32_t f0_begin, n_f0; /* grid bank: slices of the batch's f0, f1 and sky arrays    */

@@ -1341,12 +1341,13 @@ int assign_run_tile(BatchPlan &pl, int r, int tile, const ft_run &R, const doubl
     return tile;
 }
 
-// Work items of batch run r: its tiles, or 256-template chunks for the direct kernel.
+// Work items of batch run r: its tiles, or for the small-bank kernel its
+// (f0 chunk, 64-wide (f1, sky) chunk) pairs.
 int64_t run_items(const BatchPlan &pl, int r)
 {
     const EvalRun &E = pl.runs[r];
     if (pl.tile[r] >= 0) return (int64_t)E.tiles_f0 * E.tiles_f1 * E.tiles_sky;
-    return ((int64_t)E.n_f0 * E.n_f1 * E.n_sky + 255) / 256;
+    return (int64_t)((E.n_f0 + SMALL_F0_CHUNK - 1) / SMALL_F0_CHUNK) * (((int64_t)E.n_f1 * E.n_sky + 63) / 64);
 }
 
 void append_items(const BatchPlan &pl, int r, std::vector<int2> &out)
@@ -1390,8 +1391,8 @@ static ft_status launch_batch_sequence(ft_ctx c, const BatchPlan &pl, bool gener
     {
         const int n_direct = (int)pl.items[tile_count()].size();
         if (e == hipSuccess && n_direct > 0)
-            e = launch_eval_batch_direct(b.runs, b.items + item_off, n_direct, b.counters + tile_count(),
-                                         std::min(n_direct, 4096), st);
+            e = launch_eval_batch_small(b.runs, b.items + item_off, n_direct, b.counters + tile_count(),
+                                        std::min(n_direct, 8192), st);
     }
     if (e == hipSuccess)
         e = launch_select_batch(b.runs, n_runs, c->batch_k, c->batch_cap, b.cand, b.s64, b.out, b.nout, b.maxz, c->d_err,
@@ -1590,6 +1591,8 @@ ft_status ft_eval_batch(ft_ctx c, const ft_batch *bt, int32_t use_graph)
             return fail(c, FT_E_INVALID, "run %d: SFT slice out of range", r);
         if (R.n_bins < 1 || R.first_bin < 0 || R.first_bin + (int64_t)R.n_bins >= 0x7fffffffLL)
             return fail(c, FT_E_INVALID, "run %d: bad table columns", r);
+        if (R.n_bins >= (1 << 28))
+            return fail(c, FT_E_UNSUPPORTED, "run %d: batch tables hold fewer than 2^28 columns", r);
         if (R.n_f0 < 1 || R.n_f1 < 1 || R.n_sky < 1 || R.f0_begin < 0 || R.f1_begin < 0 || R.sky_begin < 0 ||
             (int64_t)R.f0_begin + R.n_f0 > bt->n_f0_total || (int64_t)R.f1_begin + R.n_f1 > bt->n_f1_total ||
             (int64_t)R.sky_begin + R.n_sky > bt->n_sky_total)

@@ -190,23 +190,156 @@ __global__ __launch_bounds__(256) void eval_direct_kernel(EvalRun r)
         eval_direct_one<GRID>(r, t);
 }
 
-// Persistent direct evaluation of batch runs whose grid is too small for the
-// tile kernel: workgroups pull (run, chunk of 256 templates) items.
-__global__ __launch_bounds__(256) void eval_batch_direct_kernel(const EvalRun *runs,
-                                                                const int2 *items, int n_items,
-                                                                unsigned *counter)
+// Persistent evaluation of batch runs whose grid is too small for the tile
+// kernel (or whose window does not fit in LDS).  A wavefront pulls an item
+// (run, chunk) from the queue; chunk = f0 chunk * n_js_chunks + js chunk,
+// covering up to SMALL_F0 consecutive f0 values and 64 consecutive (f1, sky)
+// pairs js = s * n_f1 + j, one pair per lane.  Per SFT a lane forms the
+// canonical Doppler factor and f1 * dt once and then the canonical FP64 bin of
+// each of its f0 values, gathering from the (cached) table; the gathers of SFT
+// k+1 are issued before the values of SFT k are added.  The bin is monotone
+// in f0 (f0 strictly increasing, g > 0), so the run's first and last bins
+// bound all of them and only those two are range-checked; a wave with an
+// out-of-range lane clamps every read into the row and flags the error.
+constexpr int SMALL_F0 = SMALL_F0_CHUNK;
+static_assert(SUM_BLOCK % 2 == 0, "blocks are walked in pairs of SFTs");
+
+// Read-only inputs that the kernel reaches through pointers held in the run
+// record, read through the constant address space so that wave-uniform reads
+// (velocities, time offsets, f0 values) become scalar loads.
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(4))) T *as_const(const T *p)
 {
-    __shared__ int item_sh;
+    return (const __attribute__((address_space(4))) T *)p;
+}
+typedef const __attribute__((address_space(1))) float global_float;
+
+// Velocity and time offset of one SFT (wave-uniform, loaded a step ahead).
+struct SmallSft {
+    double vx, vy, vz, dt;
+};
+
+__device__ __forceinline__ SmallSft small_sft(const EvalRun &r, int k)
+{
+    const auto *vk = as_const(r.v + 3 * (int64_t)k);
+    return {vk[0], vk[1], vk[2], as_const(r.dt)[k]};
+}
+
+// Bins of one SFT step as byte offsets (B - first_bin) * 4 into row k (exact
+// in 32 bits: rows hold fewer than 2^28 columns); returns false in every lane
+// if some lane of the wave left the table (the offsets are then clamped into
+// the row).
+__device__ __forceinline__ bool small_bins(const EvalRun &r, const SmallSft &q, const double (&f0v)[SMALL_F0],
+                                           double f1, double nx, double ny, double nz, uint32_t (&off)[SMALL_F0],
+                                           bool &bad)
+{
+    const double g = doppler_factor(q.vx, q.vy, q.vz, nx, ny, nz);
+    const double c = f1 * q.dt;
+    int B[SMALL_F0];
+#pragma unroll
+    for (int l = 0; l < SMALL_F0; ++l) B[l] = bin_fp64(f0v[l], c, g, r.t_sft);
+    // B[l] is non-decreasing in l (the last f0 repeats past the chunk's end)
+    const bool in = B[0] >= r.first_bin && B[SMALL_F0 - 1] - r.first_bin < r.n_bins;
+    const bool wave_in = __builtin_amdgcn_ballot_w64(!in) == 0;
+    if (!wave_in) {
+        bad |= !in;
+#pragma unroll
+        for (int l = 0; l < SMALL_F0; ++l) B[l] = min(max(B[l], r.first_bin), r.first_bin + r.n_bins - 1);
+    }
+    const uint32_t fb4 = (uint32_t)r.first_bin * 4u;
+#pragma unroll
+    for (int l = 0; l < SMALL_F0; ++l) off[l] = (uint32_t)B[l] * 4u - fb4;
+    return wave_in;
+}
+
+__device__ __forceinline__ void small_gather(const EvalRun &r, int k, const uint32_t (&off)[SMALL_F0],
+                                             float (&v)[SMALL_F0])
+{
+    const char *base = (const char *)(r.power_w + (int64_t)k * r.n_bins);
+#pragma unroll
+    for (int l = 0; l < SMALL_F0; ++l) v[l] = *(global_float *)(base + off[l]);
+}
+
+__device__ __forceinline__ void small_add(const float (&v)[SMALL_F0], float (&acc)[SMALL_F0])
+{
+#pragma unroll
+    for (int l = 0; l < SMALL_F0; ++l) acc[l] += v[l];
+}
+
+__global__ __launch_bounds__(64) void eval_batch_small_kernel(const EvalRun *__restrict__ runs,
+                                                              const int2 *__restrict__ items, int n_items,
+                                                              unsigned *counter)
+{
+    const int lane = threadIdx.x;
     for (;;) {
-        __syncthreads();
-        if (threadIdx.x == 0) item_sh = (int)atomicAdd(counter, 1u);
-        __syncthreads();
-        const int item = __builtin_amdgcn_readfirstlane(item_sh);
+        unsigned got = 0;
+        if (lane == 0) got = atomicAdd(counter, 1u);
+        const int item = __builtin_amdgcn_readlane((int)got, 0);
         if (item >= n_items) break;
         const int2 it = items[item];
-        const EvalRun r = runs[__builtin_amdgcn_readfirstlane(it.x)];
-        const int64_t t = (int64_t)it.y * 256 + threadIdx.x;
-        if (t < (int64_t)r.n_f0 * r.n_f1 * r.n_sky) eval_direct_one<true>(r, t);
+        const EvalRun r = runs[it.x];
+        const int n_js = r.n_f1 * r.n_sky;
+        const int n_jsc = (n_js + 63) / 64;
+        const int i0 = (it.y / n_jsc) * SMALL_F0;
+        const int n_i = min(SMALL_F0, r.n_f0 - i0);
+        const int js_raw = (it.y % n_jsc) * 64 + lane;
+        const bool live = js_raw < n_js;
+        const int js = live ? js_raw : n_js - 1;
+        const int j = js % r.n_f1, s = js / r.n_f1;
+        const double f1 = r.f1[j];
+        const double nx = r.sky[3 * s], ny = r.sky[3 * s + 1], nz = r.sky[3 * s + 2];
+        double f0v[SMALL_F0];
+#pragma unroll
+        for (int l = 0; l < SMALL_F0; ++l) f0v[l] = as_const(r.f0)[i0 + min(l, n_i - 1)];
+        float acc[SMALL_F0];
+        double tot[SMALL_F0];
+#pragma unroll
+        for (int l = 0; l < SMALL_F0; ++l) {
+            acc[l] = 0.f;
+            tot[l] = 0.0;
+        }
+        bool bad = false;
+        const int n = r.n_sft;
+        // Two value buffers in turn: the gathers of SFT k+1 go out before the
+        // values of SFT k are added; velocities are read a step ahead.  Reads
+        // past the last SFT re-read the last SFT (unused).  Summation blocks
+        // of SUM_BLOCK SFTs (even) are walked in pairs, so va holds the next
+        // block's first SFT when a block ends.
+        uint32_t off[SMALL_F0];
+        float va[SMALL_F0], vb[SMALL_F0];
+        SmallSft q = small_sft(r, 0);
+        small_bins(r, q, f0v, f1, nx, ny, nz, off, bad);
+        small_gather(r, 0, off, va);
+        q = small_sft(r, min(1, n - 1));
+        for (int kb = 0; kb < n; kb += SUM_BLOCK) {
+            const int ke = min(kb + SUM_BLOCK, n);
+            int k = kb;
+            for (; k + 1 < ke; k += 2) {
+                small_bins(r, q, f0v, f1, nx, ny, nz, off, bad);
+                q = small_sft(r, min(k + 2, n - 1));
+                small_gather(r, k + 1, off, vb);
+                small_add(va, acc);
+                small_bins(r, q, f0v, f1, nx, ny, nz, off, bad);
+                q = small_sft(r, min(k + 3, n - 1));
+                small_gather(r, min(k + 2, n - 1), off, va);
+                small_add(vb, acc);
+            }
+            if (k < ke) small_add(va, acc);  // odd tail: k = n - 1
+            if (r.sum_mode == FT_SUM_BLOCKED) {
+#pragma unroll
+                for (int l = 0; l < SMALL_F0; ++l) {
+                    tot[l] += (double)acc[l];
+                    acc[l] = 0.f;
+                }
+            }
+        }
+        if (bad && live) atomicOr(r.err, ERR_RANGE);
+        if (live) {
+            float *out = r.stats + (int64_t)js * r.n_f0 + i0;
+#pragma unroll
+            for (int l = 0; l < SMALL_F0; ++l)
+                if (l < n_i) out[l] = (float)(tot[l] + (double)acc[l]);
+        }
     }
 }
 
@@ -358,12 +491,12 @@ hipError_t launch_eval_grid_direct(const EvalRun &run, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_eval_batch_direct(const EvalRun *runs, const int2 *items, int n_items,
-                                    unsigned *counter, int grid, hipStream_t s)
+hipError_t launch_eval_batch_small(const EvalRun *runs, const int2 *items, int n_items, unsigned *counter,
+                                   int grid, hipStream_t s)
 {
     if (n_items <= 0) return hipSuccess;
-    hipLaunchKernelGGL(eval_batch_direct_kernel, dim3((unsigned)grid), dim3(256), 0, s, runs, items,
-                       n_items, counter);
+    hipLaunchKernelGGL(eval_batch_small_kernel, dim3((unsigned)grid), dim3(64), 0, s, runs, items, n_items,
+                       counter);
     return hipGetLastError();
 }
 

@@ -115,3 +115,117 @@ def test_batch_given_tables_and_errors(ft):
         with pytest.raises(ft.FtError) as e:
             c.eval_batch(bad, cp.t_mid, cp.v, cp.t_sft, cp.f0, cp.f1, cp.sky, cp.k, power=power)
         assert e.value.status == ft.FT_E_INVALID
+
+
+def _small_bank_batch(seed=47):
+    """Runs below the tile kernel's 32 f0 values, at the shapes where the
+    small-bank kernel has edges: f0 chunks of 8 (1, 5, 8, 9, 31 values, one
+    irregular grid), 64-lane (f1, sky) chunks (1, 48, 65, 176 pairs), SFT
+    counts with odd tails and partial 32-SFT sum blocks (1, 2, 31, 33, 517);
+    random tables wide enough for every track."""
+    pool = synth.campaign(1, seed=seed, n_pool=700, n_sft_range=(80, 600))
+    rng = np.random.default_rng(seed)
+    t_sft = pool.t_sft
+    vmax = float(np.max(np.linalg.norm(pool.v, axis=1)))
+    shapes = [(1, 1, 1, 1), (5, 11, 16, 517), (8, 3, 16, 33), (9, 13, 5, 31), (31, 1, 48, 2),
+              (5, 11, 16, 100), (12, 5, 13, 64)]
+    f0s, f1s, skys, runs, tables = [], [], [], [], []
+    off = n0 = n1 = ns = 0
+    for q, (nf0, nf1, nsk, nsft) in enumerate(shapes):
+        begin = int(rng.integers(0, len(pool.t_mid) - nsft + 1))
+        t_ref = float(pool.t_mid[begin])
+        f_lo = float(rng.uniform(100.0, 300.0))
+        if q == 3:   # irregular, strictly increasing
+            f0 = f_lo + np.cumsum(rng.uniform(0.2, 1.7, nf0)) / t_sft
+        else:
+            f0 = f_lo + np.arange(nf0) / t_sft
+        f1 = np.linspace(-1e-9, 0.0, nf1) if nf1 > 1 else np.array([-3e-10])
+        sky = synth.isotropic_sky(nsk, rng)
+        dt = pool.t_mid[begin:begin + nsft] - t_ref
+        cmin = min(f1.min() * dt.min(), f1.min() * dt.max(), f1.max() * dt.min(), f1.max() * dt.max())
+        cmax = max(f1.min() * dt.min(), f1.min() * dt.max(), f1.max() * dt.min(), f1.max() * dt.max())
+        lo = int(np.floor((f0[0] + cmin) * (1 - vmax) * t_sft)) - 2
+        hi = int(np.ceil((f0[-1] + cmax) * (1 + vmax) * t_sft)) + 2
+        table = rng.exponential(2.0, (nsft, hi - lo + 1)).astype(np.float32)
+        runs.append(dict(sft_begin=begin, n_sft=nsft, first_bin=lo, n_bins=hi - lo + 1,
+                         table_offset=off, f0_begin=n0, n_f0=nf0, f1_begin=n1, n_f1=nf1,
+                         sky_begin=ns, n_sky=nsk, t_ref=t_ref))
+        tables.append(table)
+        f0s.append(f0), f1s.append(f1), skys.append(sky)
+        off += table.size
+        n0, n1, ns = n0 + nf0, n1 + nf1, ns + nsk
+    return pool, runs, tables, np.concatenate(f0s), np.concatenate(f1s), np.concatenate(skys)
+
+
+def test_small_bank_runs_match_oracle(ft):
+    """Batch runs with fewer than 32 f0 values (the small-bank kernel): every
+    toplist member is the oracle's, with its exact FP64 statistic; the FP32
+    statistic is within the blocked-sum bound and equals a plain call's."""
+    import torch
+    pool, runs, tables, f0, f1, sky = _small_bank_batch()
+    k = 512
+    power = np.concatenate([t.ravel() for t in tables])
+    with ft.Context(0, torch.cuda.current_stream().cuda_stream) as c:
+        for use_graph in (0, 1):
+            c.eval_batch(runs, pool.t_mid, pool.v, pool.t_sft, f0, f1, sky, k, power=power,
+                         use_graph=use_graph)
+            batched = [c.batch_toplist(r, k) for r in range(len(runs))]
+            if use_graph == 0:
+                first = [_key(t) for t in batched]
+            else:
+                assert [_key(t) for t in batched] == first
+        plain = []
+        for R, table in zip(runs, tables):
+            sl = slice(R["sft_begin"], R["sft_begin"] + R["n_sft"])
+            c.set_sfts([R["n_sft"]], pool.t_mid[sl], pool.t_sft, R["first_bin"], table)
+            c.set_velocities(pool.v[sl])
+            rf0 = f0[R["f0_begin"]:R["f0_begin"] + R["n_f0"]]
+            c.eval_templates(rf0, f1[R["f1_begin"]:R["f1_begin"] + R["n_f1"]],
+                             sky[R["sky_begin"]:R["sky_begin"] + R["n_sky"]], R["t_ref"], k,
+                             np.array([rf0[0] - 1.0, rf0[-1] + 1.0]))
+            plain.append(c.toplist(0, k))
+    for R, table, top, ptop in zip(runs, tables, batched, plain):
+        sl = slice(R["sft_begin"], R["sft_begin"] + R["n_sft"])
+        s64, bad = oracle.eval_grid(pool.t_mid[sl], R["t_ref"], pool.t_sft, R["first_bin"], table,
+                                    None, pool.v[sl], f0[R["f0_begin"]:R["f0_begin"] + R["n_f0"]],
+                                    f1[R["f1_begin"]:R["f1_begin"] + R["n_f1"]],
+                                    sky[R["sky_begin"]:R["sky_begin"] + R["n_sky"]])
+        assert bad == -1
+        want = sorted(range(s64.size), key=lambda t: (-s64[t], t))[:k]
+        assert [t.index for t in top] == want, R
+        assert all(t.s64 == s64[t.index] for t in top)
+        e = 40 * 2.0 ** -24 + 4 * R["n_sft"] * 2.0 ** -53
+        assert all(abs(t.s32 - t.s64) <= e * t.s64 for t in top)
+        assert _key(top) == _key(ptop), R
+
+
+def test_small_bank_range_error(ft):
+    """A small-bank run whose table is too narrow for its tracks reports
+    FT_E_RANGE (device flag, reads kept inside the table); the next batch on
+    the same context is clean."""
+    import torch
+    pool, runs, tables, f0, f1, sky = _small_bank_batch(seed=48)
+    power = np.concatenate([t.ravel() for t in tables])
+    R = runs[1]
+    sl = slice(R["sft_begin"], R["sft_begin"] + R["n_sft"])
+    i, j, s = np.meshgrid(np.arange(R["n_f0"]), np.arange(R["n_f1"]), np.arange(R["n_sky"]),
+                          indexing="ij")
+    bins = oracle.bins_list(pool.t_mid[sl], R["t_ref"], pool.t_sft, pool.v[sl],
+                            f0[R["f0_begin"] + i.ravel()], f1[R["f1_begin"] + j.ravel()],
+                            sky[R["sky_begin"] + s.ravel()])
+    bad = [dict(Q) for Q in runs]
+    bad[1]["first_bin"] = int(bins.min()) + 1   # the lowest track bin falls below column 0
+    with ft.Context(0, torch.cuda.current_stream().cuda_stream) as c:
+        c.eval_batch(bad, pool.t_mid, pool.v, pool.t_sft, f0, f1, sky, 5, power=power)
+        with pytest.raises(ft.FtError) as e:
+            c.batch_toplist(0, 5)
+        assert e.value.status == ft.FT_E_RANGE
+        # the highest track bin one past the last column (a narrower slice)
+        high = [dict(Q) for Q in runs]
+        high[1]["n_bins"] = int(bins.max()) - R["first_bin"]
+        c.eval_batch(high, pool.t_mid, pool.v, pool.t_sft, f0, f1, sky, 5, power=power)
+        with pytest.raises(ft.FtError) as e:
+            c.batch_toplist(0, 5)
+        assert e.value.status == ft.FT_E_RANGE
+        c.eval_batch(runs, pool.t_mid, pool.v, pool.t_sft, f0, f1, sky, 5, power=power)
+        assert len(c.batch_toplist(1, 5)) == 5
