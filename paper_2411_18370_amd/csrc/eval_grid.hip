@@ -33,9 +33,10 @@
 // is linear in l).  The kernel forms t2 = t~ - u_lo directly (h carries the
 // shift); then u in [u_lo, u_hi) exactly when fract(t2) < u_hi - u_lo, and in
 // that case floor(t2) = floor(t~): one compare per run.  The extra rounding of
-// the shift is inside eta.  If any lane of the wave fails for any f1 value the
-// wave evaluates every template of the step with the canonical FP64
-// expression.  Either way every bin equals the canonical FP64 bin.
+// the shift is inside eta.  The values at the estimated bins are read first;
+// for every f1 value where some lane of the wave fails, the wave then re-reads
+// that f1 value's templates at their canonical FP64 bins.  Either way every bin
+// equals the canonical FP64 bin.
 //
 // Sums: FP32 within aligned blocks of 32 SFTs, block sums accumulated in FP64.
 #include "ft_internal.h"
@@ -258,71 +259,40 @@ __device__ __forceinline__ StepParams<JT> load_step(const StageParams<L, JT, NW,
 
 // Run estimates of one SFT step from its parameters (already in registers):
 // B[jl] = floor(t2) with t2 = f0 G + h (the LDS row offset of the run's first
-// bin), and the lanes (a wave mask) where a run fails the guard fract(t2) < w.
+// bin), and per f1 value the lanes (a wave mask) where a run fails the guard
+// fract(t2) < w.  Returns true if some run of the wave failed.
 template <int JT>
-__device__ __forceinline__ uint64_t run_bins(double f0_lane, const StepParams<JT> &q, int (&B)[JT])
+__device__ __forceinline__ bool run_bins(double f0_lane, const StepParams<JT> &q, int (&B)[JT], uint64_t (&fail)[JT])
 {
-    uint64_t fail = 0;
+    uint64_t any = 0;
 #pragma unroll
     for (int jl = 0; jl < JT; ++jl) {
         const double t = fma(f0_lane, q.G, q.h[jl]);
         B[jl] = (int)t;
-        fail |= __builtin_amdgcn_ballot_w64(!(__builtin_amdgcn_fract(t) < q.w));
+        fail[jl] = __builtin_amdgcn_ballot_w64(!(__builtin_amdgcn_fract(t) < q.w));
+        any |= fail[jl];
     }
-    return fail;
+    return any != 0;
 }
 
-// Guard fallback of one SFT step: the values at the canonical FP64 bins of
-// every template of the lane's runs.  All parameters are read first and all
-// bins formed before the table reads are issued, so the reads go out back to
-// back (one LDS round trip rather than one per template).
+// Guard fallback of one SFT step: for every f1 value with a failing run, the
+// values at the canonical FP64 bins of the lane's run replace the values read
+// at the estimated bins (the other f1 values keep theirs).
 template <int L, int JT, int NW, int KS>
-__device__ __forceinline__ void canonical_values(const StageParams<L, JT, NW, KS> &P,
-                                                 const Shared<L, JT, NW, KS> &sh, const TileGeom &tg,
-                                                 const float *wb, int base, int kk, int wave, int lane,
-                                                 double T, float (&out)[JT][L])
+__device__ __forceinline__ void canonical_fix(const StageParams<L, JT, NW, KS> &P, const Shared<L, JT, NW, KS> &sh,
+                                              const TileGeom &tg, const float *wb, int base, int kk, int wave,
+                                              int lane, double T, const uint64_t (&fail)[JT], float (&v)[JT][L])
 {
     const double g = P.g[wave][kk];
-    double c[JT], f0l[L];
 #pragma unroll
-    for (int jl = 0; jl < JT; ++jl) c[jl] = P.c[jl][kk];
+    for (int jl = 0; jl < JT; ++jl) {
+        if (fail[jl] == 0) continue;
+        const double c = P.c[jl][kk];
+        int idx[L];
 #pragma unroll
-    for (int l = 0; l < L; ++l) f0l[l] = sh.f0[min(lane * L + l, tg.n_in - 1)];
-    int idx[JT][L];
+        for (int l = 0; l < L; ++l) idx[l] = base + bin_fp64(sh.f0[min(lane * L + l, tg.n_in - 1)], c, g, T);
 #pragma unroll
-    for (int jl = 0; jl < JT; ++jl)
-#pragma unroll
-        for (int l = 0; l < L; ++l) idx[jl][l] = base + bin_fp64(f0l[l], c[jl], g, T);
-#pragma unroll
-    for (int jl = 0; jl < JT; ++jl)
-#pragma unroll
-        for (int l = 0; l < L; ++l) out[jl][l] = slow_read(wb + idx[jl][l]);
-}
-
-// Guard fallback accumulating directly: one run position l at a time (its JT
-// canonical bins formed, their reads issued together, then added), which
-// keeps the fallback's register footprint below the fast path's.
-template <int L, int JT, int NW, int KS>
-__device__ __forceinline__ void canonical_accumulate(const StageParams<L, JT, NW, KS> &P,
-                                                     const Shared<L, JT, NW, KS> &sh, const TileGeom &tg,
-                                                     const float *wb, int base, int kk, int wave, int lane,
-                                                     double T, float (&acc)[JT][L])
-{
-    const double g = P.g[wave][kk];
-    double c[JT];
-#pragma unroll
-    for (int jl = 0; jl < JT; ++jl) c[jl] = P.c[jl][kk];
-#pragma unroll
-    for (int l = 0; l < L; ++l) {
-        const double f0l = sh.f0[min(lane * L + l, tg.n_in - 1)];
-        int idx[JT];
-#pragma unroll
-        for (int jl = 0; jl < JT; ++jl) idx[jl] = base + bin_fp64(f0l, c[jl], g, T);
-        float v[JT];
-#pragma unroll
-        for (int jl = 0; jl < JT; ++jl) v[jl] = slow_read(wb + idx[jl]);
-#pragma unroll
-        for (int jl = 0; jl < JT; ++jl) acc[jl][l] += v[jl];
+        for (int l = 0; l < L; ++l) v[jl][l] = slow_read(wb + idx[l]);
     }
 }
 
@@ -344,7 +314,8 @@ __device__ __forceinline__ void accumulate_pipelined(const EvalRun &r, const Sta
 {
     const double T = r.t_sft;
     int B[JT];
-    bool ok = run_bins<JT>(f0_lane, load_step<L, JT, NW, KS>(P, wave, 0), B) == 0;
+    uint64_t fail[JT];
+    bool any = run_bins<JT>(f0_lane, load_step<L, JT, NW, KS>(P, wave, 0), B, fail);
     for (int kk = 0; kk < ks; ++kk) {
         const int kn = min(kk + 1, ks - 1);
         const StepParams<JT> qn = load_step<L, JT, NW, KS>(P, wave, kn);
@@ -355,22 +326,25 @@ __device__ __forceinline__ void accumulate_pipelined(const EvalRun &r, const Sta
 #pragma unroll
             for (int l = 0; l < L; ++l) v[jl][l] = wk[B[jl] + l];
         int Bn[JT];
+        uint64_t fn[JT];
         // keep the next bins ahead of the adds (the compiler would otherwise
         // sink them past the branch, after the wait for the gathers)
-        const int fast_next = run_bins<JT>(f0_lane, qn, Bn) == 0 ? 1 : 0;
+        const bool any_next = run_bins<JT>(f0_lane, qn, Bn, fn);
 #pragma unroll
-        for (int jl = 0; jl < JT; ++jl) asm volatile("" ::"v"(Bn[jl]));
-        asm volatile("" ::"s"(fast_next));
-        if (!ok)  // rare: some lane is within the guard margin of a bin edge
-            canonical_values<L, JT, NW, KS>(P, sh, tg, wb, kk * wtp - P.lo[kk], kk, wave, lane, T, v);
+        for (int jl = 0; jl < JT; ++jl) asm volatile("" ::"v"(Bn[jl]), "s"(fn[jl]));
+        if (any)  // rare: some lane is within the guard margin of a bin edge
+            canonical_fix<L, JT, NW, KS>(P, sh, tg, wb, kk * wtp - P.lo[kk], kk, wave, lane, T, fail, v);
 #pragma unroll
         for (int jl = 0; jl < JT; ++jl)
 #pragma unroll
             for (int l = 0; l < L; ++l) acc[jl][l] += v[jl][l];
         flush_block<L, JT>(r, k0 + kk, acc, tot);
 #pragma unroll
-        for (int jl = 0; jl < JT; ++jl) B[jl] = Bn[jl];
-        ok = fast_next != 0;
+        for (int jl = 0; jl < JT; ++jl) {
+            B[jl] = Bn[jl];
+            fail[jl] = fn[jl];
+        }
+        any = any_next;
     }
 }
 
@@ -454,20 +428,24 @@ __device__ __forceinline__ void eval_tile(const EvalRun &r, int64_t b, float *wi
                     acc[jl][0] += wb[base + B];
                 }
             } else {
+                // reads at the estimated bins first; the rare failing f1
+                // values (some lane within the guard margin of a bin edge)
+                // are then re-read at their canonical bins
                 const StepParams<JT> q = load_step<L, JT, NW, KS>(P, wave, kk);
                 int B[JT];
-                if (run_bins<JT>(f0_lane, q, B) == 0) {
-                    const float *wk = wb + kk * wtp;
+                uint64_t fail[JT];
+                const bool any = run_bins<JT>(f0_lane, q, B, fail);
+                const float *wk = wb + kk * wtp;
+                float v[JT][L];
 #pragma unroll
-                    for (int jl = 0; jl < JT; ++jl) {
-                        const float *wp = wk + B[jl];
+                for (int jl = 0; jl < JT; ++jl)
 #pragma unroll
-                        for (int l = 0; l < L; ++l) acc[jl][l] += wp[l];
-                    }
-                } else {
-                    // rare: some lane is within the guard margin of a bin edge
-                    canonical_accumulate<L, JT, NW, KS>(P, sh, tg, wb, kk * wtp - P.lo[kk], kk, wave, lane, T, acc);
-                }
+                    for (int l = 0; l < L; ++l) v[jl][l] = wk[B[jl] + l];
+                if (any) canonical_fix<L, JT, NW, KS>(P, sh, tg, wb, kk * wtp - P.lo[kk], kk, wave, lane, T, fail, v);
+#pragma unroll
+                for (int jl = 0; jl < JT; ++jl)
+#pragma unroll
+                    for (int l = 0; l < L; ++l) acc[jl][l] += v[jl][l];
             }
         }
         // blocks of SUM_BLOCK SFTs end with a stage (KS divides SUM_BLOCK)
