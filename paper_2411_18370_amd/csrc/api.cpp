@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <array>
 #include <map>
 #include <string>
 #include <numeric>
@@ -1554,6 +1555,7 @@ ft_status ft_eval_batch(ft_ctx c, const ft_batch *bt, int32_t use_graph)
         fetch(skyh, bt->sky_xyz, (size_t)bt->n_sky_total * 3) != hipSuccess)
         return fail(c, FT_E_INVALID, "cannot read the batch arrays");
     std::vector<double> vabs((size_t)NS);
+    std::map<std::pair<int32_t, int32_t>, std::array<double, 3>> slice_extremes;  // (min t, max t, max |v|)
     for (int64_t k = 0; k < NS; ++k) {
         const double x = vh[3 * k], y = vh[3 * k + 1], z = vh[3 * k + 2];
         if (!is_finite(tm[k]) || !is_finite(x) || !is_finite(y) || !is_finite(z))
@@ -1618,13 +1620,21 @@ ft_status ft_eval_batch(ft_ctx c, const ft_batch *bt, int32_t use_graph)
         for (int i = 0; i < R.n_f0; ++i)
             if (!is_finite(f0[i]) || !(f0[i] > 0.0) || (i > 0 && !(f0[i] > f0[i - 1])))
                 return fail(c, FT_E_INVALID, "run %d: f0 must be finite, > 0 and strictly increasing", r);
-        double dt_min = 1e300, dt_max = -1e300, vmax = 0.0;
-        for (int k = 0; k < R.n_sft; ++k) {
-            const double dt = tm[R.sft_begin + k] - R.t_ref;
-            dt_min = std::min(dt_min, dt);
-            dt_max = std::max(dt_max, dt);
-            vmax = std::max(vmax, vabs[R.sft_begin + k]);
+        // extremes of the run's SFT slice, once per distinct slice (campaigns
+        // often share one); t - t_ref rounds monotonically in t, so the
+        // extreme time offsets are those of the extreme mid-times
+        auto slice = slice_extremes.find({R.sft_begin, R.n_sft});
+        if (slice == slice_extremes.end()) {
+            std::array<double, 3> x{1e300, -1e300, 0.0};
+            for (int k = R.sft_begin; k < R.sft_begin + R.n_sft; ++k) {
+                x[0] = std::min(x[0], tm[k]);
+                x[1] = std::max(x[1], tm[k]);
+                x[2] = std::max(x[2], vabs[k]);
+            }
+            slice = slice_extremes.emplace(std::make_pair(R.sft_begin, R.n_sft), x).first;
         }
+        const double dt_min = slice->second[0] - R.t_ref, dt_max = slice->second[1] - R.t_ref;
+        const double vmax = slice->second[2];
         double f1_min = 1e300, f1_max = -1e300;
         for (int j = 0; j < R.n_f1; ++j) {
             f1_min = std::min(f1_min, f1[j]);
