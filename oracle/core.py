@@ -46,6 +46,13 @@ def _load():
             lib.ftor_eval_list.argtypes = [i32, P, f64, f64, i64, i32, P, P, P, i64, P, P, P, P, P]
             lib.ftor_eval_grid.argtypes = [i32, P, f64, f64, i64, i32, P, P, P, i64, P, i64, P,
                                            i64, P, P, P]
+            lib.ftor_pcos.argtypes = [i64, P, P, P]
+            lib.ftor_pcos.restype = None
+            lib.ftor_bins_binary.argtypes = [i32, P, f64, f64, P, i64, P, P, P, P, P, P]
+            lib.ftor_eval_binary.argtypes = [i32, P, f64, f64, i64, i32, P, P, P, i64, P, P, P, P, P,
+                                             P, P]
+            lib.ftor_bins_binary.restype = C.c_int
+            lib.ftor_eval_binary.restype = C.c_int
             lib.ftor_noise_moments.argtypes = [i32, P, P, P]
             lib.ftor_critical_ratio.argtypes = [i64, P, i32, P, P]
             lib.ftor_subband.argtypes = [i64, P, i32, P, P]
@@ -164,3 +171,43 @@ def grid_params(f0, f1, n_sky):
     j = np.tile(np.repeat(np.arange(f1.size), f0.size), n_sky)
     s = np.repeat(np.arange(n_sky), f0.size * f1.size)
     return f0[i], f1[j], s
+
+
+def pcos(x):
+    """(cos x, sin x) with the project's FP64 cosine/sine (|x| < 1.6e6)."""
+    lib = _load()
+    x = _f64(x)
+    c = np.empty_like(x)
+    s = np.empty_like(x)
+    lib.ftor_pcos(x.size, _p(x), _p(c), _p(s))
+    return c, s
+
+
+def bins_binary(t_mid, t_ref, t_sft, v, f0, sky, ap, omega, phib):
+    """Absolute bins [n_tmpl, n_sft] (int64) of binary-system templates."""
+    lib = _load()
+    t_mid, v, f0, sky, ap, omega, phib = map(_f64, (t_mid, v, f0, sky, ap, omega, phib))
+    n = f0.size
+    out = np.empty((n, t_mid.size), np.int64)
+    rc = lib.ftor_bins_binary(t_mid.size, _p(t_mid), t_ref, t_sft, _p(v), n, _p(f0), _p(sky), _p(ap),
+                              _p(omega), _p(phib), _p(out))
+    if rc != 0:
+        raise ValueError("ftor_bins_binary failed: %d" % rc)
+    return out
+
+
+def eval_binary(t_mid, t_ref, t_sft, first_bin, power, weight, v, f0, sky, ap, omega, phib):
+    """(S64 [n_tmpl], first_bad) for binary-system templates."""
+    lib = _load()
+    t_mid, v, f0, sky, ap, omega, phib = map(_f64, (t_mid, v, f0, sky, ap, omega, phib))
+    power = _f32(power)
+    weight = _f32(weight)
+    n = f0.size
+    out = np.empty(n, np.float64)
+    bad = C.c_int64(-1)
+    rc = lib.ftor_eval_binary(t_mid.size, _p(t_mid), t_ref, t_sft, first_bin, power.shape[1], _p(power),
+                              _p(weight), _p(v), n, _p(f0), _p(sky), _p(ap), _p(omega), _p(phib), _p(out),
+                              C.byref(bad))
+    if rc not in (0, -3):
+        raise ValueError("ftor_eval_binary failed: %d" % rc)
+    return out, bad.value

@@ -148,6 +148,132 @@ int ftor_eval_grid(int32_t n_sft, const double *t_mid, double t_ref, double t_sf
     return bad >= 0 ? OR_E_RANGE : OR_OK;
 }
 
+/* ---------------------------------------------------------------------------
+ * Sources in circular binary systems (Eq. track with a_p > 0, no spindown).
+ *
+ *   f_k = f0 * (1 + v_k . n - a_p Omega cos(Omega (t_k - t_ref) - phi_b))
+ *
+ * (the orbital phase phi_b refers to t_ref).  Canonical operation order:
+ *   d = (vx*nx + vy*ny) + vz*nz ; g = 1 + d ; ph = Omega*dt - phi_b ;
+ *   cb = pcos(ph) ; e = (a_p*Omega)*cb ; h = g - e ; f = f0*h ; x = f*T ;
+ *   B = floor(x + 0.5).
+ * With a_p = 0, e = 0 and the bin equals the isolated track's with f1 = 0.
+ *
+ * pcos/psin: the project's FP64 cosine and sine, a fixed sequence of IEEE
+ * additions and multiplications (so any implementation of the same sequence
+ * gives the same bits):
+ *   range reduction (Cody and Waite, 1980): q = floor(x*2/pi + 1/2),
+ *     r = ((x - q*P1) - q*P2) - q*P3 with pi/2 = P1 + P2 + P3, P1 and P2 of
+ *     33 significant bits (q*P1, q*P2 exact for |q| < 2^20, i.e. |x| < 1.6e6);
+ *   Taylor polynomials on |r| <= pi/4 (truncation below 1e-19), Horner order:
+ *     sin r = r + (r*r2)*p_s(r2), p_s = -1/3! + r2(1/5! - r2(1/7! - ... + r2/17!))
+ *     cos r = (1 - r2/2) + (r2*r2)*p_c(r2), p_c = 1/4! - r2(1/6! - ... - r2/18!)
+ *   quadrant n = q mod 4: cos x = (c, -s, -c, s)[n], sin x = (s, c, -s, -c)[n].
+ * Coefficients are 1/n! rounded to double (hex literals).
+ * ------------------------------------------------------------------------- */
+#define PC_TWO_OVER_PI 0x1.45f306dc9c883p-1
+#define PC_P1 0x1.921fb54400000p+0
+#define PC_P2 0x1.0b4611a600000p-34
+#define PC_P3 0x1.3198a2e037073p-69
+
+static void psincos(double x, double *sin_out, double *cos_out)
+{
+    double t = x * PC_TWO_OVER_PI;
+    double q = floor(t + 0.5);
+    double r = x - q * PC_P1;
+    r = r - q * PC_P2;
+    r = r - q * PC_P3;
+    double r2 = r * r;
+    double ps = 0x1.952c77030ad4ap-49;            /*  1/17! */
+    ps = ps * r2; ps = ps - 0x1.ae7f3e733b81fp-41; /* -1/15! */
+    ps = ps * r2; ps = ps + 0x1.6124613a86d09p-33; /*  1/13! */
+    ps = ps * r2; ps = ps - 0x1.ae64567f544e4p-26; /* -1/11! */
+    ps = ps * r2; ps = ps + 0x1.71de3a556c734p-19; /*  1/9!  */
+    ps = ps * r2; ps = ps - 0x1.a01a01a01a01ap-13; /* -1/7!  */
+    ps = ps * r2; ps = ps + 0x1.1111111111111p-7;  /*  1/5!  */
+    ps = ps * r2; ps = ps - 0x1.5555555555555p-3;  /* -1/3!  */
+    double s = r + (r * r2) * ps;
+    double pc = -0x1.6827863b97d97p-53;            /* -1/18! */
+    pc = pc * r2; pc = pc + 0x1.ae7f3e733b81fp-45; /*  1/16! */
+    pc = pc * r2; pc = pc - 0x1.93974a8c07c9dp-37; /* -1/14! */
+    pc = pc * r2; pc = pc + 0x1.1eed8eff8d898p-29; /*  1/12! */
+    pc = pc * r2; pc = pc - 0x1.27e4fb7789f5cp-22; /* -1/10! */
+    pc = pc * r2; pc = pc + 0x1.a01a01a01a01ap-16; /*  1/8!  */
+    pc = pc * r2; pc = pc - 0x1.6c16c16c16c17p-10; /* -1/6!  */
+    pc = pc * r2; pc = pc + 0x1.5555555555555p-5;  /*  1/4!  */
+    double c = (1.0 - 0.5 * r2) + (r2 * r2) * pc;
+    int n = (int)((int64_t)q & 3);
+    double cv = n == 0 ? c : n == 1 ? -s : n == 2 ? -c : s;
+    double sv = n == 0 ? s : n == 1 ? c : n == 2 ? -s : -c;
+    if (sin_out) *sin_out = sv;
+    if (cos_out) *cos_out = cv;
+}
+
+/* The project cosine and sine of x[0..n) (|x| < 1.6e6). */
+void ftor_pcos(int64_t n, const double *x, double *c_out, double *s_out)
+{
+    for (int64_t i = 0; i < n; ++i) psincos(x[i], s_out ? s_out + i : NULL, c_out ? c_out + i : NULL);
+}
+
+/* Absolute bin of a binary-system template at an SFT (offset dt, velocity v). */
+static int64_t binary_bin(double f0, const double *n, double ap, double omega, double phib,
+                          const double *v, double dt, double t_sft)
+{
+    double g = doppler_factor(v, n);
+    double ph = omega * dt;
+    ph = ph - phib;
+    double cb;
+    psincos(ph, NULL, &cb);
+    double aw = ap * omega;
+    double e = aw * cb;
+    double h = g - e;
+    double f = f0 * h;
+    double x = f * t_sft;
+    return (int64_t)floor(x + 0.5);
+}
+
+/* Bins of binary templates: bins[t*n_sft + k]. */
+int ftor_bins_binary(int32_t n_sft, const double *t_mid, double t_ref, double t_sft, const double *v,
+                     int64_t n_tmpl, const double *f0, const double *sky, const double *ap,
+                     const double *omega, const double *phib, int64_t *bins)
+{
+    if (n_sft <= 0 || n_tmpl < 0 || t_sft <= 0.0) return OR_E_INVALID;
+    for (int64_t t = 0; t < n_tmpl; ++t)
+        for (int32_t k = 0; k < n_sft; ++k)
+            bins[t * n_sft + k] = binary_bin(f0[t], sky + 3 * t, ap[t], omega[t], phib[t],
+                                             v + 3 * (int64_t)k, t_mid[k] - t_ref, t_sft);
+    return OR_OK;
+}
+
+/* Statistic of binary templates (sequential FP64 sum in SFT order; templates
+ * are independent and run on separate OpenMP threads). */
+int ftor_eval_binary(int32_t n_sft, const double *t_mid, double t_ref, double t_sft, int64_t first_bin,
+                     int32_t n_bins, const float *power, const float *weight, const double *v, int64_t n_tmpl,
+                     const double *f0, const double *sky, const double *ap, const double *omega,
+                     const double *phib, double *s_out, int64_t *first_bad)
+{
+    if (n_sft <= 0 || n_bins <= 0 || n_tmpl < 0 || t_sft <= 0.0) return OR_E_INVALID;
+    int64_t bad = -1;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t t = 0; t < n_tmpl; ++t) {
+        double acc = 0.0;
+        for (int32_t k = 0; k < n_sft; ++k) {
+            int64_t b = binary_bin(f0[t], sky + 3 * t, ap[t], omega[t], phib[t], v + 3 * (int64_t)k,
+                                   t_mid[k] - t_ref, t_sft) - first_bin;
+            if (b < 0 || b >= n_bins) {
+#pragma omp critical
+                { if (bad < 0 || t < bad) bad = t; }
+                acc = NAN;
+                break;
+            }
+            acc = acc + weight_of(weight, k) * (double)power[(int64_t)k * n_bins + b];
+        }
+        s_out[t] = acc;
+    }
+    if (first_bad) *first_bad = bad;
+    return bad >= 0 ? OR_E_RANGE : OR_OK;
+}
+
 /* Noise-hypothesis moments: mu_G = 2 sum w, sigma_G = 2 sqrt(sum w^2)
  * (Sec. II.B.1), sums sequential in SFT order. */
 void ftor_noise_moments(int32_t n_sft, const float *weight, double *mu, double *sigma)

@@ -385,3 +385,82 @@ def label_campaign(n_runs: int, seed: int, base: "Workload", amp_range=(0.005, 0
     alpha = np.mod(np.arctan2(inj_sky[:, 1], inj_sky[:, 0]), 2.0 * np.pi)
     raw = np.stack([amp, cos_iota, psi, inj_sky[:, 2], alpha, f_inj], axis=1)
     return cp, raw
+
+
+@dataclass
+class BinaryWorkload:
+    """SFTs plus a list bank of sources in circular binary systems (inputs only)."""
+    name: str
+    t_sft: float
+    n_sft_per_det: list
+    t_mid: np.ndarray            # [N] float64, detector-major, time ascending
+    v: np.ndarray                # [N,3] float64, v/c
+    arms: np.ndarray             # [N,6]
+    t_ref: float
+    first_bin: int
+    n_bins: int
+    power: np.ndarray            # [N, n_bins] float32
+    f0: np.ndarray               # [n] Hz
+    sky: np.ndarray              # [n,3]
+    ap: np.ndarray               # [n] light-seconds
+    omega: np.ndarray            # [n] rad/s
+    phib: np.ndarray             # [n] rad at t_ref
+    region: dict                 # f0_lo, f0_hi, ap_lo, ap_hi, omega_lo, omega_hi
+    k: int
+    sub_edges: np.ndarray
+
+    @property
+    def n_sft(self):
+        return int(self.t_mid.shape[0])
+
+    @property
+    def n_templates(self):
+        return int(self.f0.size)
+
+    @property
+    def evals(self):
+        return self.n_templates * self.n_sft
+
+
+DAY = 86400.0
+
+
+def binary_band(seed: int = 3, n_tmpl: int = 10_000, n_per_det: int = 5000, f_lo: float = 110.5,
+                width: float = 0.125, t_sft: float = 1024.0, gap: float = 0.1, period_days=(7.0, 15.0),
+                ap_range=(5.0, 15.0), k: int = 10, n_sub: int = 5, with_noise: bool = True) -> BinaryWorkload:
+    """The search setup of the real-data section as synthetic input: 2 detectors,
+    SFTs of T = 1024 s overlapping by half (a new SFT every 512 s; 10% of the slots
+    missing), a 0.125 Hz band at f_lo, orbital periods 7-15 days and projected
+    semimajor axes 5-15 light-seconds; `n_tmpl` templates drawn uniformly in each
+    parameter (f0, isotropic sky, a_p, period, phi_b in [0, 2 pi)); noise table."""
+    rng = np.random.default_rng(seed)
+    stride = 0.5 * t_sft
+    t_parts, v_parts, a_parts = [], [], []
+    for d in range(2):
+        n_slots = int(math.ceil(n_per_det / (1.0 - gap)))
+        slots = np.sort(rng.choice(n_slots, size=n_per_det, replace=False))
+        t = EPOCH + slots.astype(np.float64) * stride + 0.5 * t_sft
+        t_parts.append(t)
+        v_parts.append(detector_velocity(t, DETECTORS[d]))
+        a_parts.append(detector_arms(t, DETECTORS[d]))
+    t_mid = np.concatenate(t_parts)
+    v = np.concatenate(v_parts)
+    arms = np.concatenate(a_parts)
+    f_hi = f_lo + width
+    om_lo, om_hi = 2.0 * np.pi / (period_days[1] * DAY), 2.0 * np.pi / (period_days[0] * DAY)
+    f0 = rng.uniform(f_lo, f_hi, n_tmpl)
+    sky = isotropic_sky(n_tmpl, rng)
+    ap = rng.uniform(ap_range[0], ap_range[1], n_tmpl)
+    omega = 2.0 * np.pi / (rng.uniform(period_days[0], period_days[1], n_tmpl) * DAY)
+    phib = rng.uniform(0.0, 2.0 * np.pi, n_tmpl)
+    vmax = float(np.max(np.linalg.norm(v, axis=1)))
+    awmax = ap_range[1] * om_hi
+    first_bin = int(math.floor(f_lo * (1.0 - vmax - awmax) * t_sft)) - 2
+    last = int(math.ceil(f_hi * (1.0 + vmax + awmax) * t_sft)) + 2
+    n_bins = last - first_bin + 1
+    power = noise_power(t_mid.size, n_bins, rng) if with_noise else \
+        np.zeros((t_mid.size, n_bins), np.float32)
+    edges = f_lo + width * np.arange(n_sub + 1) / n_sub
+    region = dict(f0_lo=f_lo, f0_hi=f_hi, ap_lo=ap_range[0], ap_hi=ap_range[1], omega_lo=om_lo, omega_hi=om_hi)
+    return BinaryWorkload("binary-2det-%dsft-%gHz" % (2 * n_per_det, f_lo), t_sft, [n_per_det] * 2, t_mid, v,
+                          arms, EPOCH, first_bin, n_bins, power, f0, sky, ap, omega, phib, region, k, edges)

@@ -1,0 +1,129 @@
+"""Pins of the oracle's sources in circular binary systems (Eq. track with
+a_p > 0): its cosine against libm, the track against the isolated track and
+against an independent libm track, the statistic against sequential sums, and
+the random template bank against the distribution of the binary appendix's
+uniform coordinates (Eq. unif_transform)."""
+import math
+
+import numpy as np
+import pytest
+from scipy import stats as sps
+
+import oracle
+from oracle import bank
+from paper_2411_18370_amd import synth
+
+
+def test_library_cosine_against_libm():
+    rng = np.random.default_rng(0)
+    x = np.concatenate([np.linspace(-50.0, 50.0, 100_001), rng.uniform(-1.5e6, 1.5e6, 100_000),
+                        rng.uniform(-1e-3, 1e-3, 10_000)])
+    c, s = oracle.pcos(x)
+    assert np.max(np.abs(c - np.cos(x))) <= 2.0 ** -52
+    assert np.max(np.abs(s - np.sin(x))) <= 2.0 ** -52
+    # exact limits: cos 0 = 1, sin x = x and cos x = 1 for |x| far below 2^-26
+    tiny = np.array([0.0, 1e-300, -3e-12, 5e-10])
+    c, s = oracle.pcos(tiny)
+    assert np.all(c == 1.0) and np.all(s == tiny)
+    # quadrant selection: cos and sin of multiples of pi/2
+    q = np.arange(-8, 9) * (math.pi / 2)
+    c, s = oracle.pcos(q)
+    assert np.allclose(c, np.round(np.cos(q)), atol=1e-15)
+    assert np.allclose(s, np.round(np.sin(q)), atol=1e-15)
+
+
+def _small(seed=11, n=400, n_per_det=150):
+    return synth.binary_band(seed=seed, n_tmpl=n, n_per_det=n_per_det)
+
+
+def test_binary_track_reduces_to_isolated_track():
+    """a_p = 0: the binary bin is the isolated track's bin with f1 = 0, bit for bit."""
+    w = _small()
+    zero = np.zeros_like(w.ap)
+    b2 = oracle.bins_binary(w.t_mid, w.t_ref, w.t_sft, w.v, w.f0, w.sky, zero, w.omega, w.phib)
+    b1 = oracle.bins_list(w.t_mid, w.t_ref, w.t_sft, w.v, w.f0, np.zeros_like(w.f0), w.sky)
+    assert np.array_equal(b1, b2)
+
+
+def test_binary_track_against_independent_libm_track():
+    """The track written out with numpy and libm's cosine: every bin agrees except
+    where x lies within 1e-7 of a half-bin (where rounding may legitimately differ).
+    A flipped sign or a missing factor of the orbital term moves bins by up to
+    ~18 (a_p Omega f0 T_sft), so it cannot pass."""
+    w = _small(n=2000)
+    dt = w.t_mid - w.t_ref
+    d = (w.v[None, :, 0] * w.sky[:, None, 0] + w.v[None, :, 1] * w.sky[:, None, 1]) \
+        + w.v[None, :, 2] * w.sky[:, None, 2]
+    ph = w.omega[:, None] * dt[None, :] - w.phib[:, None]
+    x = w.f0[:, None] * ((1.0 + d) - (w.ap * w.omega)[:, None] * np.cos(ph)) * w.t_sft
+    want = np.floor(x + 0.5).astype(np.int64)
+    got = oracle.bins_binary(w.t_mid, w.t_ref, w.t_sft, w.v, w.f0, w.sky, w.ap, w.omega, w.phib)
+    diff = got != want
+    near = np.abs((x + 0.5) - np.round(x + 0.5)) < 1e-7
+    assert not np.any(diff & ~near)
+    assert diff.mean() < 1e-5
+    # the orbital term is there: without it most bins would move
+    x0 = w.f0[:, None] * (1.0 + d) * w.t_sft
+    assert np.mean(np.floor(x0 + 0.5) != got) > 0.5
+
+
+def test_binary_statistic_is_sequential_sum_over_track_bins():
+    w = _small(n=300)
+    bins = oracle.bins_binary(w.t_mid, w.t_ref, w.t_sft, w.v, w.f0, w.sky, w.ap, w.omega, w.phib)
+    s64, bad = oracle.eval_binary(w.t_mid, w.t_ref, w.t_sft, w.first_bin, w.power, None, w.v, w.f0,
+                                  w.sky, w.ap, w.omega, w.phib)
+    assert bad == -1
+    vals = w.power[np.arange(w.n_sft)[None, :], bins - w.first_bin].astype(np.float64)
+    want = np.cumsum(vals, axis=1)[:, -1]   # sequential in SFT order
+    assert np.array_equal(s64, want)
+    # noise only: the mean of S over templates is near 2 N (chi^2_2 per bin)
+    assert abs(s64.mean() / (2 * w.n_sft) - 1.0) < 0.02
+
+
+def test_binary_track_leaving_the_table_is_flagged():
+    w = _small(n=50)
+    first = w.first_bin + 40          # the lowest tracks now start below the table
+    s64, bad = oracle.eval_binary(w.t_mid, w.t_ref, w.t_sft, first, w.power[:, 40:], None, w.v,
+                                  w.f0, w.sky, w.ap, w.omega, w.phib)
+    bins = oracle.bins_binary(w.t_mid, w.t_ref, w.t_sft, w.v, w.f0, w.sky, w.ap, w.omega, w.phib)
+    out = np.any((bins < first) | (bins >= first + w.n_bins - 40), axis=1)
+    assert out.any() and bad == int(np.argmax(out))
+
+
+REGION = dict(f0_lo=110.5, f0_hi=110.625, ap_lo=5.0, ap_hi=15.0, omega_lo=2 * np.pi / (15 * 86400.0),
+              omega_hi=2 * np.pi / (7 * 86400.0))
+
+
+def test_random_bank_is_uniform_in_the_xi_coordinates():
+    """Each uniform coordinate of Eq. unif_transform (up to its constant) is an
+    affine image of one Philox uniform, so a draw uniform in xi is recovered
+    exactly up to rounding; the uniforms themselves pass a KS test."""
+    n = 200_000
+    u = bank.uniforms(7, 0, n)
+    f0, sky, ap, om, phib = bank.random_binary_bank(7, 0, n, **REGION)
+    r = REGION
+    for x, lo, hi, p, j in ((f0, r["f0_lo"], r["f0_hi"], 6, 0), (ap, r["ap_lo"], r["ap_hi"], 3, 3),
+                            (om, r["omega_lo"], r["omega_hi"], 4, 4)):
+        assert np.all((x >= lo * (1 - 1e-15)) & (x <= hi * (1 + 1e-15)))
+        xi = (x ** p - lo ** p) / (hi ** p - lo ** p)
+        assert np.max(np.abs(xi - u[:, j])) < 1e-9
+    alpha = np.mod(np.arctan2(sky[:, 1], sky[:, 0]), 2 * np.pi)
+    assert np.max(np.abs(alpha / (2 * np.pi) - u[:, 1])) < 1e-12
+    assert np.max(np.abs((sky[:, 2] + 1) / 2 - u[:, 2])) < 1e-15
+    assert np.max(np.abs(phib / (2 * np.pi) - u[:, 5])) < 1e-15
+    assert np.max(np.abs(np.linalg.norm(sky, axis=1) - 1.0)) < 1e-15
+    assert all(sps.kstest(u[:, j], "uniform").pvalue > 1e-4 for j in range(6))
+    # a template depends on (seed, index) only
+    g = bank.random_binary_bank(7, 1234, 10, **REGION)
+    assert all(np.array_equal(a[1234:1244], b) for a, b in zip((f0, sky, ap, om, phib), g))
+
+
+@pytest.mark.parametrize("p", [3, 4, 6])
+def test_bank_roots_are_accurate(p):
+    rng = np.random.default_rng(p)
+    lo, hi = {3: (5.0, 15.0), 4: (4.8e-6, 1.04e-5), 6: (100.0, 300.0)}[p]
+    u = rng.uniform(0, 1, 50_000)
+    z = bank.root(lo, hi, u, p)
+    y = lo ** p + u * (hi ** p - lo ** p)
+    exact = np.array([float(math.pow(float(v), 1.0 / p)) for v in y[:2000]])
+    assert np.max(np.abs(z[:2000] - exact) / exact) < 8 * 2.0 ** -53
