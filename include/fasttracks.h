@@ -99,7 +99,7 @@ ft_status ft_set_sfts(ft_ctx ctx, int32_t n_det, const int32_t *n_sft, const dou
  */
 ft_status ft_set_velocities(ft_ctx ctx, const double *v_over_c);
 
-enum { FT_BANK_GRID = 0, FT_BANK_LIST = 1 };
+enum { FT_BANK_GRID = 0, FT_BANK_LIST = 1, FT_BANK_BINARY = 2 };
 
 /*
  * Template bank (Sec. III: a batch of templates with no assumption on its
@@ -108,6 +108,17 @@ enum { FT_BANK_GRID = 0, FT_BANK_LIST = 1 };
  *   GRID: f0[n_f0] strictly increasing and > 0, f1[n_f1], sky_xyz[n_sky][3]
  *         unit vectors; template index t = (s*n_f1 + j)*n_f0 + i.
  *   LIST: f0[n_list] > 0, f1[n_list], sky_xyz[n_list][3]; template index t.
+ *   BINARY: sources in circular binary systems (Eq. track with a_p > 0, no
+ *         spindown; the paper's benchmark and search workload):
+ *         f0[n_list] > 0, sky_xyz[n_list][3], ap[n_list] (projected semimajor
+ *         axis, light-seconds, >= 0), omega[n_list] (orbital angular frequency,
+ *         rad/s, >= 0, a_p*Omega < 1/2), phib[n_list] (orbital phase at t_ref,
+ *         rad); f1 is ignored.  Track
+ *           f_k = f0 (1 + v_k.n - a_p Omega cos(Omega (t_k - t_ref) - phi_b)),
+ *         canonical order d = (vx nx + vy ny) + vz nz, g = 1 + d,
+ *         ph = Omega dt - phi_b, e = (a_p Omega) lib_cos(ph), f = f0 (g - e),
+ *         B = floor(f T + 1/2), lib_cos the library cosine (ft_lib_sincos);
+ *         |Omega dt| + |phi_b| < 1.5e6.  Index mode FT_INDEX_FP64 only.
  * Every f0 + f1*(t_k - t_ref) must be > 0.
  */
 typedef struct {
@@ -118,7 +129,19 @@ typedef struct {
     const double *f0;
     const double *f1;
     const double *sky_xyz;
+    const double *ap, *omega, *phib;  /* BINARY banks only (else ignored) */
 } ft_bank;
+
+/*
+ * ft_lib_sincos -- the library's FP64 cosine and sine (the phase function of
+ * BINARY banks): a fixed sequence of IEEE additions and multiplications --
+ * Cody-Waite reduction by pi/2 (three-part constant, 33-bit leading parts)
+ * and Taylor polynomials to r^17 / r^18 on |r| <= pi/4 in Horner form -- so
+ * the same bits come out of any implementation of that sequence.  Within
+ * 2^-52 of the exact values.  x[0..n) finite with |x| < 1.5e6 (host or device
+ * arrays); cos_out / sin_out [n] (either may be NULL).  Synchronous.
+ */
+ft_status ft_lib_sincos(ft_ctx ctx, const double *x, int64_t n, double *cos_out, double *sin_out);
 
 enum {
     FT_INDEX_FP64 = 0,    /* exact: canonical FP64 bins (default)                       */
@@ -166,6 +189,46 @@ typedef struct {
  */
 ft_status ft_eval_templates(ft_ctx ctx, const ft_bank *bank, double t_ref,
                             const ft_eval_opts *opts, float *stats);
+
+/*
+ * Random template banks of sources in circular binary systems (Sec. IV.A: a
+ * random bank drawn uniformly in the uniform-density coordinates, which for
+ * this model are, up to constants, (f0^6, alpha, sin delta, a_p^3, Omega^4,
+ * phi_b) -- Eq. unif_transform of the binary appendix).  The region is the box
+ * [f0_lo, f0_hi] x full sky x [ap_lo, ap_hi] x [omega_lo, omega_hi] x [0, 2 pi);
+ * 0 < lo <= hi for f0, a_p and Omega, ap_hi * omega_hi < 1/2.
+ */
+typedef struct {
+    double f0_lo, f0_hi;        /* Hz                    */
+    double ap_lo, ap_hi;        /* light-seconds         */
+    double omega_lo, omega_hi;  /* rad/s                 */
+} ft_binary_region;
+
+/*
+ * ft_gen_binary_bank -- templates first .. first + n - 1 of the random bank
+ * with key `seed`: f0[n], sky_xyz[n][3], ap[n], omega[n], phib[n] (host or
+ * device arrays, caller-owned).  Template i depends on (seed, i) only: six
+ * 53-bit uniforms (m + 1/2) 2^-53 from Philox-4x32-10 with counter
+ * (i_lo, i_hi, 0, 1 + j), j = 0, 1, 2, key (seed_lo, seed_hi); f0, a_p and
+ * Omega are p-th roots of lo^p + u (hi^p - lo^p) (p = 6, 3, 4) by 12 Newton
+ * steps from lo + u (hi - lo); alpha = 2 pi u1, sin delta = 2 u2 - 1,
+ * phi_b = 2 pi u5 -- a fixed sequence of IEEE operations, reproducible bit
+ * for bit.  Synchronous.  Errors: FT_E_INVALID (region, sizes, null arrays).
+ */
+ft_status ft_gen_binary_bank(ft_ctx ctx, const ft_binary_region *region, uint64_t seed, int64_t first,
+                             int64_t n, double *f0, double *sky_xyz, double *ap, double *omega,
+                             double *phib);
+
+/*
+ * ft_eval_binary_random -- generate templates 0 .. n-1 of the random bank on
+ * the device (as ft_gen_binary_bank) and evaluate them as a BINARY bank with
+ * `opts` (the paper's timed pipeline: template generation, bins, gathers,
+ * sums), building the toplists.  Candidates report f0 and the sky vector;
+ * ft_gen_binary_bank(first = index, n = 1) recovers the orbital parameters.
+ * Asynchronous; errors as ft_eval_templates.  1 <= n < 2^31.
+ */
+ft_status ft_eval_binary_random(ft_ctx ctx, const ft_binary_region *region, uint64_t seed, int64_t n,
+                                double t_ref, const ft_eval_opts *opts, float *stats);
 
 /* One toplist entry. */
 typedef struct {

@@ -62,11 +62,15 @@ struct ft_ctx_s {
     uint32_t *d_err = nullptr;
 
     // bank
-    std::vector<double> f0_h, f1_h, sky_h, sky_tile_h;
+    std::vector<double> f0_h, f1_h, sky_h, sky_tile_h, ap_h, omega_h, phib_h;
     std::vector<int32_t> perm_h;
     double *d_f0 = nullptr, *d_f1 = nullptr, *d_sky = nullptr, *d_edges = nullptr,
-           *d_sky_tile = nullptr;
-    size_t cap_f0 = 0, cap_f1 = 0, cap_sky = 0, cap_edges = 0, cap_sky_tile = 0;
+           *d_sky_tile = nullptr, *d_bin = nullptr;  // d_bin: binary banks' [3][n] a_p, Omega, phi_b
+    size_t cap_f0 = 0, cap_f1 = 0, cap_sky = 0, cap_edges = 0, cap_sky_tile = 0, cap_bin = 0;
+    double *d_sincos = nullptr;  // ft_lib_sincos staging
+    size_t cap_sincos = 0;
+    double *d_genbank = nullptr;  // ft_gen_binary_bank staging: f0 | sky | ap | omega | phib
+    size_t cap_genbank = 0;
     int32_t *d_perm = nullptr;
     size_t cap_perm = 0;
     float *d_stats = nullptr;
@@ -456,6 +460,9 @@ void ft_destroy(ft_ctx c)
     release(&c->d_mu_sigma, nullptr);
     release(&c->d_err, nullptr);
     release(&c->d_f0, &c->cap_f0);
+    release(&c->d_bin, &c->cap_bin);
+    release(&c->d_sincos, &c->cap_sincos);
+    release(&c->d_genbank, &c->cap_genbank);
     release(&c->d_f1, &c->cap_f1);
     release(&c->d_sky, &c->cap_sky);
     release(&c->d_sky_tile, &c->cap_sky_tile);
@@ -830,8 +837,12 @@ static ft_status prepare_bank(ft_ctx c, const ft_bank *bank, double t_ref, EvalR
     if (!c->have_sfts || !c->have_vel) return fail(c, FT_E_STATE, "ft_set_sfts and ft_set_velocities must come first");
     if (!is_finite(t_ref)) return fail(c, FT_E_INVALID, "t_ref must be finite");
     grid = bank->kind == FT_BANK_GRID;
-    if (!grid && bank->kind != FT_BANK_LIST) return fail(c, FT_E_INVALID, "unknown bank kind %d", bank->kind);
-    if (!bank->f0 || !bank->f1 || !bank->sky_xyz) return fail(c, FT_E_INVALID, "bank arrays must be non-null");
+    const bool binary = bank->kind == FT_BANK_BINARY;
+    if (!grid && !binary && bank->kind != FT_BANK_LIST) return fail(c, FT_E_INVALID, "unknown bank kind %d", bank->kind);
+    if (!bank->f0 || (!binary && !bank->f1) || !bank->sky_xyz) return fail(c, FT_E_INVALID, "bank arrays must be non-null");
+    if (binary && (!bank->ap || !bank->omega || !bank->phib))
+        return fail(c, FT_E_INVALID, "binary banks need ap, omega and phib");
+    if (binary && c->n_bins >= (1 << 28)) return fail(c, FT_E_UNSUPPORTED, "binary banks need tables of fewer than 2^28 columns");
     int64_t n0, n1, ns;
     if (grid) {
         n0 = bank->n_f0;
@@ -848,9 +859,16 @@ static ft_status prepare_bank(ft_ctx c, const ft_bank *bank, double t_ref, EvalR
     if (grid && (n_t / ns / n1 != n0 || n_t > (1LL << 40)))
         return fail(c, FT_E_UNSUPPORTED, "more than 2^40 templates in one call");
     hipError_t e;
-    if (fetch(c->f0_h, bank->f0, (size_t)n0) != hipSuccess || fetch(c->f1_h, bank->f1, (size_t)n1) != hipSuccess ||
-        fetch(c->sky_h, bank->sky_xyz, (size_t)ns * 3) != hipSuccess)
+    if (fetch(c->f0_h, bank->f0, (size_t)n0) != hipSuccess || fetch(c->sky_h, bank->sky_xyz, (size_t)ns * 3) != hipSuccess)
         return fail(c, FT_E_INVALID, "cannot read the bank arrays");
+    if (binary) {
+        c->f1_h.assign((size_t)n1, 0.0);  // no spindown in the binary model
+        if (fetch(c->ap_h, bank->ap, (size_t)n0) != hipSuccess || fetch(c->omega_h, bank->omega, (size_t)n0) != hipSuccess ||
+            fetch(c->phib_h, bank->phib, (size_t)n0) != hipSuccess)
+            return fail(c, FT_E_INVALID, "cannot read the binary parameters");
+    } else if (fetch(c->f1_h, bank->f1, (size_t)n1) != hipSuccess) {
+        return fail(c, FT_E_INVALID, "cannot read the bank arrays");
+    }
     // validation
     double dt_min = c->t_mid_h[0] - t_ref, dt_max = dt_min;
     for (double t : c->t_mid_h) {
@@ -892,7 +910,23 @@ static ft_status prepare_bank(ft_ctx c, const ft_bank *bank, double t_ref, EvalR
             if (!(a > 0.0)) return fail(c, FT_E_INVALID, "f0 + f1*(t - t_ref) must stay > 0 (template %lld)", (long long)t);
         }
     }
-    const double x_max = (f0_max + c_max) * (1.0 + c->vmax) * c->t_sft;
+    double aw_max = 0.0;
+    if (binary) {
+        // the orbital phase stays inside the library cosine's reduction range,
+        // and the track frequency stays positive: a_p Omega < 1/2
+        const double dt_abs = std::max(std::fabs(dt_min), std::fabs(dt_max));
+        for (int64_t t = 0; t < n0; ++t) {
+            const double ap = c->ap_h[t], om = c->omega_h[t], pb = c->phib_h[t];
+            if (!is_finite(ap) || !is_finite(om) || !is_finite(pb) || ap < 0.0 || om < 0.0)
+                return fail(c, FT_E_INVALID, "binary parameters must be finite, a_p >= 0, Omega >= 0 (template %lld)",
+                            (long long)t);
+            if (!(ap * om < 0.5)) return fail(c, FT_E_INVALID, "a_p * Omega must be < 1/2 (template %lld)", (long long)t);
+            if (!(om * dt_abs + std::fabs(pb) < 1.5e6))
+                return fail(c, FT_E_UNSUPPORTED, "orbital phase beyond 1.5e6 rad (template %lld)", (long long)t);
+            aw_max = std::max(aw_max, ap * om);
+        }
+    }
+    const double x_max = (f0_max + c_max) * (1.0 + c->vmax + aw_max) * c->t_sft;
     if (!(x_max < 2147483000.0)) return fail(c, FT_E_UNSUPPORTED, "track frequencies above 2^31/T_sft");
 
     // upload
@@ -919,6 +953,14 @@ static ft_status prepare_bank(ft_ctx c, const ft_bank *bank, double t_ref, EvalR
         e = hipMemcpyAsync(c->d_f1, c->f1_h.data(), n1 * sizeof(double), hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(c->d_sky, c->sky_h.data(), ns * 3 * sizeof(double), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess && binary) {
+        if ((e = ensure(&c->d_bin, &c->cap_bin, (size_t)n0 * 3)) != hipSuccess) return hip_fail(c, e, "alloc binary bank");
+        e = hipMemcpyAsync(c->d_bin, c->ap_h.data(), n0 * sizeof(double), hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(c->d_bin + n0, c->omega_h.data(), n0 * sizeof(double), hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(c->d_bin + 2 * n0, c->phib_h.data(), n0 * sizeof(double), hipMemcpyHostToDevice, c->stream);
+    }
     if (e == hipSuccess) e = launch_dt(c->d_tmid, t_ref, c->d_dt, c->n_sft, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "upload bank");
 
@@ -931,6 +973,9 @@ static ft_status prepare_bank(ft_ctx c, const ft_bank *bank, double t_ref, EvalR
     run.f0 = c->d_f0;
     run.f1 = c->d_f1;
     run.sky = c->d_sky;
+    run.ap = binary ? c->d_bin : nullptr;
+    run.omega = binary ? c->d_bin + n0 : nullptr;
+    run.phib = binary ? c->d_bin + 2 * n0 : nullptr;
     run.sky_tile = grid ? c->d_sky_tile : nullptr;
     run.sky_perm = grid ? c->d_perm : nullptr;
     run.stats = c->d_stats;
@@ -1055,12 +1100,9 @@ static ft_status tune_plain(ft_ctx c, const EvalRun &run, double dt_absmax, bool
     return FT_OK;
 }
 
-ft_status ft_eval_templates(ft_ctx c, const ft_bank *bank, double t_ref, const ft_eval_opts *opts,
-                            float *stats)
+// Evaluation options shared by every bank: validated, sub-band edges read.
+static ft_status check_eval_opts(ft_ctx c, const ft_eval_opts *opts, std::vector<double> &edges)
 {
-    if (!c) return FT_E_INVALID;
-    c->err.clear();
-    if (hipSetDevice(c->device) != hipSuccess) return fail(c, FT_E_DEVICE, "hipSetDevice");
     if (!opts) return fail(c, FT_E_INVALID, "opts is null");
     if (opts->precision != FT_INDEX_FP64)
         return fail(c, FT_E_UNSUPPORTED,
@@ -1072,13 +1114,27 @@ ft_status ft_eval_templates(ft_ctx c, const ft_bank *bank, double t_ref, const f
     if (opts->sum_mode != FT_SUM_BLOCKED && opts->sum_mode != FT_SUM_PLAIN_FP32)
         return fail(c, FT_E_INVALID, "unknown sum_mode");
     if (opts->tile < FT_TILE_TUNE || opts->tile > tile_count()) return fail(c, FT_E_INVALID, "unknown tile %d", opts->tile);
-    std::vector<double> edges;
     if (fetch(edges, opts->sub_edges, (size_t)opts->n_sub + 1) != hipSuccess)
         return fail(c, FT_E_INVALID, "cannot read sub_edges");
     for (size_t j = 0; j < edges.size(); ++j) {
         if (!is_finite(edges[j])) return fail(c, FT_E_INVALID, "sub_edges must be finite");
         if (j > 0 && !(edges[j] > edges[j - 1])) return fail(c, FT_E_INVALID, "sub_edges must be strictly increasing");
     }
+    return FT_OK;
+}
+
+static ft_status launch_eval_select(ft_ctx c, EvalRun &run, bool grid, int tile, int64_t n_t, int64_t n_seg_map,
+                                    const ft_eval_opts *opts, const std::vector<double> &edges, float *stats);
+
+ft_status ft_eval_templates(ft_ctx c, const ft_bank *bank, double t_ref, const ft_eval_opts *opts,
+                            float *stats)
+{
+    if (!c) return FT_E_INVALID;
+    c->err.clear();
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, FT_E_DEVICE, "hipSetDevice");
+    std::vector<double> edges;
+    ft_status st0 = check_eval_opts(c, opts, edges);
+    if (st0 != FT_OK) return st0;
     EvalRun run;
     bool grid;
     int64_t n_t;
@@ -1123,20 +1179,30 @@ ft_status ft_eval_templates(ft_ctx c, const ft_bank *bank, double t_ref, const f
             return fail(c, FT_E_UNSUPPORTED, "too many tiles");
     }
 
-    // launch: clear flags, evaluate, select, re-sum, rank
+    return launch_eval_select(c, run, grid, tile, n_t, grid ? bank->n_f0 : n_t, opts, edges, stats);
+}
+
+// Launch sequence of an evaluation: clear flags, map sub-bands, evaluate,
+// select, re-sum, rank (run fully prepared; n_seg_map = f0 values to map).
+static ft_status launch_eval_select(ft_ctx c, EvalRun &run, bool grid, int tile, int64_t n_t, int64_t n_seg_map,
+                                    const ft_eval_opts *opts, const std::vector<double> &edges, float *stats)
+{
+    hipError_t e;
+    ft_status st;
     const int n_seg = opts->n_sub;
     const int k = opts->k;
     const int64_t cap = std::max<int64_t>(65536, (int64_t)64 * k * n_seg);
-    st = ensure_select(c, n_seg, k, grid ? bank->n_f0 : n_t, cap);
+    st = ensure_select(c, n_seg, k, n_seg_map, cap);
     if (st != FT_OK) return st;
     if ((e = ensure(&c->d_edges, &c->cap_edges, edges.size())) != hipSuccess) return hip_fail(c, e, "alloc edges");
     e = hipMemcpyAsync(c->d_edges, edges.data(), edges.size() * sizeof(double), hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = launch_fill_u32(c->d_err, 0u, 1, c->stream);
-    if (e == hipSuccess) e = launch_subband_map(c->d_f0, grid ? bank->n_f0 : n_t, c->d_edges, n_seg, c->d_seg, c->stream);
+    if (e == hipSuccess) e = launch_subband_map(c->d_f0, n_seg_map, c->d_edges, n_seg, c->d_seg, c->stream);
     if (e == hipSuccess) e = hipEventRecord(c->ev[0], c->stream);
     if (e == hipSuccess)
-        e = !grid ? launch_eval_list(run, c->stream)
-                  : tile < 0 ? launch_eval_grid_direct(run, c->stream) : launch_eval_grid(run, tile_cfg(tile), c->stream);
+        e = run.ap ? launch_eval_binary(run, c->stream)
+            : !grid ? launch_eval_list(run, c->stream)
+            : tile < 0 ? launch_eval_grid_direct(run, c->stream) : launch_eval_grid(run, tile_cfg(tile), c->stream);
     if (e == hipSuccess) e = hipEventRecord(c->ev[1], c->stream);
     const double N = (double)c->n_sft;
     const double rel_err = opts->sum_mode == FT_SUM_BLOCKED ? 40.0 * std::ldexp(1.0, -24) + 4.0 * N * std::ldexp(1.0, -53)
@@ -1157,6 +1223,95 @@ ft_status ft_eval_templates(ft_ctx c, const ft_bank *bank, double t_ref, const f
     c->last_rel_err = rel_err;
     c->last_tile = tile;
     return FT_OK;
+}
+
+static ft_status check_region(ft_ctx c, const ft_binary_region *reg)
+{
+    if (!reg) return fail(c, FT_E_INVALID, "region is null");
+    const double v[6] = {reg->f0_lo, reg->f0_hi, reg->ap_lo, reg->ap_hi, reg->omega_lo, reg->omega_hi};
+    for (double x : v)
+        if (!is_finite(x)) return fail(c, FT_E_INVALID, "region bounds must be finite");
+    if (!(reg->f0_lo > 0.0 && reg->f0_lo <= reg->f0_hi) || !(reg->ap_lo > 0.0 && reg->ap_lo <= reg->ap_hi) ||
+        !(reg->omega_lo > 0.0 && reg->omega_lo <= reg->omega_hi))
+        return fail(c, FT_E_INVALID, "region needs 0 < lo <= hi for f0, a_p and Omega");
+    if (!(reg->ap_hi * reg->omega_hi < 0.5)) return fail(c, FT_E_INVALID, "region needs a_p * Omega < 1/2");
+    return FT_OK;
+}
+
+ft_status ft_gen_binary_bank(ft_ctx c, const ft_binary_region *reg, uint64_t seed, int64_t first, int64_t n,
+                             double *f0, double *sky_xyz, double *ap, double *omega, double *phib)
+{
+    if (!c) return FT_E_INVALID;
+    c->err.clear();
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, FT_E_DEVICE, "hipSetDevice");
+    ft_status st = check_region(c, reg);
+    if (st != FT_OK) return st;
+    if (n < 0 || first < 0 || first > INT64_MAX - n) return fail(c, FT_E_INVALID, "bad template range");
+    if (n == 0) return FT_OK;
+    if (!f0 || !sky_xyz || !ap || !omega || !phib) return fail(c, FT_E_INVALID, "output arrays must be non-null");
+    if (n > (1LL << 31)) return fail(c, FT_E_UNSUPPORTED, "at most 2^31 templates per call");
+    hipError_t e;
+    if ((e = ensure(&c->d_genbank, &c->cap_genbank, (size_t)n * 7)) != hipSuccess) return hip_fail(c, e, "alloc bank");
+    double *d = c->d_genbank;
+    e = launch_gen_binary_bank(*reg, seed, first, n, d, d + n, d + 4 * n, d + 5 * n, d + 6 * n, c->stream);
+    const std::pair<double *, int64_t> outs[5] = {{f0, 0}, {sky_xyz, n}, {ap, 4 * n}, {omega, 5 * n}, {phib, 6 * n}};
+    for (int q = 0; q < 5 && e == hipSuccess; ++q)
+        e = hipMemcpyAsync(outs[q].first, d + outs[q].second, (q == 1 ? 3 : 1) * n * sizeof(double), hipMemcpyDefault,
+                           c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "generate bank");
+    return FT_OK;
+}
+
+ft_status ft_eval_binary_random(ft_ctx c, const ft_binary_region *reg, uint64_t seed, int64_t n, double t_ref,
+                                const ft_eval_opts *opts, float *stats)
+{
+    if (!c) return FT_E_INVALID;
+    c->err.clear();
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, FT_E_DEVICE, "hipSetDevice");
+    std::vector<double> edges;
+    ft_status st = check_eval_opts(c, opts, edges);
+    if (st == FT_OK) st = check_region(c, reg);
+    if (st != FT_OK) return st;
+    if (!c->have_sfts || !c->have_vel) return fail(c, FT_E_STATE, "ft_set_sfts and ft_set_velocities must come first");
+    if (!is_finite(t_ref)) return fail(c, FT_E_INVALID, "t_ref must be finite");
+    if (n < 1 || n >= (1LL << 31)) return fail(c, FT_E_UNSUPPORTED, "n must be in [1, 2^31)");
+    if (c->n_bins >= (1 << 28)) return fail(c, FT_E_UNSUPPORTED, "binary banks need tables of fewer than 2^28 columns");
+    double dt_abs = 0.0;
+    for (double t : c->t_mid_h) dt_abs = std::max(dt_abs, std::fabs(t - t_ref));
+    if (!(reg->omega_hi * dt_abs + 7.0 < 1.5e6)) return fail(c, FT_E_UNSUPPORTED, "orbital phase beyond 1.5e6 rad");
+    const double x_max = reg->f0_hi * (1.0 + c->vmax + reg->ap_hi * reg->omega_hi) * c->t_sft;
+    if (!(x_max < 2147483000.0)) return fail(c, FT_E_UNSUPPORTED, "track frequencies above 2^31/T_sft");
+    hipError_t e;
+    if ((e = ensure(&c->d_f0, &c->cap_f0, (size_t)n)) != hipSuccess || (e = ensure(&c->d_sky, &c->cap_sky, (size_t)n * 3)) != hipSuccess ||
+        (e = ensure(&c->d_bin, &c->cap_bin, (size_t)n * 3)) != hipSuccess ||
+        (e = ensure(&c->d_stats, &c->cap_stats, (size_t)n)) != hipSuccess)
+        return hip_fail(c, e, "alloc bank");
+    e = launch_gen_binary_bank(*reg, seed, 0, n, c->d_f0, c->d_sky, c->d_bin, c->d_bin + n, c->d_bin + 2 * n, c->stream);
+    if (e == hipSuccess) e = launch_dt(c->d_tmid, t_ref, c->d_dt, c->n_sft, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "generate bank");
+    EvalRun run{};
+    run.power = c->d_power;
+    run.power_w = c->has_weight ? c->d_power_w : c->d_power;
+    run.weight = c->has_weight ? c->d_weight : nullptr;
+    run.dt = c->d_dt;
+    run.v = c->d_v;
+    run.f0 = c->d_f0;
+    run.f1 = nullptr;
+    run.sky = c->d_sky;
+    run.ap = c->d_bin;
+    run.omega = c->d_bin + n;
+    run.phib = c->d_bin + 2 * n;
+    run.stats = c->d_stats;
+    run.err = c->d_err;
+    run.n_sft = c->n_sft;
+    run.n_bins = c->n_bins;
+    run.first_bin = (int32_t)c->first_bin;
+    run.n_list = n;
+    run.t_sft = c->t_sft;
+    run.sum_mode = opts->sum_mode;
+    run.precision = opts->precision;
+    return launch_eval_select(c, run, false, -1, n, n, opts, edges, stats);
 }
 
 ft_status ft_sync(ft_ctx c)
@@ -1230,6 +1385,30 @@ ft_status ft_last_eval_info(ft_ctx c, ft_eval_info *info)
     return FT_OK;
 }
 
+ft_status ft_lib_sincos(ft_ctx c, const double *x, int64_t n, double *cos_out, double *sin_out)
+{
+    if (!c) return FT_E_INVALID;
+    c->err.clear();
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, FT_E_DEVICE, "hipSetDevice");
+    if (n < 0 || (n > 0 && (!x || (!cos_out && !sin_out)))) return fail(c, FT_E_INVALID, "bad arguments");
+    if (n == 0) return FT_OK;
+    std::vector<double> xh;
+    if (fetch(xh, x, (size_t)n) != hipSuccess) return fail(c, FT_E_INVALID, "cannot read x");
+    for (double v : xh)
+        if (!is_finite(v) || !(std::fabs(v) < 1.5e6)) return fail(c, FT_E_INVALID, "x must be finite with |x| < 1.5e6");
+    hipError_t e;
+    if ((e = ensure(&c->d_sincos, &c->cap_sincos, (size_t)n * 3)) != hipSuccess) return hip_fail(c, e, "alloc sincos");
+    e = hipMemcpyAsync(c->d_sincos, xh.data(), n * sizeof(double), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = launch_lib_sincos(c->d_sincos, n, c->d_sincos + n, c->d_sincos + 2 * n, c->stream);
+    if (e == hipSuccess && cos_out)
+        e = hipMemcpyAsync(cos_out, c->d_sincos + n, n * sizeof(double), hipMemcpyDefault, c->stream);
+    if (e == hipSuccess && sin_out)
+        e = hipMemcpyAsync(sin_out, c->d_sincos + 2 * n, n * sizeof(double), hipMemcpyDefault, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "lib sincos");
+    return FT_OK;
+}
+
 ft_status ft_bins(ft_ctx c, const ft_bank *bank, double t_ref, int32_t precision, int32_t *bins)
 {
     if (!c) return FT_E_INVALID;
@@ -1237,7 +1416,10 @@ ft_status ft_bins(ft_ctx c, const ft_bank *bank, double t_ref, int32_t precision
     if (hipSetDevice(c->device) != hipSuccess) return fail(c, FT_E_DEVICE, "hipSetDevice");
     if (!bins) return fail(c, FT_E_INVALID, "bins is null");
     if (precision < FT_INDEX_FP64 || precision > FT_INDEX_GUARDED) return fail(c, FT_E_INVALID, "unknown precision");
-    if (bank && bank->kind != FT_BANK_LIST) return fail(c, FT_E_UNSUPPORTED, "ft_bins takes a LIST bank");
+    if (bank && bank->kind != FT_BANK_LIST && bank->kind != FT_BANK_BINARY)
+        return fail(c, FT_E_UNSUPPORTED, "ft_bins takes a LIST or BINARY bank");
+    if (bank && bank->kind == FT_BANK_BINARY && precision != FT_INDEX_FP64)
+        return fail(c, FT_E_UNSUPPORTED, "binary banks have canonical FP64 bins only");
     EvalRun run;
     bool grid;
     int64_t n_t;
@@ -1260,6 +1442,7 @@ ft_status ft_count_index_mismatches(ft_ctx c, const ft_bank *bank, double t_ref,
     c->err.clear();
     if (hipSetDevice(c->device) != hipSuccess) return fail(c, FT_E_DEVICE, "hipSetDevice");
     if (!n_mismatch) return fail(c, FT_E_INVALID, "n_mismatch is null");
+    if (bank && bank->kind == FT_BANK_BINARY) return fail(c, FT_E_UNSUPPORTED, "the index study covers GRID and LIST banks");
     if (precision < FT_INDEX_FP64 || precision > FT_INDEX_GUARDED) return fail(c, FT_E_INVALID, "unknown precision");
     EvalRun run;
     bool grid;

@@ -343,12 +343,152 @@ __global__ __launch_bounds__(64) void eval_batch_small_kernel(const EvalRun *__r
     }
 }
 
+// Binary-system list banks: one lane per template (the paper's random
+// template banks carry no structure to share between lanes).  Per SFT a lane
+// forms the canonical Doppler factor and orbital phase, then an estimate of
+// the track position x with a single-precision cosine, and keeps
+// B = floor(x + 1/2) when x + 1/2 is farther than eps from an integer; else
+// (about once per 10^4 evaluations) it forms the canonical bin with the
+// library cosine.  It gathers from the table (scalar row base, lane offset);
+// velocities and time offsets are wave-uniform scalar loads.  Lanes past the
+// bank's end repeat its last template and store nothing, so the SFT loop
+// stays wave-uniform.
+//
+// Estimate and guard.  The phase is reduced by pi/2 in FP64 with the first
+// two parts of the library constant (the same quadrant q as the library
+// cosine; the dropped q P3 term is below 4e-15), rounded to float (error
+// <= 2^-24 pi/4 < 5e-8) and put through Taylor polynomials of cos to r^8 and
+// sin to r^9 (truncation < 2.6e-8) in fused single-precision Horner steps
+// (rounding < 3e-7 on |values| <= 1): |cos_est - cos| < 4e-7, and the library
+// cosine is within 2^-52 of cos.  With delta = 1e-6 as the cosine bound, the
+// orbital term a_p Omega cos moves x by at most f0 a_p Omega T delta, and the
+// remaining operations (the canonical ones, on values that differ by that
+// much) add at most a few ulps of x: eps = f0 a_p Omega T delta + 1e-9.
+constexpr double BINARY_COS_DELTA = 1e-6;
+
+__device__ __forceinline__ float binary_cos_estimate(double ph)
+{
+    const double q = floor(ph * 0x1.45f306dc9c883p-1 + 0.5);
+    const double rd = (ph - q * 0x1.921fb54400000p+0) - q * 0x1.0b4611a600000p-34;
+    const float r = (float)rd;
+    const float r2 = r * r;
+    float ps = __builtin_fmaf(r2, 2.75573192e-6f, -1.98412698e-4f);   // 1/9!, -1/7!
+    ps = __builtin_fmaf(ps, r2, 8.33333333e-3f);                       // 1/5!
+    ps = __builtin_fmaf(ps, r2, -1.66666667e-1f);                      // -1/3!
+    const float sv = __builtin_fmaf(r * r2, ps, r);
+    float pc = __builtin_fmaf(r2, 2.48015873e-5f, -1.38888889e-3f);   // 1/8!, -1/6!
+    pc = __builtin_fmaf(pc, r2, 4.16666667e-2f);                       // 1/4!
+    pc = __builtin_fmaf(pc, r2, -0.5f);
+    const float cv = __builtin_fmaf(r2, pc, 1.0f);
+    const int n = (int)q & 3;
+    return n == 0 ? cv : n == 1 ? -sv : n == 2 ? -cv : sv;
+}
+
+// Byte offset of the canonical bin of one binary template in row k (clamped
+// into the row and flagged when the track leaves the table).
+struct BinaryLane {
+    double f0, nx, ny, nz, aw, omega, phib, eps;
+};
+
+__device__ __forceinline__ uint32_t binary_offset(const EvalRun &r, const BinaryLane &p, int k, bool &bad)
+{
+    const auto *vk = as_const(r.v + 3 * (int64_t)k);
+    const double dt = as_const(r.dt)[k];
+    const double g = doppler_factor(vk[0], vk[1], vk[2], p.nx, p.ny, p.nz);
+    double ph = p.omega * dt;
+    ph = ph - p.phib;
+    const double e = p.aw * (double)binary_cos_estimate(ph);
+    const double u = ((p.f0 * (g - e)) * r.t_sft) + 0.5;
+    const double fr = u - floor(u);
+    int B = (int)u;
+    if (!(fr > p.eps && fr < 1.0 - p.eps)) B = bin_binary(p.f0, g, p.aw, p.omega, p.phib, dt, r.t_sft);
+    int b = B - r.first_bin;
+    if (b < 0 || b >= r.n_bins) {
+        bad = true;
+        b = min(max(b, 0), r.n_bins - 1);
+    }
+    return (uint32_t)b * 4u;
+}
+
+__device__ __forceinline__ float binary_gather(const EvalRun &r, int k, uint32_t off)
+{
+    return *(global_float *)((const char *)(r.power_w + (int64_t)k * r.n_bins) + off);
+}
+
+__global__ __launch_bounds__(256) void eval_binary_kernel(EvalRun r)
+{
+    const int64_t n = r.n_list;
+    const int n_sft = r.n_sft;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < n; base += stride) {
+        const int64_t t_raw = base + threadIdx.x;
+        const bool live = t_raw < n;
+        const int64_t t = live ? t_raw : n - 1;
+        BinaryLane p;
+        p.f0 = r.f0[t];
+        p.nx = r.sky[3 * t];
+        p.ny = r.sky[3 * t + 1];
+        p.nz = r.sky[3 * t + 2];
+        p.omega = r.omega[t];
+        p.phib = r.phib[t];
+        p.aw = r.ap[t] * p.omega;
+        p.eps = p.f0 * p.aw * r.t_sft * BINARY_COS_DELTA + 1e-9;
+        float acc = 0.f;
+        double tot = 0.0;
+        bool bad = false;
+        // Two value buffers in turn: the gather of SFT k+1 goes out before the
+        // value of SFT k is added (reads past the last SFT re-read it, unused);
+        // blocks of SUM_BLOCK SFTs (even) are walked in pairs, so va holds the
+        // next block's first SFT when a block ends.
+        float va = binary_gather(r, 0, binary_offset(r, p, 0, bad));
+        for (int kb = 0; kb < n_sft; kb += SUM_BLOCK) {
+            const int ke = min(kb + SUM_BLOCK, n_sft);
+            int k = kb;
+            for (; k + 1 < ke; k += 2) {
+                const float vb = binary_gather(r, k + 1, binary_offset(r, p, k + 1, bad));
+                acc += va;
+                const int k2 = min(k + 2, n_sft - 1);
+                va = binary_gather(r, k2, binary_offset(r, p, k2, bad));
+                acc += vb;
+            }
+            if (k < ke) acc += va;  // odd tail: k = n_sft - 1
+            if (r.sum_mode == FT_SUM_BLOCKED) {
+                tot += (double)acc;
+                acc = 0.f;
+            }
+        }
+        if (bad && live) atomicOr(r.err, ERR_RANGE);
+        if (live) r.stats[t] = (float)(tot + (double)acc);
+    }
+}
+
+// The library cosine and sine of an array (exposed for callers that
+// reproduce binary-track phases, and for parity checks of the library cosine).
+__global__ void lib_sincos_kernel(const double *x, int64_t n, double *c, double *s)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        double sv, cv;
+        lib_sincos(x[i], sv, cv);
+        if (c) c[i] = cv;
+        if (s) s[i] = sv;
+    }
+}
+
 __global__ __launch_bounds__(256) void bins_list_kernel(EvalRun r, int mode, int32_t *bins)
 {
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < r.n_list;
          t += (int64_t)gridDim.x * blockDim.x) {
         const double *n = r.sky + 3 * t;
         int fallback = 0;
+        if (r.ap) {
+            const double aw = r.ap[t] * r.omega[t];
+            for (int k = 0; k < r.n_sft; ++k) {
+                const double *vk = r.v + 3 * (int64_t)k;
+                const double g = doppler_factor(vk[0], vk[1], vk[2], n[0], n[1], n[2]);
+                bins[t * r.n_sft + k] = bin_binary(r.f0[t], g, aw, r.omega[t], r.phib[t], r.dt[k], r.t_sft);
+            }
+            continue;
+        }
         for (int k = 0; k < r.n_sft; ++k)
             bins[t * r.n_sft + k] = bin_mode(mode, r.f0[t], r.f1[t], r.dt[k],
                                              r.v + 3 * (int64_t)k, n, r.t_sft, &fallback);
@@ -479,6 +619,20 @@ hipError_t launch_eval_list(const EvalRun &run, hipStream_t s)
     if (run.n_list <= 0) return hipSuccess;
     hipLaunchKernelGGL(eval_direct_kernel<false>, dim3(grid_for(run.n_list, 256, (1u << 22))),
                        dim3(256), 0, s, run);
+    return hipGetLastError();
+}
+
+hipError_t launch_eval_binary(const EvalRun &run, hipStream_t s)
+{
+    if (run.n_list <= 0) return hipSuccess;
+    hipLaunchKernelGGL(eval_binary_kernel, dim3(grid_for(run.n_list, 256, (1u << 16))), dim3(256), 0, s, run);
+    return hipGetLastError();
+}
+
+hipError_t launch_lib_sincos(const double *x, int64_t n, double *c, double *s, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(lib_sincos_kernel, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, x, n, c, s);
     return hipGetLastError();
 }
 

@@ -46,6 +46,68 @@ __device__ __forceinline__ int bin_fp64(double f0, double c, double g, double t_
     return (int)t;
 }
 
+// ---------------------------------------------------------------------------
+// Sources in circular binary systems (Eq. track with a_p > 0, no spindown):
+// f = f0 (1 + v.n - a_p Omega cos(Omega (t - t_ref) - phi_b)).
+// ---------------------------------------------------------------------------
+// The library's FP64 cosine and sine: a fixed sequence of IEEE additions and
+// multiplications (compiled without contraction), so every implementation of
+// the same sequence returns the same bits.  Range reduction after Cody and
+// Waite (1980): q = floor(x 2/pi + 1/2), r = ((x - q P1) - q P2) - q P3 with
+// pi/2 = P1 + P2 + P3 and P1, P2 of 33 significant bits (exact products for
+// |q| < 2^20, i.e. |x| < 1.6e6); Taylor polynomials of sin and cos on
+// |r| <= pi/4 (terms to r^17 and r^18, truncation below 1e-19) in Horner form
+// with coefficients 1/n! rounded to double; the quadrant q mod 4 picks
+// (c, -s, -c, s) for the cosine and (s, c, -s, -c) for the sine.
+__device__ __forceinline__ void lib_sincos(double x, double &sin_out, double &cos_out)
+{
+    const double t = x * 0x1.45f306dc9c883p-1;  // 2/pi
+    const double q = floor(t + 0.5);
+    double r = x - q * 0x1.921fb54400000p+0;
+    r = r - q * 0x1.0b4611a600000p-34;
+    r = r - q * 0x1.3198a2e037073p-69;
+    const double r2 = r * r;
+    double ps = 0x1.952c77030ad4ap-49;                // 1/17!
+    ps = ps * r2; ps = ps - 0x1.ae7f3e733b81fp-41;    // 1/15!
+    ps = ps * r2; ps = ps + 0x1.6124613a86d09p-33;    // 1/13!
+    ps = ps * r2; ps = ps - 0x1.ae64567f544e4p-26;    // 1/11!
+    ps = ps * r2; ps = ps + 0x1.71de3a556c734p-19;    // 1/9!
+    ps = ps * r2; ps = ps - 0x1.a01a01a01a01ap-13;    // 1/7!
+    ps = ps * r2; ps = ps + 0x1.1111111111111p-7;     // 1/5!
+    ps = ps * r2; ps = ps - 0x1.5555555555555p-3;     // 1/3!
+    const double s = r + (r * r2) * ps;
+    double pc = -0x1.6827863b97d97p-53;               // 1/18!
+    pc = pc * r2; pc = pc + 0x1.ae7f3e733b81fp-45;    // 1/16!
+    pc = pc * r2; pc = pc - 0x1.93974a8c07c9dp-37;    // 1/14!
+    pc = pc * r2; pc = pc + 0x1.1eed8eff8d898p-29;    // 1/12!
+    pc = pc * r2; pc = pc - 0x1.27e4fb7789f5cp-22;    // 1/10!
+    pc = pc * r2; pc = pc + 0x1.a01a01a01a01ap-16;    // 1/8!
+    pc = pc * r2; pc = pc - 0x1.6c16c16c16c17p-10;    // 1/6!
+    pc = pc * r2; pc = pc + 0x1.5555555555555p-5;     // 1/4!
+    const double c = (1.0 - 0.5 * r2) + (r2 * r2) * pc;
+    const int n = (int)q & 3;  // |q| < 2^20: the 32-bit conversion is exact
+    cos_out = n == 0 ? c : n == 1 ? -s : n == 2 ? -c : s;
+    sin_out = n == 0 ? s : n == 1 ? c : n == 2 ? -s : -c;
+}
+
+// Canonical bin of a binary-system template at an SFT (offset dt from t_ref,
+// Doppler factor g = 1 + v.n in canonical order; aw = a_p * Omega):
+// ph = Omega dt - phi_b, e = aw cos(ph), f = f0 (g - e), B = floor(f T + 1/2).
+__device__ __forceinline__ int bin_binary(double f0, double g, double aw, double omega, double phib,
+                                          double dt, double t_sft)
+{
+    double ph = omega * dt;
+    ph = ph - phib;
+    double sb, cb;
+    lib_sincos(ph, sb, cb);
+    const double e = aw * cb;
+    const double h = g - e;
+    const double f = f0 * h;
+    const double x = f * t_sft;
+    const double t = x + 0.5;
+    return (int)t;
+}
+
 // The data of one evaluation: an SFT set, its velocities and a grid bank.
 struct EvalRun {
     const float *power;   // [n_sft][n_bins]
@@ -58,6 +120,9 @@ struct EvalRun {
     const double *sky;    // grid [n_sky][3] / list [n][3]
     const double *sky_tile;   // grid: sky points in tile (Doppler-coherent) order
     const int32_t *sky_perm;  // grid: tile position -> original sky index
+    const double *ap;     // binary list banks: [n] a_p (light-seconds), else nullptr
+    const double *omega;  // binary list banks: [n] Omega (rad/s)
+    const double *phib;   // binary list banks: [n] phi_b (rad, at t_ref)
     float *stats;         // [n_templates]
     uint32_t *err;        // error flags
     int32_t n_sft;
@@ -107,6 +172,10 @@ hipError_t launch_select_batch(const EvalRun *runs, int n_runs, int k, int cap_p
 hipError_t launch_labels(const double *max_z, int n_runs, double tau, uint8_t *labels,
                          hipStream_t s);
 hipError_t launch_eval_list(const EvalRun &run, hipStream_t s);
+// Binary-system list bank (run.ap/omega/phib set): one lane per template.
+hipError_t launch_eval_binary(const EvalRun &run, hipStream_t s);
+// The library cosine/sine of x[0..n) into c[], s[] (device arrays).
+hipError_t launch_lib_sincos(const double *x, int64_t n, double *c, double *s, hipStream_t st);
 hipError_t launch_eval_grid_direct(const EvalRun &run, hipStream_t s);
 // LDS gather probe of a tile shape: n_blocks workgroups, n_step SFT steps over
 // a staged window of LDS row stride wtp; out [n_blocks * 64 NW] floats.
@@ -161,6 +230,12 @@ struct GenRun {
 hipError_t launch_gen_tables(const GenRun *prep, int n_prep, const int64_t *prep_prefix, int64_t total_prep_sft,
                              const GenRun *runs, int n_runs, const int64_t *row_prefix, int64_t total_rows,
                              hipStream_t s);
+
+// Random binary-system bank (uniform in the xi coordinates) of templates
+// first .. first + n - 1 into device arrays f0[n], sky[n][3], ap[n],
+// omega[n], phib[n].
+hipError_t launch_gen_binary_bank(const ft_binary_region &reg, uint64_t seed, int64_t first, int64_t n, double *f0,
+                                  double *sky, double *ap, double *omega, double *phib, hipStream_t s);
 
 // Selection: exact toplists per segment (segment = sub-band here).
 struct SelectBufs {

@@ -209,7 +209,83 @@ __global__ __launch_bounds__(256) void gen_noise_kernel(const GenRun *runs, int 
         }
     }
 }
+// Random template bank of sources in circular binary systems, uniform in the
+// binary appendix's xi coordinates (Eq. unif_transform: up to constants xi is
+// (f0^6, alpha, sin delta, a_p^3, Omega^4, phi_b)).  Template i draws six
+// 53-bit uniforms from three Philox calls with counter (i_lo, i_hi, 0, 1 + j)
+// and key (seed_lo, seed_hi) (the noise counters carry word 3 = 0), then
+//   f0 = root6(lo^6 + u0 (hi^6 - lo^6)), alpha = 2 pi u1, sin delta = 2 u2 - 1,
+//   a_p = root3(...u3...), Omega = root4(...u4...), phi_b = 2 pi u5,
+//   n = (cos delta cos alpha, cos delta sin alpha, sin delta), cos delta =
+//   sqrt(1 - sin^2 delta), library cosine/sine of alpha.
+// Roots: 12 Newton steps z <- z - (z^p - y)/(p z^(p-1)) from the linear
+// interpolation lo + u (hi - lo), powers as z^3 = (z z) z, z^4 = (z z)(z z),
+// z^5 = ((z z)(z z)) z, z^6 = ((z z) z)((z z) z): a fixed sequence of IEEE
+// operations, so the bank is reproducible bit for bit.
+constexpr double TWO_PI_D = 0x1.921fb54442d18p+2;
+
+template <int P>
+__device__ __forceinline__ double xi_pow(double z)
+{
+    const double z2 = z * z;
+    if (P == 2) return z2;
+    if (P == 3) return z2 * z;
+    if (P == 4) return z2 * z2;
+    if (P == 5) return (z2 * z2) * z;
+    const double z3 = z2 * z;
+    return z3 * z3;
+}
+
+template <int P>
+__device__ __forceinline__ double xi_root(double lo, double hi, double u)
+{
+    const double y = xi_pow<P>(lo) + u * (xi_pow<P>(hi) - xi_pow<P>(lo));
+    double z = lo + u * (hi - lo);
+    for (int it = 0; it < 12; ++it) z = z - (xi_pow<P>(z) - y) / ((double)P * xi_pow<P - 1>(z));
+    return z;
+}
+
+__global__ __launch_bounds__(256) void gen_binary_bank_kernel(ft_binary_region reg, uint64_t seed, int64_t first,
+                                                              int64_t n, double *f0, double *sky, double *ap,
+                                                              double *omega, double *phib)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t t = (uint64_t)(first + i);
+        double u[6];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            uint32_t c[4] = {(uint32_t)t, (uint32_t)(t >> 32), 0u, 1u + (uint32_t)j};
+            philox4x32_10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+            u[2 * j] = unit53(c[0], c[1]);
+            u[2 * j + 1] = unit53(c[2], c[3]);
+        }
+        f0[i] = xi_root<6>(reg.f0_lo, reg.f0_hi, u[0]);
+        const double alpha = u[1] * TWO_PI_D;
+        const double sd = u[2] * 2.0 - 1.0;
+        const double cd = sqrt(1.0 - sd * sd);
+        double sa, ca;
+        lib_sincos(alpha, sa, ca);
+        sky[3 * i] = cd * ca;
+        sky[3 * i + 1] = cd * sa;
+        sky[3 * i + 2] = sd;
+        ap[i] = xi_root<3>(reg.ap_lo, reg.ap_hi, u[3]);
+        omega[i] = xi_root<4>(reg.omega_lo, reg.omega_hi, u[4]);
+        phib[i] = u[5] * TWO_PI_D;
+    }
+}
+
 }  // namespace
+
+hipError_t launch_gen_binary_bank(const ft_binary_region &reg, uint64_t seed, int64_t first, int64_t n, double *f0,
+                                  double *sky, double *ap, double *omega, double *phib, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(gen_binary_bank_kernel, dim3((unsigned)blocks), dim3(256), 0, s, reg, seed, first, n, f0, sky,
+                       ap, omega, phib);
+    return hipGetLastError();
+}
 
 hipError_t launch_gen_tables(const GenRun *prep, int n_prep, const int64_t *prep_prefix, int64_t total_prep_sft,
                              const GenRun *runs, int n_runs, const int64_t *row_prefix, int64_t total_rows,

@@ -189,6 +189,7 @@ __global__ __launch_bounds__(256) void scatter_kernel(const float *stats, const 
 
 struct TemplateParams {
     double f0, f1, nx, ny, nz;
+    double aw, omega, phib;  // binary-system list banks (aw = a_p Omega), else 0
 };
 
 __device__ __forceinline__ TemplateParams params_of(const EvalRun &r, bool grid, int64_t t)
@@ -205,7 +206,13 @@ __device__ __forceinline__ TemplateParams params_of(const EvalRun &r, bool grid,
     } else {
         s = t;
         p.f0 = r.f0[t];
-        p.f1 = r.f1[t];
+        p.f1 = r.ap ? 0.0 : r.f1[t];
+    }
+    p.aw = p.omega = p.phib = 0.0;
+    if (!grid && r.ap) {
+        p.omega = r.omega[t];
+        p.phib = r.phib[t];
+        p.aw = r.ap[t] * p.omega;
     }
     p.nx = r.sky[3 * s];
     p.ny = r.sky[3 * s + 1];
@@ -239,7 +246,9 @@ __global__ __launch_bounds__(256) void rescore_kernel(EvalRun r, bool grid, cons
             if (k < r.n_sft) {
                 const double *vk = r.v + 3 * (int64_t)k;
                 const double g = doppler_factor(vk[0], vk[1], vk[2], tp.nx, tp.ny, tp.nz);
-                int b = bin_fp64(tp.f0, tp.f1 * r.dt[k], g, r.t_sft) - r.first_bin;
+                int b = (r.ap ? bin_binary(tp.f0, g, tp.aw, tp.omega, tp.phib, r.dt[k], r.t_sft)
+                              : bin_fp64(tp.f0, tp.f1 * r.dt[k], g, r.t_sft)) -
+                        r.first_bin;
                 if (b < 0 || b >= r.n_bins) {
                     bad = ERR_RANGE;
                     b = b < 0 ? 0 : r.n_bins - 1;

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libfasttracks.so")
 
 FT_OK, FT_E_INVALID, FT_E_STATE, FT_E_RANGE, FT_E_NOMEM, FT_E_DEVICE, FT_E_UNSUPPORTED, \
     FT_E_INTERNAL = 0, -1, -2, -3, -4, -5, -6, -7
-FT_BANK_GRID, FT_BANK_LIST = 0, 1
+FT_BANK_GRID, FT_BANK_LIST, FT_BANK_BINARY = 0, 1, 2
 FT_INDEX_FP64, FT_INDEX_FP32, FT_INDEX_DF64, FT_INDEX_GUARDED = 0, 1, 2, 3
 FT_SUM_BLOCKED, FT_SUM_PLAIN_FP32 = 0, 1
 FT_TILE_TUNE = -1
@@ -32,7 +32,20 @@ class FtError(RuntimeError):
 class ft_bank(C.Structure):
     _fields_ = [("kind", C.c_int32), ("reserved", C.c_int32), ("n_f0", C.c_int64),
                 ("n_f1", C.c_int64), ("n_sky", C.c_int64), ("n_list", C.c_int64),
-                ("f0", C.c_void_p), ("f1", C.c_void_p), ("sky_xyz", C.c_void_p)]
+                ("f0", C.c_void_p), ("f1", C.c_void_p), ("sky_xyz", C.c_void_p),
+                ("ap", C.c_void_p), ("omega", C.c_void_p), ("phib", C.c_void_p)]
+
+
+class ft_binary_region(C.Structure):
+    _fields_ = [("f0_lo", C.c_double), ("f0_hi", C.c_double), ("ap_lo", C.c_double),
+                ("ap_hi", C.c_double), ("omega_lo", C.c_double), ("omega_hi", C.c_double)]
+
+
+def make_region(d):
+    r = ft_binary_region()
+    for name, _ in ft_binary_region._fields_:
+        setattr(r, name, float(d[name]))
+    return r
 
 
 class ft_eval_opts(C.Structure):
@@ -85,7 +98,8 @@ class ft_tune_entry(C.Structure):
 _lib = None
 EXPORTS = ("ft_create", "ft_destroy", "ft_last_error", "ft_status_string", "ft_set_sfts",
            "ft_set_velocities", "ft_eval_templates", "ft_toplist", "ft_sync",
-           "ft_last_eval_info", "ft_bins", "ft_count_index_mismatches", "ft_tile_count",
+           "ft_last_eval_info", "ft_bins", "ft_count_index_mismatches", "ft_lib_sincos",
+           "ft_gen_binary_bank", "ft_eval_binary_random", "ft_tile_count",
            "ft_tile_name", "ft_gen_sfts", "ft_eval_batch", "ft_batch_toplist", "ft_batch_labels",
            "ft_batch_replay", "ft_batch_time", "ft_mlp_create", "ft_mlp_destroy",
            "ft_mlp_get_params", "ft_mlp_predict", "ft_mlp_loss_grad", "ft_mlp_train",
@@ -114,6 +128,11 @@ def load(path: str = LIB_PATH):
         "ft_sync": (C.c_int, [P]),
         "ft_last_eval_info": (C.c_int, [P, C.POINTER(ft_eval_info)]),
         "ft_bins": (C.c_int, [P, C.POINTER(ft_bank), f64, i32, P]),
+        "ft_lib_sincos": (C.c_int, [P, P, i64, P, P]),
+        "ft_gen_binary_bank": (C.c_int, [P, C.POINTER(ft_binary_region), C.c_uint64, i64, i64, P, P, P,
+                                         P, P]),
+        "ft_eval_binary_random": (C.c_int, [P, C.POINTER(ft_binary_region), C.c_uint64, i64, f64,
+                                            C.POINTER(ft_eval_opts), P]),
         "ft_count_index_mismatches": (C.c_int, [P, C.POINTER(ft_bank), f64, i32,
                                                 C.POINTER(i64)]),
         "ft_tile_count": (i32, []),
@@ -246,6 +265,69 @@ def _bank(f0, f1, sky, kind):
         b.n_list = len(f0)
     b.f0, b.f1, b.sky_xyz = a0.ptr, a1.ptr, a2.ptr
     return b, (a0, a1, a2)
+
+
+def _binary_bank(f0, sky, ap, omega, phib):
+    arrs = [_Arr(x, np.float64) for x in (f0, sky, ap, omega, phib)]
+    b = ft_bank()
+    b.kind = FT_BANK_BINARY
+    b.n_list = len(f0)
+    b.f0, b.sky_xyz, b.ap, b.omega, b.phib = (a.ptr for a in arrs)
+    return b, arrs
+
+
+def ft_eval_binary(ctx, f0, sky, ap, omega, phib, t_ref, k, sub_edges, sum_mode=FT_SUM_BLOCKED,
+                   stats=None):
+    """Evaluate a BINARY bank (f0, sky[n,3], a_p, Omega, phi_b, each [n]); optional
+    `stats` output (float32 [n], host or device)."""
+    bank, keep = _binary_bank(f0, sky, ap, omega, phib)
+    edges = _Arr(sub_edges, np.float64)
+    o = ft_eval_opts()
+    o.precision, o.k, o.n_sub, o.sum_mode, o.tile = FT_INDEX_FP64, k, len(sub_edges) - 1, sum_mode, 0
+    o.sub_edges = edges.ptr
+    s = _Arr(stats, np.float32)
+    _check(ctx, load().ft_eval_templates(ctx, C.byref(bank), float(t_ref), C.byref(o), s.ptr))
+
+
+def ft_bins_binary(ctx, f0, sky, ap, omega, phib, t_ref):
+    """Absolute bins [n, N] (int32) of a BINARY bank."""
+    bank, keep = _binary_bank(f0, sky, ap, omega, phib)
+    out = np.empty((len(f0), _n_sft_of(ctx)), np.int32)
+    _check(ctx, load().ft_bins(ctx, C.byref(bank), float(t_ref), FT_INDEX_FP64,
+                               out.ctypes.data_as(C.c_void_p)))
+    return out
+
+
+def ft_gen_binary_bank(ctx, region, seed, first, n):
+    """Templates first .. first+n-1 of the random binary bank: (f0, sky [n,3], ap, omega, phib)."""
+    reg = make_region(region)
+    out = [np.empty(n), np.empty((n, 3)), np.empty(n), np.empty(n), np.empty(n)]
+    _check(ctx, load().ft_gen_binary_bank(ctx, C.byref(reg), int(seed), int(first), int(n),
+                                          *[a.ctypes.data_as(C.c_void_p) for a in out]))
+    return tuple(out)
+
+
+def ft_eval_binary_random(ctx, region, seed, n, t_ref, k, sub_edges, sum_mode=FT_SUM_BLOCKED,
+                          stats=None):
+    """Generate templates 0..n-1 of the random binary bank on the device and evaluate them."""
+    reg = make_region(region)
+    edges = _Arr(sub_edges, np.float64)
+    o = ft_eval_opts()
+    o.precision, o.k, o.n_sub, o.sum_mode, o.tile = FT_INDEX_FP64, k, len(sub_edges) - 1, sum_mode, 0
+    o.sub_edges = edges.ptr
+    s = _Arr(stats, np.float32)
+    _check(ctx, load().ft_eval_binary_random(ctx, C.byref(reg), int(seed), int(n), float(t_ref),
+                                             C.byref(o), s.ptr))
+
+
+def ft_lib_sincos(ctx, x):
+    """(cos x, sin x) with the library's FP64 cosine/sine (numpy float64 arrays)."""
+    x = np.ascontiguousarray(x, np.float64)
+    c = np.empty_like(x)
+    s = np.empty_like(x)
+    _check(ctx, load().ft_lib_sincos(ctx, x.ctypes.data_as(C.c_void_p), x.size,
+                                     c.ctypes.data_as(C.c_void_p), s.ctypes.data_as(C.c_void_p)))
+    return c, s
 
 
 def ft_eval_templates(ctx, f0, f1, sky, t_ref, k, sub_edges, kind=FT_BANK_GRID,
@@ -536,6 +618,21 @@ class Context:
 
     def bins(self, *a, **kw):
         return ft_bins(self.ctx, *a, **kw)
+
+    def eval_binary(self, *a, **kw):
+        ft_eval_binary(self.ctx, *a, **kw)
+
+    def bins_binary(self, *a, **kw):
+        return ft_bins_binary(self.ctx, *a, **kw)
+
+    def lib_sincos(self, x):
+        return ft_lib_sincos(self.ctx, x)
+
+    def gen_binary_bank(self, *a, **kw):
+        return ft_gen_binary_bank(self.ctx, *a, **kw)
+
+    def eval_binary_random(self, *a, **kw):
+        ft_eval_binary_random(self.ctx, *a, **kw)
 
     def count_index_mismatches(self, *a, **kw):
         return ft_count_index_mismatches(self.ctx, *a, **kw)

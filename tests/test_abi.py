@@ -46,7 +46,7 @@ def test_host_only_entry_points():
 
 def test_struct_layouts_match_header():
     from paper_2411_18370_amd import fasttracks as ft
-    assert C.sizeof(ft.ft_bank) == 64
+    assert C.sizeof(ft.ft_bank) == 88
     assert C.sizeof(ft.ft_eval_opts) == 32
     assert C.sizeof(ft.ft_candidate) == 72
     assert ft.ft_candidate.s64.offset == 56
@@ -62,6 +62,10 @@ def test_null_arguments_are_rejected_without_a_device():
     assert lib.ft_sync(None) == ft.FT_E_INVALID
     assert lib.ft_tune_clear(None) == ft.FT_E_INVALID
     assert lib.ft_tune_report(None, None, 0, None, None) == ft.FT_E_INVALID
+    assert lib.ft_lib_sincos(None, None, 0, None, None) == ft.FT_E_INVALID
+    assert lib.ft_gen_binary_bank(None, None, 0, 0, 0, None, None, None, None, None) == ft.FT_E_INVALID
+    assert lib.ft_eval_binary_random(None, None, 0, 0, 0.0, None, None) == ft.FT_E_INVALID
+    assert C.sizeof(ft.ft_binary_region) == 48
 
 
 def test_oracle_and_library_share_no_code():
