@@ -185,6 +185,58 @@ def bench_precision(ft, synth, log):
     return out
 
 
+def paper_cost_per_template(n, n_sft):
+    """The paper's fit of the GPU cost per template (Sec. III, seconds assumed):
+    log10 c = -(5/3) log10 n + log10 N_SFT / (1 + (10^6/n)^(5/6))."""
+    import math
+    return 10.0 ** (-(5.0 / 3.0) * math.log10(n) + math.log10(n_sft) / (1.0 + (1e6 / n) ** (5.0 / 6.0)))
+
+
+def bench_binary(ft, synth, log, sizes=(10 ** 5, 10 ** 6, 10 ** 7), reps=3):
+    """The paper's benchmark workload (Sec. III): random banks of sources in
+    circular binary systems, generated on the device and evaluated over 10^4
+    SFTs (T = 1024 s, half-overlapping, 2 detectors; 110.5 Hz, 0.125 Hz band,
+    periods 7-15 d, a_p 5-15 lt-s), per batch size n, next to the paper's cost
+    model (its fit for one H100; context, not a target)."""
+    import torch
+    w = synth.binary_band(seed=3, n_tmpl=1, n_per_det=5000)
+    dev = torch.device("cuda:0")
+    c = ft.Context(0, torch.cuda.current_stream().cuda_stream)
+    c.set_sfts(w.n_sft_per_det, torch.from_numpy(w.t_mid).to(dev), w.t_sft, w.first_bin,
+               torch.from_numpy(w.power).to(dev))
+    c.set_velocities(torch.from_numpy(w.v).to(dev))
+    out = {"workload": "random binary-system banks uniform in the xi coordinates, generated on "
+                       "the GPU; 2 det x 5000 SFTs of 1024 s (half-overlapping, 10%% gaps), "
+                       "110.5-110.625 Hz, periods 7-15 d, a_p 5-15 lt-s, K=10 per 0.025 Hz",
+           "n_sft": w.n_sft, "batches": []}
+    for n in sizes:
+        c.eval_binary_random(w.region, 99, n, w.t_ref, w.k, w.sub_edges)
+        c.toplist(0, w.k)
+        eval_ms = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for r in range(reps):
+            c.eval_binary_random(w.region, 100 + r, n, w.t_ref, w.k, w.sub_edges)
+            c.toplist(0, w.k)  # synchronises
+            eval_ms.append(c.info().eval_ms)
+        t1 = time.perf_counter()
+        evals = n * w.n_sft
+        call_s = (t1 - t0) / reps
+        model = paper_cost_per_template(n, w.n_sft)
+        e = {"n_templates": n, "evals": evals,
+             "evals_per_s_kernel": evals / (sum(eval_ms) / reps * 1e-3),
+             "evals_per_s_call": evals / call_s,
+             "s_per_template_call": call_s / n,
+             "paper_model_s_per_template": model,
+             "paper_model_evals_per_s": w.n_sft / model}
+        out["batches"].append(e)
+        log("binary bank n=%d: kernel %.3g evals/s, whole call %.3g evals/s (%.3g s/template; "
+            "paper's H100 fit %.3g)" % (n, e["evals_per_s_kernel"], e["evals_per_s_call"],
+                                         e["s_per_template_call"], model))
+    c.close()
+    return out
+
+
 def bench_surrogate(ft, synth, tau, n_train, n_test, log):
     """Labels from GPU injection campaigns, GPU training, calibration on held-out
     injections, and the cost of a surrogate query against a plain label."""
@@ -238,6 +290,8 @@ def main():
     ap.add_argument("--surrogate-test", type=int, default=100_000)
     ap.add_argument("--skip-extras", action="store_true",
                     help="plain workload only (no batched, precision or surrogate sections)")
+    ap.add_argument("--sections", default="batched,precision,surrogate,binary",
+                    help="comma-separated extra sections to run")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -370,12 +424,16 @@ def main():
     log("LDS gather: kernel %.3g evals/s, probe %.3g evals/s (%.0f%%)"
         % (achieved_evals, probe, 100 * achieved_evals / probe))
     c.close()
-    if not args.skip_extras:
+    sections = set() if args.skip_extras else set(args.sections.split(","))
+    if "batched" in sections:
         line["batched"] = bench_batched(ft, synth, args.batched_runs, log)
+    if "precision" in sections:
         line["precision"] = bench_precision(ft, synth, log)
-        if args.surrogate_train > 0:
-            line["surrogate"] = bench_surrogate(ft, synth, tau, args.surrogate_train,
-                                                args.surrogate_test, log)
+    if "surrogate" in sections and args.surrogate_train > 0:
+        line["surrogate"] = bench_surrogate(ft, synth, tau, args.surrogate_train,
+                                            args.surrogate_test, log)
+    if "binary" in sections:
+        line["binary"] = bench_binary(ft, synth, log)
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on a CPU sample")
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)

@@ -57,6 +57,9 @@ struct ft_ctx_s {
     float *d_power_w = nullptr;
     size_t cap_power_w = 0;
     double *d_tmid = nullptr, *d_v = nullptr, *d_dt = nullptr;
+    float *d_v32 = nullptr;  // velocities rounded to float (estimates of binary tracks)
+    size_t cap_v32 = 0;
+    std::vector<float> v32_h;
     size_t cap_tmid = 0, cap_v = 0, cap_dt = 0;
     double *d_mu_sigma = nullptr;
     uint32_t *d_err = nullptr;
@@ -456,6 +459,7 @@ void ft_destroy(ft_ctx c)
     release(&c->d_prefix, &c->cap_prefix);
     release(&c->d_tmid, &c->cap_tmid);
     release(&c->d_v, &c->cap_v);
+    release(&c->d_v32, &c->cap_v32);
     release(&c->d_dt, &c->cap_dt);
     release(&c->d_mu_sigma, nullptr);
     release(&c->d_err, nullptr);
@@ -620,8 +624,13 @@ static ft_status set_velocities_impl(ft_ctx c, const double *v, bool sync)
         vmax = std::max(vmax, m);
     }
     hipError_t e = ensure(&c->d_v, &c->cap_v, n3);
+    if (e == hipSuccess) e = ensure(&c->d_v32, &c->cap_v32, n3);
     if (e != hipSuccess) return hip_fail(c, e, "alloc velocities");
+    c->v32_h.resize(n3);
+    for (size_t q = 0; q < n3; ++q) c->v32_h[q] = (float)vh[q];
     e = hipMemcpyAsync(c->d_v, vh.data(), n3 * sizeof(double), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(c->d_v32, c->v32_h.data(), n3 * sizeof(float), hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess && sync) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "copy velocities");
     c->v_h.swap(vh);
@@ -973,6 +982,7 @@ static ft_status prepare_bank(ft_ctx c, const ft_bank *bank, double t_ref, EvalR
     run.f0 = c->d_f0;
     run.f1 = c->d_f1;
     run.sky = c->d_sky;
+    run.v32 = c->d_v32;
     run.ap = binary ? c->d_bin : nullptr;
     run.omega = binary ? c->d_bin + n0 : nullptr;
     run.phib = binary ? c->d_bin + 2 * n0 : nullptr;
@@ -988,6 +998,7 @@ static ft_status prepare_bank(ft_ctx c, const ft_bank *bank, double t_ref, EvalR
     run.n_sky = (int32_t)(grid ? ns : 0);
     run.n_list = grid ? 0 : n0;
     run.t_sft = c->t_sft;
+    run.vmax = c->vmax;
     // bounds used by the grid kernel
     if (grid) guard_params(c->f0_h.data(), n0, f0_max, x_max, c->vmax, c->t_sft, run.dT, run.eta);
     (void)dt_min;
@@ -1296,6 +1307,7 @@ ft_status ft_eval_binary_random(ft_ctx c, const ft_binary_region *reg, uint64_t 
     run.weight = c->has_weight ? c->d_weight : nullptr;
     run.dt = c->d_dt;
     run.v = c->d_v;
+    run.v32 = c->d_v32;
     run.f0 = c->d_f0;
     run.f1 = nullptr;
     run.sky = c->d_sky;
@@ -1309,6 +1321,7 @@ ft_status ft_eval_binary_random(ft_ctx c, const ft_binary_region *reg, uint64_t 
     run.first_bin = (int32_t)c->first_bin;
     run.n_list = n;
     run.t_sft = c->t_sft;
+    run.vmax = c->vmax;
     run.sum_mode = opts->sum_mode;
     run.precision = opts->precision;
     return launch_eval_select(c, run, false, -1, n, n, opts, edges, stats);

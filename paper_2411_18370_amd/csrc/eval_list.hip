@@ -345,63 +345,70 @@ __global__ __launch_bounds__(64) void eval_batch_small_kernel(const EvalRun *__r
 
 // Binary-system list banks: one lane per template (the paper's random
 // template banks carry no structure to share between lanes).  Per SFT a lane
-// forms the canonical Doppler factor and orbital phase, then an estimate of
-// the track position x with a single-precision cosine, and keeps
+// forms an estimate of the track position x (single-precision Doppler factor,
+// orbital phase in FP64, single-precision cosine) and keeps
 // B = floor(x + 1/2) when x + 1/2 is farther than eps from an integer; else
-// (about once per 10^4 evaluations) it forms the canonical bin with the
-// library cosine.  It gathers from the table (scalar row base, lane offset);
-// velocities and time offsets are wave-uniform scalar loads.  Lanes past the
-// bank's end repeat its last template and store nothing, so the SFT loop
-// stays wave-uniform.
+// (about once per 2*10^4 evaluations) it forms the canonical bin with the
+// library cosine and FP64 throughout.  It gathers from the table (scalar row
+// base, lane offset); velocities and time offsets are wave-uniform scalar
+// loads.  Lanes past the bank's end repeat its last template and store
+// nothing, so the SFT loop stays wave-uniform.
 //
-// Estimate and guard.  The phase is reduced by pi/2 in FP64 with the first
-// two parts of the library constant (the same quadrant q as the library
-// cosine; the dropped q P3 term is below 4e-15), rounded to float (error
-// <= 2^-24 pi/4 < 5e-8) and put through Taylor polynomials of cos to r^8 and
-// sin to r^9 (truncation < 2.6e-8) in fused single-precision Horner steps
-// (rounding < 3e-7 on |values| <= 1): |cos_est - cos| < 4e-7, and the library
-// cosine is within 2^-52 of cos.  With delta = 1e-6 as the cosine bound, the
-// orbital term a_p Omega cos moves x by at most f0 a_p Omega T delta, and the
-// remaining operations (the canonical ones, on values that differ by that
-// much) add at most a few ulps of x: eps = f0 a_p Omega T delta + 1e-9.
+// Estimate.  y = (Omega/pi) dt - phi_b/pi (the phase in units of pi),
+// q = floor(y + 1/2), r = (y - q) pi (y - q is exact), cos ph = (-1)^q cos r
+// with |r| <= pi/2; r is rounded to float (< 1e-7) and put through the Taylor
+// polynomial of cos to r^12 (truncation < 6.5e-9) in fused single-precision
+// Horner steps (seven roundings of values of magnitude <= 1.3: < 6e-7).
+// Measured over 4e6 phases the estimate stays within 1.6e-7 of cos; the
+// library cosine is within 2^-52 of cos, and the rounding of the phase (a few
+// ulps of y) moves cos by < 1e-13.  delta = 1e-6 bounds the cosine error.
+// Then w = d - (a_p Omega) c with d = v.n, in float from rounded velocities
+// and sky: the roundings of v, n, a_p Omega, the three products and the two
+// fused steps are each below 2^-24 (|v| + |w|) with |w| <= |v| + a_p Omega,
+// so |w - (d - a_p Omega cos ph)| <= a_p Omega delta + 8 * 2^-24 (2|v| + a_p Omega).
+// u = f0 T w + (f0 T + 1/2) is one FP64 fused multiply-add; the canonical
+// x + 1/2 differs from u by at most
+//   eps = f0 T (a_p Omega delta + 8 * 2^-24 (2 |v|max + a_p Omega)) + 1e-9
+// (the last term covers the FP64 roundings, a few ulps of x).
 constexpr double BINARY_COS_DELTA = 1e-6;
 
-__device__ __forceinline__ float binary_cos_estimate(double ph)
+__device__ __forceinline__ float binary_cos_estimate(double y)
 {
-    const double q = floor(ph * 0x1.45f306dc9c883p-1 + 0.5);
-    const double rd = (ph - q * 0x1.921fb54400000p+0) - q * 0x1.0b4611a600000p-34;
-    const float r = (float)rd;
+    const double q = floor(y + 0.5);
+    const float r = (float)((y - q) * 0x1.921fb54442d18p+1);  // pi
     const float r2 = r * r;
-    float ps = __builtin_fmaf(r2, 2.75573192e-6f, -1.98412698e-4f);   // 1/9!, -1/7!
-    ps = __builtin_fmaf(ps, r2, 8.33333333e-3f);                       // 1/5!
-    ps = __builtin_fmaf(ps, r2, -1.66666667e-1f);                      // -1/3!
-    const float sv = __builtin_fmaf(r * r2, ps, r);
-    float pc = __builtin_fmaf(r2, 2.48015873e-5f, -1.38888889e-3f);   // 1/8!, -1/6!
-    pc = __builtin_fmaf(pc, r2, 4.16666667e-2f);                       // 1/4!
-    pc = __builtin_fmaf(pc, r2, -0.5f);
-    const float cv = __builtin_fmaf(r2, pc, 1.0f);
-    const int n = (int)q & 3;
-    return n == 0 ? cv : n == 1 ? -sv : n == 2 ? -cv : sv;
+    float p = __builtin_fmaf(r2, 2.08767570e-9f, -2.75573192e-7f);  // 1/12!, -1/10!
+    p = __builtin_fmaf(p, r2, 2.48015873e-5f);                      // 1/8!
+    p = __builtin_fmaf(p, r2, -1.38888889e-3f);                     // -1/6!
+    p = __builtin_fmaf(p, r2, 4.16666667e-2f);                      // 1/4!
+    p = __builtin_fmaf(p, r2, -0.5f);
+    const float c = __builtin_fmaf(p, r2, 1.0f);
+    return ((int)q & 1) ? -c : c;
 }
+
+// Per-lane constants of one binary template.
+struct BinaryLane {
+    double f0, f0T, f0T_half, nx, ny, nz, aw, omega, phib, om_pi, phib_pi, eps;
+    float nxf, nyf, nzf, awf;
+};
 
 // Byte offset of the canonical bin of one binary template in row k (clamped
 // into the row and flagged when the track leaves the table).
-struct BinaryLane {
-    double f0, nx, ny, nz, aw, omega, phib, eps;
-};
-
 __device__ __forceinline__ uint32_t binary_offset(const EvalRun &r, const BinaryLane &p, int k, bool &bad)
 {
-    const auto *vk = as_const(r.v + 3 * (int64_t)k);
+    const auto *v32 = as_const(r.v32 + 3 * (int64_t)k);
     const double dt = as_const(r.dt)[k];
-    const double g = doppler_factor(vk[0], vk[1], vk[2], p.nx, p.ny, p.nz);
-    double ph = p.omega * dt;
-    ph = ph - p.phib;
-    const double e = p.aw * (double)binary_cos_estimate(ph);
-    const double u = ((p.f0 * (g - e)) * r.t_sft) + 0.5;
-    const double fr = u - floor(u);
+    const float d = __builtin_fmaf(v32[2], p.nzf, __builtin_fmaf(v32[1], p.nyf, v32[0] * p.nxf));
+    const float c = binary_cos_estimate(p.om_pi * dt - p.phib_pi);
+    const float w = __builtin_fmaf(-p.awf, c, d);
+    const double u = fma(p.f0T, (double)w, p.f0T_half);
+    const double fr = __builtin_amdgcn_fract(u);
     int B = (int)u;
-    if (!(fr > p.eps && fr < 1.0 - p.eps)) B = bin_binary(p.f0, g, p.aw, p.omega, p.phib, dt, r.t_sft);
+    if (!(fr > p.eps && fr < 1.0 - p.eps)) {
+        const auto *vk = as_const(r.v + 3 * (int64_t)k);
+        const double g = doppler_factor(vk[0], vk[1], vk[2], p.nx, p.ny, p.nz);
+        B = bin_binary(p.f0, g, p.aw, p.omega, p.phib, dt, r.t_sft);
+    }
     int b = B - r.first_bin;
     if (b < 0 || b >= r.n_bins) {
         bad = true;
@@ -432,7 +439,15 @@ __global__ __launch_bounds__(256) void eval_binary_kernel(EvalRun r)
         p.omega = r.omega[t];
         p.phib = r.phib[t];
         p.aw = r.ap[t] * p.omega;
-        p.eps = p.f0 * p.aw * r.t_sft * BINARY_COS_DELTA + 1e-9;
+        p.f0T = p.f0 * r.t_sft;
+        p.f0T_half = p.f0T + 0.5;
+        p.om_pi = p.omega * 0x1.45f306dc9c883p-2;   // 1/pi
+        p.phib_pi = p.phib * 0x1.45f306dc9c883p-2;
+        p.nxf = (float)p.nx;
+        p.nyf = (float)p.ny;
+        p.nzf = (float)p.nz;
+        p.awf = (float)p.aw;
+        p.eps = p.f0T * (p.aw * BINARY_COS_DELTA + 8.0 * 0x1p-24 * (2.0 * r.vmax + p.aw)) + 1e-9;
         float acc = 0.f;
         double tot = 0.0;
         bool bad = false;

@@ -115,6 +115,7 @@ struct EvalRun {
     const float *weight;  // [n_sft] or nullptr (all ones)
     const double *dt;     // [n_sft] t_mid - t_ref
     const double *v;      // [n_sft][3]
+    const float *v32;     // [n_sft][3] v rounded to float (binary-track estimates)
     const double *f0;     // grid [n_f0] / list [n]
     const double *f1;     // grid [n_f1] / list [n]
     const double *sky;    // grid [n_sky][3] / list [n][3]
@@ -131,6 +132,7 @@ struct EvalRun {
     int32_t n_f0, n_f1, n_sky;
     int64_t n_list;
     double t_sft;
+    double vmax;          // max |v_k| (binary-track estimate bound)
     double dT;            // grid spacing * T_sft (run guard)
     double eta;           // run-guard margin in bins
     int32_t wt;           // LDS window width per SFT (bins, including run padding)
@@ -203,6 +205,7 @@ struct GenRun {
     int64_t first_bin;
     const double *t_mid;  // [n_sft]
     const double *v;      // [n_sft][3]
+    const float *v32;     // [n_sft][3] v rounded to float (binary-track estimates)
     const double *arms;   // [n_sft][6]
     double t_ref, t_sft;
     double amp, cos_iota, psi, sky[3], f0, f1;
