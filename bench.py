@@ -237,6 +237,32 @@ def bench_binary(ft, synth, log, sizes=(10 ** 5, 10 ** 6, 10 ** 7), reps=3):
     return out
 
 
+def bench_mismatch(ft, synth, log, oversampling=(1.0, 3.44, 10.0), n_trials=100):
+    """Mismatch distribution p(m|o) of random binary-system banks (Sec. IV.A) at
+    the paper's oversampling 3.44 and around it: per trial a binary signal in
+    noise (h0/sqrt(Sn) = 1), a random bank of o N(box) templates in a +-2
+    resolution-cell box around it, m of the loudest template (Eq. mismatch)."""
+    import numpy as np
+    import torch
+    from paper_2411_18370_amd import mismatch
+    w = synth.binary_band(seed=3, n_tmpl=1, n_per_det=5000)
+    c = ft.Context(0, torch.cuda.current_stream().cuda_stream)
+    out = {"workload": "2 det x 5000 SFTs of 1024 s (half-overlapping), 110.5-110.625 Hz, periods 7-15 d, "
+                       "a_p 5-15 lt-s; %d trials per oversampling" % n_trials, "p_m_given_o": []}
+    for o in oversampling:
+        t0 = time.perf_counter()
+        r = mismatch.sample(c, w, o=o, n_trials=n_trials, seed=int(o * 1000), amp=1.0)
+        s = mismatch.summary(r["m"])
+        s["o"] = o
+        s["mean_bank_templates"] = float(np.mean([t["n_bank"] for t in r["trials"]]))
+        s["seconds"] = time.perf_counter() - t0
+        out["p_m_given_o"].append(s)
+        log("mismatch o=%.2f: mean %.3f, median %.3f, 90%% in [%.3f, %.3f], %.0f templates per bank (%.1f s)"
+            % (o, s["mean"], s["median"], s["q05"], s["q95"], s["mean_bank_templates"], s["seconds"]))
+    c.close()
+    return out
+
+
 def bench_surrogate(ft, synth, tau, n_train, n_test, log):
     """Labels from GPU injection campaigns, GPU training, calibration on held-out
     injections, and the cost of a surrogate query against a plain label."""
@@ -290,7 +316,7 @@ def main():
     ap.add_argument("--surrogate-test", type=int, default=100_000)
     ap.add_argument("--skip-extras", action="store_true",
                     help="plain workload only (no batched, precision or surrogate sections)")
-    ap.add_argument("--sections", default="batched,precision,surrogate,binary",
+    ap.add_argument("--sections", default="batched,precision,surrogate,binary,mismatch",
                     help="comma-separated extra sections to run")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -434,6 +460,8 @@ def main():
                                             args.surrogate_test, log)
     if "binary" in sections:
         line["binary"] = bench_binary(ft, synth, log)
+    if "mismatch" in sections:
+        line["mismatch"] = bench_mismatch(ft, synth, log)
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on a CPU sample")
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)

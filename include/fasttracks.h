@@ -195,13 +195,19 @@ ft_status ft_eval_templates(ft_ctx ctx, const ft_bank *bank, double t_ref,
  * random bank drawn uniformly in the uniform-density coordinates, which for
  * this model are, up to constants, (f0^6, alpha, sin delta, a_p^3, Omega^4,
  * phi_b) -- Eq. unif_transform of the binary appendix).  The region is the box
- * [f0_lo, f0_hi] x full sky x [ap_lo, ap_hi] x [omega_lo, omega_hi] x [0, 2 pi);
- * 0 < lo <= hi for f0, a_p and Omega, ap_hi * omega_hi < 1/2.
+ * [f0_lo, f0_hi] x [alpha_lo, alpha_hi] x [sdec_lo, sdec_hi] x [ap_lo, ap_hi]
+ * x [omega_lo, omega_hi] x [phib_lo, phib_hi] (right ascension, sine of the
+ * declination; the whole sky and phase range is [0, 2 pi] x [-1, 1] and
+ * [0, 2 pi]); lo <= hi everywhere, 0 < lo for f0, a_p and Omega,
+ * -1 <= sdec_lo, sdec_hi <= 1, |alpha|, |phi_b| < 1e6, ap_hi * omega_hi < 1/2.
  */
 typedef struct {
     double f0_lo, f0_hi;        /* Hz                    */
     double ap_lo, ap_hi;        /* light-seconds         */
     double omega_lo, omega_hi;  /* rad/s                 */
+    double alpha_lo, alpha_hi;  /* rad                   */
+    double sdec_lo, sdec_hi;    /* sin(declination)      */
+    double phib_lo, phib_hi;    /* rad, at t_ref         */
 } ft_binary_region;
 
 /*
@@ -211,9 +217,12 @@ typedef struct {
  * 53-bit uniforms (m + 1/2) 2^-53 from Philox-4x32-10 with counter
  * (i_lo, i_hi, 0, 1 + j), j = 0, 1, 2, key (seed_lo, seed_hi); f0, a_p and
  * Omega are p-th roots of lo^p + u (hi^p - lo^p) (p = 6, 3, 4) by 12 Newton
- * steps from lo + u (hi - lo); alpha = 2 pi u1, sin delta = 2 u2 - 1,
- * phi_b = 2 pi u5 -- a fixed sequence of IEEE operations, reproducible bit
- * for bit.  Synchronous.  Errors: FT_E_INVALID (region, sizes, null arrays).
+ * steps from lo + u (hi - lo); alpha = alpha_lo + u1 (alpha_hi - alpha_lo),
+ * sin delta = sdec_lo + u2 (sdec_hi - sdec_lo), phi_b = phib_lo + u5 (phib_hi
+ * - phib_lo), n = (cos delta cos alpha, cos delta sin alpha, sin delta) with
+ * cos delta = sqrt(1 - sin^2 delta) and the library cosine/sine -- a fixed
+ * sequence of IEEE operations, reproducible bit for bit.  Synchronous.
+ * Errors: FT_E_INVALID (region, sizes, null arrays).
  */
 ft_status ft_gen_binary_bank(ft_ctx ctx, const ft_binary_region *region, uint64_t seed, int64_t first,
                              int64_t n, double *f0, double *sky_xyz, double *ap, double *omega,
@@ -284,11 +293,17 @@ ft_status ft_count_index_mismatches(ft_ctx ctx, const ft_bank *bank, double t_re
 /* One injected continuous-wave signal (Sec. II.B.2).  amp = h0/sqrt(S_n)
  * (the inverse sensitivity depth of Sec. V; 0 = no signal), cos_iota and psi
  * its orientation, sky its unit direction, f0/f1 its frequency and spindown at
- * t_ref. */
+ * t_ref.  ap > 0 puts the source in a circular binary orbit (Eq. track):
+ * projected semimajor axis ap (light-seconds), orbital angular frequency
+ * omega (rad/s), orbital phase phib at t_ref; the track is then
+ * x_k = (f0 + f1 dt) (g - (ap omega) lib_cos(omega dt - phib)) T_sft with the
+ * library cosine (ft_lib_sincos), the BINARY bank's canonical track for
+ * f1 = 0.  ap = 0: an isolated source (omega, phib ignored). */
 typedef struct {
     double amp, cos_iota, psi;
     double sky[3];
     double f0, f1;
+    double ap, omega, phib;
 } ft_injection;
 
 /*

@@ -4,9 +4,10 @@ systems -- TEST INFRASTRUCTURE ONLY.
 Templates are drawn uniformly in the uniform-density coordinates of the
 binary appendix (Eq. unif_transform): xi is, up to constants, (f0^6, alpha,
 sin delta, a_p^3, Omega^4, phi_b), so a uniform draw in xi is
-  f0 = root6(lo^6 + u0 (hi^6 - lo^6)),  alpha = 2 pi u1,  sin delta = 2 u2 - 1,
-  a_p = root3(lo^3 + u3 (hi^3 - lo^3)), Omega = root4(lo^4 + u4 (hi^4 - lo^4)),
-  phi_b = 2 pi u5,
+  f0 = root6(lo^6 + u0 (hi^6 - lo^6)), alpha = lo + u1 (hi - lo),
+  sin delta = lo + u2 (hi - lo), a_p = root3(lo^3 + u3 (hi^3 - lo^3)),
+  Omega = root4(lo^4 + u4 (hi^4 - lo^4)), phi_b = lo + u5 (hi - lo)
+(the whole sky and phase range: alpha and phi_b in [0, 2 pi], sin delta in [-1, 1]),
 with n = (cos delta cos alpha, cos delta sin alpha, sin delta), cos delta =
 sqrt(1 - sin^2 delta) and the library cosine/sine for alpha.
 
@@ -78,16 +79,19 @@ def uniforms(seed, first, n):
     return u
 
 
-def random_binary_bank(seed, first, n, f0_lo, f0_hi, ap_lo, ap_hi, omega_lo, omega_hi):
-    """(f0, sky [n,3], ap, omega, phib) of templates first .. first + n - 1."""
+def random_binary_bank(seed, first, n, f0_lo, f0_hi, ap_lo, ap_hi, omega_lo, omega_hi, alpha_lo=0.0,
+                       alpha_hi=TWO_PI, sdec_lo=-1.0, sdec_hi=1.0, phib_lo=0.0, phib_hi=TWO_PI):
+    """(f0, sky [n,3], ap, omega, phib) of templates first .. first + n - 1 of the
+    region (right ascension, sin(declination) and phase limits default to the
+    whole range)."""
     u = uniforms(seed, first, n)
     f0 = root(f0_lo, f0_hi, u[:, 0], 6)
-    alpha = u[:, 1] * TWO_PI
-    sd = u[:, 2] * 2.0 - 1.0
+    alpha = alpha_lo + u[:, 1] * (alpha_hi - alpha_lo)
+    sd = sdec_lo + u[:, 2] * (sdec_hi - sdec_lo)
     cd = np.sqrt(1.0 - sd * sd)
     ca, sa = pcos(alpha)
     sky = np.stack([cd * ca, cd * sa, sd], axis=1)
     ap = root(ap_lo, ap_hi, u[:, 3], 3)
     omega = root(omega_lo, omega_hi, u[:, 4], 4)
-    phib = u[:, 5] * TWO_PI
+    phib = phib_lo + u[:, 5] * (phib_hi - phib_lo)
     return f0, sky, ap, omega, phib

@@ -9,7 +9,9 @@ hypothesis of Sec. II.B.2:
   SC'11) with counter (b, k, run, 0) and key (seed_lo, seed_hi); two 53-bit
   uniforms per call feed the Box-Muller transform (Box and Muller 1958);
 * signal: in SFT k the track sits at x_k = (f0 + f1 dt_k)(1 + v_k.n) T_sft bins
-  (Eq. track with a_p = 0), B_k = floor(x_k + 1/2), delta_k = x_k - B_k.  Its
+  (Eq. track with a_p = 0), or for a source in a circular binary orbit at
+  x_k = (f0 + f1 dt_k)(1 + v_k.n - a_p Omega cos(Omega dt_k - phi_b)) T_sft
+  (Eq. track), B_k = floor(x_k + 1/2), delta_k = x_k - B_k.  Its
   power non-centrality is rho_k^2 = T_sft (h0^2/S_n) (F+^2 A+^2 + Fx^2 Ax^2),
   A+ = (1 + cos^2 iota)/2, Ax = cos iota -- rho^2 = 4|h~|^2/(T S_n) with
   |h~| = (T/2) h0 |F+ A+ + i Fx Ax| (the two polarisations in quadrature); the
@@ -26,6 +28,8 @@ The GPU generator implements the same specification independently.
 from __future__ import annotations
 
 import numpy as np
+
+from .core import pcos
 
 M0, M1 = 0xD2511F53, 0xCD9E8D57     # Philox-4x32 round multipliers
 W0, W1 = 0x9E3779B9, 0xBB67AE85     # Weyl key increments
@@ -106,11 +110,21 @@ def antenna_patterns(arms, n, psi):
     return fp, fx
 
 
-def track_bins(t_mid, t_ref, t_sft, v, n, f0, f1):
-    """(x_k, B_k): exact FP64 track position in bins and its nearest bin."""
+def track_bins(t_mid, t_ref, t_sft, v, n, f0, f1, ap=0.0, omega=0.0, phib=0.0):
+    """(x_k, B_k): exact FP64 track position in bins and its nearest bin.  With
+    ap > 0 the source is in a circular binary orbit (Eq. track): the Doppler
+    factor g becomes g - (ap omega) cos(omega dt - phib), cos the library cosine
+    of the oracle (core.pcos)."""
     d = (v[:, 0] * n[0] + v[:, 1] * n[1]) + v[:, 2] * n[2]
     g = 1.0 + d
-    x = ((f0 + f1 * (t_mid - t_ref)) * g) * t_sft
+    dt = t_mid - t_ref
+    h = g
+    if ap > 0.0:
+        ph = omega * dt
+        ph = ph - phib
+        cb, _ = pcos(ph)
+        h = g - (ap * omega) * cb
+    x = ((f0 + f1 * dt) * h) * t_sft
     return x, np.floor(x + 0.5)
 
 
@@ -133,7 +147,8 @@ def sinc(y):
 def signal_amplitudes(t_mid, t_ref, t_sft, v, arms, inj):
     """(B_k, A [N, 3]) -- amplitude added to Re at bins B_k - 1, B_k, B_k + 1."""
     n = np.asarray(inj["sky"], np.float64)
-    x, B = track_bins(t_mid, t_ref, t_sft, v, n, inj["f0"], inj["f1"])
+    x, B = track_bins(t_mid, t_ref, t_sft, v, n, inj["f0"], inj.get("f1", 0.0), inj.get("ap", 0.0),
+                      inj.get("omega", 0.0), inj.get("phib", 0.0))
     delta = x - B
     r2 = rho2(arms, n, inj["psi"], inj["cos_iota"], inj["amp"], t_sft)
     A = np.stack([np.sqrt(r2) * np.abs(sinc(np.pi * (delta - m))) for m in (-1, 0, 1)], axis=1)

@@ -640,6 +640,23 @@ static ft_status set_velocities_impl(ft_ctx c, const double *v, bool sync)
     return FT_OK;
 }
 
+// Validation of one injected signal; returns an error text or nullptr.
+static const char *injection_error(const ft_injection &in)
+{
+    const double vals[] = {in.amp, in.cos_iota, in.psi, in.sky[0], in.sky[1], in.sky[2], in.f0, in.f1,
+                           in.ap, in.omega, in.phib};
+    for (double x : vals)
+        if (!std::isfinite(x)) return "injection parameters must be finite";
+    if (in.amp < 0.0 || in.cos_iota < -1.0 || in.cos_iota > 1.0) return "injection needs amp >= 0 and cos_iota in [-1, 1]";
+    if (in.amp > 0.0 && std::fabs(std::sqrt(in.sky[0] * in.sky[0] + in.sky[1] * in.sky[1] + in.sky[2] * in.sky[2]) - 1.0) > 1e-12)
+        return "injection sky must be a unit vector";
+    if (in.amp > 0.0 && !(in.f0 > 0.0)) return "injection f0 must be > 0";
+    if (in.ap < 0.0 || in.omega < 0.0) return "injection needs ap >= 0 and omega >= 0";
+    if (in.ap > 0.0 && !(in.ap * in.omega < 0.5)) return "injection needs ap * omega < 1/2";
+    if (in.ap > 0.0 && !(std::fabs(in.phib) < 1e6)) return "injection phib must satisfy |phib| < 1e6";
+    return nullptr;
+}
+
 ft_status ft_gen_sfts(ft_ctx c, int32_t n_det, const int32_t *n_sft, const double *t_mid, double t_sft,
                       int64_t first_bin, int32_t n_bins, const double *v_over_c, const double *arms,
                       uint64_t seed, uint32_t run, double t_ref, const ft_injection *inj, int32_t n_inj,
@@ -668,14 +685,8 @@ ft_status ft_gen_sfts(ft_ctx c, int32_t n_det, const int32_t *n_sft, const doubl
     std::vector<ft_injection> ins;
     if (n_inj > 0 && fetch(ins, inj, (size_t)n_inj) != hipSuccess) return fail(c, FT_E_INVALID, "cannot read inj");
     for (const ft_injection &in : ins) {
-        const double vals[] = {in.amp, in.cos_iota, in.psi, in.sky[0], in.sky[1], in.sky[2], in.f0, in.f1};
-        for (double x : vals)
-            if (!is_finite(x)) return fail(c, FT_E_INVALID, "injection parameters must be finite");
-        if (in.amp < 0.0 || in.cos_iota < -1.0 || in.cos_iota > 1.0)
-            return fail(c, FT_E_INVALID, "injection needs amp >= 0 and cos_iota in [-1, 1]");
-        if (in.amp > 0.0 && std::fabs(std::sqrt(in.sky[0] * in.sky[0] + in.sky[1] * in.sky[1] + in.sky[2] * in.sky[2]) - 1.0) > 1e-12)
-            return fail(c, FT_E_INVALID, "injection sky must be a unit vector");
-        if (in.amp > 0.0 && !(in.f0 > 0.0)) return fail(c, FT_E_INVALID, "injection f0 must be > 0");
+        const char *msg = injection_error(in);
+        if (msg) return fail(c, FT_E_INVALID, "%s", msg);
     }
     std::vector<double> tm, ah;
     if (fetch(tm, t_mid, (size_t)total) != hipSuccess || fetch(ah, arms, (size_t)total * 6) != hipSuccess)
@@ -737,6 +748,9 @@ ft_status ft_gen_sfts(ft_ctx c, int32_t n_det, const int32_t *n_sft, const doubl
         for (int d = 0; d < 3; ++d) p.sky[d] = in.sky[d];
         p.f0 = in.f0;
         p.f1 = in.f1;
+        p.ap = in.ap;
+        p.omega = in.omega;
+        p.phib = in.phib;
         p.inj_bin = c->d_inj_bin + (int64_t)i * total;
         p.inj_amp = c->d_inj_amp + 3 * (int64_t)i * total;
         p.n_inj = 1;
@@ -1239,9 +1253,16 @@ static ft_status launch_eval_select(ft_ctx c, EvalRun &run, bool grid, int tile,
 static ft_status check_region(ft_ctx c, const ft_binary_region *reg)
 {
     if (!reg) return fail(c, FT_E_INVALID, "region is null");
-    const double v[6] = {reg->f0_lo, reg->f0_hi, reg->ap_lo, reg->ap_hi, reg->omega_lo, reg->omega_hi};
+    const double v[12] = {reg->f0_lo,    reg->f0_hi,    reg->ap_lo,   reg->ap_hi,   reg->omega_lo, reg->omega_hi,
+                          reg->alpha_lo, reg->alpha_hi, reg->sdec_lo, reg->sdec_hi, reg->phib_lo,  reg->phib_hi};
     for (double x : v)
         if (!is_finite(x)) return fail(c, FT_E_INVALID, "region bounds must be finite");
+    if (!(reg->alpha_lo <= reg->alpha_hi) || !(reg->sdec_lo <= reg->sdec_hi) || !(reg->phib_lo <= reg->phib_hi) ||
+        reg->sdec_lo < -1.0 || reg->sdec_hi > 1.0)
+        return fail(c, FT_E_INVALID, "region needs lo <= hi and sin(declination) in [-1, 1]");
+    if (!(std::fabs(reg->alpha_lo) < 1e6 && std::fabs(reg->alpha_hi) < 1e6 && std::fabs(reg->phib_lo) < 1e6 &&
+          std::fabs(reg->phib_hi) < 1e6))
+        return fail(c, FT_E_INVALID, "region angles must lie within 1e6 rad");
     if (!(reg->f0_lo > 0.0 && reg->f0_lo <= reg->f0_hi) || !(reg->ap_lo > 0.0 && reg->ap_lo <= reg->ap_hi) ||
         !(reg->omega_lo > 0.0 && reg->omega_lo <= reg->omega_hi))
         return fail(c, FT_E_INVALID, "region needs 0 < lo <= hi for f0, a_p and Omega");
@@ -1290,7 +1311,8 @@ ft_status ft_eval_binary_random(ft_ctx c, const ft_binary_region *reg, uint64_t 
     if (c->n_bins >= (1 << 28)) return fail(c, FT_E_UNSUPPORTED, "binary banks need tables of fewer than 2^28 columns");
     double dt_abs = 0.0;
     for (double t : c->t_mid_h) dt_abs = std::max(dt_abs, std::fabs(t - t_ref));
-    if (!(reg->omega_hi * dt_abs + 7.0 < 1.5e6)) return fail(c, FT_E_UNSUPPORTED, "orbital phase beyond 1.5e6 rad");
+    if (!(reg->omega_hi * dt_abs + std::max(std::fabs(reg->phib_lo), std::fabs(reg->phib_hi)) < 1.5e6))
+        return fail(c, FT_E_UNSUPPORTED, "orbital phase beyond 1.5e6 rad");
     const double x_max = reg->f0_hi * (1.0 + c->vmax + reg->ap_hi * reg->omega_hi) * c->t_sft;
     if (!(x_max < 2147483000.0)) return fail(c, FT_E_UNSUPPORTED, "track frequencies above 2^31/T_sft");
     hipError_t e;
@@ -1800,16 +1822,8 @@ ft_status ft_eval_batch(ft_ctx c, const ft_batch *bt, int32_t use_graph)
         if (!gen && (R.table_offset < 0 || R.table_offset + cells > bt->power_len))
             return fail(c, FT_E_INVALID, "run %d: table slice out of range", r);
         if (gen) {
-            const ft_injection &in = R.inj;
-            const double vals[] = {in.amp, in.cos_iota, in.psi, in.sky[0], in.sky[1], in.sky[2], in.f0, in.f1};
-            for (double x : vals)
-                if (!is_finite(x)) return fail(c, FT_E_INVALID, "run %d: injection must be finite", r);
-            if (in.amp < 0.0 || in.cos_iota < -1.0 || in.cos_iota > 1.0)
-                return fail(c, FT_E_INVALID, "run %d: injection needs amp >= 0 and cos_iota in [-1, 1]", r);
-            if (in.amp > 0.0 &&
-                (std::fabs(std::sqrt(in.sky[0] * in.sky[0] + in.sky[1] * in.sky[1] + in.sky[2] * in.sky[2]) - 1.0) > 1e-12 ||
-                 !(in.f0 > 0.0)))
-                return fail(c, FT_E_INVALID, "run %d: injection needs a unit sky vector and f0 > 0", r);
+            const char *msg = injection_error(R.inj);
+            if (msg) return fail(c, FT_E_INVALID, "run %d: %s", r, msg);
         }
         const double *f0 = f0h.data() + R.f0_begin;
         const double *f1 = f1h.data() + R.f1_begin;
@@ -1963,6 +1977,9 @@ ft_status ft_eval_batch(ft_ctx c, const ft_batch *bt, int32_t use_graph)
             for (int d = 0; d < 3; ++d) g.sky[d] = R.inj.sky[d];
             g.f0 = R.inj.f0;
             g.f1 = R.inj.f1;
+            g.ap = R.inj.ap;
+            g.omega = R.inj.omega;
+            g.phib = R.inj.phib;
             g.table = b.power + pl.gen_prefix_elem[r];
             g.inj_bin = b.inj_bin + pl.gen_prefix_sft[r];
             g.inj_amp = b.inj_amp + 3 * pl.gen_prefix_sft[r];

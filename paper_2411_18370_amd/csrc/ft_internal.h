@@ -209,6 +209,7 @@ struct GenRun {
     const double *arms;   // [n_sft][6]
     double t_ref, t_sft;
     double amp, cos_iota, psi, sky[3], f0, f1;
+    double ap, omega, phib;  // binary orbit of the signal (ap = 0: isolated)
     float *table;         // [n_sft][n_bins] output
     int32_t *inj_bin;     // [n_inj][n_sft] scratch (a preparation record: [n_sft])
     double *inj_amp;      // [n_inj][n_sft][3] scratch (a preparation record: [n_sft][3])

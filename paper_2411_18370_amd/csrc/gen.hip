@@ -114,7 +114,16 @@ __device__ void gen_prep_one(const GenRun &g, int k)
     const double dt = g.t_mid[k] - g.t_ref;
     const double c = g.f1 * dt;
     const double a = g.f0 + c;
-    const double f = a * gk;
+    double h = gk;
+    if (g.ap > 0.0) {  // binary orbit: h = g - (a_p Omega) cos(Omega dt - phi_b)
+        double ph = g.omega * dt;
+        ph = ph - g.phib;
+        double sb, cb;
+        lib_sincos(ph, sb, cb);
+        const double e = (g.ap * g.omega) * cb;
+        h = gk - e;
+    }
+    const double f = a * h;
     const double x = f * g.t_sft;
     const double B = floor(x + 0.5);
     const double delta = x - B;
@@ -214,16 +223,15 @@ __global__ __launch_bounds__(256) void gen_noise_kernel(const GenRun *runs, int 
 // (f0^6, alpha, sin delta, a_p^3, Omega^4, phi_b)).  Template i draws six
 // 53-bit uniforms from three Philox calls with counter (i_lo, i_hi, 0, 1 + j)
 // and key (seed_lo, seed_hi) (the noise counters carry word 3 = 0), then
-//   f0 = root6(lo^6 + u0 (hi^6 - lo^6)), alpha = 2 pi u1, sin delta = 2 u2 - 1,
-//   a_p = root3(...u3...), Omega = root4(...u4...), phi_b = 2 pi u5,
+//   f0 = root6(lo^6 + u0 (hi^6 - lo^6)), alpha = alpha_lo + u1 (alpha_hi -
+//   alpha_lo), sin delta = sdec_lo + u2 (sdec_hi - sdec_lo), a_p = root3(...u3...),
+//   Omega = root4(...u4...), phi_b = phib_lo + u5 (phib_hi - phib_lo),
 //   n = (cos delta cos alpha, cos delta sin alpha, sin delta), cos delta =
 //   sqrt(1 - sin^2 delta), library cosine/sine of alpha.
 // Roots: 12 Newton steps z <- z - (z^p - y)/(p z^(p-1)) from the linear
 // interpolation lo + u (hi - lo), powers as z^3 = (z z) z, z^4 = (z z)(z z),
 // z^5 = ((z z)(z z)) z, z^6 = ((z z) z)((z z) z): a fixed sequence of IEEE
 // operations, so the bank is reproducible bit for bit.
-constexpr double TWO_PI_D = 0x1.921fb54442d18p+2;
-
 template <int P>
 __device__ __forceinline__ double xi_pow(double z)
 {
@@ -260,8 +268,8 @@ __global__ __launch_bounds__(256) void gen_binary_bank_kernel(ft_binary_region r
             u[2 * j + 1] = unit53(c[2], c[3]);
         }
         f0[i] = xi_root<6>(reg.f0_lo, reg.f0_hi, u[0]);
-        const double alpha = u[1] * TWO_PI_D;
-        const double sd = u[2] * 2.0 - 1.0;
+        const double alpha = reg.alpha_lo + u[1] * (reg.alpha_hi - reg.alpha_lo);
+        const double sd = reg.sdec_lo + u[2] * (reg.sdec_hi - reg.sdec_lo);
         const double cd = sqrt(1.0 - sd * sd);
         double sa, ca;
         lib_sincos(alpha, sa, ca);
@@ -270,7 +278,7 @@ __global__ __launch_bounds__(256) void gen_binary_bank_kernel(ft_binary_region r
         sky[3 * i + 2] = sd;
         ap[i] = xi_root<3>(reg.ap_lo, reg.ap_hi, u[3]);
         omega[i] = xi_root<4>(reg.omega_lo, reg.omega_hi, u[4]);
-        phib[i] = u[5] * TWO_PI_D;
+        phib[i] = reg.phib_lo + u[5] * (reg.phib_hi - reg.phib_lo);
     }
 }
 

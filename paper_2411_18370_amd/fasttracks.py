@@ -38,13 +38,21 @@ class ft_bank(C.Structure):
 
 class ft_binary_region(C.Structure):
     _fields_ = [("f0_lo", C.c_double), ("f0_hi", C.c_double), ("ap_lo", C.c_double),
-                ("ap_hi", C.c_double), ("omega_lo", C.c_double), ("omega_hi", C.c_double)]
+                ("ap_hi", C.c_double), ("omega_lo", C.c_double), ("omega_hi", C.c_double),
+                ("alpha_lo", C.c_double), ("alpha_hi", C.c_double), ("sdec_lo", C.c_double),
+                ("sdec_hi", C.c_double), ("phib_lo", C.c_double), ("phib_hi", C.c_double)]
+
+
+FULL_SKY_AND_PHASE = dict(alpha_lo=0.0, alpha_hi=2.0 * np.pi, sdec_lo=-1.0, sdec_hi=1.0, phib_lo=0.0,
+                          phib_hi=2.0 * np.pi)
 
 
 def make_region(d):
+    """ft_binary_region from a dict (sky and phase limits default to the whole range)."""
     r = ft_binary_region()
+    full = dict(FULL_SKY_AND_PHASE, **d)
     for name, _ in ft_binary_region._fields_:
-        setattr(r, name, float(d[name]))
+        setattr(r, name, float(full[name]))
     return r
 
 
@@ -62,7 +70,8 @@ class ft_candidate(C.Structure):
 
 class ft_injection(C.Structure):
     _fields_ = [("amp", C.c_double), ("cos_iota", C.c_double), ("psi", C.c_double),
-                ("sky", C.c_double * 3), ("f0", C.c_double), ("f1", C.c_double)]
+                ("sky", C.c_double * 3), ("f0", C.c_double), ("f1", C.c_double),
+                ("ap", C.c_double), ("omega", C.c_double), ("phib", C.c_double)]
 
 
 class ft_run(C.Structure):
@@ -227,14 +236,16 @@ def ft_set_sfts(ctx, n_sft_per_det, t_mid, t_sft, first_bin, power, weight=None)
 
 
 def make_injection(inj):
-    """ft_injection from a dict with amp, cos_iota, psi, sky, f0, f1 (or None)."""
+    """ft_injection from a dict with amp, cos_iota, psi, sky, f0, f1 and, for a
+    binary orbit, ap, omega, phib (or None)."""
     if inj is None:
         return None
     r = ft_injection()
     r.amp, r.cos_iota, r.psi = inj["amp"], inj["cos_iota"], inj["psi"]
     for d in range(3):
         r.sky[d] = float(inj["sky"][d])
-    r.f0, r.f1 = inj["f0"], inj["f1"]
+    r.f0, r.f1 = inj["f0"], inj.get("f1", 0.0)
+    r.ap, r.omega, r.phib = inj.get("ap", 0.0), inj.get("omega", 0.0), inj.get("phib", 0.0)
     return r
 
 
@@ -418,7 +429,8 @@ RUN_DTYPE = np.dtype([("seed", "<u8"), ("run_id", "<u4"), ("sft_begin", "<i4"),
                       ("f1_begin", "<i4"), ("n_f1", "<i4"), ("sky_begin", "<i4"),
                       ("n_sky", "<i4"), ("t_ref", "<f8"), ("amp", "<f8"), ("cos_iota", "<f8"),
                       ("psi", "<f8"), ("inj_sky", "<f8", (3,)), ("inj_f0", "<f8"),
-                      ("inj_f1", "<f8")], align=True)
+                      ("inj_f1", "<f8"), ("inj_ap", "<f8"), ("inj_omega", "<f8"),
+                      ("inj_phib", "<f8")], align=True)
 
 
 def make_runs(runs):

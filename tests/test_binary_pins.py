@@ -127,3 +127,31 @@ def test_bank_roots_are_accurate(p):
     y = lo ** p + u * (hi ** p - lo ** p)
     exact = np.array([float(math.pow(float(v), 1.0 / p)) for v in y[:2000]])
     assert np.max(np.abs(z[:2000] - exact) / exact) < 8 * 2.0 ** -53
+
+
+def test_binary_injection_track_is_the_template_track():
+    """The injector's binary track (f1 = 0) lands on the BINARY template's
+    canonical bins, and a strong injection lights exactly the template's path."""
+    from oracle import inject
+    w = _small(n=1, n_per_det=120)
+    rng = np.random.default_rng(5)
+    n = synth.isotropic_sky(1, rng)[0]
+    lam = dict(f0=110.55, ap=9.0, omega=2 * np.pi / (8.5 * 86400.0), phib=0.7)
+    x, B = inject.track_bins(w.t_mid, w.t_ref, w.t_sft, w.v, n, lam["f0"], 0.0, lam["ap"], lam["omega"],
+                             lam["phib"])
+    bins = oracle.bins_binary(w.t_mid, w.t_ref, w.t_sft, w.v, [lam["f0"]], n[None, :], [lam["ap"]],
+                              [lam["omega"]], [lam["phib"]])[0]
+    assert np.array_equal(B.astype(np.int64), bins)
+    # ap = 0: the isolated track
+    x0, B0 = inject.track_bins(w.t_mid, w.t_ref, w.t_sft, w.v, n, lam["f0"], 0.0)
+    x1, B1 = inject.track_bins(w.t_mid, w.t_ref, w.t_sft, w.v, n, lam["f0"], 0.0, 0.0, lam["omega"], 1.0)
+    assert np.array_equal(x0, x1)
+    # a strong injection: the template collects about rho^2 per SFT more than noise
+    inj = dict(amp=3.0, cos_iota=0.3, psi=0.1, sky=n, f0=lam["f0"], f1=0.0, **{k: lam[k] for k in ("ap", "omega", "phib")})
+    table = inject.generate_table(11, 2, w.t_mid, w.t_ref, w.t_sft, w.v, w.arms, w.first_bin, w.n_bins, inj)
+    s_sig, _ = oracle.eval_binary(w.t_mid, w.t_ref, w.t_sft, w.first_bin, table, None, w.v, [lam["f0"]],
+                                  n[None, :], [lam["ap"]], [lam["omega"]], [lam["phib"]])
+    s_off, _ = oracle.eval_binary(w.t_mid, w.t_ref, w.t_sft, w.first_bin, table, None, w.v, [lam["f0"]],
+                                  n[None, :], [lam["ap"]], [lam["omega"]], [lam["phib"] + 1.5])
+    mu, sig = oracle.noise_moments(w.n_sft)
+    assert (s_sig[0] - mu) / sig > 30 and (s_off[0] - mu) / sig < 0.5 * (s_sig[0] - mu) / sig

@@ -101,6 +101,15 @@ def test_random_bank_is_bitexact_and_evaluates_like_the_explicit_bank(ft):
             assert np.array_equal(a.view(np.uint64), b.view(np.uint64))
         part = c.gen_binary_bank(w.region, seed, 4000, 7)
         assert all(np.array_equal(a, b[4000:4007]) for a, b in zip(part, (f0, sky, ap, om, pb)))
+        # a local box (sky and phase limits)
+        box = dict(w.region, alpha_lo=1.0, alpha_hi=1.3, sdec_lo=-0.2, sdec_hi=0.05, phib_lo=-2.0,
+                   phib_hi=3.5)
+        gb = c.gen_binary_bank(box, seed, 17, 3000)
+        ob = obank.random_binary_bank(seed, 17, 3000, **box)
+        for a, b in zip(gb, ob):
+            assert np.array_equal(a.view(np.uint64), b.view(np.uint64))
+        assert np.all((gb[1][:, 2] >= -0.2) & (gb[1][:, 2] <= 0.05))
+        assert np.all((gb[4] >= -2.0) & (gb[4] <= 3.5))
         c.eval_binary_random(w.region, seed, n, w.t_ref, k, w.sub_edges)
         _check_toplists(ft, c, w, s64, k, f0)
         c.eval_binary(f0, sky, ap, om, pb, w.t_ref, k, w.sub_edges)
