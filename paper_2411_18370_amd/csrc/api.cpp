@@ -2249,7 +2249,7 @@ ft_status ft_mlp_create(ft_ctx c, const float *params, uint64_t seed, const floa
     if (e == hipSuccess) e = mlp_alloc(p, &m.logit, (size_t)mb);
     if (e == hipSuccess) e = mlp_alloc(p, &m.dlogit, (size_t)mb);
     if (e == hipSuccess) e = mlp_alloc(p, &m.loss, (size_t)1);
-    if (e == hipSuccess) e = mlp_alloc(p, &m.part, (size_t)(mb / 64) * MLP_H * 6);
+    if (e == hipSuccess) e = mlp_alloc(p, &m.part, (size_t)(mb / 16) * MLP_H * 7);
     if (e != hipSuccess) {
         mlp_free(p);
         delete p;

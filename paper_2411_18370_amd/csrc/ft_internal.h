@@ -282,7 +282,7 @@ struct MlpBufs {
     __bf16 *w2b, *w3b;
     float *x, *z1, *z2, *z3, *dz1, *dz2, *dz3, *logit, *dlogit, *loss;
     __bf16 *a1, *a2, *a3, *dz1b, *dz2b, *dz3b;
-    float *part;    // [max_batch / 64][MLP_H * 6] partial sums of the gradient reductions
+    float *part;    // [max_batch / 16][MLP_H * 7] partial sums of the gradient reductions
     int max_batch;  // multiple of 64
 };
 hipError_t mlp_refresh_bf16(const MlpBufs &m, hipStream_t s);

@@ -190,13 +190,16 @@ __global__ void head_back_kernel(const float *dlogit, const float *params, const
 }
 
 // Gradient reductions over the batch, in two deterministic stages: chunk c of
-// 64 rows writes part[c][q] = sum over its rows of term(b, q); then
+// RED_ROWS rows writes part[c][q] = sum over its rows of term(b, q); then
 // out[q] = sum_c part[c][q] in chunk order.
 //   RED_COL:  term = v[b][q], q < 256 (bias gradients)
 //   RED_HEAD: term = dlogit[b] a3[b][q] for q < 256, dlogit[b] for q = 256
 //             (output-layer weights and bias)
-//   RED_W1:   term = dz1[b][q / 6] x[b][q % 6], q < 1536 (first-layer weights)
-enum { RED_COL = 0, RED_HEAD = 1, RED_W1 = 2 };
+//   RED_L1:   the first layer: for hidden unit j, term = dz1[b][j] x[b][i] at
+//             q = 6 j + i (i < 6, weights) and dz1[b][j] at q = 1536 + j
+//             (bias), one thread per unit holding its seven sums
+enum { RED_COL = 0, RED_HEAD = 1, RED_L1 = 2 };
+constexpr int RED_ROWS = 16;
 
 template <int MODE>
 __global__ __launch_bounds__(256) void reduce_part_kernel(const float *v, const __bf16 *a3,
@@ -204,13 +207,27 @@ __global__ __launch_bounds__(256) void reduce_part_kernel(const float *v, const 
                                                           float *part)
 {
     const int c = blockIdx.x;
-    const int b0 = c * 64, b1 = min(b0 + 64, bsz);
+    const int b0 = c * RED_ROWS, b1 = min(b0 + RED_ROWS, bsz);
+    if (MODE == RED_L1) {
+        const int j = threadIdx.x;  // blockDim.x == H
+        float s[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        for (int b = b0; b < b1; ++b) {
+            const float d = v[(int64_t)b * H + j];
+#pragma unroll
+            for (int i = 0; i < 6; ++i) s[i] += d * x[b * 6 + i];
+            s[6] += d;
+        }
+        float *out = part + (int64_t)c * n_out;
+#pragma unroll
+        for (int i = 0; i < 6; ++i) out[6 * j + i] = s[i];
+        out[6 * H + j] = s[6];
+        return;
+    }
     for (int q = threadIdx.x; q < n_out; q += blockDim.x) {
         float s = 0.f;
         for (int b = b0; b < b1; ++b) {
             if (MODE == RED_COL) s += v[(int64_t)b * H + q];
             if (MODE == RED_HEAD) s += q < H ? v[b] * (float)a3[(int64_t)b * H + q] : v[b];
-            if (MODE == RED_W1) s += v[(int64_t)b * H + q / 6] * x[b * 6 + q % 6];
         }
         part[(int64_t)c * n_out + q] = s;
     }
@@ -256,7 +273,7 @@ template <int MODE>
 void reduce_rows(const float *v, const __bf16 *a3, const float *x, int bsz, int n_out, float *part,
                  float *out, hipStream_t s)
 {
-    const int n_chunks = (bsz + 63) / 64;
+    const int n_chunks = (bsz + RED_ROWS - 1) / RED_ROWS;
     hipLaunchKernelGGL(reduce_part_kernel<MODE>, dim3(n_chunks), dim3(256), 0, s, v, a3, x, bsz, n_out,
                        part);
     hipLaunchKernelGGL(reduce_sum_kernel, dim3(blocks(n_out, 256)), dim3(256), 0, s, part, n_chunks, n_out,
@@ -314,8 +331,8 @@ hipError_t mlp_backward(const MlpBufs &m, int bsz, hipStream_t s)
     hipLaunchKernelGGL((gemm_bf16_kernel<true, false, EPI_BWD>), g2, dim3(256), 0, s, m.dz2b, m.w2b,
                        m_pad, H, H, H, H, nullptr, m.z1, m.dz1, m.dz1b);
     // layer 1
-    reduce_rows<RED_W1>(m.dz1, nullptr, m.x, bsz, H * 6, m.part, g, s);
-    reduce_rows<RED_COL>(m.dz1, nullptr, nullptr, bsz, H, m.part, g + H * 6, s);
+    // weights and bias of the first layer are contiguous: g[0 .. 7H)
+    reduce_rows<RED_L1>(m.dz1, nullptr, m.x, bsz, H * 7, m.part, g, s);
     return hipGetLastError();
 }
 
