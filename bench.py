@@ -263,6 +263,39 @@ def bench_mismatch(ft, synth, log, oversampling=(1.0, 3.44, 10.0), n_trials=100)
     return out
 
 
+def bench_sensitivity(ft, synth, log, o=3.44, tau=8.0, depths=(15.0, 22.0, 27.0, 33.0, 45.0), n_inj=150,
+                      n_q=100_000):
+    """Semi-analytic sensitivity estimate (Sec. V) against plain injections (the
+    comparison of Sec. VI) for the random-bank binary search at oversampling o:
+    p_det at each depth from q samples of 10^5 population draws and p(m|o), and
+    from n_inj injections per depth (loudest template of a random bank around
+    each), rule z > tau; with the cost of each."""
+    import numpy as np
+    import torch
+    from paper_2411_18370_amd import mismatch, sensitivity
+    w = synth.binary_band(seed=3, n_tmpl=1, n_per_det=5000)
+    c = ft.Context(0, torch.cuda.current_stream().cuda_stream)
+    m = mismatch.sample(c, w, o=o, n_trials=100, seed=12, amp=1.0)["m"]
+    c.set_sfts(w.n_sft_per_det, w.t_mid, w.t_sft, w.first_bin, w.power)
+    t0 = time.perf_counter()
+    q = sensitivity.q_samples(c, w.arms, n_q, seed=13)
+    p_sa = sensitivity.p_det(q, m, depths, tau, seed=14)
+    t_sa = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    p_inj = sensitivity.injection_p_det(c, w, depths, n_inj, o, tau, seed=15)
+    t_inj = time.perf_counter() - t0
+    c.close()
+    se = np.sqrt(np.maximum(p_inj * (1 - p_inj), 1.0 / n_inj) / n_inj)
+    out = {"workload": "random-bank binary search, 2 det x 5000 SFTs of 1024 s, 110.5 Hz; oversampling %g, "
+                       "rule z > %g; %d q samples, %d injections per depth" % (o, tau, n_q, n_inj),
+           "depths": list(depths), "p_det_semi_analytic": p_sa.tolist(), "p_det_injections": p_inj.tolist(),
+           "binomial_se": se.tolist(), "max_abs_diff": float(np.max(np.abs(p_sa - p_inj))),
+           "seconds_semi_analytic": t_sa, "seconds_injections": t_inj}
+    log("sensitivity: depths %s, semi-analytic %s (%.2f s), injections %s (%.1f s)"
+        % (list(depths), np.round(p_sa, 3).tolist(), t_sa, np.round(p_inj, 3).tolist(), t_inj))
+    return out
+
+
 def bench_surrogate(ft, synth, tau, n_train, n_test, log):
     """Labels from GPU injection campaigns, GPU training, calibration on held-out
     injections, and the cost of a surrogate query against a plain label."""
@@ -316,7 +349,7 @@ def main():
     ap.add_argument("--surrogate-test", type=int, default=100_000)
     ap.add_argument("--skip-extras", action="store_true",
                     help="plain workload only (no batched, precision or surrogate sections)")
-    ap.add_argument("--sections", default="batched,precision,surrogate,binary,mismatch",
+    ap.add_argument("--sections", default="batched,precision,surrogate,binary,mismatch,sensitivity",
                     help="comma-separated extra sections to run")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -462,6 +495,8 @@ def main():
         line["binary"] = bench_binary(ft, synth, log)
     if "mismatch" in sections:
         line["mismatch"] = bench_mismatch(ft, synth, log)
+    if "sensitivity" in sections:
+        line["sensitivity"] = bench_sensitivity(ft, synth, log)
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on a CPU sample")
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)

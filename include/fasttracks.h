@@ -133,6 +133,25 @@ typedef struct {
 } ft_bank;
 
 /*
+ * ft_q_sample -- the four signal-response quantities of the semi-analytic
+ * sensitivity estimate (Sec. V.A) for population samples i = 0..n-1 (sky
+ * unit vectors sky[n][3], cos_iota[n] in [-1, 1], psi[n]) on the context's
+ * SFTs (ft_set_sfts: count, T_sft, weights u_k, all 1 when none), with the
+ * detectors' arm unit vectors arms[N][6] = (u, w) at the SFT mid-times:
+ *   q[i] = (mu_G, sigma_G, rho1, rho2) = (2 sum u, 2 sqrt(sum u^2),
+ *           sum u rho_k, sum u^2 rho_k),
+ *   rho_k = T_sft (F+^2 A+^2 + Fx^2 Ax^2), A+ = (1 + cos^2 iota)/2,
+ *   Ax = cos iota, F+ = D:e+, Fx = D:ex, D = (u u^T - w w^T)/2, (e+, ex) from
+ *   the source frame (e_alpha, e_delta) rotated by psi -- rho_hat^2 of
+ *   Sec. II.B.2 with the polarisations in quadrature (h0^2/S_n = 1; the bin
+ *   offset's power loss is not included).  Sums in FP64, sequential in SFT
+ *   order.  q_out[n][4] host or device; synchronous.  Errors: FT_E_STATE
+ *   before ft_set_sfts, FT_E_INVALID (inputs).
+ */
+ft_status ft_q_sample(ft_ctx ctx, const double *arms, int64_t n, const double *sky, const double *cos_iota,
+                      const double *psi, double *q_out);
+
+/*
  * ft_lib_sincos -- the library's FP64 cosine and sine (the phase function of
  * BINARY banks): a fixed sequence of IEEE additions and multiplications --
  * Cody-Waite reduction by pi/2 (three-part constant, 33-bit leading parts)

@@ -74,6 +74,8 @@ struct ft_ctx_s {
     size_t cap_sincos = 0;
     double *d_genbank = nullptr;  // ft_gen_binary_bank staging: f0 | sky | ap | omega | phib
     size_t cap_genbank = 0;
+    double *d_qsample = nullptr;  // ft_q_sample staging
+    size_t cap_qsample = 0;
     int32_t *d_perm = nullptr;
     size_t cap_perm = 0;
     float *d_stats = nullptr;
@@ -467,6 +469,7 @@ void ft_destroy(ft_ctx c)
     release(&c->d_bin, &c->cap_bin);
     release(&c->d_sincos, &c->cap_sincos);
     release(&c->d_genbank, &c->cap_genbank);
+    release(&c->d_qsample, &c->cap_qsample);
     release(&c->d_f1, &c->cap_f1);
     release(&c->d_sky, &c->cap_sky);
     release(&c->d_sky_tile, &c->cap_sky_tile);
@@ -1417,6 +1420,49 @@ ft_status ft_last_eval_info(ft_ctx c, ft_eval_info *info)
     info->n_candidates = total;
     info->tile = c->last_tile + 1;
     info->window = c->last_grid ? r.wt : 0;
+    return FT_OK;
+}
+
+ft_status ft_q_sample(ft_ctx c, const double *arms, int64_t n, const double *sky, const double *cos_iota,
+                      const double *psi, double *q_out)
+{
+    if (!c) return FT_E_INVALID;
+    c->err.clear();
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, FT_E_DEVICE, "hipSetDevice");
+    if (!c->have_sfts) return fail(c, FT_E_STATE, "ft_set_sfts must come first");
+    if (n < 0 || (n > 0 && (!arms || !sky || !cos_iota || !psi || !q_out))) return fail(c, FT_E_INVALID, "bad arguments");
+    if (n == 0) return FT_OK;
+    if (n >= (1LL << 31)) return fail(c, FT_E_UNSUPPORTED, "at most 2^31 - 1 samples per call");
+    const int64_t N = c->n_sft;
+    std::vector<double> ah, sh, ch, ph;
+    if (fetch(ah, arms, (size_t)N * 6) != hipSuccess || fetch(sh, sky, (size_t)n * 3) != hipSuccess ||
+        fetch(ch, cos_iota, (size_t)n) != hipSuccess || fetch(ph, psi, (size_t)n) != hipSuccess)
+        return fail(c, FT_E_INVALID, "cannot read the inputs");
+    for (double a : ah)
+        if (!is_finite(a)) return fail(c, FT_E_INVALID, "arms hold a non-finite value");
+    for (int64_t i = 0; i < n; ++i) {
+        const double x = sh[3 * i], y = sh[3 * i + 1], z = sh[3 * i + 2];
+        if (!is_finite(x) || !is_finite(y) || !is_finite(z) || std::fabs(std::sqrt(x * x + y * y + z * z) - 1.0) > 1e-12)
+            return fail(c, FT_E_INVALID, "sky vectors must be finite unit vectors (sample %lld)", (long long)i);
+        if (!is_finite(ch[i]) || ch[i] < -1.0 || ch[i] > 1.0 || !is_finite(ph[i]))
+            return fail(c, FT_E_INVALID, "cos_iota must lie in [-1, 1] and psi be finite (sample %lld)", (long long)i);
+    }
+    // staging: arms | sky | cos_iota | psi | q
+    const size_t need = (size_t)N * 6 + (size_t)n * 9;
+    hipError_t e;
+    if ((e = ensure(&c->d_qsample, &c->cap_qsample, need)) != hipSuccess) return hip_fail(c, e, "alloc q samples");
+    double *d = c->d_qsample;
+    double *d_arms = d, *d_sky = d + N * 6, *d_ci = d_sky + n * 3, *d_psi = d_ci + n, *d_q = d_psi + n;
+    e = hipMemcpyAsync(d_arms, ah.data(), N * 6 * sizeof(double), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_sky, sh.data(), n * 3 * sizeof(double), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_ci, ch.data(), n * sizeof(double), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_psi, ph.data(), n * sizeof(double), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess)
+        e = launch_q_sample(d_arms, c->has_weight ? c->d_weight : nullptr, (int)N, c->t_sft, d_sky, d_ci, d_psi, n, d_q,
+                            c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(q_out, d_q, n * 4 * sizeof(double), hipMemcpyDefault, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "q samples");
     return FT_OK;
 }
 

@@ -241,6 +241,12 @@ hipError_t launch_gen_tables(const GenRun *prep, int n_prep, const int64_t *prep
 hipError_t launch_gen_binary_bank(const ft_binary_region &reg, uint64_t seed, int64_t first, int64_t n, double *f0,
                                   double *sky, double *ap, double *omega, double *phib, hipStream_t s);
 
+// Semi-analytic sensitivity: q[i] = (mu_G, sigma_G, rho_hat_1^2, rho_hat_2^2)
+// of population samples (sky [n][3], cos_iota [n], psi [n]) for the SFTs'
+// arms [n_sft][6] and weights (nullptr: all 1).
+hipError_t launch_q_sample(const double *arms, const float *weight, int n_sft, double t_sft, const double *sky,
+                           const double *cos_iota, const double *psi, int64_t n, double *q, hipStream_t s);
+
 // Selection: exact toplists per segment (segment = sub-band here).
 struct SelectBufs {
     uint32_t *hist;       // [n_seg][256]

@@ -71,6 +71,48 @@ __device__ __forceinline__ int find_run(const int64_t *prefix, int n_runs, int64
     return lo;
 }
 
+// Polarisation basis (p, q) of a source in direction n: (e_alpha, e_delta)
+// rotated by psi (right ascension 0 at a pole).
+__device__ __forceinline__ void source_frame(const double *n, double psi, double p[3], double q[3])
+{
+    const double n0 = n[0], n1 = n[1], n2 = n[2];
+    const double rho = hypot(n0, n1);
+    double ea[3], ed[3];
+    if (rho > 0.0) {
+        ea[0] = -n1 / rho;
+        ea[1] = n0 / rho;
+        ea[2] = 0.0;
+        ed[0] = -n2 * n0 / rho;
+        ed[1] = -n2 * n1 / rho;
+        ed[2] = rho;
+    } else {
+        ea[0] = 0.0;
+        ea[1] = 1.0;
+        ea[2] = 0.0;
+        ed[0] = -n2;
+        ed[1] = 0.0;
+        ed[2] = 0.0;
+    }
+    const double cp = cos(psi), sp = sin(psi);
+    for (int i = 0; i < 3; ++i) {
+        p[i] = cp * ea[i] + sp * ed[i];
+        q[i] = -sp * ea[i] + cp * ed[i];
+    }
+}
+
+// Antenna patterns F+ = D:e+, Fx = D:ex with D = (u u^T - w w^T)/2 from the arm
+// unit vectors arm = (u, w) and e+ = p p^T - q q^T, ex = p q^T + q p^T.
+__device__ __forceinline__ void antenna(const double *arm, const double p[3], const double q[3], double &fp,
+                                        double &fx)
+{
+    const double up = arm[0] * p[0] + arm[1] * p[1] + arm[2] * p[2];
+    const double uq = arm[0] * q[0] + arm[1] * q[1] + arm[2] * q[2];
+    const double wp = arm[3] * p[0] + arm[4] * p[1] + arm[5] * p[2];
+    const double wq = arm[3] * q[0] + arm[4] * q[1] + arm[5] * q[2];
+    fp = 0.5 * ((up * up - uq * uq) - (wp * wp - wq * wq));
+    fx = up * uq - wp * wq;
+}
+
 // Per SFT of a run: injection bin and the three bin amplitudes.
 // Column range of SFT k that the run's grid bank can reach: the canonical bin
 // is monotone in f0, in c = f1 dt and in the Doppler factor g, so the range
@@ -127,38 +169,10 @@ __device__ void gen_prep_one(const GenRun &g, int k)
     const double x = f * g.t_sft;
     const double B = floor(x + 0.5);
     const double delta = x - B;
-    // polarisation frame of the source
-    const double n0 = g.sky[0], n1 = g.sky[1], n2 = g.sky[2];
-    const double rho = hypot(n0, n1);
-    double ea[3], ed[3];
-    if (rho > 0.0) {
-        ea[0] = -n1 / rho;
-        ea[1] = n0 / rho;
-        ea[2] = 0.0;
-        ed[0] = -n2 * n0 / rho;
-        ed[1] = -n2 * n1 / rho;
-        ed[2] = rho;
-    } else {
-        ea[0] = 0.0;
-        ea[1] = 1.0;
-        ea[2] = 0.0;
-        ed[0] = -n2;
-        ed[1] = 0.0;
-        ed[2] = 0.0;
-    }
-    const double cp = cos(g.psi), sp = sin(g.psi);
     double p[3], q[3];
-    for (int i = 0; i < 3; ++i) {
-        p[i] = cp * ea[i] + sp * ed[i];
-        q[i] = -sp * ea[i] + cp * ed[i];
-    }
-    const double *arm = g.arms + 6 * (int64_t)k;
-    const double up = arm[0] * p[0] + arm[1] * p[1] + arm[2] * p[2];
-    const double uq = arm[0] * q[0] + arm[1] * q[1] + arm[2] * q[2];
-    const double wp = arm[3] * p[0] + arm[4] * p[1] + arm[5] * p[2];
-    const double wq = arm[3] * q[0] + arm[4] * q[1] + arm[5] * q[2];
-    const double fp = 0.5 * ((up * up - uq * uq) - (wp * wp - wq * wq));
-    const double fx = up * uq - wp * wq;
+    source_frame(g.sky, g.psi, p, q);
+    double fp, fx;
+    antenna(g.arms + 6 * (int64_t)k, p, q, fp, fx);
     const double ap = 0.5 * (1.0 + g.cos_iota * g.cos_iota);
     const double ax = g.cos_iota;
     const double r2 = g.t_sft * g.amp * g.amp * (fp * fp * ap * ap + fx * fx * ax * ax);
@@ -282,7 +296,54 @@ __global__ __launch_bounds__(256) void gen_binary_bank_kernel(ft_binary_region r
     }
 }
 
+// Signal-response quantities of the semi-analytic sensitivity estimate
+// (Sec. V.A: q = (mu_G, sigma_G, rho_hat_1^2, rho_hat_2^2)) for population
+// samples (sky n_i, cos iota_i, psi_i), one lane per sample, sums sequential
+// in SFT order with the per-SFT weights u_k (1 when absent):
+//   mu_G = 2 sum u, sigma_G = 2 sqrt(sum u^2), rho1 = sum u rho_k, rho2 = sum u^2 rho_k,
+//   rho_k = T_sft (F+^2 A+^2 + Fx^2 Ax^2), A+ = (1 + cos^2 iota)/2, Ax = cos iota
+// (rho_hat^2 of Sec. II.B.2 with the two polarisations in quadrature; the
+// power lost to the bin offset is applied by the caller).
+__global__ __launch_bounds__(256) void q_sample_kernel(const double *arms, const float *weight, int n_sft,
+                                                       double t_sft, const double *sky, const double *cos_iota,
+                                                       const double *psi, int64_t n, double *q)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        double p[3], qq[3];
+        source_frame(sky + 3 * i, psi[i], p, qq);
+        const double ci = cos_iota[i];
+        const double ap = 0.5 * (1.0 + ci * ci);
+        const double ax = ci;
+        double s1 = 0.0, s2 = 0.0, r1 = 0.0, r2 = 0.0;
+        for (int k = 0; k < n_sft; ++k) {
+            double fp, fx;
+            antenna(arms + 6 * (int64_t)k, p, qq, fp, fx);
+            const double rk = t_sft * (fp * fp * ap * ap + fx * fx * ax * ax);
+            const double u = weight ? (double)weight[k] : 1.0;
+            s1 = s1 + u;
+            s2 = s2 + u * u;
+            r1 = r1 + u * rk;
+            r2 = r2 + (u * u) * rk;
+        }
+        q[4 * i] = 2.0 * s1;
+        q[4 * i + 1] = 2.0 * sqrt(s2);
+        q[4 * i + 2] = r1;
+        q[4 * i + 3] = r2;
+    }
+}
+
 }  // namespace
+
+hipError_t launch_q_sample(const double *arms, const float *weight, int n_sft, double t_sft, const double *sky,
+                           const double *cos_iota, const double *psi, int64_t n, double *q, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(q_sample_kernel, dim3((unsigned)blocks), dim3(256), 0, s, arms, weight, n_sft, t_sft, sky,
+                       cos_iota, psi, n, q);
+    return hipGetLastError();
+}
 
 hipError_t launch_gen_binary_bank(const ft_binary_region &reg, uint64_t seed, int64_t first, int64_t n, double *f0,
                                   double *sky, double *ap, double *omega, double *phib, hipStream_t s)

@@ -108,7 +108,7 @@ _lib = None
 EXPORTS = ("ft_create", "ft_destroy", "ft_last_error", "ft_status_string", "ft_set_sfts",
            "ft_set_velocities", "ft_eval_templates", "ft_toplist", "ft_sync",
            "ft_last_eval_info", "ft_bins", "ft_count_index_mismatches", "ft_lib_sincos",
-           "ft_gen_binary_bank", "ft_eval_binary_random", "ft_tile_count",
+           "ft_gen_binary_bank", "ft_eval_binary_random", "ft_q_sample", "ft_tile_count",
            "ft_tile_name", "ft_gen_sfts", "ft_eval_batch", "ft_batch_toplist", "ft_batch_labels",
            "ft_batch_replay", "ft_batch_time", "ft_mlp_create", "ft_mlp_destroy",
            "ft_mlp_get_params", "ft_mlp_predict", "ft_mlp_loss_grad", "ft_mlp_train",
@@ -138,6 +138,7 @@ def load(path: str = LIB_PATH):
         "ft_last_eval_info": (C.c_int, [P, C.POINTER(ft_eval_info)]),
         "ft_bins": (C.c_int, [P, C.POINTER(ft_bank), f64, i32, P]),
         "ft_lib_sincos": (C.c_int, [P, P, i64, P, P]),
+        "ft_q_sample": (C.c_int, [P, P, i64, P, P, P, P]),
         "ft_gen_binary_bank": (C.c_int, [P, C.POINTER(ft_binary_region), C.c_uint64, i64, i64, P, P, P,
                                          P, P]),
         "ft_eval_binary_random": (C.c_int, [P, C.POINTER(ft_binary_region), C.c_uint64, i64, f64,
@@ -329,6 +330,19 @@ def ft_eval_binary_random(ctx, region, seed, n, t_ref, k, sub_edges, sum_mode=FT
     s = _Arr(stats, np.float32)
     _check(ctx, load().ft_eval_binary_random(ctx, C.byref(reg), int(seed), int(n), float(t_ref),
                                              C.byref(o), s.ptr))
+
+
+def ft_q_sample(ctx, arms, sky, cos_iota, psi):
+    """q [n, 4] = (mu_G, sigma_G, rho1, rho2) of population samples on the context's SFTs."""
+    a = np.ascontiguousarray(arms, np.float64)
+    sk = np.ascontiguousarray(sky, np.float64)
+    ci = np.ascontiguousarray(cos_iota, np.float64)
+    ps = np.ascontiguousarray(psi, np.float64)
+    q = np.empty((ci.size, 4))
+    _check(ctx, load().ft_q_sample(ctx, a.ctypes.data_as(C.c_void_p), ci.size, sk.ctypes.data_as(C.c_void_p),
+                                   ci.ctypes.data_as(C.c_void_p), ps.ctypes.data_as(C.c_void_p),
+                                   q.ctypes.data_as(C.c_void_p)))
+    return q
 
 
 def ft_lib_sincos(ctx, x):
@@ -639,6 +653,9 @@ class Context:
 
     def lib_sincos(self, x):
         return ft_lib_sincos(self.ctx, x)
+
+    def q_sample(self, *a, **kw):
+        return ft_q_sample(self.ctx, *a, **kw)
 
     def gen_binary_bank(self, *a, **kw):
         return ft_gen_binary_bank(self.ctx, *a, **kw)

@@ -63,6 +63,7 @@ def test_null_arguments_are_rejected_without_a_device():
     assert lib.ft_tune_clear(None) == ft.FT_E_INVALID
     assert lib.ft_tune_report(None, None, 0, None, None) == ft.FT_E_INVALID
     assert lib.ft_lib_sincos(None, None, 0, None, None) == ft.FT_E_INVALID
+    assert lib.ft_q_sample(None, None, 0, None, None, None, None) == ft.FT_E_INVALID
     assert lib.ft_gen_binary_bank(None, None, 0, 0, 0, None, None, None, None, None) == ft.FT_E_INVALID
     assert lib.ft_eval_binary_random(None, None, 0, 0, 0.0, None, None) == ft.FT_E_INVALID
     assert C.sizeof(ft.ft_binary_region) == 96
