@@ -56,7 +56,8 @@ def p_det(q, m_samples, depths, tau, seed=0, eta=BIN_OFFSET_POWER):
 
 def injection_p_det(ctx: ft.Context, w, depths, n_inj, o, tau, seed=0):
     """Detected fraction of plain injections at each depth: the loudest template
-    of a random bank at oversampling o around each signal, rule z > tau."""
+    of a random bank at oversampling o around each signal, rule z > tau.  The
+    trials run on unit weights, so z = (s - 2N) / (2 sqrt(N))."""
     mu, sig = 2.0 * w.n_sft, 2.0 * np.sqrt(w.n_sft)
     out = []
     for i, d in enumerate(depths):
