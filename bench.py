@@ -296,6 +296,55 @@ def bench_sensitivity(ft, synth, log, o=3.44, tau=8.0, depths=(15.0, 22.0, 27.0,
     return out
 
 
+def bench_weighted(ft, c, w, f0, f1, sky, edges, arms, log, reps=2):
+    """The all-sky band (table already loaded in c) with the other statistics and
+    weights of Sec. II.B: the power with the all-sky weights (a^2 + b^2)/S_n, the
+    weighted number count with per-SFT and with all-sky weights; kernel rates
+    (HIP events) and the whole call; then the persistence-checked candidate of
+    Sec. VI.A (loudest power with number-count z >= 3) of each injected sub-band."""
+    import numpy as np
+    import torch
+    from paper_2411_18370_amd import persistence
+    c.set_arms(arms)
+    out = {}
+    n_sub = len(w.sub_edges) - 1
+    for name, stat, wts in (("power_sky_weights", ft.FT_STAT_POWER, ft.FT_WEIGHTS_SKY),
+                            ("number_count", ft.FT_STAT_NUMBER_COUNT, ft.FT_WEIGHTS_SFT),
+                            ("number_count_sky_weights", ft.FT_STAT_NUMBER_COUNT, ft.FT_WEIGHTS_SKY)):
+        ms, wall = [], []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            c.eval_templates(f0, f1, sky, w.t_ref, w.k, edges, statistic=stat, weights=wts)
+            tops = [c.toplist(j, w.k) for j in range(n_sub)]
+            wall.append(time.perf_counter() - t0)
+            ms.append(c.info().eval_ms)
+        info = c.info()
+        inj_z = []
+        for inj in w.injections:
+            j = int(np.searchsorted(w.sub_edges, inj["f0"], side="right")) - 1
+            inj_z.append(tops[j][0].z)
+        out[name] = {"kernel_evals_per_s": w.evals / (min(ms) * 1e-3), "kernel_ms": min(ms),
+                     "call_evals_per_s": w.evals / min(wall), "tile": ft.ft_tile_name(info.tile),
+                     "top_z_injected_subbands": inj_z}
+        log("weighted %s: kernel %.3g evals/s (%.0f ms, %s), call %.3g evals/s, top z at injections %s"
+            % (name, out[name]["kernel_evals_per_s"], min(ms), out[name]["tile"],
+               out[name]["call_evals_per_s"], np.round(inj_z, 1).tolist()))
+    # persistence-checked candidates (power toplists with their exact number counts)
+    c.eval_templates(f0, f1, sky, w.t_ref, w.k, edges)
+    t0 = time.perf_counter()
+    cands = []
+    for inj in w.injections:
+        j = int(np.searchsorted(w.sub_edges, inj["f0"], side="right")) - 1
+        got = persistence.loudest_persistent(c, j, w.k, 3.0)
+        cands.append(None if got is None else {"sub_band": j, "z": got[0].z, "nc": got[1], "z_nc": got[2],
+                                               "df0_bins": (got[0].f0 - inj["f0"]) * w.t_sft})
+    out["persistent_candidates"] = cands
+    out["persistence_check_s"] = time.perf_counter() - t0
+    log("persistent candidates at the injections: %s" % cands)
+    return out
+
+
 def bench_surrogate(ft, synth, tau, n_train, n_test, log):
     """Labels from GPU injection campaigns, GPU training, calibration on held-out
     injections, and the cost of a surrogate query against a plain label."""
@@ -349,7 +398,7 @@ def main():
     ap.add_argument("--surrogate-test", type=int, default=100_000)
     ap.add_argument("--skip-extras", action="store_true",
                     help="plain workload only (no batched, precision or surrogate sections)")
-    ap.add_argument("--sections", default="batched,precision,surrogate,binary,mismatch,sensitivity",
+    ap.add_argument("--sections", default="weighted,batched,precision,surrogate,binary,mismatch,sensitivity",
                     help="comma-separated extra sections to run")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -482,8 +531,10 @@ def main():
                 "pattern alone (ft_probe_lds_gather) at the same occupancy"}
     log("LDS gather: kernel %.3g evals/s, probe %.3g evals/s (%.0f%%)"
         % (achieved_evals, probe, 100 * achieved_evals / probe))
-    c.close()
     sections = set() if args.skip_extras else set(args.sections.split(","))
+    if "weighted" in sections:
+        line["weighted"] = bench_weighted(ft, c, w, f0, f1, sky, edges, arms, log)
+    c.close()
     if "batched" in sections:
         line["batched"] = bench_batched(ft, synth, args.batched_runs, log)
     if "precision" in sections:

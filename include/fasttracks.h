@@ -99,6 +99,15 @@ ft_status ft_set_sfts(ft_ctx ctx, int32_t n_det, const int32_t *n_sft, const dou
  */
 ft_status ft_set_velocities(ft_ctx ctx, const double *v_over_c);
 
+/*
+ * ft_set_arms -- unit vectors of the two detector arms at each SFT mid-time,
+ * arms[N][6] = (u, w), equatorial Cartesian, same order as t_mid (host or
+ * device), for FT_WEIGHTS_SKY.  Errors: FT_E_STATE before ft_set_sfts;
+ * FT_E_INVALID if a vector is non-finite or its norm is off 1 by more than
+ * 1e-6.  Invalidated when the SFT count changes.
+ */
+ft_status ft_set_arms(ft_ctx ctx, const double *arms);
+
 enum { FT_BANK_GRID = 0, FT_BANK_LIST = 1, FT_BANK_BINARY = 2 };
 
 /*
@@ -171,6 +180,27 @@ enum {
 
 enum { FT_SUM_BLOCKED = 0, FT_SUM_PLAIN_FP32 = 1 };
 
+/* Detection statistic (Sec. II.B).  POWER: s = sum_k w_k P_k[B_k] (Eq.
+ * short_coh_general with the normalised power of Eq. s_tf).  NUMBER_COUNT: the
+ * weighted number count nc = sum_k w_k 1[P_k[B_k] > 3.2] (Eq. number_count; P
+ * is compared as a real number, i.e. P >= 3.2f for FP32 P). */
+enum { FT_STAT_POWER = 0, FT_STAT_NUMBER_COUNT = 1 };
+
+/* SFT weights.  SFT: w_k = u_k, the per-SFT weights of ft_set_sfts (1 when
+ * none).  SKY: the all-sky weights of Sec. II.B, w_k(n) = c_k(n) / sum_k' c_k'(n)
+ * with c_k(n) = u_k (a_k^2(n) + b_k^2(n)) (u_k in the role of 1/S_n), a, b the
+ * detector response functions at the SFT mid-time; a^2 + b^2 = F+^2 + Fx^2 for
+ * any polarisation angle, F+ = D:e+, Fx = D:ex, D = (u u^T - w w^T)/2 from the
+ * arms of ft_set_arms.  GRID banks only. */
+enum { FT_WEIGHTS_SFT = 0, FT_WEIGHTS_SKY = 1 };
+
+/* Noise-only moments of the statistics (z = (s - mu)/sigma), with
+ * W1 = sum w_k and W2 = sum w_k^2 (sums in FP64):
+ *   POWER         mu = 2 W1,     sigma = 2 sqrt(W2)        (Sec. II.B.1)
+ *   NUMBER_COUNT  mu = p W1,     sigma = sqrt(p (1-p) W2), p = exp(-1.6), the
+ *                 probability that P > 3.2 when P is chi^2 with 2 degrees of
+ *                 freedom. */
+
 /*
  * Evaluation options.
  *   precision  FT_INDEX_* (bins of the stored statistic; toplists are always
@@ -186,7 +216,14 @@ enum { FT_SUM_BLOCKED = 0, FT_SUM_PLAIN_FP32 = 1 };
  *              shape class in this context, else the cost model);
  *              FT_TILE_TUNE = time the eligible tiles first if the class is
  *              not cached (see ft_tune_report); otherwise a tile id in
- *              1..ft_tile_count() (see ft_tile_name); ignored for LIST banks
+ *              1..ft_tile_count() (see ft_tile_name); ignored for LIST banks;
+ *              with FT_WEIGHTS_SKY the library chooses among the tiles that
+ *              have a sky-weighted form (a tile id without one is an error)
+ *   statistic  FT_STAT_POWER (default) or FT_STAT_NUMBER_COUNT; stats,
+ *              toplists (s32, s64) and z are then of that statistic
+ *   weights    FT_WEIGHTS_SFT (default) or FT_WEIGHTS_SKY (GRID banks, after
+ *              ft_set_arms; the statistic is normalised by sum w = 1 per sky
+ *              point and z uses the sky point's moments)
  */
 typedef struct {
     int32_t precision;
@@ -195,7 +232,9 @@ typedef struct {
     int32_t sum_mode;
     const double *sub_edges;
     int32_t tile;
-    int32_t reserved;
+    int32_t statistic;  /* FT_STAT_*                                              */
+    int32_t weights;    /* FT_WEIGHTS_*                                           */
+    int32_t reserved;   /* 0                                                      */
 } ft_eval_opts;
 
 /*
@@ -276,6 +315,20 @@ typedef struct {
  * errors (FT_E_RANGE).
  */
 ft_status ft_toplist(ft_ctx ctx, int32_t sub, ft_candidate *out, int32_t *n_out);
+
+/*
+ * ft_toplist_number_count -- the exact weighted number count (Eq.
+ * number_count, weights as in the evaluation: FP64 sum in SFT order at the
+ * canonical bins) of each entry of sub-band `sub`'s toplist of the last
+ * evaluation, in toplist order, into nc_out[0..*n_out-1] (capacity k), and
+ * its critical ratio (nc - p W1)/sqrt(p (1-p) W2), p = exp(-1.6), W1, W2 the
+ * sums of the entry's weights and squared weights, into z_out (may be NULL).  With
+ * the POWER statistic this is the persistence check of Sec. VI.A: the loudest
+ * template whose number count reaches a minimum is the first entry that
+ * reaches it (when none of the k does, it lies deeper than the toplist).
+ * Synchronises the context's stream.  Errors as ft_toplist.
+ */
+ft_status ft_toplist_number_count(ft_ctx ctx, int32_t sub, double *nc_out, double *z_out, int32_t *n_out);
 
 /* Wait for the context's stream and report deferred GPU errors. */
 ft_status ft_sync(ft_ctx ctx);

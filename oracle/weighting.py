@@ -1,0 +1,116 @@
+"""FP64 reference of the weighted number count and of the all-sky weights
+(Sec. II.B) -- TEST INFRASTRUCTURE ONLY.
+
+Number count (Eq. number_count): nc[t; f] = 1 when the normalised power exceeds
+3.2, else 0; the weighted number count of a template is the sum over SFTs of
+w_k nc_k at the template's bins, the same form as Eq. short_coh_general.  In
+Gaussian noise P is chi^2 with 2 degrees of freedom, so nc_k is Bernoulli with
+p = P(P > 3.2) = exp(-3.2 / 2): noise mean p sum w and variance p (1 - p) sum w^2.
+
+All-sky weights: w_k(n) proportional to (a_k^2(n) + b_k^2(n)) / S_n,k and
+normalised to sum 1 over the SFTs, a and b the detector response functions
+(F+ = a cos 2psi + b sin 2psi, Fx = b cos 2psi - a sin 2psi, so a^2 + b^2 is
+F+^2 + Fx^2 at any psi, here evaluated at psi = 0 with the injector's antenna
+patterns); 1/S_n,k is the caller's per-SFT weight u_k.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from . import core
+from .inject import antenna_patterns
+
+NC_THRESHOLD = 3.2
+
+
+def number_count_table(power):
+    """1[P > 3.2] of every table cell (float32 0/1), P compared as a real number."""
+    return (np.asarray(power, np.float32).astype(np.float64) > NC_THRESHOLD).astype(np.float32)
+
+
+def nc_probability():
+    """P(P > 3.2) for P ~ chi^2_2: the survival function exp(-x/2) at x = 3.2."""
+    return math.exp(-NC_THRESHOLD / 2.0)
+
+
+def nc_moments(weights):
+    """Noise-only (mean, sigma) of the weighted number count for weights w_k (FP64)."""
+    w = np.asarray(weights, np.float64)
+    p = nc_probability()
+    w1 = 0.0
+    w2 = 0.0
+    for x in w:
+        w1 = w1 + x
+        w2 = w2 + x * x
+    return p * w1, math.sqrt(p * (1.0 - p) * w2)
+
+
+def power_moments(weights):
+    """Noise-only (mean, sigma) of S = sum w P: 2 sum w and 2 sqrt(sum w^2) (Sec. II.B.1)."""
+    w = np.asarray(weights, np.float64)
+    w1 = 0.0
+    w2 = 0.0
+    for x in w:
+        w1 = w1 + x
+        w2 = w2 + x * x
+    return 2.0 * w1, 2.0 * math.sqrt(w2)
+
+
+def response_ab(arms, n):
+    """a^2 + b^2 [N] of every SFT's detector for a source in direction n."""
+    fp, fx = antenna_patterns(np.asarray(arms, np.float64), np.asarray(n, np.float64), 0.0)
+    return fp * fp + fx * fx
+
+
+def sky_weights(arms, u, sky):
+    """[n_sky, N] all-sky weights w_k(n) = u_k (a^2 + b^2)_k / sum_k' u_k' (a^2 + b^2)_k'
+    (u: per-SFT weights, float32 or None for 1)."""
+    arms = np.asarray(arms, np.float64)
+    sky = np.atleast_2d(np.asarray(sky, np.float64))
+    n_sft = arms.shape[0]
+    uu = np.ones(n_sft) if u is None else np.asarray(u, np.float32).astype(np.float64)
+    out = np.empty((sky.shape[0], n_sft))
+    for s in range(sky.shape[0]):
+        c = uu * response_ab(arms, sky[s])
+        total = 0.0
+        for x in c:
+            total = total + x
+        out[s] = c / total
+    return out
+
+
+def weighted_sums(t_mid, t_ref, t_sft, first_bin, table, weights, v, f0, f1, sky):
+    """S[t] = sum_k weights[t, k] table[k, B_tk] for templates t of a list bank
+    (canonical bins of the oracle), sums sequential in SFT order in FP64."""
+    bins = core.bins_list(t_mid, t_ref, t_sft, v, f0, f1, sky)
+    tab = np.asarray(table, np.float32).astype(np.float64)
+    cols = bins - int(first_bin)
+    assert cols.min() >= 0 and cols.max() < tab.shape[1], "track leaves the table"
+    w = np.asarray(weights, np.float64)
+    acc = np.zeros(bins.shape[0])
+    rows = np.arange(bins.shape[1])
+    for k in rows:
+        acc = acc + w[:, k] * tab[k, cols[:, k]]
+    return acc
+
+
+def grid_as_list(f0, f1, sky):
+    """The templates of a grid bank in template order t = (s n_f1 + j) n_f0 + i:
+    (f0[t], f1[t], sky[t], sky index[t])."""
+    f0 = np.asarray(f0, np.float64)
+    f1 = np.asarray(f1, np.float64)
+    sky = np.asarray(sky, np.float64)
+    s_idx, j_idx, i_idx = np.meshgrid(np.arange(sky.shape[0]), np.arange(f1.size), np.arange(f0.size),
+                                      indexing="ij")
+    s_idx, j_idx, i_idx = s_idx.ravel(), j_idx.ravel(), i_idx.ravel()
+    return f0[i_idx], f1[j_idx], sky[s_idx], s_idx
+
+
+def eval_grid_sky_weighted(t_mid, t_ref, t_sft, first_bin, table, arms, u, v, f0, f1, sky):
+    """Statistic of every template of a grid bank with the all-sky weights:
+    (S [n_templates], W [n_sky, N])."""
+    W = sky_weights(arms, u, sky)
+    lf0, lf1, lsky, s_idx = grid_as_list(f0, f1, sky)
+    return weighted_sums(t_mid, t_ref, t_sft, first_bin, table, W[s_idx], v, lf0, lf1, lsky), W

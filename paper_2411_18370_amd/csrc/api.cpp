@@ -40,6 +40,16 @@ struct ft_ctx_s {
     double vmax = 0.0;
     double *d_arms = nullptr;
     size_t cap_arms = 0;
+    bool have_arms = false;  // d_arms holds the arms of the current SFT set
+    float *d_ind = nullptr, *d_ind_w = nullptr;  // number-count tables 1[P > 3.2], u_k 1[P > 3.2]
+    size_t cap_ind = 0, cap_ind_w = 0;
+    bool ind_valid = false;
+    double *d_mu_sigma_nc = nullptr;  // noise moments of the number count
+    size_t cap_mu_sigma_nc = 0;
+    double *d_sky_norm = nullptr, *d_sky_ms = nullptr;  // sky-dependent weights of the last evaluation
+    size_t cap_sky_norm = 0, cap_sky_ms = 0;
+    double *d_top_nc = nullptr;  // ft_toplist_number_count staging
+    size_t cap_top_nc = 0;
     int32_t *d_inj_bin = nullptr;
     size_t cap_inj_bin = 0;
     double *d_inj_amp = nullptr;
@@ -140,6 +150,7 @@ struct ft_ctx_s {
     int64_t last_cap = 0;
     double last_rel_err = 0.0;
     int last_tile = -1;
+    int last_stat = FT_STAT_POWER;
     hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
 
     float *d_probe = nullptr;  // output of the LDS gather probe
@@ -455,6 +466,12 @@ void ft_destroy(ft_ctx c)
     release(&c->d_weight, &c->cap_weight);
     release(&c->d_power_w, &c->cap_power_w);
     release(&c->d_arms, &c->cap_arms);
+    release(&c->d_ind, &c->cap_ind);
+    release(&c->d_ind_w, &c->cap_ind_w);
+    release(&c->d_mu_sigma_nc, &c->cap_mu_sigma_nc);
+    release(&c->d_sky_norm, &c->cap_sky_norm);
+    release(&c->d_sky_ms, &c->cap_sky_ms);
+    release(&c->d_top_nc, &c->cap_top_nc);
     release(&c->d_inj_bin, &c->cap_inj_bin);
     release(&c->d_inj_amp, &c->cap_inj_amp);
     release(&c->d_genruns, &c->cap_genruns);
@@ -579,7 +596,7 @@ ft_status ft_set_sfts(ft_ctx c, int32_t n_det, const int32_t *n_sft, const doubl
     if ((e = launch_check_table(c->d_power, weight ? c->d_weight : nullptr, total, n_bins, c->d_err,
                                 c->stream)) != hipSuccess)
         return hip_fail(c, e, "check table");
-    if ((e = launch_noise_moments(weight ? c->d_weight : nullptr, (int)total, c->d_mu_sigma,
+    if ((e = launch_noise_moments(weight ? c->d_weight : nullptr, (int)total, FT_STAT_POWER, c->d_mu_sigma,
                                   c->stream)) != hipSuccess)
         return hip_fail(c, e, "noise moments");
     // The grid kernel stages w_k * P[k][b] (FP32 product) directly into LDS.
@@ -592,7 +609,8 @@ ft_status ft_set_sfts(ft_ctx c, int32_t n_det, const int32_t *n_sft, const doubl
         launch_fill_u32(c->d_err, 0u, 1, c->stream);
         return st;
     }
-    if (c->have_sfts && c->n_sft != (int32_t)total) c->have_vel = false;
+    if (c->have_sfts && c->n_sft != (int32_t)total) c->have_vel = c->have_arms = false;
+    c->ind_valid = false;
     c->n_sft = (int32_t)total;
     c->n_bins = n_bins;
     c->first_bin = first_bin;
@@ -607,6 +625,49 @@ ft_status ft_set_sfts(ft_ctx c, int32_t n_det, const int32_t *n_sft, const doubl
 static ft_status set_velocities_impl(ft_ctx c, const double *v, bool sync);
 
 ft_status ft_set_velocities(ft_ctx c, const double *v) { return set_velocities_impl(c, v, true); }
+
+ft_status ft_set_arms(ft_ctx c, const double *arms)
+{
+    if (!c) return FT_E_INVALID;
+    c->err.clear();
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, FT_E_DEVICE, "hipSetDevice");
+    if (!c->have_sfts) return fail(c, FT_E_STATE, "ft_set_sfts must come first");
+    if (!arms) return fail(c, FT_E_INVALID, "arms is null");
+    std::vector<double> ah;
+    if (fetch(ah, arms, (size_t)c->n_sft * 6) != hipSuccess) return fail(c, FT_E_INVALID, "cannot read arms");
+    for (size_t q = 0; q < ah.size(); q += 3) {
+        const double n2 = ah[q] * ah[q] + ah[q + 1] * ah[q + 1] + ah[q + 2] * ah[q + 2];
+        if (!is_finite(n2) || std::fabs(std::sqrt(n2) - 1.0) > 1e-6)
+            return fail(c, FT_E_INVALID, "arm vector %zu (SFT %zu) is not a unit vector", q / 3 % 2, q / 6);
+    }
+    hipError_t e = ensure(&c->d_arms, &c->cap_arms, ah.size());
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(c->d_arms, ah.data(), ah.size() * sizeof(double), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "upload arms");
+    c->have_arms = true;
+    return FT_OK;
+}
+
+// Number-count tables of the current SFT set (built on first use).
+static ft_status ensure_nc(ft_ctx c)
+{
+    if (c->ind_valid) return FT_OK;
+    const size_t n_cells = (size_t)c->n_sft * (size_t)c->n_bins;
+    hipError_t e;
+    if ((e = ensure(&c->d_ind, &c->cap_ind, n_cells)) != hipSuccess ||
+        (c->has_weight && (e = ensure(&c->d_ind_w, &c->cap_ind_w, n_cells)) != hipSuccess) ||
+        (e = ensure(&c->d_mu_sigma_nc, &c->cap_mu_sigma_nc, 2)) != hipSuccess)
+        return hip_fail(c, e, "alloc number-count tables");
+    e = launch_nc_table(c->d_power, c->has_weight ? c->d_weight : nullptr, c->d_ind, c->d_ind_w, c->n_sft, c->n_bins,
+                        c->stream);
+    if (e == hipSuccess)
+        e = launch_noise_moments(c->has_weight ? c->d_weight : nullptr, c->n_sft, FT_STAT_NUMBER_COUNT,
+                                 c->d_mu_sigma_nc, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "number-count tables");
+    c->ind_valid = true;
+    return FT_OK;
+}
 
 static ft_status set_velocities_impl(ft_ctx c, const double *v, bool sync)
 {
@@ -721,6 +782,8 @@ ft_status ft_gen_sfts(ft_ctx c, int32_t n_det, const int32_t *n_sft, const doubl
     c->t_mid_h.swap(tm);
     c->have_eval = false;
     c->have_vel = false;
+    c->have_arms = true;
+    c->ind_valid = false;
     ft_status st = set_velocities_impl(c, v_over_c, false);
     if (st != FT_OK) {
         c->have_sfts = false;
@@ -777,7 +840,7 @@ ft_status ft_gen_sfts(ft_ctx c, int32_t n_det, const int32_t *n_sft, const doubl
     if (e == hipSuccess)
         e = launch_gen_tables(c->d_genruns, n_inj, c->d_prefix, (int64_t)n_inj * total, c->d_genruns + n_inj, 1,
                               c->d_prefix + (n_inj + 1), total, c->stream);
-    if (e == hipSuccess) e = launch_noise_moments(nullptr, (int)total, c->d_mu_sigma, c->stream);
+    if (e == hipSuccess) e = launch_noise_moments(nullptr, (int)total, FT_STAT_POWER, c->d_mu_sigma, c->stream);
     if (e == hipSuccess && power_out)
         e = hipMemcpyAsync(power_out, c->d_power, n_cells * sizeof(float), hipMemcpyDefault, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
@@ -1039,7 +1102,7 @@ static ft_status ensure_select(ft_ctx c, int n_seg, int k, int64_t n_seg_map, in
     return FT_OK;
 }
 
-static SelectBufs select_bufs(ft_ctx c, int64_t cap)
+static SelectBufs select_bufs(ft_ctx c, int64_t cap, int stat)
 {
     SelectBufs b;
     b.hist = c->d_hist;
@@ -1052,7 +1115,7 @@ static SelectBufs select_bufs(ft_ctx c, int64_t cap)
     b.seg_of_f0 = c->d_seg;
     b.out = c->d_out;
     b.n_out = c->d_nout;
-    b.mu_sigma = c->d_mu_sigma;
+    b.mu_sigma = stat == FT_STAT_NUMBER_COUNT ? c->d_mu_sigma_nc : c->d_mu_sigma;
     b.cap = cap;
     return b;
 }
@@ -1142,6 +1205,10 @@ static ft_status check_eval_opts(ft_ctx c, const ft_eval_opts *opts, std::vector
     if (opts->sum_mode != FT_SUM_BLOCKED && opts->sum_mode != FT_SUM_PLAIN_FP32)
         return fail(c, FT_E_INVALID, "unknown sum_mode");
     if (opts->tile < FT_TILE_TUNE || opts->tile > tile_count()) return fail(c, FT_E_INVALID, "unknown tile %d", opts->tile);
+    if (opts->statistic != FT_STAT_POWER && opts->statistic != FT_STAT_NUMBER_COUNT)
+        return fail(c, FT_E_INVALID, "unknown statistic %d", opts->statistic);
+    if (opts->weights != FT_WEIGHTS_SFT && opts->weights != FT_WEIGHTS_SKY)
+        return fail(c, FT_E_INVALID, "unknown weights %d", opts->weights);
     if (fetch(edges, opts->sub_edges, (size_t)opts->n_sub + 1) != hipSuccess)
         return fail(c, FT_E_INVALID, "cannot read sub_edges");
     for (size_t j = 0; j < edges.size(); ++j) {
@@ -1153,6 +1220,35 @@ static ft_status check_eval_opts(ft_ctx c, const ft_eval_opts *opts, std::vector
 
 static ft_status launch_eval_select(ft_ctx c, EvalRun &run, bool grid, int tile, int64_t n_t, int64_t n_seg_map,
                                     const ft_eval_opts *opts, const std::vector<double> &edges, float *stats);
+
+// The statistic's tables (number count: the indicator tables) and, for
+// sky-dependent weights, the per-sky buffers the evaluation fills.
+static ft_status apply_stat_weights(ft_ctx c, const ft_eval_opts *opts, bool grid, int64_t n_sky, EvalRun &run)
+{
+    if (opts->statistic == FT_STAT_NUMBER_COUNT) {
+        ft_status st = ensure_nc(c);
+        if (st != FT_OK) return st;
+        run.power = c->d_ind;
+        run.power_w = c->has_weight ? c->d_ind_w : c->d_ind;
+    }
+    if (opts->weights == FT_WEIGHTS_SKY) {
+        if (!grid) return fail(c, FT_E_UNSUPPORTED, "sky-dependent weights are available for GRID banks");
+        if (!c->have_arms) return fail(c, FT_E_STATE, "sky-dependent weights need ft_set_arms");
+        hipError_t e;
+        if ((e = ensure(&c->d_sky_norm, &c->cap_sky_norm, (size_t)n_sky)) != hipSuccess ||
+            (e = ensure(&c->d_sky_ms, &c->cap_sky_ms, (size_t)n_sky * 2)) != hipSuccess)
+            return hip_fail(c, e, "alloc sky weights");
+        run.arms = c->d_arms;
+        run.sky_norm = c->d_sky_norm;
+        run.sky_ms = c->d_sky_ms;
+    }
+    return FT_OK;
+}
+
+// Tiles with a sky-weighted form: the run tile for uniform f0 grids and the
+// single-f0 tile otherwise.
+constexpr int kSkyTileRun = 17;  // L5_J4_W4_K8_O4
+constexpr int kSkyTileOne = 1;   // L1_J4_W4_K16
 
 ft_status ft_eval_templates(ft_ctx c, const ft_bank *bank, double t_ref, const ft_eval_opts *opts,
                             float *stats)
@@ -1168,9 +1264,11 @@ ft_status ft_eval_templates(ft_ctx c, const ft_bank *bank, double t_ref, const f
     int64_t n_t;
     ft_status st = prepare_bank(c, bank, t_ref, run, grid, n_t);
     if (st != FT_OK) return st;
+    st = apply_stat_weights(c, opts, grid, grid ? bank->n_sky : 0, run);
+    if (st != FT_OK) return st;
+    const bool sky = run.sky_norm != nullptr;
     run.sum_mode = opts->sum_mode;
     run.precision = opts->precision;
-    hipError_t e;
 
     // tile choice and LDS window for the grid kernel
     int tile = -1;
@@ -1179,7 +1277,11 @@ ft_status ft_eval_templates(ft_ctx c, const ft_bank *bank, double t_ref, const f
         const bool uniform = run.eta < 1e-4;
         double dt_absmax = 0.0;
         for (double t : c->t_mid_h) dt_absmax = std::max(dt_absmax, std::fabs(t - t_ref));
-        if (opts->tile > 0) {
+        if (sky) {
+            if (opts->tile > 0 && !tile_has_sky_weights(opts->tile - 1))
+                return fail(c, FT_E_INVALID, "tile %d has no form with sky-dependent weights", opts->tile);
+            tile = opts->tile > 0 ? opts->tile - 1 : uniform ? kSkyTileRun : kSkyTileOne;
+        } else if (opts->tile > 0) {
             tile = opts->tile - 1;
         } else {
             const std::vector<int64_t> key = plain_tune_key(c, n0, n1, ns, uniform);
@@ -1194,7 +1296,7 @@ ft_status ft_eval_templates(ft_ctx c, const ft_bank *bank, double t_ref, const f
             }
             if (tile < 0) tile = choose_tile(n0, n1, uniform);
         }
-        if (tile_cfg(tile).L > 1 && !uniform) tile = 1;
+        if (tile_cfg(tile).L > 1 && !uniform) tile = kSkyTileOne;
         const WindowPlan wp = plan_window(c->f0_h.data(), n0, c->f1_h.data(), n1, c->sky_tile_h.data(), ns,
                                           dt_absmax, c->vmax, c->t_sft, tile);
         tile = wp.tile;  // -1: the window does not fit in LDS, use the direct kernel
@@ -1227,15 +1329,20 @@ static ft_status launch_eval_select(ft_ctx c, EvalRun &run, bool grid, int tile,
     if (e == hipSuccess) e = launch_fill_u32(c->d_err, 0u, 1, c->stream);
     if (e == hipSuccess) e = launch_subband_map(c->d_f0, n_seg_map, c->d_edges, n_seg, c->d_seg, c->stream);
     if (e == hipSuccess) e = hipEventRecord(c->ev[0], c->stream);
+    if (e == hipSuccess && run.sky_norm)
+        e = launch_sky_moments(run.arms, run.weight, run.n_sft, run.sky, run.n_sky, opts->statistic, c->d_sky_norm,
+                               c->d_sky_ms, c->d_err, c->stream);
     if (e == hipSuccess)
         e = run.ap ? launch_eval_binary(run, c->stream)
             : !grid ? launch_eval_list(run, c->stream)
             : tile < 0 ? launch_eval_grid_direct(run, c->stream) : launch_eval_grid(run, tile_cfg(tile), c->stream);
     if (e == hipSuccess) e = hipEventRecord(c->ev[1], c->stream);
     const double N = (double)c->n_sft;
-    const double rel_err = opts->sum_mode == FT_SUM_BLOCKED ? 40.0 * std::ldexp(1.0, -24) + 4.0 * N * std::ldexp(1.0, -53)
-                                                            : (N + 8.0) * std::ldexp(1.0, -24) + 4.0 * N * std::ldexp(1.0, -53);
-    SelectBufs sb = select_bufs(c, cap);
+    // sky-dependent weights: one more rounding per term (the factor)
+    const double rel_err = (opts->sum_mode == FT_SUM_BLOCKED ? 40.0 * std::ldexp(1.0, -24) + 4.0 * N * std::ldexp(1.0, -53)
+                                                             : (N + 8.0) * std::ldexp(1.0, -24) + 4.0 * N * std::ldexp(1.0, -53)) +
+                           (run.sky_norm ? 4.0 * std::ldexp(1.0, -24) : 0.0);
+    SelectBufs sb = select_bufs(c, cap, opts->statistic);
     if (e == hipSuccess) e = launch_select(run, grid, n_seg, k, rel_err, sb, c->stream);
     if (e == hipSuccess) e = launch_rescore_rank(run, grid, n_seg, k, sb, c->stream);
     if (e == hipSuccess) e = hipEventRecord(c->ev[2], c->stream);
@@ -1250,6 +1357,7 @@ static ft_status launch_eval_select(ft_ctx c, EvalRun &run, bool grid, int tile,
     c->last_cap = cap;
     c->last_rel_err = rel_err;
     c->last_tile = tile;
+    c->last_stat = opts->statistic;
     return FT_OK;
 }
 
@@ -1349,6 +1457,8 @@ ft_status ft_eval_binary_random(ft_ctx c, const ft_binary_region *reg, uint64_t 
     run.vmax = c->vmax;
     run.sum_mode = opts->sum_mode;
     run.precision = opts->precision;
+    st = apply_stat_weights(c, opts, false, 0, run);
+    if (st != FT_OK) return st;
     return launch_eval_select(c, run, false, -1, n, n, opts, edges, stats);
 }
 
@@ -1369,7 +1479,7 @@ ft_status ft_sync(ft_ctx c)
         if (st != FT_OK) return st;
         c->last_run.err = c->d_err;
         c->last_cap = cap;
-        SelectBufs sb = select_bufs(c, cap);
+        SelectBufs sb = select_bufs(c, cap, c->last_stat);
         hipError_t e = launch_fill_u32(c->d_err, 0u, 1, c->stream);
         if (e == hipSuccess) e = launch_select(c->last_run, c->last_grid, c->last_nsub, c->last_k, c->last_rel_err, sb, c->stream);
         if (e == hipSuccess) e = launch_rescore_rank(c->last_run, c->last_grid, c->last_nsub, c->last_k, sb, c->stream);
@@ -1396,6 +1506,48 @@ ft_status ft_toplist(ft_ctx c, int32_t sub, ft_candidate *out, int32_t *n_out)
     if (e == hipSuccess && n > 0)
         e = hipMemcpy(out, c->d_out + (size_t)sub * c->last_k, (size_t)n * sizeof(ft_candidate), hipMemcpyDefault);
     if (e != hipSuccess) return hip_fail(c, e, "copy toplist");
+    *n_out = n;
+    return FT_OK;
+}
+
+ft_status ft_toplist_number_count(ft_ctx c, int32_t sub, double *nc_out, double *z_out, int32_t *n_out)
+{
+    if (!c) return FT_E_INVALID;
+    c->err.clear();
+    if (!c->have_eval) return fail(c, FT_E_STATE, "no evaluation to read a toplist from");
+    if (sub < 0 || sub >= c->last_nsub) return fail(c, FT_E_INVALID, "sub-band %d out of range", sub);
+    if (!nc_out || !n_out) return fail(c, FT_E_INVALID, "nc_out and n_out must be non-null");
+    ft_status st = ft_sync(c);
+    if (st == FT_OK) st = ensure_nc(c);
+    if (st != FT_OK) return st;
+    hipError_t e = ensure(&c->d_top_nc, &c->cap_top_nc, (size_t)c->last_k * 3);
+    if (e != hipSuccess) return hip_fail(c, e, "alloc number counts");
+    EvalRun r = c->last_run;
+    r.power = c->d_ind;  // the weights (per SFT or per sky point) stay those of the evaluation
+    int32_t n = 0;
+    e = launch_rescore_entries(r, c->last_grid, c->d_out + (size_t)sub * c->last_k, c->d_nout + sub, c->d_top_nc,
+                               c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(&n, c->d_nout + sub, sizeof n, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    std::vector<double> h((size_t)std::max(n, 0) * 3);
+    if (e == hipSuccess && n > 0)
+        e = hipMemcpyAsync(h.data(), c->d_top_nc, h.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "number counts of the toplist");
+    st = sync_and_check(c);
+    if (st != FT_OK) return st;
+    // the critical ratio of the number count, moments from the entry's own weights
+    const double p = std::exp(-1.6);
+    std::vector<double> nc((size_t)std::max(n, 0)), z(nc.size());
+    for (int32_t i = 0; i < n; ++i) {
+        nc[(size_t)i] = h[3 * (size_t)i];
+        z[(size_t)i] = (h[3 * (size_t)i] - p * h[3 * (size_t)i + 1]) / std::sqrt(p * (1.0 - p) * h[3 * (size_t)i + 2]);
+    }
+    if (n > 0) {
+        e = hipMemcpy(nc_out, nc.data(), nc.size() * sizeof(double), hipMemcpyDefault);
+        if (e == hipSuccess && z_out) e = hipMemcpy(z_out, z.data(), z.size() * sizeof(double), hipMemcpyDefault);
+        if (e != hipSuccess) return hip_fail(c, e, "copy number counts");
+    }
     *n_out = n;
     return FT_OK;
 }

@@ -39,6 +39,11 @@
 // equals the canonical FP64 bin.
 //
 // Sums: FP32 within aligned blocks of 32 SFTs, block sums accumulated in FP64.
+//
+// Sky-dependent weights (SKYW): the staged table holds u_k P (as without
+// them), and each accumulation multiplies by the wave's factor
+// ab_k(n) / sum_k' u_k' ab_k'(n) of its sky point (one FMA instead of the add),
+// formed per SFT in the stage preparation.
 #include "ft_internal.h"
 
 namespace ft {
@@ -58,6 +63,7 @@ struct StageParams {
     double g[NW][KS];                // canonical Doppler factor
     StepParams<JT> q[NW][KS];        // run-estimate parameters
     double c[JT][KS];                // canonical f1 * dt
+    float wt[NW][KS];                // sky-dependent weight factor (SKYW)
     int lo[KS];                      // first staged bin
 };
 
@@ -70,6 +76,7 @@ struct Shared {
     int lo_w[NW][KS], hi_w[NW][KS];  // per sky point bin range of the stage being prepared
     double vdt[2][4 * KS];           // per stage: v/c [KS][3] then dt [KS], prefetched a stage ahead
     double f1[JT], sky[NW][3];       // the tile's f1 values and sky points
+    double norm[NW];                 // 1 / sum_k u_k ab_k(n) of the sky points (SKYW)
 };
 
 // Asynchronous copy of the velocities and time offsets of SFTs [k0, k0 + ks)
@@ -127,7 +134,7 @@ struct TileGeom {
 // in lane kk (the FP64 bin is monotone in f0, c and g, so the union is the
 // exact range of the tile).  Returns false, in every wave, if the window does
 // not fit the LDS rows (flagged).
-template <int L, int JT, int NW, int KS>
+template <int L, int JT, int NW, int KS, bool SKYW>
 __device__ __forceinline__ bool prepare_stage(const EvalRun &r, const TileGeom &tg, int stage,
                                               StageParams<L, JT, NW, KS> &P,
                                               Shared<L, JT, NW, KS> &sh, float *wbuf)
@@ -153,6 +160,7 @@ __device__ __forceinline__ bool prepare_stage(const EvalRun &r, const TileGeom &
         if (wave == 0) P.c[jl][kk] = c;
         if (jl == 0) {
             P.g[wave][kk] = g;
+            if (SKYW) P.wt[wave][kk] = (float)(sky_ab(r.arms + 6 * (int64_t)(k0 + kk), nx, ny, nz) * sh.norm[wave]);
             P.q[wave][kk].G = G;
             if (L > 1) P.q[wave][kk].w = ((1.0 - r.eta) - fmax(0.0, eL)) - ulo;
             double cmin = c, cmax = c;
@@ -305,7 +313,7 @@ __device__ __forceinline__ void canonical_fix(const StageParams<L, JT, NW, KS> &
 // The gathers are issued before the guard verdict: an estimate is within one
 // bin of the canonical bin, the LDS rows carry that margin, and reads past
 // the last row stay inside the workgroup's LDS allocation.
-template <int L, int JT, int NW, int KS>
+template <int L, int JT, int NW, int KS, bool SKYW>
 __device__ __forceinline__ void accumulate_pipelined(const EvalRun &r, const StageParams<L, JT, NW, KS> &P,
                                                      const Shared<L, JT, NW, KS> &sh, const TileGeom &tg,
                                                      const float *wb, int wtp, int k0, int ks, int wave,
@@ -334,10 +342,18 @@ __device__ __forceinline__ void accumulate_pipelined(const EvalRun &r, const Sta
         for (int jl = 0; jl < JT; ++jl) asm volatile("" ::"v"(Bn[jl]), "s"(fn[jl]));
         if (any)  // rare: some lane is within the guard margin of a bin edge
             canonical_fix<L, JT, NW, KS>(P, sh, tg, wb, kk * wtp - P.lo[kk], kk, wave, lane, T, fail, v);
+        if (SKYW) {
+            const float wt = P.wt[wave][kk];
 #pragma unroll
-        for (int jl = 0; jl < JT; ++jl)
+            for (int jl = 0; jl < JT; ++jl)
 #pragma unroll
-            for (int l = 0; l < L; ++l) acc[jl][l] += v[jl][l];
+                for (int l = 0; l < L; ++l) acc[jl][l] = __builtin_fmaf(v[jl][l], wt, acc[jl][l]);
+        } else {
+#pragma unroll
+            for (int jl = 0; jl < JT; ++jl)
+#pragma unroll
+                for (int l = 0; l < L; ++l) acc[jl][l] += v[jl][l];
+        }
         flush_block<L, JT>(r, k0 + kk, acc, tot);
 #pragma unroll
         for (int jl = 0; jl < JT; ++jl) {
@@ -348,7 +364,7 @@ __device__ __forceinline__ void accumulate_pipelined(const EvalRun &r, const Sta
     }
 }
 
-template <int L, int JT, int NW, int KS, bool PIPE>
+template <int L, int JT, int NW, int KS, bool PIPE, bool SKYW>
 __device__ __forceinline__ void eval_tile(const EvalRun &r, int64_t b, float *win,
                                           Shared<L, JT, NW, KS> &sh)
 {
@@ -386,6 +402,7 @@ __device__ __forceinline__ void eval_tile(const EvalRun &r, int64_t b, float *wi
         const int sl = threadIdx.x / 3, d = threadIdx.x % 3;
         sh.sky[sl][d] = r.sky_tile[3 * (int64_t)min(tg.s_base + sl, tg.s_last) + d];
     }
+    if (SKYW && threadIdx.x < NW) sh.norm[threadIdx.x] = r.sky_norm[r.sky_perm[min(tg.s_base + (int)threadIdx.x, tg.s_last)]];
     if (wave == 0) stage_vdt<KS>(r, 0, min(KS, r.n_sft), sh.vdt[0]);
     wait_loads();
     __syncthreads();
@@ -401,7 +418,7 @@ __device__ __forceinline__ void eval_tile(const EvalRun &r, int64_t b, float *wi
         }
 
     const int n_stage = (r.n_sft + KS - 1) / KS;
-    if (!prepare_stage<L, JT, NW, KS>(r, tg, 0, sh.p[0], sh, win)) return;
+    if (!prepare_stage<L, JT, NW, KS, SKYW>(r, tg, 0, sh.p[0], sh, win)) return;
     wait_loads();
     __syncthreads();
 
@@ -410,13 +427,13 @@ __device__ __forceinline__ void eval_tile(const EvalRun &r, int64_t b, float *wi
         const int ks = min(KS, r.n_sft - k0);
         const int cur = p & 1;
         if (p + 1 < n_stage) {
-            if (!prepare_stage<L, JT, NW, KS>(r, tg, p + 1, sh.p[cur ^ 1], sh, win + (cur ^ 1) * KS * wtp))
+            if (!prepare_stage<L, JT, NW, KS, SKYW>(r, tg, p + 1, sh.p[cur ^ 1], sh, win + (cur ^ 1) * KS * wtp))
                 return;
         }
         const StageParams<L, JT, NW, KS> &P = sh.p[cur];
         const float *wb = win + cur * KS * wtp;
         if (L > 1 && PIPE) {
-            accumulate_pipelined<L, JT, NW, KS>(r, P, sh, tg, wb, wtp, k0, ks, wave, lane, f0_lane, acc, tot);
+            accumulate_pipelined<L, JT, NW, KS, SKYW>(r, P, sh, tg, wb, wtp, k0, ks, wave, lane, f0_lane, acc, tot);
         } else
         for (int kk = 0; kk < ks; ++kk) {
             if (L == 1) {
@@ -425,7 +442,8 @@ __device__ __forceinline__ void eval_tile(const EvalRun &r, int64_t b, float *wi
 #pragma unroll
                 for (int jl = 0; jl < JT; ++jl) {
                     const int B = bin_fp64(f0_lane, P.c[jl][kk], g, T);
-                    acc[jl][0] += wb[base + B];
+                    if (SKYW) acc[jl][0] = __builtin_fmaf(wb[base + B], P.wt[wave][kk], acc[jl][0]);
+                    else acc[jl][0] += wb[base + B];
                 }
             } else {
                 // reads at the estimated bins first; the rare failing f1
@@ -442,10 +460,18 @@ __device__ __forceinline__ void eval_tile(const EvalRun &r, int64_t b, float *wi
 #pragma unroll
                     for (int l = 0; l < L; ++l) v[jl][l] = wk[B[jl] + l];
                 if (any) canonical_fix<L, JT, NW, KS>(P, sh, tg, wb, kk * wtp - P.lo[kk], kk, wave, lane, T, fail, v);
+                if (SKYW) {
+                    const float wt = P.wt[wave][kk];
 #pragma unroll
-                for (int jl = 0; jl < JT; ++jl)
+                    for (int jl = 0; jl < JT; ++jl)
 #pragma unroll
-                    for (int l = 0; l < L; ++l) acc[jl][l] += v[jl][l];
+                        for (int l = 0; l < L; ++l) acc[jl][l] = __builtin_fmaf(v[jl][l], wt, acc[jl][l]);
+                } else {
+#pragma unroll
+                    for (int jl = 0; jl < JT; ++jl)
+#pragma unroll
+                        for (int l = 0; l < L; ++l) acc[jl][l] += v[jl][l];
+                }
             }
         }
         // blocks of SUM_BLOCK SFTs end with a stage (KS divides SUM_BLOCK)
@@ -486,7 +512,7 @@ __device__ __forceinline__ void eval_tile(const EvalRun &r, int64_t b, float *wi
 // OCC > 0 asks the compiler for at least OCC workgroups per CU (a register
 // budget of 512 / OCC per lane at four waves per workgroup); 0 leaves the
 // allocation free.
-template <int L, int JT, int NW, int KS, int OCC, bool PIPE>
+template <int L, int JT, int NW, int KS, int OCC, bool PIPE, bool SKYW>
 __global__ __launch_bounds__(64 * NW, OCC > 0 ? OCC : 1) void eval_grid_kernel(EvalRun r)
 {
     extern __shared__ float win[];  // [2][KS][wtp]
@@ -495,7 +521,7 @@ __global__ __launch_bounds__(64 * NW, OCC > 0 ? OCC : 1) void eval_grid_kernel(E
     const int64_t full = nt - (nt & 7);
     for (int64_t b0 = blockIdx.x; b0 < nt; b0 += gridDim.x) {
         const int64_t b = b0 < full ? (b0 & 7) * (full >> 3) + (b0 >> 3) : b0;
-        eval_tile<L, JT, NW, KS, PIPE>(r, b, win, sh);
+        eval_tile<L, JT, NW, KS, PIPE, SKYW>(r, b, win, sh);
     }
 }
 
@@ -519,7 +545,7 @@ __global__ __launch_bounds__(64 * NW, OCC > 0 ? OCC : 1) void eval_batch_kernel(
         if (item >= n_items) break;
         const int2 it = items[item];
         const EvalRun r = runs[__builtin_amdgcn_readfirstlane(it.x)];
-        eval_tile<L, JT, NW, KS, PIPE>(r, __builtin_amdgcn_readfirstlane(it.y), win, sh);
+        eval_tile<L, JT, NW, KS, PIPE, false>(r, __builtin_amdgcn_readfirstlane(it.y), win, sh);
     }
 }
 
@@ -534,7 +560,7 @@ hipError_t launch_batch_t(const EvalRun *runs, const int2 *items, int n_items, i
     return hipGetLastError();
 }
 
-template <int L, int JT, int NW, int KS, int OCC, bool PIPE>
+template <int L, int JT, int NW, int KS, int OCC, bool PIPE, bool SKYW = false>
 hipError_t launch_t(const EvalRun &r, hipStream_t s)
 {
     const int64_t nt = (int64_t)r.tiles_f0 * r.tiles_f1 * r.tiles_sky;
@@ -544,7 +570,7 @@ hipError_t launch_t(const EvalRun &r, hipStream_t s)
     // every block's tiles on one XCD
     int64_t grid = nt < (1 << 22) ? nt : (1 << 22);
     if (grid > 8) grid &= ~(int64_t)7;
-    hipLaunchKernelGGL((eval_grid_kernel<L, JT, NW, KS, OCC, PIPE>), dim3((unsigned)grid), dim3(64 * NW),
+    hipLaunchKernelGGL((eval_grid_kernel<L, JT, NW, KS, OCC, PIPE, SKYW>), dim3((unsigned)grid), dim3(64 * NW),
                        lds, s, r);
     return hipGetLastError();
 }
@@ -626,23 +652,27 @@ struct TileEntry {
     BatchLauncher batch_fn;
     size_t static_lds;
     ProbeLauncher probe_fn;
+    Launcher sky_fn;  // sky-dependent weights, or nullptr (no such form of the tile)
 };
 
-#define FT_TILE(id, L, JT, NW, KS)                                                                 \
+#define FT_TILE_X(id, L, JT, NW, KS, SKY)                                                          \
     {{id, "L" #L "_J" #JT "_W" #NW "_K" #KS, L, JT, NW, KS}, &launch_t<L, JT, NW, KS, 0, false>,        \
-     &launch_batch_t<L, JT, NW, KS, 0, false>, sizeof(Shared<L, JT, NW, KS>), &launch_probe_t<L, JT, NW, KS, 0>}
-#define FT_TILE_O(id, L, JT, NW, KS, OCC)                                                          \
+     &launch_batch_t<L, JT, NW, KS, 0, false>, sizeof(Shared<L, JT, NW, KS>), &launch_probe_t<L, JT, NW, KS, 0>, SKY}
+#define FT_TILE(id, L, JT, NW, KS) FT_TILE_X(id, L, JT, NW, KS, nullptr)
+#define FT_TILE_OX(id, L, JT, NW, KS, OCC, SKY)                                                    \
     {{id, "L" #L "_J" #JT "_W" #NW "_K" #KS "_O" #OCC, L, JT, NW, KS}, &launch_t<L, JT, NW, KS, OCC, false>, \
      &launch_batch_t<L, JT, NW, KS, OCC, false>, sizeof(Shared<L, JT, NW, KS>),                     \
-     &launch_probe_t<L, JT, NW, KS, OCC>}
-#define FT_TILE_P(id, L, JT, NW, KS, OCC)                                                           \
+     &launch_probe_t<L, JT, NW, KS, OCC>, SKY}
+#define FT_TILE_O(id, L, JT, NW, KS, OCC) FT_TILE_OX(id, L, JT, NW, KS, OCC, nullptr)
+#define FT_TILE_PX(id, L, JT, NW, KS, OCC, SKY)                                                     \
     {{id, "L" #L "_J" #JT "_W" #NW "_K" #KS "_O" #OCC "_P", L, JT, NW, KS}, &launch_t<L, JT, NW, KS, OCC, true>, \
      &launch_batch_t<L, JT, NW, KS, OCC, true>, sizeof(Shared<L, JT, NW, KS>),                     \
-     &launch_probe_t<L, JT, NW, KS, OCC>}
+     &launch_probe_t<L, JT, NW, KS, OCC>, SKY}
+#define FT_TILE_P(id, L, JT, NW, KS, OCC) FT_TILE_PX(id, L, JT, NW, KS, OCC, nullptr)
 
 const TileEntry kTiles[] = {
     FT_TILE(0, 1, 1, 4, 16),
-    FT_TILE(1, 1, 4, 4, 16),
+    FT_TILE_X(1, 1, 4, 4, 16, (&launch_t<1, 4, 4, 16, 0, false, true>)),
     FT_TILE(2, 3, 4, 4, 16),
     FT_TILE(3, 5, 4, 4, 16),
     FT_TILE(4, 5, 3, 4, 16),
@@ -658,14 +688,14 @@ const TileEntry kTiles[] = {
     FT_TILE(14, 1, 3, 4, 16),
     FT_TILE(15, 3, 3, 4, 16),
     FT_TILE(16, 5, 3, 4, 8),
-    FT_TILE_O(17, 5, 4, 4, 8, 4),
+    FT_TILE_OX(17, 5, 4, 4, 8, 4, (&launch_t<5, 4, 4, 8, 4, false, true>)),
     FT_TILE_O(18, 5, 4, 4, 8, 5),
     FT_TILE(19, 3, 6, 4, 8),
     FT_TILE_O(20, 3, 6, 4, 8, 4),
     FT_TILE_O(21, 3, 6, 4, 8, 5),
     FT_TILE_O(22, 5, 3, 4, 8, 4),
     FT_TILE_O(23, 3, 4, 4, 8, 5),
-    FT_TILE_P(24, 5, 4, 4, 8, 4),
+    FT_TILE_PX(24, 5, 4, 4, 8, 4, (&launch_t<5, 4, 4, 8, 4, true, true>)),
     FT_TILE_P(25, 5, 3, 4, 8, 4),
     FT_TILE_P(26, 3, 4, 4, 8, 4),
     FT_TILE_P(27, 5, 4, 4, 8, 3),
@@ -679,8 +709,11 @@ const TileCfg &tile_cfg(int id) { return kTiles[id].cfg; }
 
 size_t tile_static_lds(int id) { return kTiles[id].static_lds; }
 
+bool tile_has_sky_weights(int id) { return kTiles[id].sky_fn != nullptr; }
+
 hipError_t launch_eval_grid(const EvalRun &run, const TileCfg &cfg, hipStream_t s)
 {
+    if (run.sky_norm) return kTiles[cfg.id].sky_fn ? kTiles[cfg.id].sky_fn(run, s) : hipErrorInvalidValue;
     return kTiles[cfg.id].fn(run, s);
 }
 

@@ -157,6 +157,8 @@ __device__ __forceinline__ void eval_direct_one(const EvalRun &r, int64_t t)
         n = r.sky + 3 * t;
     }
     const double nx = n[0], ny = n[1], nz = n[2];
+    // sky-dependent weights: w_k = u_k (ab_k(n) / sum_k' u_k' ab_k'(n))
+    const double inv = GRID && r.sky_norm ? r.sky_norm[t / ((int64_t)r.n_f0 * r.n_f1)] : 0.0;
     float acc = 0.f;
     double tot = 0.0;
     uint32_t bad = 0;
@@ -171,6 +173,7 @@ __device__ __forceinline__ void eval_direct_one(const EvalRun &r, int64_t t)
         }
         float val = r.power[(int64_t)k * r.n_bins + b];
         if (r.weight) val *= r.weight[k];
+        if (GRID && r.sky_norm) val *= (float)(sky_ab(r.arms + 6 * (int64_t)k, nx, ny, nz) * inv);
         acc += val;
         if (r.sum_mode == FT_SUM_BLOCKED && ((k + 1) & (SUM_BLOCK - 1)) == 0) {
             tot += (double)acc;
@@ -604,9 +607,25 @@ __global__ void batch_dt_kernel(const double *t_mid, const int32_t *sft_begin, c
     }
 }
 
-// mu_G = 2 sum w and sigma_G = 2 sqrt(sum w^2) (Sec. II.B.1), sequential in
-// SFT order.
-__global__ void noise_moments_kernel(const float *weight, int n, double *mu_sigma)
+// exp(-1.6): the probability that a chi^2 variable with 2 degrees of freedom
+// (the noise-only normalised power) exceeds the number-count threshold 3.2.
+constexpr double NC_P = 0x1.9d7bebefb4e15p-3;
+
+// Noise-only (mu, sigma) of statistic `stat` from W1 = sum w, W2 = sum w^2:
+// power 2 W1, 2 sqrt(W2) (Sec. II.B.1); number count p W1, sqrt(p (1-p) W2).
+__device__ __forceinline__ void stat_moments(int stat, double w1, double w2, double *out)
+{
+    if (stat == FT_STAT_NUMBER_COUNT) {
+        out[0] = NC_P * w1;
+        out[1] = sqrt((NC_P * (1.0 - NC_P)) * w2);
+    } else {
+        out[0] = 2.0 * w1;
+        out[1] = 2.0 * sqrt(w2);
+    }
+}
+
+// Moments for per-SFT weights, sums sequential in SFT order.
+__global__ void noise_moments_kernel(const float *weight, int n, int stat, double *mu_sigma)
 {
     if (blockIdx.x != 0 || threadIdx.x != 0) return;
     double sw = 0.0, sw2 = 0.0;
@@ -615,8 +634,67 @@ __global__ void noise_moments_kernel(const float *weight, int n, double *mu_sigm
         sw = sw + w;
         sw2 = sw2 + w * w;
     }
-    mu_sigma[0] = 2.0 * sw;
-    mu_sigma[1] = 2.0 * sqrt(sw2);
+    stat_moments(stat, sw, sw2, mu_sigma);
+}
+
+// Number-count tables (Eq. number_count): ind = 1[P > 3.2] and u_k ind.
+__global__ void nc_table_kernel(const float *power, const float *weight, float *ind, float *ind_w,
+                                int64_t n_rows, int64_t n_cols)
+{
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n_rows * n_cols;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const float b = power[q] >= NC_THRESHOLD_F ? 1.f : 0.f;
+        ind[q] = b;
+        if (weight) ind_w[q] = b * weight[q / n_cols];
+    }
+}
+
+__device__ __forceinline__ double wave_sum(double x)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    return x;
+}
+
+// Sky-dependent weights, one wavefront per sky point (lanes stride the SFTs):
+// norm = 1 / sum_k u_k ab_k(n), then the moments of w_k = u_k (ab_k norm).
+__global__ __launch_bounds__(256) void sky_moments_kernel(const double *arms, const float *weight, int n_sft,
+                                                          const double *sky, int64_t n_sky, int stat, double *norm,
+                                                          double *ms, uint32_t *err)
+{
+    const int lane = threadIdx.x & 63;
+    for (int64_t s = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); s < n_sky; s += (int64_t)gridDim.x * 4) {
+        const double nx = sky[3 * s], ny = sky[3 * s + 1], nz = sky[3 * s + 2];
+        double c1 = 0.0;
+        for (int k = lane; k < n_sft; k += 64) {
+            const double u = weight ? (double)weight[k] : 1.0;
+            c1 += u * sky_ab(arms + 6 * (int64_t)k, nx, ny, nz);
+        }
+        c1 = wave_sum(c1);
+        if (!(c1 > 0.0 && c1 < 1e300)) {
+            if (lane == 0) {
+                atomicOr(err, ERR_BAD_POWER);
+                norm[s] = 0.0;
+                ms[2 * s] = 0.0;
+                ms[2 * s + 1] = 1.0;
+            }
+            continue;
+        }
+        const double inv = 1.0 / c1;
+        double w1 = 0.0, w2 = 0.0;
+        for (int k = lane; k < n_sft; k += 64) {
+            const double u = weight ? (double)weight[k] : 1.0;
+            const double w = u * (sky_ab(arms + 6 * (int64_t)k, nx, ny, nz) * inv);
+            w1 += w;
+            w2 += w * w;
+        }
+        w1 = wave_sum(w1);
+        w2 = wave_sum(w2);
+        if (lane == 0) {
+            norm[s] = inv;
+            stat_moments(stat, w1, w2, ms + 2 * s);
+        }
+    }
 }
 
 unsigned grid_for(int64_t n, int block, unsigned cap = 1u << 20)
@@ -732,9 +810,26 @@ hipError_t launch_batch_dt(const double *t_mid, const int32_t *sft_begin, const 
     return hipGetLastError();
 }
 
-hipError_t launch_noise_moments(const float *weight, int n, double *mu_sigma, hipStream_t s)
+hipError_t launch_noise_moments(const float *weight, int n, int stat, double *mu_sigma, hipStream_t s)
 {
-    hipLaunchKernelGGL(noise_moments_kernel, dim3(1), dim3(64), 0, s, weight, n, mu_sigma);
+    hipLaunchKernelGGL(noise_moments_kernel, dim3(1), dim3(64), 0, s, weight, n, stat, mu_sigma);
+    return hipGetLastError();
+}
+
+hipError_t launch_nc_table(const float *power, const float *weight, float *ind, float *ind_w, int64_t n_rows,
+                           int64_t n_cols, hipStream_t s)
+{
+    hipLaunchKernelGGL(nc_table_kernel, dim3(grid_for(n_rows * n_cols, 256, 8192)), dim3(256), 0, s, power, weight,
+                       ind, ind_w, n_rows, n_cols);
+    return hipGetLastError();
+}
+
+hipError_t launch_sky_moments(const double *arms, const float *weight, int n_sft, const double *sky, int64_t n_sky,
+                              int stat, double *norm, double *ms, uint32_t *err, hipStream_t s)
+{
+    if (n_sky <= 0) return hipSuccess;
+    hipLaunchKernelGGL(sky_moments_kernel, dim3(grid_for((n_sky + 3) / 4, 1, 16384)), dim3(256), 0, s, arms, weight,
+                       n_sft, sky, n_sky, stat, norm, ms, err);
     return hipGetLastError();
 }
 

@@ -108,6 +108,29 @@ __device__ __forceinline__ int bin_binary(double f0, double g, double aw, double
     return (int)t;
 }
 
+// ---------------------------------------------------------------------------
+// All-sky weights (Sec. II.B): a^2 + b^2 = F+^2 + Fx^2 (independent of the
+// polarisation angle) of a detector with arm unit vectors u = arm[0..2],
+// w = arm[3..5] for a source in direction n.  With D = (u u^T - w w^T)/2 the
+// sum is twice the squared norm of D's transverse-traceless part with respect
+// to n, which expands to
+//   (1 - c^2) - (x^2 + y^2 - 2 c x y) + (x^2 - y^2)^2 / 4,
+// x = u.n, y = w.n, c = u.w (1 overhead, 1/4 along an arm, 2/5 on average).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double sky_ab(const double *arm, double nx, double ny, double nz)
+{
+    const double x = (arm[0] * nx + arm[1] * ny) + arm[2] * nz;
+    const double y = (arm[3] * nx + arm[4] * ny) + arm[5] * nz;
+    const double c = (arm[0] * arm[3] + arm[1] * arm[4]) + arm[2] * arm[5];
+    const double x2 = x * x, y2 = y * y;
+    const double dxy = x2 - y2;
+    return ((1.0 - c * c) - ((x2 + y2) - 2.0 * (c * x) * y)) + 0.25 * (dxy * dxy);
+}
+
+// Number-count threshold (Eq. number_count): P > 3.2 as real numbers, which for
+// FP32 P is P >= 3.2f (the float nearest 3.2 lies above it).
+constexpr float NC_THRESHOLD_F = 3.2f;
+
 // The data of one evaluation: an SFT set, its velocities and a grid bank.
 struct EvalRun {
     const float *power;   // [n_sft][n_bins]
@@ -124,6 +147,10 @@ struct EvalRun {
     const double *ap;     // binary list banks: [n] a_p (light-seconds), else nullptr
     const double *omega;  // binary list banks: [n] Omega (rad/s)
     const double *phib;   // binary list banks: [n] phi_b (rad, at t_ref)
+    const double *arms;      // [n_sft][6] detector arms (sky-dependent weights), else nullptr
+    const double *sky_norm;  // grid: [n_sky] 1 / sum_k u_k (a^2 + b^2)_k(n) per sky point
+                             // (original order) -- the sky-dependent weights are on; else nullptr
+    const double *sky_ms;    // grid with sky weights: [n_sky][2] (mu, sigma) of the statistic
     float *stats;         // [n_templates]
     uint32_t *err;        // error flags
     int32_t n_sft;
@@ -154,6 +181,7 @@ struct TileCfg {
 int tile_count();
 const TileCfg &tile_cfg(int id);
 size_t tile_static_lds(int id);
+bool tile_has_sky_weights(int id);  // the tile has a form with sky-dependent weights
 
 // Launchers (stream-ordered, no synchronisation).
 hipError_t launch_eval_grid(const EvalRun &run, const TileCfg &cfg, hipStream_t s);
@@ -191,7 +219,17 @@ hipError_t launch_weight_table(const float *power, const float *weight, float *o
                                int64_t n_rows, int64_t n_cols, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t value, int64_t n, hipStream_t s);
 hipError_t launch_dt(const double *t_mid, double t_ref, double *dt, int n, hipStream_t s);
-hipError_t launch_noise_moments(const float *weight, int n, double *mu_sigma, hipStream_t s);
+// Noise moments (mu, sigma) of statistic `stat` (FT_STAT_*) for per-SFT weights.
+hipError_t launch_noise_moments(const float *weight, int n, int stat, double *mu_sigma, hipStream_t s);
+// Number-count tables: ind = 1[P >= 3.2f], ind_w = u_k ind (when weight is non-null).
+hipError_t launch_nc_table(const float *power, const float *weight, float *ind, float *ind_w, int64_t n_rows,
+                           int64_t n_cols, hipStream_t s);
+// Sky-dependent weights of sky points sky[0..n_sky) (original order):
+// norm[s] = 1 / sum_k u_k ab_k(n_s) and ms[s] = (mu, sigma) of statistic `stat`
+// from W1 = sum w_k, W2 = sum w_k^2, w_k = u_k (ab_k norm[s]).  A sky point
+// whose weights sum to zero flags ERR_BAD_POWER.
+hipError_t launch_sky_moments(const double *arms, const float *weight, int n_sft, const double *sky, int64_t n_sky,
+                              int stat, double *norm, double *ms, uint32_t *err, hipStream_t s);
 hipError_t launch_batch_dt(const double *t_mid, const int32_t *sft_begin, const double *t_ref,
                            const int64_t *dt_prefix, int n_runs, int64_t total, double *dt,
                            hipStream_t s);
@@ -268,6 +306,11 @@ hipError_t launch_select(const EvalRun &run, bool grid, int n_seg, int k, double
                          const SelectBufs &b, hipStream_t s);
 hipError_t launch_rescore_rank(const EvalRun &run, bool grid, int n_seg, int k,
                                const SelectBufs &b, hipStream_t s);
+// FP64 re-summation (canonical bins, the run's weights and table) of the
+// templates of toplist entries top[0..n_out[0]): out[3i .. 3i+2] = (sum,
+// sum w, sum w^2).
+hipError_t launch_rescore_entries(const EvalRun &run, bool grid, const ft_candidate *top, const int32_t *n_out,
+                                  double *out, hipStream_t s);
 
 // Surrogate MLP (6 -> 256 -> 256 -> 256 -> 1).
 constexpr int MLP_H = 256;

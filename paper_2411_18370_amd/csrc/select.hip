@@ -227,7 +227,53 @@ __device__ __forceinline__ double readlane_f64(double v, int l)
     return __hiloint2double(hi, lo);
 }
 
-// FP64 re-summation in SFT order, one wavefront per candidate.
+// FP64 re-summation of template t in SFT order by one wavefront (lanes form
+// the terms of 64 SFTs at a time, lane 0's result is the sum); the weight is
+// u_k, times ab_k(n) / sum_k' u_k' ab_k'(n) with sky-dependent weights.  With
+// MOM the weight sums W1 = sum w and W2 = sum w^2 come out as well.
+template <bool MOM>
+__device__ __forceinline__ double rescore_one(const EvalRun &r, bool grid, int64_t t, int lane, uint32_t &bad,
+                                              double *w1 = nullptr, double *w2 = nullptr)
+{
+    const TemplateParams tp = params_of(r, grid, t);
+    const double inv = grid && r.sky_norm ? r.sky_norm[t / ((int64_t)r.n_f0 * r.n_f1)] : 0.0;
+    double acc = 0.0, sw = 0.0, sw2 = 0.0;
+    for (int k0 = 0; k0 < r.n_sft; k0 += 64) {
+        const int k = k0 + lane;
+        double val = 0.0, wk = 0.0;
+        if (k < r.n_sft) {
+            const double *vk = r.v + 3 * (int64_t)k;
+            const double g = doppler_factor(vk[0], vk[1], vk[2], tp.nx, tp.ny, tp.nz);
+            int b = (r.ap ? bin_binary(tp.f0, g, tp.aw, tp.omega, tp.phib, r.dt[k], r.t_sft)
+                          : bin_fp64(tp.f0, tp.f1 * r.dt[k], g, r.t_sft)) -
+                    r.first_bin;
+            if (b < 0 || b >= r.n_bins) {
+                bad = ERR_RANGE;
+                b = b < 0 ? 0 : r.n_bins - 1;
+            }
+            double w = r.weight ? (double)r.weight[k] : 1.0;
+            if (grid && r.sky_norm) w = w * (sky_ab(r.arms + 6 * (int64_t)k, tp.nx, tp.ny, tp.nz) * inv);
+            val = w * (double)r.power[(int64_t)k * r.n_bins + b];
+            wk = w;
+        }
+        const int m = min(64, r.n_sft - k0);
+        for (int l = 0; l < m; ++l) {
+            acc = acc + readlane_f64(val, l);
+            if (MOM) {
+                const double x = readlane_f64(wk, l);
+                sw = sw + x;
+                sw2 = sw2 + x * x;
+            }
+        }
+    }
+    if (MOM) {
+        *w1 = sw;
+        *w2 = sw2;
+    }
+    return acc;
+}
+
+// FP64 re-summation of the candidates, one wavefront per candidate.
 __global__ __launch_bounds__(256) void rescore_kernel(EvalRun r, bool grid, const int64_t *cand,
                                                       const uint32_t *off, int n_seg,
                                                       int64_t cap, double *s64)
@@ -238,28 +284,29 @@ __global__ __launch_bounds__(256) void rescore_kernel(EvalRun r, bool grid, cons
     uint32_t bad = 0;
     for (int64_t p = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); p < total;
          p += n_waves) {
-        const TemplateParams tp = params_of(r, grid, cand[p]);
-        double acc = 0.0;
-        for (int k0 = 0; k0 < r.n_sft; k0 += 64) {
-            const int k = k0 + lane;
-            double val = 0.0;
-            if (k < r.n_sft) {
-                const double *vk = r.v + 3 * (int64_t)k;
-                const double g = doppler_factor(vk[0], vk[1], vk[2], tp.nx, tp.ny, tp.nz);
-                int b = (r.ap ? bin_binary(tp.f0, g, tp.aw, tp.omega, tp.phib, r.dt[k], r.t_sft)
-                              : bin_fp64(tp.f0, tp.f1 * r.dt[k], g, r.t_sft)) -
-                        r.first_bin;
-                if (b < 0 || b >= r.n_bins) {
-                    bad = ERR_RANGE;
-                    b = b < 0 ? 0 : r.n_bins - 1;
-                }
-                const double w = r.weight ? (double)r.weight[k] : 1.0;
-                val = w * (double)r.power[(int64_t)k * r.n_bins + b];
-            }
-            const int m = min(64, r.n_sft - k0);
-            for (int l = 0; l < m; ++l) acc = acc + readlane_f64(val, l);
-        }
+        const double acc = rescore_one<false>(r, grid, cand[p], lane, bad);
         if (lane == 0) s64[p] = acc;
+    }
+    if (bad) atomicOr(r.err, bad);
+}
+
+// FP64 re-summation of the templates of toplist entries top[0 .. n_out[0]):
+// out[3p .. 3p+2] = (sum, W1, W2).
+__global__ __launch_bounds__(256) void rescore_entries_kernel(EvalRun r, bool grid, const ft_candidate *top,
+                                                              const int32_t *n_out, double *out)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t total = n_out[0];
+    const int64_t n_waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+    uint32_t bad = 0;
+    for (int64_t p = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); p < total; p += n_waves) {
+        double w1, w2;
+        const double acc = rescore_one<true>(r, grid, top[p].index, lane, bad, &w1, &w2);
+        if (lane == 0) {
+            out[3 * p] = acc;
+            out[3 * p + 1] = w1;
+            out[3 * p + 2] = w2;
+        }
     }
     if (bad) atomicOr(r.err, bad);
 }
@@ -301,7 +348,9 @@ __global__ __launch_bounds__(256) void rank_kernel(EvalRun r, bool grid, const i
             c.n[1] = par.ny;
             c.n[2] = par.nz;
             c.s64 = sp;
-            c.z = (sp - mu_sigma[0]) / mu_sigma[1];
+            // sky-dependent weights: the moments of the template's sky point
+            const double *ms = grid && r.sky_ms ? r.sky_ms + 2 * (tp / ((int64_t)r.n_f0 * r.n_f1)) : mu_sigma;
+            c.z = (sp - ms[0]) / ms[1];
             out[(int64_t)sg * k + rank] = c;
         }
     }
@@ -568,6 +617,13 @@ hipError_t launch_rescore_rank(const EvalRun &r, bool grid, int n_seg, int k,
                        b.off, n_seg, b.cap, k, b.mu_sigma, b.out);
     hipLaunchKernelGGL(n_out_kernel, dim3((unsigned)((n_seg + 255) / 256)), dim3(256), 0, s,
                        b.cnt, n_seg, k, b.n_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_rescore_entries(const EvalRun &r, bool grid, const ft_candidate *top, const int32_t *n_out,
+                                  double *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(rescore_entries_kernel, dim3(64), dim3(256), 0, s, r, grid, top, n_out, out);
     return hipGetLastError();
 }
 

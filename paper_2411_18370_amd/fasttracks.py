@@ -20,6 +20,8 @@ FT_OK, FT_E_INVALID, FT_E_STATE, FT_E_RANGE, FT_E_NOMEM, FT_E_DEVICE, FT_E_UNSUP
 FT_BANK_GRID, FT_BANK_LIST, FT_BANK_BINARY = 0, 1, 2
 FT_INDEX_FP64, FT_INDEX_FP32, FT_INDEX_DF64, FT_INDEX_GUARDED = 0, 1, 2, 3
 FT_SUM_BLOCKED, FT_SUM_PLAIN_FP32 = 0, 1
+FT_STAT_POWER, FT_STAT_NUMBER_COUNT = 0, 1
+FT_WEIGHTS_SFT, FT_WEIGHTS_SKY = 0, 1
 FT_TILE_TUNE = -1
 
 
@@ -59,7 +61,7 @@ def make_region(d):
 class ft_eval_opts(C.Structure):
     _fields_ = [("precision", C.c_int32), ("k", C.c_int32), ("n_sub", C.c_int32),
                 ("sum_mode", C.c_int32), ("sub_edges", C.c_void_p), ("tile", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("statistic", C.c_int32), ("weights", C.c_int32), ("reserved", C.c_int32)]
 
 
 class ft_candidate(C.Structure):
@@ -112,7 +114,8 @@ EXPORTS = ("ft_create", "ft_destroy", "ft_last_error", "ft_status_string", "ft_s
            "ft_tile_name", "ft_gen_sfts", "ft_eval_batch", "ft_batch_toplist", "ft_batch_labels",
            "ft_batch_replay", "ft_batch_time", "ft_mlp_create", "ft_mlp_destroy",
            "ft_mlp_get_params", "ft_mlp_predict", "ft_mlp_loss_grad", "ft_mlp_train",
-           "ft_tune_report", "ft_tune_clear", "ft_probe_lds_gather")
+           "ft_tune_report", "ft_tune_clear", "ft_probe_lds_gather", "ft_set_arms",
+           "ft_toplist_number_count")
 
 
 def load(path: str = LIB_PATH):
@@ -164,6 +167,8 @@ def load(path: str = LIB_PATH):
                                      C.POINTER(f64)]),
         "ft_tune_clear": (C.c_int, [P]),
         "ft_probe_lds_gather": (C.c_int, [P, i32, i32, C.POINTER(f64)]),
+        "ft_set_arms": (C.c_int, [P, P]),
+        "ft_toplist_number_count": (C.c_int, [P, i32, P, P, C.POINTER(i32)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -289,13 +294,14 @@ def _binary_bank(f0, sky, ap, omega, phib):
 
 
 def ft_eval_binary(ctx, f0, sky, ap, omega, phib, t_ref, k, sub_edges, sum_mode=FT_SUM_BLOCKED,
-                   stats=None):
+                   stats=None, statistic=FT_STAT_POWER):
     """Evaluate a BINARY bank (f0, sky[n,3], a_p, Omega, phi_b, each [n]); optional
     `stats` output (float32 [n], host or device)."""
     bank, keep = _binary_bank(f0, sky, ap, omega, phib)
     edges = _Arr(sub_edges, np.float64)
     o = ft_eval_opts()
     o.precision, o.k, o.n_sub, o.sum_mode, o.tile = FT_INDEX_FP64, k, len(sub_edges) - 1, sum_mode, 0
+    o.statistic = statistic
     o.sub_edges = edges.ptr
     s = _Arr(stats, np.float32)
     _check(ctx, load().ft_eval_templates(ctx, C.byref(bank), float(t_ref), C.byref(o), s.ptr))
@@ -320,12 +326,13 @@ def ft_gen_binary_bank(ctx, region, seed, first, n):
 
 
 def ft_eval_binary_random(ctx, region, seed, n, t_ref, k, sub_edges, sum_mode=FT_SUM_BLOCKED,
-                          stats=None):
+                          stats=None, statistic=FT_STAT_POWER):
     """Generate templates 0..n-1 of the random binary bank on the device and evaluate them."""
     reg = make_region(region)
     edges = _Arr(sub_edges, np.float64)
     o = ft_eval_opts()
     o.precision, o.k, o.n_sub, o.sum_mode, o.tile = FT_INDEX_FP64, k, len(sub_edges) - 1, sum_mode, 0
+    o.statistic = statistic
     o.sub_edges = edges.ptr
     s = _Arr(stats, np.float32)
     _check(ctx, load().ft_eval_binary_random(ctx, C.byref(reg), int(seed), int(n), float(t_ref),
@@ -356,7 +363,8 @@ def ft_lib_sincos(ctx, x):
 
 
 def ft_eval_templates(ctx, f0, f1, sky, t_ref, k, sub_edges, kind=FT_BANK_GRID,
-                      precision=FT_INDEX_FP64, sum_mode=FT_SUM_BLOCKED, tile=0, stats=None):
+                      precision=FT_INDEX_FP64, sum_mode=FT_SUM_BLOCKED, tile=0, stats=None,
+                      statistic=FT_STAT_POWER, weights=FT_WEIGHTS_SFT):
     """Evaluate a GRID (f0[n_f0], f1[n_f1], sky[n_sky,3]) or LIST bank; optional
     `stats` output (float32, n_templates, host or device)."""
     bank, keep = _bank(f0, f1, sky, kind)
@@ -364,6 +372,7 @@ def ft_eval_templates(ctx, f0, f1, sky, t_ref, k, sub_edges, kind=FT_BANK_GRID,
     o = ft_eval_opts()
     o.precision, o.k, o.n_sub, o.sum_mode, o.tile = precision, k, len(sub_edges) - 1, \
         sum_mode, tile
+    o.statistic, o.weights = statistic, weights
     o.sub_edges = edges.ptr
     s = _Arr(stats, np.float32)
     _check(ctx, load().ft_eval_templates(ctx, C.byref(bank), float(t_ref), C.byref(o), s.ptr))
@@ -375,6 +384,23 @@ def ft_toplist(ctx, sub, k):
     n = C.c_int32()
     _check(ctx, load().ft_toplist(ctx, sub, out, C.byref(n)))
     return [out[i] for i in range(n.value)]
+
+
+def ft_toplist_number_count(ctx, sub, k):
+    """(nc, z_nc): exact weighted number counts (float64) of the entries of sub-band
+    `sub`'s toplist and their critical ratios."""
+    out = np.empty(max(1, k), np.float64)
+    z = np.empty(max(1, k), np.float64)
+    n = C.c_int32()
+    _check(ctx, load().ft_toplist_number_count(ctx, sub, out.ctypes.data_as(C.c_void_p),
+                                               z.ctypes.data_as(C.c_void_p), C.byref(n)))
+    return out[:n.value].copy(), z[:n.value].copy()
+
+
+def ft_set_arms(ctx, arms):
+    """Detector arm unit vectors [N, 6] = (u, w) at the SFT mid-times (host or device)."""
+    a = _Arr(arms, np.float64)
+    _check(ctx, load().ft_set_arms(ctx, a.ptr))
 
 
 def ft_sync(ctx):
@@ -623,6 +649,12 @@ class Context:
 
     def set_velocities(self, v):
         ft_set_velocities(self.ctx, v)
+
+    def set_arms(self, arms):
+        ft_set_arms(self.ctx, arms)
+
+    def toplist_number_count(self, sub, k):
+        return ft_toplist_number_count(self.ctx, sub, k)
 
     def gen_sfts(self, n_sft_per_det, t_mid, t_sft, first_bin, n_bins, v, arms, seed, run, t_ref,
                  inj=None, power_out=None):

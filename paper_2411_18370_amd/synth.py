@@ -209,6 +209,14 @@ def plain_small(seed: int = 1, n_sky: int = 20) -> Workload:
                   [-1e-10, 0.0, 1e-10], n_sky, 10, 1, seed)
 
 
+def weighted_small(seed: int = 5, n_sky: int = 24, n_per_det: int = 300) -> Workload:
+    """2 detectors x 300 SFTs of 1800 s (10% gaps), 150.0-150.22 Hz, 400 f0 x 2 f1 x 24 sky,
+    K = 20 in each of 4 sub-bands: several tiles with a ragged tail, for the weighted
+    statistics (arms included)."""
+    return _build("weighted-2det-300sft-150Hz", 2, n_per_det, 1800.0, 0.1, 150.0, 400,
+                  [-2e-10, 1e-10], n_sky, 20, 4, seed)
+
+
 def allsky_band(seed: int = 2, n_sky: int = 100_000, n_per_det: int = 5000) -> Workload:
     """2 detectors x 5000 SFTs (10% gaps), 200-200.5 Hz, 900 f0 x 11 f1 x n_sky, K=100/0.05 Hz.
 

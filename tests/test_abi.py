@@ -47,7 +47,8 @@ def test_host_only_entry_points():
 def test_struct_layouts_match_header():
     from paper_2411_18370_amd import fasttracks as ft
     assert C.sizeof(ft.ft_bank) == 88
-    assert C.sizeof(ft.ft_eval_opts) == 32
+    assert C.sizeof(ft.ft_eval_opts) == 40
+    assert ft.ft_eval_opts.statistic.offset == 28 and ft.ft_eval_opts.weights.offset == 32
     assert C.sizeof(ft.ft_candidate) == 72
     assert ft.ft_candidate.s64.offset == 56
     assert C.sizeof(ft.ft_tune_entry) == 32
@@ -66,6 +67,8 @@ def test_null_arguments_are_rejected_without_a_device():
     assert lib.ft_q_sample(None, None, 0, None, None, None, None) == ft.FT_E_INVALID
     assert lib.ft_gen_binary_bank(None, None, 0, 0, 0, None, None, None, None, None) == ft.FT_E_INVALID
     assert lib.ft_eval_binary_random(None, None, 0, 0, 0.0, None, None) == ft.FT_E_INVALID
+    assert lib.ft_set_arms(None, None) == ft.FT_E_INVALID
+    assert lib.ft_toplist_number_count(None, 0, None, None, None) == ft.FT_E_INVALID
     assert C.sizeof(ft.ft_binary_region) == 96
 
 

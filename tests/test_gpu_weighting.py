@@ -1,0 +1,236 @@
+"""The weighted number count and the all-sky weights (Sec. II.B, Eq.
+number_count) on the GPU against the oracle: number-count statistics and
+toplists bit-exact (canonical bins, FP64 re-summation of an indicator table);
+sky-weighted statistics within the FP32 bound and toplists within FP64
+rounding of the weights; the persistence-constrained candidate of Sec. VI.A
+against brute force over every template."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import weighting as ow
+from paper_2411_18370_amd import persistence, synth
+
+pytestmark = pytest.mark.gpu
+
+
+def rel_bound(n_sft, sky=False):
+    return (44 if sky else 40) * 2.0 ** -24 + 4 * n_sft * 2.0 ** -53
+
+
+def _ctx(ft, w, u=None, arms=True):
+    import torch
+    c = ft.Context(0, torch.cuda.current_stream().cuda_stream)
+    c.set_sfts(w.n_sft_per_det, w.t_mid, w.t_sft, w.first_bin, w.power, u)
+    c.set_velocities(w.v)
+    if arms:
+        c.set_arms(w.arms)
+    return c
+
+
+def _grid_eval(ft, c, w, tile=0, statistic=0, weights=0, f0=None):
+    import torch
+    f0 = w.f0 if f0 is None else f0
+    n_t = f0.size * w.f1.size * w.sky.shape[0]
+    stats = torch.empty(n_t, dtype=torch.float32, device="cuda:0")
+    c.eval_templates(f0, w.f1, w.sky, w.t_ref, w.k, w.sub_edges, tile=tile, stats=stats,
+                     statistic=statistic, weights=weights)
+    tops = [c.toplist(j, w.k) for j in range(len(w.sub_edges) - 1)]
+    return stats.cpu().numpy().astype(np.float64), tops
+
+
+def _want_tops(w, s64, f0=None):
+    f0 = w.f0 if f0 is None else f0
+    f0t, _, _ = oracle.grid_params(f0, w.f1, w.sky.shape[0])
+    n_sub = len(w.sub_edges) - 1
+    return oracle.toplist(s64, oracle.subband(f0t, w.sub_edges), n_sub, w.k)
+
+
+def _weights(w, weighted):
+    return np.linspace(0.5, 1.5, w.t_mid.size).astype(np.float32) if weighted else None
+
+
+@pytest.mark.parametrize("weighted", [False, True])
+@pytest.mark.parametrize("tile", [0, 2, 25])
+def test_number_count_grid_is_exact(ft, weighted, tile):
+    w = synth.weighted_small(seed=5)
+    u = _weights(w, weighted)
+    ind = ow.number_count_table(w.power)
+    s64, bad = oracle.eval_grid(w.t_mid, w.t_ref, w.t_sft, w.first_bin, ind, u, w.v, w.f0, w.f1, w.sky)
+    assert bad == -1
+    c = _ctx(ft, w, u, arms=False)
+    try:
+        s32, tops = _grid_eval(ft, c, w, tile=tile, statistic=ft.FT_STAT_NUMBER_COUNT)
+    finally:
+        c.close()
+    assert np.all(np.abs(s32 - s64) <= rel_bound(w.t_mid.size) * s64)
+    if not weighted:  # integer counts: the FP32 blocked sums are exact
+        assert np.array_equal(s32, s64)
+    mu, sig = ow.nc_moments(np.ones(w.t_mid.size) if u is None else u.astype(np.float64))
+    for got, idx in zip(tops, _want_tops(w, s64)):
+        assert [t.index for t in got] == list(idx)
+        assert all(t.s64 == s64[t.index] for t in got)
+        assert all(abs(t.z - (t.s64 - mu) / sig) <= 1e-12 * max(1.0, abs(t.z)) for t in got)
+
+
+def test_number_count_list_and_binary_are_exact(ft):
+    w = synth.weighted_small(seed=7, n_sky=6)
+    u = _weights(w, True)
+    ind = ow.number_count_table(w.power)
+    f0, f1, sky, _ = ow.grid_as_list(w.f0, w.f1, w.sky)
+    s64, bad = oracle.eval_list(w.t_mid, w.t_ref, w.t_sft, w.first_bin, ind, u, w.v, f0, f1, sky)
+    assert bad == -1
+    import torch
+    c = _ctx(ft, w, u, arms=False)
+    try:
+        stats = torch.empty(f0.size, dtype=torch.float32, device="cuda:0")
+        c.eval_templates(f0, f1, sky, w.t_ref, w.k, w.sub_edges, kind=ft.FT_BANK_LIST, stats=stats,
+                         statistic=ft.FT_STAT_NUMBER_COUNT)
+        tops = [c.toplist(j, w.k) for j in range(len(w.sub_edges) - 1)]
+        s32 = stats.cpu().numpy().astype(np.float64)
+    finally:
+        c.close()
+    assert np.all(np.abs(s32 - s64) <= rel_bound(w.t_mid.size) * s64)
+    want = oracle.toplist(s64, oracle.subband(f0, w.sub_edges), len(w.sub_edges) - 1, w.k)
+    for got, idx in zip(tops, want):
+        assert [t.index for t in got] == list(idx)
+        assert all(t.s64 == s64[t.index] for t in got)
+
+    b = synth.binary_band(seed=8, n_tmpl=3000, n_per_det=150)
+    ind = ow.number_count_table(b.power)
+    s64, bad = oracle.eval_binary(b.t_mid, b.t_ref, b.t_sft, b.first_bin, ind, None, b.v, b.f0, b.sky,
+                                  b.ap, b.omega, b.phib)
+    assert bad == -1
+    c = ft.Context(0, torch.cuda.current_stream().cuda_stream)
+    try:
+        c.set_sfts(b.n_sft_per_det, b.t_mid, b.t_sft, b.first_bin, b.power)
+        c.set_velocities(b.v)
+        stats = torch.empty(b.f0.size, dtype=torch.float32, device="cuda:0")
+        c.eval_binary(b.f0, b.sky, b.ap, b.omega, b.phib, b.t_ref, b.k, b.sub_edges, stats=stats,
+                      statistic=ft.FT_STAT_NUMBER_COUNT)
+        tops = [c.toplist(j, b.k) for j in range(len(b.sub_edges) - 1)]
+        s32 = stats.cpu().numpy().astype(np.float64)
+    finally:
+        c.close()
+    assert np.array_equal(s32, s64)
+    want = oracle.toplist(s64, oracle.subband(b.f0, b.sub_edges), len(b.sub_edges) - 1, b.k)
+    for got, idx in zip(tops, want):
+        assert [t.index for t in got] == list(idx)
+        assert all(t.s64 == s64[t.index] for t in got)
+
+
+@pytest.mark.parametrize("weighted", [False, True])
+def test_toplist_number_counts_and_persistent_candidate(ft, weighted):
+    """Number counts of a power toplist's entries are exact, and the loudest
+    template with z_nc >= 3 is the brute-force answer over every template."""
+    w = synth.weighted_small(seed=9)
+    u = _weights(w, weighted)
+    ind = ow.number_count_table(w.power)
+    args = (w.t_mid, w.t_ref, w.t_sft, w.first_bin)
+    s64, _ = oracle.eval_grid(*args, w.power, u, w.v, w.f0, w.f1, w.sky)
+    nc64, _ = oracle.eval_grid(*args, ind, u, w.v, w.f0, w.f1, w.sky)
+    mu, sig = ow.nc_moments(np.ones(w.t_mid.size) if u is None else u.astype(np.float64))
+    z_nc = (nc64 - mu) / sig
+    k = 400
+    f0t, _, _ = oracle.grid_params(w.f0, w.f1, w.sky.shape[0])
+    sub = oracle.subband(f0t, w.sub_edges)
+    c = _ctx(ft, w, u, arms=False)
+    try:
+        c.eval_templates(w.f0, w.f1, w.sky, w.t_ref, k, w.sub_edges)
+        n_found = 0
+        for j in range(len(w.sub_edges) - 1):
+            tops = c.toplist(j, k)
+            nc, z = c.toplist_number_count(j, k)
+            assert len(nc) == len(tops) == k
+            for t, n, zz in zip(tops, nc, z):
+                assert n == nc64[t.index]
+                assert abs(zz - z_nc[t.index]) <= 1e-12 * max(1.0, abs(zz))
+            got = persistence.loudest_persistent(c, j, k, 3.0)
+            members = np.flatnonzero(sub == j)
+            passing = members[z_nc[members] >= 3.0]
+            order = members[np.lexsort((members, -s64[members]))]
+            if passing.size:
+                best = passing[np.lexsort((passing, -s64[passing]))][0]
+                rank = int(np.flatnonzero(order == best)[0])
+            else:
+                rank = k
+            if rank < k:
+                assert got is not None and got[0].index == best and got[1] == nc64[best]
+                n_found += 1
+            else:
+                assert got is None
+    finally:
+        c.close()
+    assert n_found >= 1
+
+
+def _sky_case(w, u, statistic, f0=None):
+    f0 = w.f0 if f0 is None else f0
+    table = w.power if statistic == 0 else ow.number_count_table(w.power)
+    S, W = ow.eval_grid_sky_weighted(w.t_mid, w.t_ref, w.t_sft, w.first_bin, table, w.arms, u, w.v, f0,
+                                     w.f1, w.sky)
+    moments = ow.power_moments if statistic == 0 else ow.nc_moments
+    ms = np.array([moments(W[s]) for s in range(W.shape[0])])
+    return S, ms
+
+
+@pytest.mark.parametrize("statistic", [0, 1])
+@pytest.mark.parametrize("tile,uniform", [(0, True), (25, True), (2, True), (0, False)])
+def test_sky_weights_grid(ft, statistic, tile, uniform):
+    w = synth.weighted_small(seed=10)
+    u = _weights(w, True)
+    f0 = w.f0 if uniform else np.sort(w.f0 + np.random.default_rng(1).uniform(0, 0.3, w.f0.size) / w.t_sft)
+    S, ms = _sky_case(w, u, statistic, f0)
+    c = _ctx(ft, w, u)
+    try:
+        s32, tops = _grid_eval(ft, c, w, tile=tile, statistic=statistic, weights=ft.FT_WEIGHTS_SKY, f0=f0)
+        info = c.info()
+    finally:
+        c.close()
+    if not uniform:
+        assert ft.ft_tile_name(info.tile) == "L1_J4_W4_K16"
+    assert np.all(np.abs(s32 - S) <= rel_bound(w.t_mid.size, sky=True) * S + 1e-13)
+    n_per_sky = f0.size * w.f1.size
+    want = _want_tops(w, S, f0)
+    for got, idx in zip(tops, want):
+        assert len(got) == len(idx)
+        kth = S[idx[-1]]
+        for t in got:
+            assert abs(t.s64 - S[t.index]) <= 1e-13 * S[t.index]
+            s = t.index // n_per_sky
+            assert abs(t.z - (S[t.index] - ms[s, 0]) / ms[s, 1]) <= 1e-9
+            # a member may differ from the oracle's only within FP64 rounding of a tie
+            assert S[t.index] >= kth * (1 - 1e-13)
+        gi = {t.index for t in got}
+        for i in idx:
+            if i not in gi:
+                assert S[i] <= got[-1].s64 * (1 + 1e-13)
+
+
+def test_weighting_errors(ft):
+    w = synth.weighted_small(seed=5, n_sky=4, n_per_det=40)
+    c = _ctx(ft, w, arms=False)
+    try:
+        with pytest.raises(ft.FtError, match="FT_E_STATE"):
+            c.eval_templates(w.f0, w.f1, w.sky, w.t_ref, w.k, w.sub_edges, weights=ft.FT_WEIGHTS_SKY)
+        bad = w.arms.copy()
+        bad[3, :3] *= 1.01
+        with pytest.raises(ft.FtError, match="FT_E_INVALID"):
+            c.set_arms(bad)
+        c.set_arms(w.arms)
+        f0, f1, sky, _ = ow.grid_as_list(w.f0[:10], w.f1, w.sky)
+        with pytest.raises(ft.FtError, match="FT_E_UNSUPPORTED"):
+            c.eval_templates(f0, f1, sky, w.t_ref, w.k, w.sub_edges, kind=ft.FT_BANK_LIST,
+                             weights=ft.FT_WEIGHTS_SKY)
+        with pytest.raises(ft.FtError, match="FT_E_INVALID"):
+            c.eval_templates(w.f0, w.f1, w.sky, w.t_ref, w.k, w.sub_edges, tile=1, weights=ft.FT_WEIGHTS_SKY)
+        for field in ("statistic", "weights"):
+            with pytest.raises(ft.FtError, match="FT_E_INVALID"):
+                c.eval_templates(w.f0, w.f1, w.sky, w.t_ref, w.k, w.sub_edges, **{field: 7})
+        # a new SFT set of another size drops the arms
+        c.set_sfts([10], w.t_mid[:10], w.t_sft, w.first_bin, w.power[:10])
+        c.set_velocities(w.v[:10])
+        with pytest.raises(ft.FtError, match="FT_E_STATE"):
+            c.eval_templates(w.f0, w.f1, w.sky, w.t_ref, w.k, w.sub_edges, weights=ft.FT_WEIGHTS_SKY)
+    finally:
+        c.close()
