@@ -301,7 +301,7 @@ def bench_weighted(ft, c, w, f0, f1, sky, edges, arms, log, reps=2):
     weights of Sec. II.B: the power with the all-sky weights (a^2 + b^2)/S_n, the
     weighted number count with per-SFT and with all-sky weights; kernel rates
     (HIP events) and the whole call; then the persistence-checked candidate of
-    Sec. VI.A (loudest power with number-count z >= 3) of each injected sub-band."""
+    Sec. VI.B (loudest power with number-count z >= 3) of each injected sub-band."""
     import numpy as np
     import torch
     from paper_2411_18370_amd import persistence

@@ -297,6 +297,31 @@ ft_status ft_gen_binary_bank(ft_ctx ctx, const ft_binary_region *region, uint64_
 ft_status ft_eval_binary_random(ft_ctx ctx, const ft_binary_region *region, uint64_t seed, int64_t n,
                                 double t_ref, const ft_eval_opts *opts, float *stats);
 
+/*
+ * Ahead-of-time hyperbox partition of a random binary bank's region (Sec.
+ * IV.B): the uniform-density coordinates xi (f0^6, alpha, sin delta, a_p^3,
+ * Omega^4, phi_b) are cut into n_div[d] equal intervals each, so every box
+ * holds the same coordinate volume -- the same expected number of templates.
+ * Template i lies in box b = (((((b0 n1 + b1) n2 + b2) n3 + b3) n4 + b4) n5 + b5)
+ * with b_d = min(floor(n_div[d] * u_d), n_div[d] - 1), u_d the uniform its
+ * coordinate d was drawn from (ft_gen_binary_bank: u0 f0, u1 alpha,
+ * u2 sin delta, u3 a_p, u4 Omega, u5 phi_b; the product in IEEE FP64).
+ * 1 <= n_div[d] <= 2^20, prod n_div <= 2^26.
+ */
+typedef struct {
+    int32_t n_div[6];
+    int32_t reserved[2];
+} ft_box_partition;
+
+/* The loudest template of one box (index -1 and count 0 for an empty box). */
+typedef struct {
+    int64_t index;  /* template index in the random bank                          */
+    int32_t count;  /* templates of the bank in the box                           */
+    float s32;      /* FP32 statistic of the evaluation pass                      */
+    double s64;     /* statistic re-summed in FP64 (the box maximum, exactly)      */
+    double z;       /* critical ratio (Eq. critical_ratio)                        */
+} ft_box_result;
+
 /* One toplist entry. */
 typedef struct {
     int64_t index;   /* template index in the bank                              */
@@ -323,7 +348,7 @@ ft_status ft_toplist(ft_ctx ctx, int32_t sub, ft_candidate *out, int32_t *n_out)
  * evaluation, in toplist order, into nc_out[0..*n_out-1] (capacity k), and
  * its critical ratio (nc - p W1)/sqrt(p (1-p) W2), p = exp(-1.6), W1, W2 the
  * sums of the entry's weights and squared weights, into z_out (may be NULL).  With
- * the POWER statistic this is the persistence check of Sec. VI.A: the loudest
+ * the POWER statistic this is the persistence check of Sec. VI.B: the loudest
  * template whose number count reaches a minimum is the first entry that
  * reaches it (when none of the k does, it lies deeper than the toplist).
  * Synchronises the context's stream.  Errors as ft_toplist.
@@ -332,6 +357,22 @@ ft_status ft_toplist_number_count(ft_ctx ctx, int32_t sub, double *nc_out, doubl
 
 /* Wait for the context's stream and report deferred GPU errors. */
 ft_status ft_sync(ft_ctx ctx);
+
+/*
+ * ft_eval_binary_boxes -- the search step of Sec. IV.B over a random binary
+ * bank: generate templates 0 .. n-1 (as ft_eval_binary_random), evaluate them
+ * with opts->statistic and opts->sum_mode (per-SFT weights; k, n_sub,
+ * sub_edges and tile are not used) and return the loudest template of every
+ * box of `part` in out[0 .. prod n_div - 1] (host or device): the maximum of
+ * the FP64 re-summed statistic, ties to the lower index, exact (every
+ * template whose FP32 statistic is within the certified bound of its box's
+ * FP32 maximum is re-summed).  stats [n] receives the FP32 statistic (or
+ * NULL).  Synchronous.  Errors as ft_eval_binary_random; FT_E_INVALID for a
+ * partition outside the limits.
+ */
+ft_status ft_eval_binary_boxes(ft_ctx ctx, const ft_binary_region *region, uint64_t seed, int64_t n,
+                               double t_ref, const ft_box_partition *part, const ft_eval_opts *opts,
+                               ft_box_result *out, float *stats);
 
 /* Timing and bookkeeping of the last ft_eval_templates (after ft_sync). */
 typedef struct {

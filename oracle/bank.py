@@ -95,3 +95,34 @@ def random_binary_bank(seed, first, n, f0_lo, f0_hi, ap_lo, ap_hi, omega_lo, ome
     omega = root(omega_lo, omega_hi, u[:, 4], 4)
     phib = phib_lo + u[:, 5] * (phib_hi - phib_lo)
     return f0, sky, ap, omega, phib
+
+
+def boxes(seed, first, n, n_div):
+    """Hyperbox of templates first .. first + n - 1 for a regular partition of the
+    uniform-density coordinates into n_div[d] intervals per coordinate (Sec. IV.B):
+    b_d = min(floor(n_div[d] u_d), n_div[d] - 1) from the uniform u_d each
+    coordinate was drawn from, row-major with f0 slowest."""
+    u = uniforms(seed, first, n)
+    b = np.zeros(n, np.int64)
+    for d in range(6):
+        nd = int(n_div[d])
+        bd = np.minimum(np.floor(np.float64(nd) * u[:, d]).astype(np.int64), nd - 1)
+        b = b * nd + bd
+    return b
+
+
+def loudest_per_box(s, box, n_boxes):
+    """(index, count, max) per box: the template with the largest s, ties to the
+    lower index; index -1 and max 0 for an empty box."""
+    s = np.asarray(s, np.float64)
+    box = np.asarray(box, np.int64)
+    order = np.lexsort((np.arange(s.size), -s, box))
+    idx = np.full(n_boxes, -1, np.int64)
+    best = np.zeros(n_boxes)
+    count = np.bincount(box, minlength=n_boxes)
+    first = np.ones(order.size, bool)
+    first[1:] = box[order[1:]] != box[order[:-1]]
+    winners = order[first]
+    idx[box[winners]] = winners
+    best[box[winners]] = s[winners]
+    return idx, count, best

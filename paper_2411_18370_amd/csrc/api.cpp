@@ -50,6 +50,15 @@ struct ft_ctx_s {
     size_t cap_sky_norm = 0, cap_sky_ms = 0;
     double *d_top_nc = nullptr;  // ft_toplist_number_count staging
     size_t cap_top_nc = 0;
+    // hyperbox search (ft_eval_binary_boxes)
+    int32_t *d_box = nullptr, *d_bcount = nullptr;
+    uint32_t *d_bmax32 = nullptr, *d_bncand = nullptr;
+    unsigned long long *d_bmax64 = nullptr, *d_bidx = nullptr;
+    int64_t *d_bcand = nullptr;
+    double *d_bcand_s64 = nullptr;
+    ft_box_result *d_bout = nullptr;
+    size_t cap_box = 0, cap_bcount = 0, cap_bmax32 = 0, cap_bncand = 0, cap_bmax64 = 0, cap_bidx = 0, cap_bcand = 0,
+           cap_bcand_s64 = 0, cap_bout = 0;
     int32_t *d_inj_bin = nullptr;
     size_t cap_inj_bin = 0;
     double *d_inj_amp = nullptr;
@@ -472,6 +481,15 @@ void ft_destroy(ft_ctx c)
     release(&c->d_sky_norm, &c->cap_sky_norm);
     release(&c->d_sky_ms, &c->cap_sky_ms);
     release(&c->d_top_nc, &c->cap_top_nc);
+    release(&c->d_box, &c->cap_box);
+    release(&c->d_bcount, &c->cap_bcount);
+    release(&c->d_bmax32, &c->cap_bmax32);
+    release(&c->d_bncand, &c->cap_bncand);
+    release(&c->d_bmax64, &c->cap_bmax64);
+    release(&c->d_bidx, &c->cap_bidx);
+    release(&c->d_bcand, &c->cap_bcand);
+    release(&c->d_bcand_s64, &c->cap_bcand_s64);
+    release(&c->d_bout, &c->cap_bout);
     release(&c->d_inj_bin, &c->cap_inj_bin);
     release(&c->d_inj_amp, &c->cap_inj_amp);
     release(&c->d_genruns, &c->cap_genruns);
@@ -1192,23 +1210,31 @@ static ft_status tune_plain(ft_ctx c, const EvalRun &run, double dt_absmax, bool
 }
 
 // Evaluation options shared by every bank: validated, sub-band edges read.
-static ft_status check_eval_opts(ft_ctx c, const ft_eval_opts *opts, std::vector<double> &edges)
+// The statistic's options (precision, sums, statistic, weights).
+static ft_status check_stat_opts(ft_ctx c, const ft_eval_opts *opts)
 {
     if (!opts) return fail(c, FT_E_INVALID, "opts is null");
     if (opts->precision != FT_INDEX_FP64)
         return fail(c, FT_E_UNSUPPORTED,
                     "ft_eval_templates computes canonical FP64 bins; the FP32/df64/guarded index "
                     "forms are available through ft_count_index_mismatches and ft_bins");
-    if (opts->k < 1 || opts->k > 65536) return fail(c, FT_E_INVALID, "k must be in [1, 65536]");
-    if (opts->n_sub < 1 || opts->n_sub > 4096) return fail(c, FT_E_INVALID, "n_sub must be in [1, 4096]");
-    if (!opts->sub_edges) return fail(c, FT_E_INVALID, "sub_edges is null");
     if (opts->sum_mode != FT_SUM_BLOCKED && opts->sum_mode != FT_SUM_PLAIN_FP32)
         return fail(c, FT_E_INVALID, "unknown sum_mode");
-    if (opts->tile < FT_TILE_TUNE || opts->tile > tile_count()) return fail(c, FT_E_INVALID, "unknown tile %d", opts->tile);
     if (opts->statistic != FT_STAT_POWER && opts->statistic != FT_STAT_NUMBER_COUNT)
         return fail(c, FT_E_INVALID, "unknown statistic %d", opts->statistic);
     if (opts->weights != FT_WEIGHTS_SFT && opts->weights != FT_WEIGHTS_SKY)
         return fail(c, FT_E_INVALID, "unknown weights %d", opts->weights);
+    return FT_OK;
+}
+
+static ft_status check_eval_opts(ft_ctx c, const ft_eval_opts *opts, std::vector<double> &edges)
+{
+    ft_status st = check_stat_opts(c, opts);
+    if (st != FT_OK) return st;
+    if (opts->k < 1 || opts->k > 65536) return fail(c, FT_E_INVALID, "k must be in [1, 65536]");
+    if (opts->n_sub < 1 || opts->n_sub > 4096) return fail(c, FT_E_INVALID, "n_sub must be in [1, 4096]");
+    if (!opts->sub_edges) return fail(c, FT_E_INVALID, "sub_edges is null");
+    if (opts->tile < FT_TILE_TUNE || opts->tile > tile_count()) return fail(c, FT_E_INVALID, "unknown tile %d", opts->tile);
     if (fetch(edges, opts->sub_edges, (size_t)opts->n_sub + 1) != hipSuccess)
         return fail(c, FT_E_INVALID, "cannot read sub_edges");
     for (size_t j = 0; j < edges.size(); ++j) {
@@ -1406,15 +1432,12 @@ ft_status ft_gen_binary_bank(ft_ctx c, const ft_binary_region *reg, uint64_t see
     return FT_OK;
 }
 
-ft_status ft_eval_binary_random(ft_ctx c, const ft_binary_region *reg, uint64_t seed, int64_t n, double t_ref,
-                                const ft_eval_opts *opts, float *stats)
+// Random binary bank generated on the device (with each template's hyperbox
+// when div is given) and the evaluation run over it.
+static ft_status binary_random_run(ft_ctx c, const ft_binary_region *reg, uint64_t seed, int64_t n, double t_ref,
+                                   const ft_eval_opts *opts, EvalRun &run, const BoxDiv *div, int32_t *box)
 {
-    if (!c) return FT_E_INVALID;
-    c->err.clear();
-    if (hipSetDevice(c->device) != hipSuccess) return fail(c, FT_E_DEVICE, "hipSetDevice");
-    std::vector<double> edges;
-    ft_status st = check_eval_opts(c, opts, edges);
-    if (st == FT_OK) st = check_region(c, reg);
+    ft_status st = check_region(c, reg);
     if (st != FT_OK) return st;
     if (!c->have_sfts || !c->have_vel) return fail(c, FT_E_STATE, "ft_set_sfts and ft_set_velocities must come first");
     if (!is_finite(t_ref)) return fail(c, FT_E_INVALID, "t_ref must be finite");
@@ -1431,10 +1454,11 @@ ft_status ft_eval_binary_random(ft_ctx c, const ft_binary_region *reg, uint64_t 
         (e = ensure(&c->d_bin, &c->cap_bin, (size_t)n * 3)) != hipSuccess ||
         (e = ensure(&c->d_stats, &c->cap_stats, (size_t)n)) != hipSuccess)
         return hip_fail(c, e, "alloc bank");
-    e = launch_gen_binary_bank(*reg, seed, 0, n, c->d_f0, c->d_sky, c->d_bin, c->d_bin + n, c->d_bin + 2 * n, c->stream);
+    e = launch_gen_binary_bank(*reg, seed, 0, n, c->d_f0, c->d_sky, c->d_bin, c->d_bin + n, c->d_bin + 2 * n, c->stream,
+                               div, box);
     if (e == hipSuccess) e = launch_dt(c->d_tmid, t_ref, c->d_dt, c->n_sft, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "generate bank");
-    EvalRun run{};
+    run = EvalRun{};
     run.power = c->d_power;
     run.power_w = c->has_weight ? c->d_power_w : c->d_power;
     run.weight = c->has_weight ? c->d_weight : nullptr;
@@ -1457,9 +1481,88 @@ ft_status ft_eval_binary_random(ft_ctx c, const ft_binary_region *reg, uint64_t 
     run.vmax = c->vmax;
     run.sum_mode = opts->sum_mode;
     run.precision = opts->precision;
-    st = apply_stat_weights(c, opts, false, 0, run);
+    return apply_stat_weights(c, opts, false, 0, run);
+}
+
+ft_status ft_eval_binary_random(ft_ctx c, const ft_binary_region *reg, uint64_t seed, int64_t n, double t_ref,
+                                const ft_eval_opts *opts, float *stats)
+{
+    if (!c) return FT_E_INVALID;
+    c->err.clear();
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, FT_E_DEVICE, "hipSetDevice");
+    std::vector<double> edges;
+    ft_status st = check_eval_opts(c, opts, edges);
+    if (st != FT_OK) return st;
+    EvalRun run;
+    st = binary_random_run(c, reg, seed, n, t_ref, opts, run, nullptr, nullptr);
     if (st != FT_OK) return st;
     return launch_eval_select(c, run, false, -1, n, n, opts, edges, stats);
+}
+
+ft_status ft_eval_binary_boxes(ft_ctx c, const ft_binary_region *reg, uint64_t seed, int64_t n, double t_ref,
+                               const ft_box_partition *part, const ft_eval_opts *opts, ft_box_result *out,
+                               float *stats)
+{
+    if (!c) return FT_E_INVALID;
+    c->err.clear();
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, FT_E_DEVICE, "hipSetDevice");
+    ft_status st = check_stat_opts(c, opts);
+    if (st != FT_OK) return st;
+    if (!part || !out) return fail(c, FT_E_INVALID, "part and out must be non-null");
+    BoxDiv div;
+    int64_t n_boxes = 1;
+    for (int d = 0; d < 6; ++d) {
+        div.n[d] = part->n_div[d];
+        if (div.n[d] < 1 || div.n[d] > (1 << 20)) return fail(c, FT_E_INVALID, "n_div[%d] must be in [1, 2^20]", d);
+        n_boxes *= div.n[d];
+        if (n_boxes > (1 << 26)) return fail(c, FT_E_INVALID, "more than 2^26 boxes");
+    }
+    if (n >= 1 && n < (1LL << 31)) {
+        hipError_t e;
+        if ((e = ensure(&c->d_box, &c->cap_box, (size_t)n)) != hipSuccess ||
+            (e = ensure(&c->d_bcount, &c->cap_bcount, (size_t)n_boxes)) != hipSuccess ||
+            (e = ensure(&c->d_bmax32, &c->cap_bmax32, (size_t)n_boxes)) != hipSuccess ||
+            (e = ensure(&c->d_bmax64, &c->cap_bmax64, (size_t)n_boxes)) != hipSuccess ||
+            (e = ensure(&c->d_bidx, &c->cap_bidx, (size_t)n_boxes)) != hipSuccess ||
+            (e = ensure(&c->d_bout, &c->cap_bout, (size_t)n_boxes)) != hipSuccess ||
+            (e = ensure(&c->d_bncand, &c->cap_bncand, 2)) != hipSuccess)
+            return hip_fail(c, e, "alloc box buffers");
+    }
+    EvalRun run;
+    st = binary_random_run(c, reg, seed, n, t_ref, opts, run, &div, c->d_box);
+    if (st != FT_OK) return st;
+    c->have_eval = false;  // the bank and statistics are replaced
+    const double N = (double)c->n_sft;
+    const double rel_err = opts->sum_mode == FT_SUM_BLOCKED ? 40.0 * std::ldexp(1.0, -24) + 4.0 * N * std::ldexp(1.0, -53)
+                                                            : (N + 8.0) * std::ldexp(1.0, -24) + 4.0 * N * std::ldexp(1.0, -53);
+    int64_t cap = std::max<int64_t>(65536, 4 * n_boxes);
+    for (int attempt = 0; attempt < 2; ++attempt) {
+        hipError_t e;
+        if ((e = ensure(&c->d_bcand, &c->cap_bcand, (size_t)cap)) != hipSuccess ||
+            (e = ensure(&c->d_bcand_s64, &c->cap_bcand_s64, (size_t)cap)) != hipSuccess)
+            return hip_fail(c, e, "alloc box candidates");
+        BoxBufs bb{c->d_box, c->d_bmax32, c->d_bcount, c->d_bmax64, c->d_bidx, c->d_bcand, c->d_bcand_s64, c->d_bncand, cap};
+        e = launch_fill_u32(c->d_err, 0u, 1, c->stream);
+        if (e == hipSuccess && attempt == 0) e = launch_eval_binary(run, c->stream);
+        if (e == hipSuccess) e = launch_box_max(run, n, n_boxes, bb, rel_err, c->stream);
+        uint32_t n_cand[2] = {0, 0};
+        if (e == hipSuccess) e = hipMemcpyAsync(n_cand, c->d_bncand, sizeof n_cand, hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "box maxima");
+        if ((int64_t)n_cand[1] > cap) {  // grow and redo the candidate pass
+            cap = (int64_t)n_cand[1] + 1024;
+            continue;
+        }
+        const double *ms = opts->statistic == FT_STAT_NUMBER_COUNT ? c->d_mu_sigma_nc : c->d_mu_sigma;
+        e = launch_box_pick(run, n_boxes, bb, ms, c->d_bout, c->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(out, c->d_bout, (size_t)n_boxes * sizeof(ft_box_result), hipMemcpyDefault, c->stream);
+        if (e == hipSuccess && stats)
+            e = hipMemcpyAsync(stats, c->d_stats, (size_t)n * sizeof(float), hipMemcpyDefault, c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "box selection");
+        return sync_and_check(c);
+    }
+    return fail(c, FT_E_INTERNAL, "box candidate buffer overflow after growth");
 }
 
 ft_status ft_sync(ft_ctx c)

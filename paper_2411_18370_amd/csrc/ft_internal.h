@@ -273,11 +273,36 @@ hipError_t launch_gen_tables(const GenRun *prep, int n_prep, const int64_t *prep
                              const GenRun *runs, int n_runs, const int64_t *row_prefix, int64_t total_rows,
                              hipStream_t s);
 
+// Hyperbox partition: divisions of (f0, alpha, sin delta, a_p, Omega, phi_b).
+struct BoxDiv {
+    int32_t n[6];
+};
+
 // Random binary-system bank (uniform in the xi coordinates) of templates
 // first .. first + n - 1 into device arrays f0[n], sky[n][3], ap[n],
-// omega[n], phib[n].
+// omega[n], phib[n]; with a partition, box[n] receives each template's box.
 hipError_t launch_gen_binary_bank(const ft_binary_region &reg, uint64_t seed, int64_t first, int64_t n, double *f0,
-                                  double *sky, double *ap, double *omega, double *phib, hipStream_t s);
+                                  double *sky, double *ap, double *omega, double *phib, hipStream_t s,
+                                  const BoxDiv *div = nullptr, int32_t *box = nullptr);
+
+// Loudest template per hyperbox (templates' FP32 statistics in run.stats, their
+// boxes in box[n]): per-box FP32 maximum, candidates within the certified
+// bound of it (cand, n_cand = {0, count}; overflow flags ERR_CAND_OVERFLOW),
+// FP64 re-summation, per-box FP64 maximum and lowest index, and the results.
+struct BoxBufs {
+    const int32_t *box;      // [n] box of each template
+    uint32_t *max32;         // [n_boxes] FP32 maximum (bits)
+    int32_t *count;          // [n_boxes]
+    unsigned long long *max64, *idx;  // [n_boxes] FP64 maximum (bits), lowest index attaining it
+    int64_t *cand;           // [cap]
+    double *cand_s64;        // [cap]
+    uint32_t *n_cand;        // [2] = {0, candidates}
+    int64_t cap;
+};
+hipError_t launch_box_max(const EvalRun &run, int64_t n, int64_t n_boxes, const BoxBufs &b, double rel_err,
+                          hipStream_t s);
+hipError_t launch_box_pick(const EvalRun &run, int64_t n_boxes, const BoxBufs &b, const double *mu_sigma,
+                           ft_box_result *out, hipStream_t s);
 
 // Semi-analytic sensitivity: q[i] = (mu_G, sigma_G, rho_hat_1^2, rho_hat_2^2)
 // of population samples (sky [n][3], cos_iota [n], psi [n]) for the SFTs'

@@ -269,7 +269,8 @@ __device__ __forceinline__ double xi_root(double lo, double hi, double u)
 
 __global__ __launch_bounds__(256) void gen_binary_bank_kernel(ft_binary_region reg, uint64_t seed, int64_t first,
                                                               int64_t n, double *f0, double *sky, double *ap,
-                                                              double *omega, double *phib)
+                                                              double *omega, double *phib, BoxDiv div,
+                                                              int32_t *box)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const uint64_t t = (uint64_t)(first + i);
@@ -293,6 +294,16 @@ __global__ __launch_bounds__(256) void gen_binary_bank_kernel(ft_binary_region r
         ap[i] = xi_root<3>(reg.ap_lo, reg.ap_hi, u[3]);
         omega[i] = xi_root<4>(reg.omega_lo, reg.omega_hi, u[4]);
         phib[i] = reg.phib_lo + u[5] * (reg.phib_hi - reg.phib_lo);
+        if (box) {
+            // hyperbox of the template: b_d = floor(n_d u_d) (clamped), row-major
+            int32_t b = 0;
+#pragma unroll
+            for (int d = 0; d < 6; ++d) {
+                const int bd = min((int)floor((double)div.n[d] * u[d]), div.n[d] - 1);
+                b = b * div.n[d] + bd;
+            }
+            box[i] = b;
+        }
     }
 }
 
@@ -346,13 +357,15 @@ hipError_t launch_q_sample(const double *arms, const float *weight, int n_sft, d
 }
 
 hipError_t launch_gen_binary_bank(const ft_binary_region &reg, uint64_t seed, int64_t first, int64_t n, double *f0,
-                                  double *sky, double *ap, double *omega, double *phib, hipStream_t s)
+                                  double *sky, double *ap, double *omega, double *phib, hipStream_t s,
+                                  const BoxDiv *div, int32_t *box)
 {
     if (n <= 0) return hipSuccess;
     int64_t blocks = (n + 255) / 256;
     if (blocks > 65536) blocks = 65536;
+    const BoxDiv d = div ? *div : BoxDiv{{1, 1, 1, 1, 1, 1}};
     hipLaunchKernelGGL(gen_binary_bank_kernel, dim3((unsigned)blocks), dim3(256), 0, s, reg, seed, first, n, f0, sky,
-                       ap, omega, phib);
+                       ap, omega, phib, d, div ? box : nullptr);
     return hipGetLastError();
 }
 

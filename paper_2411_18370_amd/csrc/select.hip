@@ -16,6 +16,8 @@
 //    ranks < K are the toplist, identical to sorting all FP64 statistics.
 #include "ft_internal.h"
 
+#include <algorithm>
+
 namespace ft {
 
 namespace {
@@ -617,6 +619,117 @@ hipError_t launch_rescore_rank(const EvalRun &r, bool grid, int n_seg, int k,
                        b.off, n_seg, b.cap, k, b.mu_sigma, b.out);
     hipLaunchKernelGGL(n_out_kernel, dim3((unsigned)((n_seg + 255) / 256)), dim3(256), 0, s,
                        b.cnt, n_seg, k, b.n_out);
+    return hipGetLastError();
+}
+
+// --- loudest template per hyperbox ------------------------------------------
+__global__ void box_init_kernel(int64_t n_boxes, uint32_t *max32, int32_t *count, unsigned long long *max64,
+                                unsigned long long *idx, uint32_t *n_cand)
+{
+    for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < n_boxes;
+         b += (int64_t)gridDim.x * blockDim.x) {
+        max32[b] = 0u;
+        count[b] = 0;
+        max64[b] = 0ull;
+        idx[b] = ~0ull;
+    }
+    if (blockIdx.x == 0 && threadIdx.x < 2) n_cand[threadIdx.x] = 0u;
+}
+
+// Statistics are >= 0, so their bit patterns order like their values.
+__global__ void box_max_kernel(const float *stats, const int32_t *box, int64_t n, uint32_t *max32, int32_t *count)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t b = box[i];
+        atomicMax(max32 + b, __float_as_uint(stats[i]));
+        atomicAdd(count + b, 1);
+    }
+}
+
+// Candidates: S32 >= max32 (1 - 2 rel_err).  The template with the largest
+// S64 of a box has S32 >= S64 (1 - rel) and the box's FP32 maximum is at most
+// S64max (1 + rel), so it is always kept.
+__global__ void box_cand_kernel(const float *stats, const int32_t *box, int64_t n, const uint32_t *max32, double keep,
+                                int64_t *cand, uint32_t *n_cand, int64_t cap, uint32_t *err)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double thr = (double)__uint_as_float(max32[box[i]]) * keep;
+        if ((double)stats[i] >= thr) {
+            const uint32_t pos = atomicAdd(n_cand + 1, 1u);
+            if (pos < cap) cand[pos] = i;
+            else atomicOr(err, ERR_CAND_OVERFLOW);
+        }
+    }
+}
+
+__global__ void box_pick_kernel(const int64_t *cand, const double *s64, const uint32_t *n_cand, int64_t cap,
+                                const int32_t *box, unsigned long long *max64)
+{
+    const int64_t total = min((int64_t)n_cand[1], cap);
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < total; p += (int64_t)gridDim.x * blockDim.x)
+        atomicMax(max64 + box[cand[p]], (unsigned long long)__double_as_longlong(s64[p]));
+}
+
+__global__ void box_index_kernel(const int64_t *cand, const double *s64, const uint32_t *n_cand, int64_t cap,
+                                 const int32_t *box, const unsigned long long *max64, unsigned long long *idx)
+{
+    const int64_t total = min((int64_t)n_cand[1], cap);
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < total;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t b = box[cand[p]];
+        if ((unsigned long long)__double_as_longlong(s64[p]) == max64[b]) atomicMin(idx + b, (unsigned long long)cand[p]);
+    }
+}
+
+__global__ void box_out_kernel(int64_t n_boxes, const int32_t *count, const unsigned long long *max64,
+                               const unsigned long long *idx, const float *stats, const double *mu_sigma,
+                               ft_box_result *out)
+{
+    for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < n_boxes;
+         b += (int64_t)gridDim.x * blockDim.x) {
+        ft_box_result r;
+        r.count = count[b];
+        if (r.count > 0) {
+            r.index = (int64_t)idx[b];
+            r.s32 = stats[r.index];
+            r.s64 = __longlong_as_double((long long)max64[b]);
+            r.z = (r.s64 - mu_sigma[0]) / mu_sigma[1];
+        } else {
+            r.index = -1;
+            r.s32 = 0.f;
+            r.s64 = 0.0;
+            r.z = 0.0;
+        }
+        out[b] = r;
+    }
+}
+
+hipError_t launch_box_max(const EvalRun &r, int64_t n, int64_t n_boxes, const BoxBufs &b, double rel_err,
+                          hipStream_t s)
+{
+    const unsigned gb = (unsigned)std::min<int64_t>((n_boxes + 255) / 256, 8192);
+    const unsigned gn = (unsigned)std::min<int64_t>((n + 255) / 256, 16384);
+    hipLaunchKernelGGL(box_init_kernel, dim3(gb > 0 ? gb : 1), dim3(256), 0, s, n_boxes, b.max32, b.count, b.max64,
+                       b.idx, b.n_cand);
+    if (n <= 0) return hipGetLastError();
+    hipLaunchKernelGGL(box_max_kernel, dim3(gn), dim3(256), 0, s, r.stats, b.box, n, b.max32, b.count);
+    hipLaunchKernelGGL(box_cand_kernel, dim3(gn), dim3(256), 0, s, r.stats, b.box, n, b.max32, 1.0 - 2.0 * rel_err,
+                       b.cand, b.n_cand, b.cap, r.err);
+    return hipGetLastError();
+}
+
+hipError_t launch_box_pick(const EvalRun &r, int64_t n_boxes, const BoxBufs &b, const double *mu_sigma,
+                           ft_box_result *out, hipStream_t s)
+{
+    const unsigned gb = (unsigned)std::min<int64_t>((n_boxes + 255) / 256, 8192);
+    hipLaunchKernelGGL(rescore_kernel, dim3(2048), dim3(256), 0, s, r, false, b.cand, b.n_cand, 1, b.cap,
+                       b.cand_s64);
+    hipLaunchKernelGGL(box_pick_kernel, dim3(1024), dim3(256), 0, s, b.cand, b.cand_s64, b.n_cand, b.cap, b.box,
+                       b.max64);
+    hipLaunchKernelGGL(box_index_kernel, dim3(1024), dim3(256), 0, s, b.cand, b.cand_s64, b.n_cand, b.cap, b.box,
+                       b.max64, b.idx);
+    hipLaunchKernelGGL(box_out_kernel, dim3(gb > 0 ? gb : 1), dim3(256), 0, s, n_boxes, b.count, b.max64, b.idx,
+                       r.stats, mu_sigma, out);
     return hipGetLastError();
 }
 

@@ -64,6 +64,19 @@ class ft_eval_opts(C.Structure):
                 ("statistic", C.c_int32), ("weights", C.c_int32), ("reserved", C.c_int32)]
 
 
+class ft_box_partition(C.Structure):
+    _fields_ = [("n_div", C.c_int32 * 6), ("reserved", C.c_int32 * 2)]
+
+
+class ft_box_result(C.Structure):
+    _fields_ = [("index", C.c_int64), ("count", C.c_int32), ("s32", C.c_float), ("s64", C.c_double),
+                ("z", C.c_double)]
+
+
+BOX_DTYPE = np.dtype([("index", np.int64), ("count", np.int32), ("s32", np.float32), ("s64", np.float64),
+                      ("z", np.float64)])
+
+
 class ft_candidate(C.Structure):
     _fields_ = [("index", C.c_int64), ("sub", C.c_int32), ("s32", C.c_float),
                 ("f0", C.c_double), ("f1", C.c_double), ("n", C.c_double * 3),
@@ -115,7 +128,7 @@ EXPORTS = ("ft_create", "ft_destroy", "ft_last_error", "ft_status_string", "ft_s
            "ft_batch_replay", "ft_batch_time", "ft_mlp_create", "ft_mlp_destroy",
            "ft_mlp_get_params", "ft_mlp_predict", "ft_mlp_loss_grad", "ft_mlp_train",
            "ft_tune_report", "ft_tune_clear", "ft_probe_lds_gather", "ft_set_arms",
-           "ft_toplist_number_count")
+           "ft_toplist_number_count", "ft_eval_binary_boxes")
 
 
 def load(path: str = LIB_PATH):
@@ -168,6 +181,8 @@ def load(path: str = LIB_PATH):
         "ft_tune_clear": (C.c_int, [P]),
         "ft_probe_lds_gather": (C.c_int, [P, i32, i32, C.POINTER(f64)]),
         "ft_set_arms": (C.c_int, [P, P]),
+        "ft_eval_binary_boxes": (C.c_int, [P, C.POINTER(ft_binary_region), C.c_uint64, i64, f64,
+                                           C.POINTER(ft_box_partition), C.POINTER(ft_eval_opts), P, P]),
         "ft_toplist_number_count": (C.c_int, [P, i32, P, P, C.POINTER(i32)]),
     }
     for name, (res, args) in sig.items():
@@ -337,6 +352,25 @@ def ft_eval_binary_random(ctx, region, seed, n, t_ref, k, sub_edges, sum_mode=FT
     s = _Arr(stats, np.float32)
     _check(ctx, load().ft_eval_binary_random(ctx, C.byref(reg), int(seed), int(n), float(t_ref),
                                              C.byref(o), s.ptr))
+
+
+def ft_eval_binary_boxes(ctx, region, seed, n, t_ref, n_div, statistic=FT_STAT_POWER,
+                         sum_mode=FT_SUM_BLOCKED, stats=None):
+    """Loudest template of every hyperbox of the random binary bank: numpy array of
+    BOX_DTYPE records (index, count, s32, s64, z), one per box in box order."""
+    reg = make_region(region)
+    part = ft_box_partition()
+    for d in range(6):
+        part.n_div[d] = int(n_div[d])
+    o = ft_eval_opts()
+    o.precision, o.sum_mode, o.statistic = FT_INDEX_FP64, sum_mode, statistic
+    n_boxes = int(np.prod([int(x) for x in n_div]))
+    out = np.zeros(max(1, n_boxes), BOX_DTYPE)
+    assert BOX_DTYPE.itemsize == C.sizeof(ft_box_result)
+    st = _Arr(stats, np.float32)
+    _check(ctx, load().ft_eval_binary_boxes(ctx, C.byref(reg), int(seed), int(n), float(t_ref), C.byref(part),
+                                            C.byref(o), out.ctypes.data_as(C.c_void_p), st.ptr))
+    return out[:n_boxes]
 
 
 def ft_q_sample(ctx, arms, sky, cos_iota, psi):
@@ -694,6 +728,9 @@ class Context:
 
     def eval_binary_random(self, *a, **kw):
         ft_eval_binary_random(self.ctx, *a, **kw)
+
+    def eval_binary_boxes(self, *a, **kw):
+        return ft_eval_binary_boxes(self.ctx, *a, **kw)
 
     def count_index_mismatches(self, *a, **kw):
         return ft_count_index_mismatches(self.ctx, *a, **kw)

@@ -1,4 +1,4 @@
-"""Candidate choice with a persistence requirement (Sec. VI.A): the loudest
+"""Candidate choice with a persistence requirement (Sec. VI.B): the loudest
 template by the power statistic whose weighted number count (Eq.
 number_count) reaches a minimum, set in units of the number count's noise
 standard deviation above its noise mean (3 in the paper).

@@ -39,19 +39,52 @@ def q_samples(ctx: ft.Context, arms, n, seed):
     return ctx.q_sample(arms, sky, ci, psi)
 
 
+def z_samples(q, m, eps, depth, eta=BIN_OFFSET_POWER):
+    """Critical ratios of the Gaussian model (Eq. s_gauss) for population samples
+    q [n, 4], mismatches m [n] and standard normal draws eps [n] at one depth:
+    s = mu_G + lambda rho1 + eps sqrt(sigma_G^2 + 4 lambda rho2), lambda = (1 - m) eta / D^2."""
+    lam = (1.0 - m) * eta / (depth * depth)
+    sd_s = np.sqrt(q[:, 1] ** 2 + 4.0 * lam * q[:, 3])
+    return (lam * q[:, 2] + eps * sd_s) / q[:, 1]
+
+
 def p_det(q, m_samples, depths, tau, seed=0, eta=BIN_OFFSET_POWER):
-    """Semi-analytic p_det at each depth (Monte Carlo over the rows of q)."""
+    """Semi-analytic p_det at each depth (Monte Carlo over the rows of q); tau is
+    the detection threshold on z, one value or one per sample."""
     rng = np.random.default_rng(seed)
     q = np.asarray(q, np.float64)
     out = []
     for d in depths:
         m = rng.choice(np.asarray(m_samples, np.float64), q.shape[0])
-        lam = (1.0 - m) * eta / (d * d)
-        mu_s = q[:, 0] + lam * q[:, 2]
-        sd_s = np.sqrt(q[:, 1] ** 2 + 4.0 * lam * q[:, 3])
-        z = (rng.normal(mu_s, sd_s) - q[:, 0]) / q[:, 1]
-        out.append(float(np.mean(z > tau)))
+        eps = rng.standard_normal(q.shape[0])
+        out.append(float(np.mean(z_samples(q, m, eps, d, eta) > tau)))
     return np.array(out)
+
+
+def depth_at(q, m_samples, p, tau, seed=0, eta=BIN_OFFSET_POWER, d_lo=1.0, d_hi=1e4, iters=60):
+    """Sensitivity depth D^p (Eq. solve_this): the depth at which the
+    semi-analytic p_det equals p, by bisection in log D with the same mismatch
+    and normal draws at every depth (so p_det is monotone in D)."""
+    rng = np.random.default_rng(seed)
+    q = np.asarray(q, np.float64)
+    m = rng.choice(np.asarray(m_samples, np.float64), q.shape[0])
+    eps = rng.standard_normal(q.shape[0])
+
+    def pd(d):
+        return float(np.mean(z_samples(q, m, eps, d, eta) > tau))
+
+    if pd(d_lo) < p:
+        return d_lo
+    if pd(d_hi) >= p:
+        return d_hi
+    lo, hi = np.log(d_lo), np.log(d_hi)
+    for _ in range(iters):
+        mid = 0.5 * (lo + hi)
+        if pd(np.exp(mid)) >= p:
+            lo = mid
+        else:
+            hi = mid
+    return float(np.exp(lo))
 
 
 def injection_p_det(ctx: ft.Context, w, depths, n_inj, o, tau, seed=0):

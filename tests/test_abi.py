@@ -52,6 +52,8 @@ def test_struct_layouts_match_header():
     assert C.sizeof(ft.ft_candidate) == 72
     assert ft.ft_candidate.s64.offset == 56
     assert C.sizeof(ft.ft_tune_entry) == 32
+    assert C.sizeof(ft.ft_box_partition) == 32 and C.sizeof(ft.ft_box_result) == 32
+    assert ft.BOX_DTYPE.itemsize == 32 and ft.ft_box_result.s64.offset == 16
 
 
 def test_null_arguments_are_rejected_without_a_device():
@@ -68,6 +70,7 @@ def test_null_arguments_are_rejected_without_a_device():
     assert lib.ft_gen_binary_bank(None, None, 0, 0, 0, None, None, None, None, None) == ft.FT_E_INVALID
     assert lib.ft_eval_binary_random(None, None, 0, 0, 0.0, None, None) == ft.FT_E_INVALID
     assert lib.ft_set_arms(None, None) == ft.FT_E_INVALID
+    assert lib.ft_eval_binary_boxes(None, None, 0, 0, 0.0, None, None, None, None) == ft.FT_E_INVALID
     assert lib.ft_toplist_number_count(None, 0, None, None, None) == ft.FT_E_INVALID
     assert C.sizeof(ft.ft_binary_region) == 96
 

@@ -2,7 +2,7 @@
 number_count) on the GPU against the oracle: number-count statistics and
 toplists bit-exact (canonical bins, FP64 re-summation of an indicator table);
 sky-weighted statistics within the FP32 bound and toplists within FP64
-rounding of the weights; the persistence-constrained candidate of Sec. VI.A
+rounding of the weights; the persistence-constrained candidate of Sec. VI.B
 against brute force over every template."""
 import numpy as np
 import pytest
