@@ -296,6 +296,82 @@ def bench_sensitivity(ft, synth, log, o=3.44, tau=8.0, depths=(15.0, 22.0, 27.0,
     return out
 
 
+def bench_hyperbox(ft, synth, log, n_bank=10 ** 8, min_boxes=10_000, o=3.44, n_q=100_000,
+                   n_cands=(1, 10, 100, 1000), rejects=(0, 1, 3, 10, 30, 100, 300, 500)):
+    """Search step of Sec. IV.B / VI.A on the paper's binary workload: a random
+    bank of n_bank templates (o = 3.44, full sky and orbital phase, a_p 5-15
+    lt-s, periods 7-15 d, f0 from 110.5 Hz up to the width that holds them)
+    partitioned into at least 10^4 equal-volume hyperboxes, the exact loudest
+    template of each (whole call timed: generation, evaluation, per-box
+    selection); then D^95% for N_cand candidates with the optimal number of
+    rejected boxes (semi-analytic estimate with p(m|o) and 10^5 q samples), on
+    Gaussian noise and with a synthetic transient instrumental line (+4 in the
+    bin 6 bins above the band, over the middle 30% of the SFTs)."""
+    import numpy as np
+    import torch
+    from paper_2411_18370_amd import hyperbox, mismatch, sensitivity
+    w = synth.binary_band(seed=3, n_tmpl=1, n_per_det=5000)
+    t_obs = float(w.t_mid.max() - w.t_mid.min() + w.t_sft)
+    vmax = float(np.max(np.linalg.norm(w.v, axis=1)))
+    region = dict(w.region, alpha_lo=0.0, alpha_hi=2 * np.pi, sdec_lo=-1.0, sdec_hi=1.0, phib_lo=0.0,
+                  phib_hi=2 * np.pi)
+    per_f06 = mismatch.n_templates(region, w.t_sft, t_obs, vmax) / (region["f0_hi"] ** 6 - region["f0_lo"] ** 6)
+    region["f0_hi"] = (region["f0_lo"] ** 6 + n_bank / (o * per_f06)) ** (1.0 / 6.0)
+    n_div = hyperbox.partition(region, w.t_sft, t_obs, vmax, o, n_bank / min_boxes, min_boxes=min_boxes)
+    n_boxes = int(np.prod(n_div))
+    dev = torch.device("cuda:0")
+    c = ft.Context(0, torch.cuda.current_stream().cuda_stream)
+    power = torch.from_numpy(w.power).to(dev)
+    c.set_sfts(w.n_sft_per_det, torch.from_numpy(w.t_mid).to(dev), w.t_sft, w.first_bin, power)
+    c.set_velocities(torch.from_numpy(w.v).to(dev))
+    c.eval_binary_boxes(region, 1, 10 ** 6, w.t_ref, n_div)  # warm-up
+    runs = {}
+    # the line sits 6 bins above the band: only tracks with a large orbital
+    # Doppler amplitude a_p Omega f0 T (up to ~8 bins here) reach it
+    line_col = int(round(region["f0_lo"] * w.t_sft)) + 6 - w.first_bin
+    k0, k1 = int(0.35 * w.n_sft), int(0.65 * w.n_sft)
+    for case in ("gaussian", "line"):
+        if case == "line":
+            tab = w.power.copy()
+            tab[k0:k1, line_col] += 4.0
+            c.set_sfts(w.n_sft_per_det, torch.from_numpy(w.t_mid).to(dev), w.t_sft, w.first_bin,
+                       torch.from_numpy(tab).to(dev))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = c.eval_binary_boxes(region, 7, n_bank, w.t_ref, n_div)
+        secs = time.perf_counter() - t0
+        runs[case] = (res, secs)
+        z = res["z"][res["index"] >= 0]
+        log("hyperbox %s: %d templates in %d boxes (n_div %s) in %.2f s (%.3g evals/s); box z max %.1f, "
+            "median %.2f" % (case, n_bank, n_boxes, n_div, secs, n_bank * w.n_sft / secs, z.max(), np.median(z)))
+    m = mismatch.sample(c, w, o=o, n_trials=100, seed=12, amp=1.0)["m"]
+    c.set_sfts(w.n_sft_per_det, w.t_mid, w.t_sft, w.first_bin, w.power)
+    q = sensitivity.q_samples(c, w.arms, n_q, seed=13)
+    c.close()
+    out = {"workload": "random binary bank of %d templates (o = %g) over f0 %.6f-%.6f Hz, full sky and phase, "
+                       "a_p 5-15 lt-s, periods 7-15 d; 2 det x 5000 SFTs of 1024 s"
+                       % (n_bank, o, region["f0_lo"], region["f0_hi"]),
+           "n_div": n_div, "n_boxes": n_boxes, "cases": {}}
+    for case, (res, secs) in runs.items():
+        z_box = np.where(res["index"] >= 0, res["z"], np.nan)
+        t0 = time.perf_counter()
+        rows = []
+        for n_cand in n_cands:
+            best, table = hyperbox.optimize_reject(q, m, z_box, n_cand, rejects, p=0.95, seed=21)
+            d = dict(table)
+            rows.append({"n_cand": n_cand, "d95_no_reject": d[0], "best_n_reject": best, "d95_best": d[best],
+                         "table": table})
+            log("hyperbox %s N_cand=%d: D95 %.2f without rejection, %.2f rejecting %d boxes"
+                % (case, n_cand, d[0], d[best], best))
+        out["cases"][case] = {"seconds": secs, "evals_per_s_call": n_bank * w.n_sft / secs,
+                              "empty_boxes": int((res["index"] < 0).sum()),
+                              "templates_per_box_mean": float(res["count"].mean()),
+                              "box_z_max": float(np.nanmax(z_box)), "selection": rows,
+                              "optimisation_s": time.perf_counter() - t0}
+    out["line"] = {"column_hz": (w.first_bin + line_col) / w.t_sft, "sfts": [k0, k1], "excess_power": 4.0}
+    return out
+
+
 def bench_weighted(ft, c, w, f0, f1, sky, edges, arms, log, reps=2):
     """The all-sky band (table already loaded in c) with the other statistics and
     weights of Sec. II.B: the power with the all-sky weights (a^2 + b^2)/S_n, the
@@ -398,7 +474,7 @@ def main():
     ap.add_argument("--surrogate-test", type=int, default=100_000)
     ap.add_argument("--skip-extras", action="store_true",
                     help="plain workload only (no batched, precision or surrogate sections)")
-    ap.add_argument("--sections", default="weighted,batched,precision,surrogate,binary,mismatch,sensitivity",
+    ap.add_argument("--sections", default="weighted,batched,precision,surrogate,binary,mismatch,sensitivity,hyperbox",
                     help="comma-separated extra sections to run")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -548,6 +624,8 @@ def main():
         line["mismatch"] = bench_mismatch(ft, synth, log)
     if "sensitivity" in sections:
         line["sensitivity"] = bench_sensitivity(ft, synth, log)
+    if "hyperbox" in sections:
+        line["hyperbox"] = bench_hyperbox(ft, synth, log)
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on a CPU sample")
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
