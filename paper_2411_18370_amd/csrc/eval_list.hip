@@ -624,17 +624,31 @@ __device__ __forceinline__ void stat_moments(int stat, double w1, double w2, dou
     }
 }
 
-// Moments for per-SFT weights, sums sequential in SFT order.
+// Moments for per-SFT weights: one wavefront, lane l sums SFTs l, l + 64, ...
+// in order, then lane 0 adds the 64 partial sums in lane order (a fixed
+// order, so the result does not depend on scheduling).
 __global__ void noise_moments_kernel(const float *weight, int n, int stat, double *mu_sigma)
 {
-    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    __shared__ double part[2][64];
+    const int lane = threadIdx.x;
+    if (blockIdx.x != 0 || lane >= 64) return;
     double sw = 0.0, sw2 = 0.0;
-    for (int k = 0; k < n; ++k) {
+    for (int k = lane; k < n; k += 64) {
         const double w = weight ? (double)weight[k] : 1.0;
         sw = sw + w;
         sw2 = sw2 + w * w;
     }
-    stat_moments(stat, sw, sw2, mu_sigma);
+    part[0][lane] = sw;
+    part[1][lane] = sw2;
+    __syncthreads();
+    if (lane == 0) {
+        double a = 0.0, b = 0.0;
+        for (int l = 0; l < 64; ++l) {
+            a = a + part[0][l];
+            b = b + part[1][l];
+        }
+        stat_moments(stat, a, b, mu_sigma);
+    }
 }
 
 // Number-count tables (Eq. number_count): ind = 1[P > 3.2] and u_k ind.
