@@ -104,3 +104,69 @@ def test_allsky_full_size(ft):
         assert z_inj[q] > 20
         assert top.z >= 0.25 * z_inj[q]
         assert abs(top.f0 - x["f0"]) * w.t_sft <= 3.0
+
+
+def test_allsky_full_size_number_count_sky_weights(ft):
+    """The same band with the weighted number count and the all-sky weights
+    (Sec. II.B): sampled templates and every toplist member against the oracle's
+    sky weights and indicator table; nothing outside a toplist beats its K-th
+    member beyond the FP32 bound."""
+    import torch
+    from oracle import weighting as ow
+    dev = torch.device("cuda:0")
+    w = synth.allsky_band(seed=2)
+    table = inject.generate_table(2, 0, w.t_mid, w.t_ref, w.t_sft, w.v, w.arms, w.first_bin,
+                                  w.n_bins, w.injections)
+    n0, n1, ns = w.f0.size, w.f1.size, w.sky.shape[0]
+    n_sub = len(w.sub_edges) - 1
+    stats = torch.empty(n0 * n1 * ns, dtype=torch.float32, device=dev)
+    with ft.Context(0, torch.cuda.current_stream().cuda_stream) as c:
+        c.set_sfts(w.n_sft_per_det, torch.from_numpy(w.t_mid).to(dev), w.t_sft, w.first_bin,
+                   torch.from_numpy(table).to(dev))
+        c.set_velocities(torch.from_numpy(w.v).to(dev))
+        c.set_arms(torch.from_numpy(w.arms).to(dev))
+        c.eval_templates(w.f0, w.f1, w.sky, w.t_ref, w.k, w.sub_edges, stats=stats,
+                         statistic=ft.FT_STAT_NUMBER_COUNT, weights=ft.FT_WEIGHTS_SKY)
+        tops = [c.toplist(j, w.k) for j in range(n_sub)]
+        info = c.info()
+    print("tile", ft.ft_tile_name(info.tile), "eval ms", info.eval_ms, flush=True)
+    rng = np.random.default_rng(6)
+    sample = rng.choice(n0 * n1 * ns, 3000, replace=False)
+    members = np.array([t.index for top in tops for t in top], dtype=np.int64)
+    idx = np.concatenate([sample, members])
+    i, j, s = idx % n0, (idx // n0) % n1, idx // (n0 * n1)
+    W = ow.sky_weights(w.arms, None, w.sky[s])
+    ind = ow.number_count_table(table)
+    S = ow.weighted_sums(w.t_mid, w.t_ref, w.t_sft, w.first_bin, ind, W, w.v, w.f0[i], w.f1[j], w.sky[s])
+    s32 = stats[torch.from_numpy(idx).to(dev)].cpu().numpy().astype(np.float64)
+    e = 44 * 2.0 ** -24 + 4 * w.n_sft * 2.0 ** -53
+    assert np.all(np.abs(s32 - S) <= e * S + 1e-13)
+    exact = dict(zip(idx.tolist(), S.tolist()))
+    wrow = dict(zip(idx.tolist(), range(idx.size)))
+    thr = []
+    for jsub, top in enumerate(tops):
+        assert len(top) == w.k
+        for t in top:
+            assert abs(t.s64 - exact[t.index]) <= 1e-13 * exact[t.index]
+            mu, sig = ow.nc_moments(W[wrow[t.index]])
+            assert abs(t.z - (exact[t.index] - mu) / sig) <= 1e-9
+        keys = [(-t.s64, t.index) for t in top]
+        assert keys == sorted(keys)
+        thr.append(top[-1].s64)
+    member_set = set(members.tolist())
+    sub_of = np.searchsorted(w.sub_edges, w.f0[i[:len(sample)]], side="right") - 1
+    for q, t in enumerate(sample.tolist()):
+        jsub = int(sub_of[q])
+        if t in member_set or not 0 <= jsub < n_sub:
+            continue
+        assert exact[t] <= thr[jsub] * (1 + 1e-13)
+    Sg = stats.view(ns * n1, n0)
+    for jsub, top in enumerate(tops):
+        lo = int(np.searchsorted(w.f0, w.sub_edges[jsub], side="left"))
+        hi = int(np.searchsorted(w.f0, w.sub_edges[jsub + 1], side="left"))
+        block = Sg[:, lo:hi].clone()
+        rows = torch.tensor([t.index // n0 for t in top], device=dev)
+        cols = torch.tensor([t.index % n0 - lo for t in top], device=dev)
+        block[rows, cols] = -float("inf")
+        assert block.max().item() <= thr[jsub] * (1 + e)
+        del block
