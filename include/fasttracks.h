@@ -287,6 +287,17 @@ ft_status ft_gen_binary_bank(ft_ctx ctx, const ft_binary_region *region, uint64_
                              double *phib);
 
 /*
+ * ft_binary_cos_mode -- how BINARY evaluations estimate the orbital cosine
+ * before the guard (the bins are the canonical ones either way).  mode 0
+ * (default): the hardware cosine v_cos_f32 when its error, measured on first
+ * use over every float in [0, 1] against the library cosine, is at most 1e-4
+ * (the guard margin includes it); mode 1: a single-precision Taylor polynomial
+ * with a fixed bound.  *hw_err (may be NULL) receives the measured error.
+ * Errors: FT_E_INVALID (mode).
+ */
+ft_status ft_binary_cos_mode(ft_ctx ctx, int32_t mode, double *hw_err);
+
+/*
  * ft_eval_binary_random -- generate templates 0 .. n-1 of the random bank on
  * the device (as ft_gen_binary_bank) and evaluate them as a BINARY bank with
  * `opts` (the paper's timed pipeline: template generation, bins, gathers,

@@ -50,6 +50,12 @@ struct ft_ctx_s {
     size_t cap_sky_norm = 0, cap_sky_ms = 0;
     double *d_top_nc = nullptr;  // ft_toplist_number_count staging
     size_t cap_top_nc = 0;
+    // binary-track estimate: measured error of the hardware cosine (-1: not yet
+    // measured) and the mode (0 auto, 1 library polynomial)
+    double hw_cos_err = -1.0;
+    int32_t cos_mode = 0;
+    unsigned long long *d_cos_err = nullptr;
+    size_t cap_cos_err = 0;
     // hyperbox search (ft_eval_binary_boxes)
     int32_t *d_box = nullptr, *d_bcount = nullptr;
     uint32_t *d_bmax32 = nullptr, *d_bncand = nullptr;
@@ -481,6 +487,7 @@ void ft_destroy(ft_ctx c)
     release(&c->d_sky_norm, &c->cap_sky_norm);
     release(&c->d_sky_ms, &c->cap_sky_ms);
     release(&c->d_top_nc, &c->cap_top_nc);
+    release(&c->d_cos_err, &c->cap_cos_err);
     release(&c->d_box, &c->cap_box);
     release(&c->d_bcount, &c->cap_bcount);
     release(&c->d_bmax32, &c->cap_bmax32);
@@ -937,6 +944,41 @@ static WindowPlan plan_window(const double *f0, int64_t n0, const double *f1, in
     return wp;
 }
 
+// Largest hardware-cosine error accepted for the binary-track estimate (the
+// guard margin grows with it; beyond this the polynomial estimate is used).
+constexpr double kHwCosMaxErr = 1e-4;
+
+// The cosine bound of binary runs: measured once per context (every float in
+// [0, 1] through v_cos_f32 against the library cosine, a few milliseconds),
+// then delta = err + 2.1e-7 (phase roundings); 0 selects the polynomial.
+static ft_status binary_cos_delta(ft_ctx c, double &delta)
+{
+    delta = 0.0;
+    if (c->cos_mode == 1) return FT_OK;
+    if (c->hw_cos_err < 0.0) {
+        hipError_t e = ensure(&c->d_cos_err, &c->cap_cos_err, 1);
+        unsigned long long bits = 0;
+        if (e == hipSuccess) e = launch_hw_cos_error(c->d_cos_err, c->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(&bits, c->d_cos_err, sizeof bits, hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "measure the hardware cosine");
+        double err;
+        memcpy(&err, &bits, sizeof err);
+        c->hw_cos_err = is_finite(err) ? err : 1e300;
+    }
+    if (c->hw_cos_err <= kHwCosMaxErr) delta = c->hw_cos_err * (1.0 + 1e-3) + 2.1e-7;
+    return FT_OK;
+}
+
+// Every canonical bin of f0 (1 + v.n - a_p Omega cos) lies within
+// f0 (1 -+ (vmax + aw)) T + 1/2 (a bin of margin each side for roundings).
+static bool binary_range_ok(ft_ctx c, double f0_lo, double f0_hi, double aw_max)
+{
+    const double lo = std::floor(f0_lo * (1.0 - c->vmax - aw_max) * c->t_sft + 0.5) - 2.0;
+    const double hi = std::floor(f0_hi * (1.0 + c->vmax + aw_max) * c->t_sft + 0.5) + 2.0;
+    return lo >= (double)c->first_bin && hi < (double)c->first_bin + (double)c->n_bins;
+}
+
 static ft_status prepare_bank(ft_ctx c, const ft_bank *bank, double t_ref, EvalRun &run,
                               bool &grid, int64_t &n_t)
 {
@@ -1035,6 +1077,12 @@ static ft_status prepare_bank(ft_ctx c, const ft_bank *bank, double t_ref, EvalR
     }
     const double x_max = (f0_max + c_max) * (1.0 + c->vmax + aw_max) * c->t_sft;
     if (!(x_max < 2147483000.0)) return fail(c, FT_E_UNSUPPORTED, "track frequencies above 2^31/T_sft");
+    bool bin_range_ok = false;
+    if (binary) {
+        bin_range_ok = true;
+        for (int64_t t = 0; t < n0 && bin_range_ok; ++t)
+            bin_range_ok = binary_range_ok(c, c->f0_h[t], c->f0_h[t], c->ap_h[t] * c->omega_h[t]);
+    }
 
     // upload
     if ((e = ensure(&c->d_f0, &c->cap_f0, (size_t)n0)) != hipSuccess ||
@@ -1097,6 +1145,11 @@ static ft_status prepare_bank(ft_ctx c, const ft_bank *bank, double t_ref, EvalR
     run.n_list = grid ? 0 : n0;
     run.t_sft = c->t_sft;
     run.vmax = c->vmax;
+    if (binary) {
+        ft_status stc = binary_cos_delta(c, run.cos_delta);
+        if (stc != FT_OK) return stc;
+        run.range_ok = bin_range_ok ? 1 : 0;
+    }
     // bounds used by the grid kernel
     if (grid) guard_params(c->f0_h.data(), n0, f0_max, x_max, c->vmax, c->t_sft, run.dT, run.eta);
     (void)dt_min;
@@ -1481,6 +1534,9 @@ static ft_status binary_random_run(ft_ctx c, const ft_binary_region *reg, uint64
     run.vmax = c->vmax;
     run.sum_mode = opts->sum_mode;
     run.precision = opts->precision;
+    st = binary_cos_delta(c, run.cos_delta);
+    if (st != FT_OK) return st;
+    run.range_ok = binary_range_ok(c, reg->f0_lo, reg->f0_hi, reg->ap_hi * reg->omega_hi) ? 1 : 0;
     return apply_stat_weights(c, opts, false, 0, run);
 }
 
@@ -1610,6 +1666,21 @@ ft_status ft_toplist(ft_ctx c, int32_t sub, ft_candidate *out, int32_t *n_out)
         e = hipMemcpy(out, c->d_out + (size_t)sub * c->last_k, (size_t)n * sizeof(ft_candidate), hipMemcpyDefault);
     if (e != hipSuccess) return hip_fail(c, e, "copy toplist");
     *n_out = n;
+    return FT_OK;
+}
+
+ft_status ft_binary_cos_mode(ft_ctx c, int32_t mode, double *hw_err)
+{
+    if (!c) return FT_E_INVALID;
+    c->err.clear();
+    if (mode != 0 && mode != 1) return fail(c, FT_E_INVALID, "mode must be 0 (auto) or 1 (library polynomial)");
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, FT_E_DEVICE, "hipSetDevice");
+    c->cos_mode = 0;
+    double delta;
+    ft_status st = binary_cos_delta(c, delta);  // measures once
+    c->cos_mode = mode;
+    if (st != FT_OK) return st;
+    if (hw_err) *hw_err = c->hw_cos_err;
     return FT_OK;
 }
 

@@ -393,7 +393,19 @@ __device__ __forceinline__ float binary_cos_estimate(double y)
 struct BinaryLane {
     double f0, f0T, f0T_half, nx, ny, nz, aw, omega, phib, om_pi, phib_pi, eps;
     float nxf, nyf, nzf, awf;
+    // hardware-cosine form: phase in revolutions, pre-scaled track terms
+    double om_rev, phib_rev;
+    float Fx, Fy, Fz, Cw, Af, thr;
+    int32_t off_base;  // 4 (Ai - first_bin)
 };
+
+// Canonical bin of a binary template (the rare guard fallback).
+__device__ __forceinline__ int binary_canonical(const EvalRun &r, const BinaryLane &p, int k, double dt)
+{
+    const auto *vk = as_const(r.v + 3 * (int64_t)k);
+    const double g = doppler_factor(vk[0], vk[1], vk[2], p.nx, p.ny, p.nz);
+    return bin_binary(p.f0, g, p.aw, p.omega, p.phib, dt, r.t_sft);
+}
 
 // Byte offset of the canonical bin of one binary template in row k (clamped
 // into the row and flagged when the track leaves the table).
@@ -407,11 +419,7 @@ __device__ __forceinline__ uint32_t binary_offset(const EvalRun &r, const Binary
     const double u = fma(p.f0T, (double)w, p.f0T_half);
     const double fr = __builtin_amdgcn_fract(u);
     int B = (int)u;
-    if (!(fr > p.eps && fr < 1.0 - p.eps)) {
-        const auto *vk = as_const(r.v + 3 * (int64_t)k);
-        const double g = doppler_factor(vk[0], vk[1], vk[2], p.nx, p.ny, p.nz);
-        B = bin_binary(p.f0, g, p.aw, p.omega, p.phib, dt, r.t_sft);
-    }
+    if (!(fr > p.eps && fr < 1.0 - p.eps)) B = binary_canonical(r, p, k, dt);
     int b = B - r.first_bin;
     if (b < 0 || b >= r.n_bins) {
         bad = true;
@@ -420,11 +428,54 @@ __device__ __forceinline__ uint32_t binary_offset(const EvalRun &r, const Binary
     return (uint32_t)b * 4u;
 }
 
+// Hardware-cosine form of the estimate.  The phase in revolutions
+// x = (Omega/2pi) dt - phi_b/2pi is reduced in FP64 (fract) and rounded to
+// float (< 2^-25 rev), and c = v_cos_f32(x) = cos 2 pi x, whose error over every
+// float in [0, 1] the library measures on the device (delta_hw); with the
+// phase rounding and the canonical phase's own rounding the cosine is within
+// delta = delta_hw + 2.1e-7 of the canonical one.  The track, shifted by eps
+// and relative to the integer Ai, is four single-precision fused steps:
+//   U = Af + Cw c + Fx vx + Fy vy + Fz vz,
+// Cw = -f0 T a_p Omega, F = f0 T n, Af = (f0 T + 1/2 - eps) - Ai in [0, 1),
+// all rounded to float, v rounded to float.  Against the canonical
+// x + 1/2 - eps - Ai the error is below
+//   f0 T a_p Omega delta + 2^-24 (5 f0 T a_p Omega + 6 f0 T |v|max + 4) + 2^-25,
+// which eps (twice that, plus 1e-7) covers.  So when fract(U) < 1 - 2 eps the
+// canonical bin is Ai + floor(U); otherwise (about once per 3*10^4
+// evaluations) the canonical bin is formed in FP64.  RANGE: the host has not
+// proved that every track stays in the table, so each bin is checked.
+template <bool RANGE>
+__device__ __forceinline__ uint32_t binary_offset_hw(const EvalRun &r, const BinaryLane &p, int k, bool &bad)
+{
+    const auto *v32 = as_const(r.v32 + 3 * (int64_t)k);
+    const double dt = as_const(r.dt)[k];
+    const float x = (float)__builtin_amdgcn_fract(fma(p.om_rev, dt, -p.phib_rev));
+    const float c = __builtin_amdgcn_cosf(x);
+    float U = __builtin_fmaf(p.Cw, c, p.Af);
+    U = __builtin_fmaf(p.Fx, v32[0], U);
+    U = __builtin_fmaf(p.Fy, v32[1], U);
+    U = __builtin_fmaf(p.Fz, v32[2], U);
+    const float fr = __builtin_amdgcn_fractf(U);
+    int off;
+    if (fr < p.thr) {
+        off = (int)(U - fr) * 4 + p.off_base;
+    } else {
+        off = (binary_canonical(r, p, k, dt) - r.first_bin) * 4;
+    }
+    if (RANGE && !(off >= 0 && off < r.n_bins * 4)) {
+        bad = true;
+        off = min(max(off, 0), (r.n_bins - 1) * 4);
+    }
+    return (uint32_t)off;
+}
+
 __device__ __forceinline__ float binary_gather(const EvalRun &r, int k, uint32_t off)
 {
     return *(global_float *)((const char *)(r.power_w + (int64_t)k * r.n_bins) + off);
 }
 
+// HW: the hardware-cosine estimate (r.cos_delta > 0), else the polynomial one.
+template <bool HW, bool RANGE>
 __global__ __launch_bounds__(256) void eval_binary_kernel(EvalRun r)
 {
     const int64_t n = r.n_list;
@@ -443,14 +494,35 @@ __global__ __launch_bounds__(256) void eval_binary_kernel(EvalRun r)
         p.phib = r.phib[t];
         p.aw = r.ap[t] * p.omega;
         p.f0T = p.f0 * r.t_sft;
-        p.f0T_half = p.f0T + 0.5;
-        p.om_pi = p.omega * 0x1.45f306dc9c883p-2;   // 1/pi
-        p.phib_pi = p.phib * 0x1.45f306dc9c883p-2;
-        p.nxf = (float)p.nx;
-        p.nyf = (float)p.ny;
-        p.nzf = (float)p.nz;
-        p.awf = (float)p.aw;
-        p.eps = p.f0T * (p.aw * BINARY_COS_DELTA + 8.0 * 0x1p-24 * (2.0 * r.vmax + p.aw)) + 1e-9;
+        if (HW) {
+            const double delta = r.cos_delta;
+            const double e = 2.0 * (p.f0T * p.aw * delta +
+                                    0x1p-24 * (5.0 * p.f0T * p.aw + 6.0 * p.f0T * r.vmax + 4.0) + 0x1p-25) +
+                             1e-7;
+            const double a = (p.f0T + 0.5) - e;
+            const double ai = floor(a);
+            p.om_rev = p.omega * 0x1.45f306dc9c883p-3;  // 1/(2 pi)
+            p.phib_rev = p.phib * 0x1.45f306dc9c883p-3;
+            p.Fx = (float)(p.f0T * p.nx);
+            p.Fy = (float)(p.f0T * p.ny);
+            p.Fz = (float)(p.f0T * p.nz);
+            p.Cw = (float)(-(p.f0T * p.aw));
+            p.Af = (float)(a - ai);
+            p.thr = (float)(1.0 - 2.0 * e) - 0x1p-23f;
+            p.off_base = ((int)ai - r.first_bin) * 4;
+        } else {
+            p.f0T_half = p.f0T + 0.5;
+            p.om_pi = p.omega * 0x1.45f306dc9c883p-2;   // 1/pi
+            p.phib_pi = p.phib * 0x1.45f306dc9c883p-2;
+            p.nxf = (float)p.nx;
+            p.nyf = (float)p.ny;
+            p.nzf = (float)p.nz;
+            p.awf = (float)p.aw;
+            p.eps = p.f0T * (p.aw * BINARY_COS_DELTA + 8.0 * 0x1p-24 * (2.0 * r.vmax + p.aw)) + 1e-9;
+        }
+        auto offset = [&](int k, bool &bad) {
+            return HW ? binary_offset_hw<RANGE>(r, p, k, bad) : binary_offset(r, p, k, bad);
+        };
         float acc = 0.f;
         double tot = 0.0;
         bool bad = false;
@@ -458,15 +530,15 @@ __global__ __launch_bounds__(256) void eval_binary_kernel(EvalRun r)
         // value of SFT k is added (reads past the last SFT re-read it, unused);
         // blocks of SUM_BLOCK SFTs (even) are walked in pairs, so va holds the
         // next block's first SFT when a block ends.
-        float va = binary_gather(r, 0, binary_offset(r, p, 0, bad));
+        float va = binary_gather(r, 0, offset(0, bad));
         for (int kb = 0; kb < n_sft; kb += SUM_BLOCK) {
             const int ke = min(kb + SUM_BLOCK, n_sft);
             int k = kb;
             for (; k + 1 < ke; k += 2) {
-                const float vb = binary_gather(r, k + 1, binary_offset(r, p, k + 1, bad));
+                const float vb = binary_gather(r, k + 1, offset(k + 1, bad));
                 acc += va;
                 const int k2 = min(k + 2, n_sft - 1);
-                va = binary_gather(r, k2, binary_offset(r, p, k2, bad));
+                va = binary_gather(r, k2, offset(k2, bad));
                 acc += vb;
             }
             if (k < ke) acc += va;  // odd tail: k = n_sft - 1
@@ -478,6 +550,24 @@ __global__ __launch_bounds__(256) void eval_binary_kernel(EvalRun r)
         if (bad && live) atomicOr(r.err, ERR_RANGE);
         if (live) r.stats[t] = (float)(tot + (double)acc);
     }
+}
+
+// Largest error of the hardware cosine over every float x in [0, 1]:
+// |v_cos_f32(x) - cos 2 pi x|, the reference from the library cosine of the
+// FP64 product 2 pi x (within 1e-15).  The maximum of non-negative doubles is
+// taken on their bit patterns.
+__global__ __launch_bounds__(256) void hw_cos_error_kernel(unsigned long long *max_bits)
+{
+    double worst = 0.0;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i <= 0x3F800000u; i += gridDim.x * blockDim.x) {
+        const float x = __uint_as_float(i);
+        double sv, cv;
+        lib_sincos((double)x * 0x1.921fb54442d18p+2, sv, cv);  // 2 pi x
+        worst = fmax(worst, fabs((double)__builtin_amdgcn_cosf(x) - cv));
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) worst = fmax(worst, __shfl_xor(worst, o, 64));
+    if ((threadIdx.x & 63) == 0) atomicMax(max_bits, (unsigned long long)__double_as_longlong(worst));
 }
 
 // The library cosine and sine of an array (exposed for callers that
@@ -576,6 +666,13 @@ __global__ void weight_table_kernel(const float *power, const float *weight, flo
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n_rows * n_cols;
          q += (int64_t)gridDim.x * blockDim.x)
         out[q] = power[q] * weight[q / n_cols];
+}
+
+__global__ void fill_u64_kernel(unsigned long long *p, unsigned long long value, int64_t n)
+{
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
+         q += (int64_t)gridDim.x * blockDim.x)
+        p[q] = value;
 }
 
 __global__ void fill_u32_kernel(uint32_t *p, uint32_t value, int64_t n)
@@ -732,7 +829,20 @@ hipError_t launch_eval_list(const EvalRun &run, hipStream_t s)
 hipError_t launch_eval_binary(const EvalRun &run, hipStream_t s)
 {
     if (run.n_list <= 0) return hipSuccess;
-    hipLaunchKernelGGL(eval_binary_kernel, dim3(grid_for(run.n_list, 256, (1u << 16))), dim3(256), 0, s, run);
+    const dim3 grid(grid_for(run.n_list, 256, (1u << 16)));
+    if (run.cos_delta > 0.0) {
+        if (run.range_ok) hipLaunchKernelGGL((eval_binary_kernel<true, false>), grid, dim3(256), 0, s, run);
+        else hipLaunchKernelGGL((eval_binary_kernel<true, true>), grid, dim3(256), 0, s, run);
+    } else {
+        hipLaunchKernelGGL((eval_binary_kernel<false, true>), grid, dim3(256), 0, s, run);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_hw_cos_error(unsigned long long *max_bits, hipStream_t s)
+{
+    hipLaunchKernelGGL(fill_u64_kernel, dim3(1), dim3(64), 0, s, max_bits, 0ull, (int64_t)1);
+    hipLaunchKernelGGL(hw_cos_error_kernel, dim3(4096), dim3(256), 0, s, max_bits);
     return hipGetLastError();
 }
 

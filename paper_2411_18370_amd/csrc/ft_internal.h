@@ -160,6 +160,9 @@ struct EvalRun {
     int64_t n_list;
     double t_sft;
     double vmax;          // max |v_k| (binary-track estimate bound)
+    double cos_delta;     // binary banks: bound of the hardware-cosine estimate (> 0 selects it; else
+                          // the polynomial estimate)
+    int32_t range_ok;     // binary banks: every track is proved to stay in the table (no per-bin check)
     double dT;            // grid spacing * T_sft (run guard)
     double eta;           // run-guard margin in bins
     int32_t wt;           // LDS window width per SFT (bins, including run padding)
@@ -204,6 +207,9 @@ hipError_t launch_labels(const double *max_z, int n_runs, double tau, uint8_t *l
 hipError_t launch_eval_list(const EvalRun &run, hipStream_t s);
 // Binary-system list bank (run.ap/omega/phib set): one lane per template.
 hipError_t launch_eval_binary(const EvalRun &run, hipStream_t s);
+// Largest |v_cos_f32(x) - cos 2 pi x| over every float x in [0, 1], as the bit
+// pattern of a non-negative double in *max_bits (device memory).
+hipError_t launch_hw_cos_error(unsigned long long *max_bits, hipStream_t s);
 // The library cosine/sine of x[0..n) into c[], s[] (device arrays).
 hipError_t launch_lib_sincos(const double *x, int64_t n, double *c, double *s, hipStream_t st);
 hipError_t launch_eval_grid_direct(const EvalRun &run, hipStream_t s);

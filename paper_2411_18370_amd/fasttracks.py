@@ -128,7 +128,7 @@ EXPORTS = ("ft_create", "ft_destroy", "ft_last_error", "ft_status_string", "ft_s
            "ft_batch_replay", "ft_batch_time", "ft_mlp_create", "ft_mlp_destroy",
            "ft_mlp_get_params", "ft_mlp_predict", "ft_mlp_loss_grad", "ft_mlp_train",
            "ft_tune_report", "ft_tune_clear", "ft_probe_lds_gather", "ft_set_arms",
-           "ft_toplist_number_count", "ft_eval_binary_boxes")
+           "ft_toplist_number_count", "ft_eval_binary_boxes", "ft_binary_cos_mode")
 
 
 def load(path: str = LIB_PATH):
@@ -181,6 +181,7 @@ def load(path: str = LIB_PATH):
         "ft_tune_clear": (C.c_int, [P]),
         "ft_probe_lds_gather": (C.c_int, [P, i32, i32, C.POINTER(f64)]),
         "ft_set_arms": (C.c_int, [P, P]),
+        "ft_binary_cos_mode": (C.c_int, [P, i32, C.POINTER(f64)]),
         "ft_eval_binary_boxes": (C.c_int, [P, C.POINTER(ft_binary_region), C.c_uint64, i64, f64,
                                            C.POINTER(ft_box_partition), C.POINTER(ft_eval_opts), P, P]),
         "ft_toplist_number_count": (C.c_int, [P, i32, P, P, C.POINTER(i32)]),
@@ -429,6 +430,14 @@ def ft_toplist_number_count(ctx, sub, k):
     _check(ctx, load().ft_toplist_number_count(ctx, sub, out.ctypes.data_as(C.c_void_p),
                                                z.ctypes.data_as(C.c_void_p), C.byref(n)))
     return out[:n.value].copy(), z[:n.value].copy()
+
+
+def ft_binary_cos_mode(ctx, mode):
+    """Set the binary-track cosine estimate (0 auto/hardware, 1 polynomial);
+    returns the measured error of the hardware cosine."""
+    err = C.c_double()
+    _check(ctx, load().ft_binary_cos_mode(ctx, int(mode), C.byref(err)))
+    return err.value
 
 
 def ft_set_arms(ctx, arms):
@@ -686,6 +695,9 @@ class Context:
 
     def set_arms(self, arms):
         ft_set_arms(self.ctx, arms)
+
+    def binary_cos_mode(self, mode):
+        return ft_binary_cos_mode(self.ctx, mode)
 
     def toplist_number_count(self, sub, k):
         return ft_toplist_number_count(self.ctx, sub, k)

@@ -70,6 +70,7 @@ def test_null_arguments_are_rejected_without_a_device():
     assert lib.ft_gen_binary_bank(None, None, 0, 0, 0, None, None, None, None, None) == ft.FT_E_INVALID
     assert lib.ft_eval_binary_random(None, None, 0, 0, 0.0, None, None) == ft.FT_E_INVALID
     assert lib.ft_set_arms(None, None) == ft.FT_E_INVALID
+    assert lib.ft_binary_cos_mode(None, 0, None) == ft.FT_E_INVALID
     assert lib.ft_eval_binary_boxes(None, None, 0, 0, 0.0, None, None, None, None) == ft.FT_E_INVALID
     assert lib.ft_toplist_number_count(None, 0, None, None, None) == ft.FT_E_INVALID
     assert C.sizeof(ft.ft_binary_region) == 96

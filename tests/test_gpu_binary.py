@@ -64,9 +64,11 @@ def _check_toplists(ft, c, w, s64, k, f0, stats=None):
         assert rel.max() <= rel_bound(w.n_sft)
 
 
+@pytest.mark.parametrize("cos_mode", [0, 1])
 @pytest.mark.parametrize("n_tmpl,n_per_det,trim", [(5000, 300, 0), (777, 61, 1), (300, 7, 1)])
-def test_binary_bank_toplists_match_oracle(ft, n_tmpl, n_per_det, trim):
-    """Ragged template counts and SFT counts (odd, and below one 32-SFT sum block)."""
+def test_binary_bank_toplists_match_oracle(ft, n_tmpl, n_per_det, trim, cos_mode):
+    """Ragged template counts and SFT counts (odd, and below one 32-SFT sum block),
+    with the hardware-cosine and the polynomial track estimates."""
     import torch
     w = synth.binary_band(seed=22, n_tmpl=n_tmpl, n_per_det=n_per_det)
     if trim:
@@ -78,6 +80,7 @@ def test_binary_bank_toplists_match_oracle(ft, n_tmpl, n_per_det, trim):
     k = 25
     stats = torch.empty(n_tmpl, dtype=torch.float32, device="cuda")
     with _ctx(ft, w) as c:
+        c.binary_cos_mode(cos_mode)
         c.eval_binary(w.f0, w.sky, w.ap, w.omega, w.phib, w.t_ref, k, w.sub_edges, stats=stats)
         c.sync()  # the library may run on its own stream
         _check_toplists(ft, c, w, s64, k, w.f0, stats.cpu().numpy())
@@ -88,7 +91,8 @@ def test_binary_bank_toplists_match_oracle(ft, n_tmpl, n_per_det, trim):
             list(oracle.toplist(s64, oracle.subband(w.f0, w.sub_edges), len(w.sub_edges) - 1, k)[0])
 
 
-def test_random_bank_is_bitexact_and_evaluates_like_the_explicit_bank(ft):
+@pytest.mark.parametrize("cos_mode", [0, 1])
+def test_random_bank_is_bitexact_and_evaluates_like_the_explicit_bank(ft, cos_mode):
     w = synth.binary_band(seed=23, n_tmpl=1, n_per_det=250)
     n, seed, k = 6000, 12345, 20
     f0, sky, ap, om, pb = obank.random_binary_bank(seed, 0, n, **w.region)
@@ -110,10 +114,25 @@ def test_random_bank_is_bitexact_and_evaluates_like_the_explicit_bank(ft):
             assert np.array_equal(a.view(np.uint64), b.view(np.uint64))
         assert np.all((gb[1][:, 2] >= -0.2) & (gb[1][:, 2] <= 0.05))
         assert np.all((gb[4] >= -2.0) & (gb[4] <= 3.5))
+        c.binary_cos_mode(cos_mode)
         c.eval_binary_random(w.region, seed, n, w.t_ref, k, w.sub_edges)
         _check_toplists(ft, c, w, s64, k, f0)
         c.eval_binary(f0, sky, ap, om, pb, w.t_ref, k, w.sub_edges)
         _check_toplists(ft, c, w, s64, k, f0)
+
+
+def test_hardware_cosine_bound(ft):
+    """The error of v_cos_f32 over every float in [0, 1] is measured once per
+    context; it is small enough for the estimate, and mode 1 switches to the
+    polynomial (the bins are canonical either way)."""
+    w = synth.binary_band(seed=25, n_tmpl=50, n_per_det=20)
+    with _ctx(ft, w) as c:
+        err = c.binary_cos_mode(0)
+        print("hardware cosine max error over [0, 1]:", err, flush=True)
+        assert 0.0 < err < 1e-4
+        assert c.binary_cos_mode(1) == err
+        with pytest.raises(ft.FtError):
+            c.binary_cos_mode(2)
 
 
 def test_binary_range_and_argument_errors(ft):
