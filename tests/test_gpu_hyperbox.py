@@ -94,3 +94,45 @@ def test_box_errors(ft):
             c.eval_binary_boxes(reg, 1, 100, b.t_ref, (2, 1, 1, 1, 1, 1), statistic=5)
     finally:
         c.close()
+
+
+def test_box_search_at_benchmark_size(ft):
+    """The bench's box search: 10^8 templates (o = 3.44, full sky and phase) in at
+    least 10^4 boxes, 2 x 5000 SFTs.  The oracle cannot enumerate every box at this
+    size, so it checks sampled boxes and templates one by one: each winner lies in
+    its box and its S64 is the oracle's bit for bit; every sampled template's S64 is
+    at most its box's maximum (and not a lower-index tie); counts add up to n."""
+    from paper_2411_18370_amd import hyperbox, mismatch
+    b = synth.binary_band(seed=3, n_tmpl=1, n_per_det=5000)
+    t_obs = float(b.t_mid.max() - b.t_mid.min() + b.t_sft)
+    vmax = float(np.max(np.linalg.norm(b.v, axis=1)))
+    reg = _region(b)
+    per_f06 = mismatch.n_templates(reg, b.t_sft, t_obs, vmax) / (reg["f0_hi"] ** 6 - reg["f0_lo"] ** 6)
+    n, o, seed = 10 ** 8, 3.44, 7
+    reg["f0_hi"] = (reg["f0_lo"] ** 6 + n / (o * per_f06)) ** (1.0 / 6.0)
+    n_div = hyperbox.partition(reg, b.t_sft, t_obs, vmax, o, n / 10_000, min_boxes=10_000)
+    n_boxes = int(np.prod(n_div))
+    c = _setup(ft, b)
+    try:
+        res = c.eval_binary_boxes(reg, seed, n, b.t_ref, n_div)
+    finally:
+        c.close()
+    assert n_boxes >= 10_000 and int(res["count"].sum()) == n
+    rng = np.random.default_rng(4)
+    boxes = rng.choice(np.flatnonzero(res["index"] >= 0), 600, replace=False)
+    winners = res["index"][boxes]
+    samples = rng.choice(n, 1500, replace=False)
+    idx = np.concatenate([winners, samples])
+    par = [np.concatenate(x) for x in zip(*[obank.random_binary_bank(seed, int(i), 1, **reg) for i in idx])]
+    s64, bad = oracle.eval_binary(b.t_mid, b.t_ref, b.t_sft, b.first_bin, b.power, None, b.v, par[0],
+                                  par[1].reshape(-1, 3), par[2], par[3], par[4])
+    assert bad == -1
+    box_of = np.array([obank.boxes(seed, int(i), 1, n_div)[0] for i in idx])
+    assert np.array_equal(box_of[:len(boxes)], boxes)
+    assert np.array_equal(s64[:len(boxes)], res["s64"][boxes])
+    N = b.t_mid.size
+    assert np.allclose(res["z"][boxes], (res["s64"][boxes] - 2.0 * N) / (2.0 * np.sqrt(N)), rtol=1e-12, atol=1e-12)
+    for q in range(len(boxes), idx.size):
+        bx, t = box_of[q], idx[q]
+        top, win = res["s64"][bx], res["index"][bx]
+        assert s64[q] < top or (s64[q] == top and t >= win)
