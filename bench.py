@@ -233,6 +233,18 @@ def bench_binary(ft, synth, log, sizes=(10 ** 5, 10 ** 6, 10 ** 7), reps=3):
         log("binary bank n=%d: kernel %.3g evals/s, whole call %.3g evals/s (%.3g s/template; "
             "paper's H100 fit %.3g)" % (n, e["evals_per_s_kernel"], e["evals_per_s_call"],
                                          e["s_per_template_call"], model))
+    # the all-sky weights of Sec. II.B on the largest batch (normalised per template)
+    n = sizes[-1]
+    c.set_arms(torch.from_numpy(w.arms).to(dev))
+    c.eval_binary_random(w.region, 99, n, w.t_ref, w.k, w.sub_edges, weights=ft.FT_WEIGHTS_SKY)
+    c.toplist(0, w.k)
+    ms = []
+    for r in range(reps):
+        c.eval_binary_random(w.region, 100 + r, n, w.t_ref, w.k, w.sub_edges, weights=ft.FT_WEIGHTS_SKY)
+        c.toplist(0, w.k)
+        ms.append(c.info().eval_ms)
+    out["sky_weights"] = {"n_templates": n, "evals_per_s_kernel": n * w.n_sft / (sum(ms) / reps * 1e-3)}
+    log("binary bank n=%d with all-sky weights: kernel %.3g evals/s" % (n, out["sky_weights"]["evals_per_s_kernel"]))
     c.close()
     return out
 

@@ -191,7 +191,8 @@ enum { FT_STAT_POWER = 0, FT_STAT_NUMBER_COUNT = 1 };
  * with c_k(n) = u_k (a_k^2(n) + b_k^2(n)) (u_k in the role of 1/S_n), a, b the
  * detector response functions at the SFT mid-time; a^2 + b^2 = F+^2 + Fx^2 for
  * any polarisation angle, F+ = D:e+, Fx = D:ex, D = (u u^T - w w^T)/2 from the
- * arms of ft_set_arms.  GRID banks only. */
+ * arms of ft_set_arms.  GRID banks (normalised per sky point) and BINARY
+ * banks (normalised per template); not LIST banks or the box search. */
 enum { FT_WEIGHTS_SFT = 0, FT_WEIGHTS_SKY = 1 };
 
 /* Noise-only moments of the statistics (z = (s - mu)/sigma), with
@@ -221,9 +222,9 @@ enum { FT_WEIGHTS_SFT = 0, FT_WEIGHTS_SKY = 1 };
  *              have a sky-weighted form (a tile id without one is an error)
  *   statistic  FT_STAT_POWER (default) or FT_STAT_NUMBER_COUNT; stats,
  *              toplists (s32, s64) and z are then of that statistic
- *   weights    FT_WEIGHTS_SFT (default) or FT_WEIGHTS_SKY (GRID banks, after
- *              ft_set_arms; the statistic is normalised by sum w = 1 per sky
- *              point and z uses the sky point's moments)
+ *   weights    FT_WEIGHTS_SFT (default) or FT_WEIGHTS_SKY (GRID and BINARY
+ *              banks, after ft_set_arms; the statistic is normalised by
+ *              sum w = 1 per sky point and z uses that point's moments)
  */
 typedef struct {
     int32_t precision;

@@ -85,6 +85,13 @@ def weighted_sums(t_mid, t_ref, t_sft, first_bin, table, weights, v, f0, f1, sky
     """S[t] = sum_k weights[t, k] table[k, B_tk] for templates t of a list bank
     (canonical bins of the oracle), sums sequential in SFT order in FP64."""
     bins = core.bins_list(t_mid, t_ref, t_sft, v, f0, f1, sky)
+    return weighted_sums_at(first_bin, table, weights, bins)
+
+
+def weighted_sums_at(first_bin, table, weights, bins):
+    """S[t] = sum_k weights[t, k] table[k, bins[t, k] - first_bin], sequential in
+    SFT order in FP64 (bins from any of the oracle's track models)."""
+    bins = np.asarray(bins, np.int64)
     tab = np.asarray(table, np.float32).astype(np.float64)
     cols = bins - int(first_bin)
     assert cols.min() >= 0 and cols.max() < tab.shape[1], "track leaves the table"

@@ -111,8 +111,8 @@ struct ft_ctx_s {
              *d_fill = nullptr;
     size_t cap_hist = 0, cap_state = 0, cap_cnt = 0, cap_off = 0, cap_fill = 0;
     int64_t *d_cand = nullptr;
-    double *d_cand_s64 = nullptr;
-    size_t cap_cand = 0, cap_cand_s64 = 0;
+    double *d_cand_s64 = nullptr, *d_cand_mom = nullptr;
+    size_t cap_cand = 0, cap_cand_s64 = 0, cap_cand_mom = 0;
     int32_t *d_seg = nullptr;
     size_t cap_seg = 0;
     ft_candidate *d_out = nullptr;
@@ -525,6 +525,7 @@ void ft_destroy(ft_ctx c)
     release(&c->d_fill, &c->cap_fill);
     release(&c->d_cand, &c->cap_cand);
     release(&c->d_cand_s64, &c->cap_cand_s64);
+    release(&c->d_cand_mom, &c->cap_cand_mom);
     release(&c->d_seg, &c->cap_seg);
     release(&c->d_out, &c->cap_out);
     release(&c->d_nout, &c->cap_nout);
@@ -1166,6 +1167,7 @@ static ft_status ensure_select(ft_ctx c, int n_seg, int k, int64_t n_seg_map, in
         (e = ensure(&c->d_fill, &c->cap_fill, (size_t)n_seg)) != hipSuccess ||
         (e = ensure(&c->d_cand, &c->cap_cand, (size_t)cap)) != hipSuccess ||
         (e = ensure(&c->d_cand_s64, &c->cap_cand_s64, (size_t)cap)) != hipSuccess ||
+        (e = ensure(&c->d_cand_mom, &c->cap_cand_mom, (size_t)cap * 2)) != hipSuccess ||
         (e = ensure(&c->d_seg, &c->cap_seg, (size_t)n_seg_map)) != hipSuccess ||
         (e = ensure(&c->d_out, &c->cap_out, (size_t)n_seg * k)) != hipSuccess ||
         (e = ensure(&c->d_nout, &c->cap_nout, (size_t)n_seg)) != hipSuccess)
@@ -1183,6 +1185,7 @@ static SelectBufs select_bufs(ft_ctx c, int64_t cap, int stat)
     b.fill = c->d_fill;
     b.cand = c->d_cand;
     b.cand_s64 = c->d_cand_s64;
+    b.cand_mom = c->d_cand_mom;
     b.seg_of_f0 = c->d_seg;
     b.out = c->d_out;
     b.n_out = c->d_nout;
@@ -1304,6 +1307,7 @@ static ft_status launch_eval_select(ft_ctx c, EvalRun &run, bool grid, int tile,
 // sky-dependent weights, the per-sky buffers the evaluation fills.
 static ft_status apply_stat_weights(ft_ctx c, const ft_eval_opts *opts, bool grid, int64_t n_sky, EvalRun &run)
 {
+    run.stat = opts->statistic;
     if (opts->statistic == FT_STAT_NUMBER_COUNT) {
         ft_status st = ensure_nc(c);
         if (st != FT_OK) return st;
@@ -1311,8 +1315,13 @@ static ft_status apply_stat_weights(ft_ctx c, const ft_eval_opts *opts, bool gri
         run.power_w = c->has_weight ? c->d_ind_w : c->d_ind;
     }
     if (opts->weights == FT_WEIGHTS_SKY) {
-        if (!grid) return fail(c, FT_E_UNSUPPORTED, "sky-dependent weights are available for GRID banks");
+        if (!grid && !run.ap)
+            return fail(c, FT_E_UNSUPPORTED, "sky-dependent weights are available for GRID and BINARY banks");
         if (!c->have_arms) return fail(c, FT_E_STATE, "sky-dependent weights need ft_set_arms");
+        if (!grid) {  // binary banks: weights normalised per template in the kernels
+            run.arms = c->d_arms;
+            return FT_OK;
+        }
         hipError_t e;
         if ((e = ensure(&c->d_sky_norm, &c->cap_sky_norm, (size_t)n_sky)) != hipSuccess ||
             (e = ensure(&c->d_sky_ms, &c->cap_sky_ms, (size_t)n_sky * 2)) != hipSuccess)
@@ -1420,7 +1429,7 @@ static ft_status launch_eval_select(ft_ctx c, EvalRun &run, bool grid, int tile,
     // sky-dependent weights: one more rounding per term (the factor)
     const double rel_err = (opts->sum_mode == FT_SUM_BLOCKED ? 40.0 * std::ldexp(1.0, -24) + 4.0 * N * std::ldexp(1.0, -53)
                                                              : (N + 8.0) * std::ldexp(1.0, -24) + 4.0 * N * std::ldexp(1.0, -53)) +
-                           (run.sky_norm ? 4.0 * std::ldexp(1.0, -24) : 0.0);
+                           (run.arms ? 4.0 * std::ldexp(1.0, -24) : 0.0);
     SelectBufs sb = select_bufs(c, cap, opts->statistic);
     if (e == hipSuccess) e = launch_select(run, grid, n_seg, k, rel_err, sb, c->stream);
     if (e == hipSuccess) e = launch_rescore_rank(run, grid, n_seg, k, sb, c->stream);
@@ -1565,6 +1574,8 @@ ft_status ft_eval_binary_boxes(ft_ctx c, const ft_binary_region *reg, uint64_t s
     ft_status st = check_stat_opts(c, opts);
     if (st != FT_OK) return st;
     if (!part || !out) return fail(c, FT_E_INVALID, "part and out must be non-null");
+    if (opts->weights != FT_WEIGHTS_SFT)
+        return fail(c, FT_E_UNSUPPORTED, "the box search uses per-SFT weights (one noise mean and spread for all boxes)");
     BoxDiv div;
     int64_t n_boxes = 1;
     for (int d = 0; d < 6; ++d) {

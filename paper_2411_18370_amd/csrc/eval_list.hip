@@ -475,7 +475,10 @@ __device__ __forceinline__ float binary_gather(const EvalRun &r, int k, uint32_t
 }
 
 // HW: the hardware-cosine estimate (r.cos_delta > 0), else the polynomial one.
-template <bool HW, bool RANGE>
+// SKYW: sky-dependent weights (Sec. II.B): the staged values u_k P are
+// multiplied by ab_k(n) (FP64, rounded to float) and the sum is divided at the
+// end by W1 = sum_k u_k ab_k (FP64, sequential in SFT order).
+template <bool HW, bool RANGE, bool SKYW>
 __global__ __launch_bounds__(256) void eval_binary_kernel(EvalRun r)
 {
     const int64_t n = r.n_list;
@@ -523,6 +526,14 @@ __global__ __launch_bounds__(256) void eval_binary_kernel(EvalRun r)
         auto offset = [&](int k, bool &bad) {
             return HW ? binary_offset_hw<RANGE>(r, p, k, bad) : binary_offset(r, p, k, bad);
         };
+        double w1 = 0.0;
+        // acc += value of SFT k (times its sky weight, which also enters W1)
+        auto add = [&](float acc_in, float v, int k) {
+            if (!SKYW) return acc_in + v;
+            const double ab = sky_ab(as_const(r.arms + 6 * (int64_t)k), p.nx, p.ny, p.nz);
+            w1 += (r.weight ? (double)as_const(r.weight)[k] : 1.0) * ab;
+            return __builtin_fmaf(v, (float)ab, acc_in);
+        };
         float acc = 0.f;
         double tot = 0.0;
         bool bad = false;
@@ -536,19 +547,24 @@ __global__ __launch_bounds__(256) void eval_binary_kernel(EvalRun r)
             int k = kb;
             for (; k + 1 < ke; k += 2) {
                 const float vb = binary_gather(r, k + 1, offset(k + 1, bad));
-                acc += va;
+                acc = add(acc, va, k);
                 const int k2 = min(k + 2, n_sft - 1);
                 va = binary_gather(r, k2, offset(k2, bad));
-                acc += vb;
+                acc = add(acc, vb, k + 1);
             }
-            if (k < ke) acc += va;  // odd tail: k = n_sft - 1
+            if (k < ke) acc = add(acc, va, k);  // odd tail: k = n_sft - 1
             if (r.sum_mode == FT_SUM_BLOCKED) {
                 tot += (double)acc;
                 acc = 0.f;
             }
         }
         if (bad && live) atomicOr(r.err, ERR_RANGE);
-        if (live) r.stats[t] = (float)(tot + (double)acc);
+        if (SKYW) {
+            if (!(w1 > 0.0) && live) atomicOr(r.err, ERR_BAD_POWER);
+            if (live) r.stats[t] = (float)((tot + (double)acc) / w1);
+        } else if (live) {
+            r.stats[t] = (float)(tot + (double)acc);
+        }
     }
 }
 
@@ -704,23 +720,6 @@ __global__ void batch_dt_kernel(const double *t_mid, const int32_t *sft_begin, c
     }
 }
 
-// exp(-1.6): the probability that a chi^2 variable with 2 degrees of freedom
-// (the noise-only normalised power) exceeds the number-count threshold 3.2.
-constexpr double NC_P = 0x1.9d7bebefb4e15p-3;
-
-// Noise-only (mu, sigma) of statistic `stat` from W1 = sum w, W2 = sum w^2:
-// power 2 W1, 2 sqrt(W2) (Sec. II.B.1); number count p W1, sqrt(p (1-p) W2).
-__device__ __forceinline__ void stat_moments(int stat, double w1, double w2, double *out)
-{
-    if (stat == FT_STAT_NUMBER_COUNT) {
-        out[0] = NC_P * w1;
-        out[1] = sqrt((NC_P * (1.0 - NC_P)) * w2);
-    } else {
-        out[0] = 2.0 * w1;
-        out[1] = 2.0 * sqrt(w2);
-    }
-}
-
 // Moments for per-SFT weights: one wavefront, lane l sums SFTs l, l + 64, ...
 // in order, then lane 0 adds the 64 partial sums in lane order (a fixed
 // order, so the result does not depend on scheduling).
@@ -830,11 +829,16 @@ hipError_t launch_eval_binary(const EvalRun &run, hipStream_t s)
 {
     if (run.n_list <= 0) return hipSuccess;
     const dim3 grid(grid_for(run.n_list, 256, (1u << 16)));
-    if (run.cos_delta > 0.0) {
-        if (run.range_ok) hipLaunchKernelGGL((eval_binary_kernel<true, false>), grid, dim3(256), 0, s, run);
-        else hipLaunchKernelGGL((eval_binary_kernel<true, true>), grid, dim3(256), 0, s, run);
+    const bool sky = run.arms != nullptr;
+    if (run.cos_delta > 0.0 && run.range_ok) {
+        if (sky) hipLaunchKernelGGL((eval_binary_kernel<true, false, true>), grid, dim3(256), 0, s, run);
+        else hipLaunchKernelGGL((eval_binary_kernel<true, false, false>), grid, dim3(256), 0, s, run);
+    } else if (run.cos_delta > 0.0) {
+        if (sky) hipLaunchKernelGGL((eval_binary_kernel<true, true, true>), grid, dim3(256), 0, s, run);
+        else hipLaunchKernelGGL((eval_binary_kernel<true, true, false>), grid, dim3(256), 0, s, run);
     } else {
-        hipLaunchKernelGGL((eval_binary_kernel<false, true>), grid, dim3(256), 0, s, run);
+        if (sky) hipLaunchKernelGGL((eval_binary_kernel<false, true, true>), grid, dim3(256), 0, s, run);
+        else hipLaunchKernelGGL((eval_binary_kernel<false, true, false>), grid, dim3(256), 0, s, run);
     }
     return hipGetLastError();
 }

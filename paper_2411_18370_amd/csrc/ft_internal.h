@@ -117,7 +117,9 @@ __device__ __forceinline__ int bin_binary(double f0, double g, double aw, double
 //   (1 - c^2) - (x^2 + y^2 - 2 c x y) + (x^2 - y^2)^2 / 4,
 // x = u.n, y = w.n, c = u.w (1 overhead, 1/4 along an arm, 2/5 on average).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double sky_ab(const double *arm, double nx, double ny, double nz)
+// (arm: any pointer type to six doubles, e.g. one into the scalar address space)
+template <typename ArmPtr>
+__device__ __forceinline__ double sky_ab(ArmPtr arm, double nx, double ny, double nz)
 {
     const double x = (arm[0] * nx + arm[1] * ny) + arm[2] * nz;
     const double y = (arm[3] * nx + arm[4] * ny) + arm[5] * nz;
@@ -130,6 +132,23 @@ __device__ __forceinline__ double sky_ab(const double *arm, double nx, double ny
 // Number-count threshold (Eq. number_count): P > 3.2 as real numbers, which for
 // FP32 P is P >= 3.2f (the float nearest 3.2 lies above it).
 constexpr float NC_THRESHOLD_F = 3.2f;
+
+// exp(-1.6): the probability that a chi^2 variable with 2 degrees of freedom
+// (the noise-only normalised power) exceeds the number-count threshold 3.2.
+constexpr double NC_P = 0x1.9d7bebefb4e15p-3;
+
+// Noise-only (mu, sigma) of statistic `stat` from W1 = sum w, W2 = sum w^2:
+// power 2 W1, 2 sqrt(W2) (Sec. II.B.1); number count p W1, sqrt(p (1-p) W2).
+__device__ __forceinline__ void stat_moments(int stat, double w1, double w2, double *out)
+{
+    if (stat == FT_STAT_NUMBER_COUNT) {
+        out[0] = NC_P * w1;
+        out[1] = sqrt((NC_P * (1.0 - NC_P)) * w2);
+    } else {
+        out[0] = 2.0 * w1;
+        out[1] = 2.0 * sqrt(w2);
+    }
+}
 
 // The data of one evaluation: an SFT set, its velocities and a grid bank.
 struct EvalRun {
@@ -151,6 +170,9 @@ struct EvalRun {
     const double *sky_norm;  // grid: [n_sky] 1 / sum_k u_k (a^2 + b^2)_k(n) per sky point
                              // (original order) -- the sky-dependent weights are on; else nullptr
     const double *sky_ms;    // grid with sky weights: [n_sky][2] (mu, sigma) of the statistic
+                             // (binary banks with sky weights: arms set, sky_norm null; the
+                             // weights are normalised per template)
+    int32_t stat;            // FT_STAT_* of the evaluation (moments of per-template weights)
     float *stats;         // [n_templates]
     uint32_t *err;        // error flags
     int32_t n_sft;
@@ -325,6 +347,7 @@ struct SelectBufs {
     uint32_t *fill;       // [n_seg]
     int64_t *cand;        // [cap]
     double *cand_s64;     // [cap]
+    double *cand_mom;     // [cap][2] sums of each candidate's weights and squared weights
     int32_t *seg_of_f0;   // grid [n_f0] or list [n]
     ft_candidate *out;    // [n_seg][k]
     int32_t *n_out;       // [n_seg]

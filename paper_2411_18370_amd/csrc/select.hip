@@ -238,7 +238,18 @@ __device__ __forceinline__ double rescore_one(const EvalRun &r, bool grid, int64
                                               double *w1 = nullptr, double *w2 = nullptr)
 {
     const TemplateParams tp = params_of(r, grid, t);
-    const double inv = grid && r.sky_norm ? r.sky_norm[t / ((int64_t)r.n_f0 * r.n_f1)] : 0.0;
+    // sky-dependent weights: 1 / sum_k u_k ab_k(n) of the template's sky point
+    // (grid: per sky point, precomputed; binary banks: per template, here)
+    const bool bsky = !grid && r.arms;
+    double inv = grid && r.sky_norm ? r.sky_norm[t / ((int64_t)r.n_f0 * r.n_f1)] : 0.0;
+    if (bsky) {
+        double part = 0.0;
+        for (int k = lane; k < r.n_sft; k += 64)
+            part += (r.weight ? (double)r.weight[k] : 1.0) * sky_ab(r.arms + 6 * (int64_t)k, tp.nx, tp.ny, tp.nz);
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
+        inv = 1.0 / part;
+    }
     double acc = 0.0, sw = 0.0, sw2 = 0.0;
     for (int k0 = 0; k0 < r.n_sft; k0 += 64) {
         const int k = k0 + lane;
@@ -254,7 +265,7 @@ __device__ __forceinline__ double rescore_one(const EvalRun &r, bool grid, int64
                 b = b < 0 ? 0 : r.n_bins - 1;
             }
             double w = r.weight ? (double)r.weight[k] : 1.0;
-            if (grid && r.sky_norm) w = w * (sky_ab(r.arms + 6 * (int64_t)k, tp.nx, tp.ny, tp.nz) * inv);
+            if ((grid && r.sky_norm) || bsky) w = w * (sky_ab(r.arms + 6 * (int64_t)k, tp.nx, tp.ny, tp.nz) * inv);
             val = w * (double)r.power[(int64_t)k * r.n_bins + b];
             wk = w;
         }
@@ -275,10 +286,11 @@ __device__ __forceinline__ double rescore_one(const EvalRun &r, bool grid, int64
     return acc;
 }
 
-// FP64 re-summation of the candidates, one wavefront per candidate.
+// FP64 re-summation of the candidates, one wavefront per candidate; with
+// mom, also each candidate's sums of weights and squared weights.
 __global__ __launch_bounds__(256) void rescore_kernel(EvalRun r, bool grid, const int64_t *cand,
                                                       const uint32_t *off, int n_seg,
-                                                      int64_t cap, double *s64)
+                                                      int64_t cap, double *s64, double *mom)
 {
     const int lane = threadIdx.x & 63;
     const int64_t total = min((int64_t)off[n_seg], cap);
@@ -286,8 +298,18 @@ __global__ __launch_bounds__(256) void rescore_kernel(EvalRun r, bool grid, cons
     uint32_t bad = 0;
     for (int64_t p = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); p < total;
          p += n_waves) {
-        const double acc = rescore_one<false>(r, grid, cand[p], lane, bad);
-        if (lane == 0) s64[p] = acc;
+        if (mom) {
+            double w1, w2;
+            const double acc = rescore_one<true>(r, grid, cand[p], lane, bad, &w1, &w2);
+            if (lane == 0) {
+                s64[p] = acc;
+                mom[2 * p] = w1;
+                mom[2 * p + 1] = w2;
+            }
+        } else {
+            const double acc = rescore_one<false>(r, grid, cand[p], lane, bad);
+            if (lane == 0) s64[p] = acc;
+        }
     }
     if (bad) atomicOr(r.err, bad);
 }
@@ -317,7 +339,8 @@ __global__ __launch_bounds__(256) void rescore_entries_kernel(EvalRun r, bool gr
 __global__ __launch_bounds__(256) void rank_kernel(EvalRun r, bool grid, const int64_t *cand,
                                                    const double *s64, const uint32_t *off,
                                                    int n_seg, int64_t cap, int k,
-                                                   const double *mu_sigma, ft_candidate *out)
+                                                   const double *mu_sigma, const double *mom,
+                                                   ft_candidate *out)
 {
     const int64_t total = min((int64_t)off[n_seg], cap);
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < total;
@@ -351,7 +374,15 @@ __global__ __launch_bounds__(256) void rank_kernel(EvalRun r, bool grid, const i
             c.n[2] = par.nz;
             c.s64 = sp;
             // sky-dependent weights: the moments of the template's sky point
-            const double *ms = grid && r.sky_ms ? r.sky_ms + 2 * (tp / ((int64_t)r.n_f0 * r.n_f1)) : mu_sigma;
+            // (grid) or of the template's own weights (binary banks)
+            double own[2];
+            const double *ms = mu_sigma;
+            if (grid && r.sky_ms) {
+                ms = r.sky_ms + 2 * (tp / ((int64_t)r.n_f0 * r.n_f1));
+            } else if (mom) {
+                stat_moments(r.stat, mom[2 * p], mom[2 * p + 1], own);
+                ms = own;
+            }
             c.z = (sp - ms[0]) / ms[1];
             out[(int64_t)sg * k + rank] = c;
         }
@@ -613,10 +644,11 @@ hipError_t launch_select(const EvalRun &r, bool grid, int n_seg, int k, double r
 hipError_t launch_rescore_rank(const EvalRun &r, bool grid, int n_seg, int k,
                                const SelectBufs &b, hipStream_t s)
 {
+    double *mom = !grid && r.arms ? b.cand_mom : nullptr;  // binary banks with sky weights
     hipLaunchKernelGGL(rescore_kernel, dim3(2048), dim3(256), 0, s, r, grid, b.cand, b.off, n_seg,
-                       b.cap, b.cand_s64);
+                       b.cap, b.cand_s64, mom);
     hipLaunchKernelGGL(rank_kernel, dim3(1024), dim3(256), 0, s, r, grid, b.cand, b.cand_s64,
-                       b.off, n_seg, b.cap, k, b.mu_sigma, b.out);
+                       b.off, n_seg, b.cap, k, b.mu_sigma, mom, b.out);
     hipLaunchKernelGGL(n_out_kernel, dim3((unsigned)((n_seg + 255) / 256)), dim3(256), 0, s,
                        b.cnt, n_seg, k, b.n_out);
     return hipGetLastError();
@@ -723,7 +755,7 @@ hipError_t launch_box_pick(const EvalRun &r, int64_t n_boxes, const BoxBufs &b, 
 {
     const unsigned gb = (unsigned)std::min<int64_t>((n_boxes + 255) / 256, 8192);
     hipLaunchKernelGGL(rescore_kernel, dim3(2048), dim3(256), 0, s, r, false, b.cand, b.n_cand, 1, b.cap,
-                       b.cand_s64);
+                       b.cand_s64, (double *)nullptr);
     hipLaunchKernelGGL(box_pick_kernel, dim3(1024), dim3(256), 0, s, b.cand, b.cand_s64, b.n_cand, b.cap, b.box,
                        b.max64);
     hipLaunchKernelGGL(box_index_kernel, dim3(1024), dim3(256), 0, s, b.cand, b.cand_s64, b.n_cand, b.cap, b.box,

@@ -310,14 +310,14 @@ def _binary_bank(f0, sky, ap, omega, phib):
 
 
 def ft_eval_binary(ctx, f0, sky, ap, omega, phib, t_ref, k, sub_edges, sum_mode=FT_SUM_BLOCKED,
-                   stats=None, statistic=FT_STAT_POWER):
+                   stats=None, statistic=FT_STAT_POWER, weights=FT_WEIGHTS_SFT):
     """Evaluate a BINARY bank (f0, sky[n,3], a_p, Omega, phi_b, each [n]); optional
     `stats` output (float32 [n], host or device)."""
     bank, keep = _binary_bank(f0, sky, ap, omega, phib)
     edges = _Arr(sub_edges, np.float64)
     o = ft_eval_opts()
     o.precision, o.k, o.n_sub, o.sum_mode, o.tile = FT_INDEX_FP64, k, len(sub_edges) - 1, sum_mode, 0
-    o.statistic = statistic
+    o.statistic, o.weights = statistic, weights
     o.sub_edges = edges.ptr
     s = _Arr(stats, np.float32)
     _check(ctx, load().ft_eval_templates(ctx, C.byref(bank), float(t_ref), C.byref(o), s.ptr))
@@ -342,13 +342,13 @@ def ft_gen_binary_bank(ctx, region, seed, first, n):
 
 
 def ft_eval_binary_random(ctx, region, seed, n, t_ref, k, sub_edges, sum_mode=FT_SUM_BLOCKED,
-                          stats=None, statistic=FT_STAT_POWER):
+                          stats=None, statistic=FT_STAT_POWER, weights=FT_WEIGHTS_SFT):
     """Generate templates 0..n-1 of the random binary bank on the device and evaluate them."""
     reg = make_region(region)
     edges = _Arr(sub_edges, np.float64)
     o = ft_eval_opts()
     o.precision, o.k, o.n_sub, o.sum_mode, o.tile = FT_INDEX_FP64, k, len(sub_edges) - 1, sum_mode, 0
-    o.statistic = statistic
+    o.statistic, o.weights = statistic, weights
     o.sub_edges = edges.ptr
     s = _Arr(stats, np.float32)
     _check(ctx, load().ft_eval_binary_random(ctx, C.byref(reg), int(seed), int(n), float(t_ref),

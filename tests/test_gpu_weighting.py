@@ -222,6 +222,27 @@ def test_weighting_errors(ft):
         with pytest.raises(ft.FtError, match="FT_E_UNSUPPORTED"):
             c.eval_templates(f0, f1, sky, w.t_ref, w.k, w.sub_edges, kind=ft.FT_BANK_LIST,
                              weights=ft.FT_WEIGHTS_SKY)
+        # the box search keeps one noise mean for all boxes: per-SFT weights only
+        b = synth.binary_band(seed=32, n_tmpl=1, n_per_det=40)
+        reg = dict(b.region, alpha_lo=0.0, alpha_hi=2 * np.pi, sdec_lo=-1.0, sdec_hi=1.0, phib_lo=0.0,
+                   phib_hi=2 * np.pi)
+        c.set_sfts(b.n_sft_per_det, b.t_mid, b.t_sft, b.first_bin, b.power)
+        c.set_velocities(b.v)
+        c.set_arms(b.arms)
+        o = ft.ft_eval_opts()
+        part = ft.ft_box_partition()
+        for d in range(6):
+            part.n_div[d] = 1
+        o.weights = ft.FT_WEIGHTS_SKY
+        out = np.zeros(1, ft.BOX_DTYPE)
+        import ctypes as C
+        rg = ft.make_region(reg)
+        st = ft.load().ft_eval_binary_boxes(c.ctx, C.byref(rg), 1, 100, float(b.t_ref), C.byref(part), C.byref(o),
+                                            out.ctypes.data_as(C.c_void_p), None)
+        assert st == ft.FT_E_UNSUPPORTED
+        c.set_sfts(w.n_sft_per_det, w.t_mid, w.t_sft, w.first_bin, w.power)
+        c.set_velocities(w.v)
+        c.set_arms(w.arms)
         with pytest.raises(ft.FtError, match="FT_E_INVALID"):
             c.eval_templates(w.f0, w.f1, w.sky, w.t_ref, w.k, w.sub_edges, tile=1, weights=ft.FT_WEIGHTS_SKY)
         for field in ("statistic", "weights"):
@@ -234,3 +255,49 @@ def test_weighting_errors(ft):
             c.eval_templates(w.f0, w.f1, w.sky, w.t_ref, w.k, w.sub_edges, weights=ft.FT_WEIGHTS_SKY)
     finally:
         c.close()
+
+
+@pytest.mark.parametrize("statistic,cos_mode", [(0, 0), (1, 0), (0, 1)])
+def test_sky_weights_binary_bank(ft, statistic, cos_mode):
+    """Binary-system banks with the all-sky weights, normalised per template:
+    statistics within the FP32 bound (plus one rounding of the weight), toplists
+    within FP64 rounding of the weights, z from each template's own moments."""
+    import torch
+    b = synth.binary_band(seed=31, n_tmpl=3000, n_per_det=200)
+    u = np.linspace(0.5, 1.5, b.t_mid.size).astype(np.float32)
+    table = b.power if statistic == 0 else ow.number_count_table(b.power)
+    bins = oracle.bins_binary(b.t_mid, b.t_ref, b.t_sft, b.v, b.f0, b.sky, b.ap, b.omega, b.phib)
+    W = ow.sky_weights(b.arms, u, b.sky)
+    S = ow.weighted_sums_at(b.first_bin, table, W, bins)
+    moments = ow.power_moments if statistic == 0 else ow.nc_moments
+    ms = np.array([moments(W[t]) for t in range(W.shape[0])])
+    c = ft.Context(0, torch.cuda.current_stream().cuda_stream)
+    try:
+        c.set_sfts(b.n_sft_per_det, b.t_mid, b.t_sft, b.first_bin, b.power, u)
+        c.set_velocities(b.v)
+        c.set_arms(b.arms)
+        c.binary_cos_mode(cos_mode)
+        stats = torch.empty(b.f0.size, dtype=torch.float32, device="cuda:0")
+        c.eval_binary(b.f0, b.sky, b.ap, b.omega, b.phib, b.t_ref, b.k, b.sub_edges, stats=stats,
+                      statistic=statistic, weights=ft.FT_WEIGHTS_SKY)
+        tops = [c.toplist(j, b.k) for j in range(len(b.sub_edges) - 1)]
+        nc, z_nc = c.toplist_number_count(0, b.k)
+        s32 = stats.cpu().numpy().astype(np.float64)
+    finally:
+        c.close()
+    assert np.all(np.abs(s32 - S) <= rel_bound(b.t_mid.size, sky=True) * S + 1e-13)
+    want = oracle.toplist(S, oracle.subband(b.f0, b.sub_edges), len(b.sub_edges) - 1, b.k)
+    for got, idx in zip(tops, want):
+        assert len(got) == len(idx)
+        kth = S[idx[-1]]
+        for t in got:
+            assert abs(t.s64 - S[t.index]) <= 1e-13 * S[t.index]
+            assert abs(t.z - (S[t.index] - ms[t.index, 0]) / ms[t.index, 1]) <= 1e-9
+            assert S[t.index] >= kth * (1 - 1e-13)
+    # the number counts of the first toplist's entries, with the same weights
+    ind = ow.number_count_table(b.power)
+    nc_want = ow.weighted_sums_at(b.first_bin, ind, W, bins)
+    for t, n, zz in zip(tops[0], nc, z_nc):
+        mu, sig = ow.nc_moments(W[t.index])
+        assert abs(n - nc_want[t.index]) <= 1e-13 * max(nc_want[t.index], 1e-300)
+        assert abs(zz - (nc_want[t.index] - mu) / sig) <= 1e-9
