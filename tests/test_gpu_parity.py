@@ -237,6 +237,8 @@ def test_argument_and_state_errors(ft):
             dict(k=0),
             dict(edges=np.array([101.0, 100.0])),          # edges not increasing
             dict(f0=np.array([np.nan])),
+            dict(f0=np.zeros(0)),                          # an empty bank
+            dict(sky=np.zeros((0, 3))),
         ]
         for case in cases:
             kw = dict(f0=w.f0, f1=w.f1, sky=w.sky, k=5, edges=w.sub_edges)
