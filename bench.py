@@ -365,7 +365,7 @@ def bench_hyperbox(ft, synth, log, n_bank=10 ** 8, min_boxes=10_000, o=3.44, n_q
                        % (n_bank, o, region["f0_lo"], region["f0_hi"]),
            "n_div": n_div, "n_boxes": n_boxes, "cases": {}}
     for case, (res, secs) in runs.items():
-        z_box = np.where(res["index"] >= 0, res["z"], np.nan)
+        z_box = hyperbox.box_z(res)
         t0 = time.perf_counter()
         rows = []
         for n_cand in n_cands:

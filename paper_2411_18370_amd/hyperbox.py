@@ -54,6 +54,12 @@ def partition(region, t_sft, t_obs, vmax, o, per_box, min_boxes=1, max_boxes=1 <
     return [int(x) for x in n_div]
 
 
+def box_z(res):
+    """Critical ratios of the box maxima of ft_eval_binary_boxes (records with
+    index, z), nan for empty boxes: the z_box that thresholds() takes."""
+    return np.where(res["index"] >= 0, res["z"], np.nan)
+
+
 def thresholds(z_box, n_cand, n_reject):
     """Detection threshold on z per box: boxes sorted by z (descending, ties to
     the lower box), the first n_reject rejected (+inf), the next n_cand selected

@@ -78,6 +78,14 @@ def test_thresholds_rule():
     assert np.array_equal(hyperbox.thresholds(z, 10, 0)[[0, 1, 3, 4, 5]], z[[0, 1, 3, 4, 5]])
 
 
+def test_box_z_marks_empty_boxes():
+    res = np.zeros(4, dtype=[("index", np.int64), ("z", np.float64)])
+    res["index"] = [3, -1, 7, -1]
+    res["z"] = [1.5, 0.0, -0.5, 0.0]
+    z = hyperbox.box_z(res)
+    assert z[0] == 1.5 and z[2] == -0.5 and np.isnan(z[1]) and np.isnan(z[3])
+
+
 def test_optimizer_rejects_the_outlier_boxes():
     """30 boxes on an artifact outnumber the 20 candidates: without rejection they
     set every threshold; rejecting them restores the sensitivity, and rejecting
