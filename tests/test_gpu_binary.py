@@ -199,3 +199,45 @@ def test_binary_random_bank_at_benchmark_size(ft):
         rest = S[(sub_all == j)].astype(np.float64)
         thr = top[-1].s64
         assert np.sort(rest)[-k - 1] <= thr * (1 + rel_bound(w.n_sft))
+
+
+def test_binary_random_bank_sky_weights_at_benchmark_size(ft):
+    """The bench's 10^6-template random bank with the all-sky weights (normalised
+    per template): sampled templates and every toplist member against the
+    oracle's per-template weights; nothing outside a toplist beats its K-th
+    member beyond the FP32 bound."""
+    import torch
+    from oracle import weighting as ow
+    w = synth.binary_band(seed=3, n_tmpl=1, n_per_det=5000)
+    n, seed, k = 1_000_000, 2025, 10
+    stats = torch.empty(n, dtype=torch.float32, device="cuda")
+    with _ctx(ft, w) as c:
+        c.set_arms(w.arms)
+        c.eval_binary_random(w.region, seed, n, w.t_ref, k, w.sub_edges, stats=stats,
+                             weights=ft.FT_WEIGHTS_SKY)
+        tops = [c.toplist(j, k) for j in range(len(w.sub_edges) - 1)]
+        print("eval ms", c.info().eval_ms, flush=True)
+    rng = np.random.default_rng(10)
+    sample = np.sort(rng.choice(n, 800, replace=False))
+    members = np.array([t.index for top in tops for t in top])
+    idx = np.concatenate([sample, members])
+    bank = obank.random_binary_bank(seed, 0, n, **w.region)
+    f0, sky, ap, om, pb = (a[idx] for a in bank)
+    bins = oracle.bins_binary(w.t_mid, w.t_ref, w.t_sft, w.v, f0, sky, ap, om, pb)
+    W = ow.sky_weights(w.arms, None, sky)
+    S = ow.weighted_sums_at(w.first_bin, w.power, W, bins)
+    bound = 44 * 2.0 ** -24 + 4 * w.n_sft * 2.0 ** -53
+    s32 = stats[torch.from_numpy(idx).cuda()].cpu().numpy().astype(np.float64)
+    assert np.max(np.abs(s32 - S) / S) <= bound
+    exact = dict(zip(idx.tolist(), S.tolist()))
+    row = dict(zip(idx.tolist(), range(idx.size)))
+    sub_all = oracle.subband(bank[0], w.sub_edges)
+    St = stats.cpu().numpy()
+    for j, top in enumerate(tops):
+        assert len(top) == k
+        for t in top:
+            assert abs(t.s64 - exact[t.index]) <= 1e-13 * exact[t.index] and t.sub == j
+            mu, sig = ow.power_moments(W[row[t.index]])
+            assert abs(t.z - (exact[t.index] - mu) / sig) <= 1e-9
+        rest = St[(sub_all == j)].astype(np.float64)
+        assert np.sort(rest)[-k - 1] <= top[-1].s64 * (1 + bound)
