@@ -92,6 +92,10 @@ struct ft_ctx_s {
     // bank
     std::vector<double> f0_h, f1_h, sky_h, sky_tile_h, ap_h, omega_h, phib_h;
     std::vector<int32_t> perm_h;
+    // the grid sky whose Doppler-coherent order sky_tile_h/perm_h and
+    // d_sky_tile/d_perm hold (reused while a call brings the same sky, byte for byte)
+    std::vector<double> sky_order_of;
+    bool sky_order_valid = false;
     double *d_f0 = nullptr, *d_f1 = nullptr, *d_sky = nullptr, *d_edges = nullptr,
            *d_sky_tile = nullptr, *d_bin = nullptr;  // d_bin: binary banks' [3][n] a_p, Omega, phi_b
     size_t cap_f0 = 0, cap_f1 = 0, cap_sky = 0, cap_edges = 0, cap_sky_tile = 0, cap_bin = 0;
@@ -1092,17 +1096,25 @@ static ft_status prepare_bank(ft_ctx c, const ft_bank *bank, double t_ref, EvalR
         (e = ensure(&c->d_stats, &c->cap_stats, (size_t)n_t)) != hipSuccess)
         return hip_fail(c, e, "alloc bank");
     if (grid) {
-        sky_order(c->sky_h, ns, c->perm_h);
-        c->sky_tile_h.resize((size_t)ns * 3);
-        for (int64_t s = 0; s < ns; ++s)
-            for (int d = 0; d < 3; ++d) c->sky_tile_h[3 * s + d] = c->sky_h[3 * (size_t)c->perm_h[s] + d];
-        if ((e = ensure(&c->d_sky_tile, &c->cap_sky_tile, (size_t)ns * 3)) != hipSuccess ||
-            (e = ensure(&c->d_perm, &c->cap_perm, (size_t)ns)) != hipSuccess)
-            return hip_fail(c, e, "alloc sky order");
-        e = hipMemcpyAsync(c->d_sky_tile, c->sky_tile_h.data(), ns * 3 * sizeof(double), hipMemcpyHostToDevice, c->stream);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(c->d_perm, c->perm_h.data(), ns * sizeof(int32_t), hipMemcpyHostToDevice, c->stream);
-        if (e != hipSuccess) return hip_fail(c, e, "upload sky order");
+        const bool same_sky = c->sky_order_valid && c->sky_order_of.size() == c->sky_h.size() &&
+                              std::memcmp(c->sky_order_of.data(), c->sky_h.data(), c->sky_h.size() * sizeof(double)) == 0;
+        if (!same_sky) {
+            c->sky_order_valid = false;
+            sky_order(c->sky_h, ns, c->perm_h);
+            c->sky_tile_h.resize((size_t)ns * 3);
+            for (int64_t s = 0; s < ns; ++s)
+                for (int d = 0; d < 3; ++d) c->sky_tile_h[3 * s + d] = c->sky_h[3 * (size_t)c->perm_h[s] + d];
+            if ((e = ensure(&c->d_sky_tile, &c->cap_sky_tile, (size_t)ns * 3)) != hipSuccess ||
+                (e = ensure(&c->d_perm, &c->cap_perm, (size_t)ns)) != hipSuccess)
+                return hip_fail(c, e, "alloc sky order");
+            e = hipMemcpyAsync(c->d_sky_tile, c->sky_tile_h.data(), ns * 3 * sizeof(double), hipMemcpyHostToDevice,
+                               c->stream);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(c->d_perm, c->perm_h.data(), ns * sizeof(int32_t), hipMemcpyHostToDevice, c->stream);
+            if (e != hipSuccess) return hip_fail(c, e, "upload sky order");
+            c->sky_order_of = c->sky_h;
+            c->sky_order_valid = true;
+        }
     }
     e = hipMemcpyAsync(c->d_f0, c->f0_h.data(), n0 * sizeof(double), hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess)

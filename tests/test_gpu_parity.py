@@ -273,3 +273,22 @@ def test_repeat_is_deterministic(ft):
     b, tb, _ = run_gpu(ft, w)
     assert np.array_equal(a, b)
     assert [[c.index for c in t] for t in ta] == [[c.index for c in t] for t in tb]
+
+
+def test_alternating_banks_in_one_context(ft):
+    """One context evaluating bank A, then B (another sky), then A again, then A
+    with one sky coordinate changed by an ulp: each result equals a fresh
+    context's (the cached sky order is reused only for the identical sky)."""
+    import torch
+    w = synth.allsky_band(seed=13, n_sky=40, n_per_det=150)
+    sky_b = synth.isotropic_sky(40, np.random.default_rng(99))
+    sky_c = w.sky.copy()
+    sky_c[7, 0] = np.nextafter(sky_c[7, 0], 2.0)
+    fresh = {name: run_gpu(ft, w, sky=sk)[0] for name, sk in (("a", w.sky), ("b", sky_b), ("c", sky_c))}
+    with ft.Context(0, torch.cuda.current_stream().cuda_stream) as c:
+        c.load_workload(w)
+        for name, sk in (("a", w.sky), ("b", sky_b), ("a", w.sky), ("c", sky_c), ("a", w.sky)):
+            stats = torch.empty(w.f0.size * w.f1.size * sk.shape[0], dtype=torch.float32, device="cuda:0")
+            c.eval_templates(w.f0, w.f1, sk, w.t_ref, w.k, w.sub_edges, stats=stats)
+            c.sync()
+            assert np.array_equal(stats.cpu().numpy(), fresh[name]), name
