@@ -91,6 +91,134 @@ __global__ __launch_bounds__(256) void hist_kernel(const float *stats, const int
     }
 }
 
+// Grid banks: a row is one (sky, f1) pair of n_f0 templates and the sub-band
+// depends on the f0 column only, so each thread owns the columns
+// threadIdx.x + 256 i (i < COLS) of every row it visits and keeps their
+// sub-band and selection state in registers; the rows stream through.
+template <int COLS>
+struct GridCols {
+    int32_t sg[COLS];
+    bool on[COLS];
+};
+
+template <int COLS>
+__device__ __forceinline__ GridCols<COLS> grid_cols(const int32_t *seg_of, const Rows &rw)
+{
+    GridCols<COLS> g;
+#pragma unroll
+    for (int i = 0; i < COLS; ++i) {
+        const int64_t c = threadIdx.x + 256 * i;
+        g.sg[i] = c < rw.row_len ? seg_of[c] : -1;
+        g.on[i] = g.sg[i] >= 0;
+    }
+    return g;
+}
+
+// Histogram pass over grid rows.  When every lane of the wave with a key for
+// this column hits the same (sub-band, digit) -- the common case in the first
+// passes, where a row's statistics share their leading bits -- one lane adds
+// the wave's count.
+template <int COLS>
+__global__ __launch_bounds__(256) void hist_grid_kernel(const float *stats, const int32_t *seg_of, Rows rw,
+                                                        const uint32_t *state, uint32_t *hist, int n_seg, int shift)
+{
+    extern __shared__ uint32_t hsh[];
+    for (int q = threadIdx.x; q < n_seg * 256; q += blockDim.x) hsh[q] = 0;
+    GridCols<COLS> g = grid_cols<COLS>(seg_of, rw);
+    uint32_t mask[COLS], prefix[COLS];
+#pragma unroll
+    for (int i = 0; i < COLS; ++i) {
+        const uint32_t *st = state + (int64_t)max(g.sg[i], 0) * ST;
+        g.on[i] = g.on[i] && !st[S_DONE];
+        mask[i] = st[S_MASK];
+        prefix[i] = st[S_PREFIX];
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    for (int64_t row = blockIdx.x; row < rw.n_rows; row += gridDim.x) {
+        const float *rp = stats + row * rw.row_len;
+#pragma unroll
+        for (int i = 0; i < COLS; ++i) {
+            int idx = -1;
+            if (g.on[i]) {
+                const uint32_t key = __float_as_uint(rp[threadIdx.x + 256 * i]);
+                if (key <= NAN_KEY && (key & mask[i]) == prefix[i]) idx = g.sg[i] * 256 + (int)((key >> shift) & 255u);
+            }
+            const uint64_t valid = __builtin_amdgcn_ballot_w64(idx >= 0);
+            if (valid == 0) continue;
+            const int first = __builtin_ctzll(valid);
+            const int lead = __builtin_amdgcn_readlane(idx, first);
+            const uint64_t same = __builtin_amdgcn_ballot_w64(idx == lead);
+            if (same == valid) {
+                if (lane == first) atomicAdd(&hsh[lead], (uint32_t)__builtin_popcountll(valid));
+            } else if (idx >= 0) {
+                atomicAdd(&hsh[idx], 1u);
+            }
+        }
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < n_seg * 256; q += blockDim.x)
+        if (hsh[q]) atomicAdd(&hist[q], hsh[q]);
+}
+
+// Candidates per sub-band over grid rows: counts kept per column in
+// registers, added once per thread.
+template <int COLS>
+__global__ __launch_bounds__(256) void count_grid_kernel(const float *stats, const int32_t *seg_of, Rows rw,
+                                                         const uint32_t *state, uint32_t *cnt, int n_seg)
+{
+    extern __shared__ uint32_t csh[];
+    for (int q = threadIdx.x; q < n_seg; q += blockDim.x) csh[q] = 0;
+    GridCols<COLS> g = grid_cols<COLS>(seg_of, rw);
+    uint32_t thr[COLS], n[COLS];
+#pragma unroll
+    for (int i = 0; i < COLS; ++i) {
+        thr[i] = state[(int64_t)max(g.sg[i], 0) * ST + S_THR];
+        n[i] = 0;
+    }
+    __syncthreads();
+    for (int64_t row = blockIdx.x; row < rw.n_rows; row += gridDim.x) {
+        const float *rp = stats + row * rw.row_len;
+#pragma unroll
+        for (int i = 0; i < COLS; ++i)
+            if (g.on[i]) {
+                const uint32_t key = __float_as_uint(rp[threadIdx.x + 256 * i]);
+                n[i] += (key <= NAN_KEY && key >= thr[i]) ? 1u : 0u;
+            }
+    }
+#pragma unroll
+    for (int i = 0; i < COLS; ++i)
+        if (g.on[i] && n[i]) atomicAdd(&csh[g.sg[i]], n[i]);
+    __syncthreads();
+    for (int q = threadIdx.x; q < n_seg; q += blockDim.x)
+        if (csh[q]) atomicAdd(&cnt[q], csh[q]);
+}
+
+// Compaction of the candidates over grid rows.
+template <int COLS>
+__global__ __launch_bounds__(256) void scatter_grid_kernel(const float *stats, const int32_t *seg_of, Rows rw,
+                                                           const uint32_t *state, const uint32_t *off,
+                                                           uint32_t *fill, int64_t *cand, int64_t cap)
+{
+    GridCols<COLS> g = grid_cols<COLS>(seg_of, rw);
+    uint32_t thr[COLS];
+#pragma unroll
+    for (int i = 0; i < COLS; ++i) thr[i] = state[(int64_t)max(g.sg[i], 0) * ST + S_THR];
+    for (int64_t row = blockIdx.x; row < rw.n_rows; row += gridDim.x) {
+        const float *rp = stats + row * rw.row_len;
+#pragma unroll
+        for (int i = 0; i < COLS; ++i)
+            if (g.on[i]) {
+                const int64_t c = threadIdx.x + 256 * i;
+                const uint32_t key = __float_as_uint(rp[c]);
+                if (key <= NAN_KEY && key >= thr[i]) {
+                    const int64_t pos = (int64_t)off[g.sg[i]] + atomicAdd(&fill[g.sg[i]], 1u);
+                    if (pos < cap) cand[pos] = row * rw.row_len + c;
+                }
+            }
+    }
+}
+
 // One thread per segment: choose the digit holding the k_rem-th largest key.
 __global__ void scan_kernel(uint32_t *state, const uint32_t *hist, int n_seg, int shift,
                             double two_e)
@@ -612,11 +740,20 @@ hipError_t launch_select(const EvalRun &r, bool grid, int n_seg, int k, double r
                        b.fill, n_seg, k);
     const bool lds_hist = n_seg * 256 <= 8192;
     const unsigned nb = blocks_for(rw.n_rows);
+    // grid rows of at most 2048 templates: column-owning kernels
+    const int cols = !grid || !lds_hist ? 0 : rw.row_len <= 1024 ? 4 : rw.row_len <= 2048 ? 8 : 0;
     for (int pass = 0; pass < 4; ++pass) {
         const int shift = 24 - 8 * pass;
         hipError_t e = launch_fill_u32(b.hist, 0u, (int64_t)n_seg * 256, s);
         if (e != hipSuccess) return e;
-        if (lds_hist)
+        const size_t hl = (size_t)n_seg * 256 * sizeof(uint32_t);
+        if (cols == 4)
+            hipLaunchKernelGGL(hist_grid_kernel<4>, dim3(nb), dim3(256), hl, s, r.stats, b.seg_of_f0, rw, b.state,
+                               b.hist, n_seg, shift);
+        else if (cols == 8)
+            hipLaunchKernelGGL(hist_grid_kernel<8>, dim3(nb), dim3(256), hl, s, r.stats, b.seg_of_f0, rw, b.state,
+                               b.hist, n_seg, shift);
+        else if (lds_hist)
             hipLaunchKernelGGL(hist_kernel<true>, dim3(nb), dim3(256),
                                (size_t)n_seg * 256 * sizeof(uint32_t), s, r.stats, b.seg_of_f0,
                                rw, b.state, b.hist, n_seg, shift);
@@ -627,7 +764,13 @@ hipError_t launch_select(const EvalRun &r, bool grid, int n_seg, int k, double r
                            shift, 2.0 * rel_err);
     }
     const bool lds_cnt = n_seg <= 8192;
-    if (lds_cnt)
+    if (cols == 4)
+        hipLaunchKernelGGL(count_grid_kernel<4>, dim3(nb), dim3(256), (size_t)n_seg * sizeof(uint32_t), s, r.stats,
+                           b.seg_of_f0, rw, b.state, b.cnt, n_seg);
+    else if (cols == 8)
+        hipLaunchKernelGGL(count_grid_kernel<8>, dim3(nb), dim3(256), (size_t)n_seg * sizeof(uint32_t), s, r.stats,
+                           b.seg_of_f0, rw, b.state, b.cnt, n_seg);
+    else if (lds_cnt)
         hipLaunchKernelGGL(count_kernel<true>, dim3(nb), dim3(256),
                            (size_t)n_seg * sizeof(uint32_t), s, r.stats, b.seg_of_f0, rw,
                            b.state, b.cnt, n_seg);
@@ -636,8 +779,15 @@ hipError_t launch_select(const EvalRun &r, bool grid, int n_seg, int k, double r
                            rw, b.state, b.cnt, n_seg);
     hipLaunchKernelGGL(offsets_kernel, dim3(1), dim3(64), 0, s, b.cnt, b.off, n_seg, b.cap,
                        r.err);
-    hipLaunchKernelGGL(scatter_kernel, dim3(nb), dim3(256), 0, s, r.stats, b.seg_of_f0, rw,
-                       b.state, b.off, b.fill, b.cand, b.cap);
+    if (cols == 4)
+        hipLaunchKernelGGL(scatter_grid_kernel<4>, dim3(nb), dim3(256), 0, s, r.stats, b.seg_of_f0, rw, b.state,
+                           b.off, b.fill, b.cand, b.cap);
+    else if (cols == 8)
+        hipLaunchKernelGGL(scatter_grid_kernel<8>, dim3(nb), dim3(256), 0, s, r.stats, b.seg_of_f0, rw, b.state,
+                           b.off, b.fill, b.cand, b.cap);
+    else
+        hipLaunchKernelGGL(scatter_kernel, dim3(nb), dim3(256), 0, s, r.stats, b.seg_of_f0, rw,
+                           b.state, b.off, b.fill, b.cand, b.cap);
     return hipGetLastError();
 }
 
