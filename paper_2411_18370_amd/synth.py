@@ -217,6 +217,15 @@ def weighted_small(seed: int = 5, n_sky: int = 24, n_per_det: int = 300) -> Work
                   [-2e-10, 1e-10], n_sky, 20, 4, seed)
 
 
+def wide_band(n_f0: int, seed: int = 20, n_sky: int = 3, n_per_det: int = 30,
+              with_noise: bool = True) -> Workload:
+    """1 detector x n_per_det SFTs of 1800 s, n_f0 f0 from 120 Hz x 2 f1 x n_sky, K = 25:
+    long f0 rows for the selection over grid banks (with_noise False gives a table
+    of zeros, so every template ties)."""
+    return _build("wide-1det-%dsft-120Hz-%df0" % (n_per_det, n_f0), 1, n_per_det, 1800.0, 0.0,
+                  120.0, n_f0, [-1e-10, 0.0], n_sky, 25, 1, seed, with_noise=with_noise)
+
+
 def allsky_band(seed: int = 2, n_sky: int = 100_000, n_per_det: int = 5000) -> Workload:
     """2 detectors x 5000 SFTs (10% gaps), 200-200.5 Hz, 900 f0 x 11 f1 x n_sky, K=100/0.05 Hz.
 

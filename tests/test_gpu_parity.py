@@ -292,3 +292,23 @@ def test_alternating_banks_in_one_context(ft):
             c.eval_templates(w.f0, w.f1, sk, w.t_ref, w.k, w.sub_edges, stats=stats)
             c.sync()
             assert np.array_equal(stats.cpu().numpy(), fresh[name]), name
+
+
+@pytest.mark.parametrize("n_f0,n_sub", [(1024, 6), (1025, 6), (2048, 6), (2049, 6), (1500, 40)])
+@pytest.mark.parametrize("noise", [True, False])
+def test_grid_row_lengths_selection(ft, n_f0, n_sub, noise):
+    """f0 rows at both sides of the 1024 and 2048 column limits of the selection's
+    grid form, more sub-bands than fit its LDS histogram, f0 columns outside every
+    sub-band at both ends, and a table of zeros where every template ties."""
+    w = synth.wide_band(n_f0, seed=20 + n_f0, with_noise=noise)
+    cuts = np.linspace(3, n_f0 - 2, n_sub + 1).round().astype(np.int64)
+    edges = w.f0[0] + (cuts - 0.5) / w.t_sft
+    s32, tops, _ = run_gpu(ft, w, edges=edges)
+    s64, _ = oracle_grid(w)
+    f0t, _, _ = oracle.grid_params(w.f0, w.f1, w.sky.shape[0])
+    sub = oracle.subband(f0t, edges)
+    assert (sub < 0).sum() == 5 * w.f1.size * w.sky.shape[0]
+    want = oracle.toplist(s64, sub, n_sub, w.k)
+    assert_stats(s32, s64, w.n_sft)
+    assert_toplists(tops, want, s64, w.n_sft)
+    assert all(len(t) == w.k for t in tops)
