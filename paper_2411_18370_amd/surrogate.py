@@ -5,7 +5,7 @@ sampling) is estimated by injecting signals into synthetic data, searching them
 with the brute-force statistic and applying the detection rule
 R(z; tau) = 1[z > tau] (Sec. V.B) to the loudest critical ratio of each run.
 Those labels train a small network p_det(h0/sqrt(S_n), cos iota, psi, sin delta,
-alpha, f) on the GPU; plain injection campaigns remain its judge.
+alpha, f) on the GPU; plain injection campaigns remain the check on it.
 
 All arithmetic runs in the HIP library (table generation, evaluation, exact
 toplists, labels, network training and inference); this module only chunks the

@@ -312,3 +312,28 @@ def test_grid_row_lengths_selection(ft, n_f0, n_sub, noise):
     assert_stats(s32, s64, w.n_sft)
     assert_toplists(tops, want, s64, w.n_sft)
     assert all(len(t) == w.k for t in tops)
+
+
+def test_max_subbands_and_max_k(ft):
+    """The documented maxima: 4096 sub-bands (two f0 columns each, K = 5) on an
+    8192-column row, then K = 65536 in one sub-band over 81,920 templates (and
+    K above the bank size over a smaller sky)."""
+    w = synth.wide_band(8192, seed=31, n_sky=5)
+    f0t, _, _ = oracle.grid_params(w.f0, w.f1, w.sky.shape[0])
+    s64, _ = oracle_grid(w)
+    edges = w.f0[0] + (np.arange(0, 8193, 2) - 0.5) / w.t_sft
+    assert edges.size == 4097
+    s32, tops, _ = run_gpu(ft, w, k=5, edges=edges)
+    want = oracle.toplist(s64, oracle.subband(f0t, edges), 4096, 5)
+    assert_stats(s32, s64, w.n_sft)
+    assert_toplists(tops, want, s64, w.n_sft)
+    one = np.array([w.f0[0] - 0.5 / w.t_sft, w.f0[-1] + 0.5 / w.t_sft])
+    _, tops, _ = run_gpu(ft, w, k=65536, edges=one)
+    want = oracle.toplist(s64, oracle.subband(f0t, one), 1, 65536)
+    assert len(tops[0]) == 65536
+    assert_toplists(tops, want, s64, w.n_sft)
+    sky3 = w.sky[:3]
+    s64_3 = s64[:8192 * w.f1.size * 3]
+    _, tops, _ = run_gpu(ft, w, k=65536, edges=one, sky=sky3)
+    assert len(tops[0]) == s64_3.size
+    assert_toplists(tops, [oracle.toplist(s64_3, np.zeros(s64_3.size, np.int32), 1, 65536)[0]], s64_3, w.n_sft)
