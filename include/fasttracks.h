@@ -245,6 +245,10 @@ typedef struct {
  * Asynchronous on the context's stream.  Errors: FT_E_STATE (no SFTs or
  * velocities), FT_E_INVALID (bank/options), FT_E_UNSUPPORTED (sizes beyond
  * limits), FT_E_NOMEM; FT_E_RANGE is reported by the next ft_sync/ft_toplist.
+ * A BINARY bank of fewer than 2^19 templates with blocked sums and per-SFT
+ * weights may keep n_templates * ceil(N / 32) floats (at most 256 MB) of
+ * context memory for its per-block sums; the statistics are the same bits
+ * either way.
  */
 ft_status ft_eval_templates(ft_ctx ctx, const ft_bank *bank, double t_ref,
                             const ft_eval_opts *opts, float *stats);

@@ -109,6 +109,8 @@ struct ft_ctx_s {
     size_t cap_perm = 0;
     float *d_stats = nullptr;
     size_t cap_stats = 0;
+    float *d_bsum = nullptr;  // block sums of the split binary evaluation
+    size_t cap_bsum = 0;
 
     // selection
     uint32_t *d_hist = nullptr, *d_state = nullptr, *d_cnt = nullptr, *d_off = nullptr,
@@ -522,6 +524,7 @@ void ft_destroy(ft_ctx c)
     release(&c->d_perm, &c->cap_perm);
     release(&c->d_edges, &c->cap_edges);
     release(&c->d_stats, &c->cap_stats);
+    release(&c->d_bsum, &c->cap_bsum);
     release(&c->d_hist, &c->cap_hist);
     release(&c->d_state, &c->cap_state);
     release(&c->d_cnt, &c->cap_cnt);
@@ -1414,6 +1417,28 @@ ft_status ft_eval_templates(ft_ctx c, const ft_bank *bank, double t_ref, const f
 
 // Launch sequence of an evaluation: clear flags, map sub-bands, evaluate,
 // select, re-sum, rank (run fully prepared; n_seg_map = f0 values to map).
+// Binary banks too small to fill the GPU with one lane per template (about
+// 2^19 lanes are resident) split their SUM_BLOCK-SFT blocks over several
+// workgroup rows; the per-block sums take n_list ceil(N / SUM_BLOCK) floats of
+// context memory, at most 256 MB (else, or if that allocation fails, the bank
+// is evaluated unsplit).  Either way the statistics are the same bits.
+static hipError_t eval_binary(ft_ctx c, const EvalRun &run)
+{
+    constexpr int64_t kLanes = int64_t(1) << 19;
+    constexpr size_t kMaxBytes = size_t(256) << 20;
+    const int64_t n_blk = (run.n_sft + SUM_BLOCK - 1) / SUM_BLOCK;
+    int n_seg = 1;
+    if (!run.arms && run.sum_mode == FT_SUM_BLOCKED && run.n_list > 0 && run.n_list < kLanes && n_blk > 1 &&
+        (size_t)n_blk * (size_t)run.n_list * sizeof(float) <= kMaxBytes) {
+        n_seg = (int)std::min<int64_t>(n_blk, (kLanes + run.n_list - 1) / run.n_list);
+        if (n_seg > 1 && ensure(&c->d_bsum, &c->cap_bsum, (size_t)(n_blk * run.n_list)) != hipSuccess) {
+            (void)hipGetLastError();
+            n_seg = 1;
+        }
+    }
+    return launch_eval_binary(run, n_seg > 1 ? c->d_bsum : nullptr, n_seg, c->stream);
+}
+
 static ft_status launch_eval_select(ft_ctx c, EvalRun &run, bool grid, int tile, int64_t n_t, int64_t n_seg_map,
                                     const ft_eval_opts *opts, const std::vector<double> &edges, float *stats)
 {
@@ -1433,7 +1458,7 @@ static ft_status launch_eval_select(ft_ctx c, EvalRun &run, bool grid, int tile,
         e = launch_sky_moments(run.arms, run.weight, run.n_sft, run.sky, run.n_sky, opts->statistic, c->d_sky_norm,
                                c->d_sky_ms, c->d_err, c->stream);
     if (e == hipSuccess)
-        e = run.ap ? launch_eval_binary(run, c->stream)
+        e = run.ap ? eval_binary(c, run)
             : !grid ? launch_eval_list(run, c->stream)
             : tile < 0 ? launch_eval_grid_direct(run, c->stream) : launch_eval_grid(run, tile_cfg(tile), c->stream);
     if (e == hipSuccess) e = hipEventRecord(c->ev[1], c->stream);
@@ -1622,7 +1647,7 @@ ft_status ft_eval_binary_boxes(ft_ctx c, const ft_binary_region *reg, uint64_t s
             return hip_fail(c, e, "alloc box candidates");
         BoxBufs bb{c->d_box, c->d_bmax32, c->d_bcount, c->d_bmax64, c->d_bidx, c->d_bcand, c->d_bcand_s64, c->d_bncand, cap};
         e = launch_fill_u32(c->d_err, 0u, 1, c->stream);
-        if (e == hipSuccess && attempt == 0) e = launch_eval_binary(run, c->stream);
+        if (e == hipSuccess && attempt == 0) e = eval_binary(c, run);
         if (e == hipSuccess) e = launch_box_max(run, n, n_boxes, bb, rel_err, c->stream);
         uint32_t n_cand[2] = {0, 0};
         if (e == hipSuccess) e = hipMemcpyAsync(n_cand, c->d_bncand, sizeof n_cand, hipMemcpyDeviceToHost, c->stream);

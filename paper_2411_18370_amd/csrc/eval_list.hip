@@ -478,11 +478,20 @@ __device__ __forceinline__ float binary_gather(const EvalRun &r, int k, uint32_t
 // SKYW: sky-dependent weights (Sec. II.B): the staged values u_k P are
 // multiplied by ab_k(n) (FP64, rounded to float) and the sum is divided at the
 // end by W1 = sum_k u_k ab_k (FP64, sequential in SFT order).
-template <bool HW, bool RANGE, bool SKYW>
-__global__ __launch_bounds__(256) void eval_binary_kernel(EvalRun r)
+// SPLIT (blocked sums, no sky weights): workgroup row blockIdx.y takes the
+// SUM_BLOCK-SFT blocks [y bps, (y + 1) bps) and stores each block's FP32 sum
+// in bsum[block][template]; binary_block_sum_kernel then adds them in block
+// order in FP64, which is the unsplit kernel's sequence of operations.  Small
+// banks use it to fill the GPU.
+template <bool HW, bool RANGE, bool SKYW, bool SPLIT = false>
+__global__ __launch_bounds__(256) void eval_binary_kernel(EvalRun r, float *bsum, int bps)
 {
+    static_assert(!(SPLIT && SKYW), "W1 is one sequential sum over every SFT");
     const int64_t n = r.n_list;
     const int n_sft = r.n_sft;
+    const int k_begin = SPLIT ? (int)blockIdx.y * bps * SUM_BLOCK : 0;
+    const int k_end = SPLIT ? min(k_begin + bps * SUM_BLOCK, n_sft) : n_sft;
+    if (k_begin >= k_end) return;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < n; base += stride) {
         const int64_t t_raw = base + threadIdx.x;
@@ -541,8 +550,8 @@ __global__ __launch_bounds__(256) void eval_binary_kernel(EvalRun r)
         // value of SFT k is added (reads past the last SFT re-read it, unused);
         // blocks of SUM_BLOCK SFTs (even) are walked in pairs, so va holds the
         // next block's first SFT when a block ends.
-        float va = binary_gather(r, 0, offset(0, bad));
-        for (int kb = 0; kb < n_sft; kb += SUM_BLOCK) {
+        float va = binary_gather(r, k_begin, offset(k_begin, bad));
+        for (int kb = k_begin; kb < k_end; kb += SUM_BLOCK) {
             const int ke = min(kb + SUM_BLOCK, n_sft);
             int k = kb;
             for (; k + 1 < ke; k += 2) {
@@ -553,18 +562,41 @@ __global__ __launch_bounds__(256) void eval_binary_kernel(EvalRun r)
                 acc = add(acc, vb, k + 1);
             }
             if (k < ke) acc = add(acc, va, k);  // odd tail: k = n_sft - 1
-            if (r.sum_mode == FT_SUM_BLOCKED) {
+            if (SPLIT) {
+                if (live) bsum[(int64_t)(kb / SUM_BLOCK) * n + t] = acc;
+                acc = 0.f;
+            } else if (r.sum_mode == FT_SUM_BLOCKED) {
                 tot += (double)acc;
                 acc = 0.f;
             }
         }
         if (bad && live) atomicOr(r.err, ERR_RANGE);
-        if (SKYW) {
+        if (SPLIT) {
+        } else if (SKYW) {
             if (!(w1 > 0.0) && live) atomicOr(r.err, ERR_BAD_POWER);
             if (live) r.stats[t] = (float)((tot + (double)acc) / w1);
         } else if (live) {
             r.stats[t] = (float)(tot + (double)acc);
         }
+    }
+}
+
+// Statistic of the split binary evaluation: the block sums of each template
+// added in block order in FP64 (the unsplit kernel's totals).
+__global__ __launch_bounds__(256) void binary_block_sum_kernel(const float *bsum, int64_t n, int n_blk, float *stats)
+{
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
+        double tot = 0.0;
+        int b = 0;
+        for (; b + 8 <= n_blk; b += 8) {  // eight loads in flight, then the additions in order
+            float x[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) x[i] = bsum[(int64_t)(b + i) * n + t];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) tot += (double)x[i];
+        }
+        for (; b < n_blk; ++b) tot += (double)bsum[(int64_t)b * n + t];
+        stats[t] = (float)tot;
     }
 }
 
@@ -825,20 +857,35 @@ hipError_t launch_eval_list(const EvalRun &run, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_eval_binary(const EvalRun &run, hipStream_t s)
+hipError_t launch_eval_binary(const EvalRun &run, float *bsum, int n_seg, hipStream_t s)
 {
     if (run.n_list <= 0) return hipSuccess;
     const dim3 grid(grid_for(run.n_list, 256, (1u << 16)));
     const bool sky = run.arms != nullptr;
+    const int n_blk = (run.n_sft + SUM_BLOCK - 1) / SUM_BLOCK;
+    if (bsum && n_seg > 1 && !sky && run.sum_mode == FT_SUM_BLOCKED) {
+        const int bps = (n_blk + n_seg - 1) / n_seg;
+        const dim3 g2(grid.x, (unsigned)((n_blk + bps - 1) / bps));  // no empty rows
+        if (run.cos_delta > 0.0 && run.range_ok)
+            hipLaunchKernelGGL((eval_binary_kernel<true, false, false, true>), g2, dim3(256), 0, s, run, bsum, bps);
+        else if (run.cos_delta > 0.0)
+            hipLaunchKernelGGL((eval_binary_kernel<true, true, false, true>), g2, dim3(256), 0, s, run, bsum, bps);
+        else
+            hipLaunchKernelGGL((eval_binary_kernel<false, true, false, true>), g2, dim3(256), 0, s, run, bsum, bps);
+        hipLaunchKernelGGL(binary_block_sum_kernel, grid, dim3(256), 0, s, (const float *)bsum, run.n_list, n_blk,
+                           run.stats);
+        return hipGetLastError();
+    }
+    float *const none = nullptr;
     if (run.cos_delta > 0.0 && run.range_ok) {
-        if (sky) hipLaunchKernelGGL((eval_binary_kernel<true, false, true>), grid, dim3(256), 0, s, run);
-        else hipLaunchKernelGGL((eval_binary_kernel<true, false, false>), grid, dim3(256), 0, s, run);
+        if (sky) hipLaunchKernelGGL((eval_binary_kernel<true, false, true>), grid, dim3(256), 0, s, run, none, 0);
+        else hipLaunchKernelGGL((eval_binary_kernel<true, false, false>), grid, dim3(256), 0, s, run, none, 0);
     } else if (run.cos_delta > 0.0) {
-        if (sky) hipLaunchKernelGGL((eval_binary_kernel<true, true, true>), grid, dim3(256), 0, s, run);
-        else hipLaunchKernelGGL((eval_binary_kernel<true, true, false>), grid, dim3(256), 0, s, run);
+        if (sky) hipLaunchKernelGGL((eval_binary_kernel<true, true, true>), grid, dim3(256), 0, s, run, none, 0);
+        else hipLaunchKernelGGL((eval_binary_kernel<true, true, false>), grid, dim3(256), 0, s, run, none, 0);
     } else {
-        if (sky) hipLaunchKernelGGL((eval_binary_kernel<false, true, true>), grid, dim3(256), 0, s, run);
-        else hipLaunchKernelGGL((eval_binary_kernel<false, true, false>), grid, dim3(256), 0, s, run);
+        if (sky) hipLaunchKernelGGL((eval_binary_kernel<false, true, true>), grid, dim3(256), 0, s, run, none, 0);
+        else hipLaunchKernelGGL((eval_binary_kernel<false, true, false>), grid, dim3(256), 0, s, run, none, 0);
     }
     return hipGetLastError();
 }

@@ -228,7 +228,10 @@ hipError_t launch_labels(const double *max_z, int n_runs, double tau, uint8_t *l
                          hipStream_t s);
 hipError_t launch_eval_list(const EvalRun &run, hipStream_t s);
 // Binary-system list bank (run.ap/omega/phib set): one lane per template.
-hipError_t launch_eval_binary(const EvalRun &run, hipStream_t s);
+// bsum: with n_seg > 1 (blocked sums, no sky weights) the SFT blocks are split
+// over n_seg workgroup rows and bsum [ceil(n_sft / SUM_BLOCK)][n_list] holds the
+// per-block FP32 sums; else nullptr.
+hipError_t launch_eval_binary(const EvalRun &run, float *bsum, int n_seg, hipStream_t s);
 // Largest |v_cos_f32(x) - cos 2 pi x| over every float x in [0, 1], as the bit
 // pattern of a non-negative double in *max_bits (device memory).
 hipError_t launch_hw_cos_error(unsigned long long *max_bits, hipStream_t s);

@@ -357,13 +357,26 @@ __device__ __forceinline__ double readlane_f64(double v, int l)
     return __hiloint2double(hi, lo);
 }
 
-// FP64 re-summation of template t in SFT order by one wavefront (lanes form
-// the terms of 64 SFTs at a time, lane 0's result is the sum); the weight is
-// u_k, times ab_k(n) / sum_k' u_k' ab_k'(n) with sky-dependent weights.  With
-// MOM the weight sums W1 = sum w and W2 = sum w^2 come out as well.
+// FP64 re-summation of template t in SFT order by one wavefront: lanes form
+// the terms of 64 RS_UNROLL SFTs at a time and publish them to the wave's LDS
+// slice buf [2][64 RS_UNROLL], then lane 0 adds them one after another in SFT
+// order (the result is lane 0's).  The weight is u_k, times ab_k(n) / sum_k'
+// u_k' ab_k'(n) with sky-dependent weights.  With MOM the weight sums W1 =
+// sum w and W2 = sum w^2 come out as well.  The terms of the next chunk are
+// formed (their gathers issued) before the current chunk is added, so the
+// gathers' latency overlaps the additions.
+constexpr int RS_UNROLL = 4;
+constexpr int RS_BUF = 2 * 64 * RS_UNROLL;  // doubles of LDS per wave
+
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
 template <bool MOM>
 __device__ __forceinline__ double rescore_one(const EvalRun &r, bool grid, int64_t t, int lane, uint32_t &bad,
-                                              double *w1 = nullptr, double *w2 = nullptr)
+                                              double *buf, double *w1 = nullptr, double *w2 = nullptr)
 {
     const TemplateParams tp = params_of(r, grid, t);
     // sky-dependent weights: 1 / sum_k u_k ab_k(n) of the template's sky point
@@ -378,32 +391,77 @@ __device__ __forceinline__ double rescore_one(const EvalRun &r, bool grid, int64
         for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
         inv = 1.0 / part;
     }
-    double acc = 0.0, sw = 0.0, sw2 = 0.0;
-    for (int k0 = 0; k0 < r.n_sft; k0 += 64) {
-        const int k = k0 + lane;
-        double val = 0.0, wk = 0.0;
-        if (k < r.n_sft) {
-            const double *vk = r.v + 3 * (int64_t)k;
-            const double g = doppler_factor(vk[0], vk[1], vk[2], tp.nx, tp.ny, tp.nz);
-            int b = (r.ap ? bin_binary(tp.f0, g, tp.aw, tp.omega, tp.phib, r.dt[k], r.t_sft)
-                          : bin_fp64(tp.f0, tp.f1 * r.dt[k], g, r.t_sft)) -
-                    r.first_bin;
-            if (b < 0 || b >= r.n_bins) {
-                bad = ERR_RANGE;
-                b = b < 0 ? 0 : r.n_bins - 1;
+    // terms of SFTs k0 + 64 j + lane, j < RS_UNROLL (0 past the last SFT)
+    auto terms = [&](int k0, double (&val)[RS_UNROLL], double (&wk)[RS_UNROLL]) {
+#pragma unroll
+        for (int j = 0; j < RS_UNROLL; ++j) {
+            const int k = k0 + 64 * j + lane;
+            val[j] = 0.0;
+            wk[j] = 0.0;
+            if (k < r.n_sft) {
+                const double *vk = r.v + 3 * (int64_t)k;
+                const double g = doppler_factor(vk[0], vk[1], vk[2], tp.nx, tp.ny, tp.nz);
+                int b = (r.ap ? bin_binary(tp.f0, g, tp.aw, tp.omega, tp.phib, r.dt[k], r.t_sft)
+                              : bin_fp64(tp.f0, tp.f1 * r.dt[k], g, r.t_sft)) -
+                        r.first_bin;
+                if (b < 0 || b >= r.n_bins) {
+                    bad = ERR_RANGE;
+                    b = b < 0 ? 0 : r.n_bins - 1;
+                }
+                double w = r.weight ? (double)r.weight[k] : 1.0;
+                if ((grid && r.sky_norm) || bsky) w = w * (sky_ab(r.arms + 6 * (int64_t)k, tp.nx, tp.ny, tp.nz) * inv);
+                val[j] = w * (double)r.power[(int64_t)k * r.n_bins + b];
+                wk[j] = w;
             }
-            double w = r.weight ? (double)r.weight[k] : 1.0;
-            if ((grid && r.sky_norm) || bsky) w = w * (sky_ab(r.arms + 6 * (int64_t)k, tp.nx, tp.ny, tp.nz) * inv);
-            val = w * (double)r.power[(int64_t)k * r.n_bins + b];
-            wk = w;
         }
-        const int m = min(64, r.n_sft - k0);
-        for (int l = 0; l < m; ++l) {
-            acc = acc + readlane_f64(val, l);
-            if (MOM) {
-                const double x = readlane_f64(wk, l);
-                sw = sw + x;
-                sw2 = sw2 + x * x;
+    };
+    double acc = 0.0, sw = 0.0, sw2 = 0.0;
+    double val[RS_UNROLL], wk[RS_UNROLL];
+    terms(0, val, wk);
+    for (int k0 = 0; k0 < r.n_sft; k0 += 64 * RS_UNROLL) {
+        double nval[RS_UNROLL], nwk[RS_UNROLL];
+        const bool more = k0 + 64 * RS_UNROLL < r.n_sft;
+        if (more) terms(k0 + 64 * RS_UNROLL, nval, nwk);
+#pragma unroll
+        for (int j = 0; j < RS_UNROLL; ++j) {
+            buf[64 * j + lane] = val[j];
+            if (MOM) buf[64 * RS_UNROLL + 64 * j + lane] = wk[j];
+        }
+        wave_lds_sync();
+        if (lane == 0) {
+            const int m_all = min(64 * RS_UNROLL, r.n_sft - k0);
+            int q = 0;
+            for (; q + 8 <= m_all; q += 8) {
+                double x[8], y[8];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    x[i] = buf[q + i];
+                    if (MOM) y[i] = buf[64 * RS_UNROLL + q + i];
+                }
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    acc = acc + x[i];
+                    if (MOM) {
+                        sw = sw + y[i];
+                        sw2 = sw2 + y[i] * y[i];
+                    }
+                }
+            }
+            for (; q < m_all; ++q) {
+                acc = acc + buf[q];
+                if (MOM) {
+                    const double y = buf[64 * RS_UNROLL + q];
+                    sw = sw + y;
+                    sw2 = sw2 + y * y;
+                }
+            }
+        }
+        wave_lds_sync();
+        if (more) {
+#pragma unroll
+            for (int j = 0; j < RS_UNROLL; ++j) {
+                val[j] = nval[j];
+                wk[j] = nwk[j];
             }
         }
     }
@@ -420,6 +478,8 @@ __global__ __launch_bounds__(256) void rescore_kernel(EvalRun r, bool grid, cons
                                                       const uint32_t *off, int n_seg,
                                                       int64_t cap, double *s64, double *mom)
 {
+    __shared__ double rs_buf[4 * RS_BUF];
+    double *buf = rs_buf + (threadIdx.x >> 6) * RS_BUF;
     const int lane = threadIdx.x & 63;
     const int64_t total = min((int64_t)off[n_seg], cap);
     const int64_t n_waves = (int64_t)gridDim.x * (blockDim.x >> 6);
@@ -428,14 +488,14 @@ __global__ __launch_bounds__(256) void rescore_kernel(EvalRun r, bool grid, cons
          p += n_waves) {
         if (mom) {
             double w1, w2;
-            const double acc = rescore_one<true>(r, grid, cand[p], lane, bad, &w1, &w2);
+            const double acc = rescore_one<true>(r, grid, cand[p], lane, bad, buf, &w1, &w2);
             if (lane == 0) {
                 s64[p] = acc;
                 mom[2 * p] = w1;
                 mom[2 * p + 1] = w2;
             }
         } else {
-            const double acc = rescore_one<false>(r, grid, cand[p], lane, bad);
+            const double acc = rescore_one<false>(r, grid, cand[p], lane, bad, buf);
             if (lane == 0) s64[p] = acc;
         }
     }
@@ -447,13 +507,15 @@ __global__ __launch_bounds__(256) void rescore_kernel(EvalRun r, bool grid, cons
 __global__ __launch_bounds__(256) void rescore_entries_kernel(EvalRun r, bool grid, const ft_candidate *top,
                                                               const int32_t *n_out, double *out)
 {
+    __shared__ double rs_buf[4 * RS_BUF];
+    double *buf = rs_buf + (threadIdx.x >> 6) * RS_BUF;
     const int lane = threadIdx.x & 63;
     const int64_t total = n_out[0];
     const int64_t n_waves = (int64_t)gridDim.x * (blockDim.x >> 6);
     uint32_t bad = 0;
     for (int64_t p = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); p < total; p += n_waves) {
         double w1, w2;
-        const double acc = rescore_one<true>(r, grid, top[p].index, lane, bad, &w1, &w2);
+        const double acc = rescore_one<true>(r, grid, top[p].index, lane, bad, buf, &w1, &w2);
         if (lane == 0) {
             out[3 * p] = acc;
             out[3 * p + 1] = w1;

@@ -241,3 +241,28 @@ def test_binary_random_bank_sky_weights_at_benchmark_size(ft):
             assert abs(t.z - (exact[t.index] - mu) / sig) <= 1e-9
         rest = St[(sub_all == j)].astype(np.float64)
         assert np.sort(rest)[-k - 1] <= top[-1].s64 * (1 + bound)
+
+
+@pytest.mark.parametrize("cos_mode", [0, 1])
+@pytest.mark.parametrize("n_small", [1000, 100_000])
+def test_split_small_bank_equals_unsplit_bits(ft, n_small, cos_mode):
+    """Banks below 2^19 templates split their 32-SFT blocks over workgroup rows
+    and add the block sums afterwards; the same templates as the head of a bank
+    of 2^19 + 123 (evaluated one lane per template over every SFT) give the same
+    statistics bit for bit.  302 SFTs: 10 blocks, the last one of 14."""
+    import torch
+    w = synth.binary_band(seed=41, n_tmpl=n_small, n_per_det=151)
+    n_big = 2 ** 19 + 123
+    reps = -(-n_big // n_small)
+    big = [np.concatenate([a] * reps)[:n_big] for a in (w.f0, w.sky, w.ap, w.omega, w.phib)]
+    s_small = torch.empty(n_small, dtype=torch.float32, device="cuda")
+    s_big = torch.empty(n_big, dtype=torch.float32, device="cuda")
+    with _ctx(ft, w) as c:
+        c.binary_cos_mode(cos_mode)
+        c.eval_binary(w.f0, w.sky, w.ap, w.omega, w.phib, w.t_ref, 5, w.sub_edges, stats=s_small)
+        c.sync()
+        c.eval_binary(*big, w.t_ref, 5, w.sub_edges, stats=s_big)
+        c.sync()
+    a, b = s_small.cpu().numpy(), s_big.cpu().numpy()
+    assert np.array_equal(a.view(np.uint32), b[:n_small].view(np.uint32))
+    assert np.array_equal(a.view(np.uint32), b[n_small:2 * n_small].view(np.uint32))
