@@ -1316,7 +1316,8 @@ static ft_status check_eval_opts(ft_ctx c, const ft_eval_opts *opts, std::vector
 }
 
 static ft_status launch_eval_select(ft_ctx c, EvalRun &run, bool grid, int tile, int64_t n_t, int64_t n_seg_map,
-                                    const ft_eval_opts *opts, const std::vector<double> &edges, float *stats);
+                                    const ft_eval_opts *opts, const std::vector<double> &edges, float *stats,
+                                    const WindowPlan *tail = nullptr);
 
 // The statistic's tables (number count: the indicator tables) and, for
 // sky-dependent weights, the per-sky buffers the evaluation fills.
@@ -1375,6 +1376,7 @@ ft_status ft_eval_templates(ft_ctx c, const ft_bank *bank, double t_ref, const f
 
     // tile choice and LDS window for the grid kernel
     int tile = -1;
+    WindowPlan tail;  // the tile of the last f1 values (tile -1: none)
     if (grid) {
         const int64_t n0 = bank->n_f0, n1 = bank->n_f1, ns = bank->n_sky;
         const bool uniform = run.eta < 1e-4;
@@ -1410,9 +1412,21 @@ ft_status ft_eval_templates(ft_ctx c, const ft_bank *bank, double t_ref, const f
         run.tiles_sky = wp.tiles_sky;
         if ((int64_t)run.tiles_f0 * run.tiles_f1 * run.tiles_sky >= 0x7fffffffLL)
             return fail(c, FT_E_UNSUPPORTED, "too many tiles");
+        // When JT does not divide n_f1, the last rem f1 values go to the tile of
+        // the same shape with JT = rem (no idle f1 slots); every tile shape gives
+        // the same bits.
+        if (tile >= 0) {
+            const int jt = tile_cfg(tile).JT;
+            const int rem = (int)(n1 % jt);
+            const int comp = rem && n1 > jt ? tile_companion(tile, rem) : -1;
+            if (comp >= 0 && (!run.sky_norm || tile_has_sky_weights(comp)))
+                tail = plan_window(c->f0_h.data(), n0, c->f1_h.data() + (n1 - rem), rem, c->sky_tile_h.data(), ns,
+                                   dt_absmax, c->vmax, c->t_sft, comp);
+        }
     }
 
-    return launch_eval_select(c, run, grid, tile, n_t, grid ? bank->n_f0 : n_t, opts, edges, stats);
+    return launch_eval_select(c, run, grid, tile, n_t, grid ? bank->n_f0 : n_t, opts, edges, stats,
+                              tail.tile >= 0 ? &tail : nullptr);
 }
 
 // Launch sequence of an evaluation: clear flags, map sub-bands, evaluate,
@@ -1439,8 +1453,36 @@ static hipError_t eval_binary(ft_ctx c, const EvalRun &run)
     return launch_eval_binary(run, n_seg > 1 ? c->d_bsum : nullptr, n_seg, c->stream);
 }
 
+// Grid launch of `tile`; with `tail`, the f1 values past the last multiple of
+// JT go to the tail's tile (a view of the same bank: f1 and stats shifted, the
+// output rows keeping the whole bank's f1 count).
+static hipError_t launch_grid(const EvalRun &run, int tile, const WindowPlan *tail, hipStream_t s)
+{
+    if (!tail) return launch_eval_grid(run, tile_cfg(tile), s);
+    const TileCfg &cfg = tile_cfg(tile), &tcfg = tile_cfg(tail->tile);
+    const int n_main = run.n_f1 - tcfg.JT;
+    EvalRun a = run;
+    a.n_f1 = n_main;
+    a.n_f1_stride = run.n_f1;
+    a.tiles_f1 = n_main / cfg.JT;
+    EvalRun b = run;
+    b.f1 = run.f1 + n_main;
+    b.n_f1 = tcfg.JT;
+    b.n_f1_stride = run.n_f1;
+    b.stats = run.stats + (int64_t)n_main * run.n_f0;
+    b.wt = tail->wt;
+    b.wtp = tail->wtp;
+    b.tiles_f0 = tail->tiles_f0;
+    b.tiles_f1 = tail->tiles_f1;
+    b.tiles_sky = tail->tiles_sky;
+    hipError_t e = launch_eval_grid(a, cfg, s);
+    if (e == hipSuccess) e = launch_eval_grid(b, tcfg, s);
+    return e;
+}
+
 static ft_status launch_eval_select(ft_ctx c, EvalRun &run, bool grid, int tile, int64_t n_t, int64_t n_seg_map,
-                                    const ft_eval_opts *opts, const std::vector<double> &edges, float *stats)
+                                    const ft_eval_opts *opts, const std::vector<double> &edges, float *stats,
+                                    const WindowPlan *tail)
 {
     hipError_t e;
     ft_status st;
@@ -1460,7 +1502,7 @@ static ft_status launch_eval_select(ft_ctx c, EvalRun &run, bool grid, int tile,
     if (e == hipSuccess)
         e = run.ap ? eval_binary(c, run)
             : !grid ? launch_eval_list(run, c->stream)
-            : tile < 0 ? launch_eval_grid_direct(run, c->stream) : launch_eval_grid(run, tile_cfg(tile), c->stream);
+            : tile < 0 ? launch_eval_grid_direct(run, c->stream) : launch_grid(run, tile, tail, c->stream);
     if (e == hipSuccess) e = hipEventRecord(c->ev[1], c->stream);
     const double N = (double)c->n_sft;
     // sky-dependent weights: one more rounding per term (the factor)

@@ -46,6 +46,8 @@
 // formed per SFT in the stage preparation.
 #include "ft_internal.h"
 
+#include <cstring>
+
 namespace ft {
 
 namespace {
@@ -496,7 +498,7 @@ __device__ __forceinline__ void eval_tile(const EvalRun &r, int64_t b, float *wi
     for (int jl = 0; jl < JT; ++jl) {
         const int j = tg.j_base + jl;
         if (j > tg.j_last) continue;
-        const int64_t row = (s_orig * r.n_f1 + j) * r.n_f0;
+        const int64_t row = (s_orig * (r.n_f1_stride ? r.n_f1_stride : r.n_f1) + j) * r.n_f0;
 #pragma unroll
         for (int l = 0; l < L; ++l) {
             const int i = i0 + l;
@@ -710,6 +712,19 @@ const TileCfg &tile_cfg(int id) { return kTiles[id].cfg; }
 size_t tile_static_lds(int id) { return kTiles[id].static_lds; }
 
 bool tile_has_sky_weights(int id) { return kTiles[id].sky_fn != nullptr; }
+
+int tile_companion(int id, int jt)
+{
+    const TileCfg &c = kTiles[id].cfg;
+    const char *tail = strstr(c.name, "_K");  // stage length, register budget, pipelining
+    for (int i = 0; i < tile_count(); ++i) {
+        const TileCfg &d = kTiles[i].cfg;
+        if (d.L != c.L || d.NW != c.NW || d.KS != c.KS || d.JT != jt) continue;
+        const char *t2 = strstr(d.name, "_K");
+        if (tail && t2 && strcmp(tail, t2) == 0) return i;
+    }
+    return -1;
+}
 
 hipError_t launch_eval_grid(const EvalRun &run, const TileCfg &cfg, hipStream_t s)
 {

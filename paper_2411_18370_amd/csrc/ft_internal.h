@@ -190,6 +190,8 @@ struct EvalRun {
     int32_t wt;           // LDS window width per SFT (bins, including run padding)
     int32_t wtp;          // wt rounded up to a multiple of 64 (LDS row stride)
     int32_t tiles_f0, tiles_f1, tiles_sky;
+    int32_t n_f1_stride;  // grid: f1 count of the output's rows (0: n_f1); a launch over the f1
+                          // values [j0, j0 + n_f1) has f1 and stats shifted by j0 (rows) already
     int32_t sum_mode;
     int32_t precision;
 };
@@ -207,6 +209,8 @@ int tile_count();
 const TileCfg &tile_cfg(int id);
 size_t tile_static_lds(int id);
 bool tile_has_sky_weights(int id);  // the tile has a form with sky-dependent weights
+// The tile of the same L, NW, KS and register budget with JT = jt, or -1.
+int tile_companion(int id, int jt);
 
 // Launchers (stream-ordered, no synchronisation).
 hipError_t launch_eval_grid(const EvalRun &run, const TileCfg &cfg, hipStream_t s);
