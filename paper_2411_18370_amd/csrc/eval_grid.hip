@@ -695,7 +695,7 @@ const TileEntry kTiles[] = {
     FT_TILE(19, 3, 6, 4, 8),
     FT_TILE_O(20, 3, 6, 4, 8, 4),
     FT_TILE_O(21, 3, 6, 4, 8, 5),
-    FT_TILE_O(22, 5, 3, 4, 8, 4),
+    FT_TILE_OX(22, 5, 3, 4, 8, 4, (&launch_t<5, 3, 4, 8, 4, false, true>)),
     FT_TILE_O(23, 3, 4, 4, 8, 5),
     FT_TILE_PX(24, 5, 4, 4, 8, 4, (&launch_t<5, 4, 4, 8, 4, true, true>)),
     FT_TILE_P(25, 5, 3, 4, 8, 4),

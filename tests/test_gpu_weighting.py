@@ -207,6 +207,34 @@ def test_sky_weights_grid(ft, statistic, tile, uniform):
                 assert S[i] <= got[-1].s64 * (1 + 1e-13)
 
 
+@pytest.mark.parametrize("statistic", [0, 1])
+def test_sky_weights_grid_f1_tail(ft, statistic):
+    """11 f1 values: the tuned tile takes f1 0-7 and the last 3 go to the 3-f1
+    tile of the same shape (both with their sky-weights forms); statistics and
+    toplists against the oracle as for any grid bank."""
+    w = synth.allsky_band(seed=15, n_sky=12, n_per_det=120)
+    assert w.f1.size == 11
+    u = _weights(w, True)
+    S, ms = _sky_case(w, u, statistic)
+    c = _ctx(ft, w, u)
+    try:
+        s32, tops = _grid_eval(ft, c, w, statistic=statistic, weights=ft.FT_WEIGHTS_SKY)
+        info = c.info()
+    finally:
+        c.close()
+    assert ft.ft_tile_name(info.tile) == "L5_J4_W4_K8_O4"
+    assert np.all(np.abs(s32 - S) <= rel_bound(w.t_mid.size, sky=True) * S + 1e-13)
+    n_per_sky = w.f0.size * w.f1.size
+    for got, idx in zip(tops, _want_tops(w, S)):
+        assert len(got) == len(idx)
+        kth = S[idx[-1]]
+        for t in got:
+            assert abs(t.s64 - S[t.index]) <= 1e-13 * S[t.index]
+            s = t.index // n_per_sky
+            assert abs(t.z - (S[t.index] - ms[s, 0]) / ms[s, 1]) <= 1e-9
+            assert S[t.index] >= kth * (1 - 1e-13)
+
+
 def test_weighting_errors(ft):
     w = synth.weighted_small(seed=5, n_sky=4, n_per_det=40)
     c = _ctx(ft, w, arms=False)
