@@ -492,7 +492,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: the statistic shards by sub-band or sky point "
-              "with no exchange, and multi-GPU runs are not part of this build "
+              "with no exchange, and multi-GPU runs are not implemented "
               "(requested --gpus %d, WORLD_SIZE %d)" % (args.gpus, world), file=sys.stderr)
         sys.exit(2)
 
