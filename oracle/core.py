@@ -48,6 +48,15 @@ def _load():
                                            i64, P, P, P]
             lib.ftor_pcos.argtypes = [i64, P, P, P]
             lib.ftor_pcos.restype = None
+            lib.ftor_plog.argtypes = [i64, P, P]
+            lib.ftor_plog.restype = None
+            u32, u64 = C.c_uint32, C.c_uint64
+            lib.ftor_philox.argtypes = [i64, P, u32, u32, P]
+            lib.ftor_philox.restype = None
+            lib.ftor_noise_normals.argtypes = [u64, u32, i32, i32, i64, P, P]
+            lib.ftor_noise_normals.restype = None
+            lib.ftor_gen_table.argtypes = [u64, u32, i32, i32, i64, i64, i32, P, P, P]
+            lib.ftor_gen_table.restype = None
             lib.ftor_bins_binary.argtypes = [i32, P, f64, f64, P, i64, P, P, P, P, P, P]
             lib.ftor_eval_binary.argtypes = [i32, P, f64, f64, i64, i32, P, P, P, i64, P, P, P, P, P,
                                              P, P]
@@ -181,6 +190,47 @@ def pcos(x):
     s = np.empty_like(x)
     lib.ftor_pcos(x.size, _p(x), _p(c), _p(s))
     return c, s
+
+
+def plog(x):
+    """The project's FP64 natural logarithm (finite normal x > 0)."""
+    lib = _load()
+    x = _f64(x)
+    out = np.empty_like(x)
+    lib.ftor_plog(x.size, _p(x), _p(out))
+    return out
+
+
+def philox(ctr, key):
+    """Philox-4x32-10 words [..., 4] (uint32) of counters ctr [..., 4] under key (k0, k1)."""
+    lib = _load()
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    out = np.empty_like(c)
+    lib.ftor_philox(c.size // 4, _p(c), int(key[0]) & 0xFFFFFFFF, int(key[1]) & 0xFFFFFFFF, _p(out))
+    return out
+
+
+def noise_normals(seed, run, n_sft, n_bins, sft_offset=0):
+    """(Re, Im) [n_sft, n_bins] of one run's campaign noise (the C generator)."""
+    lib = _load()
+    re = np.empty((n_sft, n_bins))
+    im = np.empty((n_sft, n_bins))
+    lib.ftor_noise_normals(int(seed) & (2**64 - 1), int(run) & 0xFFFFFFFF, n_sft, n_bins, sft_offset,
+                           _p(re), _p(im))
+    return re, im
+
+
+def gen_table(seed, run, n_sft, n_bins, sft_offset, first_bin, bins, amps):
+    """FP32 power table [n_sft, n_bins]: noise plus signals with absolute bins
+    bins [n_inj, n_sft] (int64, INT64_MIN for none) and Re amplitudes amps
+    [n_inj, n_sft, 3] at bins - 1, bins, bins + 1."""
+    lib = _load()
+    bins = np.ascontiguousarray(bins, dtype=np.int64).reshape(-1, n_sft)
+    amps = np.ascontiguousarray(amps, dtype=np.float64).reshape(-1, n_sft, 3)
+    out = np.empty((n_sft, n_bins), np.float32)
+    lib.ftor_gen_table(int(seed) & (2**64 - 1), int(run) & 0xFFFFFFFF, n_sft, n_bins, sft_offset,
+                       int(first_bin), bins.shape[0], _p(bins), _p(amps), _p(out))
+    return out
 
 
 def bins_binary(t_mid, t_ref, t_sft, v, f0, sky, ap, omega, phib):

@@ -215,6 +215,142 @@ void ftor_pcos(int64_t n, const double *x, double *c_out, double *s_out)
     for (int64_t i = 0; i < n; ++i) psincos(x[i], s_out ? s_out + i : NULL, c_out ? c_out + i : NULL);
 }
 
+/* ---------------------------------------------------------------------------
+ * plog: the project's FP64 natural logarithm, a fixed sequence of IEEE
+ * operations (so any implementation of the same sequence gives the same bits):
+ *   x = m 2^e exactly (frexp), m moved into [sqrt(1/2), sqrt(2)) by doubling;
+ *   s = (m - 1)/(m + 1), z = s*s;
+ *   ln m = 2 atanh(s) = 2s + s*(z*P(z)), P(z) = sum_{n=1..11} 2/(2n+1) z^(n-1)
+ *     in Horner order (|s| <= 0.1716, the first omitted term is below 2^-57
+ *     of ln m);
+ *   ln x = e*LN2_HI + (e*LN2_LO + ln m), LN2_HI = ln 2 cut to 42 bits (so
+ *     e*LN2_HI is exact), LN2_LO the rest rounded to double.
+ * Defined for finite normal x > 0 (the Box-Muller uniforms lie in
+ * [2^-54, 1)).  Coefficients are 2/(2n+1) rounded to double.
+ * ------------------------------------------------------------------------- */
+#define PL_SQRT_HALF 0x1.6a09e667f3bcdp-1
+#define PL_LN2_HI 0x1.62e42fefa3800p-1
+#define PL_LN2_LO 0x1.ef35793c76730p-45
+
+static double plog(double x)
+{
+    int e;
+    double m = frexp(x, &e);
+    if (m < PL_SQRT_HALF) {
+        m = m + m;
+        e = e - 1;
+    }
+    double f = m - 1.0;
+    double s = f / (m + 1.0);
+    double z = s * s;
+    double p = 0x1.642c8590b2164p-4;             /* 2/23 */
+    p = p * z; p = p + 0x1.8618618618618p-4;     /* 2/21 */
+    p = p * z; p = p + 0x1.af286bca1af28p-4;     /* 2/19 */
+    p = p * z; p = p + 0x1.e1e1e1e1e1e1ep-4;     /* 2/17 */
+    p = p * z; p = p + 0x1.1111111111111p-3;     /* 2/15 */
+    p = p * z; p = p + 0x1.3b13b13b13b14p-3;     /* 2/13 */
+    p = p * z; p = p + 0x1.745d1745d1746p-3;     /* 2/11 */
+    p = p * z; p = p + 0x1.c71c71c71c71cp-3;     /* 2/9  */
+    p = p * z; p = p + 0x1.2492492492492p-2;     /* 2/7  */
+    p = p * z; p = p + 0x1.999999999999ap-2;     /* 2/5  */
+    p = p * z; p = p + 0x1.5555555555555p-1;     /* 2/3  */
+    double lm = (s + s) + s * (z * p);
+    double de = (double)e;
+    return de * PL_LN2_HI + (de * PL_LN2_LO + lm);
+}
+
+/* The project logarithm of x[0..n). */
+void ftor_plog(int64_t n, const double *x, double *out)
+{
+    for (int64_t i = 0; i < n; ++i) out[i] = plog(x[i]);
+}
+
+/* ---------------------------------------------------------------------------
+ * Campaign noise (test data): Philox-4x32-10 (Salmon, Moraes, Dror and Shaw,
+ * SC'11) with counter (bin b, SFT k + sft_offset, run, 0) and key (seed_lo,
+ * seed_hi); the two 64-bit halves of its output, top 53 bits m, give the
+ * uniforms (m + 1/2) 2^-53; Box-Muller (Box and Muller 1958):
+ *   r = sqrt(-2 plog(u1)), th = (2 pi) u2, Re = r pcos(th), Im = r psin(th).
+ * ------------------------------------------------------------------------- */
+static void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1)
+{
+    for (int i = 0; i < 10; ++i) {
+        uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
+        uint32_t n0 = (uint32_t)(p1 >> 32) ^ c[1] ^ k0;
+        uint32_t n2 = (uint32_t)(p0 >> 32) ^ c[3] ^ k1;
+        c[0] = n0;
+        c[1] = (uint32_t)p1;
+        c[2] = n2;
+        c[3] = (uint32_t)p0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+}
+
+/* Philox-4x32-10 of n counters ctr[4n] under key (k0, k1) into out[4n]. */
+void ftor_philox(int64_t n, const uint32_t *ctr, uint32_t k0, uint32_t k1, uint32_t *out)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        uint32_t c[4] = {ctr[4 * i], ctr[4 * i + 1], ctr[4 * i + 2], ctr[4 * i + 3]};
+        philox4x32_10(c, k0, k1);
+        for (int j = 0; j < 4; ++j) out[4 * i + j] = c[j];
+    }
+}
+
+static double unit53(uint32_t hi, uint32_t lo)
+{
+    uint64_t m = (((uint64_t)hi << 32) | lo) >> 11;
+    return ((double)m + 0.5) * 0x1p-53;
+}
+
+static void noise_pair(uint64_t seed, uint32_t run, uint32_t k, uint32_t b, double *re, double *im)
+{
+    uint32_t c[4] = {b, k, run, 0u};
+    philox4x32_10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+    double u1 = unit53(c[0], c[1]);
+    double u2 = unit53(c[2], c[3]);
+    double r = sqrt(-2.0 * plog(u1));
+    double th = (2.0 * 0x1.921fb54442d18p+1) * u2;
+    double s, co;
+    psincos(th, &s, &co);
+    *re = r * co;
+    *im = r * s;
+}
+
+/* (Re, Im) [n_sft][n_bins] of one run's noise. */
+void ftor_noise_normals(uint64_t seed, uint32_t run, int32_t n_sft, int32_t n_bins, int64_t sft_offset,
+                        double *re, double *im)
+{
+#pragma omp parallel for schedule(static)
+    for (int32_t k = 0; k < n_sft; ++k)
+        for (int32_t b = 0; b < n_bins; ++b)
+            noise_pair(seed, run, (uint32_t)(k + sft_offset), (uint32_t)b, re + (int64_t)k * n_bins + b,
+                       im + (int64_t)k * n_bins + b);
+}
+
+/* FP32 power table [n_sft][n_bins] of one run: noise plus n_inj signals, signal
+ * i adding amp[(i n_sft + k) 3 + m + 1] to Re at absolute bin
+ * bin[i n_sft + k] + m (m = -1, 0, 1; bin INT64_MIN: none), in signal order. */
+void ftor_gen_table(uint64_t seed, uint32_t run, int32_t n_sft, int32_t n_bins, int64_t sft_offset,
+                    int64_t first_bin, int32_t n_inj, const int64_t *bin, const double *amp, float *out)
+{
+#pragma omp parallel for schedule(static)
+    for (int32_t k = 0; k < n_sft; ++k) {
+        for (int32_t b = 0; b < n_bins; ++b) {
+            double re, im;
+            noise_pair(seed, run, (uint32_t)(k + sft_offset), (uint32_t)b, &re, &im);
+            for (int32_t i = 0; i < n_inj; ++i) {
+                int64_t q = (int64_t)i * n_sft + k;
+                if (bin[q] == INT64_MIN) continue;
+                int64_t m = first_bin + b - bin[q];
+                if (m >= -1 && m <= 1) re = re + amp[3 * q + (m + 1)];
+            }
+            out[(int64_t)k * n_bins + b] = (float)(re * re + im * im);
+        }
+    }
+}
+
 /* Absolute bin of a binary-system template at an SFT (offset dt, velocity v). */
 static int64_t binary_bin(double f0, const double *n, double ap, double omega, double phib,
                           const double *v, double dt, double t_sft)

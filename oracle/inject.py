@@ -23,12 +23,21 @@ hypothesis of Sec. II.B.2:
   e+ = p p^T - q q^T, ex = p q^T + q p^T, (p, q) = (e_alpha, e_delta) rotated by
   psi: p = cos psi e_alpha + sin psi e_delta, q = -sin psi e_alpha + cos psi e_delta.
 
-The GPU generator implements the same specification independently.
+Every transcendental function is one of the project's fixed sequences of IEEE
+operations (the logarithm core.plog, the cosine and sine core.pcos; square roots
+and divisions are correctly rounded), and every dot product is summed in the
+order (x0 y0 + x1 y1) + x2 y2, so any implementation of this specification
+produces the same bits.  The GPU generator implements it independently.
+
+Two implementations of the noise live here: noise_normals (Philox in numpy)
+and the C generator behind generate_table (core.gen_table); tests check that
+they agree bit for bit.
 """
 from __future__ import annotations
 
 import numpy as np
 
+from . import core
 from .core import pcos
 
 M0, M1 = 0xD2511F53, 0xCD9E8D57     # Philox-4x32 round multipliers
@@ -65,9 +74,11 @@ def uniform_pair(words):
 
 
 def box_muller(u1, u2):
-    r = np.sqrt(-2.0 * np.log(u1))
-    th = 2.0 * np.pi * u2
-    return r * np.cos(th), r * np.sin(th)
+    u1 = np.asarray(u1, np.float64)
+    r = np.sqrt(-2.0 * core.plog(u1).reshape(u1.shape))
+    th = 2.0 * np.pi * np.asarray(u2, np.float64)
+    c, s = pcos(th)
+    return r * c.reshape(th.shape), r * s.reshape(th.shape)
 
 
 def noise_normals(seed, run, n_sft, n_bins, sft_offset=0):
@@ -89,22 +100,28 @@ def noise_normals(seed, run, n_sft, n_bins, sft_offset=0):
 def wave_frame(n, psi):
     """Polarisation basis (p, q) of a source in direction n rotated by psi."""
     n = np.asarray(n, np.float64)
-    rho = np.hypot(n[0], n[1])
+    rho = np.sqrt(n[0] * n[0] + n[1] * n[1])
     if rho > 0:
         ea = np.array([-n[1] / rho, n[0] / rho, 0.0])
         ed = np.array([-n[2] * n[0] / rho, -n[2] * n[1] / rho, rho])
     else:  # at a pole: right ascension 0
         ea = np.array([0.0, 1.0, 0.0])
         ed = np.array([-n[2], 0.0, 0.0])
-    cp, sp = np.cos(psi), np.sin(psi)
+    c, s = pcos(np.array([psi], np.float64))
+    cp, sp = float(c[0]), float(s[0])
     return cp * ea + sp * ed, -sp * ea + cp * ed
+
+
+def dot3(a, b):
+    """(a0 b0 + a1 b1) + a2 b2 along the last axis (the canonical order)."""
+    return (a[..., 0] * b[..., 0] + a[..., 1] * b[..., 1]) + a[..., 2] * b[..., 2]
 
 
 def antenna_patterns(arms, n, psi):
     """F+, Fx [N] for arm unit vectors arms [N, 6] = (u, w) and source n, psi."""
     p, q = wave_frame(n, psi)
     u, w = arms[:, :3], arms[:, 3:]
-    up, uq, wp, wq = u @ p, u @ q, w @ p, w @ q
+    up, uq, wp, wq = dot3(u, p), dot3(u, q), dot3(w, p), dot3(w, q)
     fp = 0.5 * ((up * up - uq * uq) - (wp * wp - wq * wq))
     fx = up * uq - wp * wq
     return fp, fx
@@ -137,10 +154,12 @@ def rho2(arms, n, psi, cos_iota, amp, t_sft):
 
 
 def sinc(y):
+    """sin(y)/y (1 at 0) with the project sine."""
     y = np.asarray(y, np.float64)
     out = np.ones_like(y)
     nz = y != 0
-    out[nz] = np.sin(y[nz]) / y[nz]
+    _, s = pcos(y[nz])
+    out[nz] = s / y[nz]
     return out
 
 
@@ -162,6 +181,24 @@ def generate_table(seed, run, t_mid, t_ref, t_sft, v, arms, first_bin, n_bins, i
     amplitude (the strain is a sum of the sources' strains), so each adds its
     leakage amplitudes to Re, in the order given."""
     n_sft = len(t_mid)
+    injs = [] if inj is None else [inj] if isinstance(inj, dict) else list(inj)
+    bins, amps = [], []
+    for one in injs:
+        if one.get("amp", 0.0) == 0.0:
+            continue
+        B, A = signal_amplitudes(np.asarray(t_mid, np.float64), t_ref, t_sft,
+                                 np.asarray(v, np.float64), np.asarray(arms, np.float64), one)
+        bins.append(B)
+        amps.append(A)
+    bins = np.array(bins, np.int64).reshape(-1, n_sft)
+    amps = np.array(amps, np.float64).reshape(-1, n_sft, 3)
+    return core.gen_table(seed, run, n_sft, n_bins, sft_offset, first_bin, bins, amps)
+
+
+def generate_table_numpy(seed, run, t_mid, t_ref, t_sft, v, arms, first_bin, n_bins, inj=None,
+                         sft_offset=0):
+    """generate_table through noise_normals (Philox in numpy): the second implementation."""
+    n_sft = len(t_mid)
     re, im = noise_normals(seed, run, n_sft, n_bins, sft_offset)
     injs = [] if inj is None else [inj] if isinstance(inj, dict) else list(inj)
     for one in injs:
@@ -169,9 +206,9 @@ def generate_table(seed, run, t_mid, t_ref, t_sft, v, arms, first_bin, n_bins, i
             continue
         B, A = signal_amplitudes(np.asarray(t_mid, np.float64), t_ref, t_sft,
                                  np.asarray(v, np.float64), np.asarray(arms, np.float64), one)
-        rows = np.arange(n_sft)
-        for j, m in enumerate((-1, 0, 1)):
-            col = B + m - first_bin
-            ok = (col >= 0) & (col < n_bins)
-            re[rows[ok], col[ok]] += A[ok, j]
+        for k in range(n_sft):
+            for j, m in enumerate((-1, 0, 1)):
+                col = B[k] + m - first_bin
+                if 0 <= col < n_bins:
+                    re[k, col] = re[k, col] + A[k, j]
     return (re * re + im * im).astype(np.float32)

@@ -10,8 +10,18 @@ p = P(P > 3.2) = exp(-3.2 / 2): noise mean p sum w and variance p (1 - p) sum w^
 All-sky weights: w_k(n) proportional to (a_k^2(n) + b_k^2(n)) / S_n,k and
 normalised to sum 1 over the SFTs, a and b the detector response functions
 (F+ = a cos 2psi + b sin 2psi, Fx = b cos 2psi - a sin 2psi, so a^2 + b^2 is
-F+^2 + Fx^2 at any psi, here evaluated at psi = 0 with the injector's antenna
-patterns); 1/S_n,k is the caller's per-SFT weight u_k.
+F+^2 + Fx^2 at any psi); 1/S_n,k is the caller's per-SFT weight u_k.
+
+Canonical FP64 form (both sides evaluate exactly this sequence, so the
+weighted statistics agree bit for bit):
+  x = (u0 n0 + u1 n1) + u2 n2, y = (w0 n0 + w1 n1) + w2 n2,
+  c = (u0 w0 + u1 w1) + u2 w2 (arm unit vectors u, w);
+  ab = ((1 - c c) - ((x x + y y) - (2 (c x)) y)) + 0.25 ((x x - y y)(x x - y y)),
+which is F+^2 + Fx^2 of the detector tensor D = (u u^T - w w^T)/2 written out
+(twice the squared norm of D's transverse-traceless part with respect to n;
+tests check it against the antenna patterns of the injector);
+  W = sum_k u_k ab_k, sequential in SFT order; inv = 1/W;
+  w_k = u_k (ab_k inv).
 """
 from __future__ import annotations
 
@@ -59,7 +69,22 @@ def power_moments(weights):
 
 
 def response_ab(arms, n):
-    """a^2 + b^2 [N] of every SFT's detector for a source in direction n."""
+    """a^2 + b^2 [N] of every SFT's detector for a source in direction n, in
+    the canonical closed form."""
+    a = np.asarray(arms, np.float64)
+    n = np.asarray(n, np.float64)
+    x = (a[:, 0] * n[0] + a[:, 1] * n[1]) + a[:, 2] * n[2]
+    y = (a[:, 3] * n[0] + a[:, 4] * n[1]) + a[:, 5] * n[2]
+    c = (a[:, 0] * a[:, 3] + a[:, 1] * a[:, 4]) + a[:, 2] * a[:, 5]
+    x2 = x * x
+    y2 = y * y
+    dxy = x2 - y2
+    return ((1.0 - c * c) - ((x2 + y2) - (2.0 * (c * x)) * y)) + 0.25 * (dxy * dxy)
+
+
+def response_ab_patterns(arms, n):
+    """a^2 + b^2 as F+^2 + Fx^2 from the injector's antenna patterns at psi = 0
+    (the tensor contraction; used to check the closed form)."""
     fp, fx = antenna_patterns(np.asarray(arms, np.float64), np.asarray(n, np.float64), 0.0)
     return fp * fp + fx * fx
 
@@ -73,11 +98,11 @@ def sky_weights(arms, u, sky):
     uu = np.ones(n_sft) if u is None else np.asarray(u, np.float32).astype(np.float64)
     out = np.empty((sky.shape[0], n_sft))
     for s in range(sky.shape[0]):
-        c = uu * response_ab(arms, sky[s])
-        total = 0.0
-        for x in c:
-            total = total + x
-        out[s] = c / total
+        ab = response_ab(arms, sky[s])
+        c = uu * ab
+        total = np.cumsum(c)[-1]  # sequential in SFT order
+        inv = 1.0 / total
+        out[s] = uu * (ab * inv)
     return out
 
 

@@ -140,3 +140,105 @@ def test_signals_superpose_linearly_in_amplitude():
     zero = dict(a, amp=0.0)
     assert np.array_equal(inject.generate_table(*args, [a, zero]), inject.generate_table(*args, a))
     assert np.array_equal(inject.generate_table(*args, [zero]), inject.generate_table(*args))
+
+
+def _ulp_err(got, want):
+    return np.abs(got - want) / np.spacing(np.abs(want))
+
+
+def test_plog_against_libm():
+    """The project logarithm (a fixed sequence of IEEE operations) against the
+    C library's log: within 2 ulp over the Box-Muller range [2^-54, 1), exact
+    at 1, and e ln 2 at powers of two within an ulp."""
+    rng = np.random.default_rng(31)
+    x = np.concatenate([
+        2.0 ** rng.uniform(-54, 0, 400_000),            # log-uniform over the uniforms' range
+        (np.arange(200_000) + 0.5) * 2.0 ** -53,         # the smallest uniforms, exactly as drawn
+        1.0 - (np.arange(1, 200_001)) * 2.0 ** -53,      # next to 1 (ln x ~ x - 1)
+        rng.uniform(0.5, 2.0, 200_000),                  # the reduction's seam at sqrt(1/2)
+        2.0 ** rng.uniform(-1000, 1000, 100_000),
+    ])
+    got = oracle.core.plog(x)
+    want = np.log(x)
+    nz = want != 0
+    assert _ulp_err(got[nz], want[nz]).max() <= 2.0
+    assert oracle.core.plog(np.array([1.0]))[0] == 0.0
+    e = np.arange(-60, 61).astype(np.float64)
+    e = e[e != 0]
+    assert _ulp_err(oracle.core.plog(2.0 ** e), e * np.log(2.0)).max() <= 1.0
+
+
+def test_c_philox_known_answers_and_numpy_agree():
+    """The C Philox-4x32-10 behind the fast table generator gives the published
+    known answers and the same words as the numpy implementation."""
+    kat = json.load(open(os.path.join(GOLDEN, "philox4x32_10_kat.json")))
+    for v in kat["vectors"]:
+        ctr = np.array([int(x, 16) for x in v["ctr"]], np.uint32)
+        key = [int(x, 16) for x in v["key"]]
+        assert [int(x) for x in oracle.core.philox(ctr, key)] == [int(x, 16) for x in v["out"]]
+    rng = np.random.default_rng(32)
+    ctr = rng.integers(0, 2 ** 32, size=(5000, 4), dtype=np.uint64)
+    key = rng.integers(0, 2 ** 32, size=2, dtype=np.uint64)
+    a = oracle.core.philox(ctr.astype(np.uint32), key).astype(np.uint64)
+    b = inject.philox4x32_10(ctr, np.broadcast_to(key, (5000, 2)))
+    assert np.array_equal(a, b)
+
+
+def test_two_table_generators_agree_bit_for_bit():
+    """generate_table (C) and generate_table_numpy (Philox and the signal adds
+    in numpy) are two implementations of one specification: equal bits, with
+    and without signals, at an SFT offset."""
+    w = synth.plain_small(seed=33, n_sky=1)
+    rng = np.random.default_rng(34)
+    injs = [synth.injection_params(rng, 100.02, 100.08, 3.0, 3.0, -1e-10, 1e-10) for _ in range(2)]
+    for inj, off in ((None, 0), (injs[0], 0), (injs, 17)):
+        args = (0xDEADBEEF12, 5, w.t_mid, w.t_ref, w.t_sft, w.v, w.arms, w.first_bin, w.n_bins, inj, off)
+        assert np.array_equal(inject.generate_table(*args), inject.generate_table_numpy(*args))
+
+
+def _zenith_detector(n_sft):
+    """Arms along x and y for every SFT, source at the zenith z, no detector motion."""
+    arms = np.tile(np.array([1.0, 0.0, 0.0, 0.0, 1.0, 0.0]), (n_sft, 1))
+    return arms, np.array([0.0, 0.0, 1.0]), np.zeros((n_sft, 3))
+
+
+def test_rho2_absolute_scale_at_the_zenith():
+    """Source at the zenith of a detector with perpendicular arms, face on
+    (cos iota = 1): F+^2 + Fx^2 = 1 at any psi and A+ = Ax = 1, so the
+    non-centrality 4|h~|^2/(T S_n) with |h~| = (T/2) h0 is exactly T amp^2
+    (amp = h0/sqrt(S_n)).  A factor T/2, or amp in place of amp^2, fails."""
+    arms, n, _ = _zenith_detector(4)
+    t_sft = 1800.0
+    for amp in (0.25, 0.5, 2.0):
+        got = inject.rho2(arms, n, 0.0, 1.0, amp, t_sft)
+        assert np.all(got == t_sft * amp * amp), (amp, got)
+    for psi in np.linspace(-np.pi / 4, np.pi / 4, 9):
+        got = inject.rho2(arms, n, psi, 1.0, 0.25, t_sft)
+        assert np.allclose(got, 112.5, rtol=1e-14, atol=0), (psi, got)
+    # edge on (cos iota = 0): only the plus polarisation, A+ = 1/2
+    got = inject.rho2(arms, n, 0.0, 0.0, 0.25, t_sft)
+    assert np.allclose(got, 112.5 / 4, rtol=4e-16, atol=0)
+
+
+def test_mean_power_at_a_bin_centred_track():
+    """At a track centred on a bin (delta = 0) the generator adds sqrt(rho^2) to
+    Re there and nothing to the neighbours, so the mean power at that bin is
+    2 + T amp^2 (non-central chi^2_2) and 2 next to it; 300 seeds x 50 SFTs."""
+    n_sft, t_sft, amp = 50, 1800.0, 0.25
+    arms, n, v = _zenith_detector(n_sft)
+    t_mid = 1e9 + t_sft * (np.arange(n_sft) + 0.5)
+    B = 180_010
+    inj = dict(f0=B / t_sft, f1=0.0, sky=n, psi=0.0, cos_iota=1.0, amp=amp)
+    _, A = inject.signal_amplitudes(t_mid, t_mid[0], t_sft, v, arms, inj)
+    assert np.allclose(A[:, 1], np.sqrt(t_sft) * amp, rtol=1e-15) and np.all(A[:, [0, 2]] < 1e-12)
+    first = B - 4
+    at, side = [], []
+    for seed in range(300):
+        p = inject.generate_table(500 + seed, 1, t_mid, t_mid[0], t_sft, v, arms, first, 9, inj)
+        at.append(p[:, 4])
+        side.append(p[:, [3, 5]].ravel())
+    at = np.concatenate(at).astype(np.float64)
+    side = np.concatenate(side).astype(np.float64)
+    lam = t_sft * amp * amp
+    assert abs(at.mean() - (2 + lam)) < 5 * np.sqrt((4 + 4 * lam) / at.size)
+    assert abs(side.mean() - 2.0) < 5 * np.sqrt(4.0 / side.size)
