@@ -164,11 +164,15 @@ def bench_precision(ft, synth, log):
     out = {"workload": "2 det x 5000 SFTs, 1000-1000.1 Hz, 180 f0 x 5 f1 x 2e4 sky "
                        "(%.3g evals)" % w.evals}
     for name, mode in (("fp32", ft.FT_INDEX_FP32), ("df64", ft.FT_INDEX_DF64),
-                       ("guarded", ft.FT_INDEX_GUARDED), ("fp64", ft.FT_INDEX_FP64)):
+                       ("guarded_df64", ft.FT_INDEX_GUARDED), ("guarded_fp32", ft.FT_INDEX_GUARDED_FP32),
+                       ("fp64", ft.FT_INDEX_FP64)):
         t0 = time.perf_counter()
-        n = c.count_index_mismatches(w.f0, w.f1, w.sky, w.t_ref, mode)
+        n, fb = c.count_index_mismatches(w.f0, w.f1, w.sky, w.t_ref, mode, fallback=True)
         out["mismatch_" + name] = n
-        log("precision: %s index mismatches %d (%.2f s)" % (name, n, time.perf_counter() - t0))
+        if mode in (ft.FT_INDEX_GUARDED, ft.FT_INDEX_GUARDED_FP32):
+            out["fallback_frac_" + name] = fb / w.evals
+        log("precision: %s index mismatches %d, FP64 fallbacks %d (%.2f s)"
+            % (name, n, fb, time.perf_counter() - t0))
     out["evals"] = w.evals
     stats = torch.empty(w.n_templates, dtype=torch.float32, device=dev)
     for name, mode in (("blocked", ft.FT_SUM_BLOCKED), ("plain", ft.FT_SUM_PLAIN_FP32)):

@@ -172,10 +172,16 @@ ft_status ft_q_sample(ft_ctx ctx, const double *arms, int64_t n, const double *s
 ft_status ft_lib_sincos(ft_ctx ctx, const double *x, int64_t n, double *cos_out, double *sin_out);
 
 enum {
-    FT_INDEX_FP64 = 0,    /* exact: canonical FP64 bins (default)                       */
-    FT_INDEX_FP32 = 1,    /* study: the same expression in FP32                          */
-    FT_INDEX_DF64 = 2,    /* study: unevaluated float-float sums/products, then floor    */
-    FT_INDEX_GUARDED = 3  /* exact: FP32 estimate, FP64 recomputation near half-bins     */
+    FT_INDEX_FP64 = 0,         /* exact: canonical FP64 bins (default)                        */
+    FT_INDEX_FP32 = 1,         /* study: the same expression in FP32                           */
+    FT_INDEX_DF64 = 2,         /* study: unevaluated float-float sums/products, then floor     */
+    FT_INDEX_GUARDED = 3,      /* exact: split double-FP32 (df64) estimate verified against
+                                  FP64: accepted farther than a derived margin beta =
+                                  2^-42 (|x| + |f1 dt| T) + 2^-24 bins from a bin edge,
+                                  else the canonical FP64 bin (beta = 4.7e-7 bins at 1 kHz) */
+    FT_INDEX_GUARDED_FP32 = 4  /* exact: FP32 estimate with margin 16 2^-24 |x| + 2^-20,
+                                  else FP64 (the margin passes half a bin above x = 5.2e5,
+                                  i.e. 290 Hz at T = 1800 s: from there on all FP64)        */
 };
 
 enum { FT_SUM_BLOCKED = 0, FT_SUM_PLAIN_FP32 = 1 };
@@ -413,11 +419,14 @@ ft_status ft_bins(ft_ctx ctx, const ft_bank *bank, double t_ref, int32_t precisi
 
 /*
  * ft_count_index_mismatches -- precision study (bins of FT_INDEX_FP32/DF64/
- * GUARDED against the canonical FP64 bin): number of (template, SFT) pairs of
- * `bank` (GRID or LIST) whose bin differs, written to *n_mismatch.
+ * GUARDED/GUARDED_FP32 against the canonical FP64 bin; the bins of Sec. IV.A):
+ * number of (template, SFT) pairs of `bank` (GRID or LIST) whose bin differs,
+ * written to *n_mismatch, and the number of pairs whose estimate a guarded mode
+ * did not accept (recomputed in FP64) to *n_fallback (may be NULL; 0 for the
+ * unguarded modes).  Synchronous.
  */
 ft_status ft_count_index_mismatches(ft_ctx ctx, const ft_bank *bank, double t_ref,
-                                    int32_t precision, int64_t *n_mismatch);
+                                    int32_t precision, int64_t *n_mismatch, int64_t *n_fallback);
 
 /* One injected continuous-wave signal (Sec. II.B.2).  amp = h0/sqrt(S_n)
  * (the inverse sensitivity depth of Sec. V; 0 = no signal), cos_iota and psi

@@ -459,7 +459,7 @@ ft_status ft_create(ft_ctx *out, int device, void *hip_stream)
     }
     size_t one = 0;
     if (ensure(&c->d_err, &one, 1) != hipSuccess || hipMalloc(&c->d_mu_sigma, 2 * sizeof(double)) != hipSuccess ||
-        hipMalloc(&c->d_count, sizeof(unsigned long long)) != hipSuccess) {
+        hipMalloc(&c->d_count, 2 * sizeof(unsigned long long)) != hipSuccess) {
         ft_destroy(c);
         return FT_E_NOMEM;
     }
@@ -1912,7 +1912,7 @@ ft_status ft_bins(ft_ctx c, const ft_bank *bank, double t_ref, int32_t precision
     c->err.clear();
     if (hipSetDevice(c->device) != hipSuccess) return fail(c, FT_E_DEVICE, "hipSetDevice");
     if (!bins) return fail(c, FT_E_INVALID, "bins is null");
-    if (precision < FT_INDEX_FP64 || precision > FT_INDEX_GUARDED) return fail(c, FT_E_INVALID, "unknown precision");
+    if (precision < FT_INDEX_FP64 || precision > FT_INDEX_GUARDED_FP32) return fail(c, FT_E_INVALID, "unknown precision");
     if (bank && bank->kind != FT_BANK_LIST && bank->kind != FT_BANK_BINARY)
         return fail(c, FT_E_UNSUPPORTED, "ft_bins takes a LIST or BINARY bank");
     if (bank && bank->kind == FT_BANK_BINARY && precision != FT_INDEX_FP64)
@@ -1933,26 +1933,27 @@ ft_status ft_bins(ft_ctx c, const ft_bank *bank, double t_ref, int32_t precision
 }
 
 ft_status ft_count_index_mismatches(ft_ctx c, const ft_bank *bank, double t_ref, int32_t precision,
-                                    int64_t *n_mismatch)
+                                    int64_t *n_mismatch, int64_t *n_fallback)
 {
     if (!c) return FT_E_INVALID;
     c->err.clear();
     if (hipSetDevice(c->device) != hipSuccess) return fail(c, FT_E_DEVICE, "hipSetDevice");
     if (!n_mismatch) return fail(c, FT_E_INVALID, "n_mismatch is null");
     if (bank && bank->kind == FT_BANK_BINARY) return fail(c, FT_E_UNSUPPORTED, "the index study covers GRID and LIST banks");
-    if (precision < FT_INDEX_FP64 || precision > FT_INDEX_GUARDED) return fail(c, FT_E_INVALID, "unknown precision");
+    if (precision < FT_INDEX_FP64 || precision > FT_INDEX_GUARDED_FP32) return fail(c, FT_E_INVALID, "unknown precision");
     EvalRun run;
     bool grid;
     int64_t n_t;
     ft_status st = prepare_bank(c, bank, t_ref, run, grid, n_t);
     if (st != FT_OK) return st;
-    unsigned long long cnt = 0;
+    unsigned long long cnt[2] = {0, 0};
     hipError_t e = hipMemsetAsync(c->d_count, 0, sizeof cnt, c->stream);
     if (e == hipSuccess) e = launch_count_mismatch(run, grid, precision, c->d_count, c->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(&cnt, c->d_count, sizeof cnt, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(cnt, c->d_count, sizeof cnt, hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "count mismatches");
-    *n_mismatch = (int64_t)cnt;
+    *n_mismatch = (int64_t)cnt[0];
+    if (n_fallback) *n_fallback = (int64_t)cnt[1];
     c->have_eval = false;
     return FT_OK;
 }

@@ -71,8 +71,9 @@ __device__ __forceinline__ df df_mul(df a, df b)
     e += cross;
     return fast_two_sum(p, e);
 }
-__device__ __forceinline__ int bin_df64(double f0, double f1, double dt, const double *v,
-                                        const double *n, double t_sft)
+// x + 1/2 of the canonical track in double-float arithmetic; c_out is f1 dt.
+__device__ __forceinline__ df track_df64(double f0, double f1, double dt, const double *v, const double *n,
+                                         double t_sft, df &c_out)
 {
     const df px = df_mul(df_split(v[0]), df_split(n[0]));
     const df py = df_mul(df_split(v[1]), df_split(n[1]));
@@ -80,14 +81,26 @@ __device__ __forceinline__ int bin_df64(double f0, double f1, double dt, const d
     df d = df_add(px, py);
     d = df_add(d, pz);
     const df g = df_add(df{1.f, 0.f}, d);
-    const df c = df_mul(df_split(f1), df_split(dt));
-    const df a = df_add(df_split(f0), c);
+    c_out = df_mul(df_split(f1), df_split(dt));
+    const df a = df_add(df_split(f0), c_out);
     const df f = df_mul(a, g);
     const df x = df_mul(f, df_split(t_sft));
-    const df t = df_add(x, df{0.5f, 0.f});
+    return df_add(x, df{0.5f, 0.f});
+}
+
+// floor of a double-float value below 2^24 (t.hi integral and t.lo < 0: one less).
+__device__ __forceinline__ float df_floor(df t)
+{
     float fl = floorf(t.hi);
     if (fl == t.hi && t.lo < 0.f) fl -= 1.f;
-    return (int)fl;
+    return fl;
+}
+
+__device__ __forceinline__ int bin_df64(double f0, double f1, double dt, const double *v,
+                                        const double *n, double t_sft)
+{
+    df c;
+    return (int)df_floor(track_df64(f0, f1, dt, v, n, t_sft, c));
 }
 
 __device__ __forceinline__ int bin_canonical(double f0, double f1, double dt, const double *v,
@@ -97,12 +110,48 @@ __device__ __forceinline__ int bin_canonical(double f0, double f1, double dt, co
     return bin_fp64(f0, f1 * dt, g, t_sft);
 }
 
+// Split double-FP32 estimate verified against FP64: the double-float value t
+// of x + 1/2 is accepted when its fraction lies farther than beta from a bin
+// edge, otherwise the canonical FP64 bin is computed.  Error bound, with
+// u = 2^-24: the operations are the accurate double-word sum (relative error
+// <= 3u^2) and the double-word product with an FMA two-product (<= 8u^2: the
+// 7u^2 of its FMA form plus the separate rounding of one cross term), after
+// Joldes, Muller and Popescu (ACM TOMS 2017); each double input is split with
+// error <= u^2 |input|.  Propagated through d = (vx nx + vy ny) + vz nz
+// (<= 26u^2 |v|, |n| = 1), g = 1 + d (<= 4u^2), c = f1 dt (<= 10u^2 |c|),
+// a = f0 + c (<= u^2 (4|a| + 11|c|)), f = a g, x = f T (T = 1800 exact) and
+// t = x + 1/2, |t - (x + 1/2)_real| <= 28u^2 (|x| + |c| T) to first order
+// (|v| <= 1e-4).  The canonical FP64 bin's own error is below 8*2^-53 (|x| + 1),
+// and the float fraction (t.hi - floor) + t.lo rounds once (<= 2^-25).  So
+// beta = 2^-42 (|t.hi| + |c.hi| T) + 2^-24 (2^-42 = 64u^2, over twice the
+// derived factor) certifies floor(t) = the canonical bin.  At x = 1.8e6
+// (1 kHz) beta is 4.7e-7 bins, so nearly every evaluation is accepted.
+// Values of 2^24 bins and above (where floats stop holding every integer) are
+// always recomputed.
+__device__ __forceinline__ int bin_guarded(double f0, double f1, double dt, const double *v,
+                                           const double *n, double t_sft, int *fallback)
+{
+    df c;
+    const df t = track_df64(f0, f1, dt, v, n, t_sft, c);
+    const float ta = fabsf(t.hi);
+    if (ta < 0x1p24f) {
+        const float fl = df_floor(t);
+        const float frac = (t.hi - fl) + t.lo;
+        const float beta = 0x1p-42f * (ta + fabsf(c.hi) * (float)t_sft) + 0x1p-24f;
+        if (frac > beta && frac < 1.f - beta) return (int)fl;
+    }
+    ++*fallback;
+    return bin_canonical(f0, f1, dt, v, n, t_sft);
+}
+
 // FP32 estimate accepted only when it is farther from a bin edge than its
 // error bound; otherwise the canonical FP64 bin.  The FP32 evaluation has
 // relative error below 8*2^-24 (input roundings plus five operations), so a
-// margin of 16*2^-24*x + 2^-20 bins certifies the FP32 floor.
-__device__ __forceinline__ int bin_guarded(double f0, double f1, double dt, const double *v,
-                                           const double *n, double t_sft, int *fallback)
+// margin of 16*2^-24*x + 2^-20 bins certifies the FP32 floor.  The margin
+// reaches half a bin at x = 5.2e5 (290 Hz at T = 1800 s): above that every
+// evaluation is recomputed in FP64.
+__device__ __forceinline__ int bin_guarded_fp32(double f0, double f1, double dt, const double *v,
+                                                const double *n, double t_sft, int *fallback)
 {
     const float px = (float)v[0] * (float)n[0];
     const float py = (float)v[1] * (float)n[1];
@@ -131,6 +180,7 @@ __device__ __forceinline__ int bin_mode(int mode, double f0, double f1, double d
     case FT_INDEX_FP32: return bin_fp32(f0, f1, dt, v, n, t_sft);
     case FT_INDEX_DF64: return bin_df64(f0, f1, dt, v, n, t_sft);
     case FT_INDEX_GUARDED: return bin_guarded(f0, f1, dt, v, n, t_sft, fallback);
+    case FT_INDEX_GUARDED_FP32: return bin_guarded_fp32(f0, f1, dt, v, n, t_sft, fallback);
     default: return bin_canonical(f0, f1, dt, v, n, t_sft);
     }
 }
@@ -653,12 +703,14 @@ __global__ __launch_bounds__(256) void bins_list_kernel(EvalRun r, int mode, int
 
 // Index mismatches of `mode` against the canonical FP64 bin; one thread per
 // template, every SFT.
+// count[0] += mismatches, count[1] += evaluations the guarded modes recomputed
+// in FP64.
 template <bool GRID>
 __global__ __launch_bounds__(256) void mismatch_kernel(EvalRun r, int mode,
                                                        unsigned long long *count)
 {
     const int64_t n_t = GRID ? (int64_t)r.n_f0 * r.n_f1 * r.n_sky : r.n_list;
-    unsigned long long mism = 0;
+    unsigned long long mism = 0, fb = 0;
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n_t;
          t += (int64_t)gridDim.x * blockDim.x) {
         double f0, f1;
@@ -683,10 +735,15 @@ __global__ __launch_bounds__(256) void mismatch_kernel(EvalRun r, int mode,
             const int got = bin_mode(mode, f0, f1, r.dt[k], vk, n, r.t_sft, &fallback);
             mism += (ref != got);
         }
+        fb += (unsigned long long)fallback;
     }
-    // wave reduction, one atomic per wave
-    for (int off = 32; off > 0; off >>= 1) mism += __shfl_down(mism, off, 64);
+    // wave reduction, one atomic per counter and wave
+    for (int off = 32; off > 0; off >>= 1) {
+        mism += __shfl_down(mism, off, 64);
+        fb += __shfl_down(fb, off, 64);
+    }
     if ((threadIdx.x & 63) == 0 && mism) atomicAdd(count, mism);
+    if ((threadIdx.x & 63) == 0 && fb) atomicAdd(count + 1, fb);
 }
 
 __global__ void check_table_kernel(const float *power, const float *weight, int64_t n_rows,
@@ -791,28 +848,21 @@ __global__ void nc_table_kernel(const float *power, const float *weight, float *
     }
 }
 
-__device__ __forceinline__ double wave_sum(double x)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-    return x;
-}
-
-// Sky-dependent weights, one wavefront per sky point (lanes stride the SFTs):
-// norm = 1 / sum_k u_k ab_k(n), then the moments of w_k = u_k (ab_k norm).
+// Sky-dependent weights, one wavefront per sky point: norm = 1 / W with
+// W = sum_k u_k ab_k(n), then the moments W1 = sum w_k, W2 = sum w_k^2 of
+// w_k = u_k (ab_k norm).  All three sums are sequential in SFT order (lanes
+// form 256 terms at a time into the wave's LDS slice, lane 0 adds them), the
+// canonical order of the oracle, so norm and the moments are bit-exact.
 __global__ __launch_bounds__(256) void sky_moments_kernel(const double *arms, const float *weight, int n_sft,
                                                           const double *sky, int64_t n_sky, int stat, double *norm,
                                                           double *ms, uint32_t *err)
 {
+    __shared__ double sbuf[4][256];
+    double *buf = sbuf[threadIdx.x >> 6];
     const int lane = threadIdx.x & 63;
     for (int64_t s = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); s < n_sky; s += (int64_t)gridDim.x * 4) {
         const double nx = sky[3 * s], ny = sky[3 * s + 1], nz = sky[3 * s + 2];
-        double c1 = 0.0;
-        for (int k = lane; k < n_sft; k += 64) {
-            const double u = weight ? (double)weight[k] : 1.0;
-            c1 += u * sky_ab(arms + 6 * (int64_t)k, nx, ny, nz);
-        }
-        c1 = wave_sum(c1);
+        const double c1 = sky_norm_sum(arms, weight, n_sft, nx, ny, nz, buf, lane);
         if (!(c1 > 0.0 && c1 < 1e300)) {
             if (lane == 0) {
                 atomicOr(err, ERR_BAD_POWER);
@@ -824,14 +874,25 @@ __global__ __launch_bounds__(256) void sky_moments_kernel(const double *arms, co
         }
         const double inv = 1.0 / c1;
         double w1 = 0.0, w2 = 0.0;
-        for (int k = lane; k < n_sft; k += 64) {
-            const double u = weight ? (double)weight[k] : 1.0;
-            const double w = u * (sky_ab(arms + 6 * (int64_t)k, nx, ny, nz) * inv);
-            w1 += w;
-            w2 += w * w;
+        for (int k0 = 0; k0 < n_sft; k0 += 256) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int k = k0 + 64 * j + lane;
+                double w = 0.0;
+                if (k < n_sft) w = (weight ? (double)weight[k] : 1.0) * (sky_ab(arms + 6 * (int64_t)k, nx, ny, nz) * inv);
+                buf[64 * j + lane] = w;
+            }
+            wave_lds_sync();
+            if (lane == 0) {
+                const int m = min(256, n_sft - k0);
+                for (int q = 0; q < m; ++q) {
+                    const double w = buf[q];
+                    w1 = w1 + w;
+                    w2 = w2 + w * w;
+                }
+            }
+            wave_lds_sync();
         }
-        w1 = wave_sum(w1);
-        w2 = wave_sum(w2);
         if (lane == 0) {
             norm[s] = inv;
             stat_moments(stat, w1, w2, ms + 2 * s);

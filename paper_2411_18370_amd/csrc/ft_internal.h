@@ -90,6 +90,39 @@ __device__ __forceinline__ void lib_sincos(double x, double &sin_out, double &co
     sin_out = n == 0 ? s : n == 1 ? c : n == 2 ? -s : -c;
 }
 
+// The library's FP64 natural logarithm for finite normal x > 0, also a fixed
+// sequence of IEEE operations: x = m 2^e (frexp, exact), m doubled into
+// [sqrt(1/2), sqrt(2)); s = (m - 1)/(m + 1), z = s^2; ln m = 2 atanh(s) =
+// 2s + s (z P(z)) with P(z) = sum_{n=1..11} 2/(2n+1) z^(n-1) in Horner form
+// (|s| <= 0.1716: the first omitted term is below 2^-57 of ln m); ln x =
+// e L_hi + (e L_lo + ln m) with L_hi = ln 2 cut to 42 bits (e L_hi exact for
+// |e| < 2^11) and L_lo the rest.  Coefficients are 2/(2n+1) rounded to double.
+__device__ __forceinline__ double lib_log(double x)
+{
+    int e;
+    double m = frexp(x, &e);
+    if (m < 0x1.6a09e667f3bcdp-1) {  // sqrt(1/2)
+        m = m + m;
+        e = e - 1;
+    }
+    const double s = (m - 1.0) / (m + 1.0);
+    const double z = s * s;
+    double p = 2.0 / 23;
+    p = p * z; p = p + 2.0 / 21;
+    p = p * z; p = p + 2.0 / 19;
+    p = p * z; p = p + 2.0 / 17;
+    p = p * z; p = p + 2.0 / 15;
+    p = p * z; p = p + 2.0 / 13;
+    p = p * z; p = p + 2.0 / 11;
+    p = p * z; p = p + 2.0 / 9;
+    p = p * z; p = p + 2.0 / 7;
+    p = p * z; p = p + 2.0 / 5;
+    p = p * z; p = p + 2.0 / 3;
+    const double lm = (s + s) + s * (z * p);
+    const double de = (double)e;
+    return de * 0x1.62e42fefa3800p-1 + (de * 0x1.ef35793c76730p-45 + lm);
+}
+
 // Canonical bin of a binary-system template at an SFT (offset dt from t_ref,
 // Doppler factor g = 1 + v.n in canonical order; aw = a_p * Omega):
 // ph = Omega dt - phi_b, e = aw cos(ph), f = f0 (g - e), B = floor(f T + 1/2).
@@ -127,6 +160,43 @@ __device__ __forceinline__ double sky_ab(ArmPtr arm, double nx, double ny, doubl
     const double x2 = x * x, y2 = y * y;
     const double dxy = x2 - y2;
     return ((1.0 - c * c) - ((x2 + y2) - 2.0 * (c * x) * y)) + 0.25 * (dxy * dxy);
+}
+
+// Orders a wavefront's LDS writes before its own later reads (the lanes of one
+// wave run in lock step; this keeps the compiler from reordering across it).
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Sequential FP64 sum of u_k ab_k(n) over the SFTs k = 0 .. n_sft-1 in SFT order,
+// by one wavefront: lanes form 256 terms at a time into buf[256] (the wave's own
+// LDS slice) and lane 0 adds them one after another.  Every lane returns the sum.
+// This is the normaliser of the all-sky weights w_k = u_k (ab_k / W).
+template <typename ArmPtr>
+__device__ __forceinline__ double sky_norm_sum(ArmPtr arms, const float *weight, int n_sft, double nx, double ny,
+                                               double nz, double *buf, int lane)
+{
+    double acc = 0.0;
+    for (int k0 = 0; k0 < n_sft; k0 += 256) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int k = k0 + 64 * j + lane;
+            double term = 0.0;
+            if (k < n_sft) term = (weight ? (double)weight[k] : 1.0) * sky_ab(arms + 6 * (int64_t)k, nx, ny, nz);
+            buf[64 * j + lane] = term;
+        }
+        wave_lds_sync();
+        if (lane == 0) {
+            const int m = min(256, n_sft - k0);
+            for (int q = 0; q < m; ++q) acc = acc + buf[q];
+        }
+        wave_lds_sync();
+    }
+    const int lo = __builtin_amdgcn_readfirstlane(__double2loint(acc));
+    const int hi = __builtin_amdgcn_readfirstlane(__double2hiint(acc));
+    return __hiloint2double(hi, lo);
 }
 
 // Number-count threshold (Eq. number_count): P > 3.2 as real numbers, which for

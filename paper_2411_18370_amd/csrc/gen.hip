@@ -7,7 +7,11 @@
 // (b, k, run, 0) and key (seed_lo, seed_hi); the two 64-bit halves of the
 // output give two uniforms (m + 1/2) 2^-53 (m = top 53 bits) for the
 // Box-Muller transform (Box and Muller 1958): r = sqrt(-2 ln u1),
-// th = 2 pi u2, (Re, Im) = (r cos th, r sin th).
+// th = 2 pi u2, (Re, Im) = (r cos th, r sin th).  The logarithm, cosine and
+// sine are the library's fixed sequences (lib_log, lib_sincos), dot products
+// are summed (x0 y0 + x1 y1) + x2 y2, and square roots and divisions are
+// correctly rounded, so the tables are one fixed sequence of IEEE operations
+// and reproducible bit for bit by any implementation of it.
 //
 // Signal: in SFT k the track is at x_k = ((f0 + f1 dt_k) g_k) T bins (the
 // canonical FP64 track), B_k = floor(x_k + 1/2), delta_k = x_k - B_k; power
@@ -56,7 +60,10 @@ __device__ __forceinline__ double unit53(uint32_t hi, uint32_t lo)
 __device__ __forceinline__ double sinc_pi(double d)
 {
     const double y = M_PI * d;
-    return y != 0.0 ? sin(y) / y : 1.0;
+    if (y == 0.0) return 1.0;
+    double sy, cy;
+    lib_sincos(y, sy, cy);
+    return sy / y;
 }
 
 // Run r of a batch holding global index q, given exclusive prefix sums.
@@ -76,7 +83,7 @@ __device__ __forceinline__ int find_run(const int64_t *prefix, int n_runs, int64
 __device__ __forceinline__ void source_frame(const double *n, double psi, double p[3], double q[3])
 {
     const double n0 = n[0], n1 = n[1], n2 = n[2];
-    const double rho = hypot(n0, n1);
+    const double rho = sqrt(n0 * n0 + n1 * n1);
     double ea[3], ed[3];
     if (rho > 0.0) {
         ea[0] = -n1 / rho;
@@ -93,7 +100,8 @@ __device__ __forceinline__ void source_frame(const double *n, double psi, double
         ed[1] = 0.0;
         ed[2] = 0.0;
     }
-    const double cp = cos(psi), sp = sin(psi);
+    double cp, sp;
+    lib_sincos(psi, sp, cp);
     for (int i = 0; i < 3; ++i) {
         p[i] = cp * ea[i] + sp * ed[i];
         q[i] = -sp * ea[i] + cp * ed[i];
@@ -217,16 +225,18 @@ __global__ __launch_bounds__(256) void gen_noise_kernel(const GenRun *runs, int 
             philox4x32_10(c, (uint32_t)g.seed, (uint32_t)(g.seed >> 32));
             const double u1 = unit53(c[0], c[1]);
             const double u2 = unit53(c[2], c[3]);
-            const double r = sqrt(-2.0 * log(u1));
+            const double r = sqrt(-2.0 * lib_log(u1));
             const double th = 2.0 * M_PI * u2;
-            double re = r * cos(th);
-            const double im = r * sin(th);
+            double sth, cth;
+            lib_sincos(th, sth, cth);
+            double re = r * cth;
+            const double im = r * sth;
             for (int i = 0; i < g.n_inj; ++i) {
                 const int64_t ki = (int64_t)i * g.n_sft + k;
                 const int32_t B = g.inj_bin[ki];
                 if (B == INT32_MIN) continue;
                 const int64_t m = g.first_bin + b - (int64_t)B;
-                if (m >= -1 && m <= 1) re += g.inj_amp[3 * ki + (int)(m + 1)];
+                if (m >= -1 && m <= 1) re = re + g.inj_amp[3 * ki + (int)(m + 1)];
             }
             row[b] = (float)(re * re + im * im);
         }

@@ -368,11 +368,6 @@ __device__ __forceinline__ double readlane_f64(double v, int l)
 constexpr int RS_UNROLL = 4;
 constexpr int RS_BUF = 2 * 64 * RS_UNROLL;  // doubles of LDS per wave
 
-__device__ __forceinline__ void wave_lds_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-}
 
 template <bool MOM>
 __device__ __forceinline__ double rescore_one(const EvalRun &r, bool grid, int64_t t, int lane, uint32_t &bad,
@@ -383,14 +378,7 @@ __device__ __forceinline__ double rescore_one(const EvalRun &r, bool grid, int64
     // (grid: per sky point, precomputed; binary banks: per template, here)
     const bool bsky = !grid && r.arms;
     double inv = grid && r.sky_norm ? r.sky_norm[t / ((int64_t)r.n_f0 * r.n_f1)] : 0.0;
-    if (bsky) {
-        double part = 0.0;
-        for (int k = lane; k < r.n_sft; k += 64)
-            part += (r.weight ? (double)r.weight[k] : 1.0) * sky_ab(r.arms + 6 * (int64_t)k, tp.nx, tp.ny, tp.nz);
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
-        inv = 1.0 / part;
-    }
+    if (bsky) inv = 1.0 / sky_norm_sum(r.arms, r.weight, r.n_sft, tp.nx, tp.ny, tp.nz, buf, lane);
     // terms of SFTs k0 + 64 j + lane, j < RS_UNROLL (0 past the last SFT)
     auto terms = [&](int k0, double (&val)[RS_UNROLL], double (&wk)[RS_UNROLL]) {
 #pragma unroll

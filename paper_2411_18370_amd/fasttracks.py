@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libfasttracks.so")
 FT_OK, FT_E_INVALID, FT_E_STATE, FT_E_RANGE, FT_E_NOMEM, FT_E_DEVICE, FT_E_UNSUPPORTED, \
     FT_E_INTERNAL = 0, -1, -2, -3, -4, -5, -6, -7
 FT_BANK_GRID, FT_BANK_LIST, FT_BANK_BINARY = 0, 1, 2
-FT_INDEX_FP64, FT_INDEX_FP32, FT_INDEX_DF64, FT_INDEX_GUARDED = 0, 1, 2, 3
+FT_INDEX_FP64, FT_INDEX_FP32, FT_INDEX_DF64, FT_INDEX_GUARDED, FT_INDEX_GUARDED_FP32 = 0, 1, 2, 3, 4
 FT_SUM_BLOCKED, FT_SUM_PLAIN_FP32 = 0, 1
 FT_STAT_POWER, FT_STAT_NUMBER_COUNT = 0, 1
 FT_WEIGHTS_SFT, FT_WEIGHTS_SKY = 0, 1
@@ -160,7 +160,7 @@ def load(path: str = LIB_PATH):
         "ft_eval_binary_random": (C.c_int, [P, C.POINTER(ft_binary_region), C.c_uint64, i64, f64,
                                             C.POINTER(ft_eval_opts), P]),
         "ft_count_index_mismatches": (C.c_int, [P, C.POINTER(ft_bank), f64, i32,
-                                                C.POINTER(i64)]),
+                                                C.POINTER(i64), C.POINTER(i64)]),
         "ft_tile_count": (i32, []),
         "ft_gen_sfts": (C.c_int, [P, i32, P, P, f64, i64, i32, P, P, C.c_uint64, C.c_uint32, f64,
                                   C.POINTER(ft_injection), i32, P]),
@@ -466,12 +466,15 @@ def ft_bins(ctx, f0, f1, sky, t_ref, precision=FT_INDEX_FP64):
     return out
 
 
-def ft_count_index_mismatches(ctx, f0, f1, sky, t_ref, precision, kind=FT_BANK_GRID):
+def ft_count_index_mismatches(ctx, f0, f1, sky, t_ref, precision, kind=FT_BANK_GRID, fallback=False):
+    """Bins of `precision` that differ from the canonical FP64 bin; with
+    fallback=True, (mismatches, evaluations a guarded mode recomputed in FP64)."""
     bank, keep = _bank(f0, f1, sky, kind)
     n = C.c_int64()
+    fb = C.c_int64()
     _check(ctx, load().ft_count_index_mismatches(ctx, C.byref(bank), float(t_ref), precision,
-                                                 C.byref(n)))
-    return int(n.value)
+                                                 C.byref(n), C.byref(fb)))
+    return (int(n.value), int(fb.value)) if fallback else int(n.value)
 
 
 def ft_tile_count():

@@ -1,10 +1,11 @@
 """Parity of the GPU campaign generator with the oracle's FP64 twin.
 
 Both sides draw the same Philox-4x32-10 words (integer arithmetic, exact) and
-compute the same FP64 expressions; only the device and host implementations of
-log, sin, cos, sqrt and hypot differ (each within an ulp or two), so the FP32
-tables agree exactly except for rare last-bit differences.  Injection bins come
-from the canonical FP64 track on both sides and must agree exactly.
+evaluate the same fixed sequence of IEEE operations: the project's logarithm,
+cosine and sine (each side its own implementation of the one published
+sequence), dot products in one order, correctly rounded square roots and
+divisions.  So the FP32 tables agree bit for bit, and injection bins come from
+the canonical FP64 track on both sides.
 """
 import numpy as np
 import pytest
@@ -25,11 +26,9 @@ def _gen_gpu(ft, w, seed, run, inj):
     return out
 
 
-def _assert_tables_close(got, want):
-    ulp = np.spacing(np.maximum(np.abs(want), np.float32(1e-30)).astype(np.float32))
-    diff = np.abs(got.astype(np.float64) - want.astype(np.float64))
-    assert np.all(diff <= 4 * ulp + 1e-30), float((diff / ulp).max())
-    assert np.mean(got == want) > 0.999
+def _assert_tables_equal(got, want):
+    assert got.shape == want.shape
+    assert np.array_equal(got.view(np.uint32), want.view(np.uint32)), int(np.sum(got != want))
 
 
 @pytest.mark.parametrize("amp", [0.0, 0.1, 3.0])
@@ -41,7 +40,7 @@ def test_generated_table_matches_oracle(ft, amp):
     got = _gen_gpu(ft, w, seed, run, inj)
     want = inject.generate_table(seed, run, w.t_mid, w.t_ref, w.t_sft, w.v, w.arms, w.first_bin,
                                  w.n_bins, inj)
-    _assert_tables_close(got, want)
+    _assert_tables_equal(got, want)
 
 
 def test_several_injections_superpose_like_the_oracle(ft):
@@ -57,7 +56,7 @@ def test_several_injections_superpose_like_the_oracle(ft):
     got = _gen_gpu(ft, w, seed, run, [a, z, b])
     want = inject.generate_table(seed, run, w.t_mid, w.t_ref, w.t_sft, w.v, w.arms, w.first_bin,
                                  w.n_bins, [a, z, b])
-    _assert_tables_close(got, want)
+    _assert_tables_equal(got, want)
     one = inject.generate_table(seed, run, w.t_mid, w.t_ref, w.t_sft, w.v, w.arms, w.first_bin,
                                 w.n_bins, a)
     assert np.sum(want != one) > w.n_sft  # the second signal changed the table
@@ -87,8 +86,9 @@ def test_generated_campaign_toplist_recovers_injection(ft):
     assert bad == -1
     order = sorted(range(s64.size), key=lambda t: (-s64[t], t))
     assert top[0].index == order[0]
+    assert [c_.index for c_ in top] == order[:len(top)]
     for c_ in top:
-        assert abs(c_.s64 - s64[c_.index]) <= 1e-9 * s64[c_.index]
+        assert c_.s64 == s64[c_.index]
     # the injection is loud: the loudest template sits at the injected sky point
     assert top[0].index // (len(f0) * len(f1)) == 0 and top[0].z > 20
 
@@ -106,7 +106,7 @@ def test_binary_injection_matches_oracle(ft):
     got = _gen_gpu(ft, w, seed, run, inj)
     want = inject.generate_table(seed, run, w.t_mid, w.t_ref, w.t_sft, w.v, w.arms, w.first_bin,
                                  w.n_bins, inj)
-    _assert_tables_close(got, want)
+    _assert_tables_equal(got, want)
     one = lambda x: np.array([x], np.float64)
     s64, bad = oracle.eval_binary(w.t_mid, w.t_ref, w.t_sft, w.first_bin, want, None, w.v, one(inj["f0"]),
                                   np.asarray(inj["sky"])[None, :], one(inj["ap"]), one(inj["omega"]),
@@ -119,4 +119,4 @@ def test_binary_injection_matches_oracle(ft):
         c.eval_binary(one(inj["f0"]), np.asarray(inj["sky"])[None, :], one(inj["ap"]), one(inj["omega"]),
                       one(inj["phib"]), w.t_ref, 1, np.array([w.region["f0_lo"], w.region["f0_hi"]]))
         top = c.toplist(0, 1)
-    assert abs(top[0].s64 - s64[0]) <= 1e-9 * s64[0]
+    assert top[0].s64 == s64[0]

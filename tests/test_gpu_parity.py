@@ -131,15 +131,21 @@ def test_bins_fp64_bitexact(ft):
         c.load_workload(w)
         got = c.bins(f0, f1, sky, w.t_ref, ft.FT_INDEX_FP64)
         guarded = c.bins(f0, f1, sky, w.t_ref, ft.FT_INDEX_GUARDED)
+        guarded32 = c.bins(f0, f1, sky, w.t_ref, ft.FT_INDEX_GUARDED_FP32)
         fp32 = c.bins(f0, f1, sky, w.t_ref, ft.FT_INDEX_FP32)
         df64 = c.bins(f0, f1, sky, w.t_ref, ft.FT_INDEX_DF64)
-        counts = {m: c.count_index_mismatches(f0, f1, sky, w.t_ref, m, kind=ft.FT_BANK_LIST)
-                  for m in (0, 1, 2, 3)}
+        counts = {m: c.count_index_mismatches(f0, f1, sky, w.t_ref, m, kind=ft.FT_BANK_LIST, fallback=True)
+                  for m in (0, 1, 2, 3, 4)}
     assert np.array_equal(got, want)
     assert np.array_equal(guarded, want)
-    assert counts[0] == 0 and counts[3] == 0
-    assert counts[1] == int(np.sum(fp32 != want)) and counts[1] > 0
-    assert counts[2] == int(np.sum(df64 != want))
+    assert np.array_equal(guarded32, want)
+    assert counts[0] == (0, 0) and counts[3][0] == 0 and counts[4][0] == 0
+    assert counts[1][0] == int(np.sum(fp32 != want)) and counts[1][0] > 0 and counts[1][1] == 0
+    assert counts[2][0] == int(np.sum(df64 != want)) and counts[2][1] == 0
+    # at 1 kHz the df64 margin (4.7e-7 bins) accepts nearly every estimate, the
+    # FP32 margin (1.7 bins) none
+    assert counts[3][1] <= 1e-4 * want.size
+    assert counts[4][1] == want.size
     # FP32 at 1 kHz is off by at most a bin or two; df64 only near half-bins
     assert np.abs(fp32 - want).max() <= 2
     assert np.abs(df64 - want).max() <= 1
@@ -166,6 +172,33 @@ def test_guard_fallback_on_half_bin_grid(ft):
         s32, tops, _ = run_gpu(ft, w, tile=tile)
         assert_stats(s32, s64, n_sft)
         assert_toplists(tops, want, s64, n_sft)
+
+
+def test_guarded_index_modes_on_half_bins(ft):
+    """Tracks placed on half-bins at 1 kHz (zero Doppler, f1 = 0) and a hair to
+    either side: the guarded modes must recompute every such evaluation in FP64
+    and return the canonical bin; the unguarded df64 estimate is not held to it."""
+    import torch
+    n_sft, t_sft, b0 = 64, 1800.0, 1_800_000
+    t_mid = 1.2e9 + t_sft * (np.arange(n_sft) + 0.5)
+    v = np.zeros((n_sft, 3))
+    x = b0 + np.arange(50) + 0.5
+    f0 = np.concatenate([x, np.nextafter(x, 0), np.nextafter(x, np.inf)]) / t_sft
+    f1 = np.zeros_like(f0)
+    sky = np.tile([[0.0, 0.0, 1.0]], (f0.size, 1))
+    first_bin, n_bins = b0 - 4, 64
+    power = np.ones((n_sft, n_bins), np.float32)
+    w = synth.Workload("half-bin-1kHz", t_sft, [n_sft], t_mid, v, 1.2e9, first_bin, n_bins, power,
+                       None, f0[:1], f1[:1], sky[:1], 1, np.array([0.0, 2e3]))
+    want = oracle.bins_list(w.t_mid, w.t_ref, w.t_sft, w.v, f0, f1, sky)
+    with ft.Context(0, torch.cuda.current_stream().cuda_stream) as c:
+        c.load_workload(w)
+        for mode in (ft.FT_INDEX_GUARDED, ft.FT_INDEX_GUARDED_FP32):
+            got = c.bins(f0, f1, sky, w.t_ref, mode)
+            n, fb = c.count_index_mismatches(f0, f1, sky, w.t_ref, mode, kind=ft.FT_BANK_LIST,
+                                             fallback=True)
+            assert np.array_equal(got, want) and n == 0
+            assert fb == want.size  # every one of them within the margin of an edge
 
 
 def test_weights_and_host_inputs(ft):

@@ -31,9 +31,9 @@ def test_labels_match_oracle_max_z(ft):
                                     table, None, base.v, f0, cp.f1, sky)
         assert bad == -1
         z = oracle.critical_ratio(s64, base.n_sft)
-        assert abs(mz[r] - z.max()) <= 1e-9 * max(1.0, abs(z.max()))
-        if abs(z.max() - 3.0) > 1e-6:
-            assert lab[r] == (z.max() > 3.0)
+        # the tables are the oracle's bit for bit, so the loudest z is too
+        assert mz[r] == z.max()
+        assert lab[r] == (z.max() > 3.0)
 
 
 def test_surrogate_tracks_injections_small(ft):

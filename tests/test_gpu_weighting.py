@@ -174,6 +174,18 @@ def _sky_case(w, u, statistic, f0=None):
     return S, ms
 
 
+def _assert_sky_tops(tops, want, S, ms, n_per_sky):
+    """Toplists with the all-sky weights: the same members in the same order as
+    the oracle's, S64 and z equal to the oracle's bit for bit (the weights, their
+    normaliser and moments follow one canonical FP64 sequence on both sides)."""
+    for got, idx in zip(tops, want):
+        assert [t.index for t in got] == [int(i) for i in idx]
+        for t in got:
+            assert t.s64 == S[t.index]
+            s = t.index // n_per_sky
+            assert t.z == (S[t.index] - ms[s, 0]) / ms[s, 1]
+
+
 @pytest.mark.parametrize("statistic", [0, 1])
 @pytest.mark.parametrize("tile,uniform", [(0, True), (25, True), (2, True), (0, False)])
 def test_sky_weights_grid(ft, statistic, tile, uniform):
@@ -190,21 +202,7 @@ def test_sky_weights_grid(ft, statistic, tile, uniform):
     if not uniform:
         assert ft.ft_tile_name(info.tile) == "L1_J4_W4_K16"
     assert np.all(np.abs(s32 - S) <= rel_bound(w.t_mid.size, sky=True) * S + 1e-13)
-    n_per_sky = f0.size * w.f1.size
-    want = _want_tops(w, S, f0)
-    for got, idx in zip(tops, want):
-        assert len(got) == len(idx)
-        kth = S[idx[-1]]
-        for t in got:
-            assert abs(t.s64 - S[t.index]) <= 1e-13 * S[t.index]
-            s = t.index // n_per_sky
-            assert abs(t.z - (S[t.index] - ms[s, 0]) / ms[s, 1]) <= 1e-9
-            # a member may differ from the oracle's only within FP64 rounding of a tie
-            assert S[t.index] >= kth * (1 - 1e-13)
-        gi = {t.index for t in got}
-        for i in idx:
-            if i not in gi:
-                assert S[i] <= got[-1].s64 * (1 + 1e-13)
+    _assert_sky_tops(tops, _want_tops(w, S, f0), S, ms, f0.size * w.f1.size)
 
 
 @pytest.mark.parametrize("statistic", [0, 1])
@@ -224,15 +222,7 @@ def test_sky_weights_grid_f1_tail(ft, statistic):
         c.close()
     assert ft.ft_tile_name(info.tile) == "L5_J4_W4_K8_O4"
     assert np.all(np.abs(s32 - S) <= rel_bound(w.t_mid.size, sky=True) * S + 1e-13)
-    n_per_sky = w.f0.size * w.f1.size
-    for got, idx in zip(tops, _want_tops(w, S)):
-        assert len(got) == len(idx)
-        kth = S[idx[-1]]
-        for t in got:
-            assert abs(t.s64 - S[t.index]) <= 1e-13 * S[t.index]
-            s = t.index // n_per_sky
-            assert abs(t.z - (S[t.index] - ms[s, 0]) / ms[s, 1]) <= 1e-9
-            assert S[t.index] >= kth * (1 - 1e-13)
+    _assert_sky_tops(tops, _want_tops(w, S), S, ms, w.f0.size * w.f1.size)
 
 
 def test_weighting_errors(ft):
@@ -288,8 +278,8 @@ def test_weighting_errors(ft):
 @pytest.mark.parametrize("statistic,cos_mode", [(0, 0), (1, 0), (0, 1)])
 def test_sky_weights_binary_bank(ft, statistic, cos_mode):
     """Binary-system banks with the all-sky weights, normalised per template:
-    statistics within the FP32 bound (plus one rounding of the weight), toplists
-    within FP64 rounding of the weights, z from each template's own moments."""
+    statistics within the FP32 bound (plus one rounding of the weight), toplists,
+    S64 and z (from each template's own moments) equal to the oracle's."""
     import torch
     b = synth.binary_band(seed=31, n_tmpl=3000, n_per_det=200)
     u = np.linspace(0.5, 1.5, b.t_mid.size).astype(np.float32)
@@ -315,17 +305,11 @@ def test_sky_weights_binary_bank(ft, statistic, cos_mode):
         c.close()
     assert np.all(np.abs(s32 - S) <= rel_bound(b.t_mid.size, sky=True) * S + 1e-13)
     want = oracle.toplist(S, oracle.subband(b.f0, b.sub_edges), len(b.sub_edges) - 1, b.k)
-    for got, idx in zip(tops, want):
-        assert len(got) == len(idx)
-        kth = S[idx[-1]]
-        for t in got:
-            assert abs(t.s64 - S[t.index]) <= 1e-13 * S[t.index]
-            assert abs(t.z - (S[t.index] - ms[t.index, 0]) / ms[t.index, 1]) <= 1e-9
-            assert S[t.index] >= kth * (1 - 1e-13)
+    _assert_sky_tops(tops, want, S, ms, 1)
     # the number counts of the first toplist's entries, with the same weights
     ind = ow.number_count_table(b.power)
     nc_want = ow.weighted_sums_at(b.first_bin, ind, W, bins)
     for t, n, zz in zip(tops[0], nc, z_nc):
         mu, sig = ow.nc_moments(W[t.index])
-        assert abs(n - nc_want[t.index]) <= 1e-13 * max(nc_want[t.index], 1e-300)
-        assert abs(zz - (nc_want[t.index] - mu) / sig) <= 1e-9
+        assert n == nc_want[t.index]
+        assert zz == (nc_want[t.index] - mu) / sig
