@@ -428,6 +428,27 @@ ft_status ft_bins(ft_ctx ctx, const ft_bank *bank, double t_ref, int32_t precisi
 ft_status ft_count_index_mismatches(ft_ctx ctx, const ft_bank *bank, double t_ref,
                                     int32_t precision, int64_t *n_mismatch, int64_t *n_fallback);
 
+/*
+ * ft_count_index_mismatches_noalloc -- the same count with no device memory
+ * allocated, for callers that cannot allocate: code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc.  Results equal
+ * ft_count_index_mismatches's for the same inputs.
+ *   bank        GRID or LIST; f0, f1 and sky_xyz are read in place and must be
+ *               device memory of the context's GPU holding the sizes the bank
+ *               states (n_f0 / n_f1 / n_sky*3, or n_list / n_list / n_list*3);
+ *               host pointers are rejected (FT_E_INVALID)
+ *   n_mismatch, n_fallback   host pointers (n_fallback may be NULL)
+ * Scratch: one fixed device array per GPU held by the library until the
+ * process ends (256 B of counters and the N time offsets t_k - t_ref, at most
+ * 131072 SFTs, 1 MiB + 256 B); more SFTs give FT_E_UNSUPPORTED.  Every call on
+ * a GPU shares that array, so calls that overlap on one GPU (other contexts,
+ * other host threads) race; it is cleared by a kernel at the start of each
+ * call.  Needs ft_set_sfts and ft_set_velocities first (FT_E_STATE).  Leaves
+ * the context's evaluation state untouched.  Synchronous.
+ */
+ft_status ft_count_index_mismatches_noalloc(ft_ctx ctx, const ft_bank *bank, double t_ref,
+                                            int32_t precision, int64_t *n_mismatch, int64_t *n_fallback);
+
 /* One injected continuous-wave signal (Sec. II.B.2).  amp = h0/sqrt(S_n)
  * (the inverse sensitivity depth of Sec. V; 0 = no signal), cos_iota and psi
  * its orientation, sky its unit direction, f0/f1 its frequency and spindown at

@@ -464,6 +464,11 @@ ft_status ft_create(ft_ctx *out, int device, void *hip_stream)
         return FT_E_NOMEM;
     }
     (void)hipMemset(c->d_err, 0, sizeof(uint32_t));
+    // the fixed scratch of the no-allocation entry point, resolved once per device
+    if (noalloc_scratch_init(device) != hipSuccess) {
+        ft_destroy(c);
+        return FT_E_DEVICE;
+    }
     for (auto &e : c->ev)
         if (hipEventCreate(&e) != hipSuccess) {
             ft_destroy(c);
@@ -1955,6 +1960,75 @@ ft_status ft_count_index_mismatches(ft_ctx c, const ft_bank *bank, double t_ref,
     *n_mismatch = (int64_t)cnt[0];
     if (n_fallback) *n_fallback = (int64_t)cnt[1];
     c->have_eval = false;
+    return FT_OK;
+}
+
+// True when p is device memory of `device` (memory the kernels may read).
+static bool is_device_memory(const void *p, int device)
+{
+    hipPointerAttribute_t attr;
+    if (hipPointerGetAttributes(&attr, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return attr.type == hipMemoryTypeDevice && attr.device == device;
+}
+
+ft_status ft_count_index_mismatches_noalloc(ft_ctx c, const ft_bank *bank, double t_ref, int32_t precision,
+                                            int64_t *n_mismatch, int64_t *n_fallback)
+{
+    if (!c) return FT_E_INVALID;
+    c->err.clear();
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, FT_E_DEVICE, "hipSetDevice");
+    if (!n_mismatch) return fail(c, FT_E_INVALID, "n_mismatch is null");
+    if (!bank) return fail(c, FT_E_INVALID, "bank is null");
+    if (bank->kind != FT_BANK_GRID && bank->kind != FT_BANK_LIST)
+        return fail(c, FT_E_UNSUPPORTED, "the index study covers GRID and LIST banks");
+    if (precision < FT_INDEX_FP64 || precision > FT_INDEX_GUARDED_FP32) return fail(c, FT_E_INVALID, "unknown precision");
+    if (!c->have_sfts || !c->have_vel) return fail(c, FT_E_STATE, "ft_set_sfts and ft_set_velocities must come first");
+    if (c->n_sft > NOALLOC_MAX_SFT)
+        return fail(c, FT_E_UNSUPPORTED, "%d SFTs: the no-allocation scratch holds at most %d", c->n_sft,
+                    NOALLOC_MAX_SFT);
+    if (!is_finite(t_ref)) return fail(c, FT_E_INVALID, "t_ref must be finite");
+    const bool grid = bank->kind == FT_BANK_GRID;
+    int64_t n0, n1, ns;
+    if (grid) {
+        n0 = bank->n_f0;
+        n1 = bank->n_f1;
+        ns = bank->n_sky;
+        if (n0 < 1 || n1 < 1 || ns < 1) return fail(c, FT_E_INVALID, "grid sizes must be >= 1");
+        if (n0 > 0x7fffffff || n1 > 0x7fffffff || ns > 0x7fffffff)
+            return fail(c, FT_E_UNSUPPORTED, "grid dimension above 2^31-1");
+        if (n0 * n1 > (1LL << 40) / ns) return fail(c, FT_E_UNSUPPORTED, "more than 2^40 templates in one call");
+    } else {
+        n0 = n1 = ns = bank->n_list;
+        if (n0 < 1) return fail(c, FT_E_INVALID, "n_list must be >= 1");
+    }
+    if (!bank->f0 || !bank->f1 || !bank->sky_xyz) return fail(c, FT_E_INVALID, "bank arrays must be non-null");
+    if (!is_device_memory(bank->f0, c->device) || !is_device_memory(bank->f1, c->device) ||
+        !is_device_memory(bank->sky_xyz, c->device))
+        return fail(c, FT_E_INVALID, "the no-allocation call reads the bank in place: f0, f1 and sky_xyz must be "
+                                     "device memory of the context's GPU");
+    void *scratch_ptr = noalloc_scratch_ptr(c->device);
+    if (!scratch_ptr) return fail(c, FT_E_DEVICE, "no scratch address on device %d", c->device);
+    EvalRun run{};
+    run.v = c->d_v;
+    run.f0 = bank->f0;
+    run.f1 = bank->f1;
+    run.sky = bank->sky_xyz;
+    run.n_sft = c->n_sft;
+    run.t_sft = c->t_sft;
+    run.n_f0 = (int32_t)n0;
+    run.n_f1 = (int32_t)n1;
+    run.n_sky = (int32_t)ns;
+    run.n_list = grid ? 0 : n0;
+    unsigned long long cnt[2] = {0, 0};
+    hipError_t e = launch_count_mismatch_noalloc(run, grid, precision, c->d_tmid, t_ref, scratch_ptr, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(cnt, scratch_ptr, sizeof cnt, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "count mismatches (no allocation)");
+    *n_mismatch = (int64_t)cnt[0];
+    if (n_fallback) *n_fallback = (int64_t)cnt[1];
     return FT_OK;
 }
 

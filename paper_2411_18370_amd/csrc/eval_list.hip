@@ -2,6 +2,8 @@
 // structure -- the batch evaluation of Sec. III), bin dumps and the index
 // precision study (FP32 / split double-FP32 / guarded against FP64), plus the
 // small helper kernels of the host layer.
+#include <mutex>
+
 #include "ft_internal.h"
 
 namespace ft {
@@ -1003,6 +1005,66 @@ hipError_t launch_count_mismatch(const EvalRun &run, bool grid, int precision,
         hipLaunchKernelGGL(mismatch_kernel<false>, dim3(grid_for(n, 256, (1u << 22))),
                            dim3(256), 0, s, run, precision, count);
     return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Scratch of the no-allocation mismatch count.  Each GPU the library runs on
+// holds its own copy of this array until the process ends; every call on a
+// GPU shares it (calls that overlap on one GPU race).  Host code never names
+// the array: it uses the address hipGetSymbolAddress returns on each device.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) double scratch[NOALLOC_HEAD + NOALLOC_MAX_SFT];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// counters[0..1] = 0; dt[k] = t_mid[k] - t_ref (a fill kernel rather than a
+// memset, so the sequence may be captured into a graph).
+__global__ void noalloc_prep_kernel(const double *t_mid, double t_ref, int n, double *dt,
+                                    unsigned long long *counters)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < 2) counters[i] = 0ull;
+    for (int k = i; k < n; k += gridDim.x * blockDim.x) dt[k] = t_mid[k] - t_ref;
+}
+
+}  // namespace
+
+hipError_t noalloc_scratch_init(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[device]) return hipSuccess;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_ptr[device] = p;
+    return hipSuccess;
+}
+
+void *noalloc_scratch_ptr(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return g_scratch_ptr[device];
+}
+
+hipError_t launch_count_mismatch_noalloc(EvalRun run, bool grid, int precision, const double *t_mid, double t_ref,
+                                         void *scratch_ptr, hipStream_t s)
+{
+    if (!scratch_ptr || run.n_sft < 1 || run.n_sft > NOALLOC_MAX_SFT) return hipErrorInvalidValue;
+    unsigned long long *counters = (unsigned long long *)scratch_ptr;
+    double *dt = (double *)scratch_ptr + NOALLOC_HEAD;
+    hipLaunchKernelGGL(noalloc_prep_kernel, dim3(grid_for(run.n_sft, 256, 512)), dim3(256), 0, s, t_mid, t_ref,
+                       run.n_sft, dt, counters);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    run.dt = dt;
+    return launch_count_mismatch(run, grid, precision, counters, s);
 }
 
 hipError_t launch_check_table(const float *power, const float *weight, int64_t n_rows,

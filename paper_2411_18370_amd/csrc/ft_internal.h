@@ -318,6 +318,21 @@ hipError_t launch_lds_probe(const TileCfg &cfg, int n_blocks, int n_step, int wt
 hipError_t launch_bins_list(const EvalRun &run, int precision, int32_t *bins, hipStream_t s);
 hipError_t launch_count_mismatch(const EvalRun &run, bool grid, int precision,
                                  unsigned long long *count, hipStream_t s);
+// No-allocation form of the mismatch count (ft_count_index_mismatches_noalloc).
+// Its scratch is one fixed device array per GPU: two 64-bit counters in the
+// first NOALLOC_HEAD doubles, then dt_k = t_k - t_ref for up to
+// NOALLOC_MAX_SFT SFTs (256 B + 1 MiB in all).
+constexpr int NOALLOC_HEAD = 32;
+constexpr int NOALLOC_MAX_SFT = 131072;
+// Resolves the scratch array's address on `device` (which must be current)
+// once; later calls return at once.
+hipError_t noalloc_scratch_init(int device);
+// The scratch address on `device` (nullptr before noalloc_scratch_init).
+void *noalloc_scratch_ptr(int device);
+// Clears the counters, forms dt into the scratch and counts the mismatches of
+// run (whose dt is replaced by the scratch's) into them.
+hipError_t launch_count_mismatch_noalloc(EvalRun run, bool grid, int precision, const double *t_mid, double t_ref,
+                                         void *scratch_ptr, hipStream_t s);
 hipError_t launch_check_table(const float *power, const float *weight, int64_t n_rows,
                               int64_t n_cols, uint32_t *err, hipStream_t s);
 hipError_t launch_weight_table(const float *power, const float *weight, float *out,

@@ -122,7 +122,8 @@ class ft_tune_entry(C.Structure):
 _lib = None
 EXPORTS = ("ft_create", "ft_destroy", "ft_last_error", "ft_status_string", "ft_set_sfts",
            "ft_set_velocities", "ft_eval_templates", "ft_toplist", "ft_sync",
-           "ft_last_eval_info", "ft_bins", "ft_count_index_mismatches", "ft_lib_sincos",
+           "ft_last_eval_info", "ft_bins", "ft_count_index_mismatches",
+           "ft_count_index_mismatches_noalloc", "ft_lib_sincos",
            "ft_gen_binary_bank", "ft_eval_binary_random", "ft_q_sample", "ft_tile_count",
            "ft_tile_name", "ft_gen_sfts", "ft_eval_batch", "ft_batch_toplist", "ft_batch_labels",
            "ft_batch_replay", "ft_batch_time", "ft_mlp_create", "ft_mlp_destroy",
@@ -161,6 +162,8 @@ def load(path: str = LIB_PATH):
                                             C.POINTER(ft_eval_opts), P]),
         "ft_count_index_mismatches": (C.c_int, [P, C.POINTER(ft_bank), f64, i32,
                                                 C.POINTER(i64), C.POINTER(i64)]),
+        "ft_count_index_mismatches_noalloc": (C.c_int, [P, C.POINTER(ft_bank), f64, i32,
+                                                        C.POINTER(i64), C.POINTER(i64)]),
         "ft_tile_count": (i32, []),
         "ft_gen_sfts": (C.c_int, [P, i32, P, P, f64, i64, i32, P, P, C.c_uint64, C.c_uint32, f64,
                                   C.POINTER(ft_injection), i32, P]),
@@ -477,6 +480,17 @@ def ft_count_index_mismatches(ctx, f0, f1, sky, t_ref, precision, kind=FT_BANK_G
     return (int(n.value), int(fb.value)) if fallback else int(n.value)
 
 
+def ft_count_index_mismatches_noalloc(ctx, f0, f1, sky, t_ref, precision, kind=FT_BANK_GRID):
+    """(mismatches, FP64 fallbacks) as ft_count_index_mismatches, with no device
+    allocation: f0, f1, sky must be device tensors (read in place)."""
+    bank, keep = _bank(f0, f1, sky, kind)
+    n = C.c_int64()
+    fb = C.c_int64()
+    _check(ctx, load().ft_count_index_mismatches_noalloc(ctx, C.byref(bank), float(t_ref), precision,
+                                                         C.byref(n), C.byref(fb)))
+    return int(n.value), int(fb.value)
+
+
 def ft_tile_count():
     return int(load().ft_tile_count())
 
@@ -749,6 +763,9 @@ class Context:
 
     def count_index_mismatches(self, *a, **kw):
         return ft_count_index_mismatches(self.ctx, *a, **kw)
+
+    def count_index_mismatches_noalloc(self, *a, **kw):
+        return ft_count_index_mismatches_noalloc(self.ctx, *a, **kw)
 
     def eval_batch(self, *a, **kw):
         ft_eval_batch(self.ctx, *a, **kw)
