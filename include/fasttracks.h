@@ -632,6 +632,34 @@ ft_status ft_tune_clear(ft_ctx ctx);
  */
 ft_status ft_probe_lds_gather(ft_ctx ctx, int32_t tile, int32_t wtp, double *evals_per_s);
 
+/*
+ * Chip ceilings measured on the device (the denominators of the roofline
+ * fractions; vendor nominal figures are not measurements).
+ *
+ * ft_probe_lds_read: LDS read bandwidth (bytes per second, whole chip) of one
+ * instruction form, FT_LDS_*: 4-wave workgroups, 8 per CU, each lane reading
+ * 8 dwords per iteration of a 16 KB LDS array with consecutive lanes at
+ * consecutive addresses; consume_all != 0 adds every dword read into an FP32
+ * accumulator (the gather-sum's VALU load), 0 adds one per instruction.
+ * Timed with HIP events over 2048 workgroups x 4096 iterations after a
+ * warm-up launch; synchronises.
+ *
+ * ft_probe_hbm_read: read bandwidth of HBM (bytes per second) of a streaming
+ * kernel (16 bytes per lane per load) over `bytes` of device memory (rounded
+ * down to 16 B; at least 1 GiB, so the 256 MB last-level cache cannot hold
+ * it), allocated by the call and freed before it returns; synchronises.
+ */
+enum {
+    FT_LDS_B32 = 0,           /* ds_read_b32                                       */
+    FT_LDS_READ2ST64 = 1,     /* ds_read2st64_b32: two rows of 64 dwords           */
+    FT_LDS_READ2_ADJ = 2,     /* ds_read2_b32 of two adjacent dwords, 4-byte aligned */
+    FT_LDS_B64 = 3,           /* ds_read_b64, 8-byte aligned                       */
+    FT_LDS_B128 = 4,          /* ds_read_b128, 16-byte aligned                     */
+    FT_LDS_READ2ST64_B64 = 5  /* ds_read2st64_b64: two 8-byte pairs 512 bytes apart */
+};
+ft_status ft_probe_lds_read(ft_ctx ctx, int32_t form, int32_t consume_all, double *bytes_per_s);
+ft_status ft_probe_hbm_read(ft_ctx ctx, int64_t bytes, double *bytes_per_s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfasttracks.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-SOURCES = ["api.cpp", "eval_grid.hip", "eval_list.hip", "select.hip", "gen.hip", "mlp.hip"]
+SOURCES = ["api.cpp", "eval_grid.hip", "eval_list.hip", "select.hip", "gen.hip", "mlp.hip", "probe.hip"]
 # -ffp-contract=off: the bin index expression must never be fused into an FMA.
 # -packed-fp32-ops off: no v_pk_*_f32 instructions are generated.
 FLAGS = ["-O3", "--offload-arch=gfx950", "-fPIC", "-std=c++17", "-ffp-contract=off",

@@ -426,6 +426,59 @@ ft_status ft_probe_lds_gather(ft_ctx c, int32_t tile, int32_t wtp, double *evals
     return FT_OK;
 }
 
+ft_status ft_probe_lds_read(ft_ctx c, int32_t form, int32_t consume_all, double *bytes_per_s)
+{
+    if (!c) return FT_E_INVALID;
+    c->err.clear();
+    if (!bytes_per_s) return fail(c, FT_E_INVALID, "bytes_per_s must be non-null");
+    if (form < FT_LDS_B32 || form > FT_LDS_READ2ST64_B64) return fail(c, FT_E_INVALID, "unknown LDS read form %d", form);
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, FT_E_DEVICE, "hipSetDevice");
+    const int n_blocks = 8 * 256, n_iter = 4096;
+    hipError_t e = ensure(&c->d_probe, &c->cap_probe, (size_t)n_blocks * 256);
+    if (e == hipSuccess) e = launch_lds_read_probe(form, consume_all != 0, n_blocks, 64, c->d_probe, c->stream);
+    if (e == hipSuccess) e = hipEventRecord(c->ev[0], c->stream);
+    if (e == hipSuccess) e = launch_lds_read_probe(form, consume_all != 0, n_blocks, n_iter, c->d_probe, c->stream);
+    if (e == hipSuccess) e = hipEventRecord(c->ev[1], c->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(c->ev[1]);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, c->ev[0], c->ev[1]);
+    if (e != hipSuccess) return hip_fail(c, e, "LDS read probe");
+    const double bytes = (double)n_blocks * 256 * n_iter * 8 * 4.0;
+    *bytes_per_s = ms > 0.f ? bytes / (ms * 1e-3) : 0.0;
+    return FT_OK;
+}
+
+ft_status ft_probe_hbm_read(ft_ctx c, int64_t bytes, double *bytes_per_s)
+{
+    if (!c) return FT_E_INVALID;
+    c->err.clear();
+    if (!bytes_per_s) return fail(c, FT_E_INVALID, "bytes_per_s must be non-null");
+    bytes &= ~(int64_t)15;
+    if (bytes < ((int64_t)1 << 30)) return fail(c, FT_E_INVALID, "at least 1 GiB, got %lld", (long long)bytes);
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, FT_E_DEVICE, "hipSetDevice");
+    void *src = nullptr;
+    if (hipMalloc(&src, (size_t)bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(c, FT_E_NOMEM, "HBM probe buffer of %lld bytes", (long long)bytes);
+    }
+    const int n_blocks = 256 * 16;
+    hipError_t e = ensure(&c->d_probe, &c->cap_probe, (size_t)n_blocks * 256);
+    if (e == hipSuccess) e = launch_fill_u32((uint32_t *)src, 0u, bytes / 4, c->stream);
+    if (e == hipSuccess) e = launch_hbm_read_probe(src, bytes, n_blocks, c->d_probe, c->stream);  // warm-up
+    if (e == hipSuccess) e = hipEventRecord(c->ev[0], c->stream);
+    const int reps = 5;
+    for (int i = 0; i < reps && e == hipSuccess; ++i) e = launch_hbm_read_probe(src, bytes, n_blocks, c->d_probe, c->stream);
+    if (e == hipSuccess) e = hipEventRecord(c->ev[1], c->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(c->ev[1]);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, c->ev[0], c->ev[1]);
+    (void)hipStreamSynchronize(c->stream);
+    (void)hipFree(src);
+    if (e != hipSuccess) return hip_fail(c, e, "HBM read probe");
+    *bytes_per_s = ms > 0.f ? (double)bytes * reps / (ms * 1e-3) : 0.0;
+    return FT_OK;
+}
+
 ft_status ft_tune_clear(ft_ctx c)
 {
     if (!c) return FT_E_INVALID;

@@ -315,6 +315,11 @@ hipError_t launch_eval_grid_direct(const EvalRun &run, hipStream_t s);
 // LDS gather probe of a tile shape: n_blocks workgroups, n_step SFT steps over
 // a staged window of LDS row stride wtp; out [n_blocks * 64 NW] floats.
 hipError_t launch_lds_probe(const TileCfg &cfg, int n_blocks, int n_step, int wtp, float *out, hipStream_t s);
+// Chip-ceiling microbenchmarks: LDS reads of one FT_LDS_* form (n_blocks
+// workgroups of 256 lanes, out [n_blocks * 256]) and a streaming HBM read of
+// `bytes` from src (out [n_blocks * 256]).
+hipError_t launch_lds_read_probe(int form, bool consume_all, int n_blocks, int n_iter, float *out, hipStream_t s);
+hipError_t launch_hbm_read_probe(const void *src, int64_t bytes, int n_blocks, float *out, hipStream_t s);
 hipError_t launch_bins_list(const EvalRun &run, int precision, int32_t *bins, hipStream_t s);
 hipError_t launch_count_mismatch(const EvalRun &run, bool grid, int precision,
                                  unsigned long long *count, hipStream_t s);

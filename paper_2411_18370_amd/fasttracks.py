@@ -23,6 +23,9 @@ FT_SUM_BLOCKED, FT_SUM_PLAIN_FP32 = 0, 1
 FT_STAT_POWER, FT_STAT_NUMBER_COUNT = 0, 1
 FT_WEIGHTS_SFT, FT_WEIGHTS_SKY = 0, 1
 FT_TILE_TUNE = -1
+FT_LDS_B32, FT_LDS_READ2ST64, FT_LDS_READ2_ADJ, FT_LDS_B64, FT_LDS_B128, FT_LDS_READ2ST64_B64 = range(6)
+LDS_FORMS = {"b32": FT_LDS_B32, "read2st64_b32": FT_LDS_READ2ST64, "read2_b32_adjacent": FT_LDS_READ2_ADJ,
+             "b64": FT_LDS_B64, "b128": FT_LDS_B128, "read2st64_b64": FT_LDS_READ2ST64_B64}
 
 
 class FtError(RuntimeError):
@@ -129,7 +132,8 @@ EXPORTS = ("ft_create", "ft_destroy", "ft_last_error", "ft_status_string", "ft_s
            "ft_batch_replay", "ft_batch_time", "ft_mlp_create", "ft_mlp_destroy",
            "ft_mlp_get_params", "ft_mlp_predict", "ft_mlp_loss_grad", "ft_mlp_train",
            "ft_tune_report", "ft_tune_clear", "ft_probe_lds_gather", "ft_set_arms",
-           "ft_toplist_number_count", "ft_eval_binary_boxes", "ft_binary_cos_mode")
+           "ft_toplist_number_count", "ft_eval_binary_boxes", "ft_binary_cos_mode",
+           "ft_probe_lds_read", "ft_probe_hbm_read")
 
 
 def load(path: str = LIB_PATH):
@@ -183,6 +187,8 @@ def load(path: str = LIB_PATH):
                                      C.POINTER(f64)]),
         "ft_tune_clear": (C.c_int, [P]),
         "ft_probe_lds_gather": (C.c_int, [P, i32, i32, C.POINTER(f64)]),
+        "ft_probe_lds_read": (C.c_int, [P, i32, i32, C.POINTER(f64)]),
+        "ft_probe_hbm_read": (C.c_int, [P, i64, C.POINTER(f64)]),
         "ft_set_arms": (C.c_int, [P, P]),
         "ft_binary_cos_mode": (C.c_int, [P, i32, C.POINTER(f64)]),
         "ft_eval_binary_boxes": (C.c_int, [P, C.POINTER(ft_binary_region), C.c_uint64, i64, f64,
@@ -519,6 +525,18 @@ def ft_probe_lds_gather(ctx, tile, wtp=0):
     return r.value
 
 
+def ft_probe_lds_read(ctx, form, consume_all=True):
+    r = C.c_double()
+    _check(ctx, load().ft_probe_lds_read(ctx, int(form), int(bool(consume_all)), C.byref(r)))
+    return r.value
+
+
+def ft_probe_hbm_read(ctx, n_bytes=4 << 30):
+    r = C.c_double()
+    _check(ctx, load().ft_probe_hbm_read(ctx, int(n_bytes), C.byref(r)))
+    return r.value
+
+
 def ft_tile_name(tile):
     return load().ft_tile_name(tile).decode()
 
@@ -790,6 +808,12 @@ class Context:
 
     def probe_lds_gather(self, tile, wtp=0):
         return ft_probe_lds_gather(self.ctx, tile, wtp)
+
+    def probe_lds_read(self, form, consume_all=True):
+        return ft_probe_lds_read(self.ctx, form, consume_all)
+
+    def probe_hbm_read(self, n_bytes=4 << 30):
+        return ft_probe_hbm_read(self.ctx, n_bytes)
 
     def eval_campaign(self, cp, use_graph=0, tile=0, power=None):
         """Evaluate a synth.Campaign (tables generated on the GPU unless given)."""

@@ -1,10 +1,15 @@
 """The all-sky band at its full size -- 2 detectors x 5000 SFTs, 900 f0 x 11 f1 x
 1e5 sky points (9.9e8 templates), K = 100 in each of 10 sub-bands, 3 injected
 signals -- in the launch configuration the benchmark times (autotuned tile).
-The oracle cannot evaluate 9.9e12 template-SFT pairs, so it checks sampled
-templates and every toplist member one by one; properties that hold at any
-size cover the rest (no statistic outside a toplist beats its K-th member
-beyond the FP32 bound; the injections are the loudest candidates near them)."""
+The plain statistic's toplists are compared bit for bit with the oracle's
+evaluation of all 9.9e12 template-SFT pairs (stored under tests/golden/, about
+an hour of host time); sampled templates and every toplist member are checked
+one by one, and properties that hold at any size cover the rest (no statistic
+outside a toplist beats its K-th member beyond the FP32 bound; the injections
+are the loudest candidates near them)."""
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -13,6 +18,16 @@ from oracle import inject
 from paper_2411_18370_amd import synth
 
 pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "allsky_toplists.json")
+
+
+def golden_toplists():
+    """The oracle's exact toplists of the full band (tests/golden/make_allsky_toplists.py):
+    per sub-band, (template index, S64) of its K members in order."""
+    with open(GOLDEN) as fh:
+        doc = json.load(fh)
+    return [[(int(i), float.fromhex(h)) for i, h in top] for top in doc["toplists"]]
 
 
 def rel_bound(n_sft):
@@ -39,6 +54,13 @@ def test_allsky_full_size(ft):
     print("tile", ft.ft_tile_name(info.tile), "eval ms", info.eval_ms, flush=True)
     assert info.tile > 0 and info.n_templates == n0 * n1 * ns
     e = rel_bound(w.n_sft)
+
+    # every toplist of the whole bank, bit for bit: the oracle's full FP64
+    # evaluation of all 9.9e12 template-SFT pairs, written once on the CPU
+    gold = golden_toplists()
+    assert len(gold) == n_sub
+    for jsub, top in enumerate(tops):
+        assert [(t.index, t.s64) for t in top] == gold[jsub], jsub
 
     # sampled templates and every toplist member against the oracle
     rng = np.random.default_rng(5)
