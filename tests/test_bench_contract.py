@@ -44,3 +44,10 @@ def test_traffic_figure_is_tied_to_its_tile_and_source():
     with open(os.path.join(ROOT, "profiles", "eval_grid_allsky_band_traffic.txt")) as fh:
         text = fh.read()
     assert ("source_sha256: " + bench.kernel_source_hash()) in text or t is None
+
+
+def test_cpu_baseline_reports_model_and_one_thread():
+    assert isinstance(bench.cpu_model(), str) and bench.cpu_model()
+    r = bench.cpu_baseline_one_thread(n_sky=1)
+    assert r["cores"] == 1 and r["value"] > 1e7, r
+    assert "first 1 sky points" in r["sample"]
