@@ -321,36 +321,45 @@ def bench_mismatch(ft, synth, log, oversampling=(1.0, 3.44, 10.0), n_trials=100)
     return out
 
 
-def bench_sensitivity(ft, synth, log, o=3.44, tau=8.0, depths=(15.0, 22.0, 27.0, 33.0, 45.0), n_inj=150,
-                      n_q=100_000):
+def bench_sensitivity(ft, synth, log, o=3.44, tau=8.0, depths=(15.0, 22.0, 27.0, 33.0, 45.0), n_inj=500,
+                      n_q=100_000, k_best=16):
     """Semi-analytic sensitivity estimate (Sec. V) against plain injections (the
     comparison of Sec. VI) for the random-bank binary search at oversampling o:
     p_det at each depth from q samples of 10^5 population draws and p(m|o), and
     from n_inj injections per depth (loudest template of a random bank around
-    each), rule z > tau; with the cost of each."""
+    each), rule z > tau; with the cost of each.  The loudest-of-bank noise gain
+    is bracketed by the one-template lower bound and the independent-noise
+    maximum over the k_best smallest mismatches of each bank."""
     import numpy as np
     import torch
     from paper_2411_18370_amd import mismatch, sensitivity
     w = synth.binary_band(seed=3, n_tmpl=1, n_per_det=5000)
     c = ft.Context(0, torch.cuda.current_stream().cuda_stream)
-    m = mismatch.sample(c, w, o=o, n_trials=100, seed=12, amp=1.0)["m"]
+    ms = mismatch.sample(c, w, o=o, n_trials=100, seed=12, amp=1.0, k_best=k_best)
+    m = ms["m"]
     c.set_sfts(w.n_sft_per_det, w.t_mid, w.t_sft, w.first_bin, w.power)
     t0 = time.perf_counter()
     q = sensitivity.q_samples(c, w.arms, n_q, seed=13)
     p_sa = sensitivity.p_det(q, m, depths, tau, seed=14)
     t_sa = time.perf_counter() - t0
+    p_lo, p_hi = sensitivity.p_det_bounds(q, ms["m_k"], depths, tau, seed=16)
     t0 = time.perf_counter()
     p_inj = sensitivity.injection_p_det(c, w, depths, n_inj, o, tau, seed=15)
     t_inj = time.perf_counter() - t0
     c.close()
     se = np.sqrt(np.maximum(p_inj * (1 - p_inj), 1.0 / n_inj) / n_inj)
+    # distance of the injections' fraction outside the [lower, upper] band, in binomial se
+    outside = np.maximum(np.maximum(p_lo - p_inj, p_inj - p_hi), 0.0) / se
     out = {"workload": "random-bank binary search, 2 det x 5000 SFTs of 1024 s, 110.5 Hz; oversampling %g, "
                        "rule z > %g; %d q samples, %d injections per depth" % (o, tau, n_q, n_inj),
            "depths": list(depths), "p_det_semi_analytic": p_sa.tolist(), "p_det_injections": p_inj.tolist(),
            "binomial_se": se.tolist(), "max_abs_diff": float(np.max(np.abs(p_sa - p_inj))),
+           "loudest_of_bank_bounds": {"k_best": k_best, "lower": p_lo.tolist(), "upper": p_hi.tolist(),
+                                      "injections_outside_band_in_se": outside.tolist()},
            "seconds_semi_analytic": t_sa, "seconds_injections": t_inj}
-    log("sensitivity: depths %s, semi-analytic %s (%.2f s), injections %s (%.1f s)"
-        % (list(depths), np.round(p_sa, 3).tolist(), t_sa, np.round(p_inj, 3).tolist(), t_inj))
+    log("sensitivity: depths %s, semi-analytic %s (%.2f s), band [%s, %s], injections %s (%.1f s)"
+        % (list(depths), np.round(p_sa, 3).tolist(), t_sa, np.round(p_lo, 3).tolist(),
+           np.round(p_hi, 3).tolist(), np.round(p_inj, 3).tolist(), t_inj))
     return out
 
 
@@ -493,6 +502,7 @@ def bench_surrogate(ft, synth, tau, n_train, n_test, log):
     t_labels = time.perf_counter() - t0
     log("surrogate: %d + %d labels in %.1f s (GPU %.1f s), detected fraction %.3f"
         % (n_train, n_test, t_labels, gpu_tr + gpu_te, y.mean()))
+    torch.cuda.synchronize()
     net, hist, t_train = surrogate.train(c, raw, y, seed=13)
     t0 = time.perf_counter()
     p = net.predict(rt.astype(np.float32))
@@ -503,6 +513,18 @@ def bench_surrogate(ft, synth, tau, n_train, n_test, log):
     net.close()
     c.close()
     per_label = (gpu_tr + gpu_te) / (n_train + n_test)
+    # matrix-core work of training: per step of m rows (padded to 64) the two
+    # 256 x 256 layers take 2 m 256^2 flops in each of the forward, input-
+    # gradient and weight-gradient products
+    batch = 2048
+    epochs = sum(e for e, _ in surrogate.SCHEDULE)
+    rows = epochs * (n_train // batch * batch + ((n_train % batch + 63) // 64 * 64))
+    flops = rows * 2 * 3 * 2 * 256 * 256
+    mfma = {"flops": flops, "steps": epochs * -(-n_train // batch), "TFLOPs": flops / t_train / 1e12,
+            "frac_of_bf16_dense_peak": flops / t_train / 2.5e15,
+            "note": "whole training call (host validation, 10 launches per step) over the "
+                    "bf16 dense peak of 2.5 PFLOP/s; batch 2048 leaves each product at 0.27 "
+                    "GFLOP, so a step is bound by launch and reduction latency"}
     per_query = t_pred / n_test
     return {"workload": "labels on the all-sky SFT set (2 det x 5000 SFTs), local bank 5 f0 x "
                         "11 f1 x 16 sky, f ~ U[100,300] Hz, h0/sqrt(Sn) log-uniform [0.005, 0.1]; "
@@ -513,6 +535,7 @@ def bench_surrogate(ft, synth, tau, n_train, n_test, log):
             "p_det_abs_err_p_deciles": cal["max_abs_err_p_deciles"],
             "binomial_se_worst_bin": cal["se_worst_amp_bin"],
             "train_s": t_train, "final_loss": float(hist[-1]),
+            "train_mfma": mfma,
             "s_per_plain_label": per_label, "s_per_surrogate_query": per_query,
             "speedup": per_label / per_query}
 

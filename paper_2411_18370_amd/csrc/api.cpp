@@ -2839,7 +2839,9 @@ ft_status ft_mlp_create(ft_ctx c, const float *params, uint64_t seed, const floa
     if (e == hipSuccess) e = mlp_alloc(p, &m.logit, (size_t)mb);
     if (e == hipSuccess) e = mlp_alloc(p, &m.dlogit, (size_t)mb);
     if (e == hipSuccess) e = mlp_alloc(p, &m.loss, (size_t)1);
-    if (e == hipSuccess) e = mlp_alloc(p, &m.part, (size_t)(mb / 16) * MLP_H * 7);
+    if (e == hipSuccess) e = mlp_alloc(p, &m.lossv, (size_t)mb);
+    if (e == hipSuccess) e = mlp_alloc(p, &m.part, (size_t)(mb / MLP_RED_ROWS + 1) * MLP_RED_VEC);
+    if (e == hipSuccess) e = mlp_alloc(p, &m.wpart, (size_t)2 * MLP_MAX_SLICES * MLP_H * MLP_H);
     if (e != hipSuccess) {
         mlp_free(p);
         delete p;
@@ -2965,7 +2967,7 @@ ft_status ft_mlp_loss_grad(ft_mlp p, const float *raw, const float *y, int32_t n
     cst.perm_a = 0;
     hipError_t e = launch_fill_u32((uint32_t *)p->m.loss, 0u, 1, c->stream);
     if (e == hipSuccess) e = mlp_forward(p->m, p->d_raw, p->d_y, cst, n, nullptr, c->stream);
-    if (e == hipSuccess) e = mlp_backward(p->m, n, c->stream);
+    if (e == hipSuccess) e = mlp_backward(p->m, n, nullptr, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(loss, p->m.loss, 4, hipMemcpyDefault, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(grad, p->m.grad, (size_t)MLP_N_PARAMS * 4, hipMemcpyDefault, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
@@ -3001,8 +3003,8 @@ ft_status ft_mlp_train(ft_mlp p, const float *raw, const float *y, int64_t n, in
             cst.perm_a = n > 1 ? a : 0;
             cst.perm_c = b;
             e = mlp_forward(p->m, p->d_raw, p->d_y, cst, bsz, nullptr, c->stream);
-            if (e == hipSuccess) e = mlp_backward(p->m, bsz, c->stream);
-            if (e == hipSuccess) e = mlp_adam(p->m, lr, ++p->step, c->stream);
+            const MlpAdamStep adam{lr, ++p->step};
+            if (e == hipSuccess) e = mlp_backward(p->m, bsz, &adam, c->stream);
             ++n_batches;
         }
         if (epoch_loss && e == hipSuccess) {

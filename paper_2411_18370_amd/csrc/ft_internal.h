@@ -477,18 +477,30 @@ struct MlpConst {
     uint64_t perm_a, perm_c;   // sample = (perm_a * i + perm_c) mod n_total (perm_a = 0: i)
 };
 
+// Gradient reductions: column sums in chunks of MLP_RED_ROWS rows over the
+// MLP_RED_VEC entries that are not 256 x 256 weights (W1, b1, b2, b3, W4, b4),
+// and the two weight-gradient products in up to MLP_MAX_SLICES batch slices.
+constexpr int MLP_RED_ROWS = 64;
+constexpr int MLP_RED_VEC = 10 * MLP_H + 1;
+constexpr int MLP_MAX_SLICES = 8;
+
 struct MlpBufs {
     float *theta, *m, *v, *grad;
     __bf16 *w2b, *w3b;
     float *x, *z1, *z2, *z3, *dz1, *dz2, *dz3, *logit, *dlogit, *loss;
+    float *lossv;   // [max_batch] per-sample loss of the current batch
     __bf16 *a1, *a2, *a3, *dz1b, *dz2b, *dz3b;
-    float *part;    // [max_batch / 16][MLP_H * 7] partial sums of the gradient reductions
+    float *part;    // [max_batch / MLP_RED_ROWS][MLP_RED_VEC] per-chunk column sums
+    float *wpart;   // [2][MLP_MAX_SLICES][MLP_H][MLP_H] per-slice weight gradients
     int max_batch;  // multiple of 64
+};
+struct MlpAdamStep {
+    float lr;
+    int t;  // step count, from 1
 };
 hipError_t mlp_refresh_bf16(const MlpBufs &m, hipStream_t s);
 hipError_t mlp_forward(const MlpBufs &m, const float *raw, const float *labels, const MlpConst &c,
                        int bsz, float *prob, hipStream_t s);
-hipError_t mlp_backward(const MlpBufs &m, int bsz, hipStream_t s);
-hipError_t mlp_adam(const MlpBufs &m, float lr, int t, hipStream_t s);
+hipError_t mlp_backward(const MlpBufs &m, int bsz, const MlpAdamStep *adam, hipStream_t s);
 
 }  // namespace ft

@@ -12,6 +12,16 @@
 //
 // Parameter vector (flat FP32): W1 [256][6], b1 [256], W2 [256][256], b2,
 // W3 [256][256], b3, W4 [256], b4 -- 133,633 values; Z_l = A_{l-1} W_l^T + b_l.
+//
+// One training step is ten launches: the input layer, two forward GEMMs, the
+// output layer fused with its backward step, four backward GEMMs (the two
+// weight-gradient products split over the batch into up to 8 slices so they
+// fill more than 16 workgroups), one kernel of per-chunk column sums for every
+// bias and the first and last layers, and one kernel that finishes every
+// gradient entry (sum over chunks or slices, in a fixed order), applies Adam
+// and adds the batch loss.  Every reduction is deterministic.
+#include <algorithm>
+
 #include "ft_internal.h"
 
 namespace ft {
@@ -39,14 +49,15 @@ enum { EPI_FWD = 0, EPI_BWD = 1, EPI_STORE = 2 };
 
 // C[M][N] = A[M][K] B[K][N].  A_KMAJOR: A(m, k) = A[m*lda + k], else
 // A(m, k) = A[k*lda + m].  B_KMAJOR: B(k, n) = B[n*ldb + k], else
-// B(k, n) = B[k*ldb + n].  M, N multiples of 64, K a multiple of 32.
+// B(k, n) = B[k*ldb + n].  M, N multiples of 64, K and k_slice multiples of
+// 32.  Workgroup z sums k in [z k_slice, min(K, (z + 1) k_slice)).
 // Epilogues (ld = N):
 //   EPI_FWD:   z = acc + bias[n]; zf[m][n] = z; act[m][n] = bf16(gelu(z))
 //   EPI_BWD:   d = acc * gelu'(zprev[m][n]); zf[m][n] = d; act[m][n] = bf16(d)
-//   EPI_STORE: zf[m][n] = acc
+//   EPI_STORE: zf[z][m][n] = acc (one partial product per slice z)
 template <bool A_KMAJOR, bool B_KMAJOR, int EPI>
 __global__ __launch_bounds__(256) void gemm_bf16_kernel(const __bf16 *A, const __bf16 *B, int M,
-                                                        int N, int K, int lda, int ldb,
+                                                        int N, int K, int k_slice, int lda, int ldb,
                                                         const float *bias, const float *zprev,
                                                         float *zf, __bf16 *act)
 {
@@ -61,7 +72,9 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(const __bf16 *A, const _
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < K; k0 += 32) {
+    const int k_begin = blockIdx.z * k_slice, k_end = min(K, k_begin + k_slice);
+    if (EPI == EPI_STORE) zf += (int64_t)blockIdx.z * M * N;
+    for (int k0 = k_begin; k0 < k_end; k0 += 32) {
         bf16x8 a[2], b[2];
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
@@ -152,113 +165,161 @@ __global__ void layer1_kernel(const float *raw, const float *params, MlpConst c,
     a1[q] = (__bf16)gelu(z);
 }
 
-// Layer 4 (256 -> 1) + sigmoid + BCE: one wavefront per sample.
-__global__ void head_kernel(const __bf16 *a3, const float *params, const float *labels,
-                            MlpConst c, int bsz, float inv_n, float *logit, float *dlogit,
-                            float *prob, float *loss_sum)
+// Layer 4 (256 -> 1) and sigmoid, one wavefront per row of the padded batch.
+// With labels it also forms the per-sample loss and the output-side backward
+// step: dlogit = (p - y)/n and dZ3 = dlogit w4 * gelu'(z3) (zero on padding
+// rows, which the weight-gradient products sum over).
+__global__ void head_kernel(const __bf16 *a3, const float *z3, const float *params,
+                            const float *labels, MlpConst c, int bsz, int m_pad, float inv_n,
+                            float *logit, float *dlogit, float *prob, float *lossv, float *dz,
+                            __bf16 *dzb)
 {
     const int lane = threadIdx.x & 63;
     const int b = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    if (b >= bsz) return;
+    if (b >= m_pad) return;
     const float *W4 = params + MLP_OFF_W4;
-    float s = 0.f;
-    for (int i = lane; i < H; i += 64) s += W4[i] * (float)a3[(int64_t)b * H + i];
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-    if (lane != 0) return;
-    const float z = s + params[MLP_OFF_W4 + H];
-    const float p = 1.f / (1.f + expf(-z));
-    logit[b] = z;
-    if (prob) prob[b] = p;
-    if (labels) {
-        const float y = labels[sample_index(b, c)];
-        dlogit[b] = (p - y) * inv_n;
-        const float l = fmaxf(z, 0.f) - z * y + log1pf(expf(-fabsf(z)));
-        atomicAdd(loss_sum, l * inv_n);
-    }
-}
-
-// dZ3 = (dlogit w4) * gelu'(z3), padded rows zero.
-__global__ void head_back_kernel(const float *dlogit, const float *params, const float *z3,
-                                 int bsz, int m_pad, float *dz, __bf16 *dzb)
-{
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= (int64_t)m_pad * H) return;
-    const int b = (int)(q / H), i = (int)(q % H);
-    const float d = b < bsz ? dlogit[b] * params[MLP_OFF_W4 + i] * gelu_grad(z3[q]) : 0.f;
-    dz[q] = d;
-    dzb[q] = (__bf16)d;
-}
-
-// Gradient reductions over the batch, in two deterministic stages: chunk c of
-// RED_ROWS rows writes part[c][q] = sum over its rows of term(b, q); then
-// out[q] = sum_c part[c][q] in chunk order.
-//   RED_COL:  term = v[b][q], q < 256 (bias gradients)
-//   RED_HEAD: term = dlogit[b] a3[b][q] for q < 256, dlogit[b] for q = 256
-//             (output-layer weights and bias)
-//   RED_L1:   the first layer: for hidden unit j, term = dz1[b][j] x[b][i] at
-//             q = 6 j + i (i < 6, weights) and dz1[b][j] at q = 1536 + j
-//             (bias), one thread per unit holding its seven sums
-enum { RED_COL = 0, RED_HEAD = 1, RED_L1 = 2 };
-constexpr int RED_ROWS = 16;
-
-template <int MODE>
-__global__ __launch_bounds__(256) void reduce_part_kernel(const float *v, const __bf16 *a3,
-                                                          const float *x, int bsz, int n_out,
-                                                          float *part)
-{
-    const int c = blockIdx.x;
-    const int b0 = c * RED_ROWS, b1 = min(b0 + RED_ROWS, bsz);
-    if (MODE == RED_L1) {
-        const int j = threadIdx.x;  // blockDim.x == H
-        float s[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-        for (int b = b0; b < b1; ++b) {
-            const float d = v[(int64_t)b * H + j];
-#pragma unroll
-            for (int i = 0; i < 6; ++i) s[i] += d * x[b * 6 + i];
-            s[6] += d;
-        }
-        float *out = part + (int64_t)c * n_out;
-#pragma unroll
-        for (int i = 0; i < 6; ++i) out[6 * j + i] = s[i];
-        out[6 * H + j] = s[6];
+    if (b >= bsz) {
+        if (labels)
+            for (int i = lane; i < H; i += 64) {
+                dz[(int64_t)b * H + i] = 0.f;
+                dzb[(int64_t)b * H + i] = (__bf16)0.f;
+            }
         return;
     }
-    for (int q = threadIdx.x; q < n_out; q += blockDim.x) {
-        float s = 0.f;
-        for (int b = b0; b < b1; ++b) {
-            if (MODE == RED_COL) s += v[(int64_t)b * H + q];
-            if (MODE == RED_HEAD) s += q < H ? v[b] * (float)a3[(int64_t)b * H + q] : v[b];
-        }
-        part[(int64_t)c * n_out + q] = s;
+    float s = 0.f;
+    for (int i = lane; i < H; i += 64) s += W4[i] * (float)a3[(int64_t)b * H + i];
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);  // every lane holds the sum
+    const float z = s + params[MLP_OFF_W4 + H];
+    const float p = 1.f / (1.f + expf(-z));
+    if (lane == 0) {
+        logit[b] = z;
+        if (prob) prob[b] = p;
+    }
+    if (!labels) return;
+    const float y = labels[sample_index(b, c)];
+    const float d = (p - y) * inv_n;
+    if (lane == 0) {
+        dlogit[b] = d;
+        lossv[b] = fmaxf(z, 0.f) - z * y + log1pf(expf(-fabsf(z)));
+    }
+    for (int i = lane; i < H; i += 64) {
+        const int64_t q = (int64_t)b * H + i;
+        const float v = d * W4[i] * gelu_grad(z3[q]);
+        dz[q] = v;
+        dzb[q] = (__bf16)v;
     }
 }
 
-__global__ void reduce_sum_kernel(const float *part, int n_chunks, int n_out, float *out)
+// Column sums over the batch for every gradient entry that is not a 256 x 256
+// weight, in chunks of MLP_RED_ROWS rows: part[c][q] = sum over the rows of
+// chunk c.  Compact index q (MLP_RED_VEC entries):
+//   [0, 6H)     W1 (unit j, input i at 6 j + i): dZ1[b][j] x[b][i]
+//   [6H, 7H)    b1: dZ1[b][j]
+//   [7H, 8H)    b2: dZ2[b][j]
+//   [8H, 9H)    b3: dZ3[b][j]
+//   [9H, 10H)   W4: dlogit[b] A3[b][j]
+//   10H         b4: dlogit[b]
+// Workgroup (c, section) handles one chunk of one section; thread j one unit.
+__global__ __launch_bounds__(256) void grad_part_kernel(const float *dz1, const float *dz2,
+                                                        const float *dz3, const float *dlogit,
+                                                        const __bf16 *a3, const float *x, int bsz,
+                                                        float *part)
 {
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= n_out) return;
-    float s = 0.f;
-    for (int c = 0; c < n_chunks; ++c) s += part[(int64_t)c * n_out + q];
-    out[q] = s;
+    const int c = blockIdx.x, sec = blockIdx.y, j = threadIdx.x;  // blockDim.x == H
+    const int b0 = c * MLP_RED_ROWS, b1 = min(b0 + MLP_RED_ROWS, bsz);
+    float *out = part + (int64_t)c * MLP_RED_VEC;
+    if (sec == 0) {
+        float t[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        for (int b = b0; b < b1; ++b) {
+            const float d = dz1[(int64_t)b * H + j];
+#pragma unroll
+            for (int i = 0; i < 6; ++i) t[i] += d * x[b * 6 + i];
+            t[6] += d;
+        }
+#pragma unroll
+        for (int i = 0; i < 6; ++i) out[6 * j + i] = t[i];
+        out[6 * H + j] = t[6];
+    } else if (sec < 3) {
+        const float *v = sec == 1 ? dz2 : dz3;
+        float t = 0.f;
+        for (int b = b0; b < b1; ++b) t += v[(int64_t)b * H + j];
+        out[(6 + sec) * H + j] = t;
+    } else {
+        float t = 0.f, u = 0.f;
+        for (int b = b0; b < b1; ++b) {
+            t += dlogit[b] * (float)a3[(int64_t)b * H + j];
+            u += dlogit[b];
+        }
+        out[9 * H + j] = t;
+        if (j == 0) out[10 * H] = u;
+    }
 }
 
-// Adam (Kingma and Ba 2015) with bias correction; refreshes the BF16 copies of
-// the two 256 x 256 weight matrices.
-__global__ void adam_kernel(float *theta, const float *g, float *m, float *v, int n, float lr,
-                            float b1, float b2, float eps, float c1, float c2, __bf16 *w2b,
-                            __bf16 *w3b)
+// Finishes the gradient: g[i] = sum over chunks of part (compact entries) or
+// over the slices of the split weight-gradient products (wpart [2][n_slices]
+// [H][H], W2 then W3), each in index order.  With adam set, Adam (Kingma and
+// Ba 2015, bias-corrected) updates theta and refreshes the BF16 copies of W2
+// and W3.  The last workgroup adds the batch's mean loss to *loss.
+struct AdamArgs {
+    bool on;
+    float lr, b1, b2, eps, c1, c2;
+};
+
+__global__ __launch_bounds__(256) void grad_finish_kernel(const float *part, int n_chunks,
+                                                          const float *wpart, int n_slices,
+                                                          const float *lossv, int bsz, float inv_n,
+                                                          float *loss, float *g, AdamArgs ad,
+                                                          float *theta, float *m, float *v,
+                                                          __bf16 *w2b, __bf16 *w3b)
 {
+    if (blockIdx.x == gridDim.x - 1) {
+        __shared__ float red[256];
+        float t = 0.f;
+        for (int b = threadIdx.x; b < bsz; b += 256) t += lossv[b];
+        red[threadIdx.x] = t;
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) *loss += red[0] * inv_n;
+        return;
+    }
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const float gi = g[i];
-    const float mi = b1 * m[i] + (1.f - b1) * gi;
-    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    if (i >= MLP_N_PARAMS) return;
+    float gi = 0.f;
+    int wm = -1, r = 0, q = 0;
+    if (i >= MLP_OFF_W2 && i < MLP_OFF_W2 + H * H) {
+        wm = 0;
+        r = i - MLP_OFF_W2;
+    } else if (i >= MLP_OFF_W3 && i < MLP_OFF_W3 + H * H) {
+        wm = 1;
+        r = i - MLP_OFF_W3;
+    } else if (i < MLP_OFF_W2) {
+        q = i;  // W1, b1
+    } else if (i < MLP_OFF_W3) {
+        q = 7 * H + (i - MLP_OFF_W2 - H * H);  // b2
+    } else if (i < MLP_OFF_W4) {
+        q = 8 * H + (i - MLP_OFF_W3 - H * H);  // b3
+    } else {
+        q = 9 * H + (i - MLP_OFF_W4);  // W4, b4
+    }
+    if (wm >= 0) {
+        const float *w = wpart + (int64_t)wm * n_slices * H * H + r;
+        for (int z = 0; z < n_slices; ++z) gi += w[(int64_t)z * H * H];
+    } else {
+        for (int c = 0; c < n_chunks; ++c) gi += part[(int64_t)c * MLP_RED_VEC + q];
+    }
+    g[i] = gi;
+    if (!ad.on) return;
+    const float mi = ad.b1 * m[i] + (1.f - ad.b1) * gi;
+    const float vi = ad.b2 * v[i] + (1.f - ad.b2) * gi * gi;
     m[i] = mi;
     v[i] = vi;
-    const float t = theta[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    const float t = theta[i] - ad.lr * (mi / ad.c1) / (sqrtf(vi / ad.c2) + ad.eps);
     theta[i] = t;
-    if (i >= MLP_OFF_W2 && i < MLP_OFF_W2 + H * H) w2b[i - MLP_OFF_W2] = (__bf16)t;
-    if (i >= MLP_OFF_W3 && i < MLP_OFF_W3 + H * H) w3b[i - MLP_OFF_W3] = (__bf16)t;
+    if (wm == 0) w2b[r] = (__bf16)t;
+    if (wm == 1) w3b[r] = (__bf16)t;
 }
 
 __global__ void to_bf16_kernel(const float *src, __bf16 *dst, int n)
@@ -268,17 +329,6 @@ __global__ void to_bf16_kernel(const float *src, __bf16 *dst, int n)
 }
 
 unsigned blocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
-
-template <int MODE>
-void reduce_rows(const float *v, const __bf16 *a3, const float *x, int bsz, int n_out, float *part,
-                 float *out, hipStream_t s)
-{
-    const int n_chunks = (bsz + RED_ROWS - 1) / RED_ROWS;
-    hipLaunchKernelGGL(reduce_part_kernel<MODE>, dim3(n_chunks), dim3(256), 0, s, v, a3, x, bsz, n_out,
-                       part);
-    hipLaunchKernelGGL(reduce_sum_kernel, dim3(blocks(n_out, 256)), dim3(256), 0, s, part, n_chunks, n_out,
-                       out);
-}
 
 }  // namespace
 
@@ -300,48 +350,50 @@ hipError_t mlp_forward(const MlpBufs &m, const float *raw, const float *labels, 
     hipLaunchKernelGGL(layer1_kernel, dim3(blocks((int64_t)m_pad * H, 256)), dim3(256), 0, s, raw,
                        m.theta, c, bsz, m_pad, m.x, m.z1, m.a1);
     hipLaunchKernelGGL((gemm_bf16_kernel<true, true, EPI_FWD>), g2, dim3(256), 0, s, m.a1, m.w2b,
-                       m_pad, H, H, H, H, m.theta + MLP_OFF_W2 + H * H, nullptr, m.z2, m.a2);
+                       m_pad, H, H, H, H, H, m.theta + MLP_OFF_W2 + H * H, nullptr, m.z2, m.a2);
     hipLaunchKernelGGL((gemm_bf16_kernel<true, true, EPI_FWD>), g2, dim3(256), 0, s, m.a2, m.w3b,
-                       m_pad, H, H, H, H, m.theta + MLP_OFF_W3 + H * H, nullptr, m.z3, m.a3);
-    hipLaunchKernelGGL(head_kernel, dim3(blocks(bsz, 4)), dim3(256), 0, s, m.a3, m.theta, labels, c,
-                       bsz, 1.f / (float)bsz, m.logit, m.dlogit, prob, m.loss);
+                       m_pad, H, H, H, H, H, m.theta + MLP_OFF_W3 + H * H, nullptr, m.z3, m.a3);
+    hipLaunchKernelGGL(head_kernel, dim3(blocks(labels ? m_pad : bsz, 4)), dim3(256), 0, s, m.a3,
+                       m.z3, m.theta, labels, c, bsz, m_pad, 1.f / (float)bsz, m.logit, m.dlogit,
+                       prob, m.lossv, m.dz3, m.dz3b);
     return hipGetLastError();
 }
 
-// Backward pass after mlp_forward with labels: gradient into m.grad.
-hipError_t mlp_backward(const MlpBufs &m, int bsz, hipStream_t s)
+// Backward pass after mlp_forward with labels (which already formed dZ3):
+// the gradient into m.grad, then, with adam, one Adam step t.
+hipError_t mlp_backward(const MlpBufs &m, int bsz, const MlpAdamStep *adam, hipStream_t s)
 {
     const int m_pad = (bsz + 63) / 64 * 64;
     const dim3 g2(H / 64, m_pad / 64);
-    const dim3 gw(H / 64, H / 64);
-    float *g = m.grad;
-    reduce_rows<RED_HEAD>(m.dlogit, m.a3, nullptr, bsz, H + 1, m.part, g + MLP_OFF_W4, s);
-    hipLaunchKernelGGL(head_back_kernel, dim3(blocks((int64_t)m_pad * H, 256)), dim3(256), 0, s,
-                       m.dlogit, m.theta, m.z3, bsz, m_pad, m.dz3, m.dz3b);
-    // layer 3: dW3 = dZ3^T A2, db3 = colsum dZ3, dZ2 = (dZ3 W3) * gelu'(Z2)
+    // the weight-gradient products sum over the batch in n_sl slices of >= 256 rows
+    const int n_sl = std::max(1, std::min(MLP_MAX_SLICES, m_pad / 256));
+    const int k_sl = (m_pad / n_sl + 31) / 32 * 32;
+    const dim3 gw(H / 64, H / 64, n_sl);
+    float *w2p = m.wpart, *w3p = m.wpart + (int64_t)n_sl * H * H;
+    // layer 3: dW3 = dZ3^T A2, dZ2 = (dZ3 W3) * gelu'(Z2)
     hipLaunchKernelGGL((gemm_bf16_kernel<false, false, EPI_STORE>), gw, dim3(256), 0, s, m.dz3b,
-                       m.a2, H, H, m_pad, H, H, nullptr, nullptr, g + MLP_OFF_W3, nullptr);
-    reduce_rows<RED_COL>(m.dz3, nullptr, nullptr, bsz, H, m.part, g + MLP_OFF_W3 + H * H, s);
+                       m.a2, H, H, m_pad, k_sl, H, H, nullptr, nullptr, w3p, nullptr);
     hipLaunchKernelGGL((gemm_bf16_kernel<true, false, EPI_BWD>), g2, dim3(256), 0, s, m.dz3b, m.w3b,
-                       m_pad, H, H, H, H, nullptr, m.z2, m.dz2, m.dz2b);
+                       m_pad, H, H, H, H, H, nullptr, m.z2, m.dz2, m.dz2b);
     // layer 2
     hipLaunchKernelGGL((gemm_bf16_kernel<false, false, EPI_STORE>), gw, dim3(256), 0, s, m.dz2b,
-                       m.a1, H, H, m_pad, H, H, nullptr, nullptr, g + MLP_OFF_W2, nullptr);
-    reduce_rows<RED_COL>(m.dz2, nullptr, nullptr, bsz, H, m.part, g + MLP_OFF_W2 + H * H, s);
+                       m.a1, H, H, m_pad, k_sl, H, H, nullptr, nullptr, w2p, nullptr);
     hipLaunchKernelGGL((gemm_bf16_kernel<true, false, EPI_BWD>), g2, dim3(256), 0, s, m.dz2b, m.w2b,
-                       m_pad, H, H, H, H, nullptr, m.z1, m.dz1, m.dz1b);
-    // layer 1
-    // weights and bias of the first layer are contiguous: g[0 .. 7H)
-    reduce_rows<RED_L1>(m.dz1, nullptr, m.x, bsz, H * 7, m.part, g, s);
-    return hipGetLastError();
-}
-
-hipError_t mlp_adam(const MlpBufs &m, float lr, int t, hipStream_t s)
-{
-    const float b1 = 0.9f, b2 = 0.999f;
-    const float c1 = 1.f - powf(b1, (float)t), c2 = 1.f - powf(b2, (float)t);
-    hipLaunchKernelGGL(adam_kernel, dim3(blocks(MLP_N_PARAMS, 256)), dim3(256), 0, s, m.theta, m.grad,
-                       m.m, m.v, MLP_N_PARAMS, lr, b1, b2, 1e-8f, c1, c2, m.w2b, m.w3b);
+                       m_pad, H, H, H, H, H, nullptr, m.z1, m.dz1, m.dz1b);
+    // column sums (biases, first and last layer), then every entry finished at once
+    const int n_chunks = (bsz + MLP_RED_ROWS - 1) / MLP_RED_ROWS;
+    hipLaunchKernelGGL(grad_part_kernel, dim3(n_chunks, 4), dim3(256), 0, s, m.dz1, m.dz2, m.dz3,
+                       m.dlogit, m.a3, m.x, bsz, m.part);
+    AdamArgs ad{false, 0.f, 0.9f, 0.999f, 1e-8f, 1.f, 1.f};
+    if (adam) {
+        ad.on = true;
+        ad.lr = adam->lr;
+        ad.c1 = 1.f - powf(ad.b1, (float)adam->t);
+        ad.c2 = 1.f - powf(ad.b2, (float)adam->t);
+    }
+    hipLaunchKernelGGL(grad_finish_kernel, dim3(blocks(MLP_N_PARAMS, 256) + 1), dim3(256), 0, s,
+                       m.part, n_chunks, m.wpart, n_sl, m.lossv, bsz, 1.f / (float)bsz, m.loss,
+                       m.grad, ad, m.theta, m.m, m.v, m.w2b, m.w3b);
     return hipGetLastError();
 }
 

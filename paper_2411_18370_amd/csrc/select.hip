@@ -10,8 +10,10 @@
 //    the FP64 top-K has S32 >= K32 (1 - e)/(1 + e).  Candidates are compacted
 //    per sub-band.
 // 3. Each candidate is re-summed in FP64 in SFT order with canonical bins
-//    (one wavefront per candidate: lanes gather 64 SFTs at a time, the sum is
-//    then taken sequentially across lanes).
+//    (one wavefront per candidate: the 64 lanes form the weighted terms of
+//    256 consecutive SFTs at a time, 4 per lane, and store them to LDS; lane 0
+//    then adds them to the running sum one by one in SFT order, so the sum is
+//    the plain sequential FP64 sum).
 // 4. Candidates are ranked within their sub-band by (S64 desc, index asc);
 //    ranks < K are the toplist, identical to sorting all FP64 statistics.
 #include "ft_internal.h"

@@ -80,15 +80,19 @@ def draw_signal(rng, region):
 
 
 def sample(ctx: ft.Context, w: BinaryWorkload, o: float, n_trials: int, seed: int, amp: float = 1.0,
-           half_cells: float = 2.0, f_margin: float = 0.01):
+           half_cells: float = 2.0, f_margin: float = 0.01, k_best: int = 1):
     """n_trials mismatches of random banks at oversampling o.  Returns a dict with
-    the mismatches and every trial's inputs (signal, injection, seeds, box, n)."""
+    the mismatches and every trial's inputs (signal, injection, seeds, box, n).
+    With k_best > 1, "m_k" [n_trials, k_best] also holds the mismatches of the
+    k_best loudest templates of each bank in decreasing order of s (1.0 where
+    the bank has fewer templates); at a high signal amplitude these are the
+    bank's k_best smallest mismatches."""
     rng = np.random.default_rng(seed)
     t_obs = float(w.t_mid.max() - w.t_mid.min() + w.t_sft)
     vmax = float(np.max(np.linalg.norm(w.v, axis=1)))
     mu_g = 2.0 * w.n_sft
     inner = dict(w.region, f0_lo=w.region["f0_lo"] + f_margin, f0_hi=w.region["f0_hi"] - f_margin)
-    ms, trials = [], []
+    ms, mks, trials = [], [], []
     for trial in range(n_trials):
         lam = draw_signal(rng, inner)
         f0, alpha, sdec, ap, om, pb = lam
@@ -107,13 +111,17 @@ def sample(ctx: ft.Context, w: BinaryWorkload, o: float, n_trials: int, seed: in
         s_sig = ctx.toplist(0, 1)[0].s64
         box = box_around(lam, half_cells, w, t_obs, vmax)
         n_bank = max(1, int(round(o * n_templates(box, w.t_sft, t_obs, vmax))))
-        ctx.eval_binary_random(box, bank_seed, n_bank, w.t_ref, 1, edges)
-        best = ctx.toplist(0, 1)[0]
+        ctx.eval_binary_random(box, bank_seed, n_bank, w.t_ref, k_best, edges)
+        top = ctx.toplist(0, k_best)
+        best = top[0]
         m = (s_sig - best.s64) / (s_sig - mu_g)
         ms.append(m)
+        mk = np.ones(k_best)
+        mk[:len(top)] = [(s_sig - t.s64) / (s_sig - mu_g) for t in top]
+        mks.append(mk)
         trials.append(dict(inj=inj, noise_seed=noise_seed, run=trial, bank_seed=bank_seed, box=box,
                            n_bank=n_bank, s_signal=s_sig, s_best=best.s64, best_index=best.index))
-    return dict(o=o, m=np.array(ms), trials=trials, t_obs=t_obs, vmax=vmax)
+    return dict(o=o, m=np.array(ms), m_k=np.array(mks), trials=trials, t_obs=t_obs, vmax=vmax)
 
 
 def summary(m):

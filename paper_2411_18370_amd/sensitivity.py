@@ -15,6 +15,15 @@ sigma_S^2 is the variance 4 + 4 rho^2 of a non-central chi^2_2 (the printed
 variance lacks it).  injection_p_det is the comparison the paper makes: plain
 injections into Gaussian noise, the loudest template of a random bank around
 each, and the same detection rule.
+
+The estimate models the search's loudest template as one template at the
+bank's smallest mismatch.  The loudest of a bank is at least as loud as that
+template, and near threshold it also collects the noise of its neighbours.
+p_det_bounds brackets this gain: the one-template estimate is a lower bound,
+and the maximum over the k best templates of each bank (joint mismatches from
+one trial) with independent noise draws is an upper bound, since the noise of
+nearby templates is positively correlated (Slepian's inequality) and the
+templates beyond the k-th add only their chance of a noise excursion past tau.
 """
 from __future__ import annotations
 
@@ -59,6 +68,26 @@ def p_det(q, m_samples, depths, tau, seed=0, eta=BIN_OFFSET_POWER):
         eps = rng.standard_normal(q.shape[0])
         out.append(float(np.mean(z_samples(q, m, eps, d, eta) > tau)))
     return np.array(out)
+
+
+def p_det_bounds(q, m_k, depths, tau, seed=0, eta=BIN_OFFSET_POWER):
+    """(lower, upper) p_det at each depth: lower is the one-template estimate at
+    the smallest mismatch of each bank; upper detects when any of the k best
+    templates of a bank (rows of m_k, drawn jointly) crosses tau with
+    independent noise draws.  The same draws serve both bounds and every depth
+    (so both fall with depth)."""
+    rng = np.random.default_rng(seed)
+    q = np.asarray(q, np.float64)
+    m_k = np.asarray(m_k, np.float64)
+    n, k = q.shape[0], m_k.shape[1]
+    rows = m_k[rng.integers(0, m_k.shape[0], n)]
+    eps = rng.standard_normal((n, k))
+    lo, hi = [], []
+    for d in depths:
+        z = np.stack([z_samples(q, rows[:, j], eps[:, j], d, eta) for j in range(k)], axis=1)
+        lo.append(float(np.mean(z[:, 0] > tau)))
+        hi.append(float(np.mean(z.max(axis=1) > tau)))
+    return np.array(lo), np.array(hi)
 
 
 def depth_at(q, m_samples, p, tau, seed=0, eta=BIN_OFFSET_POWER, d_lo=1.0, d_hi=1e4, iters=60):

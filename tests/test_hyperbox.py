@@ -67,6 +67,29 @@ def test_p_det_matches_its_closed_form():
     assert abs(p_at - 0.95) < 0.003
 
 
+def test_p_det_bounds_closed_forms():
+    """Fixed q and each bank's k mismatches fixed: the lower bound is the
+    one-template p_1 = P(N(mu_1, sd_1) > tau) and the upper bound is
+    1 - prod_j (1 - p_j) for k independent templates; with k = 1 they agree."""
+    n = 400_000
+    q = np.tile([2000.0, 2.0 * math.sqrt(1000.0), 640.0, 640.0], (n, 1))
+    tau = 5.0
+    mk = np.array([[0.05, 0.2, 0.4, 0.9]])
+    lam = lambda d, m: (1 - m) * sensitivity.BIN_OFFSET_POWER / d ** 2
+    for d in (10.0, 14.0, 20.0):
+        p = [sps.norm.sf(tau, lam(d, m) * q[0, 2] / q[0, 1],
+                         math.sqrt(q[0, 1] ** 2 + 4 * lam(d, m) * q[0, 3]) / q[0, 1]) for m in mk[0]]
+        want_hi = 1 - np.prod([1 - x for x in p])
+        lo, hi = sensitivity.p_det_bounds(q, mk, [d], tau, seed=7)
+        se = lambda x: 5 * math.sqrt(x * (1 - x) / n) + 1e-4
+        assert abs(lo[0] - p[0]) < se(p[0]) and abs(hi[0] - want_hi) < se(want_hi)
+        lo1, hi1 = sensitivity.p_det_bounds(q, mk[:, :1], [d], tau, seed=7)
+        assert lo1[0] == hi1[0]
+    # monotone in depth on common draws
+    lo, hi = sensitivity.p_det_bounds(q[:20000], mk, [8.0, 12.0, 16.0, 24.0], tau, seed=8)
+    assert np.all(np.diff(lo) <= 0) and np.all(np.diff(hi) <= 0) and np.all(lo <= hi)
+
+
 def test_thresholds_rule():
     z = np.array([3.0, 9.0, np.nan, 5.0, 9.0, 1.0])
     thr = hyperbox.thresholds(z, n_cand=2, n_reject=1)
