@@ -2829,6 +2829,8 @@ ft_status ft_mlp_create(ft_ctx c, const float *params, uint64_t seed, const floa
         if (e == hipSuccess) e = mlp_alloc(p, q, (size_t)MLP_N_PARAMS);
     if (e == hipSuccess) e = mlp_alloc(p, &m.w2b, (size_t)MLP_H * MLP_H);
     if (e == hipSuccess) e = mlp_alloc(p, &m.w3b, (size_t)MLP_H * MLP_H);
+    if (e == hipSuccess) e = mlp_alloc(p, &m.w2t, (size_t)MLP_H * MLP_H);
+    if (e == hipSuccess) e = mlp_alloc(p, &m.w3t, (size_t)MLP_H * MLP_H);
     float **acts[] = {&m.z1, &m.z2, &m.z3, &m.dz1, &m.dz2, &m.dz3};
     for (float **q : acts)
         if (e == hipSuccess) e = mlp_alloc(p, q, act);

@@ -486,7 +486,8 @@ constexpr int MLP_MAX_SLICES = 8;
 
 struct MlpBufs {
     float *theta, *m, *v, *grad;
-    __bf16 *w2b, *w3b;
+    __bf16 *w2b, *w3b;  // BF16 copies of W2, W3 ([out][in])
+    __bf16 *w2t, *w3t;  // and transposed ([in][out])
     float *x, *z1, *z2, *z3, *dz1, *dz2, *dz3, *logit, *dlogit, *loss;
     float *lossv;   // [max_batch] per-sample loss of the current batch
     __bf16 *a1, *a2, *a3, *dz1b, *dz2b, *dz3b;

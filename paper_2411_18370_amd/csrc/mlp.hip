@@ -50,12 +50,14 @@ enum { EPI_FWD = 0, EPI_BWD = 1, EPI_STORE = 2 };
 // C[M][N] = A[M][K] B[K][N].  A_KMAJOR: A(m, k) = A[m*lda + k], else
 // A(m, k) = A[k*lda + m].  B_KMAJOR: B(k, n) = B[n*ldb + k], else
 // B(k, n) = B[k*ldb + n].  M, N multiples of 64, K and k_slice multiples of
-// 32.  Workgroup z sums k in [z k_slice, min(K, (z + 1) k_slice)).
+// 32.  Workgroup z sums k in [z k_slice, min(K, (z + 1) k_slice)).  KC > 0
+// fixes K = k_slice = KC at compile time: the k loop is unrolled, so every
+// operand load is issued before the first product waits on one.
 // Epilogues (ld = N):
 //   EPI_FWD:   z = acc + bias[n]; zf[m][n] = z; act[m][n] = bf16(gelu(z))
 //   EPI_BWD:   d = acc * gelu'(zprev[m][n]); zf[m][n] = d; act[m][n] = bf16(d)
 //   EPI_STORE: zf[z][m][n] = acc (one partial product per slice z)
-template <bool A_KMAJOR, bool B_KMAJOR, int EPI>
+template <bool A_KMAJOR, bool B_KMAJOR, int EPI, int KC = 0>
 __global__ __launch_bounds__(256) void gemm_bf16_kernel(const __bf16 *A, const __bf16 *B, int M,
                                                         int N, int K, int k_slice, int lda, int ldb,
                                                         const float *bias, const float *zprev,
@@ -72,10 +74,7 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(const __bf16 *A, const _
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-    const int k_begin = blockIdx.z * k_slice, k_end = min(K, k_begin + k_slice);
-    if (EPI == EPI_STORE) zf += (int64_t)blockIdx.z * M * N;
-    for (int k0 = k_begin; k0 < k_end; k0 += 32) {
-        bf16x8 a[2], b[2];
+    auto load = [&](int k0, bf16x8 (&a)[2], bf16x8 (&b)[2]) {
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
             const int m = m0 + i * 16 + lr;
@@ -96,11 +95,30 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(const __bf16 *A, const _
                 for (int q = 0; q < 8; ++q) b[j][q] = B[(int64_t)(k0 + lk + q) * ldb + n];
             }
         }
+    };
+    auto mma = [&](const bf16x8 (&a)[2], const bf16x8 (&b)[2]) {
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
             for (int j = 0; j < 2; ++j)
                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    };
+    if (KC) {
+        // every operand of the product is loaded before the first MFMA
+        bf16x8 a[KC ? KC / 32 : 1][2], b[KC ? KC / 32 : 1][2];
+#pragma unroll
+        for (int t = 0; t < KC / 32; ++t) load(32 * t, a[t], b[t]);
+        __builtin_amdgcn_sched_barrier(0);  // keep the scheduler from interleaving them again
+#pragma unroll
+        for (int t = 0; t < KC / 32; ++t) mma(a[t], b[t]);
+    } else {
+        const int k_begin = blockIdx.z * k_slice, k_end = min(K, k_begin + k_slice);
+        if (EPI == EPI_STORE) zf += (int64_t)blockIdx.z * M * N;
+        for (int k0 = k_begin; k0 < k_end; k0 += 32) {
+            bf16x8 a[2], b[2];
+            load(k0, a, b);
+            mma(a, b);
+        }
     }
     // output layout: lane holds column n0 + j*16 + lane%16, rows 4*(lane/16) + r
 #pragma unroll
@@ -219,47 +237,86 @@ __global__ void head_kernel(const __bf16 *a3, const float *z3, const float *para
 //   [8H, 9H)    b3: dZ3[b][j]
 //   [9H, 10H)   W4: dlogit[b] A3[b][j]
 //   10H         b4: dlogit[b]
-// Workgroup (c, section) handles one chunk of one section; thread j one unit.
+// Workgroup (c, section) handles one chunk of one section: wave w sums rows
+// b0 + w, b0 + w + 4, ..., lane l units l + 64 u (u < 4), and the four wave
+// sums are added in wave order.
 __global__ __launch_bounds__(256) void grad_part_kernel(const float *dz1, const float *dz2,
                                                         const float *dz3, const float *dlogit,
                                                         const __bf16 *a3, const float *x, int bsz,
                                                         float *part)
 {
-    const int c = blockIdx.x, sec = blockIdx.y, j = threadIdx.x;  // blockDim.x == H
+    __shared__ float red[4][7 * H];
+    const int c = blockIdx.x, sec = blockIdx.y;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int b0 = c * MLP_RED_ROWS, b1 = min(b0 + MLP_RED_ROWS, bsz);
+    float *mine = red[wave];
     float *out = part + (int64_t)c * MLP_RED_VEC;
+    int n_red, at;  // entries of this section and their first compact index
     if (sec == 0) {
-        float t[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-        for (int b = b0; b < b1; ++b) {
-            const float d = dz1[(int64_t)b * H + j];
+        float t[4][7];
 #pragma unroll
-            for (int i = 0; i < 6; ++i) t[i] += d * x[b * 6 + i];
-            t[6] += d;
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int i = 0; i < 7; ++i) t[u][i] = 0.f;
+#pragma unroll 4
+        for (int b = b0 + wave; b < b1; b += 4) {
+            float xi[6];
+#pragma unroll
+            for (int i = 0; i < 6; ++i) xi[i] = x[b * 6 + i];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const float d = dz1[(int64_t)b * H + lane + 64 * u];
+#pragma unroll
+                for (int i = 0; i < 6; ++i) t[u][i] += d * xi[i];
+                t[u][6] += d;
+            }
         }
 #pragma unroll
-        for (int i = 0; i < 6; ++i) out[6 * j + i] = t[i];
-        out[6 * H + j] = t[6];
+        for (int u = 0; u < 4; ++u) {
+            const int j = lane + 64 * u;
+#pragma unroll
+            for (int i = 0; i < 6; ++i) mine[6 * j + i] = t[u][i];
+            mine[6 * H + j] = t[u][6];
+        }
+        n_red = 7 * H;
+        at = 0;
     } else if (sec < 3) {
         const float *v = sec == 1 ? dz2 : dz3;
-        float t = 0.f;
-        for (int b = b0; b < b1; ++b) t += v[(int64_t)b * H + j];
-        out[(6 + sec) * H + j] = t;
+        float t[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll 4
+        for (int b = b0 + wave; b < b1; b += 4)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) t[u] += v[(int64_t)b * H + lane + 64 * u];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) mine[lane + 64 * u] = t[u];
+        n_red = H;
+        at = (6 + sec) * H;
     } else {
-        float t = 0.f, u = 0.f;
-        for (int b = b0; b < b1; ++b) {
-            t += dlogit[b] * (float)a3[(int64_t)b * H + j];
-            u += dlogit[b];
+        float t[4] = {0.f, 0.f, 0.f, 0.f}, tb = 0.f;
+#pragma unroll 4
+        for (int b = b0 + wave; b < b1; b += 4) {
+            const float dl = dlogit[b];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) t[u] += dl * (float)a3[(int64_t)b * H + lane + 64 * u];
+            tb += dl;
         }
-        out[9 * H + j] = t;
-        if (j == 0) out[10 * H] = u;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) mine[lane + 64 * u] = t[u];
+        if (lane == 0) mine[H] = tb;
+        n_red = H + 1;
+        at = 9 * H;
     }
+    __syncthreads();
+    for (int q = threadIdx.x; q < n_red; q += 256)
+        out[at + q] = ((red[0][q] + red[1][q]) + red[2][q]) + red[3][q];
 }
 
 // Finishes the gradient: g[i] = sum over chunks of part (compact entries) or
 // over the slices of the split weight-gradient products (wpart [2][n_slices]
 // [H][H], W2 then W3), each in index order.  With adam set, Adam (Kingma and
 // Ba 2015, bias-corrected) updates theta and refreshes the BF16 copies of W2
-// and W3.  The last workgroup adds the batch's mean loss to *loss.
+// and W3 (row-major and transposed).  The last workgroup adds the batch's
+// mean loss to *loss.
 struct AdamArgs {
     bool on;
     float lr, b1, b2, eps, c1, c2;
@@ -270,7 +327,8 @@ __global__ __launch_bounds__(256) void grad_finish_kernel(const float *part, int
                                                           const float *lossv, int bsz, float inv_n,
                                                           float *loss, float *g, AdamArgs ad,
                                                           float *theta, float *m, float *v,
-                                                          __bf16 *w2b, __bf16 *w3b)
+                                                          __bf16 *w2b, __bf16 *w3b, __bf16 *w2t,
+                                                          __bf16 *w3t)
 {
     if (blockIdx.x == gridDim.x - 1) {
         __shared__ float red[256];
@@ -308,6 +366,7 @@ __global__ __launch_bounds__(256) void grad_finish_kernel(const float *part, int
         const float *w = wpart + (int64_t)wm * n_slices * H * H + r;
         for (int z = 0; z < n_slices; ++z) gi += w[(int64_t)z * H * H];
     } else {
+#pragma unroll 8
         for (int c = 0; c < n_chunks; ++c) gi += part[(int64_t)c * MLP_RED_VEC + q];
     }
     g[i] = gi;
@@ -318,14 +377,24 @@ __global__ __launch_bounds__(256) void grad_finish_kernel(const float *part, int
     v[i] = vi;
     const float t = theta[i] - ad.lr * (mi / ad.c1) / (sqrtf(vi / ad.c2) + ad.eps);
     theta[i] = t;
-    if (wm == 0) w2b[r] = (__bf16)t;
-    if (wm == 1) w3b[r] = (__bf16)t;
+    const int rt = (r % H) * H + r / H;  // W[o][i] -> Wt[i][o]
+    if (wm == 0) {
+        w2b[r] = (__bf16)t;
+        w2t[rt] = (__bf16)t;
+    }
+    if (wm == 1) {
+        w3b[r] = (__bf16)t;
+        w3t[rt] = (__bf16)t;
+    }
 }
 
-__global__ void to_bf16_kernel(const float *src, __bf16 *dst, int n)
+// BF16 copies of a 256 x 256 weight matrix, row-major and transposed.
+__global__ void to_bf16_kernel(const float *src, __bf16 *dst, __bf16 *dst_t)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) dst[i] = (__bf16)src[i];
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= H * H) return;
+    dst[r] = (__bf16)src[r];
+    dst_t[(r % H) * H + r / H] = (__bf16)src[r];
 }
 
 unsigned blocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
@@ -335,9 +404,9 @@ unsigned blocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 hipError_t mlp_refresh_bf16(const MlpBufs &m, hipStream_t s)
 {
     hipLaunchKernelGGL(to_bf16_kernel, dim3(blocks(H * H, 256)), dim3(256), 0, s,
-                       m.theta + MLP_OFF_W2, m.w2b, H * H);
+                       m.theta + MLP_OFF_W2, m.w2b, m.w2t);
     hipLaunchKernelGGL(to_bf16_kernel, dim3(blocks(H * H, 256)), dim3(256), 0, s,
-                       m.theta + MLP_OFF_W3, m.w3b, H * H);
+                       m.theta + MLP_OFF_W3, m.w3b, m.w3t);
     return hipGetLastError();
 }
 
@@ -349,9 +418,9 @@ hipError_t mlp_forward(const MlpBufs &m, const float *raw, const float *labels, 
     const dim3 g2(H / 64, m_pad / 64);
     hipLaunchKernelGGL(layer1_kernel, dim3(blocks((int64_t)m_pad * H, 256)), dim3(256), 0, s, raw,
                        m.theta, c, bsz, m_pad, m.x, m.z1, m.a1);
-    hipLaunchKernelGGL((gemm_bf16_kernel<true, true, EPI_FWD>), g2, dim3(256), 0, s, m.a1, m.w2b,
+    hipLaunchKernelGGL((gemm_bf16_kernel<true, true, EPI_FWD, H>), g2, dim3(256), 0, s, m.a1, m.w2b,
                        m_pad, H, H, H, H, H, m.theta + MLP_OFF_W2 + H * H, nullptr, m.z2, m.a2);
-    hipLaunchKernelGGL((gemm_bf16_kernel<true, true, EPI_FWD>), g2, dim3(256), 0, s, m.a2, m.w3b,
+    hipLaunchKernelGGL((gemm_bf16_kernel<true, true, EPI_FWD, H>), g2, dim3(256), 0, s, m.a2, m.w3b,
                        m_pad, H, H, H, H, H, m.theta + MLP_OFF_W3 + H * H, nullptr, m.z3, m.a3);
     hipLaunchKernelGGL(head_kernel, dim3(blocks(labels ? m_pad : bsz, 4)), dim3(256), 0, s, m.a3,
                        m.z3, m.theta, labels, c, bsz, m_pad, 1.f / (float)bsz, m.logit, m.dlogit,
@@ -370,15 +439,15 @@ hipError_t mlp_backward(const MlpBufs &m, int bsz, const MlpAdamStep *adam, hipS
     const int k_sl = (m_pad / n_sl + 31) / 32 * 32;
     const dim3 gw(H / 64, H / 64, n_sl);
     float *w2p = m.wpart, *w3p = m.wpart + (int64_t)n_sl * H * H;
-    // layer 3: dW3 = dZ3^T A2, dZ2 = (dZ3 W3) * gelu'(Z2)
+    // layer 3: dW3 = dZ3^T A2, dZ2 = (dZ3 W3) * gelu'(Z2) (W3 read transposed, k-major)
     hipLaunchKernelGGL((gemm_bf16_kernel<false, false, EPI_STORE>), gw, dim3(256), 0, s, m.dz3b,
                        m.a2, H, H, m_pad, k_sl, H, H, nullptr, nullptr, w3p, nullptr);
-    hipLaunchKernelGGL((gemm_bf16_kernel<true, false, EPI_BWD>), g2, dim3(256), 0, s, m.dz3b, m.w3b,
+    hipLaunchKernelGGL((gemm_bf16_kernel<true, true, EPI_BWD, H>), g2, dim3(256), 0, s, m.dz3b, m.w3t,
                        m_pad, H, H, H, H, H, nullptr, m.z2, m.dz2, m.dz2b);
     // layer 2
     hipLaunchKernelGGL((gemm_bf16_kernel<false, false, EPI_STORE>), gw, dim3(256), 0, s, m.dz2b,
                        m.a1, H, H, m_pad, k_sl, H, H, nullptr, nullptr, w2p, nullptr);
-    hipLaunchKernelGGL((gemm_bf16_kernel<true, false, EPI_BWD>), g2, dim3(256), 0, s, m.dz2b, m.w2b,
+    hipLaunchKernelGGL((gemm_bf16_kernel<true, true, EPI_BWD, H>), g2, dim3(256), 0, s, m.dz2b, m.w2t,
                        m_pad, H, H, H, H, H, nullptr, m.z1, m.dz1, m.dz1b);
     // column sums (biases, first and last layer), then every entry finished at once
     const int n_chunks = (bsz + MLP_RED_ROWS - 1) / MLP_RED_ROWS;
@@ -393,7 +462,7 @@ hipError_t mlp_backward(const MlpBufs &m, int bsz, const MlpAdamStep *adam, hipS
     }
     hipLaunchKernelGGL(grad_finish_kernel, dim3(blocks(MLP_N_PARAMS, 256) + 1), dim3(256), 0, s,
                        m.part, n_chunks, m.wpart, n_sl, m.lossv, bsz, 1.f / (float)bsz, m.loss,
-                       m.grad, ad, m.theta, m.m, m.v, m.w2b, m.w3b);
+                       m.grad, ad, m.theta, m.m, m.v, m.w2b, m.w3b, m.w2t, m.w3t);
     return hipGetLastError();
 }
 
