@@ -728,5 +728,24 @@ def main():
     print(json.dumps(line), flush=True)
 
 
+def report_children():
+    """Print to stderr any child process of this one that is still alive."""
+    try:
+        import psutil
+        kids = psutil.Process().children(recursive=True)
+    except Exception as e:  # psutil missing or /proc unreadable
+        log("child processes at exit: unknown (%s)" % e)
+        return
+    desc = []
+    for k in kids:
+        try:
+            desc.append("%d %s" % (k.pid, " ".join(k.cmdline()[:4])))
+        except Exception:  # gone meanwhile, or not readable
+            desc.append("%d ?" % k.pid)
+    if desc:
+        log("child processes at exit: %s" % ", ".join(desc))
+
+
 if __name__ == "__main__":
     main()
+    report_children()

@@ -1546,7 +1546,11 @@ static ft_status launch_eval_select(ft_ctx c, EvalRun &run, bool grid, int tile,
     ft_status st;
     const int n_seg = opts->n_sub;
     const int k = opts->k;
-    const int64_t cap = std::max<int64_t>(65536, (int64_t)64 * k * n_seg);
+    // first guess of the candidate buffer: 64 per toplist slot, never more than
+    // the templates themselves nor 2^26 entries (ft_sync regrows it to the
+    // exact count when the threshold ties many templates)
+    const int64_t cap = std::min<int64_t>({std::max<int64_t>(65536, (int64_t)64 * k * n_seg),
+                                           std::max<int64_t>(n_t, 1), (int64_t)1 << 26});
     st = ensure_select(c, n_seg, k, n_seg_map, cap);
     if (st != FT_OK) return st;
     if ((e = ensure(&c->d_edges, &c->cap_edges, edges.size())) != hipSuccess) return hip_fail(c, e, "alloc edges");
@@ -1781,7 +1785,12 @@ ft_status ft_sync(ft_ctx c)
     if (flags & ERR_CAND_OVERFLOW) {
         uint32_t total = 0;
         hipMemcpy(&total, c->d_off + c->last_nsub, sizeof total, hipMemcpyDeviceToHost);
-        const int64_t cap = (int64_t)total + 1024;
+        // the per-sub-band offsets are 32-bit and saturate at 2^32 - 1
+        if (total == 0xffffffffu)
+            return fail(c, FT_E_UNSUPPORTED, "2^32 - 1 or more toplist candidates (the K-th largest statistic ties too many templates)");
+        const EvalRun &lr = c->last_run;
+        const int64_t n_last = c->last_grid ? (int64_t)lr.n_f0 * lr.n_f1 * lr.n_sky : lr.n_list;
+        const int64_t cap = std::min<int64_t>((int64_t)total + 1024, std::max<int64_t>(n_last, 1));
         st = ensure_select(c, c->last_nsub, c->last_k, c->last_grid ? c->last_run.n_f0 : c->last_run.n_list, cap);
         if (st != FT_OK) return st;
         c->last_run.err = c->d_err;

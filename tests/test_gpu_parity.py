@@ -370,3 +370,28 @@ def test_max_subbands_and_max_k(ft):
     _, tops, _ = run_gpu(ft, w, k=65536, edges=one, sky=sky3)
     assert len(tops[0]) == s64_3.size
     assert_toplists(tops, [oracle.toplist(s64_3, np.zeros(s64_3.size, np.int32), 1, 65536)[0]], s64_3, w.n_sft)
+
+
+def test_joint_maxima_and_candidate_regrowth(ft):
+    """K = 65536 with 4096 sub-bands in one call: every sub-band returns all of
+    its 20 templates, and the candidate buffer is sized by the bank, not by
+    K x sub-bands.  Then a table of zeros over 81,920 templates with K = 25 in
+    one sub-band: every template ties at the threshold, more than the first
+    candidate buffer (65,536) holds, so the selection grows it to the exact
+    count and runs again."""
+    w = synth.wide_band(8192, seed=31, n_sky=5)
+    f0t, _, _ = oracle.grid_params(w.f0, w.f1, w.sky.shape[0])
+    s64, _ = oracle_grid(w)
+    edges = w.f0[0] + (np.arange(0, 8193, 2) - 0.5) / w.t_sft
+    s32, tops, _ = run_gpu(ft, w, k=65536, edges=edges)
+    want = oracle.toplist(s64, oracle.subband(f0t, edges), 4096, 65536)
+    assert all(len(t) == 20 for t in tops)
+    assert_stats(s32, s64, w.n_sft)
+    assert_toplists(tops, want, s64, w.n_sft)
+    z = synth.wide_band(8192, seed=32, n_sky=5, with_noise=False)
+    one = np.array([z.f0[0] - 0.5 / z.t_sft, z.f0[-1] + 0.5 / z.t_sft])
+    s32, tops, info = run_gpu(ft, z, k=25, edges=one)
+    assert info.n_candidates == s32.size == 81920
+    s64z, _ = oracle_grid(z)
+    f0z, _, _ = oracle.grid_params(z.f0, z.f1, z.sky.shape[0])
+    assert_toplists(tops, oracle.toplist(s64z, oracle.subband(f0z, one), 1, 25), s64z, z.n_sft)
