@@ -18,15 +18,17 @@
 //      into LDS; columns are clamped into the table (a column outside it can
 //      only be read after a range error, which is reported).
 //   accumulate(p): for every f1 value each lane forms the estimate
-//      t2 = f0*G + h (one fused multiply-add) of x + 1/2 - u_lo - lo for the
-//      first template of its run, takes B = floor(t2) -- the LDS row offset of
-//      the bin -- and reads B, B+1, ..., B+L-1 (one address per run from a
-//      wave-uniform row base, immediate offsets; lanes hit distinct banks for
-//      odd L).
+//      t2 = d*G + H (one FP32 fused multiply-add, d = f0 - f0min of the tile,
+//      H = f0min*G + h - lo formed in FP64 and rounded once) of
+//      x + 1/2 - u_lo - lo for the first template of its run, takes
+//      B = floor(t2) -- the LDS row offset of the bin -- and reads B, B+1, ...,
+//      B+L-1 (one address per run from a wave-uniform row base, immediate
+//      offsets; lanes hit distinct banks for odd L).
 //
 // Run guard.  |t~ - (x + 1/2)| and the rounding of every canonical evaluation
 // are bounded by the host, together with the grid's deviation from uniform
-// spacing dT/T_sft, by eta.  With u = fract(t~) and e = dT*g - 1, template l of
+// spacing dT/T_sft, by eta; the FP32 estimate adds the bound of est_err_fp32
+// (both together are eta below).  With u = fract(t~) and e = dT*g - 1, template l of
 // the run has canonical floor(x_l + 1/2) = floor(t~) + l whenever u + l*e lies
 // in [eta, 1 - eta) for every l in [0, L) -- i.e. u in [u_lo, u_hi) with
 // u_lo = eta + max(0, -(L-1)e), u_hi = 1 - eta - max(0, (L-1)e) (the expression
@@ -52,12 +54,14 @@ namespace ft {
 
 namespace {
 
-// One SFT step of one sky point, as the accumulation reads it (one address):
-// G = g T_sft, w = u_hi - u_lo (run-guard window) and, per f1 value,
-// h = c G + 1/2 - u_lo - lo (the estimate then lands on the LDS row offset).
+// One SFT step of one sky point, as the accumulation reads it, in FP32:
+// per f1 value H = f0min G + c G + 1/2 - u_lo - lo (so d G + H lands on the
+// LDS row offset), G = g T_sft and w = u_hi - u_lo (the run-guard window,
+// rounded down).  Two LDS reads per step.
 template <int JT>
-struct StepParams {
-    double G, w, h[JT];
+struct alignas(16) StepParams {
+    float h[JT];
+    float G, w;
 };
 
 template <int L, int JT, int NW, int KS>
@@ -128,6 +132,18 @@ struct TileGeom {
     double f0min, f0max;
 };
 
+// Bound (bins) on the error of the FP32 run estimate t2 = fma(d, G, H)
+// against the FP64 estimate it replaces, for |d G| <= span and |t2| <= wtp + 2
+// (the row offset of a bin inside the window; farther lanes fail the guard):
+// the FP32 roundings of d and of G (each <= 2^-24 span), of H = t2 - d G
+// (<= 2^-24 (wtp + 2 + span)) and of the fused multiply-add (<= 2^-24
+// (wtp + 2)), plus 10^-9 for the FP64 roundings in forming H; 1% margin.
+__device__ __forceinline__ double est_err_fp32(const EvalRun &r, const TileGeom &tg)
+{
+    const double span = (tg.f0max - tg.f0min) * r.t_sft * 1.01 + 1.0;
+    return 0x1p-24 * (3.0 * span + 2.0 * ((double)r.wtp + 2.0)) * 1.01 + 1e-9;
+}
+
 // Parameters and exact window of SFT stage [k0, k0 + ks) of a tile, then the
 // asynchronous HBM/L2 -> LDS copies of its windows.  Every wave derives the
 // parameters of its own sky point (lane (jl, kk) for f1 value jl and SFT kk)
@@ -148,23 +164,30 @@ __device__ __forceinline__ bool prepare_stage(const EvalRun &r, const TileGeom &
     const double T = r.t_sft;
     const double nx = sh.sky[wave][0], ny = sh.sky[wave][1], nz = sh.sky[wave][2];
     const double *vdt = sh.vdt[stage & 1];
-    for (int q = lane; q < JT * KS; q += 64) {
+    const double eta = r.eta + est_err_fp32(r, tg);
+    constexpr int NQ = (JT * KS + 63) / 64;
+    double hq[NQ];  // FP64 H of the lane's (jl, kk) before the shift by lo
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) {
+        const int q = lane + 64 * i;
         const int jl = q / KS, kk = q % KS;
-        if (kk >= ks) continue;
+        hq[i] = 0.0;
+        if (q >= JT * KS || kk >= ks) continue;
         const double *vk = vdt + 3 * kk;
         const double g = doppler_factor(vk[0], vk[1], vk[2], nx, ny, nz);
         const double G = g * T;
         const double dt = vdt[3 * KS + kk];
         const double c = sh.f1[jl] * dt;
         const double eL = (double)(L - 1) * (r.dT * g - 1.0);
-        const double ulo = r.eta + fmax(0.0, -eL);
-        if (L > 1) P.q[wave][kk].h[jl] = (c * G + 0.5) - ulo;  // rebased on lo below
+        const double ulo = eta + fmax(0.0, -eL);
+        hq[i] = ((c * G + 0.5) - ulo) + tg.f0min * G;  // shifted by lo below
         if (wave == 0) P.c[jl][kk] = c;
         if (jl == 0) {
             P.g[wave][kk] = g;
             if (SKYW) P.wt[wave][kk] = (float)(sky_ab(r.arms + 6 * (int64_t)(k0 + kk), nx, ny, nz) * sh.norm[wave]);
-            P.q[wave][kk].G = G;
-            if (L > 1) P.q[wave][kk].w = ((1.0 - r.eta) - fmax(0.0, eL)) - ulo;
+            P.q[wave][kk].G = (float)G;
+            // rounded down, so fract(t2) < w in FP32 implies it in real numbers
+            if (L > 1) P.q[wave][kk].w = (float)((((1.0 - eta) - fmax(0.0, eL)) - ulo) * (1.0 - 0x1p-22));
             double cmin = c, cmax = c;
 #pragma unroll
             for (int j = 1; j < JT; ++j) {
@@ -197,17 +220,19 @@ __device__ __forceinline__ bool prepare_stage(const EvalRun &r, const TileGeom &
         bad = (err & ERR_WINDOW) != 0;
     }
     if (!wave_all(!bad)) return false;
-    // rebase the estimates on the first staged bin (each lane its own entries;
-    // lo is an integer near the estimate, so the difference rounds at most by
-    // an ulp of the window width)
+    // shift the estimates to the first staged bin and round them to FP32 (each
+    // lane its own entries; lo is an integer near the estimate, so the FP64
+    // difference is exact to an ulp of the window width)
     if (L > 1)
-        for (int q = lane; q < JT * KS; q += 64) {
+#pragma unroll
+        for (int i = 0; i < NQ; ++i) {
+            const int q = lane + 64 * i;
             const int jl = q / KS, kk = q % KS;
-            if (kk >= ks) continue;
+            if (q >= JT * KS || kk >= ks) continue;
             int lo_k = sh.lo_w[0][kk];
 #pragma unroll
             for (int w = 1; w < NW; ++w) lo_k = min(lo_k, sh.lo_w[w][kk]);
-            P.q[wave][kk].h[jl] -= (double)lo_k;
+            P.q[wave][kk].h[jl] = (float)(hq[i] - (double)lo_k);
         }
 
     // the next stage's velocities and time offsets (read by its preparation,
@@ -268,18 +293,21 @@ __device__ __forceinline__ StepParams<JT> load_step(const StageParams<L, JT, NW,
 }
 
 // Run estimates of one SFT step from its parameters (already in registers):
-// B[jl] = floor(t2) with t2 = f0 G + h (the LDS row offset of the run's first
-// bin), and per f1 value the lanes (a wave mask) where a run fails the guard
-// fract(t2) < w.  Returns true if some run of the wave failed.
+// B[jl] = floor(t2) with t2 = d G + H in FP32 (the LDS row offset of the
+// run's first bin; d = f0 - f0min of the lane), and per f1 value the lanes (a
+// wave mask) where a run fails the guard fract(t2) < w.  t2 >= -(eta + u_lo)
+// (lo is the smallest bin of the tile), so a negative t2 has
+// fract(t2) >= 1 - eta - u_lo >= w and fails.  Returns true if some run of
+// the wave failed.
 template <int JT>
-__device__ __forceinline__ bool run_bins(double f0_lane, const StepParams<JT> &q, int (&B)[JT], uint64_t (&fail)[JT])
+__device__ __forceinline__ bool run_bins(float d_lane, const StepParams<JT> &q, int (&B)[JT], uint64_t (&fail)[JT])
 {
     uint64_t any = 0;
 #pragma unroll
     for (int jl = 0; jl < JT; ++jl) {
-        const double t = fma(f0_lane, q.G, q.h[jl]);
+        const float t = __builtin_fmaf(d_lane, q.G, q.h[jl]);
         B[jl] = (int)t;
-        fail[jl] = __builtin_amdgcn_ballot_w64(!(__builtin_amdgcn_fract(t) < q.w));
+        fail[jl] = __builtin_amdgcn_ballot_w64(!(__builtin_amdgcn_fractf(t) < q.w));
         any |= fail[jl];
     }
     return any != 0;
@@ -319,13 +347,13 @@ template <int L, int JT, int NW, int KS, bool SKYW>
 __device__ __forceinline__ void accumulate_pipelined(const EvalRun &r, const StageParams<L, JT, NW, KS> &P,
                                                      const Shared<L, JT, NW, KS> &sh, const TileGeom &tg,
                                                      const float *wb, int wtp, int k0, int ks, int wave,
-                                                     int lane, double f0_lane, float (&acc)[JT][L],
+                                                     int lane, float d_lane, float (&acc)[JT][L],
                                                      double (&tot)[JT][L])
 {
     const double T = r.t_sft;
     int B[JT];
     uint64_t fail[JT];
-    bool any = run_bins<JT>(f0_lane, load_step<L, JT, NW, KS>(P, wave, 0), B, fail);
+    bool any = run_bins<JT>(d_lane, load_step<L, JT, NW, KS>(P, wave, 0), B, fail);
     for (int kk = 0; kk < ks; ++kk) {
         const int kn = min(kk + 1, ks - 1);
         const StepParams<JT> qn = load_step<L, JT, NW, KS>(P, wave, kn);
@@ -339,7 +367,7 @@ __device__ __forceinline__ void accumulate_pipelined(const EvalRun &r, const Sta
         uint64_t fn[JT];
         // keep the next bins ahead of the adds (the compiler would otherwise
         // sink them past the branch, after the wait for the gathers)
-        const bool any_next = run_bins<JT>(f0_lane, qn, Bn, fn);
+        const bool any_next = run_bins<JT>(d_lane, qn, Bn, fn);
 #pragma unroll
         for (int jl = 0; jl < JT; ++jl) asm volatile("" ::"v"(Bn[jl]), "s"(fn[jl]));
         if (any)  // rare: some lane is within the guard margin of a bin edge
@@ -393,6 +421,7 @@ __device__ __forceinline__ void eval_tile(const EvalRun &r, int64_t b, float *wi
     const double T = r.t_sft;
     const int i0 = tg.i_base + lane * L;
     const double f0_lane = r.f0[min(i0, tg.i_last)];
+    const float d_lane = (float)(f0_lane - tg.f0min);  // FP64 difference, one FP32 rounding
     const int wtp = r.wtp;
 
     __syncthreads();  // the previous tile's threads are done with the shared state
@@ -435,7 +464,7 @@ __device__ __forceinline__ void eval_tile(const EvalRun &r, int64_t b, float *wi
         const StageParams<L, JT, NW, KS> &P = sh.p[cur];
         const float *wb = win + cur * KS * wtp;
         if (L > 1 && PIPE) {
-            accumulate_pipelined<L, JT, NW, KS, SKYW>(r, P, sh, tg, wb, wtp, k0, ks, wave, lane, f0_lane, acc, tot);
+            accumulate_pipelined<L, JT, NW, KS, SKYW>(r, P, sh, tg, wb, wtp, k0, ks, wave, lane, d_lane, acc, tot);
         } else
         for (int kk = 0; kk < ks; ++kk) {
             if (L == 1) {
@@ -454,7 +483,7 @@ __device__ __forceinline__ void eval_tile(const EvalRun &r, int64_t b, float *wi
                 const StepParams<JT> q = load_step<L, JT, NW, KS>(P, wave, kk);
                 int B[JT];
                 uint64_t fail[JT];
-                const bool any = run_bins<JT>(f0_lane, q, B, fail);
+                const bool any = run_bins<JT>(d_lane, q, B, fail);
                 const float *wk = wb + kk * wtp;
                 float v[JT][L];
 #pragma unroll
