@@ -1274,9 +1274,13 @@ static std::vector<int64_t> plain_tune_key(ft_ctx c, int64_t n0, int64_t n1, int
     return {0, n0, n1, (int64_t)c->n_sft, (int64_t)floor_log2(ns), (int64_t)dop, uniform ? 1 : 0};
 }
 
+static hipError_t launch_grid(const EvalRun &run, int tile, const WindowPlan *tail, hipStream_t s);
+
 // Times the candidate tiles on one contiguous range of the Doppler-ordered sky
 // (the middle of the list, about 2.5e11 evaluations) and returns the fastest
-// in best (0-based; -1 when no candidate's window fits in LDS).
+// in best (0-based; -1 when no candidate's window fits in LDS).  Each
+// candidate runs as a call would run it: with its f1-tail companion when its
+// JT does not divide n_f1.
 static ft_status tune_plain(ft_ctx c, const EvalRun &run, double dt_absmax, bool uniform, int &best)
 {
     const auto t_start = std::chrono::steady_clock::now();
@@ -1290,6 +1294,7 @@ static ft_status tune_plain(ft_ctx c, const EvalRun &run, double dt_absmax, bool
     struct Trial {
         int tile;
         EvalRun r;
+        WindowPlan tail;  // tile -1: no f1-tail dispatch
     };
     std::vector<Trial> trials;
     for (int id : tune_candidates((double)n0, (double)n1, uniform)) {
@@ -1305,16 +1310,26 @@ static ft_status tune_plain(ft_ctx c, const EvalRun &run, double dt_absmax, bool
         r.sky_perm = run.sky_perm + s0;
         r.n_sky = (int32_t)n_s;
         r.tiles_sky = (int32_t)((n_s + tile_cfg(id).NW - 1) / tile_cfg(id).NW);
-        trials.push_back({id, r});
+        WindowPlan tail;
+        const int jt = tile_cfg(id).JT;
+        const int rem = (int)(n1 % jt);
+        const int comp = rem && n1 > jt ? tile_companion(id, rem) : -1;
+        if (comp >= 0 && (!run.sky_norm || tile_has_sky_weights(comp))) {
+            tail = plan_window(c->f0_h.data(), n0, c->f1_h.data() + (n1 - rem), rem, c->sky_tile_h.data(), ns,
+                               dt_absmax, c->vmax, c->t_sft, comp);
+            if (tail.tile >= 0) tail.tiles_sky = (int32_t)((n_s + tile_cfg(comp).NW - 1) / tile_cfg(comp).NW);
+        }
+        trials.push_back({id, r, tail});
     }
     c->tune_log.clear();
     if (trials.empty()) return FT_OK;
     // the first launch also brings the clocks up; it is not timed
-    hipError_t e = launch_eval_grid(trials[0].r, tile_cfg(trials[0].tile), c->stream);
+    auto tail_of = [](const Trial &t) { return t.tail.tile >= 0 ? &t.tail : nullptr; };
+    hipError_t e = launch_grid(trials[0].r, trials[0].tile, tail_of(trials[0]), c->stream);
     std::vector<float> ms(trials.size(), 0.f);
     for (size_t i = 0; i < trials.size() && e == hipSuccess; ++i) {
         e = hipEventRecord(c->ev[0], c->stream);
-        if (e == hipSuccess) e = launch_eval_grid(trials[i].r, tile_cfg(trials[i].tile), c->stream);
+        if (e == hipSuccess) e = launch_grid(trials[i].r, trials[i].tile, tail_of(trials[i]), c->stream);
         if (e == hipSuccess) e = hipEventRecord(c->ev[1], c->stream);
         if (e == hipSuccess) e = hipEventSynchronize(c->ev[1]);
         if (e == hipSuccess) e = hipEventElapsedTime(&ms[i], c->ev[0], c->ev[1]);
