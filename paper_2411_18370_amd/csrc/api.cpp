@@ -2150,6 +2150,7 @@ struct BatchPlan {
     std::vector<char> uniform;             // per run: the run-length guard applies
     std::vector<double> dt_absmax, vmax;   // per run: window inputs
     std::vector<int> group_wtp;            // per tile id: widest LDS row of its runs
+    int small_chunk = 8;                   // f0 values per item of the small-bank kernel (5 or 8)
 };
 
 // Tile-dependent fields of batch run r for `tile` (0-based, -1: direct).
@@ -2180,7 +2181,26 @@ int64_t run_items(const BatchPlan &pl, int r)
 {
     const EvalRun &E = pl.runs[r];
     if (pl.tile[r] >= 0) return (int64_t)E.tiles_f0 * E.tiles_f1 * E.tiles_sky;
-    return (int64_t)((E.n_f0 + SMALL_F0_CHUNK - 1) / SMALL_F0_CHUNK) * (((int64_t)E.n_f1 * E.n_sky + 63) / 64);
+    return (int64_t)((E.n_f0 + pl.small_chunk - 1) / pl.small_chunk) * (((int64_t)E.n_f1 * E.n_sky + 63) / 64);
+}
+
+// f0 chunk of the small-bank kernel for the batch's small runs: the one with
+// fewer modelled lane operations, counting per item and SFT a fixed part
+// (Doppler factor, f1 dt, loads: about 1.5 bins' worth) plus one bin, gather
+// and add per f0 slot.  Label campaigns (5 f0 values per run) take 5; a batch
+// of 16- or 24-value runs takes 8.
+int choose_small_chunk(const BatchPlan &pl)
+{
+    double cost[2] = {0.0, 0.0};
+    const int chunks[2] = {5, 8};
+    for (size_t r = 0; r < pl.runs.size(); ++r) {
+        if (pl.tile[r] >= 0) continue;
+        const EvalRun &E = pl.runs[r];
+        const double js = (double)(((int64_t)E.n_f1 * E.n_sky + 63) / 64) * (double)E.n_sft;
+        for (int q = 0; q < 2; ++q)
+            cost[q] += (double)((E.n_f0 + chunks[q] - 1) / chunks[q]) * js * (1.5 + chunks[q]);
+    }
+    return cost[0] < cost[1] ? 5 : 8;
 }
 
 void append_items(const BatchPlan &pl, int r, std::vector<int2> &out)
@@ -2224,7 +2244,7 @@ static ft_status launch_batch_sequence(ft_ctx c, const BatchPlan &pl, bool gener
     {
         const int n_direct = (int)pl.items[tile_count()].size();
         if (e == hipSuccess && n_direct > 0)
-            e = launch_eval_batch_small(b.runs, b.items + item_off, n_direct, b.counters + tile_count(),
+            e = launch_eval_batch_small(b.runs, b.items + item_off, n_direct, pl.small_chunk, b.counters + tile_count(),
                                         std::min(n_direct, 8192), st);
     }
     if (e == hipSuccess)
@@ -2650,6 +2670,7 @@ ft_status ft_eval_batch(ft_ctx c, const ft_batch *bt, int32_t use_graph)
         plan_tiles();
     }
     // work items grouped by tile (the direct kernel's last)
+    pl.small_chunk = choose_small_chunk(pl);
     int64_t total_items = 0;
     for (int r = 0; r < n_runs; ++r) total_items += run_items(pl, r);
     if (total_items >= 0x7fffffff) return fail(c, FT_E_UNSUPPORTED, "too many work items");

@@ -248,7 +248,8 @@ __global__ __launch_bounds__(256) void eval_direct_kernel(EvalRun r)
 // Persistent evaluation of batch runs whose grid is too small for the tile
 // kernel (or whose window does not fit in LDS).  A wavefront pulls an item
 // (run, chunk) from the queue; chunk = f0 chunk * n_js_chunks + js chunk,
-// covering up to SMALL_F0 consecutive f0 values and 64 consecutive (f1, sky)
+// covering up to SF0 consecutive f0 values (SF0 = 5 or 8, chosen per batch)
+// and 64 consecutive (f1, sky)
 // pairs js = s * n_f1 + j, one pair per lane.  Per SFT a lane forms the
 // canonical Doppler factor and f1 * dt once and then the canonical FP64 bin of
 // each of its f0 values, gathering from the (cached) table; the gathers of SFT
@@ -256,7 +257,6 @@ __global__ __launch_bounds__(256) void eval_direct_kernel(EvalRun r)
 // in f0 (f0 strictly increasing, g > 0), so the run's first and last bins
 // bound all of them and only those two are range-checked; a wave with an
 // out-of-range lane clamps every read into the row and flags the error.
-constexpr int SMALL_F0 = SMALL_F0_CHUNK;
 static_assert(SUM_BLOCK % 2 == 0, "blocks are walked in pairs of SFTs");
 
 // Read-only inputs that the kernel reaches through pointers held in the run
@@ -284,43 +284,47 @@ __device__ __forceinline__ SmallSft small_sft(const EvalRun &r, int k)
 // in 32 bits: rows hold fewer than 2^28 columns); returns false in every lane
 // if some lane of the wave left the table (the offsets are then clamped into
 // the row).
-__device__ __forceinline__ bool small_bins(const EvalRun &r, const SmallSft &q, const double (&f0v)[SMALL_F0],
-                                           double f1, double nx, double ny, double nz, uint32_t (&off)[SMALL_F0],
+template <int SF0>
+__device__ __forceinline__ bool small_bins(const EvalRun &r, const SmallSft &q, const double (&f0v)[SF0],
+                                           double f1, double nx, double ny, double nz, uint32_t (&off)[SF0],
                                            bool &bad)
 {
     const double g = doppler_factor(q.vx, q.vy, q.vz, nx, ny, nz);
     const double c = f1 * q.dt;
-    int B[SMALL_F0];
+    int B[SF0];
 #pragma unroll
-    for (int l = 0; l < SMALL_F0; ++l) B[l] = bin_fp64(f0v[l], c, g, r.t_sft);
+    for (int l = 0; l < SF0; ++l) B[l] = bin_fp64(f0v[l], c, g, r.t_sft);
     // B[l] is non-decreasing in l (the last f0 repeats past the chunk's end)
-    const bool in = B[0] >= r.first_bin && B[SMALL_F0 - 1] - r.first_bin < r.n_bins;
+    const bool in = B[0] >= r.first_bin && B[SF0 - 1] - r.first_bin < r.n_bins;
     const bool wave_in = __builtin_amdgcn_ballot_w64(!in) == 0;
     if (!wave_in) {
         bad |= !in;
 #pragma unroll
-        for (int l = 0; l < SMALL_F0; ++l) B[l] = min(max(B[l], r.first_bin), r.first_bin + r.n_bins - 1);
+        for (int l = 0; l < SF0; ++l) B[l] = min(max(B[l], r.first_bin), r.first_bin + r.n_bins - 1);
     }
     const uint32_t fb4 = (uint32_t)r.first_bin * 4u;
 #pragma unroll
-    for (int l = 0; l < SMALL_F0; ++l) off[l] = (uint32_t)B[l] * 4u - fb4;
+    for (int l = 0; l < SF0; ++l) off[l] = (uint32_t)B[l] * 4u - fb4;
     return wave_in;
 }
 
-__device__ __forceinline__ void small_gather(const EvalRun &r, int k, const uint32_t (&off)[SMALL_F0],
-                                             float (&v)[SMALL_F0])
+template <int SF0>
+__device__ __forceinline__ void small_gather(const EvalRun &r, int k, const uint32_t (&off)[SF0],
+                                             float (&v)[SF0])
 {
     const char *base = (const char *)(r.power_w + (int64_t)k * r.n_bins);
 #pragma unroll
-    for (int l = 0; l < SMALL_F0; ++l) v[l] = *(global_float *)(base + off[l]);
+    for (int l = 0; l < SF0; ++l) v[l] = *(global_float *)(base + off[l]);
 }
 
-__device__ __forceinline__ void small_add(const float (&v)[SMALL_F0], float (&acc)[SMALL_F0])
+template <int SF0>
+__device__ __forceinline__ void small_add(const float (&v)[SF0], float (&acc)[SF0])
 {
 #pragma unroll
-    for (int l = 0; l < SMALL_F0; ++l) acc[l] += v[l];
+    for (int l = 0; l < SF0; ++l) acc[l] += v[l];
 }
 
+template <int SF0>
 __global__ __launch_bounds__(64) void eval_batch_small_kernel(const EvalRun *__restrict__ runs,
                                                               const int2 *__restrict__ items, int n_items,
                                                               unsigned *counter)
@@ -335,21 +339,21 @@ __global__ __launch_bounds__(64) void eval_batch_small_kernel(const EvalRun *__r
         const EvalRun r = runs[it.x];
         const int n_js = r.n_f1 * r.n_sky;
         const int n_jsc = (n_js + 63) / 64;
-        const int i0 = (it.y / n_jsc) * SMALL_F0;
-        const int n_i = min(SMALL_F0, r.n_f0 - i0);
+        const int i0 = (it.y / n_jsc) * SF0;
+        const int n_i = min(SF0, r.n_f0 - i0);
         const int js_raw = (it.y % n_jsc) * 64 + lane;
         const bool live = js_raw < n_js;
         const int js = live ? js_raw : n_js - 1;
         const int j = js % r.n_f1, s = js / r.n_f1;
         const double f1 = r.f1[j];
         const double nx = r.sky[3 * s], ny = r.sky[3 * s + 1], nz = r.sky[3 * s + 2];
-        double f0v[SMALL_F0];
+        double f0v[SF0];
 #pragma unroll
-        for (int l = 0; l < SMALL_F0; ++l) f0v[l] = as_const(r.f0)[i0 + min(l, n_i - 1)];
-        float acc[SMALL_F0];
-        double tot[SMALL_F0];
+        for (int l = 0; l < SF0; ++l) f0v[l] = as_const(r.f0)[i0 + min(l, n_i - 1)];
+        float acc[SF0];
+        double tot[SF0];
 #pragma unroll
-        for (int l = 0; l < SMALL_F0; ++l) {
+        for (int l = 0; l < SF0; ++l) {
             acc[l] = 0.f;
             tot[l] = 0.0;
         }
@@ -360,8 +364,8 @@ __global__ __launch_bounds__(64) void eval_batch_small_kernel(const EvalRun *__r
         // past the last SFT re-read the last SFT (unused).  Summation blocks
         // of SUM_BLOCK SFTs (even) are walked in pairs, so va holds the next
         // block's first SFT when a block ends.
-        uint32_t off[SMALL_F0];
-        float va[SMALL_F0], vb[SMALL_F0];
+        uint32_t off[SF0];
+        float va[SF0], vb[SF0];
         SmallSft q = small_sft(r, 0);
         small_bins(r, q, f0v, f1, nx, ny, nz, off, bad);
         small_gather(r, 0, off, va);
@@ -382,7 +386,7 @@ __global__ __launch_bounds__(64) void eval_batch_small_kernel(const EvalRun *__r
             if (k < ke) small_add(va, acc);  // odd tail: k = n - 1
             if (r.sum_mode == FT_SUM_BLOCKED) {
 #pragma unroll
-                for (int l = 0; l < SMALL_F0; ++l) {
+                for (int l = 0; l < SF0; ++l) {
                     tot[l] += (double)acc[l];
                     acc[l] = 0.f;
                 }
@@ -392,7 +396,7 @@ __global__ __launch_bounds__(64) void eval_batch_small_kernel(const EvalRun *__r
         if (live) {
             float *out = r.stats + (int64_t)js * r.n_f0 + i0;
 #pragma unroll
-            for (int l = 0; l < SMALL_F0; ++l)
+            for (int l = 0; l < SF0; ++l)
                 if (l < n_i) out[l] = (float)(tot[l] + (double)acc[l]);
         }
     }
@@ -976,12 +980,18 @@ hipError_t launch_eval_grid_direct(const EvalRun &run, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_eval_batch_small(const EvalRun *runs, const int2 *items, int n_items, unsigned *counter,
-                                   int grid, hipStream_t s)
+hipError_t launch_eval_batch_small(const EvalRun *runs, const int2 *items, int n_items, int f0_chunk,
+                                   unsigned *counter, int grid, hipStream_t s)
 {
     if (n_items <= 0) return hipSuccess;
-    hipLaunchKernelGGL(eval_batch_small_kernel, dim3((unsigned)grid), dim3(64), 0, s, runs, items, n_items,
-                       counter);
+    if (f0_chunk == 5)
+        hipLaunchKernelGGL(eval_batch_small_kernel<5>, dim3((unsigned)grid), dim3(64), 0, s, runs, items, n_items,
+                           counter);
+    else if (f0_chunk == 8)
+        hipLaunchKernelGGL(eval_batch_small_kernel<8>, dim3((unsigned)grid), dim3(64), 0, s, runs, items, n_items,
+                           counter);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 

@@ -289,10 +289,10 @@ hipError_t launch_eval_batch(const EvalRun *runs, const int2 *items, int n_items
                              unsigned *counter, int grid, const TileCfg &cfg, hipStream_t s);
 // Batch runs outside the tile kernel (one wavefront per item): items[i] =
 // (run, chunk), chunk = f0 chunk * ceil(n_f1 n_sky / 64) + (f1, sky) chunk,
-// f0 chunks of SMALL_F0_CHUNK values; counter must be zero at launch.
-constexpr int SMALL_F0_CHUNK = 8;
-hipError_t launch_eval_batch_small(const EvalRun *runs, const int2 *items, int n_items, unsigned *counter,
-                                   int grid, hipStream_t s);
+// f0 chunks of f0_chunk values (5 or 8; one choice per batch); counter must be
+// zero at launch.
+hipError_t launch_eval_batch_small(const EvalRun *runs, const int2 *items, int n_items, int f0_chunk,
+                                   unsigned *counter, int grid, hipStream_t s);
 // Exact per-run toplists of a batch (one workgroup per run, all of a run's
 // templates form one segment): out[r*k + rank], n_out[r], max_z[r].
 hipError_t launch_select_batch(const EvalRun *runs, int n_runs, int k, int cap_per_run,

@@ -115,18 +115,26 @@ def test_batch_given_tables_and_errors(ft):
         assert e.value.status == ft.FT_E_INVALID
 
 
-def _small_bank_batch(seed=47):
+# Shapes (n_f0, n_f1, n_sky, n_sft) of runs below the tile kernel's 32 f0
+# values.  The small-bank kernel takes f0 chunks of 5 or 8, one choice per
+# batch by a cost model: the first set (dominated by label-like 5 x 11 x 16
+# runs) takes 5, the second (16- and 24-value runs) takes 8.
+SMALL_SHAPES_5 = [(1, 1, 1, 1), (5, 11, 16, 517), (8, 3, 16, 33), (9, 13, 5, 31), (31, 1, 48, 2),
+                  (5, 11, 16, 100), (12, 5, 13, 64)]
+SMALL_SHAPES_8 = [(16, 3, 16, 300), (24, 5, 13, 200), (8, 3, 16, 33), (31, 1, 48, 2), (7, 2, 9, 50),
+                  (1, 1, 1, 1)]
+
+
+def _small_bank_batch(seed=47, shapes=SMALL_SHAPES_5):
     """Runs below the tile kernel's 32 f0 values, at the shapes where the
-    small-bank kernel has edges: f0 chunks of 8 (1, 5, 8, 9, 31 values, one
-    irregular grid), 64-lane (f1, sky) chunks (1, 48, 65, 176 pairs), SFT
-    counts with odd tails and partial 32-SFT sum blocks (1, 2, 31, 33, 517);
-    random tables wide enough for every track."""
+    small-bank kernel has edges: partial f0 chunks of 5 and 8 (1, 5, 7, 8, 9,
+    12, 16, 24, 31 values, one irregular grid), 64-lane (f1, sky) chunks (1,
+    18, 48, 65, 176 pairs), SFT counts with odd tails and partial 32-SFT sum
+    blocks (1, 2, 31, 33, 50, 517); random tables wide enough for every track."""
     pool = synth.campaign(1, seed=seed, n_pool=700, n_sft_range=(80, 600))
     rng = np.random.default_rng(seed)
     t_sft = pool.t_sft
     vmax = float(np.max(np.linalg.norm(pool.v, axis=1)))
-    shapes = [(1, 1, 1, 1), (5, 11, 16, 517), (8, 3, 16, 33), (9, 13, 5, 31), (31, 1, 48, 2),
-              (5, 11, 16, 100), (12, 5, 13, 64)]
     f0s, f1s, skys, runs, tables = [], [], [], [], []
     off = n0 = n1 = ns = 0
     for q, (nf0, nf1, nsk, nsft) in enumerate(shapes):
@@ -155,12 +163,14 @@ def _small_bank_batch(seed=47):
     return pool, runs, tables, np.concatenate(f0s), np.concatenate(f1s), np.concatenate(skys)
 
 
-def test_small_bank_runs_match_oracle(ft):
-    """Batch runs with fewer than 32 f0 values (the small-bank kernel): every
-    toplist member is the oracle's, with its exact FP64 statistic; the FP32
-    statistic is within the blocked-sum bound and equals a plain call's."""
+@pytest.mark.parametrize("shapes", [SMALL_SHAPES_5, SMALL_SHAPES_8], ids=["chunk5", "chunk8"])
+def test_small_bank_runs_match_oracle(ft, shapes):
+    """Batch runs with fewer than 32 f0 values (the small-bank kernel, with
+    either f0 chunk): every toplist member is the oracle's, with its exact
+    FP64 statistic; the FP32 statistic is within the blocked-sum bound and
+    equals a plain call's."""
     import torch
-    pool, runs, tables, f0, f1, sky = _small_bank_batch()
+    pool, runs, tables, f0, f1, sky = _small_bank_batch(shapes=shapes)
     k = 512
     power = np.concatenate([t.ravel() for t in tables])
     with ft.Context(0, torch.cuda.current_stream().cuda_stream) as c:
