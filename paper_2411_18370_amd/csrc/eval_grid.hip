@@ -40,6 +40,16 @@
 // that f1 value's templates at their canonical FP64 bins.  Either way every bin
 // equals the canonical FP64 bin.
 //
+// Whole-wave steps.  On a uniform grid with spacing near one bin, template m
+// of the tile has x_m + 1/2 = x_0 + 1/2 + m (1 + e) up to eta, so its
+// canonical bin is B0 + m for every m < n_in whenever u0 + m e stays in
+// [eta, 1 - eta) at m = 0 and m = n_in - 1 (u0 = fract of the FP64 estimate
+// at the first template).  The stage preparation checks this per (sky point,
+// SFT, f1) in FP64 and keeps the row offset of B0 and a per-SFT mask; a step
+// whose f1 values all pass reads at row offset + lane's first template + l,
+// with no per-lane estimate, and the other steps take the run-guard path
+// above.
+//
 // Sums: FP32 within aligned blocks of 32 SFTs, block sums accumulated in FP64.
 //
 // Sky-dependent weights (SKYW): the staged table holds u_k P (as without
@@ -64,10 +74,20 @@ struct alignas(16) StepParams {
     float G, w;
 };
 
+// One SFT step of one sky point where the whole wave is certified: per f1
+// value the LDS row offset (dwords from the stage's window buffer) of the
+// canonical bin of the tile's first template; template m of the tile then has
+// bin offset sb + m.
+template <int JT>
+struct alignas(16) WaveStep {
+    int sb[JT];
+};
+
 template <int L, int JT, int NW, int KS>
 struct StageParams {
     double g[NW][KS];                // canonical Doppler factor
     StepParams<JT> q[NW][KS];        // run-estimate parameters
+    WaveStep<JT> ws[NW][KS];         // whole-wave bins (steps whose mask bit is set)
     double c[JT][KS];                // canonical f1 * dt
     float wt[NW][KS];                // sky-dependent weight factor (SKYW)
     int lo[KS];                      // first staged bin
@@ -155,7 +175,7 @@ __device__ __forceinline__ double est_err_fp32(const EvalRun &r, const TileGeom 
 template <int L, int JT, int NW, int KS, bool SKYW>
 __device__ __forceinline__ bool prepare_stage(const EvalRun &r, const TileGeom &tg, int stage,
                                               StageParams<L, JT, NW, KS> &P,
-                                              Shared<L, JT, NW, KS> &sh, float *wbuf)
+                                              Shared<L, JT, NW, KS> &sh, float *wbuf, uint64_t &wmask)
 {
     const int k0 = stage * KS;
     const int ks = min(KS, r.n_sft - k0);
@@ -167,20 +187,36 @@ __device__ __forceinline__ bool prepare_stage(const EvalRun &r, const TileGeom &
     const double eta = r.eta + est_err_fp32(r, tg);
     constexpr int NQ = (JT * KS + 63) / 64;
     double hq[NQ];  // FP64 H of the lane's (jl, kk) before the shift by lo
+    int b0q[NQ];    // bin of the tile's first template (valid where okq)
+    bool okq[NQ];   // the whole tile's bins are b0q + m
 #pragma unroll
     for (int i = 0; i < NQ; ++i) {
         const int q = lane + 64 * i;
         const int jl = q / KS, kk = q % KS;
         hq[i] = 0.0;
+        b0q[i] = 0;
+        okq[i] = false;
         if (q >= JT * KS || kk >= ks) continue;
         const double *vk = vdt + 3 * kk;
         const double g = doppler_factor(vk[0], vk[1], vk[2], nx, ny, nz);
         const double G = g * T;
         const double dt = vdt[3 * KS + kk];
         const double c = sh.f1[jl] * dt;
-        const double eL = (double)(L - 1) * (r.dT * g - 1.0);
+        const double e = r.dT * g - 1.0;
+        const double eL = (double)(L - 1) * e;
         const double ulo = eta + fmax(0.0, -eL);
         hq[i] = ((c * G + 0.5) - ulo) + tg.f0min * G;  // shifted by lo below
+        if (L > 1) {
+            // whole-tile guard: FP64 estimate of x + 1/2 at the tile's first
+            // template, then the run guard over all n_in templates (r.eta
+            // bounds the estimate and the grid's spacing error at any offset)
+            const double x0 = (c * G + 0.5) + tg.f0min * G;
+            const double bf = floor(x0);
+            const double u0 = x0 - bf;
+            const double span = (double)(tg.n_in - 1) * e;
+            okq[i] = u0 + fmin(0.0, span) >= r.eta && u0 + fmax(0.0, span) < 1.0 - r.eta;
+            b0q[i] = (int)bf;
+        }
         if (wave == 0) P.c[jl][kk] = c;
         if (jl == 0) {
             P.g[wave][kk] = g;
@@ -222,18 +258,35 @@ __device__ __forceinline__ bool prepare_stage(const EvalRun &r, const TileGeom &
     if (!wave_all(!bad)) return false;
     // shift the estimates to the first staged bin and round them to FP32 (each
     // lane its own entries; lo is an integer near the estimate, so the FP64
-    // difference is exact to an ulp of the window width)
-    if (L > 1)
+    // difference is exact to an ulp of the window width), and the whole-wave
+    // row offsets with their step mask: bit kk is set when every f1 value of
+    // step kk is certified and the tile's reads lie inside the window row
+    wmask = 0;
+    if (L > 1) {
+        const int span_rd = ((tg.n_in - 1) / L) * L + L;  // reads of the last run end here
+        uint64_t okm[NQ];
 #pragma unroll
         for (int i = 0; i < NQ; ++i) {
             const int q = lane + 64 * i;
             const int jl = q / KS, kk = q % KS;
-            if (q >= JT * KS || kk >= ks) continue;
-            int lo_k = sh.lo_w[0][kk];
+            bool ok = false;
+            if (q < JT * KS && kk < ks) {
+                int lo_k = sh.lo_w[0][kk];
 #pragma unroll
-            for (int w = 1; w < NW; ++w) lo_k = min(lo_k, sh.lo_w[w][kk]);
-            P.q[wave][kk].h[jl] = (float)(hq[i] - (double)lo_k);
+                for (int w = 1; w < NW; ++w) lo_k = min(lo_k, sh.lo_w[w][kk]);
+                P.q[wave][kk].h[jl] = (float)(hq[i] - (double)lo_k);
+                const int off = b0q[i] - lo_k;
+                ok = okq[i] && off >= 0 && off + span_rd <= r.wt;
+                P.ws[wave][kk].sb[jl] = kk * r.wtp + (ok ? off : 0);
+            }
+            okm[i] = __builtin_amdgcn_ballot_w64(ok);
         }
+        // KS divides 64, so the KS bits of one f1 value lie in one mask word
+        uint64_t m = KS >= 64 ? ~0ull : (1ull << KS) - 1;
+#pragma unroll
+        for (int jl = 0; jl < JT; ++jl) m &= okm[(jl * KS) / 64] >> ((jl * KS) % 64);
+        wmask = m;
+    }
 
     // the next stage's velocities and time offsets (read by its preparation,
     // after the end-of-stage wait)
@@ -289,6 +342,15 @@ __device__ __forceinline__ StepParams<JT> load_step(const StageParams<L, JT, NW,
     q.w = P.q[wave][kk].w;
 #pragma unroll
     for (int jl = 0; jl < JT; ++jl) q.h[jl] = P.q[wave][kk].h[jl];
+    return q;
+}
+
+template <int L, int JT, int NW, int KS>
+__device__ __forceinline__ WaveStep<JT> load_wave_step(const StageParams<L, JT, NW, KS> &P, int wave, int kk)
+{
+    WaveStep<JT> q;
+#pragma unroll
+    for (int jl = 0; jl < JT; ++jl) q.sb[jl] = P.ws[wave][kk].sb[jl];
     return q;
 }
 
@@ -448,8 +510,11 @@ __device__ __forceinline__ void eval_tile(const EvalRun &r, int64_t b, float *wi
             tot[j][l] = 0.0;
         }
 
+    // the lane's first template in the tile (idle lanes repeat the last run)
+    const int lane_off = min(lane, (tg.n_in - 1) / L) * L;
     const int n_stage = (r.n_sft + KS - 1) / KS;
-    if (!prepare_stage<L, JT, NW, KS, SKYW>(r, tg, 0, sh.p[0], sh, win)) return;
+    uint64_t wm_cur = 0, wm_next = 0;  // whole-wave step masks of the current and next stage
+    if (!prepare_stage<L, JT, NW, KS, SKYW>(r, tg, 0, sh.p[0], sh, win, wm_cur)) return;
     wait_loads();
     __syncthreads();
 
@@ -458,11 +523,14 @@ __device__ __forceinline__ void eval_tile(const EvalRun &r, int64_t b, float *wi
         const int ks = min(KS, r.n_sft - k0);
         const int cur = p & 1;
         if (p + 1 < n_stage) {
-            if (!prepare_stage<L, JT, NW, KS, SKYW>(r, tg, p + 1, sh.p[cur ^ 1], sh, win + (cur ^ 1) * KS * wtp))
+            if (!prepare_stage<L, JT, NW, KS, SKYW>(r, tg, p + 1, sh.p[cur ^ 1], sh, win + (cur ^ 1) * KS * wtp,
+                                                    wm_next))
                 return;
         }
         const StageParams<L, JT, NW, KS> &P = sh.p[cur];
         const float *wb = win + cur * KS * wtp;
+        const uint64_t wm = wm_cur;
+        wm_cur = wm_next;
         if (L > 1 && PIPE) {
             accumulate_pipelined<L, JT, NW, KS, SKYW>(r, P, sh, tg, wb, wtp, k0, ks, wave, lane, d_lane, acc, tot);
         } else
@@ -477,20 +545,31 @@ __device__ __forceinline__ void eval_tile(const EvalRun &r, int64_t b, float *wi
                     else acc[jl][0] += wb[base + B];
                 }
             } else {
-                // reads at the estimated bins first; the rare failing f1
-                // values (some lane within the guard margin of a bin edge)
-                // are then re-read at their canonical bins
-                const StepParams<JT> q = load_step<L, JT, NW, KS>(P, wave, kk);
-                int B[JT];
-                uint64_t fail[JT];
-                const bool any = run_bins<JT>(d_lane, q, B, fail);
-                const float *wk = wb + kk * wtp;
                 float v[JT][L];
+                if ((wm >> kk) & 1) {
+                    // the whole wave is certified: bins sb + lane_off + l
+                    const WaveStep<JT> q = load_wave_step<L, JT, NW, KS>(P, wave, kk);
+                    const float *wl = wb + lane_off;
 #pragma unroll
-                for (int jl = 0; jl < JT; ++jl)
+                    for (int jl = 0; jl < JT; ++jl)
 #pragma unroll
-                    for (int l = 0; l < L; ++l) v[jl][l] = wk[B[jl] + l];
-                if (any) canonical_fix<L, JT, NW, KS>(P, sh, tg, wb, kk * wtp - P.lo[kk], kk, wave, lane, T, fail, v);
+                        for (int l = 0; l < L; ++l) v[jl][l] = wl[q.sb[jl] + l];
+                } else {
+                    // reads at the estimated bins first; the rare failing f1
+                    // values (some lane within the guard margin of a bin edge)
+                    // are then re-read at their canonical bins
+                    const StepParams<JT> q = load_step<L, JT, NW, KS>(P, wave, kk);
+                    int B[JT];
+                    uint64_t fail[JT];
+                    const bool any = run_bins<JT>(d_lane, q, B, fail);
+                    const float *wk = wb + kk * wtp;
+#pragma unroll
+                    for (int jl = 0; jl < JT; ++jl)
+#pragma unroll
+                        for (int l = 0; l < L; ++l) v[jl][l] = wk[B[jl] + l];
+                    if (any)
+                        canonical_fix<L, JT, NW, KS>(P, sh, tg, wb, kk * wtp - P.lo[kk], kk, wave, lane, T, fail, v);
+                }
                 if (SKYW) {
                     const float wt = P.wt[wave][kk];
 #pragma unroll
