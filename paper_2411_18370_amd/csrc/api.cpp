@@ -107,6 +107,9 @@ struct ft_ctx_s {
     size_t cap_qsample = 0;
     int32_t *d_perm = nullptr;
     size_t cap_perm = 0;
+    double *d_tune_sky = nullptr;  // the autotuner's sky sample (Doppler order) and its
+    int32_t *d_tune_perm = nullptr;  // original indices
+    size_t cap_tune_sky = 0, cap_tune_perm = 0;
     float *d_stats = nullptr;
     size_t cap_stats = 0;
     float *d_bsum = nullptr;  // block sums of the split binary evaluation
@@ -580,6 +583,8 @@ void ft_destroy(ft_ctx c)
     release(&c->d_sky, &c->cap_sky);
     release(&c->d_sky_tile, &c->cap_sky_tile);
     release(&c->d_perm, &c->cap_perm);
+    release(&c->d_tune_sky, &c->cap_tune_sky);
+    release(&c->d_tune_perm, &c->cap_tune_perm);
     release(&c->d_edges, &c->cap_edges);
     release(&c->d_stats, &c->cap_stats);
     release(&c->d_bsum, &c->cap_bsum);
@@ -1276,9 +1281,9 @@ static std::vector<int64_t> plain_tune_key(ft_ctx c, int64_t n0, int64_t n1, int
 
 static hipError_t launch_grid(const EvalRun &run, int tile, const WindowPlan *tail, hipStream_t s);
 
-// Times the candidate tiles on one contiguous range of the Doppler-ordered sky
-// (the middle of the list, about 2.5e11 evaluations) and returns the fastest
-// in best (0-based; -1 when no candidate's window fits in LDS).  Each
+// Times the candidate tiles on a sample of the Doppler-ordered sky (blocks
+// spread over the whole order, about 1e12 evaluations) and returns the
+// fastest in best (0-based; -1 when no candidate's window fits in LDS).  Each
 // candidate runs as a call would run it: with its f1-tail companion when its
 // JT does not divide n_f1.
 static ft_status tune_plain(ft_ctx c, const EvalRun &run, double dt_absmax, bool uniform, int &best)
@@ -1287,10 +1292,44 @@ static ft_status tune_plain(ft_ctx c, const EvalRun &run, double dt_absmax, bool
     best = -1;
     const int64_t n0 = run.n_f0, n1 = run.n_f1, ns = run.n_sky;
     const double per_sky = (double)n0 * (double)n1 * (double)c->n_sft;
-    int64_t n_s = (int64_t)std::ceil(2.5e11 / per_sky);
-    n_s = (n_s + 7) / 8 * 8;
-    if (n_s > ns) n_s = ns;
-    const int64_t s0 = (ns - n_s) / 2 / 8 * 8;
+    // the sample, about 1e12 evaluations in one launch: blocks of 64
+    // consecutive points of the Doppler-ordered sky (a tile keeps its
+    // neighbours) at evenly spaced positions over the whole order, since the
+    // share of whole-wave steps, and with it the ranking of the tiles,
+    // changes with the sky region.  Its size keeps the partly filled last
+    // round of workgroups of each dispatch (a tile and its f1-tail companion
+    // are two) below a few percent of the time.
+    constexpr int64_t kBlock = 64;
+    int64_t n_s = (int64_t)std::ceil(1e12 / per_sky);
+    n_s = (n_s + kBlock - 1) / kBlock * kBlock;
+    const double *smp_sky = run.sky_tile;
+    const int32_t *smp_perm = run.sky_perm;
+    std::vector<double> st_h;
+    std::vector<int32_t> sp_h;
+    if (n_s >= ns) {
+        n_s = ns;
+    } else {
+        const int64_t n_blk = n_s / kBlock;
+        st_h.resize((size_t)n_s * 3);
+        sp_h.resize((size_t)n_s);
+        for (int64_t b = 0; b < n_blk; ++b) {
+            const int64_t start = n_blk > 1 ? (ns - kBlock) * b / (n_blk - 1) : 0;
+            for (int64_t i = 0; i < kBlock; ++i) {
+                for (int d = 0; d < 3; ++d) st_h[(size_t)(3 * (b * kBlock + i) + d)] = c->sky_tile_h[(size_t)(3 * (start + i) + d)];
+                sp_h[(size_t)(b * kBlock + i)] = c->perm_h[(size_t)(start + i)];
+            }
+        }
+        hipError_t e = ensure(&c->d_tune_sky, &c->cap_tune_sky, (size_t)n_s * 3);
+        if (e == hipSuccess) e = ensure(&c->d_tune_perm, &c->cap_tune_perm, (size_t)n_s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(c->d_tune_sky, st_h.data(), st_h.size() * sizeof(double), hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(c->d_tune_perm, sp_h.data(), sp_h.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                               c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "tile tuning sample");
+        smp_sky = c->d_tune_sky;
+        smp_perm = c->d_tune_perm;
+    }
     struct Trial {
         int tile;
         EvalRun r;
@@ -1306,8 +1345,8 @@ static ft_status tune_plain(ft_ctx c, const EvalRun &run, double dt_absmax, bool
         r.wtp = wp.wtp;
         r.tiles_f0 = wp.tiles_f0;
         r.tiles_f1 = wp.tiles_f1;
-        r.sky_tile = run.sky_tile + 3 * s0;
-        r.sky_perm = run.sky_perm + s0;
+        r.sky_tile = smp_sky;
+        r.sky_perm = smp_perm;
         r.n_sky = (int32_t)n_s;
         r.tiles_sky = (int32_t)((n_s + tile_cfg(id).NW - 1) / tile_cfg(id).NW);
         WindowPlan tail;
@@ -1325,11 +1364,12 @@ static ft_status tune_plain(ft_ctx c, const EvalRun &run, double dt_absmax, bool
     if (trials.empty()) return FT_OK;
     // the first launch also brings the clocks up; it is not timed
     auto tail_of = [](const Trial &t) { return t.tail.tile >= 0 ? &t.tail : nullptr; };
-    hipError_t e = launch_grid(trials[0].r, trials[0].tile, tail_of(trials[0]), c->stream);
+    auto launch_sample = [&](const Trial &t) { return launch_grid(t.r, t.tile, tail_of(t), c->stream); };
+    hipError_t e = launch_sample(trials[0]);
     std::vector<float> ms(trials.size(), 0.f);
     for (size_t i = 0; i < trials.size() && e == hipSuccess; ++i) {
         e = hipEventRecord(c->ev[0], c->stream);
-        if (e == hipSuccess) e = launch_grid(trials[i].r, trials[i].tile, tail_of(trials[i]), c->stream);
+        if (e == hipSuccess) e = launch_sample(trials[i]);
         if (e == hipSuccess) e = hipEventRecord(c->ev[1], c->stream);
         if (e == hipSuccess) e = hipEventSynchronize(c->ev[1]);
         if (e == hipSuccess) e = hipEventElapsedTime(&ms[i], c->ev[0], c->ev[1]);
