@@ -161,6 +161,11 @@ struct ft_ctx_s {
     bool have_batch = false;
     int batch_runs = 0, batch_k = 0, batch_cap = 0;
     hipStream_t capture_stream = nullptr;
+    // side streams (default priority) and events of a batch's concurrent
+    // evaluation launches
+    static constexpr int kSide = 3;
+    hipStream_t side[kSide] = {nullptr, nullptr, nullptr};
+    hipEvent_t fork_ev = nullptr, join_ev[kSide] = {nullptr, nullptr, nullptr};
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     hipEvent_t bev[2] = {nullptr, nullptr};
@@ -535,6 +540,16 @@ ft_status ft_create(ft_ctx *out, int device, void *hip_stream)
             ft_destroy(c);
             return FT_E_DEVICE;
         }
+    // side streams of a batch's concurrent evaluation launches (created here,
+    // outside any graph capture)
+    bool side_ok = hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming) == hipSuccess;
+    for (int i = 0; i < ft_ctx_s::kSide && side_ok; ++i)
+        side_ok = hipStreamCreateWithFlags(&c->side[i], hipStreamNonBlocking) == hipSuccess &&
+                  hipEventCreateWithFlags(&c->join_ev[i], hipEventDisableTiming) == hipSuccess;
+    if (!side_ok) {
+        ft_destroy(c);
+        return FT_E_DEVICE;
+    }
     *out = c;
     return FT_OK;
 }
@@ -636,6 +651,11 @@ void ft_destroy(ft_ctx c)
     if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
     if (c->graph) (void)hipGraphDestroy(c->graph);
     if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
+    for (int i = 0; i < ft_ctx_s::kSide; ++i) {
+        if (c->side[i]) (void)hipStreamDestroy(c->side[i]);
+        if (c->join_ev[i]) (void)hipEventDestroy(c->join_ev[i]);
+    }
+    if (c->fork_ev) (void)hipEventDestroy(c->fork_ev);
     for (auto &e : c->bev)
         if (e) (void)hipEventDestroy(e);
     for (auto &e : c->ev)
@@ -2272,20 +2292,44 @@ static ft_status launch_batch_sequence(ft_ctx c, const BatchPlan &pl, bool gener
     if (e == hipSuccess && generate)
         e = launch_gen_tables(b.gen, n_runs, b.gen_prefix, pl.gen_prefix_sft[n_runs], b.gen, n_runs,
                               b.gen_prefix, pl.gen_prefix_sft[n_runs], st);
+    // the evaluation launches (one persistent launch per tile, then the
+    // small-bank kernel) draw on disjoint work and run concurrently: the
+    // first on st, the others on side streams forked from st and joined back
+    // before the selection (a captured graph gets parallel branches), so one
+    // launch's last workgroups overlap the next launch
+    struct Launch {
+        int id;  // tile, or tile_count() for the small-bank kernel
+        int64_t off;
+        int n;
+    };
+    std::vector<Launch> ls;
     int64_t item_off = 0;
-    for (int id = 0; id < tile_count() && e == hipSuccess; ++id) {
+    for (int id = 0; id <= tile_count(); ++id) {
         const int n_items = (int)pl.items[id].size();
-        if (n_items == 0) continue;
-        const int grid = std::min(n_items, 2048);
-        e = launch_eval_batch(b.runs, b.items + item_off, n_items, pl.group_wtp[id], b.counters + id, grid, tile_cfg(id),
-                              st);
+        if (n_items > 0) ls.push_back({id, item_off, n_items});
         item_off += n_items;
     }
-    {
-        const int n_direct = (int)pl.items[tile_count()].size();
-        if (e == hipSuccess && n_direct > 0)
-            e = launch_eval_batch_small(b.runs, b.items + item_off, n_direct, pl.small_chunk, b.counters + tile_count(),
-                                        std::min(n_direct, 8192), st);
+    const int n_side = std::min<int>((int)ls.size() - 1, ft_ctx_s::kSide);
+    if (e == hipSuccess && n_side > 0) e = hipEventRecord(c->fork_ev, st);
+    int joined = 0;  // side streams that waited on the fork (and must be joined back)
+    for (int i = 0; i < n_side && e == hipSuccess; ++i) {
+        e = hipStreamWaitEvent(c->side[i], c->fork_ev, 0);
+        if (e == hipSuccess) joined = i + 1;
+    }
+    for (size_t i = 0; i < ls.size() && e == hipSuccess; ++i) {
+        const Launch &L = ls[i];
+        hipStream_t s = i == 0 || n_side == 0 ? st : c->side[(i - 1) % n_side];
+        if (L.id < tile_count())
+            e = launch_eval_batch(b.runs, b.items + L.off, L.n, pl.group_wtp[L.id], b.counters + L.id,
+                                  std::min(L.n, 2048), tile_cfg(L.id), s);
+        else
+            e = launch_eval_batch_small(b.runs, b.items + L.off, L.n, pl.small_chunk, b.counters + tile_count(),
+                                        std::min(L.n, 8192), s);
+    }
+    for (int i = 0; i < joined; ++i) {
+        hipError_t ej = hipEventRecord(c->join_ev[i], c->side[i]);
+        if (ej == hipSuccess) ej = hipStreamWaitEvent(st, c->join_ev[i], 0);
+        if (e == hipSuccess) e = ej;
     }
     if (e == hipSuccess)
         e = launch_select_batch(b.runs, n_runs, c->batch_k, c->batch_cap, b.cand, b.s64, b.out, b.nout, b.maxz, c->d_err,
@@ -2370,6 +2414,10 @@ static ft_status tune_batch(ft_ctx c, BatchPlan &pl, const std::vector<ft_run> &
             if (active[q] && (int64_t)items.size() + n_items >= 0x7fffffffLL) active[q] = 0;
             if (!active[q]) continue;
             for (int r : cls[q].runs) append_items(pl, r, items);
+            // longest first, as the batch launch orders them
+            std::stable_sort(items.begin() + (int64_t)off[q], items.end(), [&](const int2 &a, const int2 &b2) {
+                return pl.runs[a.x].n_sft > pl.runs[b2.x].n_sft;
+            });
         }
         off[nc] = items.size();
         if (items.empty()) continue;
@@ -2720,6 +2768,13 @@ ft_status ft_eval_batch(ft_ctx c, const ft_batch *bt, int32_t use_graph)
         append_items(pl, r, pl.items[t >= 0 ? t : tile_count()]);
         if (t >= 0) pl.group_wtp[t] = std::max(pl.group_wtp[t], pl.runs[r].wtp);
     }
+    // longest first within each group (an item's time grows with its run's
+    // SFT count): the workgroups draining a queue then end together, instead
+    // of a few long items that were queued last running on an idle GPU
+    for (auto &v : pl.items)
+        std::stable_sort(v.begin(), v.end(), [&](const int2 &a, const int2 &b2) {
+            return pl.runs[a.x].n_sft > pl.runs[b2.x].n_sft;
+        });
     std::vector<int2> items_flat;
     items_flat.reserve((size_t)total_items);
     for (auto &v : pl.items) items_flat.insert(items_flat.end(), v.begin(), v.end());

@@ -594,8 +594,11 @@ __global__ void init_state_kernel(uint32_t *state, uint32_t *cnt, uint32_t *fill
 // Batches: one workgroup per run does the whole exact selection of that run
 // (runs hold at most a few 1e5 templates): radix select in LDS, candidate
 // compaction, FP64 re-summation (one wavefront per candidate) and ranking.
+// SB_THREADS threads: the 16 wavefronts re-sum up to 16 candidates at once.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void select_batch_kernel(const EvalRun *runs, int k, int cap,
+constexpr int SB_THREADS = 1024;
+
+__global__ __launch_bounds__(SB_THREADS) void select_batch_kernel(const EvalRun *runs, int k, int cap,
                                                            int64_t *cand_all, double *s64_all,
                                                            ft_candidate *out, int32_t *n_out,
                                                            double *max_z, uint32_t *err)
@@ -620,11 +623,11 @@ __global__ __launch_bounds__(256) void select_batch_kernel(const EvalRun *runs, 
     }
     for (int pass = 0; pass < 4; ++pass) {
         const int shift = 24 - 8 * pass;
-        hist[tid] = 0;
+        if (tid < 256) hist[tid] = 0;
         __syncthreads();
         if (!st_done) {
             const uint32_t mask = st_mask, prefix = st_prefix;
-            for (int64_t t = tid; t < n_t; t += 256) {
+            for (int64_t t = tid; t < n_t; t += SB_THREADS) {
                 const uint32_t key = __float_as_uint(R.stats[t]);
                 if (key > NAN_KEY || (key & mask) != prefix) continue;
                 atomicAdd(&hist[(key >> shift) & 255u], 1u);
@@ -662,7 +665,7 @@ __global__ __launch_bounds__(256) void select_batch_kernel(const EvalRun *runs, 
         __syncthreads();
     }
     const uint32_t thr = st_thr;
-    for (int64_t t = tid; t < n_t; t += 256) {
+    for (int64_t t = tid; t < n_t; t += SB_THREADS) {
         const uint32_t key = __float_as_uint(R.stats[t]);
         if (key > NAN_KEY || key < thr) continue;
         const uint32_t pos = atomicAdd(&n_cand, 1u);
@@ -674,34 +677,38 @@ __global__ __launch_bounds__(256) void select_batch_kernel(const EvalRun *runs, 
         if (tid == 0) atomicOr(err, ERR_CAND_OVERFLOW);
         nc = cap;
     }
-    // FP64 re-summation in SFT order with canonical bins
+    // FP64 re-summation in SFT order with canonical bins; the terms of the
+    // next 64 SFTs are formed (their loads issued) before the current 64 are
+    // added in order
     uint32_t bad = 0;
-    for (int p = wave; p < nc; p += 4) {
+    for (int p = wave; p < nc; p += SB_THREADS / 64) {
         const TemplateParams tp = params_of(R, true, cand[p]);
-        double acc = 0.0;
-        for (int k0 = 0; k0 < R.n_sft; k0 += 64) {
-            const int kq = k0 + lane;
-            double val = 0.0;
-            if (kq < R.n_sft) {
-                const double *vk = R.v + 3 * (int64_t)kq;
-                const double g = doppler_factor(vk[0], vk[1], vk[2], tp.nx, tp.ny, tp.nz);
-                int b = bin_fp64(tp.f0, tp.f1 * R.dt[kq], g, R.t_sft) - R.first_bin;
-                if (b < 0 || b >= R.n_bins) {
-                    bad = ERR_RANGE;
-                    b = b < 0 ? 0 : R.n_bins - 1;
-                }
-                const double w = R.weight ? (double)R.weight[kq] : 1.0;
-                val = w * (double)R.power[(int64_t)kq * R.n_bins + b];
+        auto term = [&](int kq) {
+            if (kq >= R.n_sft) return 0.0;
+            const double *vk = R.v + 3 * (int64_t)kq;
+            const double g = doppler_factor(vk[0], vk[1], vk[2], tp.nx, tp.ny, tp.nz);
+            int b = bin_fp64(tp.f0, tp.f1 * R.dt[kq], g, R.t_sft) - R.first_bin;
+            if (b < 0 || b >= R.n_bins) {
+                bad = ERR_RANGE;
+                b = b < 0 ? 0 : R.n_bins - 1;
             }
+            const double w = R.weight ? (double)R.weight[kq] : 1.0;
+            return w * (double)R.power[(int64_t)kq * R.n_bins + b];
+        };
+        double acc = 0.0;
+        double val = term(lane);
+        for (int k0 = 0; k0 < R.n_sft; k0 += 64) {
+            const double nxt = term(k0 + 64 + lane);
             const int m = min(64, R.n_sft - k0);
             for (int l = 0; l < m; ++l) acc = acc + readlane_f64(val, l);
+            val = nxt;
         }
         if (lane == 0) s64[p] = acc;
     }
     if (bad) atomicOr(err, bad);
     __syncthreads();
     const double mu = 2.0 * N, sigma = 2.0 * sqrt(N);
-    for (int p = tid; p < nc; p += 256) {
+    for (int p = tid; p < nc; p += SB_THREADS) {
         const double sp = s64[p];
         const int64_t tp = cand[p];
         int rank = 0;
@@ -760,7 +767,7 @@ hipError_t launch_select_batch(const EvalRun *runs, int n_runs, int k, int cap_p
                                int32_t *n_out, double *max_z, uint32_t *err, hipStream_t s)
 {
     if (n_runs <= 0) return hipSuccess;
-    hipLaunchKernelGGL(select_batch_kernel, dim3((unsigned)n_runs), dim3(256), 0, s, runs, k,
+    hipLaunchKernelGGL(select_batch_kernel, dim3((unsigned)n_runs), dim3(SB_THREADS), 0, s, runs, k,
                        cap_per_run, cand, cand_s64, out, n_out, max_z, err);
     return hipGetLastError();
 }

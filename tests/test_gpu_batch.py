@@ -49,15 +49,25 @@ def test_batch_equals_plain_calls(ft, use_graph):
 
 
 def test_batch_graph_replay_is_identical(ft):
+    """The captured graph (its evaluation launches on streams forked inside it)
+    gives the eager batch's toplists on capture and on every replay, with eager
+    work on the same context and synchronizations between the replays."""
     import torch
-    cp = _small_campaign(seed=42, n_runs=9)
+    cp = _small_campaign(seed=44, n_runs=9)
+    n_f0 = [R["n_f0"] for R in cp.runs]
+    # small-bank and tile runs: at least two concurrent evaluation launches
+    assert min(n_f0) < 32 <= max(n_f0)
     with ft.Context(0, torch.cuda.current_stream().cuda_stream) as c:
+        c.eval_campaign(cp, use_graph=0)
+        eager = [_key(c.batch_toplist(r, cp.k)) for r in range(len(cp.runs))]
         c.eval_campaign(cp, use_graph=1)
-        first = [_key(c.batch_toplist(r, cp.k)) for r in range(len(cp.runs))]
-        for _ in range(3):
+        assert [_key(c.batch_toplist(r, cp.k)) for r in range(len(cp.runs))] == eager
+        for i in range(4):
+            _plain_run(ft, c, cp, i)
+            torch.cuda.synchronize()
             c.batch_replay()
             again = [_key(c.batch_toplist(r, cp.k)) for r in range(len(cp.runs))]
-            assert again == first
+            assert again == eager, i
         assert c.batch_time() > 0
 
 
