@@ -6,8 +6,10 @@
 // [i0, i0 + L), i0 = tile_start + l*L) x JT f1 values x NW sky points (one per
 // wave; sky points are visited in a Doppler-coherent order chosen by the
 // host).  SFTs are processed in stages of KS, double-buffered: while stage p
-// is accumulated, the parameters of stage p+1 are derived and its table
-// windows stream from HBM/L2 straight into LDS (global_load_lds).
+// is accumulated, the table windows of stage p+1 stream from HBM/L2 straight
+// into LDS (global_load_lds), and at every other stage the parameters of the
+// next two stages are derived in one pass (a lane per (stage, f1, SFT), so
+// that a wave's lanes are busy; parameters in a ring of three stages).
 //   prepare(p): Doppler factor g[s][k] (canonical FP64 order), G = g*T_sft,
 //      run-guard bounds, c[j][k] = f1_j*dt_k and h = c*G + 1/2 - u_lo - lo; then the
 //      exact bin range [lo, hi] of the tile per SFT.  The FP64 bin is monotone
@@ -97,10 +99,10 @@ template <int L, int JT, int NW, int KS>
 struct Shared {
     static_assert(KS <= 64 && NW <= 16, "one lane per SFT of a stage");
     static_assert(SUM_BLOCK % KS == 0, "summation blocks end with a stage");
-    StageParams<L, JT, NW, KS> p[2];
+    StageParams<L, JT, NW, KS> p[3];  // stages p, p + 1, p + 2 (ring by stage % 3)
     double f0[64 * L];
-    int lo_w[NW][KS], hi_w[NW][KS];  // per sky point bin range of the stage being prepared
-    double vdt[2][4 * KS];           // per stage: v/c [KS][3] then dt [KS], prefetched a stage ahead
+    int lo_w[NW][2 * KS], hi_w[NW][2 * KS];  // per sky point bin ranges of the two stages being prepared
+    double vdt[2][8 * KS];  // per pair of stages: v/c [KS][3] then dt [KS] of each, prefetched a pair ahead
     double f1[JT], sky[NW][3];       // the tile's f1 values and sky points
     double norm[NW];                 // 1 / sum_k u_k ab_k(n) of the sky points (SKYW)
 };
@@ -164,43 +166,79 @@ __device__ __forceinline__ double est_err_fp32(const EvalRun &r, const TileGeom 
     return 0x1p-24 * (3.0 * span + 2.0 * ((double)r.wtp + 2.0)) * 1.01 + 1e-9;
 }
 
-// Parameters and exact window of SFT stage [k0, k0 + ks) of a tile, then the
-// asynchronous HBM/L2 -> LDS copies of its windows.  Every wave derives the
-// parameters of its own sky point (lane (jl, kk) for f1 value jl and SFT kk)
-// and that sky point's bin range over the tile's f0 and f1 values; one
-// barrier publishes the ranges, and every wave takes their union for each SFT
-// in lane kk (the FP64 bin is monotone in f0, c and g, so the union is the
-// exact range of the tile).  Returns false, in every wave, if the window does
-// not fit the LDS rows (flagged).
-template <int L, int JT, int NW, int KS, bool SKYW>
-__device__ __forceinline__ bool prepare_stage(const EvalRun &r, const TileGeom &tg, int stage,
-                                              StageParams<L, JT, NW, KS> &P,
-                                              Shared<L, JT, NW, KS> &sh, float *wbuf, uint64_t &wmask)
+// Window copies of SFT stage [k0, k0 + ks): rows k0 + kk, columns [lo_kk,
+// lo_kk + wtp), wave w taking rows w, w + NW, ...; lo_kk is given by c0_of(kk)
+// (wave-uniform).
+template <int NW, typename C0>
+__device__ __forceinline__ void window_dma(const EvalRun &r, int k0, int ks, float *wbuf, C0 c0_of)
 {
-    const int k0 = stage * KS;
-    const int ks = min(KS, r.n_sft - k0);
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int wtp = r.wtp;
+    for (int kk = wave; kk < ks; kk += NW) {
+        const float *row = r.power_w + (int64_t)(k0 + kk) * r.n_bins;
+        const int c0 = c0_of(kk) - r.first_bin;
+        float *dst = wbuf + kk * wtp;
+        if (c0 >= 0 && c0 <= r.n_bins - wtp) {
+            // the whole window lies in the row: scalar base, one lane offset
+            const float *src = row + c0;
+            for (int x0 = 0; x0 < wtp; x0 += 64)
+                __builtin_amdgcn_global_load_lds(src + x0 + lane, dst + x0, 4, 0, 0);
+        } else {
+            // columns clamped into the row (only after a reported range error
+            // can a clamped column be read)
+            for (int x0 = 0; x0 < wtp; x0 += 64) {
+                const int col = min(max(c0 + lane + x0, 0), r.n_bins - 1);
+                __builtin_amdgcn_global_load_lds(row + col, dst + x0, 4, 0, 0);
+            }
+        }
+    }
+}
+
+// Parameters and exact windows of SFT stages s0 and s0 + 1 of a tile (one
+// pass: lane (st, jl, kk) for stage s0 + st, f1 value jl and SFT kk, so that
+// the lanes are busy), then the asynchronous HBM/L2 -> LDS copies of stage
+// s0's windows (stage s0 + 1's follow a stage later, from its stored first
+// bins).  Every wave derives the parameters of its own sky point and that sky
+// point's bin range over the tile's f0 and f1 values; one barrier publishes
+// the ranges, and every wave takes their union for each SFT (the FP64 bin is
+// monotone in f0, c and g, so the union is the exact range of the tile).
+// Returns false, in every wave, if a window does not fit the LDS rows
+// (flagged).
+template <int L, int JT, int NW, int KS, bool SKYW>
+__device__ __forceinline__ bool prepare_pair(const EvalRun &r, const TileGeom &tg, int s0,
+                                             StageParams<L, JT, NW, KS> &P0, StageParams<L, JT, NW, KS> &P1,
+                                             Shared<L, JT, NW, KS> &sh, float *wbuf0, uint64_t &wmask0,
+                                             uint64_t &wmask1)
+{
+    const int n_stage = (r.n_sft + KS - 1) / KS;
+    const int n_st = s0 + 1 < n_stage ? 2 : 1;
+    const int ks0 = min(KS, r.n_sft - s0 * KS);
+    const int ks1 = n_st > 1 ? min(KS, r.n_sft - (s0 + 1) * KS) : 0;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const double T = r.t_sft;
     const double nx = sh.sky[wave][0], ny = sh.sky[wave][1], nz = sh.sky[wave][2];
-    const double *vdt = sh.vdt[stage & 1];
+    const double *vdt = sh.vdt[(s0 >> 1) & 1];
     const double eta = r.eta + est_err_fp32(r, tg);
-    constexpr int NQ = (JT * KS + 63) / 64;
-    double hq[NQ];  // FP64 H of the lane's (jl, kk) before the shift by lo
+    constexpr int NP = JT * KS;            // (jl, kk) pairs of one stage
+    constexpr int NQ = (2 * NP + 63) / 64;
+    double hq[NQ];  // FP64 H of the lane's (st, jl, kk) before the shift by lo
     int b0q[NQ];    // bin of the tile's first template (valid where okq)
     bool okq[NQ];   // the whole tile's bins are b0q + m
 #pragma unroll
     for (int i = 0; i < NQ; ++i) {
         const int q = lane + 64 * i;
-        const int jl = q / KS, kk = q % KS;
+        const int st = q / NP, jl = (q % NP) / KS, kk = q % KS;
         hq[i] = 0.0;
         b0q[i] = 0;
         okq[i] = false;
-        if (q >= JT * KS || kk >= ks) continue;
-        const double *vk = vdt + 3 * kk;
+        if (st >= n_st || kk >= (st ? ks1 : ks0)) continue;
+        StageParams<L, JT, NW, KS> &P = st ? P1 : P0;
+        const double *vk = vdt + 4 * KS * st + 3 * kk;
         const double g = doppler_factor(vk[0], vk[1], vk[2], nx, ny, nz);
         const double G = g * T;
-        const double dt = vdt[3 * KS + kk];
+        const double dt = vdt[4 * KS * st + 3 * KS + kk];
         const double c = sh.f1[jl] * dt;
         const double e = r.dT * g - 1.0;
         const double eL = (double)(L - 1) * e;
@@ -219,6 +257,7 @@ __device__ __forceinline__ bool prepare_stage(const EvalRun &r, const TileGeom &
         }
         if (wave == 0) P.c[jl][kk] = c;
         if (jl == 0) {
+            const int k0 = (s0 + st) * KS;
             P.g[wave][kk] = g;
             if (SKYW) P.wt[wave][kk] = (float)(sky_ab(r.arms + 6 * (int64_t)(k0 + kk), nx, ny, nz) * sh.norm[wave]);
             P.q[wave][kk].G = (float)G;
@@ -231,49 +270,55 @@ __device__ __forceinline__ bool prepare_stage(const EvalRun &r, const TileGeom &
                 cmin = fmin(cmin, cj);
                 cmax = fmax(cmax, cj);
             }
-            sh.lo_w[wave][kk] = bin_fp64(tg.f0min, cmin, g, T);
-            sh.hi_w[wave][kk] = bin_fp64(tg.f0max, cmax, g, T);
+            sh.lo_w[wave][st * KS + kk] = bin_fp64(tg.f0min, cmin, g, T);
+            sh.hi_w[wave][st * KS + kk] = bin_fp64(tg.f0max, cmax, g, T);
         }
     }
     __syncthreads();
+    // the union over the sky points, lane st * KS + kk for stage s0 + st
     int lo = 0;
     bool bad = false;
-    if (lane < ks) {
-        lo = sh.lo_w[0][lane];
-        int hi = sh.hi_w[0][lane];
+    {
+        const int st = lane / KS, kk = lane % KS;
+        if (lane < 2 * KS && st < n_st && kk < (st ? ks1 : ks0)) {
+            lo = sh.lo_w[0][lane];
+            int hi = sh.hi_w[0][lane];
 #pragma unroll
-        for (int w = 1; w < NW; ++w) {
-            lo = min(lo, sh.lo_w[w][lane]);
-            hi = max(hi, sh.hi_w[w][lane]);
+            for (int w = 1; w < NW; ++w) {
+                lo = min(lo, sh.lo_w[w][lane]);
+                hi = max(hi, sh.hi_w[w][lane]);
+            }
+            uint32_t err = 0;
+            if (lo < r.first_bin || hi - r.first_bin >= r.n_bins) err |= ERR_RANGE;
+            if (hi - lo + L > r.wt) err |= ERR_WINDOW;
+            if (wave == 0) {
+                (st ? P1 : P0).lo[kk] = lo;
+                if (err) atomicOr(r.err, err);
+            }
+            bad = (err & ERR_WINDOW) != 0;
         }
-        uint32_t err = 0;
-        if (lo < r.first_bin || hi - r.first_bin >= r.n_bins) err |= ERR_RANGE;
-        if (hi - lo + L > r.wt) err |= ERR_WINDOW;
-        if (wave == 0) {
-            P.lo[lane] = lo;
-            if (err) atomicOr(r.err, err);
-        }
-        bad = (err & ERR_WINDOW) != 0;
     }
     if (!wave_all(!bad)) return false;
     // shift the estimates to the first staged bin and round them to FP32 (each
     // lane its own entries; lo is an integer near the estimate, so the FP64
     // difference is exact to an ulp of the window width), and the whole-wave
-    // row offsets with their step mask: bit kk is set when every f1 value of
+    // row offsets with their step masks: bit kk is set when every f1 value of
     // step kk is certified and the tile's reads lie inside the window row
-    wmask = 0;
+    wmask0 = 0;
+    wmask1 = 0;
     if (L > 1) {
         const int span_rd = ((tg.n_in - 1) / L) * L + L;  // reads of the last run end here
         uint64_t okm[NQ];
 #pragma unroll
         for (int i = 0; i < NQ; ++i) {
             const int q = lane + 64 * i;
-            const int jl = q / KS, kk = q % KS;
+            const int st = q / NP, jl = (q % NP) / KS, kk = q % KS;
             bool ok = false;
-            if (q < JT * KS && kk < ks) {
-                int lo_k = sh.lo_w[0][kk];
+            if (st < n_st && kk < (st ? ks1 : ks0)) {
+                StageParams<L, JT, NW, KS> &P = st ? P1 : P0;
+                int lo_k = sh.lo_w[0][st * KS + kk];
 #pragma unroll
-                for (int w = 1; w < NW; ++w) lo_k = min(lo_k, sh.lo_w[w][kk]);
+                for (int w = 1; w < NW; ++w) lo_k = min(lo_k, sh.lo_w[w][st * KS + kk]);
                 P.q[wave][kk].h[jl] = (float)(hq[i] - (double)lo_k);
                 const int off = b0q[i] - lo_k;
                 ok = okq[i] && off >= 0 && off + span_rd <= r.wt;
@@ -281,36 +326,28 @@ __device__ __forceinline__ bool prepare_stage(const EvalRun &r, const TileGeom &
             }
             okm[i] = __builtin_amdgcn_ballot_w64(ok);
         }
-        // KS divides 64, so the KS bits of one f1 value lie in one mask word
-        uint64_t m = KS >= 64 ? ~0ull : (1ull << KS) - 1;
+        // KS divides 64, so the KS bits of one (stage, f1 value) lie in one
+        // mask word
 #pragma unroll
-        for (int jl = 0; jl < JT; ++jl) m &= okm[(jl * KS) / 64] >> ((jl * KS) % 64);
-        wmask = m;
-    }
-
-    // the next stage's velocities and time offsets (read by its preparation,
-    // after the end-of-stage wait)
-    if (wave == 0 && k0 + KS < r.n_sft)
-        stage_vdt<KS>(r, k0 + KS, min(KS, r.n_sft - k0 - KS), sh.vdt[(stage + 1) & 1]);
-    const int wtp = r.wtp;
-    for (int kk = wave; kk < ks; kk += NW) {
-        const float *row = r.power_w + (int64_t)(k0 + kk) * r.n_bins;
-        const int c0 = __builtin_amdgcn_readlane(lo, kk) - r.first_bin;
-        float *dst = wbuf + kk * wtp;
-        if (c0 >= 0 && c0 <= r.n_bins - wtp) {
-            // the whole window lies in the row: scalar base, one lane offset
-            const float *src = row + c0;
-            for (int x0 = 0; x0 < wtp; x0 += 64)
-                __builtin_amdgcn_global_load_lds(src + x0 + lane, dst + x0, 4, 0, 0);
-        } else {
-            // columns clamped into the row (only after a reported range error
-            // can a clamped column be read)
-            for (int x0 = 0; x0 < wtp; x0 += 64) {
-                const int col = min(max(c0 + lane + x0, 0), r.n_bins - 1);
-                __builtin_amdgcn_global_load_lds(row + col, dst + x0, 4, 0, 0);
-            }
+        for (int st = 0; st < 2; ++st) {
+            uint64_t m = KS >= 64 ? ~0ull : (1ull << KS) - 1;
+#pragma unroll
+            for (int jl = 0; jl < JT; ++jl) m &= okm[(st * NP + jl * KS) / 64] >> ((st * NP + jl * KS) % 64);
+            if (st == 0) wmask0 = m;
+            else wmask1 = n_st > 1 ? m : 0;
         }
     }
+
+    // the velocities and time offsets of the pair after this one (read by its
+    // preparation, after the end-of-stage waits)
+    if (wave == 0) {
+        const double *dst = sh.vdt[((s0 + 2) >> 1) & 1];
+        if ((s0 + 2) * KS < r.n_sft)
+            stage_vdt<KS>(r, (s0 + 2) * KS, min(KS, r.n_sft - (s0 + 2) * KS), (double *)dst);
+        if ((s0 + 3) * KS < r.n_sft)
+            stage_vdt<KS>(r, (s0 + 3) * KS, min(KS, r.n_sft - (s0 + 3) * KS), (double *)dst + 4 * KS);
+    }
+    window_dma<NW>(r, s0 * KS, ks0, wbuf0, [&](int kk) { return __builtin_amdgcn_readlane(lo, kk); });
     return true;
 }
 
@@ -496,7 +533,10 @@ __device__ __forceinline__ void eval_tile(const EvalRun &r, int64_t b, float *wi
         sh.sky[sl][d] = r.sky_tile[3 * (int64_t)min(tg.s_base + sl, tg.s_last) + d];
     }
     if (SKYW && threadIdx.x < NW) sh.norm[threadIdx.x] = r.sky_norm[r.sky_perm[min(tg.s_base + (int)threadIdx.x, tg.s_last)]];
-    if (wave == 0) stage_vdt<KS>(r, 0, min(KS, r.n_sft), sh.vdt[0]);
+    if (wave == 0) {
+        stage_vdt<KS>(r, 0, min(KS, r.n_sft), sh.vdt[0]);
+        if (KS < r.n_sft) stage_vdt<KS>(r, KS, min(KS, r.n_sft - KS), sh.vdt[0] + 4 * KS);
+    }
     wait_loads();
     __syncthreads();
 
@@ -513,24 +553,36 @@ __device__ __forceinline__ void eval_tile(const EvalRun &r, int64_t b, float *wi
     // the lane's first template in the tile (idle lanes repeat the last run)
     const int lane_off = min(lane, (tg.n_in - 1) / L) * L;
     const int n_stage = (r.n_sft + KS - 1) / KS;
-    uint64_t wm_cur = 0, wm_next = 0;  // whole-wave step masks of the current and next stage
-    if (!prepare_stage<L, JT, NW, KS, SKYW>(r, tg, 0, sh.p[0], sh, win, wm_cur)) return;
+    // whole-wave step masks of stages p, p + 1 and p + 2; stage parameters in
+    // the ring sh.p[stage % 3], prepared two stages per pass (at even stages)
+    uint64_t wm0 = 0, wm1 = 0, wm2 = 0;
+    if (!prepare_pair<L, JT, NW, KS, SKYW>(r, tg, 0, sh.p[0], sh.p[1], sh, win, wm0, wm1)) return;
     wait_loads();
     __syncthreads();
 
+    int slot = 0;  // p % 3
     for (int p = 0; p < n_stage; ++p) {
         const int k0 = p * KS;
         const int ks = min(KS, r.n_sft - k0);
         const int cur = p & 1;
+        const int s1 = slot == 2 ? 0 : slot + 1, s2 = s1 == 2 ? 0 : s1 + 1;
         if (p + 1 < n_stage) {
-            if (!prepare_stage<L, JT, NW, KS, SKYW>(r, tg, p + 1, sh.p[cur ^ 1], sh, win + (cur ^ 1) * KS * wtp,
-                                                    wm_next))
-                return;
+            float *wnext = win + (cur ^ 1) * KS * wtp;
+            if (((p + 1) & 1) == 0) {
+                if (!prepare_pair<L, JT, NW, KS, SKYW>(r, tg, p + 1, sh.p[s1], sh.p[s2], sh, wnext, wm1, wm2))
+                    return;
+            } else {
+                const StageParams<L, JT, NW, KS> &Pn = sh.p[s1];
+                window_dma<NW>(r, (p + 1) * KS, min(KS, r.n_sft - (p + 1) * KS), wnext,
+                               [&](int kk) { return Pn.lo[kk]; });
+            }
         }
-        const StageParams<L, JT, NW, KS> &P = sh.p[cur];
+        const StageParams<L, JT, NW, KS> &P = sh.p[slot];
         const float *wb = win + cur * KS * wtp;
-        const uint64_t wm = wm_cur;
-        wm_cur = wm_next;
+        const uint64_t wm = wm0;
+        wm0 = wm1;
+        wm1 = wm2;
+        slot = s1;
         if (L > 1 && PIPE) {
             accumulate_pipelined<L, JT, NW, KS, SKYW>(r, P, sh, tg, wb, wtp, k0, ks, wave, lane, d_lane, acc, tot);
         } else
