@@ -99,10 +99,12 @@ template <int L, int JT, int NW, int KS>
 struct Shared {
     static_assert(KS <= 64 && NW <= 16, "one lane per SFT of a stage");
     static_assert(SUM_BLOCK % KS == 0, "summation blocks end with a stage");
+    // stages prepared per pass: two when both fit a wave's lanes
+    static constexpr int NS = 2 * JT * KS <= 64 ? 2 : 1;
     StageParams<L, JT, NW, KS> p[3];  // stages p, p + 1, p + 2 (ring by stage % 3)
     double f0[64 * L];
-    int lo_w[NW][2 * KS], hi_w[NW][2 * KS];  // per sky point bin ranges of the two stages being prepared
-    double vdt[2][8 * KS];  // per pair of stages: v/c [KS][3] then dt [KS] of each, prefetched a pair ahead
+    int lo_w[NW][NS * KS], hi_w[NW][NS * KS];  // per sky point bin ranges of the stages being prepared
+    double vdt[2][4 * NS * KS];  // per pass: v/c [KS][3] then dt [KS] of each stage, prefetched a pass ahead
     double f1[JT], sky[NW][3];       // the tile's f1 values and sky points
     double norm[NW];                 // 1 / sum_k u_k ab_k(n) of the sky points (SKYW)
 };
@@ -195,11 +197,11 @@ __device__ __forceinline__ void window_dma(const EvalRun &r, int k0, int ks, flo
     }
 }
 
-// Parameters and exact windows of SFT stages s0 and s0 + 1 of a tile (one
-// pass: lane (st, jl, kk) for stage s0 + st, f1 value jl and SFT kk, so that
-// the lanes are busy), then the asynchronous HBM/L2 -> LDS copies of stage
-// s0's windows (stage s0 + 1's follow a stage later, from its stored first
-// bins).  Every wave derives the parameters of its own sky point and that sky
+// Parameters and exact windows of SFT stages s0 .. s0 + NS - 1 of a tile
+// (one pass; with NS = 2, lane (st, jl, kk) for stage s0 + st, f1 value jl and
+// SFT kk, so that the lanes are busy), then the asynchronous HBM/L2 -> LDS
+// copies of stage s0's windows (stage s0 + 1's follow a stage later, from its
+// stored first bins).  Every wave derives the parameters of its own sky point and that sky
 // point's bin range over the tile's f0 and f1 values; one barrier publishes
 // the ranges, and every wave takes their union for each SFT (the FP64 bin is
 // monotone in f0, c and g, so the union is the exact range of the tile).
@@ -211,18 +213,19 @@ __device__ __forceinline__ bool prepare_pair(const EvalRun &r, const TileGeom &t
                                              Shared<L, JT, NW, KS> &sh, float *wbuf0, uint64_t &wmask0,
                                              uint64_t &wmask1)
 {
+    constexpr int NS = Shared<L, JT, NW, KS>::NS;
     const int n_stage = (r.n_sft + KS - 1) / KS;
-    const int n_st = s0 + 1 < n_stage ? 2 : 1;
+    const int n_st = NS > 1 && s0 + 1 < n_stage ? 2 : 1;
     const int ks0 = min(KS, r.n_sft - s0 * KS);
     const int ks1 = n_st > 1 ? min(KS, r.n_sft - (s0 + 1) * KS) : 0;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const double T = r.t_sft;
     const double nx = sh.sky[wave][0], ny = sh.sky[wave][1], nz = sh.sky[wave][2];
-    const double *vdt = sh.vdt[(s0 >> 1) & 1];
+    const double *vdt = sh.vdt[(s0 / NS) & 1];
     const double eta = r.eta + est_err_fp32(r, tg);
     constexpr int NP = JT * KS;            // (jl, kk) pairs of one stage
-    constexpr int NQ = (2 * NP + 63) / 64;
+    constexpr int NQ = (NS * NP + 63) / 64;
     double hq[NQ];  // FP64 H of the lane's (st, jl, kk) before the shift by lo
     int b0q[NQ];    // bin of the tile's first template (valid where okq)
     bool okq[NQ];   // the whole tile's bins are b0q + m
@@ -280,7 +283,7 @@ __device__ __forceinline__ bool prepare_pair(const EvalRun &r, const TileGeom &t
     bool bad = false;
     {
         const int st = lane / KS, kk = lane % KS;
-        if (lane < 2 * KS && st < n_st && kk < (st ? ks1 : ks0)) {
+        if (lane < NS * KS && st < n_st && kk < (st ? ks1 : ks0)) {
             lo = sh.lo_w[0][lane];
             int hi = sh.hi_w[0][lane];
 #pragma unroll
@@ -329,7 +332,7 @@ __device__ __forceinline__ bool prepare_pair(const EvalRun &r, const TileGeom &t
         // KS divides 64, so the KS bits of one (stage, f1 value) lie in one
         // mask word
 #pragma unroll
-        for (int st = 0; st < 2; ++st) {
+        for (int st = 0; st < NS; ++st) {
             uint64_t m = KS >= 64 ? ~0ull : (1ull << KS) - 1;
 #pragma unroll
             for (int jl = 0; jl < JT; ++jl) m &= okm[(st * NP + jl * KS) / 64] >> ((st * NP + jl * KS) % 64);
@@ -338,14 +341,14 @@ __device__ __forceinline__ bool prepare_pair(const EvalRun &r, const TileGeom &t
         }
     }
 
-    // the velocities and time offsets of the pair after this one (read by its
-    // preparation, after the end-of-stage waits)
+    // the velocities and time offsets of the next pass's stages (read by it,
+    // after the end-of-stage waits)
     if (wave == 0) {
-        const double *dst = sh.vdt[((s0 + 2) >> 1) & 1];
-        if ((s0 + 2) * KS < r.n_sft)
-            stage_vdt<KS>(r, (s0 + 2) * KS, min(KS, r.n_sft - (s0 + 2) * KS), (double *)dst);
-        if ((s0 + 3) * KS < r.n_sft)
-            stage_vdt<KS>(r, (s0 + 3) * KS, min(KS, r.n_sft - (s0 + 3) * KS), (double *)dst + 4 * KS);
+        double *dst = sh.vdt[((s0 + NS) / NS) & 1];
+#pragma unroll
+        for (int st = 0; st < NS; ++st)
+            if ((s0 + NS + st) * KS < r.n_sft)
+                stage_vdt<KS>(r, (s0 + NS + st) * KS, min(KS, r.n_sft - (s0 + NS + st) * KS), dst + 4 * KS * st);
     }
     window_dma<NW>(r, s0 * KS, ks0, wbuf0, [&](int kk) { return __builtin_amdgcn_readlane(lo, kk); });
     return true;
@@ -533,9 +536,10 @@ __device__ __forceinline__ void eval_tile(const EvalRun &r, int64_t b, float *wi
         sh.sky[sl][d] = r.sky_tile[3 * (int64_t)min(tg.s_base + sl, tg.s_last) + d];
     }
     if (SKYW && threadIdx.x < NW) sh.norm[threadIdx.x] = r.sky_norm[r.sky_perm[min(tg.s_base + (int)threadIdx.x, tg.s_last)]];
+    constexpr int NS = Shared<L, JT, NW, KS>::NS;
     if (wave == 0) {
         stage_vdt<KS>(r, 0, min(KS, r.n_sft), sh.vdt[0]);
-        if (KS < r.n_sft) stage_vdt<KS>(r, KS, min(KS, r.n_sft - KS), sh.vdt[0] + 4 * KS);
+        if (NS > 1 && KS < r.n_sft) stage_vdt<KS>(r, KS, min(KS, r.n_sft - KS), sh.vdt[0] + 4 * KS);
     }
     wait_loads();
     __syncthreads();
@@ -554,7 +558,7 @@ __device__ __forceinline__ void eval_tile(const EvalRun &r, int64_t b, float *wi
     const int lane_off = min(lane, (tg.n_in - 1) / L) * L;
     const int n_stage = (r.n_sft + KS - 1) / KS;
     // whole-wave step masks of stages p, p + 1 and p + 2; stage parameters in
-    // the ring sh.p[stage % 3], prepared two stages per pass (at even stages)
+    // the ring sh.p[stage % 3], prepared NS stages per pass
     uint64_t wm0 = 0, wm1 = 0, wm2 = 0;
     if (!prepare_pair<L, JT, NW, KS, SKYW>(r, tg, 0, sh.p[0], sh.p[1], sh, win, wm0, wm1)) return;
     wait_loads();
@@ -568,7 +572,7 @@ __device__ __forceinline__ void eval_tile(const EvalRun &r, int64_t b, float *wi
         const int s1 = slot == 2 ? 0 : slot + 1, s2 = s1 == 2 ? 0 : s1 + 1;
         if (p + 1 < n_stage) {
             float *wnext = win + (cur ^ 1) * KS * wtp;
-            if (((p + 1) & 1) == 0) {
+            if ((p + 1) % NS == 0) {
                 if (!prepare_pair<L, JT, NW, KS, SKYW>(r, tg, p + 1, sh.p[s1], sh.p[s2], sh, wnext, wm1, wm2))
                     return;
             } else {
