@@ -1346,6 +1346,9 @@ static ft_status tune_plain(ft_ctx c, const EvalRun &run, double dt_absmax, bool
         if (e == hipSuccess)
             e = hipMemcpyAsync(c->d_tune_perm, sp_h.data(), sp_h.size() * sizeof(int32_t), hipMemcpyHostToDevice,
                                c->stream);
+        // the host vectors are released on every return below: complete the copies
+        hipError_t es = hipStreamSynchronize(c->stream);
+        if (e == hipSuccess) e = es;
         if (e != hipSuccess) return hip_fail(c, e, "tile tuning sample");
         smp_sky = c->d_tune_sky;
         smp_perm = c->d_tune_perm;
