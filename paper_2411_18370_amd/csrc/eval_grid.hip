@@ -675,8 +675,9 @@ __device__ __forceinline__ void eval_tile(const EvalRun &r, int64_t b, float *wi
 // and the grid is a multiple of 8, so block b stays on XCD b % 8; each XCD is
 // given a contiguous range of tiles (f0 tile slowest, sky tile fastest) so
 // the table windows it stages stay in its L2.
-// OCC > 0 asks the compiler for at least OCC workgroups per CU (a register
-// budget of 512 / OCC per lane at four waves per workgroup); 0 leaves the
+// OCC > 0 asks the compiler for at least OCC waves per SIMD (the second
+// launch-bounds argument: a register budget of 512 / OCC VGPRs per lane; with
+// four-wave workgroups that is OCC workgroups per CU); 0 leaves the
 // allocation free.
 template <int L, int JT, int NW, int KS, int OCC, bool PIPE, bool SKYW>
 __global__ __launch_bounds__(64 * NW, OCC > 0 ? OCC : 1) void eval_grid_kernel(EvalRun r)
