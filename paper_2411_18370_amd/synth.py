@@ -226,6 +226,15 @@ def wide_band(n_f0: int, seed: int = 20, n_sky: int = 3, n_per_det: int = 30,
                   120.0, n_f0, [-1e-10, 0.0], n_sky, 25, 1, seed, with_noise=with_noise)
 
 
+def tiny_bank(n_f0: int, n_f1: int, n_sky: int, n_per_det: int, seed: int = 40) -> Workload:
+    """2 detectors x n_per_det SFTs of 1800 s (10% gaps), n_f0 f0 from 150 Hz x n_f1 f1 values
+    in [-3e-10, 2e-10] x n_sky, K = 5 in one sub-band: the smallest shapes (a single template,
+    SFT counts that end inside a stage, one f0 value past a full tile)."""
+    f1 = np.linspace(-3e-10, 2e-10, n_f1) if n_f1 > 1 else [1e-10]
+    return _build("tiny-2det-%dsft-150Hz-%dx%dx%d" % (2 * n_per_det, n_f0, n_f1, n_sky), 2, n_per_det,
+                  1800.0, 0.1, 150.0, n_f0, f1, n_sky, 5, 1, seed)
+
+
 def allsky_band(seed: int = 2, n_sky: int = 100_000, n_per_det: int = 5000) -> Workload:
     """2 detectors x 5000 SFTs (10% gaps), 200-200.5 Hz, 900 f0 x 11 f1 x n_sky, K=100/0.05 Hz.
 

@@ -102,6 +102,32 @@ def test_allsky_ragged_tiles_all_tiles_identical(ft):
             assert np.array_equal(ref, s32), ft.ft_tile_name(tile)
 
 
+@pytest.mark.parametrize("n_f0,n_f1,n_sky,n_per_det", [
+    (1, 1, 1, 1),     # one template, two SFTs: a single short stage
+    (1, 3, 2, 4),     # eight SFTs: one full K8 stage, half a K16 stage
+    (2, 1, 5, 5),     # ten SFTs: a full stage and two SFTs, prepared in one pass
+    (7, 2, 3, 12),    # three K8 stages: the second pass prepares one stage
+    (65, 4, 1, 20),   # one f0 value past a 64-wide L1 tile
+    (321, 5, 4, 17),  # one f0 value past a full L5 tile; 34 SFTs cross a summation block
+])
+def test_smallest_banks_every_tile(ft, n_f0, n_f1, n_sky, n_per_det):
+    """Degenerate and short banks through every tile shape: the statistics
+    within the bound and the toplists bit for bit against the oracle, and
+    every shape giving the same bits."""
+    w = synth.tiny_bank(n_f0, n_f1, n_sky, n_per_det)
+    s64, want = oracle_grid(w)
+    ref = None
+    for tile in range(1, ft.ft_tile_count() + 1):
+        s32, tops, info = run_gpu(ft, w, tile=tile)
+        assert info.n_evals == w.evals, ft.ft_tile_name(tile)
+        assert_stats(s32, s64, w.n_sft)
+        assert_toplists(tops, want, s64, w.n_sft)
+        if ref is None:
+            ref = s32
+        else:
+            assert np.array_equal(ref, s32), ft.ft_tile_name(tile)
+
+
 def test_list_bank_parity(ft):
     w = synth.allsky_band(seed=4, n_sky=8, n_per_det=250)
     rng = np.random.default_rng(40)
